@@ -1,0 +1,275 @@
+"""Seeded generators for the rigid-body immersed-boundary workloads.
+
+Every workload is a periodic box of side L = n*h with rigid bodies described by
+surface markers spaced about 2h apart (the marker-spacing rule of Sec. 6 and the
+conclusions).  Spheres use a Fibonacci (golden-angle) placement, disks use equally
+spaced points on a circle.  Centres are rejection-sampled so that body surfaces
+stay at least ``gap`` apart under the periodic minimum image, over the whole
+prescribed trajectory when bodies move.
+
+Nothing here evaluates the method: marker velocities, kernels and solves are
+computed independently by each consumer.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+
+
+@dataclass
+class Problem:
+    """One constrained-Stokes workload.
+
+    dim        2 or 3
+    n          cells per direction (the box is n^dim cells, periodic)
+    h          grid spacing; the box side is L = n*h
+    rho, eta   density and viscosity; rho == 0 means steady Stokes
+    dt         time step (ignored when steady)
+    R          [N][dim] marker positions in [0, L)^dim, grouped by body
+    offsets    [nb+1] start of each body's markers in R
+    centres    [nb][dim] body reference points (sphere / disk centres)
+    U          [nb][dim] prescribed linear velocities
+    Omega      [nb][1 or 3] prescribed angular velocities (1 component in 2D)
+    radius     [nb] geometric radii (for reporting only)
+    nsteps     number of time steps the trajectory was checked for
+    """
+
+    dim: int
+    n: int
+    h: float
+    rho: float
+    eta: float
+    dt: float
+    R: np.ndarray
+    offsets: np.ndarray
+    centres: np.ndarray
+    U: np.ndarray
+    Omega: np.ndarray
+    radius: np.ndarray
+    nsteps: int = 0
+    name: str = ""
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def L(self) -> float:
+        return self.n * self.h
+
+    @property
+    def nbodies(self) -> int:
+        return len(self.offsets) - 1
+
+    @property
+    def nmarkers(self) -> int:
+        return int(self.offsets[-1])
+
+    @property
+    def steady(self) -> bool:
+        return self.rho == 0.0
+
+
+def fibonacci_sphere(nmark: int, radius: float, centre) -> np.ndarray:
+    """Golden-angle points on a sphere: z_i = 1-(2i+1)/N, azimuth i*pi*(3-sqrt 5)."""
+    i = np.arange(nmark, dtype=np.float64)
+    z = 1.0 - (2.0 * i + 1.0) / nmark
+    rxy = np.sqrt(np.maximum(0.0, 1.0 - z * z))
+    phi = i * math.pi * (3.0 - math.sqrt(5.0))
+    pts = np.stack([rxy * np.cos(phi), rxy * np.sin(phi), z], axis=1) * radius
+    return pts + np.asarray(centre, dtype=np.float64)[None, :]
+
+
+def disk_ring(nmark: int, radius: float, centre, phase: float = 0.0) -> np.ndarray:
+    """nmark equally spaced points on a circle, starting at angle ``phase``."""
+    t = phase + 2.0 * math.pi * np.arange(nmark, dtype=np.float64) / nmark
+    pts = np.stack([np.cos(t), np.sin(t)], axis=1) * radius
+    return pts + np.asarray(centre, dtype=np.float64)[None, :]
+
+
+def _min_image(d: np.ndarray, L: float) -> np.ndarray:
+    return d - L * np.round(d / L)
+
+
+def sample_centres(rng: np.random.Generator, radii, L: float, dim: int, gap: float,
+                   U: Optional[np.ndarray] = None, dt: float = 0.0, nsteps: int = 0,
+                   max_tries: int = 200000) -> np.ndarray:
+    """Rejection-sample body centres in [0, L)^dim.
+
+    Surfaces of every pair stay at least ``gap`` apart (periodic minimum image),
+    at every time level 0..nsteps of the straight trajectories c + t*dt*U.
+    """
+    radii = np.asarray(radii, dtype=np.float64)
+    nb = len(radii)
+    if U is None:
+        U = np.zeros((nb, dim))
+    steps = np.arange(nsteps + 1, dtype=np.float64) * dt
+    centres = np.zeros((nb, dim))
+    placed = 0
+    tries = 0
+    while placed < nb:
+        tries += 1
+        if tries > max_tries:
+            raise RuntimeError("could not place %d bodies with gap %g" % (nb, gap))
+        c = rng.uniform(0.0, L, size=dim)
+        ok = True
+        for q in range(placed):
+            # relative position over the whole trajectory
+            rel = (c - centres[q])[None, :] + steps[:, None] * (U[placed] - U[q])[None, :]
+            dist = np.sqrt((_min_image(rel, L) ** 2).sum(axis=1)).min()
+            if dist < radii[placed] + radii[q] + gap:
+                ok = False
+                break
+        if ok:
+            centres[placed] = c
+            placed += 1
+    return centres
+
+
+def _wrap(R: np.ndarray, L: float) -> np.ndarray:
+    R = np.mod(R, L)
+    R[R >= L] -= L  # guard against mod returning L for tiny negatives
+    return R
+
+
+def _assemble(dim, n, h, rho, eta, dt, bodies, centres, U, Omega, radii, nsteps, name, meta=None):
+    offsets = np.zeros(len(bodies) + 1, dtype=np.int64)
+    for p, b in enumerate(bodies):
+        offsets[p + 1] = offsets[p] + len(b)
+    R = _wrap(np.concatenate(bodies, axis=0), n * h)
+    return Problem(dim=dim, n=n, h=h, rho=rho, eta=eta, dt=dt, R=R, offsets=offsets,
+                   centres=np.asarray(centres, dtype=np.float64) % (n * h),
+                   U=np.asarray(U, dtype=np.float64), Omega=np.asarray(Omega, dtype=np.float64),
+                   radius=np.asarray(radii, dtype=np.float64), nsteps=nsteps, name=name,
+                   meta=meta or {})
+
+
+def sphere_markers_for(radius_h: float) -> int:
+    """Marker count for a sphere of radius R (in units of h) at about 2h spacing: round(pi R^2)."""
+    return int(round(math.pi * radius_h * radius_h))
+
+
+def disk_markers_for(radius_h: float) -> int:
+    """Marker count for a circle of radius R (in units of h) at about 2h spacing: round(pi R)."""
+    return int(round(math.pi * radius_h))
+
+
+def config0_disk2d(seed: int = 0, n: int = 64, radius_h: float = 8.0) -> Problem:
+    """2D steady Stokes, periodic unit square, one disk of radius 8h, ~25 markers, U = (1, 0)."""
+    rng = np.random.default_rng(seed)
+    h = 1.0 / n
+    c = rng.uniform(0.0, 1.0, size=2)
+    phase = rng.uniform(0.0, 2.0 * math.pi)
+    nm = disk_markers_for(radius_h)
+    R = disk_ring(nm, radius_h * h, c, phase)
+    return _assemble(2, n, h, 0.0, 1.0, 0.0, [R], [c], [[1.0, 0.0]], [[0.0]],
+                     [radius_h * h], 0, "disk2d_%d" % n)
+
+
+def config1_sphere3d(seed: int = 0, n: int = 64, radius_h: float = 8.0, nmark: int = 200) -> Problem:
+    """3D steady Stokes, periodic unit cube, one sphere of radius 8h with 200 markers."""
+    rng = np.random.default_rng(seed)
+    h = 1.0 / n
+    c = rng.uniform(0.0, 1.0, size=3)
+    U = rng.uniform(-1.0, 1.0, size=3)
+    W = rng.uniform(-1.0, 1.0, size=3)
+    R = fibonacci_sphere(nmark, radius_h * h, c)
+    return _assemble(3, n, h, 0.0, 1.0, 0.0, [R], [c], [U], [W], [radius_h * h], 0,
+                     "sphere3d_%d" % n)
+
+
+def config2_spheres_ns(seed: int = 0, re: float = 10.0, n: int = 128, nbodies: int = 16,
+                       radius_h: float = 6.0, nmark: int = 110, nsteps: int = 20) -> Problem:
+    """3D unsteady Navier-Stokes, periodic unit cube, moving spheres.
+
+    Re = rho*V*R/eta with R = radius, V = 1, rho = 1, so eta = R/Re; dt = 0.5h/V.
+    Velocities U_p ~ U[-1,1]^3, no rotation; centres keep a 4h surface gap over
+    all ``nsteps`` steps.
+    """
+    rng = np.random.default_rng(seed)
+    h = 1.0 / n
+    rad = radius_h * h
+    dt = 0.5 * h
+    eta = rad / re
+    U = rng.uniform(-1.0, 1.0, size=(nbodies, 3))
+    centres = sample_centres(rng, [rad] * nbodies, 1.0, 3, 4.0 * h, U=U, dt=dt, nsteps=nsteps)
+    bodies = [fibonacci_sphere(nmark, rad, c) for c in centres]
+    return _assemble(3, n, h, 1.0, eta, dt, bodies, centres, U, np.zeros((nbodies, 3)),
+                     [rad] * nbodies, nsteps, "spheres_ns_%d_re%g" % (n, re), {"re": re})
+
+
+def config4_spheres256(seed: int = 0, n: int = 256, nbodies: int = 100, radius_h: float = 8.0,
+                       nmark: int = 200) -> Problem:
+    """3D steady Stokes, periodic unit cube 256^3, 100 spheres of radius 8h, 200 markers each."""
+    rng = np.random.default_rng(seed)
+    h = 1.0 / n
+    rad = radius_h * h
+    centres = sample_centres(rng, [rad] * nbodies, 1.0, 3, 4.0 * h)
+    U = rng.uniform(-1.0, 1.0, size=(nbodies, 3))
+    W = rng.uniform(-1.0, 1.0, size=(nbodies, 3))
+    bodies = [fibonacci_sphere(nmark, rad, c) for c in centres]
+    return _assemble(3, n, h, 0.0, 1.0, 0.0, bodies, centres, U, W, [rad] * nbodies, 0,
+                     "spheres_%d" % n)
+
+
+def small_problem(seed: int, dim: int, n: int, nbodies: int = 1, radius_h: float = 3.0,
+                  rho: float = 0.0, eta: float = 1.0, dt: float = 0.0, gap_h: float = 4.0,
+                  rotate: bool = True, nsteps: int = 0, L: float = 1.0) -> Problem:
+    """Small seeded problem for parity tests (oracle finishes in seconds)."""
+    rng = np.random.default_rng(seed)
+    h = L / n
+    rad = radius_h * h
+    U = rng.uniform(-1.0, 1.0, size=(nbodies, dim))
+    centres = sample_centres(rng, [rad] * nbodies, L, dim, gap_h * h, U=U if nsteps else None,
+                             dt=dt, nsteps=nsteps)
+    if dim == 3:
+        Om = rng.uniform(-1.0, 1.0, size=(nbodies, 3)) if rotate else np.zeros((nbodies, 3))
+        nm = sphere_markers_for(radius_h)
+        bodies = [fibonacci_sphere(nm, rad, c) for c in centres]
+    else:
+        Om = rng.uniform(-1.0, 1.0, size=(nbodies, 1)) if rotate else np.zeros((nbodies, 1))
+        nm = disk_markers_for(radius_h)
+        bodies = [disk_ring(nm, rad, c, rng.uniform(0, 2 * math.pi)) for c in centres]
+    return _assemble(dim, n, h, rho, eta, dt, bodies, centres, U, Om, [rad] * nbodies, nsteps,
+                     "small_%dd_%d" % (dim, n))
+
+
+SERVING_GRIDS = [(2, 32), (2, 128), (2, 256), (3, 32), (3, 64), (3, 128)]
+
+
+def serving_trace(seed: int = 0, nreq: int = 2000, qps: float = 50.0) -> List[dict]:
+    """Poisson arrivals of steady constrained solves with random sizes and bodies.
+
+    Each request draws a grid from SERVING_GRIDS, 1-8 bodies of radius U[4h, 8h]
+    (fewer if they do not fit with a 4h gap), markers at ~2h and U, Omega ~ U[-1,1].
+    Returns a list of {"t": arrival time in s, "problem": Problem}.
+    """
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for r in range(nreq):
+        t += rng.exponential(1.0 / qps)
+        dim, n = SERVING_GRIDS[rng.integers(len(SERVING_GRIDS))]
+        nb = int(rng.integers(1, 9))
+        h = 1.0 / n
+        radii_h = rng.uniform(4.0, 8.0, size=nb)
+        while True:
+            try:
+                centres = sample_centres(rng, radii_h[:nb] * h, 1.0, dim, 4.0 * h, max_tries=2000)
+                break
+            except RuntimeError:
+                nb -= 1
+        bodies = []
+        for p in range(nb):
+            if dim == 3:
+                bodies.append(fibonacci_sphere(sphere_markers_for(radii_h[p]), radii_h[p] * h,
+                                               centres[p]))
+            else:
+                bodies.append(disk_ring(disk_markers_for(radii_h[p]), radii_h[p] * h, centres[p],
+                                        rng.uniform(0, 2 * math.pi)))
+        U = rng.uniform(-1.0, 1.0, size=(nb, dim))
+        Om = rng.uniform(-1.0, 1.0, size=(nb, 3 if dim == 3 else 1))
+        prob = _assemble(dim, n, h, 0.0, 1.0, 0.0, bodies, centres, U, Om, radii_h[:nb] * h, 0,
+                         "serve_%d_%dd_%d" % (r, dim, n))
+        out.append({"t": t, "problem": prob})
+    return out
