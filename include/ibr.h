@@ -1,0 +1,177 @@
+/*
+ * ibr.h -- C ABI of the MI355X solver for the rigidly constrained
+ * immersed-boundary Stokes / Navier-Stokes system of Kallemov, Bhalla,
+ * Griffith & Donev, "An immersed boundary method for rigid bodies".
+ *
+ * One context owns every device buffer of one problem size: the MAC grid
+ * state, the multigrid hierarchy, the Krylov bases and the factored per-body
+ * mobility blocks.  They stay resident between calls, so consecutive solves
+ * (time steps, warm starts) reuse them.  The caller owns every pointer it
+ * passes; the library copies what it needs during the call and keeps no
+ * caller pointer afterwards.  Calls on one context are not thread-safe; use
+ * one context per host thread.  Every call returns an ibr_status; on failure
+ * ibr_last_error() holds a message.  No exception crosses the ABI.
+ *
+ * Layouts (all host arrays are row-major, double precision):
+ *   grid      periodic box [0, n h)^dim, cells indexed (k, j, i) with i (x)
+ *             fastest; cell centres at ((i+1/2)h, (j+1/2)h, (k+1/2)h).
+ *   velocity  u[dim][n^dim]: component a of cell c lives on the a-face half a
+ *             cell below the centre along a (the MAC grid of Sec. 3).
+ *   pressure  p[n^dim] at cell centres, returned with zero mean.
+ *   markers   R[N][dim], grouped contiguously by body; offsets[nb+1].
+ *   Lambda    lambda[N][dim], the force each marker applies to the fluid
+ *             (the +S Lambda forcing of eq. semi_continuum).
+ *   bodies    centres X[nb][dim]; U[nb][dim]; Omega[nb][3] (3D) or [nb][1] (2D).
+ *             Marker velocities V_i = U_p + Omega_p x (R_i - X_p) (minimum
+ *             image); force F_p = sum_i Lambda_i, torque
+ *             T_p = sum_i (R_i - X_p) x Lambda_i (Sec. 2).
+ */
+#ifndef IBR_H
+#define IBR_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ibr_ctx ibr_ctx;
+
+typedef enum {
+  IBR_OK = 0,
+  IBR_EINVAL = 1,      /* an argument is out of range; nothing was changed */
+  IBR_ENOMEM = 2,      /* device allocation failed */
+  IBR_ENOCONV = 3,     /* max_iters reached; the last iterate is kept */
+  IBR_EBREAKDOWN = 4,  /* Krylov breakdown with the residual above target */
+  IBR_EFACTOR = 5,     /* a mobility block could not be factored even shifted */
+  IBR_ENUMERIC = 6,    /* NaN or Inf in the residual */
+  IBR_EDEVICE = 7,     /* a HIP call failed */
+  IBR_ESTATE = 8       /* call out of order (e.g. solve before set_bodies) */
+} ibr_status;
+
+typedef enum { IBR_FP64 = 0, IBR_MIXED = 1 } ibr_precision;
+typedef enum { IBR_PC_LOWER = 0, IBR_PC_FULL = 1 } ibr_pc;
+
+/* Problem and solver parameters.  Sec. 3.2 (eq. A_def) defines
+ * A = (rho/dt) I - eta h^-2 L; rho == 0 selects steady Stokes, where the
+ * periodic system becomes eq. constrained_periodic (S' = S - vol^-1 1 1^T,
+ * <v> = 0).  Sec. 5 defines the solver knobs. */
+typedef struct {
+  int dim;            /* 2 or 3 */
+  int n;              /* cells per direction: power of two, 16..1024 (3D: 8..512) */
+  double h;           /* grid spacing (> 0); the box side is n*h */
+  double rho;         /* density; 0 = steady Stokes */
+  double eta;         /* viscosity (> 0) */
+  double dt;          /* time step (> 0 unless steady) */
+  int precision;      /* IBR_FP64, or IBR_MIXED: fp32 preconditioner, fp64 outer */
+  int pc;             /* IBR_PC_LOWER (default) or IBR_PC_FULL, Sec. 5.1 */
+  int n_s;            /* inner Stokes GMRES iterations N_s (default 2), Sec. 5.2 */
+  int restart;        /* FGMRES restart length (default 100, Sec. 7.1) */
+  int max_iters;      /* cap on FGMRES iterations (default 1000) */
+  double rtol;        /* stop when ||b - K x||_2 <= rtol ||b||_2 (default 1e-8) */
+  int mg_pre;         /* red-black sweeps before coarsening (default 2) */
+  int mg_post;        /* red-black sweeps after prolongation (default 2) */
+  int mg_coarse;      /* red-black sweeps on the 4^dim coarsest grid (default 16) */
+  int device;         /* HIP device ordinal */
+  void* stream;       /* hipStream_t to run on, or NULL for a library stream */
+} ibr_params;
+
+/* Per-solve report.  ps_applications counts P_S^-1 applications, the cost
+ * unit of Sec. 7.1. */
+typedef struct {
+  int iters;              /* FGMRES iterations (all restart cycles) */
+  int restarts;           /* restart cycles started */
+  int ps_applications;    /* applications of P_S^-1 */
+  int vcycles;            /* scalar V-cycles (a 3-field batched cycle counts 3) */
+  int status;             /* ibr_status of the solve */
+  double rel_residual;    /* ||b - K x|| / ||b|| recomputed in fp64 at exit */
+  double ms;              /* device time of the solve, milliseconds */
+  double max_mobility_shift; /* largest shift s used to factor a block (0 = none) */
+} ibr_info;
+
+/* Fill p with the defaults listed above (3D, n = 32, h = 1/32, steady, eta = 1). */
+void ibr_default_params(ibr_params* p);
+
+/* Static string for a status code. */
+const char* ibr_status_string(int status);
+
+/* Create a context for one grid size; allocates the grid state and multigrid
+ * hierarchy on params->device.  *out is set only on IBR_OK. */
+ibr_status ibr_create(const ibr_params* params, ibr_ctx** out);
+
+/* Free every device buffer of the context (NULL is accepted). */
+void ibr_destroy(ibr_ctx* ctx);
+
+/* Message of the last failed call on this context ("" if none). */
+const char* ibr_last_error(const ibr_ctx* ctx);
+
+/* Device bytes a context would hold for these parameters and markers. */
+size_t ibr_footprint_bytes(const ibr_params* params, int nbodies, int nmarkers);
+
+/* Set the rigid bodies (Sec. 2): nbodies >= 1, offsets[nbodies+1] increasing
+ * from 0, R[N][dim] markers inside [0, n h) (wrapped otherwise), centres
+ * X[nb][dim].  Builds the marker bins, assembles and factors each body's
+ * approximate mobility block (Sec. 4, Sec. 5.3).  Velocities reset to zero. */
+ibr_status ibr_set_bodies(ibr_ctx* ctx, int nbodies, const int* offsets, const double* R,
+                          const double* centres);
+
+/* Prescribed rigid velocities U[nb][dim] and Omega[nb][3 or 1] (Sec. 2). */
+ibr_status ibr_set_velocities(ibr_ctx* ctx, const double* U, const double* Omega);
+
+/* Fluid right-hand sides g[dim][n^dim] and h[n^dim] of eq. constrained_Stokes
+ * (NULL = zero).  For steady periodic problems the mean of g is removed (the
+ * paper's consistency assumption <g> = 0, Sec. 3.4). */
+ibr_status ibr_set_rhs(ibr_ctx* ctx, const double* g, const double* hp);
+
+/* Solve eq. constrained_Stokes (eq. constrained_periodic when steady) by
+ * FGMRES with the Schur-complement preconditioner of Sec. 5.1.  warm_start
+ * != 0 starts from the context's previous solution.  info may be NULL. */
+ibr_status ibr_solve(ibr_ctx* ctx, int warm_start, ibr_info* info);
+
+/* One unsteady step (rho > 0): explicit advection right-hand side
+ * (Adams-Bashforth 2, forward Euler on the first step), markers moved by
+ * dt U_p, warm-started constrained solve.  Requires Omega == 0. */
+ibr_status ibr_step(ibr_ctx* ctx, ibr_info* info);
+
+/* Copy the current solution to host arrays (any pointer may be NULL):
+ * u[dim][n^dim], p[n^dim], lambda[N][dim], F[nb][dim], T[nb][3 or 1]. */
+ibr_status ibr_get_solution(ibr_ctx* ctx, double* u, double* p, double* lambda, double* F,
+                            double* T);
+
+/* Current marker positions R[N][dim] and centres X[nb][dim] (they move in ibr_step). */
+ibr_status ibr_get_markers(ibr_ctx* ctx, double* R, double* centres);
+
+/* ---- single-operator entry points (same layouts; used for kernel parity) ---- */
+
+/* y = K x for the stacked vector x = [u (dim n^dim), p (n^dim), lambda (N dim)],
+ * K the matrix of eq. constrained_Stokes (S' when steady). */
+ibr_status ibr_apply_operator(ibr_ctx* ctx, const double* x, double* y);
+
+/* f = S lambda (Sec. 3.1, eq. S_unweighted; no mean removal): f[dim][n^dim]. */
+ibr_status ibr_spread(ibr_ctx* ctx, const double* lambda, double* f);
+
+/* V = J u (Sec. 3.1): V[N][dim]. */
+ibr_status ibr_interp(ibr_ctx* ctx, const double* u, double* V);
+
+/* One V-cycle (Sec. 5.2) for (c0 - c1 L) x = b on nfields independent
+ * fields b[nfields][n^dim], x[nfields][n^dim]; c0 == 0 is the restricted
+ * (mean-zero) inverse.  Runs in the context's precision. */
+ibr_status ibr_vcycle(ibr_ctx* ctx, double c0, double c1, int nfields, const double* b,
+                      double* x);
+
+/* z = P r: one application of the Schur-complement preconditioner of
+ * Sec. 5.1 to a stacked vector r (layout of ibr_apply_operator). */
+ibr_status ibr_precondition(ibr_ctx* ctx, const double* r, double* z);
+
+/* Approximate mobility block of one body (Sec. 4) as assembled on the device,
+ * M[(dim Np)^2] row-major, and the shift s used to factor it. */
+ibr_status ibr_mobility_block(ibr_ctx* ctx, int body, double* M, double* shift);
+
+/* Advection term N(u) of the unsteady step on the MAC grid: N[dim][n^dim]. */
+ibr_status ibr_advect(ibr_ctx* ctx, const double* u, double* N);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IBR_H */

@@ -1,0 +1,156 @@
+// Internal launchers shared by the kernel files and the solver.  Not part of
+// the public C ABI (include/ibr.h).
+#pragma once
+
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+namespace ibr {
+
+struct DeviceError : std::runtime_error {
+  explicit DeviceError(const std::string& m) : std::runtime_error(m) {}
+};
+
+#define IBR_HIP(call)                                                                               \
+  do {                                                                                              \
+    hipError_t e_ = (call);                                                                         \
+    if (e_ != hipSuccess)                                                                           \
+      throw ::ibr::DeviceError(std::string(#call) + ": " + hipGetErrorString(e_));                  \
+  } while (0)
+
+template <typename T>
+T* dev_alloc(int64_t count) {
+  if (count <= 0) return nullptr;
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, (size_t)count * sizeof(T));
+  if (e != hipSuccess) throw DeviceError(std::string("hipMalloc: ") + hipGetErrorString(e));
+  return (T*)p;
+}
+inline void dev_free(void* p) {
+  if (p) (void)hipFree(p);
+}
+
+// ---------------------------------------------------------------- grid stencils
+template <typename TI, typename TO>
+void launch_stokes_apply(int dim, int logn, const TI* v, const TI* p, TO* yv, TO* yp, double c0, double ch2,
+                         double inv_h, const double* addc, hipStream_t s);
+template <typename T>
+void launch_div_q(int dim, int logn, const T* v, const T* hp, T* q, double inv_h, hipStream_t s);
+template <typename T>
+void launch_ps_finish(int dim, int logn, T* v, const T* phi, const T* q, T* pi, double h, double c0h2, double eta,
+                      const double* vmean, hipStream_t s);
+void launch_advect(int dim, int logn, const double* v, double* N, double inv_2h, hipStream_t s);
+void launch_ns_rhs(const double* v, const double* N1, const double* N0, double* g, int64_t len, double rdt,
+                   double rho, double w1, double w0, hipStream_t s);
+
+// ---------------------------------------------------------------- multigrid
+int mg_lds_cells();
+template <typename T>
+void launch_fill(T* x, int64_t len, T v, hipStream_t s);
+template <typename T>
+void launch_field_means(const T* x, int nf, int64_t C, double* part, int part_blocks, double* out, hipStream_t s);
+template <typename T>
+void launch_sub_field_mean(T* x, int nf, int64_t C, const double* mean, hipStream_t s);
+
+template <typename T>
+struct MGHier {
+  int dim = 3, logn = 0, nfmax = 0, lds_logn = 0;
+  std::vector<int> levels;          // log2 n of the multi-kernel levels (finest first)
+  std::vector<T*> bufs_x, bufs_b;   // per level >= 1, nfmax fields each
+  void init(int dim, int logn, int nfmax);
+  void release();
+  static size_t bytes(int dim, int logn, int nf);
+  // One V-cycle for nf fields: x = V(b).  x and b hold nf fields of n^dim.
+  void vcycle(int nf, const T* b, T* x, double c0, double c1, int nu_pre, int nu_post, int nu_coarse,
+              hipStream_t s);
+};
+
+// ---------------------------------------------------------------- markers / IB
+// Per-marker interpolation data: for every dimension beta the first tap index
+// (not wrapped) and the 4 weights, for the cell-centred (c) and the face (f)
+// staggering of that axis.  Component a uses the face staggering on axis a.
+struct MarkerTaps {
+  int* base;        // [N][2][3]: base[(m*2 + s)*3 + beta], s = 0 cell-centred, 1 face
+  double* w64;      // [N][2][3][4]
+  float* w32;       // same, fp32
+};
+
+void launch_marker_setup(int dim, int logn, int N, double h, double L, const double* R, MarkerTaps taps,
+                         int* tile_of, int tile_log, hipStream_t s);
+void launch_marker_velocity(int dim, int N, const double* R, const int* body, const double* centres,
+                            const double* U, const double* Om, double L, double* V, hipStream_t s);
+void launch_move_markers(int dim, int N, int nb, double* R, double* centres, const int* body, const double* U,
+                         double dt, double L, hipStream_t s);
+
+// Tile binning: count/scan/scatter/sort so that tile t owns perm[off[t] .. off[t+1]).
+void launch_bin_markers(int N, int ntiles, const int* tile_of, int* counts, int* offsets, int* cursor, int* perm,
+                        hipStream_t s);
+void launch_active_tiles(int dim, int tiles_log, const int* offsets, int* flags, int* active_list,
+                         int* active_count, hipStream_t s);
+
+// y_face[a] += sign * h^-dim * sum_i lam[i][a] * w  over the active tiles
+template <typename TL, typename TY>
+void launch_spread(int dim, int logn, int tile_log, int nactive, const int* active_list, const int* offsets,
+                   const int* perm, MarkerTaps taps, const TL* lam, TY* y, double scale, hipStream_t s);
+// out[i][a] = alpha * (J v)[i][a] + beta * add[i][a]   (add may be null)
+template <typename TV>
+void launch_interp(int dim, int logn, int N, MarkerTaps taps, const TV* v, double alpha, const double* add,
+                   double beta, double* out, hipStream_t s);
+void launch_lambda_sums(int dim, int N, const double* lam, double* part, double* out, double scale,
+                        hipStream_t s);
+void launch_body_force_torque(int dim, int nb, const int* offsets, const double* R, const double* centres,
+                              double L, const double* lam, double* F, double* T, hipStream_t s);
+
+// ---------------------------------------------------------------- Krylov
+// h[j] = <w, V_j> for j < k (V_j = V + j*ld); two-pass deterministic reduction.
+template <typename TV, typename TW>
+void launch_multi_dot(const TV* V, int64_t ld, int k, const TW* w, int64_t len, double* part, int nblocks,
+                      double* h, bool accumulate, hipStream_t s);
+// w -= sum_j h[j] V_j ; if norm_part != null also writes partial sums of w^2.
+template <typename TV, typename TW>
+void launch_multi_axpy(const TV* V, int64_t ld, int k, const double* h, TW* w, int64_t len, double* norm_part,
+                       int nblocks, hipStream_t s);
+// x += sum_j y[j] Z_j  (Z in TZ, x in TX)
+template <typename TZ, typename TX>
+void launch_combine(const TZ* Z, int64_t ld, int k, const double* y, TX* x, int64_t len, hipStream_t s);
+void launch_norm_finish(const double* part, int nblocks, double* out, hipStream_t s);
+template <typename T>
+void launch_sumsq_partial(const T* w, int64_t len, double* part, int nblocks, hipStream_t s);
+// dst = src * (1/ *nrm) (0 if nrm == 0); types may differ (conversion)
+template <typename TS, typename TD>
+void launch_scale_copy(const TS* src, TD* dst, int64_t len, const double* nrm, hipStream_t s);
+template <typename TS, typename TD>
+void launch_copy(const TS* src, TD* dst, int64_t len, hipStream_t s);
+// y = a*x + b*y (a, b host scalars)
+void launch_axpby(const double* x, double* y, int64_t len, double a, double b, hipStream_t s);
+
+// Givens / Hessenberg least squares (a single wavefront).
+//   H: column-major (m+1) x m, leading dimension m+1.
+void launch_givens_step(double* H, int ldh, int k, double* cs, double* sn, double* g, double* resid,
+                        hipStream_t s);
+void launch_lsq_solve(const double* H, int ldh, int k, const double* g, double* y, hipStream_t s);
+// g = (beta, 0, ..., 0) with beta read from device memory.
+void launch_init_g(double* g, int len, const double* beta, hipStream_t s);
+// Number of blocks for the two-pass reductions over a vector of length len.
+int krylov_dot_blocks(int64_t len);
+
+// ---------------------------------------------------------------- mobility blocks
+struct MobParams {
+  int dim;
+  int steady;
+  double a, eta, L, finf0, f00, alpha, dt_rho, periodic_shift;
+};
+void launch_mob_assemble(int dim, int nb, const int* offsets, const int64_t* moff, const double* R, MobParams p,
+                         double* M, int max_np, hipStream_t s);
+void launch_chol(int nb, const int* offsets, int dim, const int64_t* moff, const double* M, double* Lf,
+                 const int* active, const double* shift, double f0, double pivot_tol, int* fail,
+                 hipStream_t s);
+void launch_chol_inverse(int nb, const int* offsets, int dim, const int64_t* moff, double* Lf, double* Minv,
+                         double* X, int max_n, hipStream_t s);
+void launch_mob_apply(int nb, const int* offsets, int dim, const int64_t* moff, const double* Minv,
+                      const double* dU, double* lam, int max_rows, hipStream_t s);
+
+}  // namespace ibr

@@ -1,0 +1,206 @@
+// MAC-grid stencil kernels (Sec. 3.2): the Stokes operator [[A, G], [-D, 0]],
+// the pieces of the projection preconditioner P_S^-1 (Sec. 5.2,
+// eq. P1_practical) and the explicit advection term of the unsteady step.
+//
+// Layout: field f of a vector lives at base + f*C, C = n^dim, x fastest.
+// One thread per cell; blocks are remapped so each XCD walks a contiguous slab.
+#include "kernels.h"
+
+namespace ibr {
+
+namespace {
+
+struct Nbr {
+  int64_t m[3];  // c - e_a
+  int64_t p[3];  // c + e_a
+};
+
+template <int DIM>
+__device__ inline Nbr neighbours(int64_t c, int logn) {
+  const int n = 1 << logn;
+  const int mask = n - 1;
+  Nbr r;
+  int i = (int)(c & mask);
+  r.m[0] = c - i + ((i - 1) & mask);
+  r.p[0] = c - i + ((i + 1) & mask);
+  int j = (int)((c >> logn) & mask);
+  r.m[1] = c + ((int64_t)(((j - 1) & mask) - j) << logn);
+  r.p[1] = c + ((int64_t)(((j + 1) & mask) - j) << logn);
+  if (DIM == 3) {
+    int k = (int)(c >> (2 * logn));
+    r.m[2] = c + ((int64_t)(((k - 1) & mask) - k) << (2 * logn));
+    r.p[2] = c + ((int64_t)(((k + 1) & mask) - k) << (2 * logn));
+  } else {
+    r.m[2] = r.p[2] = c;
+  }
+  return r;
+}
+
+// yv = A v + G p + addc, yp = -D v.   A = c0 I - ch2 L,  G, D with 1/h.
+// TI: storage type of the input, TO: of the output (arithmetic in TO).
+template <typename TI, typename TO, int DIM>
+__global__ void __launch_bounds__(256) k_stokes_apply(const TI* __restrict__ v, const TI* __restrict__ p,
+                                                      TO* __restrict__ yv, TO* __restrict__ yp, int logn,
+                                                      TO c0, TO ch2, TO inv_h,
+                                                      const double* __restrict__ addc) {
+  const int64_t C = (int64_t)1 << (DIM * logn);
+  const int64_t c = xcd_block(gridDim.x) * blockDim.x + threadIdx.x;
+  if (c >= C) return;
+  const Nbr nb = neighbours<DIM>(c, logn);
+  const TO pc = (TO)p[c];
+  TO div = 0;
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) {
+    const TI* va = v + a * C;
+    const TO vc = (TO)va[c];
+    TO s = (TO)va[nb.m[0]] + (TO)va[nb.p[0]] + (TO)va[nb.m[1]] + (TO)va[nb.p[1]];
+    if (DIM == 3) s += (TO)va[nb.m[2]] + (TO)va[nb.p[2]];
+    const TO lap = s - TO(2 * DIM) * vc;
+    TO out = c0 * vc - ch2 * lap + (pc - (TO)p[nb.m[a]]) * inv_h;
+    if (addc) out += (TO)addc[a];
+    yv[a * C + c] = out;
+    div += ((TO)va[nb.p[a]] - vc) * inv_h;
+  }
+  yp[c] = -div;
+}
+
+// q = -D v - hp  (hp may be null).
+template <typename T, int DIM>
+__global__ void __launch_bounds__(256) k_div_q(const T* __restrict__ v, const T* __restrict__ hp,
+                                               T* __restrict__ q, int logn, T inv_h) {
+  const int64_t C = (int64_t)1 << (DIM * logn);
+  const int64_t c = xcd_block(gridDim.x) * blockDim.x + threadIdx.x;
+  if (c >= C) return;
+  const Nbr nb = neighbours<DIM>(c, logn);
+  T div = 0;
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) div += (v[a * C + nb.p[a]] - v[a * C + c]) * inv_h;
+  q[c] = -div - (hp ? hp[c] : T(0));
+}
+
+// v <- v - vmean + h (phi_c - phi_{c-e_a});  pi = -c0 h^2 phi + eta q.
+template <typename T, int DIM>
+__global__ void __launch_bounds__(256) k_ps_finish(T* __restrict__ v, const T* __restrict__ phi,
+                                                   const T* __restrict__ q, T* __restrict__ pi, int logn,
+                                                   T h, T c0h2, T eta, const double* __restrict__ vmean) {
+  const int64_t C = (int64_t)1 << (DIM * logn);
+  const int64_t c = xcd_block(gridDim.x) * blockDim.x + threadIdx.x;
+  if (c >= C) return;
+  const Nbr nb = neighbours<DIM>(c, logn);
+  const T ph = phi[c];
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) {
+    T m = vmean ? (T)vmean[a] : T(0);
+    v[a * C + c] = v[a * C + c] - m + h * (ph - phi[nb.m[a]]);
+  }
+  pi[c] = -c0h2 * ph + eta * q[c];
+}
+
+// Centred advective term N(v)^a = sum_b vbar^b (v^a_{c+e_b} - v^a_{c-e_b}) / (2h),
+// vbar^b the average of the four b-faces around the a-face (b != a).
+template <int DIM>
+__global__ void __launch_bounds__(256) k_advect(const double* __restrict__ v, double* __restrict__ N, int logn,
+                                                double inv_2h) {
+  const int64_t C = (int64_t)1 << (DIM * logn);
+  const int64_t c = xcd_block(gridDim.x) * blockDim.x + threadIdx.x;
+  if (c >= C) return;
+  const int n = 1 << logn;
+  const int mask = n - 1;
+  const Nbr nb = neighbours<DIM>(c, logn);
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) {
+    const double* va = v + a * C;
+    double acc = 0;
+#pragma unroll
+    for (int b = 0; b < DIM; ++b) {
+      double vb;
+      if (b == a) {
+        vb = va[c];
+      } else {
+        const double* w = v + b * C;
+        const int64_t cm = nb.m[a];  // c - e_a
+        // (c - e_a) + e_b
+        const Nbr nm = neighbours<DIM>(cm, logn);
+        vb = 0.25 * (w[c] + w[nb.p[b]] + w[cm] + w[nm.p[b]]);
+      }
+      acc += vb * (va[nb.p[b]] - va[nb.m[b]]) * inv_2h;
+    }
+    N[a * C + c] = acc;
+  }
+  (void)mask;
+}
+
+// g = (rho/dt) v - rho (w1 N1 + w0 N0)   (N0 may be null)
+__global__ void k_ns_rhs(const double* __restrict__ v, const double* __restrict__ N1,
+                         const double* __restrict__ N0, double* __restrict__ g, int64_t len, double rdt,
+                         double rho, double w1, double w0) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= len) return;
+  double s = w1 * N1[i];
+  if (N0) s += w0 * N0[i];
+  g[i] = rdt * v[i] - rho * s;
+}
+
+inline unsigned nblk(int64_t len, int bs = 256) { return (unsigned)((len + bs - 1) / bs); }
+
+}  // namespace
+
+template <typename TI, typename TO>
+void launch_stokes_apply(int dim, int logn, const TI* v, const TI* p, TO* yv, TO* yp, double c0,
+                         double ch2, double inv_h, const double* addc, hipStream_t s) {
+  const int64_t C = (int64_t)1 << (dim * logn);
+  if (dim == 3)
+    hipLaunchKernelGGL((k_stokes_apply<TI, TO, 3>), dim3(nblk(C)), dim3(256), 0, s, v, p, yv, yp, logn, (TO)c0,
+                       (TO)ch2, (TO)inv_h, addc);
+  else
+    hipLaunchKernelGGL((k_stokes_apply<TI, TO, 2>), dim3(nblk(C)), dim3(256), 0, s, v, p, yv, yp, logn, (TO)c0,
+                       (TO)ch2, (TO)inv_h, addc);
+}
+template void launch_stokes_apply<double, double>(int, int, const double*, const double*, double*, double*,
+                                                  double, double, double, const double*, hipStream_t);
+template void launch_stokes_apply<float, double>(int, int, const float*, const float*, double*, double*,
+                                                 double, double, double, const double*, hipStream_t);
+template void launch_stokes_apply<float, float>(int, int, const float*, const float*, float*, float*, double,
+                                                double, double, const double*, hipStream_t);
+
+template <typename T>
+void launch_div_q(int dim, int logn, const T* v, const T* hp, T* q, double inv_h, hipStream_t s) {
+  const int64_t C = (int64_t)1 << (dim * logn);
+  if (dim == 3)
+    hipLaunchKernelGGL((k_div_q<T, 3>), dim3(nblk(C)), dim3(256), 0, s, v, hp, q, logn, (T)inv_h);
+  else
+    hipLaunchKernelGGL((k_div_q<T, 2>), dim3(nblk(C)), dim3(256), 0, s, v, hp, q, logn, (T)inv_h);
+}
+template void launch_div_q<double>(int, int, const double*, const double*, double*, double, hipStream_t);
+template void launch_div_q<float>(int, int, const float*, const float*, float*, double, hipStream_t);
+
+template <typename T>
+void launch_ps_finish(int dim, int logn, T* v, const T* phi, const T* q, T* pi, double h, double c0h2,
+                      double eta, const double* vmean, hipStream_t s) {
+  const int64_t C = (int64_t)1 << (dim * logn);
+  if (dim == 3)
+    hipLaunchKernelGGL((k_ps_finish<T, 3>), dim3(nblk(C)), dim3(256), 0, s, v, phi, q, pi, logn, (T)h, (T)c0h2,
+                       (T)eta, vmean);
+  else
+    hipLaunchKernelGGL((k_ps_finish<T, 2>), dim3(nblk(C)), dim3(256), 0, s, v, phi, q, pi, logn, (T)h, (T)c0h2,
+                       (T)eta, vmean);
+}
+template void launch_ps_finish<double>(int, int, double*, const double*, const double*, double*, double, double,
+                                       double, const double*, hipStream_t);
+template void launch_ps_finish<float>(int, int, float*, const float*, const float*, float*, double, double,
+                                      double, const double*, hipStream_t);
+
+void launch_advect(int dim, int logn, const double* v, double* N, double inv_2h, hipStream_t s) {
+  const int64_t C = (int64_t)1 << (dim * logn);
+  if (dim == 3)
+    hipLaunchKernelGGL((k_advect<3>), dim3(nblk(C)), dim3(256), 0, s, v, N, logn, inv_2h);
+  else
+    hipLaunchKernelGGL((k_advect<2>), dim3(nblk(C)), dim3(256), 0, s, v, N, logn, inv_2h);
+}
+
+void launch_ns_rhs(const double* v, const double* N1, const double* N0, double* g, int64_t len, double rdt,
+                   double rho, double w1, double w0, hipStream_t s) {
+  hipLaunchKernelGGL(k_ns_rhs, dim3(nblk(len)), dim3(256), 0, s, v, N1, N0, g, len, rdt, rho, w1, w0);
+}
+
+}  // namespace ibr

@@ -1,0 +1,463 @@
+// Fluid-marker coupling (Sec. 3.1): interpolation J, spreading S, marker
+// binning, rigid-body kinematics and body force / torque sums (Sec. 2).
+//
+// Spreading is a deterministic, atomic-free GATHER: markers are binned by the
+// 8^3 (2D: 16^2) tile that holds their cell; each workgroup owns one active
+// tile, pulls the markers of the neighbouring tiles into LDS in a fixed order
+// and sums their weights into its own faces.  Interpolation gives one
+// wavefront to each marker: 64 lanes = the 4^3 taps, reduced with shuffles.
+#include "kernels.h"
+
+namespace ibr {
+
+namespace {
+
+inline unsigned nblk(int64_t len, int bs = 256) { return (unsigned)((len + bs - 1) / bs); }
+
+__device__ inline int tap_base_index(int m, int s, int beta) { return (m * 2 + s) * 3 + beta; }
+
+// ---------------------------------------------------------------- marker set-up
+__global__ void k_marker_setup(int dim, int logn, int N, double h, double L, const double* __restrict__ R,
+                               int* __restrict__ base, double* __restrict__ w64, float* __restrict__ w32,
+                               int* __restrict__ tile_of, int tile_log) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= N) return;
+  const int n = 1 << logn;
+  const int nt_log = logn - tile_log;
+  int tile = 0;
+  for (int beta = dim - 1; beta >= 0; --beta) {
+    double x = R[m * dim + beta];
+    x = x - L * floor(x / L);
+    for (int s = 0; s < 2; ++s) {
+      const double sc = x / h - (s == 0 ? 0.5 : 0.0);
+      const double fl = floor(sc);
+      const int b0 = (int)fl - 1;
+      const int bi = tap_base_index(m, s, beta);
+      base[bi] = b0;
+      for (int t = 0; t < 4; ++t) {
+        const double w = phi4<double>(sc - (double)(b0 + t));
+        w64[bi * 4 + t] = w;
+        w32[bi * 4 + t] = (float)w;
+      }
+    }
+    const int cell = ((int)floor(x / h)) & (n - 1);
+    tile = (tile << nt_log) | (cell >> tile_log);
+  }
+  tile_of[m] = tile;
+}
+
+__global__ void k_marker_velocity(int dim, int N, const double* __restrict__ R, const int* __restrict__ body,
+                                  const double* __restrict__ X, const double* __restrict__ U,
+                                  const double* __restrict__ Om, double L, double* __restrict__ V) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= N) return;
+  const int b = body[m];
+  double r[3] = {0, 0, 0};
+  for (int a = 0; a < dim; ++a) {
+    double d = R[m * dim + a] - X[b * dim + a];
+    d -= L * rint(d / L);
+    r[a] = d;
+  }
+  if (dim == 2) {
+    const double w = Om[b];
+    V[m * 2 + 0] = U[b * 2 + 0] - w * r[1];
+    V[m * 2 + 1] = U[b * 2 + 1] + w * r[0];
+  } else {
+    const double* w = Om + 3 * b;
+    V[m * 3 + 0] = U[b * 3 + 0] + (w[1] * r[2] - w[2] * r[1]);
+    V[m * 3 + 1] = U[b * 3 + 1] + (w[2] * r[0] - w[0] * r[2]);
+    V[m * 3 + 2] = U[b * 3 + 2] + (w[0] * r[1] - w[1] * r[0]);
+  }
+}
+
+__global__ void k_move_markers(int dim, int N, int nb, double* __restrict__ R, double* __restrict__ X,
+                               const int* __restrict__ body, const double* __restrict__ U, double dt, double L) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < N) {
+    const int b = body[t];
+    for (int a = 0; a < dim; ++a) {
+      double x = R[t * dim + a] + dt * U[b * dim + a];
+      R[t * dim + a] = x - L * floor(x / L);
+    }
+  } else if (t < N + nb) {
+    const int b = t - N;
+    for (int a = 0; a < dim; ++a) {
+      double x = X[b * dim + a] + dt * U[b * dim + a];
+      X[b * dim + a] = x - L * floor(x / L);
+    }
+  }
+}
+
+// ---------------------------------------------------------------- binning
+__global__ void k_bin_count(int N, const int* __restrict__ tile_of, int* __restrict__ counts) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m < N) atomicAdd(&counts[tile_of[m]], 1);
+}
+
+// Exclusive scan of counts[0..n) into off[0..n], single workgroup of 1024.
+__global__ void __launch_bounds__(1024) k_scan(const int* __restrict__ counts, int n, int* __restrict__ off) {
+  __shared__ int sums[1024];
+  const int tid = threadIdx.x;
+  const int chunk = (n + 1023) / 1024;
+  const int lo = tid * chunk;
+  const int hi = min(n, lo + chunk);
+  int s = 0;
+  for (int i = lo; i < hi; ++i) s += counts[i];
+  sums[tid] = s;
+  __syncthreads();
+  for (int d = 1; d < 1024; d <<= 1) {
+    int v = tid >= d ? sums[tid - d] : 0;
+    __syncthreads();
+    sums[tid] += v;
+    __syncthreads();
+  }
+  int run = sums[tid] - s;
+  for (int i = lo; i < hi; ++i) {
+    off[i] = run;
+    run += counts[i];
+  }
+  if (tid == 1023) off[n] = sums[1023];
+}
+
+__global__ void k_bin_scatter(int N, const int* __restrict__ tile_of, const int* __restrict__ off,
+                              int* __restrict__ cursor, int* __restrict__ perm) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= N) return;
+  const int t = tile_of[m];
+  const int pos = off[t] + atomicAdd(&cursor[t], 1);
+  perm[pos] = m;
+}
+
+// Sort each tile's segment by marker index (fixed order => deterministic sums).
+__global__ void k_bin_sort(int ntiles, const int* __restrict__ off, int* __restrict__ perm) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ntiles) return;
+  const int lo = off[t], hi = off[t + 1];
+  for (int i = lo + 1; i < hi; ++i) {
+    const int v = perm[i];
+    int j = i - 1;
+    while (j >= lo && perm[j] > v) {
+      perm[j + 1] = perm[j];
+      --j;
+    }
+    perm[j + 1] = v;
+  }
+}
+
+// Distinct neighbour tile coordinates along one axis (1, 2 or 3 of them).
+__device__ inline int nbr_coords(int t, int nt, int* out) {
+  if (nt == 1) {
+    out[0] = 0;
+    return 1;
+  }
+  if (nt == 2) {
+    out[0] = t;
+    out[1] = t ^ 1;
+    return 2;
+  }
+  out[0] = (t - 1 + nt) % nt;
+  out[1] = t;
+  out[2] = (t + 1) % nt;
+  return 3;
+}
+
+__global__ void k_active_tiles(int dim, int tiles_log, const int* __restrict__ off, int* __restrict__ flags,
+                               int* __restrict__ list, int* __restrict__ count) {
+  const int nt = 1 << tiles_log;
+  const int ntiles = 1 << (dim * tiles_log);
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ntiles) return;
+  int tc[3] = {t & (nt - 1), (t >> tiles_log) & (nt - 1), dim == 3 ? (t >> (2 * tiles_log)) : 0};
+  int cx[3], cy[3], cz[3];
+  const int nx = nbr_coords(tc[0], nt, cx);
+  const int ny = nbr_coords(tc[1], nt, cy);
+  const int nz = dim == 3 ? nbr_coords(tc[2], nt, cz) : 1;
+  if (dim == 2) cz[0] = 0;
+  int any = 0;
+  for (int a = 0; a < nz; ++a)
+    for (int b = 0; b < ny; ++b)
+      for (int c = 0; c < nx; ++c) {
+        const int tt = cx[c] | (cy[b] << tiles_log) | (cz[a] << (2 * tiles_log));
+        if (off[tt + 1] > off[tt]) any = 1;
+      }
+  flags[t] = any;
+  if (any) {
+    const int pos = atomicAdd(count, 1);
+    list[pos] = t;
+  }
+}
+
+// ---------------------------------------------------------------- spreading (gather)
+constexpr int kSpreadThreads = 256;
+constexpr int kSpreadChunk = 64;
+
+template <typename TL, typename TY>
+__global__ void __launch_bounds__(kSpreadThreads) k_spread(int dim, int logn, int tile_log,
+                                                            const int* __restrict__ active,
+                                                            const int* __restrict__ off,
+                                                            const int* __restrict__ perm,
+                                                            const int* __restrict__ tbase,
+                                                            const double* __restrict__ tw,
+                                                            const TL* __restrict__ lam, TY* __restrict__ y,
+                                                            double scale) {
+  __shared__ int s_base[kSpreadChunk][2][3];
+  __shared__ double s_w[kSpreadChunk][2][3][4];
+  __shared__ double s_lam[kSpreadChunk][3];
+  __shared__ int s_ids[kSpreadChunk];
+  constexpr int kMaxFaces = 6;  // faces per thread: 8^3*3/256 (3D), 16^2*2/256 (2D)
+
+  const int n = 1 << logn;
+  const int64_t C = (int64_t)1 << (dim * logn);
+  const int tiles_log = logn - tile_log;
+  const int nt = 1 << tiles_log;
+  const int tile = active[blockIdx.x];
+  const int tsz = 1 << tile_log;
+  const int tc[3] = {tile & (nt - 1), (tile >> tiles_log) & (nt - 1), dim == 3 ? (tile >> (2 * tiles_log)) : 0};
+  const int cells = 1 << (dim * tile_log);
+  const int nfaces = cells * dim;
+
+  // faces owned by this thread
+  double acc[kMaxFaces];
+  int fc[kMaxFaces][3];
+  int fa[kMaxFaces];
+  int nf = 0;
+  for (int f = threadIdx.x; f < nfaces && nf < kMaxFaces; f += blockDim.x, ++nf) {
+    const int a = f / cells;
+    const int lc = f - a * cells;
+    fa[nf] = a;
+    fc[nf][0] = tc[0] * tsz + (lc & (tsz - 1));
+    fc[nf][1] = tc[1] * tsz + ((lc >> tile_log) & (tsz - 1));
+    fc[nf][2] = dim == 3 ? tc[2] * tsz + (lc >> (2 * tile_log)) : 0;
+    acc[nf] = 0.0;
+  }
+
+  int cx[3], cy[3], cz[3];
+  const int nx = nbr_coords(tc[0], nt, cx);
+  const int ny = nbr_coords(tc[1], nt, cy);
+  const int nz = dim == 3 ? nbr_coords(tc[2], nt, cz) : 1;
+  if (dim == 2) cz[0] = 0;
+
+  for (int a3 = 0; a3 < nz; ++a3)
+    for (int b3 = 0; b3 < ny; ++b3)
+      for (int c3 = 0; c3 < nx; ++c3) {
+        const int tt = cx[c3] | (cy[b3] << tiles_log) | (cz[a3] << (2 * tiles_log));
+        const int lo = off[tt], hi = off[tt + 1];
+        for (int c0 = lo; c0 < hi; c0 += kSpreadChunk) {
+          const int cnt = min(kSpreadChunk, hi - c0);
+          __syncthreads();
+          for (int q = threadIdx.x; q < cnt; q += blockDim.x) {
+            const int m = perm[c0 + q];
+            s_ids[q] = m;
+            for (int d = 0; d < dim; ++d) s_lam[q][d] = (double)lam[m * dim + d];
+          }
+          for (int q = threadIdx.x; q < cnt * 2 * 3; q += blockDim.x) {
+            const int mm = q / 6, r = q - mm * 6;
+            const int m = perm[c0 + mm];
+            s_base[mm][r / 3][r % 3] = tbase[m * 6 + r];
+            for (int t = 0; t < 4; ++t) s_w[mm][r / 3][r % 3][t] = tw[(m * 6 + r) * 4 + t];
+          }
+          __syncthreads();
+          for (int q = 0; q < cnt; ++q) {
+            for (int f = 0; f < nf; ++f) {
+              const int a = fa[f];
+              double w = s_lam[q][a];
+              bool in = true;
+              for (int d = 0; d < dim; ++d) {
+                const int s = d == a ? 1 : 0;
+                const int t = (fc[f][d] - s_base[q][s][d]) & (n - 1);
+                if (t >= 4) {
+                  in = false;
+                  break;
+                }
+                w *= s_w[q][s][d][t];
+              }
+              if (in) acc[f] += w;
+            }
+          }
+        }
+      }
+  for (int f = 0; f < nf; ++f) {
+    const int64_t c = (int64_t)fc[f][0] + ((int64_t)fc[f][1] << logn) + ((int64_t)fc[f][2] << (2 * logn));
+    const int64_t idx = fa[f] * C + c;
+    y[idx] = (TY)((double)y[idx] + scale * acc[f]);
+  }
+}
+
+// ---------------------------------------------------------------- interpolation
+template <typename TV>
+__global__ void __launch_bounds__(256) k_interp(int dim, int logn, int N, const int* __restrict__ tbase,
+                                                const double* __restrict__ tw, const TV* __restrict__ v,
+                                                double alpha, const double* __restrict__ add, double beta,
+                                                double* __restrict__ out) {
+  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int lane = threadIdx.x & (kWave - 1);
+  if (wave >= N) return;
+  const int m = wave;
+  const int n = 1 << logn;
+  const int64_t C = (int64_t)1 << (dim * logn);
+  const int tx = lane & 3, ty = (lane >> 2) & 3, tz = lane >> 4;
+  const bool live = dim == 3 || lane < 16;
+  for (int a = 0; a < dim; ++a) {
+    double val = 0.0;
+    if (live) {
+      const int sx = a == 0, sy = a == 1, sz = a == 2;
+      const int bx = tbase[m * 6 + sx * 3 + 0], by = tbase[m * 6 + sy * 3 + 1];
+      const int ix = (bx + tx) & (n - 1), iy = (by + ty) & (n - 1);
+      double w = tw[(m * 6 + sx * 3 + 0) * 4 + tx] * tw[(m * 6 + sy * 3 + 1) * 4 + ty];
+      int64_t c = ix + ((int64_t)iy << logn);
+      if (dim == 3) {
+        const int bz = tbase[m * 6 + sz * 3 + 2];
+        const int iz = (bz + tz) & (n - 1);
+        w *= tw[(m * 6 + sz * 3 + 2) * 4 + tz];
+        c += (int64_t)iz << (2 * logn);
+      }
+      val = w * (double)v[a * C + c];
+    }
+    val = wave_sum(val);
+    if (lane == 0) {
+      double o = alpha * val;
+      if (add) o += beta * add[m * dim + a];
+      out[m * dim + a] = o;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- reductions
+__global__ void __launch_bounds__(256) k_lambda_partial(int dim, int N, const double* __restrict__ lam,
+                                                        double* __restrict__ part) {
+  __shared__ double red[256 / kWave];
+  for (int a = 0; a < dim; ++a) {
+    double s = 0;
+    for (int m = blockIdx.x * blockDim.x + threadIdx.x; m < N; m += gridDim.x * blockDim.x) s += lam[m * dim + a];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) part[a * gridDim.x + blockIdx.x] = s;
+  }
+}
+
+__global__ void k_lambda_finish(int dim, int nblocks, const double* __restrict__ part, double scale,
+                                double* __restrict__ out) {
+  __shared__ double red[256 / kWave];
+  for (int a = 0; a < dim; ++a) {
+    double s = 0;
+    for (int i = threadIdx.x; i < nblocks; i += blockDim.x) s += part[a * nblocks + i];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) out[a] = s * scale;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_body_ft(int dim, const int* __restrict__ off, const double* __restrict__ R,
+                                                 const double* __restrict__ X, double L,
+                                                 const double* __restrict__ lam, double* __restrict__ F,
+                                                 double* __restrict__ T) {
+  __shared__ double red[256 / kWave];
+  const int b = blockIdx.x;
+  const int lo = off[b], hi = off[b + 1];
+  double f[3] = {0, 0, 0}, t[3] = {0, 0, 0};
+  for (int m = lo + threadIdx.x; m < hi; m += blockDim.x) {
+    double r[3] = {0, 0, 0}, l[3] = {0, 0, 0};
+    for (int a = 0; a < dim; ++a) {
+      double d = R[m * dim + a] - X[b * dim + a];
+      d -= L * rint(d / L);
+      r[a] = d;
+      l[a] = lam[m * dim + a];
+      f[a] += l[a];
+    }
+    if (dim == 2) {
+      t[0] += r[0] * l[1] - r[1] * l[0];
+    } else {
+      t[0] += r[1] * l[2] - r[2] * l[1];
+      t[1] += r[2] * l[0] - r[0] * l[2];
+      t[2] += r[0] * l[1] - r[1] * l[0];
+    }
+  }
+  const int nt = dim == 3 ? 3 : 1;
+  for (int a = 0; a < dim; ++a) {
+    double s = block_sum(f[a], red);
+    if (threadIdx.x == 0) F[b * dim + a] = s;
+  }
+  for (int a = 0; a < nt; ++a) {
+    double s = block_sum(t[a], red);
+    if (threadIdx.x == 0) T[b * nt + a] = s;
+  }
+}
+
+}  // namespace
+
+void launch_marker_setup(int dim, int logn, int N, double h, double L, const double* R, MarkerTaps taps,
+                         int* tile_of, int tile_log, hipStream_t s) {
+  if (N <= 0) return;
+  hipLaunchKernelGGL(k_marker_setup, dim3(nblk(N)), dim3(256), 0, s, dim, logn, N, h, L, R, taps.base, taps.w64,
+                     taps.w32, tile_of, tile_log);
+}
+
+void launch_marker_velocity(int dim, int N, const double* R, const int* body, const double* centres,
+                            const double* U, const double* Om, double L, double* V, hipStream_t s) {
+  if (N <= 0) return;
+  hipLaunchKernelGGL(k_marker_velocity, dim3(nblk(N)), dim3(256), 0, s, dim, N, R, body, centres, U, Om, L, V);
+}
+
+void launch_move_markers(int dim, int N, int nb, double* R, double* centres, const int* body, const double* U,
+                         double dt, double L, hipStream_t s) {
+  hipLaunchKernelGGL(k_move_markers, dim3(nblk(N + nb)), dim3(256), 0, s, dim, N, nb, R, centres, body, U, dt, L);
+}
+
+void launch_bin_markers(int N, int ntiles, const int* tile_of, int* counts, int* offsets, int* cursor, int* perm,
+                        hipStream_t s) {
+  launch_fill<int>(counts, ntiles, 0, s);
+  launch_fill<int>(cursor, ntiles, 0, s);
+  if (N > 0) hipLaunchKernelGGL(k_bin_count, dim3(nblk(N)), dim3(256), 0, s, N, tile_of, counts);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, counts, ntiles, offsets);
+  if (N > 0) {
+    hipLaunchKernelGGL(k_bin_scatter, dim3(nblk(N)), dim3(256), 0, s, N, tile_of, offsets, cursor, perm);
+    hipLaunchKernelGGL(k_bin_sort, dim3(nblk(ntiles)), dim3(256), 0, s, ntiles, offsets, perm);
+  }
+}
+
+void launch_active_tiles(int dim, int tiles_log, const int* offsets, int* flags, int* active_list,
+                         int* active_count, hipStream_t s) {
+  const int ntiles = 1 << (dim * tiles_log);
+  launch_fill<int>(active_count, 1, 0, s);
+  hipLaunchKernelGGL(k_active_tiles, dim3(nblk(ntiles)), dim3(256), 0, s, dim, tiles_log, offsets, flags,
+                     active_list, active_count);
+}
+
+template <typename TL, typename TY>
+void launch_spread(int dim, int logn, int tile_log, int nactive, const int* active_list, const int* offsets,
+                   const int* perm, MarkerTaps taps, const TL* lam, TY* y, double scale, hipStream_t s) {
+  if (nactive <= 0) return;
+  hipLaunchKernelGGL((k_spread<TL, TY>), dim3(nactive), dim3(kSpreadThreads), 0, s, dim, logn, tile_log,
+                     active_list, offsets, perm, taps.base, taps.w64, lam, y, scale);
+}
+template void launch_spread<double, double>(int, int, int, int, const int*, const int*, const int*, MarkerTaps,
+                                            const double*, double*, double, hipStream_t);
+template void launch_spread<float, double>(int, int, int, int, const int*, const int*, const int*, MarkerTaps,
+                                           const float*, double*, double, hipStream_t);
+template void launch_spread<double, float>(int, int, int, int, const int*, const int*, const int*, MarkerTaps,
+                                           const double*, float*, double, hipStream_t);
+
+template <typename TV>
+void launch_interp(int dim, int logn, int N, MarkerTaps taps, const TV* v, double alpha, const double* add,
+                   double beta, double* out, hipStream_t s) {
+  if (N <= 0) return;
+  const int64_t threads = (int64_t)N * kWave;
+  hipLaunchKernelGGL((k_interp<TV>), dim3(nblk(threads)), dim3(256), 0, s, dim, logn, N, taps.base, taps.w64, v,
+                     alpha, add, beta, out);
+}
+template void launch_interp<double>(int, int, int, MarkerTaps, const double*, double, const double*, double,
+                                    double*, hipStream_t);
+template void launch_interp<float>(int, int, int, MarkerTaps, const float*, double, const double*, double,
+                                   double*, hipStream_t);
+
+void launch_lambda_sums(int dim, int N, const double* lam, double* part, double* out, double scale,
+                        hipStream_t s) {
+  const int nb = 64;
+  hipLaunchKernelGGL(k_lambda_partial, dim3(nb), dim3(256), 0, s, dim, N, lam, part);
+  hipLaunchKernelGGL(k_lambda_finish, dim3(1), dim3(256), 0, s, dim, nb, part, scale, out);
+}
+
+void launch_body_force_torque(int dim, int nb, const int* offsets, const double* R, const double* centres,
+                              double L, const double* lam, double* F, double* T, hipStream_t s) {
+  hipLaunchKernelGGL(k_body_ft, dim3(nb), dim3(256), 0, s, dim, offsets, R, centres, L, lam, F, T);
+}
+
+}  // namespace ibr

@@ -1,0 +1,476 @@
+// Geometric multigrid V-cycle for (c0 - c1 L) x = b on periodic n^dim lattices
+// (Sec. 5.2 approximates A^-1 and L_p^-1 by one V-cycle each).
+//
+// Cycle: red-black Gauss-Seidel (red = even i+j+k first), nu_pre sweeps from a
+// zero guess, residual + 2^dim averaging, rediscretised coarse operator
+// (c0 - c1/4 L), cell-centred multilinear prolongation (3/4, 1/4 per axis),
+// nu_post sweeps, nu_coarse sweeps on the 4^dim grid.  Singular problems
+// (c0 == 0) lose the mean of the coarsest right-hand side; the finest-level
+// mean of x is removed by the caller.
+//
+// Fine levels run one kernel per step with nfields batched in blockIdx.y.
+// Every level with at most 4096 cells runs inside ONE workgroup per field
+// (k_vcycle_lds), with the lattice held in LDS: the coarse tail of the cycle
+// costs one launch instead of ~10 per level.
+#include "kernels.h"
+
+namespace ibr {
+
+namespace {
+
+constexpr int kLdsCells = 4096;   // largest level handled inside one workgroup
+constexpr int kLdsThreads = 512;
+
+// ---------------------------------------------------------------- helpers
+template <int DIM>
+__device__ inline void cell_coords(int64_t c, int logn, int& i, int& j, int& k) {
+  const int mask = (1 << logn) - 1;
+  i = (int)(c & mask);
+  j = (int)((c >> logn) & mask);
+  k = DIM == 3 ? (int)(c >> (2 * logn)) : 0;
+}
+
+template <int DIM>
+__device__ inline int64_t cell_index(int i, int j, int k, int logn) {
+  const int mask = (1 << logn) - 1;
+  int64_t c = (int64_t)(i & mask) + ((int64_t)(j & mask) << logn);
+  if (DIM == 3) c += (int64_t)(k & mask) << (2 * logn);
+  return c;
+}
+
+template <typename T, int DIM>
+__device__ inline T nbr_sum(const T* x, int i, int j, int k, int logn) {
+  T s = x[cell_index<DIM>(i - 1, j, k, logn)] + x[cell_index<DIM>(i + 1, j, k, logn)] +
+        x[cell_index<DIM>(i, j - 1, k, logn)] + x[cell_index<DIM>(i, j + 1, k, logn)];
+  if (DIM == 3) s += x[cell_index<DIM>(i, j, k - 1, logn)] + x[cell_index<DIM>(i, j, k + 1, logn)];
+  return s;
+}
+
+// Cell of colour `color` with colour-local index t (half the cells): row-major
+// pairs, the colour picks the parity inside each pair.
+template <int DIM>
+__device__ inline void colour_cell(int64_t t, int logn, int color, int& i, int& j, int& k) {
+  const int half_log = logn - 1;
+  const int m = (int)(t & ((1 << half_log) - 1));
+  const int64_t row = t >> half_log;
+  const int mask = (1 << logn) - 1;
+  j = (int)(row & mask);
+  k = DIM == 3 ? (int)(row >> logn) : 0;
+  i = 2 * m + ((j + k + color) & 1);
+}
+
+// ---------------------------------------------------------------- fine-level kernels
+// One red-black half sweep.  from_zero: x is treated as 0 on entry (first red
+// pass of pre-smoothing): red cells get b/diag and black cells 0.
+template <typename T, int DIM>
+__global__ void __launch_bounds__(256) k_rb(T* __restrict__ x, const T* __restrict__ b, int logn, T c0, T c1,
+                                            int color, int from_zero) {
+  const int64_t C = (int64_t)1 << (DIM * logn);
+  const int64_t t = xcd_block(gridDim.x) * blockDim.x + threadIdx.x;
+  if (t >= C / 2) return;
+  const int64_t f = blockIdx.y;
+  x += f * C;
+  b += f * C;
+  int i, j, k;
+  colour_cell<DIM>(t, logn, color, i, j, k);
+  const int64_t c = cell_index<DIM>(i, j, k, logn);
+  const T inv_diag = T(1) / (c0 + T(2 * DIM) * c1);
+  if (from_zero) {
+    x[c] = b[c] * inv_diag;
+    x[cell_index<DIM>(i ^ 1, j, k, logn)] = T(0);
+  } else {
+    x[c] = (b[c] + c1 * nbr_sum<T, DIM>(x, i, j, k, logn)) * inv_diag;
+  }
+}
+
+// Coarse right-hand side = average over the 2^dim children of the residual.
+template <typename T, int DIM>
+__global__ void __launch_bounds__(256) k_resid_restrict(const T* __restrict__ x, const T* __restrict__ b,
+                                                        T* __restrict__ bc, int logn, T c0, T c1) {
+  const int lognc = logn - 1;
+  const int64_t Cc = (int64_t)1 << (DIM * lognc);
+  const int64_t C = (int64_t)1 << (DIM * logn);
+  const int64_t t = xcd_block(gridDim.x) * blockDim.x + threadIdx.x;
+  if (t >= Cc) return;
+  const int64_t f = blockIdx.y;
+  x += f * C;
+  b += f * C;
+  int I, J, K;
+  cell_coords<DIM>(t, lognc, I, J, K);
+  const T diag = c0 + T(2 * DIM) * c1;
+  T acc = 0;
+#pragma unroll
+  for (int dk = 0; dk < (DIM == 3 ? 2 : 1); ++dk)
+#pragma unroll
+    for (int dj = 0; dj < 2; ++dj)
+#pragma unroll
+      for (int di = 0; di < 2; ++di) {
+        const int i = 2 * I + di, j = 2 * J + dj, k = 2 * K + dk;
+        const int64_t c = cell_index<DIM>(i, j, k, logn);
+        acc += b[c] - (diag * x[c] - c1 * nbr_sum<T, DIM>(x, i, j, k, logn));
+      }
+  bc[f * Cc + t] = acc * (DIM == 3 ? T(0.125) : T(0.25));
+}
+
+// x += P e (multilinear, cell-centred).
+template <typename T, int DIM>
+__global__ void __launch_bounds__(256) k_prolong_add(T* __restrict__ x, const T* __restrict__ e, int logn) {
+  const int64_t C = (int64_t)1 << (DIM * logn);
+  const int lognc = logn - 1;
+  const int64_t Cc = (int64_t)1 << (DIM * lognc);
+  const int64_t c = xcd_block(gridDim.x) * blockDim.x + threadIdx.x;
+  if (c >= C) return;
+  const int64_t f = blockIdx.y;
+  x += f * C;
+  e += f * Cc;
+  int i, j, k;
+  cell_coords<DIM>(c, logn, i, j, k);
+  const int I = i >> 1, J = j >> 1, K = k >> 1;
+  const int si = (i & 1) ? 1 : -1, sj = (j & 1) ? 1 : -1, sk = (k & 1) ? 1 : -1;
+  T v;
+  if (DIM == 3) {
+    const T w0 = T(0.75), w1 = T(0.25);
+    T a00 = w0 * e[cell_index<DIM>(I, J, K, lognc)] + w1 * e[cell_index<DIM>(I + si, J, K, lognc)];
+    T a10 = w0 * e[cell_index<DIM>(I, J + sj, K, lognc)] + w1 * e[cell_index<DIM>(I + si, J + sj, K, lognc)];
+    T a01 = w0 * e[cell_index<DIM>(I, J, K + sk, lognc)] + w1 * e[cell_index<DIM>(I + si, J, K + sk, lognc)];
+    T a11 = w0 * e[cell_index<DIM>(I, J + sj, K + sk, lognc)] +
+            w1 * e[cell_index<DIM>(I + si, J + sj, K + sk, lognc)];
+    T b0 = w0 * a00 + w1 * a10;
+    T b1 = w0 * a01 + w1 * a11;
+    v = w0 * b0 + w1 * b1;
+  } else {
+    const T w0 = T(0.75), w1 = T(0.25);
+    T a0 = w0 * e[cell_index<DIM>(I, J, 0, lognc)] + w1 * e[cell_index<DIM>(I + si, J, 0, lognc)];
+    T a1 = w0 * e[cell_index<DIM>(I, J + sj, 0, lognc)] + w1 * e[cell_index<DIM>(I + si, J + sj, 0, lognc)];
+    v = w0 * a0 + w1 * a1;
+  }
+  x[c] += v;
+}
+
+// ---------------------------------------------------------------- one-workgroup tail
+template <typename T, int DIM>
+__device__ void lds_rb_sweeps(T* x, const T* b, int logn, T c0, T c1, int sweeps, bool from_zero) {
+  const int64_t C = (int64_t)1 << (DIM * logn);
+  const T inv_diag = T(1) / (c0 + T(2 * DIM) * c1);
+  if (from_zero) {
+    for (int64_t c = threadIdx.x; c < C; c += blockDim.x) x[c] = T(0);
+    __syncthreads();
+  }
+  for (int s = 0; s < sweeps; ++s) {
+    for (int color = 0; color < 2; ++color) {
+      for (int64_t t = threadIdx.x; t < C / 2; t += blockDim.x) {
+        int i, j, k;
+        colour_cell<DIM>(t, logn, color, i, j, k);
+        const int64_t c = cell_index<DIM>(i, j, k, logn);
+        x[c] = (b[c] + c1 * nbr_sum<T, DIM>(x, i, j, k, logn)) * inv_diag;
+      }
+      __syncthreads();
+    }
+  }
+}
+
+template <typename T, int DIM>
+__device__ void lds_resid_restrict(const T* x, const T* b, T* bc, int logn, T c0, T c1) {
+  const int lognc = logn - 1;
+  const int64_t Cc = (int64_t)1 << (DIM * lognc);
+  const T diag = c0 + T(2 * DIM) * c1;
+  for (int64_t t = threadIdx.x; t < Cc; t += blockDim.x) {
+    int I, J, K;
+    cell_coords<DIM>(t, lognc, I, J, K);
+    T acc = 0;
+    for (int dk = 0; dk < (DIM == 3 ? 2 : 1); ++dk)
+      for (int dj = 0; dj < 2; ++dj)
+        for (int di = 0; di < 2; ++di) {
+          const int i = 2 * I + di, j = 2 * J + dj, k = 2 * K + dk;
+          const int64_t c = cell_index<DIM>(i, j, k, logn);
+          acc += b[c] - (diag * x[c] - c1 * nbr_sum<T, DIM>(x, i, j, k, logn));
+        }
+    bc[t] = acc * (DIM == 3 ? T(0.125) : T(0.25));
+  }
+  __syncthreads();
+}
+
+template <typename T, int DIM>
+__device__ void lds_prolong_add(T* x, const T* e, int logn) {
+  const int64_t C = (int64_t)1 << (DIM * logn);
+  const int lognc = logn - 1;
+  const T w0 = T(0.75), w1 = T(0.25);
+  for (int64_t c = threadIdx.x; c < C; c += blockDim.x) {
+    int i, j, k;
+    cell_coords<DIM>(c, logn, i, j, k);
+    const int I = i >> 1, J = j >> 1, K = k >> 1;
+    const int si = (i & 1) ? 1 : -1, sj = (j & 1) ? 1 : -1, sk = (k & 1) ? 1 : -1;
+    T v;
+    if (DIM == 3) {
+      T a00 = w0 * e[cell_index<DIM>(I, J, K, lognc)] + w1 * e[cell_index<DIM>(I + si, J, K, lognc)];
+      T a10 = w0 * e[cell_index<DIM>(I, J + sj, K, lognc)] + w1 * e[cell_index<DIM>(I + si, J + sj, K, lognc)];
+      T a01 = w0 * e[cell_index<DIM>(I, J, K + sk, lognc)] + w1 * e[cell_index<DIM>(I + si, J, K + sk, lognc)];
+      T a11 = w0 * e[cell_index<DIM>(I, J + sj, K + sk, lognc)] +
+              w1 * e[cell_index<DIM>(I + si, J + sj, K + sk, lognc)];
+      T b0 = w0 * a00 + w1 * a10;
+      T b1 = w0 * a01 + w1 * a11;
+      v = w0 * b0 + w1 * b1;
+    } else {
+      T a0 = w0 * e[cell_index<DIM>(I, J, 0, lognc)] + w1 * e[cell_index<DIM>(I + si, J, 0, lognc)];
+      T a1 = w0 * e[cell_index<DIM>(I, J + sj, 0, lognc)] + w1 * e[cell_index<DIM>(I + si, J + sj, 0, lognc)];
+      v = w0 * a0 + w1 * a1;
+    }
+    x[c] += v;
+  }
+  __syncthreads();
+}
+
+template <typename T>
+__device__ void lds_remove_mean(T* b, int64_t C, T* red) {
+  T s = 0;
+  for (int64_t c = threadIdx.x; c < C; c += blockDim.x) s += b[c];
+  s = block_sum(s, red);
+  const T m = s / T(C);
+  __syncthreads();
+  for (int64_t c = threadIdx.x; c < C; c += blockDim.x) b[c] -= m;
+  __syncthreads();
+}
+
+// V-cycle from a level of at most kLdsCells cells down to n = 4, one field per
+// workgroup.  b is read from global memory (kept in L2), every other array of
+// the tail lives in LDS.  c1 is the coefficient at the entry level.
+template <typename T, int DIM>
+__global__ void __launch_bounds__(kLdsThreads) k_vcycle_lds(const T* __restrict__ bg, T* __restrict__ xg, int logn,
+                                                            T c0, T c1, int nu_pre, int nu_post, int nu_coarse) {
+  // x of every level back to back (entry level first); b of levels >= 1.
+  __shared__ T xs[kLdsCells * 4 / 3 + 64];
+  __shared__ T bs[kLdsCells / 3 + 64];
+  __shared__ T red[kLdsThreads / kWave];
+  const int64_t C0 = (int64_t)1 << (DIM * logn);
+  const T* b0 = bg + blockIdx.x * C0;
+  T* x0 = xg + blockIdx.x * C0;
+  const bool singular = c0 == T(0);
+
+  const int nlev = logn - 1;  // entry level down to n = 4
+  int64_t xoff[8], boff[8];
+  {
+    int64_t xo = 0, bo = 0;
+    for (int l = 0; l < nlev; ++l) {
+      const int64_t Cl = (int64_t)1 << (DIM * (logn - l));
+      xoff[l] = xo;
+      xo += Cl;
+      boff[l] = bo;
+      if (l >= 1) bo += Cl;
+    }
+  }
+  auto xlev = [&](int l) -> T* { return xs + xoff[l]; };
+  auto blev = [&](int l) -> T* { return bs + boff[l]; };
+
+  // The entry level reads b from global memory.
+  T cl = c1;
+  for (int l = 0; l < nlev - 1; ++l) {
+    const int lg = logn - l;
+    const T* bl = l == 0 ? b0 : blev(l);
+    lds_rb_sweeps<T, DIM>(xlev(l), bl, lg, c0, cl, nu_pre, true);
+    lds_resid_restrict<T, DIM>(xlev(l), bl, blev(l + 1), lg, c0, cl);
+    cl = cl * T(0.25);
+  }
+  {
+    const int l = nlev - 1;
+    const int lg = logn - l;
+    T* bl = l == 0 ? nullptr : blev(l);
+    if (l == 0) {
+      // whole cycle is the coarsest grid: copy b to LDS scratch first
+      bl = xs + kLdsCells;  // C0 <= 64 here
+      for (int64_t c = threadIdx.x; c < C0; c += blockDim.x) bl[c] = b0[c];
+      __syncthreads();
+    }
+    if (singular) lds_remove_mean<T>(bl, (int64_t)1 << (DIM * lg), red);
+    lds_rb_sweeps<T, DIM>(xlev(l), bl, lg, c0, cl, nu_coarse, true);
+  }
+  for (int l = nlev - 2; l >= 0; --l) {
+    cl = cl * T(4);
+    const int lg = logn - l;
+    const T* bl = l == 0 ? b0 : blev(l);
+    lds_prolong_add<T, DIM>(xlev(l), xlev(l + 1), lg);
+    lds_rb_sweeps<T, DIM>(xlev(l), bl, lg, c0, cl, nu_post, false);
+  }
+  for (int64_t c = threadIdx.x; c < C0; c += blockDim.x) x0[c] = xs[c];
+}
+
+// Per-field sums: partial[f][block] (deterministic two-pass reduction).
+template <typename T>
+__global__ void __launch_bounds__(256) k_field_partial(const T* __restrict__ x, int64_t C,
+                                                       double* __restrict__ part) {
+  __shared__ double red[256 / kWave];
+  const int64_t f = blockIdx.y;
+  double s = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < C; i += (int64_t)gridDim.x * blockDim.x)
+    s += (double)x[f * C + i];
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) part[f * gridDim.x + blockIdx.x] = s;
+}
+
+__global__ void k_field_finish(const double* __restrict__ part, int nblocks, double scale,
+                               double* __restrict__ out) {
+  __shared__ double red[256 / kWave];
+  const int f = blockIdx.x;
+  double s = 0;
+  for (int i = threadIdx.x; i < nblocks; i += blockDim.x) s += part[f * nblocks + i];
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) out[f] = s * scale;
+}
+
+template <typename T>
+__global__ void k_sub_field_mean(T* __restrict__ x, int64_t C, const double* __restrict__ mean) {
+  const int64_t f = blockIdx.y;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < C; i += (int64_t)gridDim.x * blockDim.x)
+    x[f * C + i] -= (T)mean[f];
+}
+
+template <typename T>
+__global__ void k_fill(T* __restrict__ x, int64_t len, T v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = v;
+}
+
+inline unsigned nblk(int64_t len, int bs = 256) { return (unsigned)((len + bs - 1) / bs); }
+
+}  // namespace
+
+int mg_lds_cells() { return kLdsCells; }
+
+template <typename T>
+void launch_fill(T* x, int64_t len, T v, hipStream_t s) {
+  unsigned g = nblk(len);
+  if (g > 8192) g = 8192;
+  if (g == 0) return;
+  hipLaunchKernelGGL(k_fill<T>, dim3(g), dim3(256), 0, s, x, len, v);
+}
+template void launch_fill<double>(double*, int64_t, double, hipStream_t);
+template void launch_fill<float>(float*, int64_t, float, hipStream_t);
+template void launch_fill<int>(int*, int64_t, int, hipStream_t);
+
+template <typename T>
+void launch_field_means(const T* x, int nf, int64_t C, double* part, int part_blocks, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_field_partial<T>, dim3(part_blocks, nf), dim3(256), 0, s, x, C, part);
+  hipLaunchKernelGGL(k_field_finish, dim3(nf), dim3(256), 0, s, part, part_blocks, 1.0 / (double)C, out);
+}
+template void launch_field_means<double>(const double*, int, int64_t, double*, int, double*, hipStream_t);
+template void launch_field_means<float>(const float*, int, int64_t, double*, int, double*, hipStream_t);
+
+template <typename T>
+void launch_sub_field_mean(T* x, int nf, int64_t C, const double* mean, hipStream_t s) {
+  unsigned g = nblk(C);
+  if (g > 4096) g = 4096;
+  hipLaunchKernelGGL(k_sub_field_mean<T>, dim3(g, nf), dim3(256), 0, s, x, C, mean);
+}
+template void launch_sub_field_mean<double>(double*, int, int64_t, const double*, hipStream_t);
+template void launch_sub_field_mean<float>(float*, int, int64_t, const double*, hipStream_t);
+
+template <typename T>
+void MGHier<T>::init(int dim_, int logn_, int maxf) {
+  dim = dim_;
+  logn = logn_;
+  nfmax = maxf;
+  levels.clear();
+  // multi-kernel levels: while the level has more cells than one workgroup holds
+  int lg = logn;
+  while (((int64_t)1 << (dim * lg)) > kLdsCells) {
+    levels.push_back(lg);
+    --lg;
+  }
+  lds_logn = lg;
+  bufs_x.assign(levels.size() + 1, nullptr);
+  bufs_b.assign(levels.size() + 1, nullptr);
+  for (size_t l = 1; l <= levels.size(); ++l) {
+    const int lgl = logn - (int)l;
+    const int64_t Cl = (int64_t)1 << (dim * lgl);
+    bufs_x[l] = dev_alloc<T>(Cl * nfmax);
+    bufs_b[l] = dev_alloc<T>(Cl * nfmax);
+  }
+}
+
+template <typename T>
+void MGHier<T>::release() {
+  for (auto p : bufs_x) dev_free(p);
+  for (auto p : bufs_b) dev_free(p);
+  bufs_x.clear();
+  bufs_b.clear();
+}
+
+template <typename T>
+size_t MGHier<T>::bytes(int dim, int logn, int nf) {
+  size_t tot = 0;
+  int lg = logn;
+  while (((int64_t)1 << (dim * lg)) > kLdsCells) --lg;
+  for (int l = logn - 1; l >= lg; --l) tot += 2 * ((size_t)1 << (dim * l)) * nf * sizeof(T);
+  return tot;
+}
+
+template <typename T>
+void MGHier<T>::vcycle(int nf, const T* b, T* x, double c0, double c1, int nu_pre, int nu_post, int nu_coarse,
+                       hipStream_t s) {
+  const bool three = dim == 3;
+  T cl = (T)c1;
+  const T tc0 = (T)c0;
+  const int nml = (int)levels.size();
+  for (int l = 0; l < nml; ++l) {
+    const int lg = logn - l;
+    const int64_t Cl = (int64_t)1 << (dim * lg);
+    T* xl = l == 0 ? x : bufs_x[l];
+    const T* bl = l == 0 ? b : bufs_b[l];
+    const dim3 gh(nblk(Cl / 2), nf);
+    if (nu_pre <= 0) {
+      launch_fill<T>(xl, Cl * nf, T(0), s);
+    }
+    for (int sw = 0; sw < nu_pre; ++sw) {
+      if (three) {
+        hipLaunchKernelGGL((k_rb<T, 3>), gh, dim3(256), 0, s, xl, bl, lg, tc0, cl, 0, sw == 0 ? 1 : 0);
+        hipLaunchKernelGGL((k_rb<T, 3>), gh, dim3(256), 0, s, xl, bl, lg, tc0, cl, 1, 0);
+      } else {
+        hipLaunchKernelGGL((k_rb<T, 2>), gh, dim3(256), 0, s, xl, bl, lg, tc0, cl, 0, sw == 0 ? 1 : 0);
+        hipLaunchKernelGGL((k_rb<T, 2>), gh, dim3(256), 0, s, xl, bl, lg, tc0, cl, 1, 0);
+      }
+    }
+    const int64_t Cc = Cl >> dim;
+    if (three)
+      hipLaunchKernelGGL((k_resid_restrict<T, 3>), dim3(nblk(Cc), nf), dim3(256), 0, s, xl, bl, bufs_b[l + 1], lg,
+                         tc0, cl);
+    else
+      hipLaunchKernelGGL((k_resid_restrict<T, 2>), dim3(nblk(Cc), nf), dim3(256), 0, s, xl, bl, bufs_b[l + 1], lg,
+                         tc0, cl);
+    cl = cl * T(0.25);
+  }
+  {
+    const T* bl = nml == 0 ? b : bufs_b[nml];
+    T* xl = nml == 0 ? x : bufs_x[nml];
+    if (three)
+      hipLaunchKernelGGL((k_vcycle_lds<T, 3>), dim3(nf), dim3(kLdsThreads), 0, s, bl, xl, lds_logn, tc0, cl, nu_pre,
+                         nu_post, nu_coarse);
+    else
+      hipLaunchKernelGGL((k_vcycle_lds<T, 2>), dim3(nf), dim3(kLdsThreads), 0, s, bl, xl, lds_logn, tc0, cl, nu_pre,
+                         nu_post, nu_coarse);
+  }
+  for (int l = nml - 1; l >= 0; --l) {
+    cl = cl * T(4);
+    const int lg = logn - l;
+    const int64_t Cl = (int64_t)1 << (dim * lg);
+    T* xl = l == 0 ? x : bufs_x[l];
+    const T* bl = l == 0 ? b : bufs_b[l];
+    const dim3 gh(nblk(Cl / 2), nf);
+    if (three)
+      hipLaunchKernelGGL((k_prolong_add<T, 3>), dim3(nblk(Cl), nf), dim3(256), 0, s, xl, bufs_x[l + 1], lg);
+    else
+      hipLaunchKernelGGL((k_prolong_add<T, 2>), dim3(nblk(Cl), nf), dim3(256), 0, s, xl, bufs_x[l + 1], lg);
+    for (int sw = 0; sw < nu_post; ++sw) {
+      if (three) {
+        hipLaunchKernelGGL((k_rb<T, 3>), gh, dim3(256), 0, s, xl, bl, lg, tc0, cl, 0, 0);
+        hipLaunchKernelGGL((k_rb<T, 3>), gh, dim3(256), 0, s, xl, bl, lg, tc0, cl, 1, 0);
+      } else {
+        hipLaunchKernelGGL((k_rb<T, 2>), gh, dim3(256), 0, s, xl, bl, lg, tc0, cl, 0, 0);
+        hipLaunchKernelGGL((k_rb<T, 2>), gh, dim3(256), 0, s, xl, bl, lg, tc0, cl, 1, 0);
+      }
+    }
+  }
+}
+
+template struct MGHier<double>;
+template struct MGHier<float>;
+
+}  // namespace ibr

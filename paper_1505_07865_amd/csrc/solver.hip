@@ -1,0 +1,1080 @@
+// Host orchestration and C ABI (include/ibr.h).
+//
+// Outer solver: right-preconditioned flexible GMRES (Sec. 5) on the stacked
+// fp64 vector x = [v (dim C), pi (C), Lambda (dim N)] with restart m; the
+// Arnoldi step is classical Gram-Schmidt with one re-orthogonalisation pass,
+// the Hessenberg least squares uses Givens rotations on the device, and the
+// host reads one residual estimate per iteration.
+//
+// Preconditioner (Sec. 5.1): inner GMRES(N_s) on the Stokes block with
+// P_S^-1 (eq. P1_practical) in the working precision T (fp64, or fp32 in the
+// mixed mode), slip dU = -(J v + r_L), per-body Lambda = M~^-1 dU in fp64,
+// and for the full variant a second inner solve with r_v + S'Lambda.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "ibr.h"
+#include "kernels.h"
+
+using namespace ibr;
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kA3D = 1.25;      // four-point marker hydrodynamic radius, units of h (3D)
+constexpr double kA2D = 1.04;      // four-point marker radius in the 2D periodic self-mobility
+constexpr double kPeriodic3D = 2.84;
+constexpr double kPivotTol = 1e-8;
+constexpr double kShifts[] = {0.0, 0.02, 0.05, 0.1, 0.15, 0.2, 0.3, 0.4, 0.5, 0.7, 1.0, 1.5, 2.0, 3.0, 5.0, 10.0};
+constexpr int kNumShifts = sizeof(kShifts) / sizeof(kShifts[0]);
+constexpr int kMaxBlockRows = 3072;
+
+int ilog2(int n) {
+  int l = 0;
+  while ((1 << l) < n) ++l;
+  return l;
+}
+
+struct Status : std::runtime_error {
+  ibr_status code;
+  Status(ibr_status c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+}  // namespace
+
+struct ibr_ctx {
+  ibr_params p{};
+  int dim = 3, n = 0, logn = 0;
+  int64_t C = 0;
+  double h = 0, L = 0, c0 = 0, ch2 = 0, inv_h = 0, vol = 0;
+  bool steady = true;
+  bool mixed = false;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::string err;
+
+  // markers
+  int nb = 0, N = 0, Ncap = 0;
+  std::vector<int> off_h;
+  int* off_d = nullptr;
+  int* body_d = nullptr;
+  double *R = nullptr, *X = nullptr, *U = nullptr, *Om = nullptr, *Vm = nullptr;
+  MarkerTaps taps{nullptr, nullptr, nullptr};
+  int *tile_of = nullptr, *counts = nullptr, *toff = nullptr, *cursor = nullptr, *perm = nullptr, *flags = nullptr,
+      *active = nullptr, *nactive_d = nullptr;
+  int tile_log = 3, tiles_log = 0, ntiles = 0, nactive = 0;
+
+  // mobility blocks
+  std::vector<int64_t> moff_h;
+  int64_t* moff_d = nullptr;
+  double *Mb = nullptr, *Lb = nullptr, *Xb = nullptr, *Minv = nullptr;
+  double *shift_d = nullptr;
+  int *act_d = nullptr, *fail_d = nullptr;
+  std::vector<double> shift_h;
+  int max_np = 0, max_rows = 0;
+  double f0 = 1.0;
+  MobParams mp{};
+
+  // stacked vectors (fp64)
+  int64_t NF = 0, NV = 0;
+  double *Xs = nullptr, *Bs = nullptr, *T1 = nullptr, *T2 = nullptr;
+  double *lamd = nullptr, *dU = nullptr, *addc = nullptr, *lsum_part = nullptr;
+  double *Nprev = nullptr, *Ncur = nullptr;
+  bool have_prev = false;
+  bool have_solution = false;
+
+  // outer Krylov
+  int m = 0;
+  double* Vb = nullptr;
+  void* Zb = nullptr;  // double or float
+  double *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr, *y = nullptr, *resid = nullptr, *beta = nullptr,
+         *hc2 = nullptr, *part = nullptr;
+  int part_blocks = 0;
+  double* hres = nullptr;  // pinned
+
+  // inner (precision T)
+  int ns = 2;
+  void *Qi = nullptr, *Zi = nullptr, *rhsT = nullptr, *qT = nullptr, *phiT = nullptr;
+  double *Hi = nullptr, *csi = nullptr, *sni = nullptr, *gi = nullptr, *yi = nullptr, *residi = nullptr,
+         *betai = nullptr, *hc2i = nullptr, *vmean = nullptr, *mpart = nullptr;
+  MGHier<double> mg64;
+  MGHier<float> mg32;
+
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  int64_t bytes = 0;
+
+  // counters of the current solve
+  int cnt_ps = 0, cnt_vc = 0;
+
+  ~ibr_ctx();
+  void alloc_grid();
+  void alloc_markers(int Nnew);
+  void free_markers();
+  template <typename T>
+  T* track(int64_t count) {
+    bytes += count * (int64_t)sizeof(T);
+    return dev_alloc<T>(count);
+  }
+};
+
+namespace {
+
+void sync(ibr_ctx* c) { IBR_HIP(hipStreamSynchronize(c->stream)); }
+
+template <typename T>
+MGHier<T>& mg_of(ibr_ctx* c);
+template <>
+MGHier<double>& mg_of<double>(ibr_ctx* c) {
+  return c->mg64;
+}
+template <>
+MGHier<float>& mg_of<float>(ibr_ctx* c) {
+  return c->mg32;
+}
+
+// ---------------------------------------------------------------- operator K
+// y = K x,  x stored in TI (fp64, or fp32 for mixed Z vectors), y in fp64.
+template <typename TI>
+void apply_K(ibr_ctx* c, const TI* x, double* y) {
+  hipStream_t s = c->stream;
+  const int d = c->dim;
+  const TI* xv = x;
+  const TI* xp = x + (int64_t)d * c->C;
+  const TI* xl = x + c->NF;
+  launch_copy<TI, double>(xl, c->lamd, (int64_t)c->N * d, s);
+  const double* addc = nullptr;
+  if (c->steady) {
+    // -S' Lambda = -S Lambda + vol^-1 sum Lambda
+    launch_lambda_sums(d, c->N, c->lamd, c->lsum_part, c->addc, 1.0 / c->vol, s);
+    addc = c->addc;
+  }
+  launch_stokes_apply<TI, double>(d, c->logn, xv, xp, y, y + (int64_t)d * c->C, c->c0, c->ch2, c->inv_h, addc, s);
+  launch_spread<double, double>(d, c->logn, c->tile_log, c->nactive, c->active, c->toff, c->perm, c->taps, c->lamd,
+                                y, -std::pow(c->h, -d), s);
+  launch_interp<TI>(d, c->logn, c->N, c->taps, xv, -1.0, nullptr, 0.0, y + c->NF, s);
+}
+
+// ---------------------------------------------------------------- P_S^-1
+template <typename T>
+void ps_inv(ibr_ctx* c, const T* in, T* out) {
+  hipStream_t s = c->stream;
+  const int d = c->dim;
+  const int64_t C = c->C;
+  MGHier<T>& mg = mg_of<T>(c);
+  const T* g = in;
+  const T* hp = in + (int64_t)d * C;
+  T* v = out;
+  T* pi = out + (int64_t)d * C;
+  T* q = (T*)c->qT;
+  T* phi = (T*)c->phiT;
+  mg.vcycle(d, g, v, c->c0, c->ch2, c->p.mg_pre, c->p.mg_post, c->p.mg_coarse, s);
+  const double* vmean = nullptr;
+  if (c->steady) {
+    launch_field_means<T>(v, d, C, c->mpart, 256, c->vmean, s);
+    vmean = c->vmean;
+  }
+  launch_div_q<T>(d, c->logn, v, hp, q, c->inv_h, s);
+  // L_p phi = q  <=>  (0 - (-1) L) phi = q
+  mg.vcycle(1, q, phi, 0.0, -1.0, c->p.mg_pre, c->p.mg_post, c->p.mg_coarse, s);
+  launch_ps_finish<T>(d, c->logn, v, phi, q, pi, c->h, c->c0 * c->h * c->h, c->p.eta, vmean, s);
+  c->cnt_ps += 1;
+  c->cnt_vc += d + 1;
+}
+
+// Inner right-preconditioned GMRES(N_s) on the Stokes block, zero initial
+// guess: out (fluid part, T) = approx [[A, G], [-D, 0]]^-1 rhs.
+template <typename T>
+void inner_gmres(ibr_ctx* c, const T* rhs, T* out) {
+  hipStream_t s = c->stream;
+  const int64_t NF = c->NF;
+  const int ns = c->ns;
+  const int d = c->dim;
+  T* Q = (T*)c->Qi;
+  T* Z = (T*)c->Zi;
+  const int ldh = ns + 1;
+  launch_sumsq_partial<T>(rhs, NF, c->part, c->part_blocks, s);
+  launch_norm_finish(c->part, c->part_blocks, c->betai, s);
+  launch_scale_copy<T, T>(rhs, Q, NF, c->betai, s);
+  launch_init_g(c->gi, ns + 1, c->betai, s);
+  launch_fill<double>(c->Hi, (int64_t)ldh * ns, 0.0, s);
+  for (int j = 0; j < ns; ++j) {
+    T* Qj = Q + (int64_t)j * NF;
+    T* Zj = Z + (int64_t)j * NF;
+    T* w = Q + (int64_t)(j + 1) * NF;
+    ps_inv<T>(c, Qj, Zj);
+    launch_stokes_apply<T, T>(d, c->logn, Zj, Zj + (int64_t)d * c->C, w, w + (int64_t)d * c->C, c->c0, c->ch2,
+                              c->inv_h, nullptr, s);
+    double* hcol = c->Hi + (int64_t)j * ldh;
+    launch_multi_dot<T, T>(Q, NF, j + 1, w, NF, c->part, c->part_blocks, hcol, false, s);
+    launch_multi_axpy<T, T>(Q, NF, j + 1, hcol, w, NF, nullptr, c->part_blocks, s);
+    launch_multi_dot<T, T>(Q, NF, j + 1, w, NF, c->part, c->part_blocks, c->hc2i, false, s);
+    launch_multi_axpy<T, T>(Q, NF, j + 1, c->hc2i, w, NF, c->part, c->part_blocks, s);
+    launch_axpby(c->hc2i, hcol, j + 1, 1.0, 1.0, s);
+    launch_norm_finish(c->part, c->part_blocks, hcol + j + 1, s);
+    launch_scale_copy<T, T>(w, w, NF, hcol + j + 1, s);
+    launch_givens_step(c->Hi, ldh, j, c->csi, c->sni, c->gi, c->residi, s);
+  }
+  launch_lsq_solve(c->Hi, ldh, ns, c->gi, c->yi, s);
+  launch_fill<T>(out, NF, T(0), s);
+  launch_combine<T, T>(Z, NF, ns, c->yi, out, NF, s);
+}
+
+// z = P r (Sec. 5.1).  r fp64 stacked; z stacked in T.
+template <typename T>
+void precondition(ibr_ctx* c, const double* r, T* z) {
+  hipStream_t s = c->stream;
+  const int d = c->dim;
+  const int64_t NF = c->NF;
+  T* rhs = (T*)c->rhsT;
+  launch_copy<double, T>(r, rhs, NF, s);
+  inner_gmres<T>(c, rhs, z);
+  // slip dU = -(J v + r_L)
+  launch_interp<T>(d, c->logn, c->N, c->taps, z, -1.0, r + NF, -1.0, c->dU, s);
+  launch_mob_apply(c->nb, c->off_d, d, c->moff_d, c->Minv, c->dU, c->lamd, c->max_rows, s);
+  if (c->p.pc == IBR_PC_FULL) {
+    // second fluid solve with r_v + S' Lambda
+    launch_spread<double, T>(d, c->logn, c->tile_log, c->nactive, c->active, c->toff, c->perm, c->taps, c->lamd,
+                             rhs, std::pow(c->h, -d), s);
+    if (c->steady) {
+      launch_lambda_sums(d, c->N, c->lamd, c->lsum_part, c->addc, 1.0 / c->vol, s);
+      launch_sub_field_mean<T>(rhs, d, c->C, c->addc, s);
+    }
+    inner_gmres<T>(c, rhs, z);
+  }
+  launch_copy<double, T>(c->lamd, z + NF, (int64_t)c->N * d, s);
+}
+
+// ---------------------------------------------------------------- FGMRES
+template <typename TZ>
+ibr_status fgmres(ibr_ctx* c, ibr_info* info) {
+  hipStream_t s = c->stream;
+  const int64_t NV = c->NV;
+  const int m = c->m;
+  const int ldh = m + 1;
+  TZ* Z = (TZ*)c->Zb;
+  double* V = c->Vb;
+  c->cnt_ps = 0;
+  c->cnt_vc = 0;
+  IBR_HIP(hipEventRecord(c->ev0, s));
+
+  launch_sumsq_partial<double>(c->Bs, NV, c->part, c->part_blocks, s);
+  launch_norm_finish(c->part, c->part_blocks, c->beta, s);
+  IBR_HIP(hipMemcpyAsync(c->hres, c->beta, sizeof(double), hipMemcpyDeviceToHost, s));
+  sync(c);
+  const double bnorm = c->hres[0];
+  const double target = c->p.rtol * bnorm;
+  int total = 0, restarts = 0;
+  ibr_status st = IBR_OK;
+  double relres = 0.0;
+  if (!(bnorm > 0.0)) {
+    launch_fill<double>(c->Xs, NV, 0.0, s);
+    if (!std::isfinite(bnorm)) st = IBR_ENUMERIC;
+  } else {
+    while (true) {
+      // r = b - K x
+      apply_K<double>(c, c->Xs, V);
+      launch_axpby(c->Bs, V, NV, 1.0, -1.0, s);
+      launch_sumsq_partial<double>(V, NV, c->part, c->part_blocks, s);
+      launch_norm_finish(c->part, c->part_blocks, c->beta, s);
+      IBR_HIP(hipMemcpyAsync(c->hres, c->beta, sizeof(double), hipMemcpyDeviceToHost, s));
+      sync(c);
+      const double rn = c->hres[0];
+      relres = rn / bnorm;
+      if (!std::isfinite(rn)) {
+        st = IBR_ENUMERIC;
+        break;
+      }
+      if (rn <= target) break;
+      if (total >= c->p.max_iters) {
+        st = IBR_ENOCONV;
+        break;
+      }
+      ++restarts;
+      launch_scale_copy<double, double>(V, V, NV, c->beta, s);
+      launch_init_g(c->g, m + 1, c->beta, s);
+      int kused = 0;
+      bool stop = false;
+      for (int k = 0; k < m; ++k) {
+        double* vk = V + (int64_t)k * NV;
+        double* w = V + (int64_t)(k + 1) * NV;
+        TZ* zk = Z + (int64_t)k * NV;
+        precondition<TZ>(c, vk, zk);
+        apply_K<TZ>(c, zk, w);
+        double* hcol = c->H + (int64_t)k * ldh;
+        launch_multi_dot<double, double>(V, NV, k + 1, w, NV, c->part, c->part_blocks, hcol, false, s);
+        launch_multi_axpy<double, double>(V, NV, k + 1, hcol, w, NV, nullptr, c->part_blocks, s);
+        launch_multi_dot<double, double>(V, NV, k + 1, w, NV, c->part, c->part_blocks, c->hc2, false, s);
+        launch_multi_axpy<double, double>(V, NV, k + 1, c->hc2, w, NV, c->part, c->part_blocks, s);
+        launch_axpby(c->hc2, hcol, k + 1, 1.0, 1.0, s);
+        launch_norm_finish(c->part, c->part_blocks, hcol + k + 1, s);
+        launch_scale_copy<double, double>(w, w, NV, hcol + k + 1, s);
+        launch_givens_step(c->H, ldh, k, c->cs, c->sn, c->g, c->resid, s);
+        IBR_HIP(hipMemcpyAsync(c->hres, c->resid, sizeof(double), hipMemcpyDeviceToHost, s));
+        sync(c);
+        ++total;
+        kused = k + 1;
+        const double est = c->hres[0];
+        if (!std::isfinite(est)) {
+          st = IBR_ENUMERIC;
+          stop = true;
+          break;
+        }
+        if (est <= target || total >= c->p.max_iters) break;
+      }
+      launch_lsq_solve(c->H, ldh, kused, c->g, c->y, s);
+      launch_combine<TZ, double>(Z, NV, kused, c->y, c->Xs, NV, s);
+      if (stop) break;
+    }
+  }
+  IBR_HIP(hipEventRecord(c->ev1, s));
+  sync(c);
+  float ms = 0;
+  IBR_HIP(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+  c->have_solution = true;
+  if (info) {
+    info->iters = total;
+    info->restarts = restarts;
+    info->ps_applications = c->cnt_ps;
+    info->vcycles = c->cnt_vc;
+    info->status = st;
+    info->rel_residual = relres;
+    info->ms = ms;
+    double mx = 0;
+    for (double v : c->shift_h) mx = std::max(mx, v);
+    info->max_mobility_shift = mx;
+  }
+  return st;
+}
+
+// ---------------------------------------------------------------- set-up helpers
+void validate(const ibr_params* p) {
+  if (!p) throw Status(IBR_EINVAL, "params is NULL");
+  if (p->dim != 2 && p->dim != 3) throw Status(IBR_EINVAL, "dim must be 2 or 3");
+  const int lo = p->dim == 3 ? 8 : 16;
+  const int hi = p->dim == 3 ? 512 : 4096;
+  if (p->n < lo || p->n > hi || (p->n & (p->n - 1)))
+    throw Status(IBR_EINVAL, "n must be a power of two in [" + std::to_string(lo) + ", " + std::to_string(hi) + "]");
+  if (!(p->h > 0) || !std::isfinite(p->h)) throw Status(IBR_EINVAL, "h must be > 0");
+  if (!(p->eta > 0) || !std::isfinite(p->eta)) throw Status(IBR_EINVAL, "eta must be > 0");
+  if (p->rho < 0 || !std::isfinite(p->rho)) throw Status(IBR_EINVAL, "rho must be >= 0");
+  if (p->rho > 0 && !(p->dt > 0)) throw Status(IBR_EINVAL, "dt must be > 0 when rho > 0");
+  if (p->precision != IBR_FP64 && p->precision != IBR_MIXED) throw Status(IBR_EINVAL, "bad precision");
+  if (p->pc != IBR_PC_LOWER && p->pc != IBR_PC_FULL) throw Status(IBR_EINVAL, "bad pc");
+  if (p->n_s < 1 || p->n_s > 16) throw Status(IBR_EINVAL, "n_s must be in [1, 16]");
+  if (p->restart < 1 || p->restart > 400) throw Status(IBR_EINVAL, "restart must be in [1, 400]");
+  if (p->max_iters < 1) throw Status(IBR_EINVAL, "max_iters must be >= 1");
+  if (!(p->rtol > 0) || p->rtol >= 1) throw Status(IBR_EINVAL, "rtol must be in (0, 1)");
+  if (p->mg_pre < 0 || p->mg_post < 0 || p->mg_coarse < 1 || p->mg_pre > 16 || p->mg_post > 16 ||
+      p->mg_coarse > 256)
+    throw Status(IBR_EINVAL, "bad multigrid sweep counts");
+}
+
+MobParams mob_params(const ibr_ctx* c) {
+  MobParams mp{};
+  mp.dim = c->dim;
+  mp.steady = c->steady ? 1 : 0;
+  mp.eta = c->p.eta;
+  mp.L = c->L;
+  mp.a = (c->dim == 3 ? kA3D : kA2D) * c->h;
+  if (c->dim == 3)
+    mp.finf0 = 1.0 / (6.0 * kPi * mp.eta * mp.a);
+  else
+    mp.finf0 = std::log(c->L / (3.708 * mp.a)) / (4.0 * kPi * mp.eta);
+  mp.periodic_shift = c->dim == 3 ? kPeriodic3D / (6.0 * kPi * mp.eta * c->L) : 0.0;
+  if (!c->steady) {
+    const double vm = std::pow(8.0 / 3.0, c->dim) * std::pow(c->h, c->dim);
+    const double f0inv = (c->dim - 1.0) / c->dim * (c->p.dt / c->p.rho) / vm;
+    mp.f00 = 1.0 / (1.0 / f0inv + 1.0 / mp.finf0);
+    mp.alpha = std::sqrt(c->p.rho / (mp.eta * c->p.dt));
+    mp.dt_rho = c->p.dt / c->p.rho;
+  }
+  return mp;
+}
+
+double self_term(const MobParams& mp) {
+  if (!mp.steady) return mp.f00;
+  if (mp.dim == 3) return mp.finf0 - mp.periodic_shift;
+  return mp.finf0;
+}
+
+void setup_markers(ibr_ctx* c) {
+  hipStream_t s = c->stream;
+  launch_marker_setup(c->dim, c->logn, c->N, c->h, c->L, c->R, c->taps, c->tile_of, c->tile_log, s);
+  launch_bin_markers(c->N, c->ntiles, c->tile_of, c->counts, c->toff, c->cursor, c->perm, s);
+  launch_active_tiles(c->dim, c->tiles_log, c->toff, c->flags, c->active, c->nactive_d, s);
+  int na = 0;
+  IBR_HIP(hipMemcpyAsync(c->hres, c->nactive_d, sizeof(int), hipMemcpyDeviceToHost, s));
+  sync(c);
+  std::memcpy(&na, c->hres, sizeof(int));
+  c->nactive = na;
+}
+
+void factor_blocks(ibr_ctx* c) {
+  hipStream_t s = c->stream;
+  const int nb = c->nb;
+  c->mp = mob_params(c);
+  c->f0 = self_term(c->mp);
+  launch_mob_assemble(c->dim, nb, c->off_d, c->moff_d, c->R, c->mp, c->Mb, c->max_np, s);
+  std::vector<int> idx(nb, 0), act(nb, 1), fail(nb, 0);
+  c->shift_h.assign(nb, 0.0);
+  for (int round = 0; round < kNumShifts; ++round) {
+    for (int b = 0; b < nb; ++b) c->shift_h[b] = kShifts[idx[b]];
+    IBR_HIP(hipMemcpyAsync(c->shift_d, c->shift_h.data(), nb * sizeof(double), hipMemcpyHostToDevice, s));
+    IBR_HIP(hipMemcpyAsync(c->act_d, act.data(), nb * sizeof(int), hipMemcpyHostToDevice, s));
+    launch_chol(nb, c->off_d, c->dim, c->moff_d, c->Mb, c->Lb, c->act_d, c->shift_d, c->f0, kPivotTol, c->fail_d, s);
+    IBR_HIP(hipMemcpyAsync(fail.data(), c->fail_d, nb * sizeof(int), hipMemcpyDeviceToHost, s));
+    sync(c);
+    bool any = false;
+    for (int b = 0; b < nb; ++b) {
+      if (act[b] && fail[b]) {
+        any = true;
+        if (idx[b] + 1 >= kNumShifts) throw Status(IBR_EFACTOR, "mobility block " + std::to_string(b) + " could not be factored");
+        ++idx[b];
+      } else {
+        act[b] = 0;
+      }
+    }
+    if (!any) break;
+  }
+  launch_chol_inverse(nb, c->off_d, c->dim, c->moff_d, c->Lb, c->Minv, c->Xb, c->max_rows, s);
+  sync(c);
+}
+
+void build_rhs_markers(ibr_ctx* c) {
+  // W = -V in the constraint block of b
+  launch_marker_velocity(c->dim, c->N, c->R, c->body_d, c->X, c->U, c->Om, c->L, c->Vm, c->stream);
+  launch_copy<double, double>(c->Vm, c->Bs + c->NF, (int64_t)c->N * c->dim, c->stream);
+  launch_axpby(c->Vm, c->Bs + c->NF, (int64_t)c->N * c->dim, -1.0, 0.0, c->stream);
+}
+
+template <typename F>
+ibr_status guard(ibr_ctx* c, F&& f) {
+  try {
+    f();
+    if (c) c->err.clear();
+    return IBR_OK;
+  } catch (const Status& e) {
+    if (c) c->err = e.what();
+    return e.code;
+  } catch (const DeviceError& e) {
+    if (c) c->err = e.what();
+    return IBR_EDEVICE;
+  } catch (const std::bad_alloc&) {
+    if (c) c->err = "host allocation failed";
+    return IBR_ENOMEM;
+  } catch (const std::exception& e) {
+    if (c) c->err = e.what();
+    return IBR_EDEVICE;
+  }
+}
+
+void require_bodies(const ibr_ctx* c) {
+  if (c->N <= 0) throw Status(IBR_ESTATE, "ibr_set_bodies has not been called");
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- ctx members
+ibr_ctx::~ibr_ctx() {
+  free_markers();
+  for (void* q : {(void*)Xs, (void*)Bs, (void*)T1, (void*)T2, (void*)Nprev, (void*)Ncur, (void*)H, (void*)cs,
+                  (void*)sn, (void*)g, (void*)y, (void*)resid, (void*)beta, (void*)hc2, (void*)part, (void*)Qi,
+                  (void*)Zi, (void*)rhsT, (void*)qT, (void*)phiT, (void*)Hi, (void*)csi, (void*)sni, (void*)gi,
+                  (void*)yi, (void*)residi, (void*)betai, (void*)hc2i, (void*)vmean, (void*)mpart, (void*)addc,
+                  (void*)lsum_part})
+    dev_free(q);
+  mg64.release();
+  mg32.release();
+  if (hres) (void)hipHostFree(hres);
+  if (ev0) (void)hipEventDestroy(ev0);
+  if (ev1) (void)hipEventDestroy(ev1);
+  if (own_stream && stream) (void)hipStreamDestroy(stream);
+}
+
+void ibr_ctx::free_markers() {
+  for (void* q : {(void*)off_d, (void*)body_d, (void*)R, (void*)X, (void*)U, (void*)Om, (void*)Vm, (void*)taps.base,
+                  (void*)taps.w64, (void*)taps.w32, (void*)tile_of, (void*)counts, (void*)toff, (void*)cursor,
+                  (void*)perm, (void*)flags, (void*)active, (void*)nactive_d, (void*)moff_d, (void*)Mb, (void*)Lb,
+                  (void*)Xb, (void*)Minv, (void*)shift_d, (void*)act_d, (void*)fail_d, (void*)Vb, Zb, (void*)lamd,
+                  (void*)dU})
+    dev_free(q);
+  off_d = body_d = nullptr;
+  R = X = U = Om = Vm = nullptr;
+  taps = MarkerTaps{nullptr, nullptr, nullptr};
+  tile_of = counts = toff = cursor = perm = flags = active = nactive_d = nullptr;
+  moff_d = nullptr;
+  Mb = Lb = Xb = Minv = shift_d = nullptr;
+  act_d = fail_d = nullptr;
+  Vb = nullptr;
+  Zb = nullptr;
+  lamd = dU = nullptr;
+}
+
+void ibr_ctx::alloc_grid() {
+  const int d = dim;
+  NF = (int64_t)(d + 1) * C;
+  Nprev = track<double>((int64_t)d * C);
+  Ncur = track<double>((int64_t)d * C);
+  m = p.restart;
+  ns = p.n_s;
+  H = track<double>((int64_t)(m + 1) * m);
+  cs = track<double>(m + 1);
+  sn = track<double>(m + 1);
+  g = track<double>(m + 2);
+  y = track<double>(m + 1);
+  resid = track<double>(1);
+  beta = track<double>(1);
+  hc2 = track<double>(m + 2);
+  part_blocks = 1024;
+  part = track<double>((int64_t)(m + 2) * part_blocks);
+  Hi = track<double>((int64_t)(ns + 1) * ns);
+  csi = track<double>(ns + 1);
+  sni = track<double>(ns + 1);
+  gi = track<double>(ns + 2);
+  yi = track<double>(ns + 1);
+  residi = track<double>(1);
+  betai = track<double>(1);
+  hc2i = track<double>(ns + 2);
+  vmean = track<double>(4);
+  mpart = track<double>(4 * 256);
+  addc = track<double>(4);
+  lsum_part = track<double>(4 * 64);
+  const int64_t tsz = mixed ? 4 : 8;
+  auto talloc = [&](int64_t count) -> void* {
+    bytes += count * tsz;
+    return mixed ? (void*)dev_alloc<float>(count) : (void*)dev_alloc<double>(count);
+  };
+  Qi = talloc((int64_t)(ns + 1) * NF);
+  Zi = talloc((int64_t)ns * NF);
+  rhsT = talloc(NF);
+  qT = talloc(C);
+  phiT = talloc(C);
+  if (mixed) {
+    mg32.init(d, logn, d);
+    bytes += MGHier<float>::bytes(d, logn, d);
+  } else {
+    mg64.init(d, logn, d);
+    bytes += MGHier<double>::bytes(d, logn, d);
+  }
+  IBR_HIP(hipHostMalloc((void**)&hres, 64, hipHostMallocDefault));
+  IBR_HIP(hipEventCreate(&ev0));
+  IBR_HIP(hipEventCreate(&ev1));
+  tile_log = d == 3 ? 3 : 4;
+  if (tile_log > logn) tile_log = logn;
+  tiles_log = logn - tile_log;
+  ntiles = 1 << (d * tiles_log);
+}
+
+void ibr_ctx::alloc_markers(int Nnew) {
+  // Grid-sized stacked vectors depend on N through the Lambda tail.
+  const int d = dim;
+  if (Nnew <= Ncap && Vb) return;
+  const int cap = std::max(Nnew, 16);
+  for (void* q : {(void*)R, (void*)Vm, (void*)body_d, (void*)taps.base, (void*)taps.w64, (void*)taps.w32,
+                  (void*)tile_of, (void*)perm, (void*)Vb, Zb, (void*)lamd, (void*)dU, (void*)Xs, (void*)Bs, (void*)T1,
+                  (void*)T2})
+    dev_free(q);
+  R = Vm = lamd = dU = Xs = Bs = T1 = T2 = Vb = nullptr;
+  body_d = tile_of = perm = nullptr;
+  taps = MarkerTaps{nullptr, nullptr, nullptr};
+  Zb = nullptr;
+  Ncap = 0;
+  Ncap = cap;
+  const int64_t NVc = NF + (int64_t)d * cap;
+  R = track<double>((int64_t)cap * d);
+  Vm = track<double>((int64_t)cap * d);
+  body_d = track<int>(cap);
+  taps.base = track<int>((int64_t)cap * 6);
+  taps.w64 = track<double>((int64_t)cap * 24);
+  taps.w32 = track<float>((int64_t)cap * 24);
+  tile_of = track<int>(cap);
+  perm = track<int>(cap);
+  lamd = track<double>((int64_t)cap * d);
+  dU = track<double>((int64_t)cap * d);
+  Xs = track<double>(NVc);
+  Bs = track<double>(NVc);
+  T1 = track<double>(NVc);
+  T2 = track<double>(NVc);
+  Vb = track<double>((int64_t)(m + 1) * NVc);
+  if (mixed) {
+    Zb = dev_alloc<float>((int64_t)m * NVc);
+    bytes += (int64_t)m * NVc * 4;
+  } else {
+    Zb = dev_alloc<double>((int64_t)m * NVc);
+    bytes += (int64_t)m * NVc * 8;
+  }
+  launch_fill<double>(Xs, NVc, 0.0, stream);
+  launch_fill<double>(Bs, NVc, 0.0, stream);
+}
+
+// ---------------------------------------------------------------- C ABI
+extern "C" {
+
+void ibr_default_params(ibr_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->dim = 3;
+  p->n = 32;
+  p->h = 1.0 / 32.0;
+  p->rho = 0.0;
+  p->eta = 1.0;
+  p->dt = 0.0;
+  p->precision = IBR_FP64;
+  p->pc = IBR_PC_LOWER;
+  p->n_s = 2;
+  p->restart = 100;
+  p->max_iters = 1000;
+  p->rtol = 1e-8;
+  p->mg_pre = 2;
+  p->mg_post = 2;
+  p->mg_coarse = 16;
+  p->device = 0;
+  p->stream = nullptr;
+}
+
+const char* ibr_status_string(int st) {
+  switch (st) {
+    case IBR_OK: return "ok";
+    case IBR_EINVAL: return "invalid argument";
+    case IBR_ENOMEM: return "out of device memory";
+    case IBR_ENOCONV: return "not converged";
+    case IBR_EBREAKDOWN: return "Krylov breakdown";
+    case IBR_EFACTOR: return "mobility block factorisation failed";
+    case IBR_ENUMERIC: return "NaN or Inf in the residual";
+    case IBR_EDEVICE: return "device error";
+    case IBR_ESTATE: return "call out of order";
+    default: return "unknown status";
+  }
+}
+
+ibr_status ibr_create(const ibr_params* params, ibr_ctx** out) {
+  if (!out) return IBR_EINVAL;
+  *out = nullptr;
+  std::unique_ptr<ibr_ctx> c(new ibr_ctx());
+  ibr_status st = guard(c.get(), [&] {
+    validate(params);
+    c->p = *params;
+    IBR_HIP(hipSetDevice(params->device));
+    c->dim = params->dim;
+    c->n = params->n;
+    c->logn = ilog2(params->n);
+    c->C = (int64_t)1 << (c->dim * c->logn);
+    c->h = params->h;
+    c->L = params->n * params->h;
+    c->vol = std::pow(c->L, c->dim);
+    c->steady = params->rho == 0.0;
+    c->c0 = c->steady ? 0.0 : params->rho / params->dt;
+    c->ch2 = params->eta / (c->h * c->h);
+    c->inv_h = 1.0 / c->h;
+    c->mixed = params->precision == IBR_MIXED;
+    if (params->stream) {
+      c->stream = (hipStream_t)params->stream;
+    } else {
+      IBR_HIP(hipStreamCreate(&c->stream));
+      c->own_stream = true;
+    }
+    c->alloc_grid();
+    sync(c.get());
+  });
+  if (st != IBR_OK) return st;
+  *out = c.release();
+  return IBR_OK;
+}
+
+void ibr_destroy(ibr_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->p.device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  delete c;
+}
+
+const char* ibr_last_error(const ibr_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+size_t ibr_footprint_bytes(const ibr_params* p, int nbodies, int nmarkers) {
+  if (!p || p->dim < 2 || p->dim > 3 || p->n < 4) return 0;
+  const int d = p->dim;
+  const int64_t C = (int64_t)1 << (d * ilog2(p->n));
+  const int64_t NF = (int64_t)(d + 1) * C;
+  const int64_t NV = NF + (int64_t)d * std::max(nmarkers, 16);
+  const int m = p->restart > 0 ? p->restart : 100;
+  const int ns = p->n_s > 0 ? p->n_s : 2;
+  const int64_t ts = p->precision == IBR_MIXED ? 4 : 8;
+  size_t b = 0;
+  b += (size_t)(m + 1) * NV * 8;       // V basis
+  b += (size_t)m * NV * ts;            // Z basis
+  b += (size_t)4 * NV * 8;             // x, b, two temporaries
+  b += (size_t)2 * d * C * 8;          // advection history
+  b += (size_t)((2 * ns + 2) * NF + 2 * C) * ts;  // inner bases and P_S^-1 scratch
+  b += ts == 4 ? MGHier<float>::bytes(d, ilog2(p->n), d) : MGHier<double>::bytes(d, ilog2(p->n), d);
+  // mobility blocks (4 buffers of sum (d N_p)^2), bounded by one block of all markers per body
+  const int64_t per = nbodies > 0 ? (int64_t)d * nmarkers / nbodies : 0;
+  b += (size_t)4 * nbodies * per * per * 8;
+  b += (size_t)nmarkers * 400;
+  return b;
+}
+
+ibr_status ibr_set_bodies(ibr_ctx* c, int nbodies, const int* offsets, const double* R, const double* centres) {
+  if (!c) return IBR_EINVAL;
+  return guard(c, [&] {
+    if (nbodies < 1 || !offsets || !R || !centres) throw Status(IBR_EINVAL, "need nbodies >= 1, offsets, R, centres");
+    if (offsets[0] != 0) throw Status(IBR_EINVAL, "offsets[0] must be 0");
+    int maxnp = 0;
+    for (int b = 0; b < nbodies; ++b) {
+      const int np = offsets[b + 1] - offsets[b];
+      if (np < 1) throw Status(IBR_EINVAL, "every body needs at least one marker");
+      maxnp = std::max(maxnp, np);
+    }
+    const int d = c->dim;
+    if (maxnp * d > kMaxBlockRows)
+      throw Status(IBR_EINVAL, "a body has more than " + std::to_string(kMaxBlockRows / d) + " markers");
+    const int N = offsets[nbodies];
+    for (int64_t i = 0; i < (int64_t)N * d; ++i)
+      if (!std::isfinite(R[i])) throw Status(IBR_EINVAL, "marker positions must be finite");
+    for (int64_t i = 0; i < (int64_t)nbodies * d; ++i)
+      if (!std::isfinite(centres[i])) throw Status(IBR_EINVAL, "centres must be finite");
+    IBR_HIP(hipSetDevice(c->p.device));
+    sync(c);
+    // body-sized buffers are rebuilt every call (set-up, not the solve path)
+    auto drop = [](auto*& q) {
+      dev_free((void*)q);
+      q = nullptr;
+    };
+    drop(c->off_d);
+    drop(c->X);
+    drop(c->U);
+    drop(c->Om);
+    drop(c->counts);
+    drop(c->toff);
+    drop(c->cursor);
+    drop(c->flags);
+    drop(c->active);
+    drop(c->nactive_d);
+    drop(c->moff_d);
+    drop(c->Mb);
+    drop(c->Lb);
+    drop(c->Xb);
+    drop(c->Minv);
+    drop(c->shift_d);
+    drop(c->act_d);
+    drop(c->fail_d);
+    c->N = 0;
+    const bool grow = N > c->Ncap || !c->Vb;
+    c->alloc_markers(N);
+    c->nb = nbodies;
+    c->N = N;
+    c->NV = c->NF + (int64_t)d * N;
+    c->off_h.assign(offsets, offsets + nbodies + 1);
+    c->off_d = dev_alloc<int>(nbodies + 1);
+    c->X = dev_alloc<double>((int64_t)nbodies * d);
+    c->U = dev_alloc<double>((int64_t)nbodies * d);
+    c->Om = dev_alloc<double>((int64_t)nbodies * 3);
+    c->counts = dev_alloc<int>(c->ntiles);
+    c->toff = dev_alloc<int>(c->ntiles + 1);
+    c->cursor = dev_alloc<int>(c->ntiles);
+    c->flags = dev_alloc<int>(c->ntiles);
+    c->active = dev_alloc<int>(c->ntiles);
+    c->nactive_d = dev_alloc<int>(1);
+    std::vector<int> body(N);
+    for (int b = 0; b < nbodies; ++b)
+      for (int i = offsets[b]; i < offsets[b + 1]; ++i) body[i] = b;
+    c->moff_h.assign(nbodies + 1, 0);
+    c->max_np = maxnp;
+    c->max_rows = maxnp * d;
+    for (int b = 0; b < nbodies; ++b) {
+      const int64_t nr = (int64_t)d * (offsets[b + 1] - offsets[b]);
+      c->moff_h[b + 1] = c->moff_h[b] + nr * nr;
+    }
+    const int64_t mtot = c->moff_h[nbodies];
+    c->moff_d = dev_alloc<int64_t>(nbodies + 1);
+    c->Mb = dev_alloc<double>(mtot);
+    c->Lb = dev_alloc<double>(mtot);
+    c->Xb = dev_alloc<double>(mtot);
+    c->Minv = dev_alloc<double>(mtot);
+    c->shift_d = dev_alloc<double>(nbodies);
+    c->act_d = dev_alloc<int>(nbodies);
+    c->fail_d = dev_alloc<int>(nbodies);
+    hipStream_t s = c->stream;
+    IBR_HIP(hipMemcpyAsync(c->off_d, offsets, (nbodies + 1) * sizeof(int), hipMemcpyHostToDevice, s));
+    IBR_HIP(hipMemcpyAsync(c->R, R, (size_t)N * d * sizeof(double), hipMemcpyHostToDevice, s));
+    IBR_HIP(hipMemcpyAsync(c->X, centres, (size_t)nbodies * d * sizeof(double), hipMemcpyHostToDevice, s));
+    IBR_HIP(hipMemcpyAsync(c->body_d, body.data(), N * sizeof(int), hipMemcpyHostToDevice, s));
+    IBR_HIP(hipMemcpyAsync(c->moff_d, c->moff_h.data(), (nbodies + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    launch_fill<double>(c->U, (int64_t)nbodies * d, 0.0, s);
+    launch_fill<double>(c->Om, (int64_t)nbodies * 3, 0.0, s);
+    // positions are wrapped into the box by the marker set-up kernel's taps; keep R itself wrapped too
+    launch_move_markers(d, N, nbodies, c->R, c->X, c->body_d, c->U, 0.0, c->L, s);
+    setup_markers(c);
+    factor_blocks(c);
+    if (grow) launch_fill<double>(c->Xs, c->NV, 0.0, s);
+    build_rhs_markers(c);
+    c->have_prev = false;
+    sync(c);
+  });
+}
+
+ibr_status ibr_set_velocities(ibr_ctx* c, const double* U, const double* Omega) {
+  if (!c) return IBR_EINVAL;
+  return guard(c, [&] {
+    require_bodies(c);
+    if (!U || !Omega) throw Status(IBR_EINVAL, "U and Omega are required");
+    const int d = c->dim;
+    const int no = d == 3 ? 3 : 1;
+    for (int64_t i = 0; i < (int64_t)c->nb * d; ++i)
+      if (!std::isfinite(U[i])) throw Status(IBR_EINVAL, "U must be finite");
+    for (int64_t i = 0; i < (int64_t)c->nb * no; ++i)
+      if (!std::isfinite(Omega[i])) throw Status(IBR_EINVAL, "Omega must be finite");
+    IBR_HIP(hipSetDevice(c->p.device));
+    IBR_HIP(hipMemcpyAsync(c->U, U, (size_t)c->nb * d * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    IBR_HIP(hipMemcpyAsync(c->Om, Omega, (size_t)c->nb * no * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    build_rhs_markers(c);
+    sync(c);
+  });
+}
+
+ibr_status ibr_set_rhs(ibr_ctx* c, const double* gh, const double* hp) {
+  if (!c) return IBR_EINVAL;
+  return guard(c, [&] {
+    require_bodies(c);
+    const int d = c->dim;
+    hipStream_t s = c->stream;
+    IBR_HIP(hipSetDevice(c->p.device));
+    if (gh)
+      IBR_HIP(hipMemcpyAsync(c->Bs, gh, (size_t)d * c->C * sizeof(double), hipMemcpyHostToDevice, s));
+    else
+      launch_fill<double>(c->Bs, (int64_t)d * c->C, 0.0, s);
+    if (hp)
+      IBR_HIP(hipMemcpyAsync(c->Bs + (int64_t)d * c->C, hp, (size_t)c->C * sizeof(double), hipMemcpyHostToDevice, s));
+    else
+      launch_fill<double>(c->Bs + (int64_t)d * c->C, c->C, 0.0, s);
+    // consistency: <h> = 0 always, <g> = 0 for periodic steady Stokes (Sec. 3.4)
+    launch_field_means<double>(c->Bs + (int64_t)d * c->C, 1, c->C, c->mpart, 256, c->vmean, s);
+    launch_sub_field_mean<double>(c->Bs + (int64_t)d * c->C, 1, c->C, c->vmean, s);
+    if (c->steady) {
+      launch_field_means<double>(c->Bs, d, c->C, c->mpart, 256, c->vmean, s);
+      launch_sub_field_mean<double>(c->Bs, d, c->C, c->vmean, s);
+    }
+    sync(c);
+  });
+}
+
+ibr_status ibr_solve(ibr_ctx* c, int warm_start, ibr_info* info) {
+  if (!c) return IBR_EINVAL;
+  ibr_status st = IBR_OK;
+  ibr_status g = guard(c, [&] {
+    require_bodies(c);
+    IBR_HIP(hipSetDevice(c->p.device));
+    if (!warm_start || !c->have_solution) launch_fill<double>(c->Xs, c->NV, 0.0, c->stream);
+    st = c->mixed ? fgmres<float>(c, info) : fgmres<double>(c, info);
+    if (st == IBR_ENOCONV) c->err = "FGMRES did not reach rtol within max_iters";
+    if (st == IBR_ENUMERIC) c->err = "NaN or Inf in the FGMRES residual";
+  });
+  return g != IBR_OK ? g : st;
+}
+
+ibr_status ibr_step(ibr_ctx* c, ibr_info* info) {
+  if (!c) return IBR_EINVAL;
+  ibr_status st = IBR_OK;
+  ibr_status g = guard(c, [&] {
+    require_bodies(c);
+    if (c->steady) throw Status(IBR_ESTATE, "ibr_step needs rho > 0 (unsteady)");
+    IBR_HIP(hipSetDevice(c->p.device));
+    hipStream_t s = c->stream;
+    const int d = c->dim;
+    const int64_t len = (int64_t)d * c->C;
+    if (!c->have_solution) launch_fill<double>(c->Xs, c->NV, 0.0, s);
+    // explicit advection (AB2, forward Euler on the first step)
+    launch_advect(d, c->logn, c->Xs, c->Ncur, 0.5 / c->h, s);
+    const double rho = c->p.rho;
+    if (c->have_prev)
+      launch_ns_rhs(c->Xs, c->Ncur, c->Nprev, c->Bs, len, c->c0, rho, 1.5, -0.5, s);
+    else
+      launch_ns_rhs(c->Xs, c->Ncur, nullptr, c->Bs, len, c->c0, rho, 1.0, 0.0, s);
+    launch_fill<double>(c->Bs + len, c->C, 0.0, s);
+    // move the bodies, re-bin the markers (the mobility blocks are translation invariant)
+    launch_move_markers(d, c->N, c->nb, c->R, c->X, c->body_d, c->U, c->p.dt, c->L, s);
+    setup_markers(c);
+    build_rhs_markers(c);
+    st = c->mixed ? fgmres<float>(c, info) : fgmres<double>(c, info);
+    std::swap(c->Nprev, c->Ncur);
+    c->have_prev = true;
+  });
+  return g != IBR_OK ? g : st;
+}
+
+ibr_status ibr_get_solution(ibr_ctx* c, double* u, double* pr, double* lambda, double* F, double* T) {
+  if (!c) return IBR_EINVAL;
+  return guard(c, [&] {
+    require_bodies(c);
+    IBR_HIP(hipSetDevice(c->p.device));
+    hipStream_t s = c->stream;
+    const int d = c->dim;
+    double* pdev = c->Xs + (int64_t)d * c->C;
+    launch_field_means<double>(pdev, 1, c->C, c->mpart, 256, c->vmean, s);
+    launch_sub_field_mean<double>(pdev, 1, c->C, c->vmean, s);
+    if (u) IBR_HIP(hipMemcpyAsync(u, c->Xs, (size_t)d * c->C * sizeof(double), hipMemcpyDeviceToHost, s));
+    if (pr) IBR_HIP(hipMemcpyAsync(pr, pdev, (size_t)c->C * sizeof(double), hipMemcpyDeviceToHost, s));
+    if (lambda)
+      IBR_HIP(hipMemcpyAsync(lambda, c->Xs + c->NF, (size_t)c->N * d * sizeof(double), hipMemcpyDeviceToHost, s));
+    if (F || T) {
+      const int nt = d == 3 ? 3 : 1;
+      launch_body_force_torque(d, c->nb, c->off_d, c->R, c->X, c->L, c->Xs + c->NF, c->T1, c->T1 + c->nb * 3, s);
+      if (F) IBR_HIP(hipMemcpyAsync(F, c->T1, (size_t)c->nb * d * sizeof(double), hipMemcpyDeviceToHost, s));
+      if (T)
+        IBR_HIP(hipMemcpyAsync(T, c->T1 + c->nb * 3, (size_t)c->nb * nt * sizeof(double), hipMemcpyDeviceToHost, s));
+    }
+    sync(c);
+  });
+}
+
+ibr_status ibr_get_markers(ibr_ctx* c, double* R, double* centres) {
+  if (!c) return IBR_EINVAL;
+  return guard(c, [&] {
+    require_bodies(c);
+    IBR_HIP(hipSetDevice(c->p.device));
+    if (R) IBR_HIP(hipMemcpyAsync(R, c->R, (size_t)c->N * c->dim * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    if (centres)
+      IBR_HIP(hipMemcpyAsync(centres, c->X, (size_t)c->nb * c->dim * sizeof(double), hipMemcpyDeviceToHost,
+                             c->stream));
+    sync(c);
+  });
+}
+
+ibr_status ibr_apply_operator(ibr_ctx* c, const double* x, double* yh) {
+  if (!c) return IBR_EINVAL;
+  return guard(c, [&] {
+    require_bodies(c);
+    if (!x || !yh) throw Status(IBR_EINVAL, "x and y are required");
+    IBR_HIP(hipSetDevice(c->p.device));
+    IBR_HIP(hipMemcpyAsync(c->T1, x, (size_t)c->NV * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    apply_K<double>(c, c->T1, c->T2);
+    IBR_HIP(hipMemcpyAsync(yh, c->T2, (size_t)c->NV * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    sync(c);
+  });
+}
+
+ibr_status ibr_spread(ibr_ctx* c, const double* lambda, double* f) {
+  if (!c) return IBR_EINVAL;
+  return guard(c, [&] {
+    require_bodies(c);
+    if (!lambda || !f) throw Status(IBR_EINVAL, "lambda and f are required");
+    IBR_HIP(hipSetDevice(c->p.device));
+    const int d = c->dim;
+    hipStream_t s = c->stream;
+    IBR_HIP(hipMemcpyAsync(c->lamd, lambda, (size_t)c->N * d * sizeof(double), hipMemcpyHostToDevice, s));
+    launch_fill<double>(c->T2, (int64_t)d * c->C, 0.0, s);
+    launch_spread<double, double>(d, c->logn, c->tile_log, c->nactive, c->active, c->toff, c->perm, c->taps, c->lamd,
+                                  c->T2, std::pow(c->h, -d), s);
+    IBR_HIP(hipMemcpyAsync(f, c->T2, (size_t)d * c->C * sizeof(double), hipMemcpyDeviceToHost, s));
+    sync(c);
+  });
+}
+
+ibr_status ibr_interp(ibr_ctx* c, const double* u, double* V) {
+  if (!c) return IBR_EINVAL;
+  return guard(c, [&] {
+    require_bodies(c);
+    if (!u || !V) throw Status(IBR_EINVAL, "u and V are required");
+    IBR_HIP(hipSetDevice(c->p.device));
+    const int d = c->dim;
+    hipStream_t s = c->stream;
+    IBR_HIP(hipMemcpyAsync(c->T1, u, (size_t)d * c->C * sizeof(double), hipMemcpyHostToDevice, s));
+    launch_interp<double>(d, c->logn, c->N, c->taps, c->T1, 1.0, nullptr, 0.0, c->dU, s);
+    IBR_HIP(hipMemcpyAsync(V, c->dU, (size_t)c->N * d * sizeof(double), hipMemcpyDeviceToHost, s));
+    sync(c);
+  });
+}
+
+ibr_status ibr_vcycle(ibr_ctx* c, double c0, double c1, int nf, const double* b, double* x) {
+  if (!c) return IBR_EINVAL;
+  return guard(c, [&] {
+    if (!b || !x) throw Status(IBR_EINVAL, "b and x are required");
+    if (nf < 1 || nf > c->dim) throw Status(IBR_EINVAL, "nfields must be in [1, dim]");
+    if (!(c0 >= 0) || !std::isfinite(c1) || c1 == 0.0) throw Status(IBR_EINVAL, "need c0 >= 0 and c1 != 0");
+    IBR_HIP(hipSetDevice(c->p.device));
+    hipStream_t s = c->stream;
+    const int64_t len = (int64_t)nf * c->C;
+    // staging in the advection-history buffers (dim C doubles each)
+    double* bd = c->Nprev;
+    double* xd = c->Ncur;
+    IBR_HIP(hipMemcpyAsync(bd, b, (size_t)len * sizeof(double), hipMemcpyHostToDevice, s));
+    if (c->mixed) {
+      float* bf = (float*)c->Qi;
+      float* xf = (float*)c->Zi;
+      launch_copy<double, float>(bd, bf, len, s);
+      c->mg32.vcycle(nf, bf, xf, c0, c1, c->p.mg_pre, c->p.mg_post, c->p.mg_coarse, s);
+      if (c0 == 0.0) {
+        launch_field_means<float>(xf, nf, c->C, c->mpart, 256, c->vmean, s);
+        launch_sub_field_mean<float>(xf, nf, c->C, c->vmean, s);
+      }
+      launch_copy<float, double>(xf, xd, len, s);
+    } else {
+      c->mg64.vcycle(nf, bd, xd, c0, c1, c->p.mg_pre, c->p.mg_post, c->p.mg_coarse, s);
+      if (c0 == 0.0) {
+        launch_field_means<double>(xd, nf, c->C, c->mpart, 256, c->vmean, s);
+        launch_sub_field_mean<double>(xd, nf, c->C, c->vmean, s);
+      }
+    }
+    IBR_HIP(hipMemcpyAsync(x, xd, (size_t)len * sizeof(double), hipMemcpyDeviceToHost, s));
+    c->have_prev = false;
+    sync(c);
+  });
+}
+
+ibr_status ibr_precondition(ibr_ctx* c, const double* r, double* z) {
+  if (!c) return IBR_EINVAL;
+  return guard(c, [&] {
+    require_bodies(c);
+    if (!r || !z) throw Status(IBR_EINVAL, "r and z are required");
+    IBR_HIP(hipSetDevice(c->p.device));
+    hipStream_t s = c->stream;
+    IBR_HIP(hipMemcpyAsync(c->T1, r, (size_t)c->NV * sizeof(double), hipMemcpyHostToDevice, s));
+    if (c->mixed) {
+      float* zf = (float*)c->Zb;
+      precondition<float>(c, c->T1, zf);
+      launch_copy<float, double>(zf, c->T2, c->NV, s);
+    } else {
+      precondition<double>(c, c->T1, c->T2);
+    }
+    IBR_HIP(hipMemcpyAsync(z, c->T2, (size_t)c->NV * sizeof(double), hipMemcpyDeviceToHost, s));
+    sync(c);
+  });
+}
+
+ibr_status ibr_mobility_block(ibr_ctx* c, int body, double* M, double* shift) {
+  if (!c) return IBR_EINVAL;
+  return guard(c, [&] {
+    require_bodies(c);
+    if (body < 0 || body >= c->nb) throw Status(IBR_EINVAL, "body out of range");
+    IBR_HIP(hipSetDevice(c->p.device));
+    const int64_t cnt = c->moff_h[body + 1] - c->moff_h[body];
+    if (M)
+      IBR_HIP(hipMemcpyAsync(M, c->Mb + c->moff_h[body], (size_t)cnt * sizeof(double), hipMemcpyDeviceToHost,
+                             c->stream));
+    if (shift) *shift = c->shift_h[body];
+    sync(c);
+  });
+}
+
+ibr_status ibr_advect(ibr_ctx* c, const double* u, double* N) {
+  if (!c) return IBR_EINVAL;
+  return guard(c, [&] {
+    if (!u || !N) throw Status(IBR_EINVAL, "u and N are required");
+    IBR_HIP(hipSetDevice(c->p.device));
+    const int d = c->dim;
+    hipStream_t s = c->stream;
+    IBR_HIP(hipMemcpyAsync(c->Nprev, u, (size_t)d * c->C * sizeof(double), hipMemcpyHostToDevice, s));
+    launch_advect(d, c->logn, c->Nprev, c->Ncur, 0.5 / c->h, s);
+    IBR_HIP(hipMemcpyAsync(N, c->Ncur, (size_t)d * c->C * sizeof(double), hipMemcpyDeviceToHost, s));
+    c->have_prev = false;
+    sync(c);
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,286 @@
+"""Python binding of the C ABI in include/ibr.h (argument marshalling only).
+
+Every numerical step runs inside ``libibr.so``; this module converts NumPy
+arrays to the layouts the ABI documents and raises ``IbrError`` on any status
+other than IBR_OK.  There is no fallback: if the library is missing the import
+fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libibr.so")
+
+FP64, MIXED = 0, 1
+PC_LOWER, PC_FULL = 0, 1
+
+STATUS = {0: "IBR_OK", 1: "IBR_EINVAL", 2: "IBR_ENOMEM", 3: "IBR_ENOCONV", 4: "IBR_EBREAKDOWN",
+          5: "IBR_EFACTOR", 6: "IBR_ENUMERIC", 7: "IBR_EDEVICE", 8: "IBR_ESTATE"}
+
+
+class IbrError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS.get(status, status), msg))
+        self.status = status
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int), ("h", ctypes.c_double),
+                ("rho", ctypes.c_double), ("eta", ctypes.c_double), ("dt", ctypes.c_double),
+                ("precision", ctypes.c_int), ("pc", ctypes.c_int), ("n_s", ctypes.c_int),
+                ("restart", ctypes.c_int), ("max_iters", ctypes.c_int), ("rtol", ctypes.c_double),
+                ("mg_pre", ctypes.c_int), ("mg_post", ctypes.c_int), ("mg_coarse", ctypes.c_int),
+                ("device", ctypes.c_int), ("stream", ctypes.c_void_p)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("restarts", ctypes.c_int), ("ps_applications", ctypes.c_int),
+                ("vcycles", ctypes.c_int), ("status", ctypes.c_int), ("rel_residual", ctypes.c_double),
+                ("ms", ctypes.c_double), ("max_mobility_shift", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+EXPORTS = ["ibr_default_params", "ibr_status_string", "ibr_create", "ibr_destroy", "ibr_last_error",
+           "ibr_footprint_bytes", "ibr_set_bodies", "ibr_set_velocities", "ibr_set_rhs", "ibr_solve",
+           "ibr_step", "ibr_get_solution", "ibr_get_markers", "ibr_apply_operator", "ibr_spread",
+           "ibr_interp", "ibr_vcycle", "ibr_precondition", "ibr_mobility_block", "ibr_advect"]
+
+
+def load(path=LIB_PATH):
+    if not os.path.exists(path):
+        raise ImportError("libibr.so not built (run __graft_entry__.build()): %s" % path)
+    lib = ctypes.CDLL(path)
+    P = ctypes.POINTER
+    d = ctypes.c_double
+    vp = ctypes.c_void_p
+    dp = P(d)
+    ip = P(ctypes.c_int)
+    sig = {
+        "ibr_default_params": (None, [P(Params)]),
+        "ibr_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+        "ibr_create": (ctypes.c_int, [P(Params), P(vp)]),
+        "ibr_destroy": (None, [vp]),
+        "ibr_last_error": (ctypes.c_char_p, [vp]),
+        "ibr_footprint_bytes": (ctypes.c_size_t, [P(Params), ctypes.c_int, ctypes.c_int]),
+        "ibr_set_bodies": (ctypes.c_int, [vp, ctypes.c_int, ip, dp, dp]),
+        "ibr_set_velocities": (ctypes.c_int, [vp, dp, dp]),
+        "ibr_set_rhs": (ctypes.c_int, [vp, dp, dp]),
+        "ibr_solve": (ctypes.c_int, [vp, ctypes.c_int, P(Info)]),
+        "ibr_step": (ctypes.c_int, [vp, P(Info)]),
+        "ibr_get_solution": (ctypes.c_int, [vp, dp, dp, dp, dp, dp]),
+        "ibr_get_markers": (ctypes.c_int, [vp, dp, dp]),
+        "ibr_apply_operator": (ctypes.c_int, [vp, dp, dp]),
+        "ibr_spread": (ctypes.c_int, [vp, dp, dp]),
+        "ibr_interp": (ctypes.c_int, [vp, dp, dp]),
+        "ibr_vcycle": (ctypes.c_int, [vp, d, d, ctypes.c_int, dp, dp]),
+        "ibr_precondition": (ctypes.c_int, [vp, dp, dp]),
+        "ibr_mobility_block": (ctypes.c_int, [vp, ctypes.c_int, dp, dp]),
+        "ibr_advect": (ctypes.c_int, [vp, dp, dp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+_LIB = None
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        _LIB = load()
+    return _LIB
+
+
+def _dptr(a):
+    if a is None:
+        return None
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def default_params(**kw) -> Params:
+    p = Params()
+    lib().ibr_default_params(ctypes.byref(p))
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+@dataclass
+class Solution:
+    u: np.ndarray
+    p: np.ndarray
+    lam: np.ndarray
+    F: np.ndarray
+    T: np.ndarray
+
+
+class Solver:
+    """One ibr_ctx: a grid size with resident buffers, bodies and solution."""
+
+    def __init__(self, **params):
+        self._lib = lib()
+        self.params = default_params(**params)
+        self._ctx = ctypes.c_void_p()
+        st = self._lib.ibr_create(ctypes.byref(self.params), ctypes.byref(self._ctx))
+        if st != 0:
+            raise IbrError(st, "ibr_create failed")
+        self.dim = self.params.dim
+        self.n = self.params.n
+        self.C = self.n ** self.dim
+        self.N = 0
+        self.nb = 0
+
+    def close(self):
+        if self._ctx:
+            self._lib.ibr_destroy(self._ctx)
+            self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _check(self, st, what):
+        if st != 0:
+            msg = self._lib.ibr_last_error(self._ctx)
+            raise IbrError(st, "%s: %s" % (what, msg.decode() if msg else ""))
+
+    @property
+    def NV(self):
+        return (self.dim + 1) * self.C + self.dim * self.N
+
+    # ------------------------------------------------------------ problem
+    def set_bodies(self, R, offsets, centres):
+        R = _f64(R).reshape(-1, self.dim)
+        off = np.ascontiguousarray(offsets, dtype=np.int32)
+        X = _f64(centres).reshape(-1, self.dim)
+        nb = len(off) - 1
+        self._check(self._lib.ibr_set_bodies(self._ctx, nb, off.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                                             _dptr(R), _dptr(X)), "ibr_set_bodies")
+        self.N = int(off[-1])
+        self.nb = nb
+        self._offsets = off.copy()
+
+    def set_velocities(self, U, Omega):
+        U = _f64(U).reshape(self.nb, self.dim)
+        Om = _f64(Omega).reshape(self.nb, 3 if self.dim == 3 else 1)
+        self._check(self._lib.ibr_set_velocities(self._ctx, _dptr(U), _dptr(Om)), "ibr_set_velocities")
+
+    def set_problem(self, prob):
+        self.set_bodies(prob.R, prob.offsets, prob.centres)
+        self.set_velocities(prob.U, prob.Omega)
+
+    def set_rhs(self, g=None, hp=None):
+        g = None if g is None else _f64(g)
+        hp = None if hp is None else _f64(hp)
+        self._check(self._lib.ibr_set_rhs(self._ctx, _dptr(g), _dptr(hp)), "ibr_set_rhs")
+
+    def solve(self, warm_start=False, check=True):
+        info = Info()
+        st = self._lib.ibr_solve(self._ctx, 1 if warm_start else 0, ctypes.byref(info))
+        if check:
+            self._check(st, "ibr_solve")
+        return info.as_dict()
+
+    def step(self, check=True):
+        info = Info()
+        st = self._lib.ibr_step(self._ctx, ctypes.byref(info))
+        if check:
+            self._check(st, "ibr_step")
+        return info.as_dict()
+
+    def solution(self) -> Solution:
+        d, n = self.dim, self.n
+        u = np.zeros((d,) + (n,) * d)
+        p = np.zeros((n,) * d)
+        lam = np.zeros((self.N, d))
+        F = np.zeros((self.nb, d))
+        T = np.zeros((self.nb, 3 if d == 3 else 1))
+        self._check(self._lib.ibr_get_solution(self._ctx, _dptr(u), _dptr(p), _dptr(lam), _dptr(F), _dptr(T)),
+                    "ibr_get_solution")
+        return Solution(u, p, lam, F, T)
+
+    def markers(self):
+        R = np.zeros((self.N, self.dim))
+        X = np.zeros((self.nb, self.dim))
+        self._check(self._lib.ibr_get_markers(self._ctx, _dptr(R), _dptr(X)), "ibr_get_markers")
+        return R, X
+
+    # ------------------------------------------------------------ single operators
+    def apply_operator(self, x):
+        x = _f64(x).reshape(-1)
+        y = np.zeros(self.NV)
+        self._check(self._lib.ibr_apply_operator(self._ctx, _dptr(x), _dptr(y)), "ibr_apply_operator")
+        return y
+
+    def spread(self, lam):
+        lam = _f64(lam).reshape(self.N, self.dim)
+        f = np.zeros((self.dim,) + (self.n,) * self.dim)
+        self._check(self._lib.ibr_spread(self._ctx, _dptr(lam), _dptr(f)), "ibr_spread")
+        return f
+
+    def interp(self, u):
+        u = _f64(u)
+        V = np.zeros((self.N, self.dim))
+        self._check(self._lib.ibr_interp(self._ctx, _dptr(u), _dptr(V)), "ibr_interp")
+        return V
+
+    def vcycle(self, c0, c1, b):
+        b = _f64(b)
+        nf = b.shape[0] if b.ndim == self.dim + 1 else 1
+        x = np.zeros_like(b)
+        self._check(self._lib.ibr_vcycle(self._ctx, float(c0), float(c1), nf, _dptr(b), _dptr(x)), "ibr_vcycle")
+        return x
+
+    def precondition(self, r):
+        r = _f64(r).reshape(-1)
+        z = np.zeros(self.NV)
+        self._check(self._lib.ibr_precondition(self._ctx, _dptr(r), _dptr(z)), "ibr_precondition")
+        return z
+
+    def mobility_block(self, body):
+        off = self._offsets
+        nrows = self.dim * (off[body + 1] - off[body])
+        M = np.zeros((nrows, nrows))
+        sh = ctypes.c_double()
+        self._check(self._lib.ibr_mobility_block(self._ctx, body, _dptr(M), ctypes.byref(sh)), "ibr_mobility_block")
+        return M, sh.value
+
+    def advect(self, u):
+        u = _f64(u)
+        N = np.zeros_like(u)
+        self._check(self._lib.ibr_advect(self._ctx, _dptr(u), _dptr(N)), "ibr_advect")
+        return N
+
+
+def from_problem(prob, **kw):
+    """Solver for a synthetic Problem (grid parameters taken from it)."""
+    params = dict(dim=prob.dim, n=prob.n, h=prob.h, rho=prob.rho, eta=prob.eta, dt=prob.dt)
+    params.update(kw)
+    s = Solver(**params)
+    s.set_bodies(prob.R, prob.offsets, prob.centres)
+    s.set_velocities(prob.U, prob.Omega)
+    return s

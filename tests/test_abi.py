@@ -1,0 +1,69 @@
+"""Host-side checks of the C ABI: the library builds, loads and exports every
+symbol include/ibr.h declares; host-only calls behave (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "ibr.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ibr_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1505_07865_amd import ibr
+    if not os.path.exists(ibr.LIB_PATH):
+        from paper_1505_07865_amd import build
+        build.build()
+    return ibr.load()
+
+
+def test_exports_match_header(lib):
+    from paper_1505_07865_amd import ibr
+    decl = _declared()
+    assert decl, "no declarations parsed"
+    for name in decl:
+        assert hasattr(lib, name), name
+    assert sorted(ibr.EXPORTS) == decl
+
+
+def test_default_params_and_status(lib):
+    from paper_1505_07865_amd import ibr
+    p = ibr.Params()
+    lib.ibr_default_params(ctypes.byref(p))
+    assert p.dim == 3 and p.restart == 100 and p.n_s == 2 and p.rtol == 1e-8
+    assert lib.ibr_status_string(0) == b"ok"
+    assert lib.ibr_status_string(5).startswith(b"mobility")
+
+
+def test_invalid_params_rejected_before_device_work(lib):
+    from paper_1505_07865_amd import ibr
+    for bad in (dict(dim=4), dict(n=48), dict(h=0.0), dict(eta=-1.0), dict(rho=1.0, dt=0.0), dict(n_s=0),
+                dict(rtol=0.0), dict(precision=7)):
+        p = ibr.default_params(**bad)
+        ctx = ctypes.c_void_p()
+        assert lib.ibr_create(ctypes.byref(p), ctypes.byref(ctx)) == 1, bad
+        assert not ctx.value
+
+
+def test_footprint_grows_with_grid(lib):
+    from paper_1505_07865_amd import ibr
+    f = [lib.ibr_footprint_bytes(ctypes.byref(ibr.default_params(n=n, h=1.0 / n)), 1, 200) for n in (32, 64, 128)]
+    assert f[0] < f[1] < f[2]
+    fm = lib.ibr_footprint_bytes(ctypes.byref(ibr.default_params(n=128, h=1.0 / 128, precision=1)), 1, 200)
+    assert fm < f[2]
+
+
+def test_oracle_is_not_imported_by_product():
+    pkg = os.path.join(ROOT, "paper_1505_07865_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for fn in files:
+            if fn.endswith((".py", ".hip", ".h", ".cpp")):
+                txt = open(os.path.join(dirpath, fn)).read()
+                assert "import oracle" not in txt and "from oracle" not in txt, fn
