@@ -1,0 +1,184 @@
+"""Benchmark: constrained-solve throughput on the 3D 128^3 unsteady workload.
+
+Workload (one MI355X): periodic unit cube, 128^3 MAC grid, rho = 1, Re = 10
+(eta = R/Re, R = 6h), dt = 0.5h; 16 non-overlapping spheres of radius 6h with
+110 Fibonacci markers each (1760 markers, 16 per-body 330x330 mobility blocks),
+each body translating with a seeded velocity U ~ U[-1,1]^3.  A step is one
+time step of the method: explicit advection right-hand side, markers moved and
+re-binned, warm-started FGMRES solve of the constrained system to relative
+residual 1e-8 with the Schur-complement preconditioner (N_s = 2, one V-cycle per
+field).  Inputs are resident in HBM when the timed region starts.
+
+The headline value is the mixed-precision solver's solves/s (fp32
+preconditioner, fp64 outer FGMRES/Arnoldi/Hessenberg/mobility blocks); the
+plain fp64 solver runs the same trajectory for comparison.
+
+    python bench.py [--steps K] [--warmup W] [--re 10] [--seed 0] [--no-cpu-baseline]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=18)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--re", type=float, default=10.0)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precision", choices=["both", "mixed", "fp64"], default="both")
+    return ap.parse_args()
+
+
+def percentile(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    k = (len(xs) - 1) * q / 100.0
+    lo = int(k)
+    hi = min(lo + 1, len(xs) - 1)
+    return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
+
+
+def run_precision(prob, prec, steps, warmup, torch):
+    from paper_1505_07865_amd import ibr
+    s = ibr.from_problem(prob, rtol=1e-8, precision=ibr.MIXED if prec == "mixed" else ibr.FP64, device=0)
+    for _ in range(warmup):
+        s.step()
+    for t in ibr.TIMERS:
+        ibr.timer_enable(t, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat, its, ps, res = [], [], [], []
+    for _ in range(steps):
+        t1 = time.perf_counter()
+        info = s.step()
+        lat.append((time.perf_counter() - t1) * 1e3)
+        its.append(info["iters"])
+        ps.append(info["ps_applications"])
+        res.append(info["rel_residual"])
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    timers = {t: ibr.timer_read(t) for t in ibr.TIMERS}
+    for t in ibr.TIMERS:
+        ibr.timer_enable(t, False)
+    s.close()
+    return {
+        "solves_per_s": steps / total,
+        "ms_per_step": total * 1e3 / steps,
+        "p50_ms": percentile(lat, 50),
+        "p99_ms": percentile(lat, 99),
+        "fgmres_iters_mean": sum(its) / len(its),
+        "ps_applications_mean": sum(ps) / len(ps),
+        "max_rel_residual": max(res),
+        "timers": timers,
+    }
+
+
+def roofline(timers):
+    """Dominant timed kernel class: algorithmic bytes per launch / mean launch time."""
+    best = max(timers.items(), key=lambda kv: kv[1]["ms"])
+    name, t = best
+    if t["launches"] == 0 or t["ms"] <= 0:
+        return None, {}
+    per_launch_s = t["ms"] / 1e3 / t["launches"]
+    gbs = t["bytes"] / t["launches"] / per_launch_s / 1e9
+    others = {}
+    for k, v in timers.items():
+        if v["launches"] and v["ms"] > 0:
+            others[k] = {"gbs": v["bytes"] / (v["ms"] / 1e3) / 1e9, "ms_total": v["ms"],
+                         "launches": v["launches"], "us_per_launch": v["ms"] * 1e3 / v["launches"]}
+    return name, {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                  "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "kernel": name,
+                  "us_per_launch": round(per_launch_s * 1e6, 3),
+                  "bytes_per_launch": t["bytes"] / t["launches"]}, others
+
+
+def cpu_baseline(prob):
+    """The oracle's exact solve of the workload's first time step, timed on the host."""
+    import numpy as np
+    from oracle import constrained, ib
+    b = ib.body_of(prob.offsets)
+    R = np.mod(prob.R + prob.dt * prob.U[b], prob.L)
+    X = np.mod(prob.centres + prob.dt * prob.U, prob.L)
+    V = ib.marker_velocities(R, prob.offsets, X, prob.U, prob.Omega, prob.L)
+    t0 = time.perf_counter()
+    sysm = constrained.System.from_problem(prob, R=R)
+    sol = constrained.solve(sysm, None, None, -V, prob.offsets, X, dense_limit=0, tol=1e-8)
+    dt = time.perf_counter() - t0
+    return {"value": round(1.0 / dt, 5), "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": "one exact constrained solve of the workload's first time step (Fourier Stokes "
+                      "solves + CG on the 5280x5280 mobility system to 1e-8, %d CG iterations), %.1f s "
+                      "single-threaded NumPy" % (sol.cg_iters, dt)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (--gpus 1); multi-GPU sharding is described "
+              "in DESIGN.md but not built", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from synthetic import config2_spheres_ns
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.init()
+    prob = config2_spheres_ns(args.seed, re=args.re)
+    precs = ["fp64", "mixed"] if args.precision == "both" else [args.precision]
+    res = {}
+    for p in precs:
+        print("bench: %s, %d warmup + %d timed steps" % (p, args.warmup, args.steps), file=sys.stderr,
+              flush=True)
+        res[p] = run_precision(prob, p, args.steps, args.warmup, torch)
+        print("bench: %s %.2f solves/s, %.1f FGMRES iters/step" % (p, res[p]["solves_per_s"],
+                                                                   res[p]["fgmres_iters_mean"]),
+              file=sys.stderr, flush=True)
+    head = res["mixed"] if "mixed" in res else res[precs[0]]
+    name, roof, others = roofline(head["timers"])
+    line = {
+        "metric": "solves/s + p50/p99 latency at 1e-8 residual, mixed vs FP64, 3D 128^3",
+        "value": round(head["solves_per_s"], 3),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(head["ms_per_step"], 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 preconditioner + f64 outer" if "mixed" in res else "f64",
+        "data": "synthetic",
+        "config": {"workload": "3D unsteady NS, periodic 128^3 MAC grid, Re=%g, dt=0.5h, 16 moving spheres "
+                               "R=6h x 110 markers, rtol 1e-8, N_s=2, lower-triangular Schur preconditioner"
+                               % args.re,
+                   "grid": 128, "bodies": 16, "markers": int(prob.nmarkers), "re": args.re, "seed": args.seed,
+                   "rtol": 1e-8},
+        "p50_ms": round(head["p50_ms"], 3),
+        "p99_ms": round(head["p99_ms"], 3),
+        "fgmres_iters_per_step": round(head["fgmres_iters_mean"], 2),
+        "ps_applications_per_step": round(head["ps_applications_mean"], 2),
+        "roofline": roof,
+        "kernels": others,
+    }
+    for p in precs:
+        line[p] = {k: (float("%.4g" % v) if isinstance(v, float) else v) for k, v in res[p].items() if k != "timers"}
+    if "mixed" in res and "fp64" in res:
+        line["mixed_over_fp64"] = round(res["mixed"]["solves_per_s"] / res["fp64"]["solves_per_s"], 3)
+    if not args.no_cpu_baseline:
+        print("bench: timing the CPU oracle on one step of the workload", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(prob)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

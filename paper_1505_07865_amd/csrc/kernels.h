@@ -33,6 +33,12 @@ inline void dev_free(void* p) {
   if (p) (void)hipFree(p);
 }
 
+// ---------------------------------------------------------------- live kernel timers
+enum TimerId { kTimerRbFine = 0, kTimerOrthoDot = 1, kTimerOrthoAxpy = 2, kTimerStokes = 3, kTimerCount = 4 };
+bool timer_on(int id);
+void timer_begin(int id, hipStream_t s);
+void timer_end(int id, hipStream_t s, double bytes);
+
 // ---------------------------------------------------------------- grid stencils
 template <typename TI, typename TO>
 void launch_stokes_apply(int dim, int logn, const TI* v, const TI* p, TO* yv, TO* yp, double c0, double ch2,
@@ -66,6 +72,7 @@ struct MGHier {
   // One V-cycle for nf fields: x = V(b).  x and b hold nf fields of n^dim.
   void vcycle(int nf, const T* b, T* x, double c0, double c1, int nu_pre, int nu_post, int nu_coarse,
               hipStream_t s);
+  void rb_half(T* x, const T* b, int lg, int nf, T c0, T c1, int color, bool from_zero, bool fine, hipStream_t s);
 };
 
 // ---------------------------------------------------------------- markers / IB
@@ -106,13 +113,27 @@ void launch_body_force_torque(int dim, int nb, const int* offsets, const double*
 
 // ---------------------------------------------------------------- Krylov
 // h[j] = <w, V_j> for j < k (V_j = V + j*ld); two-pass deterministic reduction.
+// cond: optional device flag; when it holds 0 the kernels return at once.
 template <typename TV, typename TW>
 void launch_multi_dot(const TV* V, int64_t ld, int k, const TW* w, int64_t len, double* part, int nblocks,
-                      double* h, bool accumulate, hipStream_t s);
+                      double* h, bool accumulate, hipStream_t s, const int* cond = nullptr);
 // w -= sum_j h[j] V_j ; if norm_part != null also writes partial sums of w^2.
 template <typename TV, typename TW>
 void launch_multi_axpy(const TV* V, int64_t ld, int k, const double* h, TW* w, int64_t len, double* norm_part,
-                       int nblocks, hipStream_t s);
+                       int nblocks, hipStream_t s, const int* cond = nullptr);
+// Arnoldi orthogonalisation of w = V_{k+1} against V_0..V_k (basis stride ld):
+// classical Gram-Schmidt; with reorth, a second pass when the DGKS criterion
+// asks for it.  Writes hcol[0..k+1] (hcol[k+1] = ||w||); w is left unnormalised.
+template <typename T>
+void arnoldi_step(const T* V, int64_t ld, int k, double* hcol, double* h2, double* part1, double* part2,
+                  int nblocks, int* flag, hipStream_t s, bool timed = false, bool reorth = true);
+// One delayed-CGS2 Arnoldi step of the outer FGMRES (see ops_krylov.hip):
+// V_k pending on entry, w = V_{k+1}; afterwards V_k is final, V_{k+1} pending,
+// H column k-1 final and rotated, column k provisional, *resid the estimate.
+// G needs 2(k+2) doubles, coef 2k+2, part 2(k+2)*nblocks.
+template <typename T>
+void dcgs2_step(T* V, int64_t ld, int k, double* H, int ldh, double* G, double* coef, double* part, int nblocks,
+                double* cs, double* sn, double* g, double* resid, hipStream_t s, bool timed);
 // x += sum_j y[j] Z_j  (Z in TZ, x in TX)
 template <typename TZ, typename TX>
 void launch_combine(const TZ* Z, int64_t ld, int k, const double* y, TX* x, int64_t len, hipStream_t s);

@@ -188,55 +188,44 @@ __global__ void k_active_tiles(int dim, int tiles_log, const int* __restrict__ o
 }
 
 // ---------------------------------------------------------------- spreading (gather)
-constexpr int kSpreadThreads = 256;
-constexpr int kSpreadChunk = 64;
+constexpr int kSpreadChunk = 128;
 
-template <typename TL, typename TY>
-__global__ void __launch_bounds__(kSpreadThreads) k_spread(int dim, int logn, int tile_log,
-                                                            const int* __restrict__ active,
-                                                            const int* __restrict__ off,
-                                                            const int* __restrict__ perm,
-                                                            const int* __restrict__ tbase,
-                                                            const double* __restrict__ tw,
-                                                            const TL* __restrict__ lam, TY* __restrict__ y,
-                                                            double scale) {
-  __shared__ int s_base[kSpreadChunk][2][3];
-  __shared__ double s_w[kSpreadChunk][2][3][4];
-  __shared__ double s_lam[kSpreadChunk][3];
-  __shared__ int s_ids[kSpreadChunk];
-  constexpr int kMaxFaces = 6;  // faces per thread: 8^3*3/256 (3D), 16^2*2/256 (2D)
-
+// One workgroup per (active tile, component a); one thread per cell of the
+// tile (8^3 in 3D, 16^2 in 2D).  The markers of the neighbouring tiles are
+// staged in LDS chunk by chunk, always in the same order, and every thread
+// sums the contributions to its own a-face: no atomics, bitwise reproducible.
+template <typename TL, typename TY, int DIM>
+__global__ void __launch_bounds__(512) k_spread(int logn, int tile_log, const int* __restrict__ active,
+                                                const int* __restrict__ off, const int* __restrict__ perm,
+                                                const int* __restrict__ tbase, const double* __restrict__ tw,
+                                                const TL* __restrict__ lam, TY* __restrict__ y, double scale) {
+  __shared__ int s_base[kSpreadChunk][DIM];
+  __shared__ double s_w[kSpreadChunk][DIM][4];
+  __shared__ double s_l[kSpreadChunk];
   const int n = 1 << logn;
-  const int64_t C = (int64_t)1 << (dim * logn);
+  const int mask = n - 1;
+  const int64_t C = (int64_t)1 << (DIM * logn);
   const int tiles_log = logn - tile_log;
   const int nt = 1 << tiles_log;
   const int tile = active[blockIdx.x];
+  const int a = blockIdx.y;
   const int tsz = 1 << tile_log;
-  const int tc[3] = {tile & (nt - 1), (tile >> tiles_log) & (nt - 1), dim == 3 ? (tile >> (2 * tiles_log)) : 0};
-  const int cells = 1 << (dim * tile_log);
-  const int nfaces = cells * dim;
-
-  // faces owned by this thread
-  double acc[kMaxFaces];
-  int fc[kMaxFaces][3];
-  int fa[kMaxFaces];
-  int nf = 0;
-  for (int f = threadIdx.x; f < nfaces && nf < kMaxFaces; f += blockDim.x, ++nf) {
-    const int a = f / cells;
-    const int lc = f - a * cells;
-    fa[nf] = a;
-    fc[nf][0] = tc[0] * tsz + (lc & (tsz - 1));
-    fc[nf][1] = tc[1] * tsz + ((lc >> tile_log) & (tsz - 1));
-    fc[nf][2] = dim == 3 ? tc[2] * tsz + (lc >> (2 * tile_log)) : 0;
-    acc[nf] = 0.0;
-  }
+  const int tc[3] = {tile & (nt - 1), (tile >> tiles_log) & (nt - 1), DIM == 3 ? (tile >> (2 * tiles_log)) : 0};
+  const int lc = threadIdx.x;
+  const bool live = lc < (1 << (DIM * tile_log));
+  int fc[3];
+  fc[0] = tc[0] * tsz + (lc & (tsz - 1));
+  fc[1] = tc[1] * tsz + ((lc >> tile_log) & (tsz - 1));
+  fc[2] = DIM == 3 ? tc[2] * tsz + ((lc >> (2 * tile_log)) & (tsz - 1)) : 0;
 
   int cx[3], cy[3], cz[3];
   const int nx = nbr_coords(tc[0], nt, cx);
   const int ny = nbr_coords(tc[1], nt, cy);
-  const int nz = dim == 3 ? nbr_coords(tc[2], nt, cz) : 1;
-  if (dim == 2) cz[0] = 0;
+  int nz = 1;
+  cz[0] = 0;
+  if (DIM == 3) nz = nbr_coords(tc[2], nt, cz);
 
+  double acc = 0.0;
   for (int a3 = 0; a3 < nz; ++a3)
     for (int b3 = 0; b3 < ny; ++b3)
       for (int c3 = 0; c3 < nx; ++c3) {
@@ -245,41 +234,35 @@ __global__ void __launch_bounds__(kSpreadThreads) k_spread(int dim, int logn, in
         for (int c0 = lo; c0 < hi; c0 += kSpreadChunk) {
           const int cnt = min(kSpreadChunk, hi - c0);
           __syncthreads();
-          for (int q = threadIdx.x; q < cnt; q += blockDim.x) {
-            const int m = perm[c0 + q];
-            s_ids[q] = m;
-            for (int d = 0; d < dim; ++d) s_lam[q][d] = (double)lam[m * dim + d];
-          }
-          for (int q = threadIdx.x; q < cnt * 2 * 3; q += blockDim.x) {
-            const int mm = q / 6, r = q - mm * 6;
+          for (int q = threadIdx.x; q < cnt * DIM; q += blockDim.x) {
+            const int mm = q / DIM, d = q - mm * DIM;
             const int m = perm[c0 + mm];
-            s_base[mm][r / 3][r % 3] = tbase[m * 6 + r];
-            for (int t = 0; t < 4; ++t) s_w[mm][r / 3][r % 3][t] = tw[(m * 6 + r) * 4 + t];
+            const int r = (d == a ? 3 : 0) + d;  // face staggering on axis a, cell-centred elsewhere
+            s_base[mm][d] = tbase[m * 6 + r];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) s_w[mm][d][t] = tw[(m * 6 + r) * 4 + t];
+            if (d == 0) s_l[mm] = (double)lam[m * DIM + a];
           }
           __syncthreads();
-          for (int q = 0; q < cnt; ++q) {
-            for (int f = 0; f < nf; ++f) {
-              const int a = fa[f];
-              double w = s_lam[q][a];
-              bool in = true;
-              for (int d = 0; d < dim; ++d) {
-                const int s = d == a ? 1 : 0;
-                const int t = (fc[f][d] - s_base[q][s][d]) & (n - 1);
-                if (t >= 4) {
-                  in = false;
-                  break;
-                }
-                w *= s_w[q][s][d][t];
+          if (live) {
+            for (int q = 0; q < cnt; ++q) {
+              const int t0 = (fc[0] - s_base[q][0]) & mask;
+              const int t1 = (fc[1] - s_base[q][1]) & mask;
+              int t2 = 0;
+              if (DIM == 3) t2 = (fc[2] - s_base[q][DIM - 1]) & mask;
+              if (t0 < 4 && t1 < 4 && t2 < 4) {
+                double w = s_l[q] * s_w[q][0][t0] * s_w[q][1][t1];
+                if (DIM == 3) w *= s_w[q][DIM - 1][t2];
+                acc += w;
               }
-              if (in) acc[f] += w;
             }
           }
         }
       }
-  for (int f = 0; f < nf; ++f) {
-    const int64_t c = (int64_t)fc[f][0] + ((int64_t)fc[f][1] << logn) + ((int64_t)fc[f][2] << (2 * logn));
-    const int64_t idx = fa[f] * C + c;
-    y[idx] = (TY)((double)y[idx] + scale * acc[f]);
+  if (live) {
+    const int64_t c = (int64_t)fc[0] + ((int64_t)fc[1] << logn) + ((int64_t)fc[2] << (2 * logn));
+    const int64_t idx = (int64_t)a * C + c;
+    y[idx] = (TY)((double)y[idx] + scale * acc);
   }
 }
 
@@ -425,8 +408,13 @@ template <typename TL, typename TY>
 void launch_spread(int dim, int logn, int tile_log, int nactive, const int* active_list, const int* offsets,
                    const int* perm, MarkerTaps taps, const TL* lam, TY* y, double scale, hipStream_t s) {
   if (nactive <= 0) return;
-  hipLaunchKernelGGL((k_spread<TL, TY>), dim3(nactive), dim3(kSpreadThreads), 0, s, dim, logn, tile_log,
-                     active_list, offsets, perm, taps.base, taps.w64, lam, y, scale);
+  const int threads = 1 << (dim * tile_log);
+  if (dim == 3)
+    hipLaunchKernelGGL((k_spread<TL, TY, 3>), dim3(nactive, 3), dim3(threads), 0, s, logn, tile_log, active_list,
+                       offsets, perm, taps.base, taps.w64, lam, y, scale);
+  else
+    hipLaunchKernelGGL((k_spread<TL, TY, 2>), dim3(nactive, 2), dim3(threads), 0, s, logn, tile_log, active_list,
+                       offsets, perm, taps.base, taps.w64, lam, y, scale);
 }
 template void launch_spread<double, double>(int, int, int, int, const int*, const int*, const int*, MarkerTaps,
                                             const double*, double*, double, hipStream_t);

@@ -15,7 +15,9 @@ inline unsigned nblk(int64_t len, int bs = 256) { return (unsigned)((len + bs - 
 // part[j * nblocks + block] = partial <w, V_j> for j in this block's column chunk.
 template <typename TV, typename TW>
 __global__ void __launch_bounds__(256) k_multi_dot(const TV* __restrict__ V, int64_t ld, int k,
-                                                   const TW* __restrict__ w, int64_t len, double* __restrict__ part) {
+                                                   const TW* __restrict__ w, int64_t len, double* __restrict__ part,
+                                                   const int* __restrict__ cond) {
+  if (cond && cond[0] == 0) return;
   __shared__ double red[kDotCols][256 / kWave];
   const int j0 = blockIdx.y * kDotCols;
   const int nj = min(kDotCols, k - j0);
@@ -43,7 +45,9 @@ __global__ void __launch_bounds__(256) k_multi_dot(const TV* __restrict__ V, int
   }
 }
 
-__global__ void k_dot_finish(const double* __restrict__ part, int nblocks, double* __restrict__ h, int accumulate) {
+__global__ void k_dot_finish(const double* __restrict__ part, int nblocks, double* __restrict__ h, int accumulate,
+                             const int* __restrict__ cond) {
+  if (cond && cond[0] == 0) return;
   __shared__ double red[256 / kWave];
   const int j = blockIdx.x;
   double s = 0;
@@ -55,7 +59,8 @@ __global__ void k_dot_finish(const double* __restrict__ part, int nblocks, doubl
 template <typename TV, typename TW>
 __global__ void __launch_bounds__(256) k_multi_axpy(const TV* __restrict__ V, int64_t ld, int k,
                                                     const double* __restrict__ h, TW* __restrict__ w, int64_t len,
-                                                    double* __restrict__ norm_part) {
+                                                    double* __restrict__ norm_part, const int* __restrict__ cond) {
+  if (cond && cond[0] == 0) return;
   __shared__ double red[256 / kWave];
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   double ss = 0;
@@ -125,6 +130,202 @@ __global__ void k_axpby(const double* __restrict__ x, double* __restrict__ y, in
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += stride) y[i] = a * x[i] + b * y[i];
 }
 
+// Daniel-Gragg-Kaufman-Stewart test after one Gram-Schmidt pass: hcol[k+1]
+// holds ||w||^2 before the pass, part1 the partial sums of ||w||^2 after it.
+// Re-orthogonalise (flag = 1) when the norm dropped below 1/sqrt(2) of its
+// value; otherwise store the final norm in hcol[k+1].
+__global__ void k_dgks_decide(double* __restrict__ hcol, int k, const double* __restrict__ part1, int nblocks,
+                              int* __restrict__ flag) {
+  __shared__ double red[256 / kWave];
+  double s = 0;
+  for (int i = threadIdx.x; i < nblocks; i += blockDim.x) s += part1[i];
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) {
+    const double before = hcol[k + 1];
+    const int f = s < 0.5 * before ? 1 : 0;
+    flag[0] = f;
+    if (!f) hcol[k + 1] = sqrt(s);
+  }
+}
+
+// After the second pass: hcol[0..k] += h2, hcol[k+1] = ||w||.
+__global__ void k_dgks_finish(double* __restrict__ hcol, int k, const double* __restrict__ h2,
+                              const double* __restrict__ part2, int nblocks, const int* __restrict__ flag) {
+  if (flag[0] == 0) return;
+  __shared__ double red[256 / kWave];
+  double s = 0;
+  for (int i = threadIdx.x; i < nblocks; i += blockDim.x) s += part2[i];
+  s = block_sum(s, red);
+  for (int i = threadIdx.x; i <= k; i += blockDim.x) hcol[i] += h2[i];
+  if (threadIdx.x == 0) hcol[k + 1] = sqrt(s);
+}
+
+// ---------------------------------------------------------------- delayed CGS2 (outer Arnoldi)
+// Basis layout V_0..V_{k+1} with stride ld.  On entry to iteration k, V_k is
+// the "pending" vector (one Gram-Schmidt pass, not normalised) and V_{k+1} = w
+// = K z_k.  One reduction computes <V_j, V_k> and <V_j, w> for all j; one
+// update pass re-orthogonalises and normalises V_k and projects w; w stays
+// pending for the next iteration.  Same stability as two-pass CGS with half
+// the passes over the basis.
+
+// part[(2 j + r) * nblocks + block]: r = 0 against V_k, r = 1 against w.
+template <typename T>
+__global__ void __launch_bounds__(256) k_dual_dot(const T* __restrict__ V, int64_t ld, int ncols, int kx,
+                                                  int64_t len, double* __restrict__ part) {
+  __shared__ double red[2 * kDotCols][256 / kWave];
+  const int j0 = blockIdx.y * kDotCols;
+  const int nj = min(kDotCols, ncols - j0);
+  const T* x1 = V + (int64_t)kx * ld;
+  const T* x2 = V + (int64_t)(kx + 1) * ld;
+  double a1[kDotCols], a2[kDotCols];
+#pragma unroll
+  for (int q = 0; q < kDotCols; ++q) a1[q] = a2[q] = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += stride) {
+    const double u = (double)x1[i], w = (double)x2[i];
+#pragma unroll
+    for (int q = 0; q < kDotCols; ++q)
+      if (q < nj) {
+        const double v = (double)V[(int64_t)(j0 + q) * ld + i];
+        a1[q] += v * u;
+        a2[q] += v * w;
+      }
+  }
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+#pragma unroll
+  for (int q = 0; q < kDotCols; ++q) {
+    const double s1 = wave_sum(a1[q]);
+    const double s2 = wave_sum(a2[q]);
+    if (lane == 0) {
+      red[2 * q][wv] = s1;
+      red[2 * q + 1][wv] = s2;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 2 * nj) {
+    double t = 0;
+    for (int u = 0; u < (int)(blockDim.x / kWave); ++u) t += red[threadIdx.x][u];
+    part[(int64_t)(2 * j0 + threadIdx.x) * gridDim.x + blockIdx.x] = t;
+  }
+}
+
+// Coefficients of the delayed step.  G[2j] = <V_j, V_k>, G[2j+1] = <V_j, w>.
+// coef[0..k) = s (re-orthogonalisation of V_k), coef[k] = nu, coef[k+1 .. 2k+1] = c.
+// Column k-1 of H is corrected (its pending vector is now resolved) and the
+// provisional column k is written.
+__global__ void k_dcgs2_coef(const double* __restrict__ G, int k, double* __restrict__ H, int ldh,
+                             double* __restrict__ coef) {
+  if (threadIdx.x != 0) return;
+  double* colk = H + (int64_t)k * ldh;
+  if (k == 0) {
+    coef[0] = 1.0;
+    coef[1] = G[1];
+    colk[0] = G[1];
+    return;
+  }
+  double ss = 0.0, sg = 0.0;
+  for (int j = 0; j < k; ++j) {
+    const double sj = G[2 * j];
+    coef[j] = sj;
+    ss += sj * sj;
+    sg += sj * G[2 * j + 1];
+  }
+  const double alpha = G[2 * k];
+  double nu2 = alpha - ss;
+  if (!(nu2 > 0.0)) nu2 = alpha > 0.0 ? alpha * 1e-30 : 1e-300;
+  const double nu = sqrt(nu2);
+  coef[k] = nu;
+  double* colp = H + (int64_t)(k - 1) * ldh;
+  for (int j = 0; j < k; ++j) colp[j] += coef[j];
+  colp[k] = nu;
+  for (int j = 0; j < k; ++j) {
+    coef[k + 1 + j] = G[2 * j + 1];
+    colk[j] = G[2 * j + 1];
+  }
+  const double ck = (G[2 * k + 1] - sg) / nu;
+  coef[2 * k + 1] = ck;
+  colk[k] = ck;
+}
+
+// V_k <- (V_k - sum_{j<k} s_j V_j) / nu ;  w <- w - sum_{j<k} c_j V_j - c_k V_k(new).
+// part[block] = partial sums of the new w^2.
+template <typename T>
+__global__ void __launch_bounds__(256) k_dcgs2_axpy(T* __restrict__ V, int64_t ld, int k,
+                                                    const double* __restrict__ coef, int64_t len,
+                                                    double* __restrict__ part) {
+  __shared__ double red[256 / kWave];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  T* vk = V + (int64_t)k * ld;
+  T* w = V + (int64_t)(k + 1) * ld;
+  const double inv_nu = 1.0 / coef[k];
+  const double* c = coef + k + 1;
+  double ss = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += stride) {
+    double q = (double)vk[i];
+    double a = (double)w[i];
+    for (int j = 0; j < k; ++j) {
+      const double v = (double)V[(int64_t)j * ld + i];
+      q -= coef[j] * v;
+      a -= c[j] * v;
+    }
+    if (k > 0) {
+      q *= inv_nu;
+      vk[i] = (T)q;
+    }
+    a -= c[k] * q;
+    const T o = (T)a;
+    w[i] = o;
+    ss += (double)o * (double)o;
+  }
+  ss = block_sum(ss, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = ss;
+}
+
+// Provisional h_{k+1,k} = ||w||; finish the Givens rotation of column k-1
+// (final now) and estimate the residual with a temporary rotation of column k.
+__global__ void k_dcgs2_finish(const double* __restrict__ part, int nblocks, double* __restrict__ H, int ldh,
+                               int k, double* __restrict__ cs, double* __restrict__ sn, double* __restrict__ g,
+                               double* __restrict__ resid) {
+  __shared__ double red[256 / kWave];
+  double s = 0;
+  for (int i = threadIdx.x; i < nblocks; i += blockDim.x) s += part[i];
+  s = block_sum(s, red);
+  if (threadIdx.x != 0) return;
+  double* colk = H + (int64_t)k * ldh;
+  colk[k + 1] = sqrt(s);
+  if (k > 0) {
+    double* col = H + (int64_t)(k - 1) * ldh;
+    const int kk = k - 1;
+    for (int i = 0; i < kk; ++i) {
+      const double t = cs[i] * col[i] + sn[i] * col[i + 1];
+      col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
+      col[i] = t;
+    }
+    const double a = col[kk], b = col[kk + 1];
+    const double r = hypot(a, b);
+    double cc = 1.0, sv = 0.0;
+    if (r > 0.0) {
+      cc = a / r;
+      sv = b / r;
+    }
+    cs[kk] = cc;
+    sn[kk] = sv;
+    col[kk] = r;
+    col[kk + 1] = 0.0;
+    const double gk = g[kk];
+    g[kk] = cc * gk;
+    g[kk + 1] = -sv * gk;
+  }
+  // residual estimate: rotations 0..k-1 applied to a copy of column k; only
+  // the rotated entry k and h_{k+1,k} matter for the new rotation.
+  double t0 = colk[0];
+  for (int i = 0; i < k; ++i) t0 = -sn[i] * t0 + cs[i] * colk[i + 1];
+  const double t1 = colk[k + 1];
+  const double r = hypot(t0, t1);
+  const double sv = r > 0.0 ? t1 / r : 0.0;
+  resid[0] = fabs(sv * g[k]);
+}
+
 // Apply the previous rotations to column k of H, build rotation k, update g.
 __global__ void k_givens_step(double* __restrict__ H, int ldh, int k, double* __restrict__ cs,
                               double* __restrict__ sn, double* __restrict__ g, double* __restrict__ resid) {
@@ -179,26 +380,54 @@ int krylov_dot_blocks(int64_t len) {
 
 template <typename TV, typename TW>
 void launch_multi_dot(const TV* V, int64_t ld, int k, const TW* w, int64_t len, double* part, int nblocks,
-                      double* h, bool accumulate, hipStream_t s) {
+                      double* h, bool accumulate, hipStream_t s, const int* cond) {
   if (k <= 0) return;
   const int nchunk = (k + kDotCols - 1) / kDotCols;
-  hipLaunchKernelGGL((k_multi_dot<TV, TW>), dim3(nblocks, nchunk), dim3(256), 0, s, V, ld, k, w, len, part);
-  hipLaunchKernelGGL(k_dot_finish, dim3(k), dim3(256), 0, s, part, nblocks, h, accumulate ? 1 : 0);
+  hipLaunchKernelGGL((k_multi_dot<TV, TW>), dim3(nblocks, nchunk), dim3(256), 0, s, V, ld, k, w, len, part, cond);
+  hipLaunchKernelGGL(k_dot_finish, dim3(k), dim3(256), 0, s, part, nblocks, h, accumulate ? 1 : 0, cond);
 }
 template void launch_multi_dot<double, double>(const double*, int64_t, int, const double*, int64_t, double*, int,
-                                               double*, bool, hipStream_t);
+                                               double*, bool, hipStream_t, const int*);
 template void launch_multi_dot<float, float>(const float*, int64_t, int, const float*, int64_t, double*, int,
-                                             double*, bool, hipStream_t);
+                                             double*, bool, hipStream_t, const int*);
 
 template <typename TV, typename TW>
 void launch_multi_axpy(const TV* V, int64_t ld, int k, const double* h, TW* w, int64_t len, double* norm_part,
-                       int nblocks, hipStream_t s) {
-  hipLaunchKernelGGL((k_multi_axpy<TV, TW>), dim3(nblocks), dim3(256), 0, s, V, ld, k, h, w, len, norm_part);
+                       int nblocks, hipStream_t s, const int* cond) {
+  hipLaunchKernelGGL((k_multi_axpy<TV, TW>), dim3(nblocks), dim3(256), 0, s, V, ld, k, h, w, len, norm_part,
+                     cond);
 }
 template void launch_multi_axpy<double, double>(const double*, int64_t, int, const double*, double*, int64_t,
-                                                double*, int, hipStream_t);
+                                                double*, int, hipStream_t, const int*);
 template void launch_multi_axpy<float, float>(const float*, int64_t, int, const double*, float*, int64_t, double*,
-                                              int, hipStream_t);
+                                              int, hipStream_t, const int*);
+
+template <typename T>
+void arnoldi_step(const T* V, int64_t ld, int k, double* hcol, double* h2, double* part1, double* part2,
+                  int nblocks, int* flag, hipStream_t s, bool timed, bool reorth) {
+  T* w = const_cast<T*>(V) + (int64_t)(k + 1) * ld;
+  const double vb = (double)ld * sizeof(T);
+  // pass 1: columns 0..k+1 (the last one is w itself, giving ||w||^2 in hcol[k+1])
+  if (timed) timer_begin(kTimerOrthoDot, s);
+  launch_multi_dot<T, T>(V, ld, k + 2, w, ld, part1, nblocks, hcol, false, s, nullptr);
+  if (timed) timer_end(kTimerOrthoDot, s, (k + 2) * vb);
+  if (timed) timer_begin(kTimerOrthoAxpy, s);
+  launch_multi_axpy<T, T>(V, ld, k + 1, hcol, w, ld, part1, nblocks, s, nullptr);
+  if (timed) timer_end(kTimerOrthoAxpy, s, (k + 3) * vb);
+  if (!reorth) {
+    launch_norm_finish(part1, nblocks, hcol + k + 1, s);
+    return;
+  }
+  hipLaunchKernelGGL(k_dgks_decide, dim3(1), dim3(256), 0, s, hcol, k, part1, nblocks, flag);
+  // pass 2 only when the DGKS test asks for it
+  launch_multi_dot<T, T>(V, ld, k + 1, w, ld, part2, nblocks, h2, false, s, flag);
+  launch_multi_axpy<T, T>(V, ld, k + 1, h2, w, ld, part2, nblocks, s, flag);
+  hipLaunchKernelGGL(k_dgks_finish, dim3(1), dim3(256), 0, s, hcol, k, h2, part2, nblocks, flag);
+}
+template void arnoldi_step<double>(const double*, int64_t, int, double*, double*, double*, double*, int, int*,
+                                   hipStream_t, bool, bool);
+template void arnoldi_step<float>(const float*, int64_t, int, double*, double*, double*, double*, int, int*,
+                                  hipStream_t, bool, bool);
 
 template <typename TZ, typename TX>
 void launch_combine(const TZ* Z, int64_t ld, int k, const double* y, TX* x, int64_t len, hipStream_t s) {
@@ -252,6 +481,25 @@ void launch_axpby(const double* x, double* y, int64_t len, double a, double b, h
   if (g > 4096) g = 4096;
   hipLaunchKernelGGL(k_axpby, dim3(g), dim3(256), 0, s, x, y, len, a, b);
 }
+
+template <typename T>
+void dcgs2_step(T* V, int64_t ld, int k, double* H, int ldh, double* G, double* coef, double* part, int nblocks,
+                double* cs, double* sn, double* g, double* resid, hipStream_t s, bool timed) {
+  const int ncols = k + 2;
+  const int nchunk = (ncols + kDotCols - 1) / kDotCols;
+  const double vb = (double)ld * sizeof(T);
+  if (timed) timer_begin(kTimerOrthoDot, s);
+  hipLaunchKernelGGL((k_dual_dot<T>), dim3(nblocks, nchunk), dim3(256), 0, s, V, ld, ncols, k, ld, part);
+  if (timed) timer_end(kTimerOrthoDot, s, ncols * vb);
+  hipLaunchKernelGGL(k_dot_finish, dim3(2 * ncols), dim3(256), 0, s, part, nblocks, G, 0, (const int*)nullptr);
+  hipLaunchKernelGGL(k_dcgs2_coef, dim3(1), dim3(64), 0, s, G, k, H, ldh, coef);
+  if (timed) timer_begin(kTimerOrthoAxpy, s);
+  hipLaunchKernelGGL((k_dcgs2_axpy<T>), dim3(nblocks), dim3(256), 0, s, V, ld, k, coef, ld, part);
+  if (timed) timer_end(kTimerOrthoAxpy, s, (ncols + 2) * vb);
+  hipLaunchKernelGGL(k_dcgs2_finish, dim3(1), dim3(256), 0, s, part, nblocks, H, ldh, k, cs, sn, g, resid);
+}
+template void dcgs2_step<double>(double*, int64_t, int, double*, int, double*, double*, double*, int, double*,
+                                 double*, double*, double*, hipStream_t, bool);
 
 void launch_givens_step(double* H, int ldh, int k, double* cs, double* sn, double* g, double* resid,
                         hipStream_t s) {

@@ -404,6 +404,20 @@ size_t MGHier<T>::bytes(int dim, int logn, int nf) {
 }
 
 template <typename T>
+void MGHier<T>::rb_half(T* x, const T* b, int lg, int nf, T c0, T c1, int color, bool from_zero, bool fine,
+                        hipStream_t s) {
+  const int64_t Cl = (int64_t)1 << (dim * lg);
+  const dim3 gh(nblk(Cl / 2), nf);
+  if (fine) timer_begin(kTimerRbFine, s);
+  if (dim == 3)
+    hipLaunchKernelGGL((k_rb<T, 3>), gh, dim3(256), 0, s, x, b, lg, c0, c1, color, from_zero ? 1 : 0);
+  else
+    hipLaunchKernelGGL((k_rb<T, 2>), gh, dim3(256), 0, s, x, b, lg, c0, c1, color, from_zero ? 1 : 0);
+  // algorithmic traffic of a half sweep: b and x of one colour, x of the other
+  if (fine) timer_end(kTimerRbFine, s, 1.5 * (double)Cl * nf * sizeof(T));
+}
+
+template <typename T>
 void MGHier<T>::vcycle(int nf, const T* b, T* x, double c0, double c1, int nu_pre, int nu_post, int nu_coarse,
                        hipStream_t s) {
   const bool three = dim == 3;
@@ -415,19 +429,11 @@ void MGHier<T>::vcycle(int nf, const T* b, T* x, double c0, double c1, int nu_pr
     const int64_t Cl = (int64_t)1 << (dim * lg);
     T* xl = l == 0 ? x : bufs_x[l];
     const T* bl = l == 0 ? b : bufs_b[l];
-    const dim3 gh(nblk(Cl / 2), nf);
     if (nu_pre <= 0) {
       launch_fill<T>(xl, Cl * nf, T(0), s);
     }
-    for (int sw = 0; sw < nu_pre; ++sw) {
-      if (three) {
-        hipLaunchKernelGGL((k_rb<T, 3>), gh, dim3(256), 0, s, xl, bl, lg, tc0, cl, 0, sw == 0 ? 1 : 0);
-        hipLaunchKernelGGL((k_rb<T, 3>), gh, dim3(256), 0, s, xl, bl, lg, tc0, cl, 1, 0);
-      } else {
-        hipLaunchKernelGGL((k_rb<T, 2>), gh, dim3(256), 0, s, xl, bl, lg, tc0, cl, 0, sw == 0 ? 1 : 0);
-        hipLaunchKernelGGL((k_rb<T, 2>), gh, dim3(256), 0, s, xl, bl, lg, tc0, cl, 1, 0);
-      }
-    }
+    for (int sw = 0; sw < nu_pre; ++sw)
+      for (int color = 0; color < 2; ++color) rb_half(xl, bl, lg, nf, tc0, cl, color, sw == 0 && color == 0, l == 0, s);
     const int64_t Cc = Cl >> dim;
     if (three)
       hipLaunchKernelGGL((k_resid_restrict<T, 3>), dim3(nblk(Cc), nf), dim3(256), 0, s, xl, bl, bufs_b[l + 1], lg,
@@ -453,20 +459,12 @@ void MGHier<T>::vcycle(int nf, const T* b, T* x, double c0, double c1, int nu_pr
     const int64_t Cl = (int64_t)1 << (dim * lg);
     T* xl = l == 0 ? x : bufs_x[l];
     const T* bl = l == 0 ? b : bufs_b[l];
-    const dim3 gh(nblk(Cl / 2), nf);
     if (three)
       hipLaunchKernelGGL((k_prolong_add<T, 3>), dim3(nblk(Cl), nf), dim3(256), 0, s, xl, bufs_x[l + 1], lg);
     else
       hipLaunchKernelGGL((k_prolong_add<T, 2>), dim3(nblk(Cl), nf), dim3(256), 0, s, xl, bufs_x[l + 1], lg);
-    for (int sw = 0; sw < nu_post; ++sw) {
-      if (three) {
-        hipLaunchKernelGGL((k_rb<T, 3>), gh, dim3(256), 0, s, xl, bl, lg, tc0, cl, 0, 0);
-        hipLaunchKernelGGL((k_rb<T, 3>), gh, dim3(256), 0, s, xl, bl, lg, tc0, cl, 1, 0);
-      } else {
-        hipLaunchKernelGGL((k_rb<T, 2>), gh, dim3(256), 0, s, xl, bl, lg, tc0, cl, 0, 0);
-        hipLaunchKernelGGL((k_rb<T, 2>), gh, dim3(256), 0, s, xl, bl, lg, tc0, cl, 1, 0);
-      }
-    }
+    for (int sw = 0; sw < nu_post; ++sw)
+      for (int color = 0; color < 2; ++color) rb_half(xl, bl, lg, nf, tc0, cl, color, false, l == 0, s);
   }
 }
 

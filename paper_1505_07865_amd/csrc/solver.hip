@@ -95,7 +95,8 @@ struct ibr_ctx {
   double* Vb = nullptr;
   void* Zb = nullptr;  // double or float
   double *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr, *y = nullptr, *resid = nullptr, *beta = nullptr,
-         *hc2 = nullptr, *part = nullptr;
+         *hc2 = nullptr, *part = nullptr, *part2 = nullptr, *G = nullptr, *coef = nullptr;
+  int* flag = nullptr;
   int part_blocks = 0;
   double* hres = nullptr;  // pinned
 
@@ -155,7 +156,9 @@ void apply_K(ibr_ctx* c, const TI* x, double* y) {
     launch_lambda_sums(d, c->N, c->lamd, c->lsum_part, c->addc, 1.0 / c->vol, s);
     addc = c->addc;
   }
+  timer_begin(kTimerStokes, s);
   launch_stokes_apply<TI, double>(d, c->logn, xv, xp, y, y + (int64_t)d * c->C, c->c0, c->ch2, c->inv_h, addc, s);
+  timer_end(kTimerStokes, s, (double)(d + 1) * c->C * (sizeof(TI) + sizeof(double)));
   launch_spread<double, double>(d, c->logn, c->tile_log, c->nactive, c->active, c->toff, c->perm, c->taps, c->lamd,
                                 y, -std::pow(c->h, -d), s);
   launch_interp<TI>(d, c->logn, c->N, c->taps, xv, -1.0, nullptr, 0.0, y + c->NF, s);
@@ -212,12 +215,8 @@ void inner_gmres(ibr_ctx* c, const T* rhs, T* out) {
     launch_stokes_apply<T, T>(d, c->logn, Zj, Zj + (int64_t)d * c->C, w, w + (int64_t)d * c->C, c->c0, c->ch2,
                               c->inv_h, nullptr, s);
     double* hcol = c->Hi + (int64_t)j * ldh;
-    launch_multi_dot<T, T>(Q, NF, j + 1, w, NF, c->part, c->part_blocks, hcol, false, s);
-    launch_multi_axpy<T, T>(Q, NF, j + 1, hcol, w, NF, nullptr, c->part_blocks, s);
-    launch_multi_dot<T, T>(Q, NF, j + 1, w, NF, c->part, c->part_blocks, c->hc2i, false, s);
-    launch_multi_axpy<T, T>(Q, NF, j + 1, c->hc2i, w, NF, c->part, c->part_blocks, s);
-    launch_axpby(c->hc2i, hcol, j + 1, 1.0, 1.0, s);
-    launch_norm_finish(c->part, c->part_blocks, hcol + j + 1, s);
+    // one Gram-Schmidt pass: the inner solve is only a preconditioner (FGMRES is flexible)
+    arnoldi_step<T>(Q, NF, j, hcol, c->hc2i, c->part, c->part2, c->part_blocks, c->flag, s, false, false);
     launch_scale_copy<T, T>(w, w, NF, hcol + j + 1, s);
     launch_givens_step(c->Hi, ldh, j, c->csi, c->sni, c->gi, c->residi, s);
   }
@@ -307,15 +306,8 @@ ibr_status fgmres(ibr_ctx* c, ibr_info* info) {
         TZ* zk = Z + (int64_t)k * NV;
         precondition<TZ>(c, vk, zk);
         apply_K<TZ>(c, zk, w);
-        double* hcol = c->H + (int64_t)k * ldh;
-        launch_multi_dot<double, double>(V, NV, k + 1, w, NV, c->part, c->part_blocks, hcol, false, s);
-        launch_multi_axpy<double, double>(V, NV, k + 1, hcol, w, NV, nullptr, c->part_blocks, s);
-        launch_multi_dot<double, double>(V, NV, k + 1, w, NV, c->part, c->part_blocks, c->hc2, false, s);
-        launch_multi_axpy<double, double>(V, NV, k + 1, c->hc2, w, NV, c->part, c->part_blocks, s);
-        launch_axpby(c->hc2, hcol, k + 1, 1.0, 1.0, s);
-        launch_norm_finish(c->part, c->part_blocks, hcol + k + 1, s);
-        launch_scale_copy<double, double>(w, w, NV, hcol + k + 1, s);
-        launch_givens_step(c->H, ldh, k, c->cs, c->sn, c->g, c->resid, s);
+        dcgs2_step<double>(V, NV, k, c->H, ldh, c->G, c->coef, c->part, c->part_blocks, c->cs, c->sn, c->g,
+                           c->resid, s, true);
         IBR_HIP(hipMemcpyAsync(c->hres, c->resid, sizeof(double), hipMemcpyDeviceToHost, s));
         sync(c);
         ++total;
@@ -328,6 +320,8 @@ ibr_status fgmres(ibr_ctx* c, ibr_info* info) {
         }
         if (est <= target || total >= c->p.max_iters) break;
       }
+      // the last column is still provisional: rotate it as it stands
+      launch_givens_step(c->H, ldh, kused - 1, c->cs, c->sn, c->g, c->resid, s);
       launch_lsq_solve(c->H, ldh, kused, c->g, c->y, s);
       launch_combine<TZ, double>(Z, NV, kused, c->y, c->Xs, NV, s);
       if (stop) break;
@@ -533,7 +527,11 @@ void ibr_ctx::alloc_grid() {
   beta = track<double>(1);
   hc2 = track<double>(m + 2);
   part_blocks = 1024;
-  part = track<double>((int64_t)(m + 2) * part_blocks);
+  part = track<double>((int64_t)(2 * m + 8) * part_blocks);
+  part2 = track<double>((int64_t)(m + 3) * part_blocks);
+  G = track<double>(2 * m + 8);
+  coef = track<double>(2 * m + 8);
+  flag = track<int>(4);
   Hi = track<double>((int64_t)(ns + 1) * ns);
   csi = track<double>(ns + 1);
   sni = track<double>(ns + 1);

@@ -1,0 +1,96 @@
+// Live per-kernel timing with HIP events on the launching stream.
+//
+// A few kernel classes (the finest-level red-black sweep, the outer Arnoldi
+// passes, the outer Stokes stencil) can bracket every launch with a pair of
+// events and accumulate the algorithmic bytes the launch must move.  Disabled
+// timers cost one branch per launch.
+#include <cstring>
+#include <vector>
+
+#include "ibr.h"
+#include "kernels.h"
+
+namespace ibr {
+
+namespace {
+
+struct TimerState {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  double bytes = 0.0;
+  long launches = 0;
+};
+
+TimerState g_timers[kTimerCount];
+
+const char* const kTimerNames[kTimerCount] = {"rb_fine", "ortho_dot", "ortho_axpy", "stokes_apply"};
+
+int timer_index(const char* name) {
+  if (!name) return -1;
+  for (int i = 0; i < kTimerCount; ++i)
+    if (std::strcmp(name, kTimerNames[i]) == 0) return i;
+  return -1;
+}
+
+hipEvent_t next_event(TimerState& t) {
+  if (t.used == t.pool.size()) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDefault) != hipSuccess) return nullptr;
+    t.pool.push_back(e);
+  }
+  return t.pool[t.used++];
+}
+
+}  // namespace
+
+bool timer_on(int id) { return id >= 0 && id < kTimerCount && g_timers[id].on; }
+
+void timer_begin(int id, hipStream_t s) {
+  if (!timer_on(id)) return;
+  hipEvent_t e = next_event(g_timers[id]);
+  if (e) (void)hipEventRecord(e, s);
+}
+
+void timer_end(int id, hipStream_t s, double bytes) {
+  if (!timer_on(id)) return;
+  TimerState& t = g_timers[id];
+  hipEvent_t e = next_event(t);
+  if (e) (void)hipEventRecord(e, s);
+  t.bytes += bytes;
+  t.launches += 1;
+}
+
+}  // namespace ibr
+
+extern "C" {
+
+int ibr_timer_enable(const char* kernel, int on) {
+  const int i = ibr::timer_index(kernel);
+  if (i < 0) return IBR_EINVAL;
+  ibr::TimerState& t = ibr::g_timers[i];
+  t.on = on != 0;
+  t.used = 0;
+  t.bytes = 0.0;
+  t.launches = 0;
+  return IBR_OK;
+}
+
+int ibr_timer_read(const char* kernel, double* ms, long* launches, double* bytes) {
+  const int i = ibr::timer_index(kernel);
+  if (i < 0) return IBR_EINVAL;
+  ibr::TimerState& t = ibr::g_timers[i];
+  double tot = 0.0;
+  for (size_t k = 0; k + 1 < t.used; k += 2) {
+    if (hipEventSynchronize(t.pool[k + 1]) != hipSuccess) return IBR_EDEVICE;
+    float e = 0.0f;
+    if (hipEventElapsedTime(&e, t.pool[k], t.pool[k + 1]) != hipSuccess) return IBR_EDEVICE;
+    tot += e;
+  }
+  if (ms) *ms = tot;
+  if (launches) *launches = t.launches;
+  if (bytes) *bytes = t.bytes;
+  return IBR_OK;
+}
+
+}  // extern "C"

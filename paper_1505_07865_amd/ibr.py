@@ -50,7 +50,8 @@ class Info(ctypes.Structure):
 EXPORTS = ["ibr_default_params", "ibr_status_string", "ibr_create", "ibr_destroy", "ibr_last_error",
            "ibr_footprint_bytes", "ibr_set_bodies", "ibr_set_velocities", "ibr_set_rhs", "ibr_solve",
            "ibr_step", "ibr_get_solution", "ibr_get_markers", "ibr_apply_operator", "ibr_spread",
-           "ibr_interp", "ibr_vcycle", "ibr_precondition", "ibr_mobility_block", "ibr_advect"]
+           "ibr_interp", "ibr_vcycle", "ibr_precondition", "ibr_mobility_block", "ibr_advect",
+           "ibr_timer_enable", "ibr_timer_read"]
 
 
 def load(path=LIB_PATH):
@@ -83,6 +84,8 @@ def load(path=LIB_PATH):
         "ibr_precondition": (ctypes.c_int, [vp, dp, dp]),
         "ibr_mobility_block": (ctypes.c_int, [vp, ctypes.c_int, dp, dp]),
         "ibr_advect": (ctypes.c_int, [vp, dp, dp]),
+        "ibr_timer_enable": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_int]),
+        "ibr_timer_read": (ctypes.c_int, [ctypes.c_char_p, dp, P(ctypes.c_long), dp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -274,6 +277,25 @@ class Solver:
         N = np.zeros_like(u)
         self._check(self._lib.ibr_advect(self._ctx, _dptr(u), _dptr(N)), "ibr_advect")
         return N
+
+
+TIMERS = ("rb_fine", "ortho_dot", "ortho_axpy", "stokes_apply")
+
+
+def timer_enable(kernel, on=True):
+    st = lib().ibr_timer_enable(kernel.encode(), 1 if on else 0)
+    if st != 0:
+        raise IbrError(st, "unknown timer %r" % kernel)
+
+
+def timer_read(kernel):
+    ms = ctypes.c_double()
+    n = ctypes.c_long()
+    b = ctypes.c_double()
+    st = lib().ibr_timer_read(kernel.encode(), ctypes.byref(ms), ctypes.byref(n), ctypes.byref(b))
+    if st != 0:
+        raise IbrError(st, "ibr_timer_read(%r)" % kernel)
+    return {"ms": ms.value, "launches": n.value, "bytes": b.value}
 
 
 def from_problem(prob, **kw):
