@@ -167,21 +167,26 @@ ibr_status ibr_precondition(ibr_ctx* ctx, const double* r, double* z);
  * M[(dim Np)^2] row-major, and the shift s used to factor it. */
 ibr_status ibr_mobility_block(ibr_ctx* ctx, int body, double* M, double* shift);
 
+/* Inverse of the (possibly shifted) block as used by the preconditioner,
+ * Minv[(dim Np)^2] row-major (Sec. 5.3 dense mobility solve). */
+ibr_status ibr_mobility_inverse(ibr_ctx* ctx, int body, double* Minv);
+
 /* Advection term N(u) of the unsteady step on the MAC grid: N[dim][n^dim]. */
 ibr_status ibr_advect(ibr_ctx* ctx, const double* u, double* N);
 
 /* ---- live kernel timing (measurement support) ---- */
 
-/* Bracket every launch of one kernel class with HIP events on its stream and
- * accumulate the launch's algorithmic bytes.  Classes: "rb_fine" (red-black
- * half sweep on the finest multigrid level), "ortho_dot" and "ortho_axpy"
- * (the outer Arnoldi Gram-Schmidt passes), "stokes_apply" (the MAC stencil of
- * the outer operator).  Process-wide; enabling resets the class's counters.
- * Returns IBR_EINVAL for an unknown class. */
-int ibr_timer_enable(const char* kernel, int on);
+/* Bracket every stride-th launch of one kernel class with HIP events on its
+ * stream and accumulate that launch's algorithmic bytes (stride 0 = off).
+ * Classes: "rb_fine" (red-black half sweep on the finest multigrid level),
+ * "ortho_dot" and "ortho_axpy" (the reduction and update passes of the outer
+ * Arnoldi step), "stokes_apply" (the MAC stencil of the outer operator).
+ * Process-wide; enabling resets the class's counters.  IBR_EINVAL for an
+ * unknown class or a negative stride. */
+int ibr_timer_enable(const char* kernel, int stride);
 
 /* Total event time in ms, number of timed launches and summed algorithmic
- * bytes of a class since it was enabled (waits for the recorded events). */
+ * bytes of the timed launches since enabling (waits for the recorded events). */
 int ibr_timer_read(const char* kernel, double* ms, long* launches, double* bytes);
 
 #ifdef __cplusplus

@@ -62,7 +62,8 @@ __device__ inline void colour_cell(int64_t t, int logn, int color, int& i, int& 
 // ---------------------------------------------------------------- fine-level kernels
 // One red-black half sweep.  from_zero: x is treated as 0 on entry (first red
 // pass of pre-smoothing): red cells get b/diag and black cells 0.
-template <typename T, int DIM>
+// FINE marks the finest level (same code; a separate symbol for profiling).
+template <typename T, int DIM, bool FINE>
 __global__ void __launch_bounds__(256) k_rb(T* __restrict__ x, const T* __restrict__ b, int logn, T c0, T c1,
                                             int color, int from_zero) {
   const int64_t C = (int64_t)1 << (DIM * logn);
@@ -409,10 +410,17 @@ void MGHier<T>::rb_half(T* x, const T* b, int lg, int nf, T c0, T c1, int color,
   const int64_t Cl = (int64_t)1 << (dim * lg);
   const dim3 gh(nblk(Cl / 2), nf);
   if (fine) timer_begin(kTimerRbFine, s);
-  if (dim == 3)
-    hipLaunchKernelGGL((k_rb<T, 3>), gh, dim3(256), 0, s, x, b, lg, c0, c1, color, from_zero ? 1 : 0);
-  else
-    hipLaunchKernelGGL((k_rb<T, 2>), gh, dim3(256), 0, s, x, b, lg, c0, c1, color, from_zero ? 1 : 0);
+  if (dim == 3) {
+    if (fine)
+      hipLaunchKernelGGL((k_rb<T, 3, true>), gh, dim3(256), 0, s, x, b, lg, c0, c1, color, from_zero ? 1 : 0);
+    else
+      hipLaunchKernelGGL((k_rb<T, 3, false>), gh, dim3(256), 0, s, x, b, lg, c0, c1, color, from_zero ? 1 : 0);
+  } else {
+    if (fine)
+      hipLaunchKernelGGL((k_rb<T, 2, true>), gh, dim3(256), 0, s, x, b, lg, c0, c1, color, from_zero ? 1 : 0);
+    else
+      hipLaunchKernelGGL((k_rb<T, 2, false>), gh, dim3(256), 0, s, x, b, lg, c0, c1, color, from_zero ? 1 : 0);
+  }
   // algorithmic traffic of a half sweep: b and x of one colour, x of the other
   if (fine) timer_end(kTimerRbFine, s, 1.5 * (double)Cl * nf * sizeof(T));
 }

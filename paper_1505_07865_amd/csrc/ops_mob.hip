@@ -84,20 +84,33 @@ __global__ void k_mob_assemble(int dim, const int* __restrict__ off, const int64
   const double r = sqrt(r2);
   double f, g;
   mob_fg(r, p, f, g);
-  const int n = dim * np;
+  const int ld = (dim * np + 15) & ~15;
   double* blk = M + moff[b];
   for (int a = 0; a < dim; ++a)
     for (int c = 0; c < dim; ++c) {
       const double ra = r > 0 ? dr[a] / r : 0.0, rc = r > 0 ? dr[c] / r : 0.0;
-      blk[(int64_t)(dim * i + a) * n + (dim * j + c)] = (a == c ? f : 0.0) + g * ra * rc;
+      blk[(int64_t)(dim * i + a) * ld + (dim * j + c)] = (a == c ? f : 0.0) + g * ra * rc;
     }
 }
 
-// Right-looking Cholesky of M_p + shift_p f0 I into Lf (lower triangle,
-// row-major), one workgroup per body.  Bodies with active[p] == 0 are skipped.
-// fail[p] = 1 when a pivot is not above pivot_tol * f0.
-constexpr int kCholThreads = 512;
+// ---------------------------------------------------------------- fp64 MFMA block factorisation
+// Blocks are stored row-major with a leading dimension ld = n rounded up to a
+// multiple of 16 (the padding is an identity block, so the padded matrix
+// factors with the same leading n x n factor).
+//
+// v_mfma_f64_16x16x4f64 operand layout (lane l of a wave64):
+//   A (16x4):  lane l holds A[l % 16][l / 16]
+//   B (4x16):  lane l holds B[l / 16][l % 16]
+//   C/D:       lane l, register r holds D[4 r + l / 16][l % 16]
+typedef double dvec4 __attribute__((ext_vector_type(4)));
 
+__device__ inline int pad16(int n) { return (n + 15) & ~15; }
+
+constexpr int kCholThreads = 256;
+
+// Blocked right-looking Cholesky of M_p + shift_p f0 I, one workgroup per body:
+// 16-column panels factored with scalar code, trailing updates
+// C -= P_I P_J^T as 16x16 fp64 MFMA tiles spread over the waves.
 __global__ void __launch_bounds__(kCholThreads) k_chol(const int* __restrict__ off, int dim,
                                                        const int64_t* __restrict__ moff, const double* __restrict__ M,
                                                        double* __restrict__ Lf, const int* __restrict__ active,
@@ -106,14 +119,20 @@ __global__ void __launch_bounds__(kCholThreads) k_chol(const int* __restrict__ o
   const int b = blockIdx.x;
   if (!active[b]) return;
   const int n = dim * (off[b + 1] - off[b]);
+  const int ld = pad16(n);
+  const int nt = ld / 16;
   const double* A = M + moff[b];
   double* L = Lf + moff[b];
   const double sh = shift[b] * f0;
-  for (int64_t q = threadIdx.x; q < (int64_t)n * n; q += blockDim.x) {
-    const int i = (int)(q / n), j = (int)(q - (int64_t)i * n);
-    L[q] = j <= i ? A[q] + (i == j ? sh : 0.0) : 0.0;
+  for (int64_t q = threadIdx.x; q < (int64_t)ld * ld; q += blockDim.x) {
+    const int i = (int)(q / ld), j = (int)(q - (int64_t)i * ld);
+    double v = 0.0;
+    if (j <= i) {
+      if (i < n) v = A[q] + (i == j ? sh : 0.0);
+      else if (i == j) v = 1.0;
+    }
+    L[q] = v;
   }
-  __shared__ double col[1024 * 3];  // column j below the diagonal (n <= 3072)
   __shared__ double s_piv;
   __shared__ int s_fail;
   if (threadIdx.x == 0) s_fail = 0;
@@ -121,26 +140,59 @@ __global__ void __launch_bounds__(kCholThreads) k_chol(const int* __restrict__ o
   const int lane = threadIdx.x & (kWave - 1);
   const int wv = threadIdx.x / kWave;
   const int nw = blockDim.x / kWave;
-  for (int j = 0; j < n; ++j) {
-    if (threadIdx.x == 0) {
-      const double d = L[(int64_t)j * n + j];
-      if (!(d > pivot_tol * f0)) s_fail = 1;
-      s_piv = sqrt(d > 0 ? d : 1.0);
-      L[(int64_t)j * n + j] = s_piv;
+  for (int p = 0; p < nt; ++p) {
+    const int c0 = 16 * p;
+    // panel: columns c0..c0+15, rows c0..ld-1, unblocked right-looking
+    for (int jj = 0; jj < 16; ++jj) {
+      const int col = c0 + jj;
+      if (threadIdx.x == 0) {
+        const double d = L[(int64_t)col * ld + col];
+        if (!(d > pivot_tol * f0)) s_fail = 1;
+        s_piv = sqrt(d > 0 ? d : 1.0);
+        L[(int64_t)col * ld + col] = s_piv;
+      }
+      __syncthreads();
+      if (s_fail) break;
+      const double inv = 1.0 / s_piv;
+      for (int i = col + 1 + threadIdx.x; i < ld; i += blockDim.x) L[(int64_t)i * ld + col] *= inv;
+      __syncthreads();
+      const int ncol = 15 - jj;  // remaining panel columns
+      if (ncol > 0) {
+        const int nrow = ld - col - 1;
+        for (int q = threadIdx.x; q < nrow * ncol; q += blockDim.x) {
+          const int i = col + 1 + q / ncol;
+          const int c = col + 1 + q % ncol;
+          if (c <= i) L[(int64_t)i * ld + c] -= L[(int64_t)i * ld + col] * L[(int64_t)c * ld + col];
+        }
+      }
+      __syncthreads();
     }
-    __syncthreads();
     if (s_fail) break;
-    const double inv = 1.0 / s_piv;
-    for (int i = j + 1 + threadIdx.x; i < n; i += blockDim.x) {
-      const double v = L[(int64_t)i * n + j] * inv;
-      L[(int64_t)i * n + j] = v;
-      col[i] = v;
-    }
-    __syncthreads();
-    for (int i = j + 1 + wv; i < n; i += nw) {
-      const double lij = col[i];
-      double* row = L + (int64_t)i * n;
-      for (int k = j + 1 + lane; k <= i; k += kWave) row[k] -= lij * col[k];
+    // trailing update of the lower tiles (I, J), p < J <= I < nt
+    const int T = nt - p - 1;
+    const int ntiles = T * (T + 1) / 2;
+    for (int t = wv; t < ntiles; t += nw) {
+      // unrank t -> (I, J) in row-major lower-triangular order
+      int I = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+      while ((I + 1) * (I + 2) / 2 <= t) ++I;
+      while (I * (I + 1) / 2 > t) --I;
+      const int J = t - I * (I + 1) / 2;
+      const int r0 = 16 * (p + 1 + I), q0 = 16 * (p + 1 + J);
+      dvec4 acc;
+      const int ci = lane & 15, rq = lane >> 4;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[r] = L[(int64_t)(r0 + 4 * r + rq) * ld + q0 + ci];
+#pragma unroll
+      for (int k0 = 0; k0 < 16; k0 += 4) {
+        const double a = -L[(int64_t)(r0 + ci) * ld + c0 + k0 + rq];
+        const double bb = L[(int64_t)(q0 + ci) * ld + c0 + k0 + rq];
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = r0 + 4 * r + rq, cc = q0 + ci;
+        if (I != J || cc <= row) L[(int64_t)row * ld + cc] = acc[r];
+      }
     }
     __syncthreads();
   }
@@ -153,42 +205,45 @@ __global__ void __launch_bounds__(256) k_tri_inv(const int* __restrict__ off, in
                                                  double* __restrict__ X) {
   const int b = blockIdx.x;
   const int n = dim * (off[b + 1] - off[b]);
+  const int ld = pad16(n);
   const double* L = Lf + moff[b];
   double* Xb = X + moff[b];
-  for (int j = threadIdx.x; j < n; j += blockDim.x) {
-    for (int i = 0; i < j; ++i) Xb[(int64_t)i * n + j] = 0.0;
-    for (int i = j; i < n; ++i) {
+  for (int j = threadIdx.x; j < ld; j += blockDim.x) {
+    for (int i = 0; i < j; ++i) Xb[(int64_t)i * ld + j] = 0.0;
+    for (int i = j; i < ld; ++i) {
       double s = i == j ? 1.0 : 0.0;
-      for (int k = j; k < i; ++k) s -= L[(int64_t)i * n + k] * Xb[(int64_t)k * n + j];
-      Xb[(int64_t)i * n + j] = s / L[(int64_t)i * n + i];
+      for (int k = j; k < i; ++k) s -= L[(int64_t)i * ld + k] * Xb[(int64_t)k * ld + j];
+      Xb[(int64_t)i * ld + j] = s / L[(int64_t)i * ld + i];
     }
   }
 }
 
-// Minv = X^T X  (X lower triangular), 16x16 output tiles, LDS-staged.
-__global__ void __launch_bounds__(256) k_xtx(const int* __restrict__ off, int dim, const int64_t* __restrict__ moff,
-                                             const double* __restrict__ X, double* __restrict__ Minv) {
+// Minv = X^T X for X = L^-1 lower triangular: one wave per 16x16 tile (I >= J),
+// fp64 MFMA over 4-row slabs of X, mirrored into the upper triangle.
+__global__ void __launch_bounds__(64) k_xtx(const int* __restrict__ off, int dim, const int64_t* __restrict__ moff,
+                                            const double* __restrict__ X, double* __restrict__ Minv) {
   const int b = blockIdx.z;
   const int n = dim * (off[b + 1] - off[b]);
-  const int i0 = blockIdx.y * 16, j0 = blockIdx.x * 16;
-  if (i0 >= n || j0 >= n) return;
+  const int ld = pad16(n);
+  const int I = blockIdx.y, J = blockIdx.x;
+  if (16 * I >= ld || J > I) return;
   const double* Xb = X + moff[b];
-  __shared__ double ti[16][17], tj[16][17];
-  const int ty = threadIdx.x / 16, tx = threadIdx.x % 16;
-  const int i = i0 + ty, j = j0 + tx;
-  double acc = 0;
-  const int kstart = (i0 > j0 ? i0 : j0);
-  for (int k0 = kstart - (kstart % 16); k0 < n; k0 += 16) {
-    // rows k0..k0+15 of X, columns i0.. and j0..
-    const int kr = k0 + ty;
-    ti[ty][tx] = (kr < n && i0 + tx < n) ? Xb[(int64_t)kr * n + i0 + tx] : 0.0;
-    tj[ty][tx] = (kr < n && j0 + tx < n) ? Xb[(int64_t)kr * n + j0 + tx] : 0.0;
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 16; ++q) acc += ti[q][ty] * tj[q][tx];
-    __syncthreads();
+  const int lane = threadIdx.x;
+  const int ci = lane & 15, rq = lane >> 4;
+  const int i0 = 16 * I, j0 = 16 * J;
+  dvec4 acc = {0.0, 0.0, 0.0, 0.0};
+  for (int k0 = i0; k0 < ld; k0 += 4) {
+    const double a = Xb[(int64_t)(k0 + rq) * ld + i0 + ci];
+    const double bb = Xb[(int64_t)(k0 + rq) * ld + j0 + ci];
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc, 0, 0, 0);
   }
-  if (i < n && j < n) Minv[moff[b] + (int64_t)i * n + j] = acc;
+  double* Mb = Minv + moff[b];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int row = i0 + 4 * r + rq, col = j0 + ci;
+    Mb[(int64_t)row * ld + col] = acc[r];
+    Mb[(int64_t)col * ld + row] = acc[r];
+  }
 }
 
 // lam_p = Minv_p dU_p: one wavefront per row.
@@ -198,10 +253,11 @@ __global__ void __launch_bounds__(256) k_mob_apply(const int* __restrict__ off, 
   const int b = blockIdx.y;
   const int lo = off[b];
   const int n = dim * (off[b + 1] - lo);
+  const int ld = pad16(n);
   const int row = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
   const int lane = threadIdx.x & (kWave - 1);
   if (row >= n) return;
-  const double* Mr = Minv + moff[b] + (int64_t)row * n;
+  const double* Mr = Minv + moff[b] + (int64_t)row * ld;
   const double* u = dU + (int64_t)lo * dim;
   double acc = 0;
   for (int k = lane; k < n; k += kWave) acc += Mr[k] * u[k];
@@ -228,7 +284,7 @@ void launch_chol_inverse(int nb, const int* offsets, int dim, const int64_t* mof
                          double* X, int max_n, hipStream_t s) {
   hipLaunchKernelGGL(k_tri_inv, dim3(nb), dim3(256), 0, s, offsets, dim, moff, Lf, X);
   const unsigned t = (unsigned)((max_n + 15) / 16);
-  hipLaunchKernelGGL(k_xtx, dim3(t, t, nb), dim3(256), 0, s, offsets, dim, moff, X, Minv);
+  hipLaunchKernelGGL(k_xtx, dim3(t, t, nb), dim3(64), 0, s, offsets, dim, moff, X, Minv);
 }
 
 void launch_mob_apply(int nb, const int* offsets, int dim, const int64_t* moff, const double* Minv,

@@ -437,7 +437,7 @@ void factor_blocks(ibr_ctx* c) {
     }
     if (!any) break;
   }
-  launch_chol_inverse(nb, c->off_d, c->dim, c->moff_d, c->Lb, c->Minv, c->Xb, c->max_rows, s);
+  launch_chol_inverse(nb, c->off_d, c->dim, c->moff_d, c->Lb, c->Minv, c->Xb, (c->max_rows + 15) & ~15, s);
   sync(c);
 }
 
@@ -786,8 +786,8 @@ ibr_status ibr_set_bodies(ibr_ctx* c, int nbodies, const int* offsets, const dou
     c->max_np = maxnp;
     c->max_rows = maxnp * d;
     for (int b = 0; b < nbodies; ++b) {
-      const int64_t nr = (int64_t)d * (offsets[b + 1] - offsets[b]);
-      c->moff_h[b + 1] = c->moff_h[b] + nr * nr;
+      const int64_t ld = ((int64_t)d * (offsets[b + 1] - offsets[b]) + 15) & ~(int64_t)15;
+      c->moff_h[b + 1] = c->moff_h[b] + ld * ld;
     }
     const int64_t mtot = c->moff_h[nbodies];
     c->moff_d = dev_alloc<int64_t>(nbodies + 1);
@@ -804,6 +804,7 @@ ibr_status ibr_set_bodies(ibr_ctx* c, int nbodies, const int* offsets, const dou
     IBR_HIP(hipMemcpyAsync(c->X, centres, (size_t)nbodies * d * sizeof(double), hipMemcpyHostToDevice, s));
     IBR_HIP(hipMemcpyAsync(c->body_d, body.data(), N * sizeof(int), hipMemcpyHostToDevice, s));
     IBR_HIP(hipMemcpyAsync(c->moff_d, c->moff_h.data(), (nbodies + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    launch_fill<double>(c->Mb, mtot, 0.0, s);
     launch_fill<double>(c->U, (int64_t)nbodies * d, 0.0, s);
     launch_fill<double>(c->Om, (int64_t)nbodies * 3, 0.0, s);
     // positions are wrapped into the box by the marker set-up kernel's taps; keep R itself wrapped too
@@ -1051,11 +1052,26 @@ ibr_status ibr_mobility_block(ibr_ctx* c, int body, double* M, double* shift) {
     require_bodies(c);
     if (body < 0 || body >= c->nb) throw Status(IBR_EINVAL, "body out of range");
     IBR_HIP(hipSetDevice(c->p.device));
-    const int64_t cnt = c->moff_h[body + 1] - c->moff_h[body];
+    const int64_t n = (int64_t)c->dim * (c->off_h[body + 1] - c->off_h[body]);
+    const int64_t ld = (n + 15) & ~(int64_t)15;
     if (M)
-      IBR_HIP(hipMemcpyAsync(M, c->Mb + c->moff_h[body], (size_t)cnt * sizeof(double), hipMemcpyDeviceToHost,
-                             c->stream));
+      IBR_HIP(hipMemcpy2DAsync(M, n * sizeof(double), c->Mb + c->moff_h[body], ld * sizeof(double),
+                               n * sizeof(double), n, hipMemcpyDeviceToHost, c->stream));
     if (shift) *shift = c->shift_h[body];
+    sync(c);
+  });
+}
+
+ibr_status ibr_mobility_inverse(ibr_ctx* c, int body, double* Minv) {
+  if (!c) return IBR_EINVAL;
+  return guard(c, [&] {
+    require_bodies(c);
+    if (body < 0 || body >= c->nb || !Minv) throw Status(IBR_EINVAL, "body out of range or Minv NULL");
+    IBR_HIP(hipSetDevice(c->p.device));
+    const int64_t n = (int64_t)c->dim * (c->off_h[body + 1] - c->off_h[body]);
+    const int64_t ld = (n + 15) & ~(int64_t)15;
+    IBR_HIP(hipMemcpy2DAsync(Minv, n * sizeof(double), c->Minv + c->moff_h[body], ld * sizeof(double),
+                             n * sizeof(double), n, hipMemcpyDeviceToHost, c->stream));
     sync(c);
   });
 }

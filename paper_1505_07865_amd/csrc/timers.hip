@@ -15,11 +15,13 @@ namespace ibr {
 namespace {
 
 struct TimerState {
-  bool on = false;
+  int stride = 0;        // 0 = off; otherwise every stride-th launch is timed
+  long seen = 0;         // launches of the class since enabling
+  bool pending = false;  // the current launch is being timed
   std::vector<hipEvent_t> pool;
   size_t used = 0;
   double bytes = 0.0;
-  long launches = 0;
+  long launches = 0;     // timed launches
 };
 
 TimerState g_timers[kTimerCount];
@@ -44,17 +46,22 @@ hipEvent_t next_event(TimerState& t) {
 
 }  // namespace
 
-bool timer_on(int id) { return id >= 0 && id < kTimerCount && g_timers[id].on; }
+bool timer_on(int id) { return id >= 0 && id < kTimerCount && g_timers[id].stride > 0; }
 
 void timer_begin(int id, hipStream_t s) {
   if (!timer_on(id)) return;
-  hipEvent_t e = next_event(g_timers[id]);
+  TimerState& t = g_timers[id];
+  t.pending = (t.seen++ % t.stride) == 0;
+  if (!t.pending) return;
+  hipEvent_t e = next_event(t);
   if (e) (void)hipEventRecord(e, s);
 }
 
 void timer_end(int id, hipStream_t s, double bytes) {
   if (!timer_on(id)) return;
   TimerState& t = g_timers[id];
+  if (!t.pending) return;
+  t.pending = false;
   hipEvent_t e = next_event(t);
   if (e) (void)hipEventRecord(e, s);
   t.bytes += bytes;
@@ -65,11 +72,13 @@ void timer_end(int id, hipStream_t s, double bytes) {
 
 extern "C" {
 
-int ibr_timer_enable(const char* kernel, int on) {
+int ibr_timer_enable(const char* kernel, int stride) {
   const int i = ibr::timer_index(kernel);
-  if (i < 0) return IBR_EINVAL;
+  if (i < 0 || stride < 0) return IBR_EINVAL;
   ibr::TimerState& t = ibr::g_timers[i];
-  t.on = on != 0;
+  t.stride = stride;
+  t.seen = 0;
+  t.pending = false;
   t.used = 0;
   t.bytes = 0.0;
   t.launches = 0;

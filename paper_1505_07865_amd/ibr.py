@@ -51,7 +51,7 @@ EXPORTS = ["ibr_default_params", "ibr_status_string", "ibr_create", "ibr_destroy
            "ibr_footprint_bytes", "ibr_set_bodies", "ibr_set_velocities", "ibr_set_rhs", "ibr_solve",
            "ibr_step", "ibr_get_solution", "ibr_get_markers", "ibr_apply_operator", "ibr_spread",
            "ibr_interp", "ibr_vcycle", "ibr_precondition", "ibr_mobility_block", "ibr_advect",
-           "ibr_timer_enable", "ibr_timer_read"]
+           "ibr_timer_enable", "ibr_timer_read", "ibr_mobility_inverse"]
 
 
 def load(path=LIB_PATH):
@@ -84,6 +84,7 @@ def load(path=LIB_PATH):
         "ibr_precondition": (ctypes.c_int, [vp, dp, dp]),
         "ibr_mobility_block": (ctypes.c_int, [vp, ctypes.c_int, dp, dp]),
         "ibr_advect": (ctypes.c_int, [vp, dp, dp]),
+        "ibr_mobility_inverse": (ctypes.c_int, [vp, ctypes.c_int, dp]),
         "ibr_timer_enable": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_int]),
         "ibr_timer_read": (ctypes.c_int, [ctypes.c_char_p, dp, P(ctypes.c_long), dp]),
     }
@@ -272,6 +273,13 @@ class Solver:
         self._check(self._lib.ibr_mobility_block(self._ctx, body, _dptr(M), ctypes.byref(sh)), "ibr_mobility_block")
         return M, sh.value
 
+    def mobility_inverse(self, body):
+        off = self._offsets
+        nrows = self.dim * (off[body + 1] - off[body])
+        Mi = np.zeros((nrows, nrows))
+        self._check(self._lib.ibr_mobility_inverse(self._ctx, body, _dptr(Mi)), "ibr_mobility_inverse")
+        return Mi
+
     def advect(self, u):
         u = _f64(u)
         N = np.zeros_like(u)
@@ -282,8 +290,9 @@ class Solver:
 TIMERS = ("rb_fine", "ortho_dot", "ortho_axpy", "stokes_apply")
 
 
-def timer_enable(kernel, on=True):
-    st = lib().ibr_timer_enable(kernel.encode(), 1 if on else 0)
+def timer_enable(kernel, stride=1):
+    """Time every stride-th launch of a kernel class (0 switches the timer off)."""
+    st = lib().ibr_timer_enable(kernel.encode(), int(stride))
     if st != 0:
         raise IbrError(st, "unknown timer %r" % kernel)
 
