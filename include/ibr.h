@@ -74,6 +74,8 @@ typedef struct {
   int mg_coarse;      /* red-black sweeps on the 4^dim coarsest grid (default 16) */
   int device;         /* HIP device ordinal */
   void* stream;       /* hipStream_t to run on, or NULL for a library stream */
+  int graphs;         /* 1 (default): replay each outer iteration as a captured
+                         HIP graph; 0: plain stream launches (same kernels) */
 } ibr_params;
 
 /* Per-solve report.  ps_applications counts P_S^-1 applications, the cost
@@ -181,8 +183,10 @@ ibr_status ibr_advect(ibr_ctx* ctx, const double* u, double* N);
  * Classes: "rb_fine" (red-black half sweep on the finest multigrid level),
  * "ortho_dot" and "ortho_axpy" (the reduction and update passes of the outer
  * Arnoldi step), "stokes_apply" (the MAC stencil of the outer operator).
- * Process-wide; enabling resets the class's counters.  IBR_EINVAL for an
- * unknown class or a negative stride. */
+ * Process-wide; enabling resets the class's counters.  While any class is
+ * enabled the solver launches its kernels directly on the stream instead of
+ * replaying captured iteration graphs, so every launch can be bracketed.
+ * IBR_EINVAL for an unknown class or a negative stride. */
 int ibr_timer_enable(const char* kernel, int stride);
 
 /* Total event time in ms, number of timed launches and summed algorithmic

@@ -38,6 +38,7 @@ enum TimerId { kTimerRbFine = 0, kTimerOrthoDot = 1, kTimerOrthoAxpy = 2, kTimer
 bool timer_on(int id);
 void timer_begin(int id, hipStream_t s);
 void timer_end(int id, hipStream_t s, double bytes);
+bool timers_any();  // some timer is enabled
 
 // ---------------------------------------------------------------- grid stencils
 template <typename TI, typename TO>
@@ -98,10 +99,13 @@ void launch_bin_markers(int N, int ntiles, const int* tile_of, int* counts, int*
 void launch_active_tiles(int dim, int tiles_log, const int* offsets, int* flags, int* active_list,
                          int* active_count, hipStream_t s);
 
-// y_face[a] += sign * h^-dim * sum_i lam[i][a] * w  over the active tiles
+// y_face[a] += scale * sum_i lam[i][a] * w  over the active tiles.  The grid
+// holds grid_cap workgroups per component; the number of active tiles is read
+// on the device from *nactive (<= grid_cap), so the launch needs no host sync.
 template <typename TL, typename TY>
-void launch_spread(int dim, int logn, int tile_log, int nactive, const int* active_list, const int* offsets,
-                   const int* perm, MarkerTaps taps, const TL* lam, TY* y, double scale, hipStream_t s);
+void launch_spread(int dim, int logn, int tile_log, int grid_cap, const int* active_list, const int* nactive,
+                   const int* offsets, const int* perm, MarkerTaps taps, const TL* lam, TY* y, double scale,
+                   hipStream_t s);
 // out[i][a] = alpha * (J v)[i][a] + beta * add[i][a]   (add may be null)
 template <typename TV>
 void launch_interp(int dim, int logn, int N, MarkerTaps taps, const TV* v, double alpha, const double* add,

@@ -2,9 +2,9 @@
 // binning, rigid-body kinematics and body force / torque sums (Sec. 2).
 //
 // Spreading is a deterministic, atomic-free GATHER: markers are binned by the
-// 8^3 (2D: 16^2) tile that holds their cell; each workgroup owns one active
-// tile, pulls the markers of the neighbouring tiles into LDS in a fixed order
-// and sums their weights into its own faces.  Interpolation gives one
+// 8^3 (2D: 16^2) tile that holds their cell; one workgroup owns one active
+// tile and component, walks the markers of the neighbouring tiles in a fixed
+// order and accumulates their taps into its own faces.  Interpolation gives one
 // wavefront to each marker: 64 lanes = the 4^3 taps, reduced with shuffles.
 #include "kernels.h"
 
@@ -188,20 +188,31 @@ __global__ void k_active_tiles(int dim, int tiles_log, const int* __restrict__ o
 }
 
 // ---------------------------------------------------------------- spreading (gather)
-constexpr int kSpreadChunk = 128;
-
-// One workgroup per (active tile, component a); one thread per cell of the
-// tile (8^3 in 3D, 16^2 in 2D).  The markers of the neighbouring tiles are
-// staged in LDS chunk by chunk, always in the same order, and every thread
-// sums the contributions to its own a-face: no atomics, bitwise reproducible.
+// One workgroup of four wavefronts per (active tile, component a).  The
+// candidate markers (those binned in the neighbouring tiles, tiles in a fixed
+// order, markers sorted inside each tile) are taken 256 at a time: each thread
+// tests one candidate against the tile and the hits are compacted, in order,
+// into LDS with their first taps and weights (lam folded into the x weights).
+// Wavefront w then takes hits w, w+4, ...; for one marker its 64 lanes are the
+// 4^3 taps (distinct faces) and add into that wavefront's own accumulator.  The
+// four accumulators are summed in a fixed order at the end: no atomics, and
+// the result is bitwise reproducible.  2D uses 16 lanes per marker.
 template <typename TL, typename TY, int DIM>
-__global__ void __launch_bounds__(512) k_spread(int logn, int tile_log, const int* __restrict__ active,
-                                                const int* __restrict__ off, const int* __restrict__ perm,
-                                                const int* __restrict__ tbase, const double* __restrict__ tw,
-                                                const TL* __restrict__ lam, TY* __restrict__ y, double scale) {
-  __shared__ int s_base[kSpreadChunk][DIM];
-  __shared__ double s_w[kSpreadChunk][DIM][4];
-  __shared__ double s_l[kSpreadChunk];
+__global__ void __launch_bounds__(256) k_spread(int logn, int tile_log, const int* __restrict__ active,
+                                                const int* __restrict__ nactive, const int* __restrict__ off,
+                                                const int* __restrict__ perm, const int* __restrict__ tbase,
+                                                const double* __restrict__ tw, const TL* __restrict__ lam,
+                                                TY* __restrict__ y, double scale) {
+  if ((int)blockIdx.x >= nactive[0]) return;  // grid sized to a capacity, count read on the device
+  constexpr int kCells = DIM == 3 ? 512 : 256;  // 8^3 or 16^2
+  constexpr int kWaves = 4;
+  constexpr int kChunk = 256;
+  __shared__ double acc[kWaves][kCells];
+  __shared__ double sw[kChunk][DIM][4];
+  __shared__ int sd[kChunk][DIM];
+  __shared__ int rlo[27], rpre[28];
+  __shared__ int wcnt[kWaves];
+
   const int n = 1 << logn;
   const int mask = n - 1;
   const int64_t C = (int64_t)1 << (DIM * logn);
@@ -211,58 +222,93 @@ __global__ void __launch_bounds__(512) k_spread(int logn, int tile_log, const in
   const int a = blockIdx.y;
   const int tsz = 1 << tile_log;
   const int tc[3] = {tile & (nt - 1), (tile >> tiles_log) & (nt - 1), DIM == 3 ? (tile >> (2 * tiles_log)) : 0};
-  const int lc = threadIdx.x;
-  const bool live = lc < (1 << (DIM * tile_log));
-  int fc[3];
-  fc[0] = tc[0] * tsz + (lc & (tsz - 1));
-  fc[1] = tc[1] * tsz + ((lc >> tile_log) & (tsz - 1));
-  fc[2] = DIM == 3 ? tc[2] * tsz + ((lc >> (2 * tile_log)) & (tsz - 1)) : 0;
+  const int lo[3] = {tc[0] * tsz, tc[1] * tsz, tc[2] * tsz};
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int cells = 1 << (DIM * tile_log);
+  for (int q = tid; q < kWaves * kCells; q += 256) (&acc[0][0])[q] = 0.0;
+  if (tid == 0) {
+    int cx[3], cy[3], cz[3];
+    const int nx = nbr_coords(tc[0], nt, cx);
+    const int ny = nbr_coords(tc[1], nt, cy);
+    int nz = 1;
+    cz[0] = 0;
+    if (DIM == 3) nz = nbr_coords(tc[2], nt, cz);
+    int r = 0, tot = 0;
+    for (int a3 = 0; a3 < nz; ++a3)
+      for (int b3 = 0; b3 < ny; ++b3)
+        for (int c3 = 0; c3 < nx; ++c3) {
+          const int tt = cx[c3] | (cy[b3] << tiles_log) | (cz[a3] << (2 * tiles_log));
+          rlo[r] = off[tt];
+          rpre[r] = tot;
+          tot += off[tt + 1] - off[tt];
+          ++r;
+        }
+    for (; r < 28; ++r) rpre[r] = tot;
+  }
+  __syncthreads();
+  const int total = rpre[27];
+  // lane -> tap offsets (x fastest)
+  const int tx = lane & 3, ty = (lane >> 2) & 3, tz = lane >> 4;
+  const bool live = DIM == 3 || lane < 16;
 
-  int cx[3], cy[3], cz[3];
-  const int nx = nbr_coords(tc[0], nt, cx);
-  const int ny = nbr_coords(tc[1], nt, cy);
-  int nz = 1;
-  cz[0] = 0;
-  if (DIM == 3) nz = nbr_coords(tc[2], nt, cz);
-
-  double acc = 0.0;
-  for (int a3 = 0; a3 < nz; ++a3)
-    for (int b3 = 0; b3 < ny; ++b3)
-      for (int c3 = 0; c3 < nx; ++c3) {
-        const int tt = cx[c3] | (cy[b3] << tiles_log) | (cz[a3] << (2 * tiles_log));
-        const int lo = off[tt], hi = off[tt + 1];
-        for (int c0 = lo; c0 < hi; c0 += kSpreadChunk) {
-          const int cnt = min(kSpreadChunk, hi - c0);
-          __syncthreads();
-          for (int q = threadIdx.x; q < cnt * DIM; q += blockDim.x) {
-            const int mm = q / DIM, d = q - mm * DIM;
-            const int m = perm[c0 + mm];
-            const int r = (d == a ? 3 : 0) + d;  // face staggering on axis a, cell-centred elsewhere
-            s_base[mm][d] = tbase[m * 6 + r];
-#pragma unroll
-            for (int t = 0; t < 4; ++t) s_w[mm][d][t] = tw[(m * 6 + r) * 4 + t];
-            if (d == 0) s_l[mm] = (double)lam[m * DIM + a];
-          }
-          __syncthreads();
-          if (live) {
-            for (int q = 0; q < cnt; ++q) {
-              const int t0 = (fc[0] - s_base[q][0]) & mask;
-              const int t1 = (fc[1] - s_base[q][1]) & mask;
-              int t2 = 0;
-              if (DIM == 3) t2 = (fc[2] - s_base[q][DIM - 1]) & mask;
-              if (t0 < 4 && t1 < 4 && t2 < 4) {
-                double w = s_l[q] * s_w[q][0][t0] * s_w[q][1][t1];
-                if (DIM == 3) w *= s_w[q][DIM - 1][t2];
-                acc += w;
-              }
-            }
-          }
+  for (int c0 = 0; c0 < total; c0 += kChunk) {
+    const int q = c0 + tid;
+    bool hit = false;
+    int m = 0, d[3] = {0, 0, 0};
+    if (q < total) {
+      int r = 0;
+      while (q >= rpre[r + 1]) ++r;
+      m = perm[rlo[r] + (q - rpre[r])];
+      hit = true;
+      for (int beta = 0; beta < DIM; ++beta) {
+        const int s = beta == a ? 1 : 0;
+        d[beta] = (tbase[(m * 2 + s) * 3 + beta] - lo[beta]) & mask;
+        // the 4 taps along beta meet the tile when the first one is within [-3, tsz)
+        hit = hit && (d[beta] < tsz || d[beta] >= n - 3);
+      }
+    }
+    const unsigned long long bal = __ballot(hit);
+    const int rank = __popcll(bal & ((1ull << lane) - 1ull));
+    if (lane == 0) wcnt[wave] = __popcll(bal);
+    __syncthreads();
+    int base = 0, nhit = 0;
+    for (int w = 0; w < kWaves; ++w) {
+      base += w < wave ? wcnt[w] : 0;
+      nhit += wcnt[w];
+    }
+    if (hit) {
+      const int slot = base + rank;
+      const double lm = (double)lam[m * DIM + a];
+      for (int beta = 0; beta < DIM; ++beta) {
+        const int s = beta == a ? 1 : 0;
+        const double* wp = tw + ((m * 2 + s) * 3 + beta) * 4;
+        sd[slot][beta] = d[beta];
+        for (int t = 0; t < 4; ++t) sw[slot][beta][t] = beta == 0 ? lm * wp[t] : wp[t];
+      }
+    }
+    __syncthreads();
+    if (live) {
+      for (int j = wave; j < nhit; j += kWaves) {
+        const int f0 = (sd[j][0] + tx) & mask;
+        const int f1 = (sd[j][1] + ty) & mask;
+        int f2 = 0;
+        if constexpr (DIM == 3) f2 = (sd[j][2] + tz) & mask;
+        if (f0 < tsz && f1 < tsz && f2 < tsz) {
+          double w = sw[j][0][tx] * sw[j][1][ty];
+          if constexpr (DIM == 3) w *= sw[j][2][tz];
+          acc[wave][f0 + (f1 << tile_log) + (f2 << (2 * tile_log))] += w;
         }
       }
-  if (live) {
-    const int64_t c = (int64_t)fc[0] + ((int64_t)fc[1] << logn) + ((int64_t)fc[2] << (2 * logn));
+    }
+    __syncthreads();
+  }
+  for (int q = tid; q < cells; q += 256) {
+    const double v = ((acc[0][q] + acc[1][q]) + acc[2][q]) + acc[3][q];
+    const int l0 = q & (tsz - 1), l1 = (q >> tile_log) & (tsz - 1), l2 = DIM == 3 ? (q >> (2 * tile_log)) : 0;
+    const int64_t c = (int64_t)(lo[0] + l0) + ((int64_t)(lo[1] + l1) << logn) + ((int64_t)(lo[2] + l2) << (2 * logn));
     const int64_t idx = (int64_t)a * C + c;
-    y[idx] = (TY)((double)y[idx] + scale * acc);
+    y[idx] = (TY)((double)y[idx] + scale * v);
   }
 }
 
@@ -405,23 +451,23 @@ void launch_active_tiles(int dim, int tiles_log, const int* offsets, int* flags,
 }
 
 template <typename TL, typename TY>
-void launch_spread(int dim, int logn, int tile_log, int nactive, const int* active_list, const int* offsets,
-                   const int* perm, MarkerTaps taps, const TL* lam, TY* y, double scale, hipStream_t s) {
-  if (nactive <= 0) return;
-  const int threads = 1 << (dim * tile_log);
+void launch_spread(int dim, int logn, int tile_log, int grid_cap, const int* active_list, const int* nactive,
+                   const int* offsets, const int* perm, MarkerTaps taps, const TL* lam, TY* y, double scale,
+                   hipStream_t s) {
+  if (grid_cap <= 0) return;
   if (dim == 3)
-    hipLaunchKernelGGL((k_spread<TL, TY, 3>), dim3(nactive, 3), dim3(threads), 0, s, logn, tile_log, active_list,
-                       offsets, perm, taps.base, taps.w64, lam, y, scale);
+    hipLaunchKernelGGL((k_spread<TL, TY, 3>), dim3(grid_cap, 3), dim3(256), 0, s, logn, tile_log, active_list,
+                       nactive, offsets, perm, taps.base, taps.w64, lam, y, scale);
   else
-    hipLaunchKernelGGL((k_spread<TL, TY, 2>), dim3(nactive, 2), dim3(threads), 0, s, logn, tile_log, active_list,
-                       offsets, perm, taps.base, taps.w64, lam, y, scale);
+    hipLaunchKernelGGL((k_spread<TL, TY, 2>), dim3(grid_cap, 2), dim3(256), 0, s, logn, tile_log, active_list,
+                       nactive, offsets, perm, taps.base, taps.w64, lam, y, scale);
 }
-template void launch_spread<double, double>(int, int, int, int, const int*, const int*, const int*, MarkerTaps,
-                                            const double*, double*, double, hipStream_t);
-template void launch_spread<float, double>(int, int, int, int, const int*, const int*, const int*, MarkerTaps,
-                                           const float*, double*, double, hipStream_t);
-template void launch_spread<double, float>(int, int, int, int, const int*, const int*, const int*, MarkerTaps,
-                                           const double*, float*, double, hipStream_t);
+template void launch_spread<double, double>(int, int, int, int, const int*, const int*, const int*, const int*,
+                                            MarkerTaps, const double*, double*, double, hipStream_t);
+template void launch_spread<float, double>(int, int, int, int, const int*, const int*, const int*, const int*,
+                                           MarkerTaps, const float*, double*, double, hipStream_t);
+template void launch_spread<double, float>(int, int, int, int, const int*, const int*, const int*, const int*,
+                                           MarkerTaps, const double*, float*, double, hipStream_t);
 
 template <typename TV>
 void launch_interp(int dim, int logn, int N, MarkerTaps taps, const TV* v, double alpha, const double* add,

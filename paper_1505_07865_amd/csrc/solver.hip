@@ -70,6 +70,7 @@ struct ibr_ctx {
   int *tile_of = nullptr, *counts = nullptr, *toff = nullptr, *cursor = nullptr, *perm = nullptr, *flags = nullptr,
       *active = nullptr, *nactive_d = nullptr;
   int tile_log = 3, tiles_log = 0, ntiles = 0, nactive = 0;
+  int act_cap = 0;  // spread grid capacity (>= nactive), baked into captured graphs
 
   // mobility blocks
   std::vector<int64_t> moff_h;
@@ -110,6 +111,16 @@ struct ibr_ctx {
 
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   int64_t bytes = 0;
+
+  // one captured graph per outer iteration index k (preconditioner, operator, Arnoldi)
+  struct IterGraph {
+    hipGraphExec_t exec = nullptr;
+    int version = -1, ps = 0, vc = 0;
+  };
+  std::vector<IterGraph> graphs;
+  int graph_version = 0;
+  bool use_graphs = true;
+  void drop_graphs();
 
   // counters of the current solve
   int cnt_ps = 0, cnt_vc = 0;
@@ -159,8 +170,8 @@ void apply_K(ibr_ctx* c, const TI* x, double* y) {
   timer_begin(kTimerStokes, s);
   launch_stokes_apply<TI, double>(d, c->logn, xv, xp, y, y + (int64_t)d * c->C, c->c0, c->ch2, c->inv_h, addc, s);
   timer_end(kTimerStokes, s, (double)(d + 1) * c->C * (sizeof(TI) + sizeof(double)));
-  launch_spread<double, double>(d, c->logn, c->tile_log, c->nactive, c->active, c->toff, c->perm, c->taps, c->lamd,
-                                y, -std::pow(c->h, -d), s);
+  launch_spread<double, double>(d, c->logn, c->tile_log, c->act_cap, c->active, c->nactive_d, c->toff, c->perm,
+                                c->taps, c->lamd, y, -std::pow(c->h, -d), s);
   launch_interp<TI>(d, c->logn, c->N, c->taps, xv, -1.0, nullptr, 0.0, y + c->NF, s);
 }
 
@@ -239,8 +250,8 @@ void precondition(ibr_ctx* c, const double* r, T* z) {
   launch_mob_apply(c->nb, c->off_d, d, c->moff_d, c->Minv, c->dU, c->lamd, c->max_rows, s);
   if (c->p.pc == IBR_PC_FULL) {
     // second fluid solve with r_v + S' Lambda
-    launch_spread<double, T>(d, c->logn, c->tile_log, c->nactive, c->active, c->toff, c->perm, c->taps, c->lamd,
-                             rhs, std::pow(c->h, -d), s);
+    launch_spread<double, T>(d, c->logn, c->tile_log, c->act_cap, c->active, c->nactive_d, c->toff, c->perm,
+                             c->taps, c->lamd, rhs, std::pow(c->h, -d), s);
     if (c->steady) {
       launch_lambda_sums(d, c->N, c->lamd, c->lsum_part, c->addc, 1.0 / c->vol, s);
       launch_sub_field_mean<T>(rhs, d, c->C, c->addc, s);
@@ -251,6 +262,67 @@ void precondition(ibr_ctx* c, const double* r, T* z) {
 }
 
 // ---------------------------------------------------------------- FGMRES
+// One outer iteration k: z_k = P v_k, w = K z_k, delayed-CGS2 Arnoldi step.
+template <typename TZ>
+void iteration_body(ibr_ctx* c, int k) {
+  const int64_t NV = c->NV;
+  double* V = c->Vb;
+  TZ* Z = (TZ*)c->Zb;
+  double* vk = V + (int64_t)k * NV;
+  double* w = V + (int64_t)(k + 1) * NV;
+  TZ* zk = Z + (int64_t)k * NV;
+  precondition<TZ>(c, vk, zk);
+  apply_K<TZ>(c, zk, w);
+  dcgs2_step<double>(V, NV, k, c->H, c->m + 1, c->G, c->coef, c->part, c->part_blocks, c->cs, c->sn, c->g,
+                     c->resid, c->stream, true);
+}
+
+// The graph of iteration k, captured on first use (and again when buffers or
+// the spread capacity changed).  All its kernels use fixed device addresses,
+// so one capture serves every restart cycle and every later solve of the
+// context.  Returns null if capture is unavailable.  Live kernel timers bracket
+// single launches on the stream, so while one is enabled no graph is used.
+template <typename TZ>
+ibr_ctx::IterGraph* iter_graph(ibr_ctx* c, int k) {
+  if ((int)c->graphs.size() < c->m) c->graphs.resize(c->m);
+  ibr_ctx::IterGraph& G = c->graphs[k];
+  if (G.exec && G.version == c->graph_version) return &G;
+  if (G.exec) {
+    (void)hipGraphExecDestroy(G.exec);
+    G.exec = nullptr;
+  }
+  hipStream_t s = c->stream;
+  const int ps0 = c->cnt_ps, vc0 = c->cnt_vc;
+  hipGraph_t graph = nullptr;
+  if (hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed) != hipSuccess) {
+    c->use_graphs = false;
+    return nullptr;
+  }
+  try {
+    iteration_body<TZ>(c, k);
+  } catch (...) {
+    (void)hipStreamEndCapture(s, &graph);
+    if (graph) (void)hipGraphDestroy(graph);
+    c->cnt_ps = ps0;
+    c->cnt_vc = vc0;
+    throw;
+  }
+  const hipError_t e1 = hipStreamEndCapture(s, &graph);
+  G.ps = c->cnt_ps - ps0;
+  G.vc = c->cnt_vc - vc0;
+  c->cnt_ps = ps0;
+  c->cnt_vc = vc0;
+  if (e1 != hipSuccess || !graph || hipGraphInstantiate(&G.exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    G.exec = nullptr;
+    c->use_graphs = false;  // stay on plain stream launches
+    return nullptr;
+  }
+  (void)hipGraphDestroy(graph);
+  G.version = c->graph_version;
+  return &G;
+}
+
 template <typename TZ>
 ibr_status fgmres(ibr_ctx* c, ibr_info* info) {
   hipStream_t s = c->stream;
@@ -301,13 +373,14 @@ ibr_status fgmres(ibr_ctx* c, ibr_info* info) {
       int kused = 0;
       bool stop = false;
       for (int k = 0; k < m; ++k) {
-        double* vk = V + (int64_t)k * NV;
-        double* w = V + (int64_t)(k + 1) * NV;
-        TZ* zk = Z + (int64_t)k * NV;
-        precondition<TZ>(c, vk, zk);
-        apply_K<TZ>(c, zk, w);
-        dcgs2_step<double>(V, NV, k, c->H, ldh, c->G, c->coef, c->part, c->part_blocks, c->cs, c->sn, c->g,
-                           c->resid, s, true);
+        ibr_ctx::IterGraph* G = c->use_graphs && !timers_any() ? iter_graph<TZ>(c, k) : nullptr;
+        if (G) {
+          IBR_HIP(hipGraphLaunch(G->exec, s));
+          c->cnt_ps += G->ps;
+          c->cnt_vc += G->vc;
+        } else {
+          iteration_body<TZ>(c, k);
+        }
         IBR_HIP(hipMemcpyAsync(c->hres, c->resid, sizeof(double), hipMemcpyDeviceToHost, s));
         sync(c);
         ++total;
@@ -408,6 +481,11 @@ void setup_markers(ibr_ctx* c) {
   sync(c);
   std::memcpy(&na, c->hres, sizeof(int));
   c->nactive = na;
+  if (na > c->act_cap) {
+    // grow the spread grid capacity; graphs captured with the old size are stale
+    c->act_cap = std::min(c->ntiles, na + na / 4 + 8);
+    ++c->graph_version;
+  }
 }
 
 void factor_blocks(ibr_ctx* c) {
@@ -476,7 +554,16 @@ void require_bodies(const ibr_ctx* c) {
 }  // namespace
 
 // ---------------------------------------------------------------- ctx members
+void ibr_ctx::drop_graphs() {
+  for (IterGraph& G : graphs) {
+    if (G.exec) (void)hipGraphExecDestroy(G.exec);
+    G.exec = nullptr;
+  }
+  graphs.clear();
+}
+
 ibr_ctx::~ibr_ctx() {
+  drop_graphs();
   free_markers();
   for (void* q : {(void*)Xs, (void*)Bs, (void*)T1, (void*)T2, (void*)Nprev, (void*)Ncur, (void*)H, (void*)cs,
                   (void*)sn, (void*)g, (void*)y, (void*)resid, (void*)beta, (void*)hc2, (void*)part, (void*)Qi,
@@ -635,6 +722,7 @@ void ibr_default_params(ibr_params* p) {
   p->mg_coarse = 16;
   p->device = 0;
   p->stream = nullptr;
+  p->graphs = 1;
 }
 
 const char* ibr_status_string(int st) {
@@ -672,6 +760,7 @@ ibr_status ibr_create(const ibr_params* params, ibr_ctx** out) {
     c->ch2 = params->eta / (c->h * c->h);
     c->inv_h = 1.0 / c->h;
     c->mixed = params->precision == IBR_MIXED;
+    c->use_graphs = params->graphs != 0;
     if (params->stream) {
       c->stream = (hipStream_t)params->stream;
     } else {
@@ -763,6 +852,9 @@ ibr_status ibr_set_bodies(ibr_ctx* c, int nbodies, const int* offsets, const dou
     drop(c->act_d);
     drop(c->fail_d);
     c->N = 0;
+    c->drop_graphs();
+    ++c->graph_version;
+    c->act_cap = 0;
     const bool grow = N > c->Ncap || !c->Vb;
     c->alloc_markers(N);
     c->nb = nbodies;
@@ -968,8 +1060,8 @@ ibr_status ibr_spread(ibr_ctx* c, const double* lambda, double* f) {
     hipStream_t s = c->stream;
     IBR_HIP(hipMemcpyAsync(c->lamd, lambda, (size_t)c->N * d * sizeof(double), hipMemcpyHostToDevice, s));
     launch_fill<double>(c->T2, (int64_t)d * c->C, 0.0, s);
-    launch_spread<double, double>(d, c->logn, c->tile_log, c->nactive, c->active, c->toff, c->perm, c->taps, c->lamd,
-                                  c->T2, std::pow(c->h, -d), s);
+    launch_spread<double, double>(d, c->logn, c->tile_log, c->act_cap, c->active, c->nactive_d, c->toff, c->perm,
+                                  c->taps, c->lamd, c->T2, std::pow(c->h, -d), s);
     IBR_HIP(hipMemcpyAsync(f, c->T2, (size_t)d * c->C * sizeof(double), hipMemcpyDeviceToHost, s));
     sync(c);
   });

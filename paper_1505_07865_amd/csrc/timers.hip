@@ -68,6 +68,12 @@ void timer_end(int id, hipStream_t s, double bytes) {
   t.launches += 1;
 }
 
+bool timers_any() {
+  for (int i = 0; i < kTimerCount; ++i)
+    if (g_timers[i].stride > 0) return true;
+  return false;
+}
+
 }  // namespace ibr
 
 extern "C" {

@@ -35,7 +35,7 @@ class Params(ctypes.Structure):
                 ("precision", ctypes.c_int), ("pc", ctypes.c_int), ("n_s", ctypes.c_int),
                 ("restart", ctypes.c_int), ("max_iters", ctypes.c_int), ("rtol", ctypes.c_double),
                 ("mg_pre", ctypes.c_int), ("mg_post", ctypes.c_int), ("mg_coarse", ctypes.c_int),
-                ("device", ctypes.c_int), ("stream", ctypes.c_void_p)]
+                ("device", ctypes.c_int), ("stream", ctypes.c_void_p), ("graphs", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):

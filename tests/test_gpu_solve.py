@@ -154,3 +154,23 @@ def test_edge_cases():
     assert e.value.status == 1
     s.close()
     s2.close()
+
+
+def test_graph_replay_matches_stream_launches():
+    """Captured iteration graphs replayed across restarts and steps give the
+    bitwise result of plain stream launches (the same kernels in the same order)."""
+    from paper_1505_07865_amd import ibr
+    prob = small_problem(23, 3, 32, nbodies=2, radius_h=3.0, rho=1.0, dt=0.5 / 32, eta=0.02, nsteps=3,
+                         rotate=False)
+    out = []
+    for graphs in (1, 0):
+        s = ibr.from_problem(prob, rtol=1e-10, restart=6, graphs=graphs)
+        sols = []
+        for _ in range(3):
+            info = s.step()
+            sols.append(s.solution())
+            assert info["restarts"] >= 2      # graphs are replayed across restart cycles
+        out.append(sols)
+        s.close()
+    for a, b in zip(*out):
+        assert np.array_equal(a.u, b.u) and np.array_equal(a.lam, b.lam) and np.array_equal(a.p, b.p)
