@@ -54,7 +54,6 @@ void launch_ns_rhs(const double* v, const double* N1, const double* N0, double* 
                    double rho, double w1, double w0, hipStream_t s);
 
 // ---------------------------------------------------------------- multigrid
-int mg_lds_cells();
 template <typename T>
 void launch_fill(T* x, int64_t len, T v, hipStream_t s);
 template <typename T>
@@ -67,13 +66,16 @@ struct MGHier {
   int dim = 3, logn = 0, nfmax = 0, lds_logn = 0;
   std::vector<int> levels;          // log2 n of the multi-kernel levels (finest first)
   std::vector<T*> bufs_x, bufs_b;   // per level >= 1, nfmax fields each
+  T* tail_b = nullptr;              // global right-hand side of the tail's second level
   void init(int dim, int logn, int nfmax);
   void release();
   static size_t bytes(int dim, int logn, int nf);
   // One V-cycle for nf fields: x = V(b).  x and b hold nf fields of n^dim.
   void vcycle(int nf, const T* b, T* x, double c0, double c1, int nu_pre, int nu_post, int nu_coarse,
               hipStream_t s);
-  void rb_half(T* x, const T* b, int lg, int nf, T c0, T c1, int color, bool from_zero, bool fine, hipStream_t s);
+  void rb_half(T* x, const T* b, int lg, int nf, T c0, T c1, int color, bool fine, hipStream_t s);
+  // first sweep (red then black) from a zero guess, in one pass
+  void rb_first(T* x, const T* b, int lg, int nf, T c0, T c1, bool fine, hipStream_t s);
 };
 
 // ---------------------------------------------------------------- markers / IB
@@ -138,9 +140,16 @@ void arnoldi_step(const T* V, int64_t ld, int k, double* hcol, double* h2, doubl
 template <typename T>
 void dcgs2_step(T* V, int64_t ld, int k, double* H, int ldh, double* G, double* coef, double* part, int nblocks,
                 double* cs, double* sn, double* g, double* resid, hipStream_t s, bool timed);
-// x += sum_j y[j] Z_j  (Z in TZ, x in TX)
+// x += sum_j y[j] Z_j  (Z in TZ, x in TX); with assign, x = sum_j y[j] Z_j
 template <typename TZ, typename TX>
-void launch_combine(const TZ* Z, int64_t ld, int k, const double* y, TX* x, int64_t len, hipStream_t s);
+void launch_combine(const TZ* Z, int64_t ld, int k, const double* y, TX* x, int64_t len, hipStream_t s,
+                    bool assign = false);
+// y[0..ns) = argmin || r - sum_j y_j W_j ||  (W_j = W + j*ld, ns in 1..3) from the
+// normal equations: one reduction pass over W and r, one single-block solve.
+// part needs (ns(ns+1)/2 + ns) * nblocks doubles.
+template <typename T>
+void launch_gram_solve(const T* W, int64_t ld, int ns, const T* r, int64_t len, double* part, int nblocks,
+                       double* y, hipStream_t s);
 void launch_norm_finish(const double* part, int nblocks, double* out, hipStream_t s);
 template <typename T>
 void launch_sumsq_partial(const T* w, int64_t len, double* part, int nblocks, hipStream_t s);

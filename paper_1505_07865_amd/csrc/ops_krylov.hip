@@ -79,12 +79,107 @@ __global__ void __launch_bounds__(256) k_multi_axpy(const TV* __restrict__ V, in
 
 template <typename TZ, typename TX>
 __global__ void __launch_bounds__(256) k_combine(const TZ* __restrict__ Z, int64_t ld, int k,
-                                                 const double* __restrict__ y, TX* __restrict__ x, int64_t len) {
+                                                 const double* __restrict__ y, TX* __restrict__ x, int64_t len,
+                                                 int assign) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += stride) {
-    double acc = (double)x[i];
+    double acc = assign ? 0.0 : (double)x[i];
     for (int j = 0; j < k; ++j) acc += y[j] * (double)Z[(int64_t)j * ld + i];
     x[i] = (TX)acc;
+  }
+}
+
+// Normal equations of min_y || r - W y || for a few columns W_0..W_{NS-1}
+// (stride ld): per-block partial sums, in fp64, of the upper triangle of W^T W
+// (row-major) followed by W^T r.  part[q * gridDim.x + block].
+template <typename T, int NS>
+__global__ void __launch_bounds__(256) k_gram_partial(const T* __restrict__ W, int64_t ld, const T* __restrict__ r,
+                                                      int64_t len, double* __restrict__ part) {
+  constexpr int NQ = NS * (NS + 1) / 2 + NS;
+  __shared__ double red[NQ][256 / kWave];
+  double acc[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += stride) {
+    double w[NS];
+#pragma unroll
+    for (int a = 0; a < NS; ++a) w[a] = (double)W[(int64_t)a * ld + i];
+    const double ri = (double)r[i];
+    int q = 0;
+#pragma unroll
+    for (int a = 0; a < NS; ++a)
+#pragma unroll
+      for (int b = a; b < NS; ++b) acc[q++] += w[a] * w[b];
+#pragma unroll
+    for (int a = 0; a < NS; ++a) acc[q++] += w[a] * ri;
+  }
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const double v = wave_sum(acc[q]);
+    if (lane == 0) red[q][wv] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < NQ) {
+    double v = 0;
+    for (int u = 0; u < (int)(blockDim.x / kWave); ++u) v += red[threadIdx.x][u];
+    part[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = v;
+  }
+}
+
+// Sums the partials (fixed order) and solves (W^T W) y = W^T r by Cholesky.
+// A column that is numerically in the span of the earlier ones (squared
+// pivot <= drop * its squared norm) is dropped and gets y = 0, so a zero or
+// rank-deficient W still yields a finite minimiser.
+template <int NS>
+__global__ void __launch_bounds__(256) k_gram_solve(const double* __restrict__ part, int nblocks,
+                                                    double* __restrict__ y, double drop) {
+  constexpr int NQ = NS * (NS + 1) / 2 + NS;
+  __shared__ double tot[NQ];
+  __shared__ double red[256 / kWave];
+  for (int q = 0; q < NQ; ++q) {
+    double v = 0;
+    for (int i = threadIdx.x; i < nblocks; i += blockDim.x) v += part[(int64_t)q * nblocks + i];
+    v = block_sum(v, red);
+    if (threadIdx.x == 0) tot[q] = v;
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  double G[NS][NS], L[NS][NS], rhs[NS], z[NS];
+  bool keep[NS];
+  int q = 0;
+  for (int a = 0; a < NS; ++a)
+    for (int b = a; b < NS; ++b) {
+      G[a][b] = tot[q];
+      G[b][a] = tot[q];
+      ++q;
+    }
+  for (int a = 0; a < NS; ++a) rhs[a] = tot[q++];
+  for (int k = 0; k < NS; ++k) {
+    double d = G[k][k];
+    for (int m = 0; m < k; ++m)
+      if (keep[m]) d -= L[k][m] * L[k][m];
+    keep[k] = G[k][k] > 0.0 && d > drop * G[k][k];
+    L[k][k] = keep[k] ? sqrt(d) : 1.0;
+    for (int i = k + 1; i < NS; ++i) {
+      double v = G[i][k];
+      for (int m = 0; m < k; ++m)
+        if (keep[m]) v -= L[i][m] * L[k][m];
+      L[i][k] = keep[k] ? v / L[k][k] : 0.0;
+    }
+  }
+  for (int k = 0; k < NS; ++k) {
+    double v = rhs[k];
+    for (int m = 0; m < k; ++m)
+      if (keep[m]) v -= L[k][m] * z[m];
+    z[k] = keep[k] ? v / L[k][k] : 0.0;
+  }
+  for (int k = NS - 1; k >= 0; --k) {
+    double v = z[k];
+    for (int m = k + 1; m < NS; ++m)
+      if (keep[m]) v -= L[m][k] * y[m];
+    y[k] = keep[k] ? v / L[k][k] : 0.0;
   }
 }
 
@@ -430,18 +525,44 @@ template void arnoldi_step<float>(const float*, int64_t, int, double*, double*, 
                                   hipStream_t, bool, bool);
 
 template <typename TZ, typename TX>
-void launch_combine(const TZ* Z, int64_t ld, int k, const double* y, TX* x, int64_t len, hipStream_t s) {
+void launch_combine(const TZ* Z, int64_t ld, int k, const double* y, TX* x, int64_t len, hipStream_t s,
+                    bool assign) {
   if (k <= 0) return;
   unsigned g = nblk(len);
   if (g > 4096) g = 4096;
-  hipLaunchKernelGGL((k_combine<TZ, TX>), dim3(g), dim3(256), 0, s, Z, ld, k, y, x, len);
+  hipLaunchKernelGGL((k_combine<TZ, TX>), dim3(g), dim3(256), 0, s, Z, ld, k, y, x, len, assign ? 1 : 0);
 }
 template void launch_combine<double, double>(const double*, int64_t, int, const double*, double*, int64_t,
-                                             hipStream_t);
+                                             hipStream_t, bool);
 template void launch_combine<float, double>(const float*, int64_t, int, const double*, double*, int64_t,
-                                            hipStream_t);
+                                            hipStream_t, bool);
 template void launch_combine<float, float>(const float*, int64_t, int, const double*, float*, int64_t,
-                                           hipStream_t);
+                                           hipStream_t, bool);
+
+template <typename T>
+void launch_gram_solve(const T* W, int64_t ld, int ns, const T* r, int64_t len, double* part, int nblocks,
+                       double* y, hipStream_t s) {
+  // a column whose squared distance from the span of the previous ones is
+  // below this fraction of its squared norm is dropped (rounding level of T)
+  const double drop = sizeof(T) == 4 ? 1e-5 : 1e-13;
+  switch (ns) {
+#define IBR_GRAM(NS)                                                                                      \
+  case NS:                                                                                                \
+    hipLaunchKernelGGL((k_gram_partial<T, NS>), dim3(nblocks), dim3(256), 0, s, W, ld, r, len, part);     \
+    hipLaunchKernelGGL((k_gram_solve<NS>), dim3(1), dim3(256), 0, s, part, nblocks, y, drop);              \
+    break;
+    IBR_GRAM(1)
+    IBR_GRAM(2)
+    IBR_GRAM(3)
+#undef IBR_GRAM
+    default:
+      throw DeviceError("launch_gram_solve: n_s must be 1, 2 or 3");
+  }
+}
+template void launch_gram_solve<double>(const double*, int64_t, int, const double*, int64_t, double*, int, double*,
+                                        hipStream_t);
+template void launch_gram_solve<float>(const float*, int64_t, int, const float*, int64_t, double*, int, double*,
+                                       hipStream_t);
 
 void launch_norm_finish(const double* part, int nblocks, double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_norm_finish, dim3(1), dim3(256), 0, s, part, nblocks, out);

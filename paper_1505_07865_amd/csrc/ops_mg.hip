@@ -9,32 +9,53 @@
 // mean of x is removed by the caller.
 //
 // Fine levels run one kernel per step with nfields batched in blockIdx.y.
-// Every level with at most 4096 cells runs inside ONE workgroup per field
-// (k_vcycle_lds), with the lattice held in LDS: the coarse tail of the cycle
-// costs one launch instead of ~10 per level.
+// The coarse tail of the cycle runs inside ONE workgroup per field
+// (k_vcycle_lds) with every array of the tail levels in LDS: one launch
+// instead of ~10 per level.  The tail starts at 4096 cells (16^3, 64^2): one
+// compute unit sweeping a 32^3 level costs more than the launches it saves.
 #include "kernels.h"
 
 namespace ibr {
 
 namespace {
 
-constexpr int kLdsCells = 4096;   // largest level handled inside one workgroup
-constexpr int kLdsThreads = 512;
+constexpr int kLdsThreads = 1024;
+
+// Largest level (cells) handled inside one workgroup, per precision and dimension.
+template <typename T, int DIM>
+constexpr int64_t lds_max_cells() {
+  return 4096;
+}
+// Cells of all levels from C down to the 4^dim grid.
+template <int DIM>
+constexpr int64_t pyramid_cells(int64_t C) {
+  int64_t t = 0;
+  for (int64_t c = C; c >= (DIM == 3 ? 64 : 16); c >>= DIM) t += c;
+  return t;
+}
+// The right-hand sides of tail levels with more cells than this stay in a
+// global scratch array (written and re-read by the same workgroup).
+template <typename T, int DIM>
+constexpr int64_t lds_b_max_cells() {
+  return lds_max_cells<T, DIM>() >> DIM;
+}
 
 // ---------------------------------------------------------------- helpers
+// Indices inside one field are 32-bit (n^dim <= 2^27 for the grids accepted);
+// field offsets are applied to the base pointers in 64-bit.
 template <int DIM>
-__device__ inline void cell_coords(int64_t c, int logn, int& i, int& j, int& k) {
+__device__ inline void cell_coords(int c, int logn, int& i, int& j, int& k) {
   const int mask = (1 << logn) - 1;
-  i = (int)(c & mask);
-  j = (int)((c >> logn) & mask);
-  k = DIM == 3 ? (int)(c >> (2 * logn)) : 0;
+  i = c & mask;
+  j = (c >> logn) & mask;
+  k = DIM == 3 ? (c >> (2 * logn)) : 0;
 }
 
 template <int DIM>
-__device__ inline int64_t cell_index(int i, int j, int k, int logn) {
+__device__ inline int cell_index(int i, int j, int k, int logn) {
   const int mask = (1 << logn) - 1;
-  int64_t c = (int64_t)(i & mask) + ((int64_t)(j & mask) << logn);
-  if (DIM == 3) c += (int64_t)(k & mask) << (2 * logn);
+  int c = (i & mask) | ((j & mask) << logn);
+  if (DIM == 3) c |= (k & mask) << (2 * logn);
   return c;
 }
 
@@ -49,38 +70,63 @@ __device__ inline T nbr_sum(const T* x, int i, int j, int k, int logn) {
 // Cell of colour `color` with colour-local index t (half the cells): row-major
 // pairs, the colour picks the parity inside each pair.
 template <int DIM>
-__device__ inline void colour_cell(int64_t t, int logn, int color, int& i, int& j, int& k) {
+__device__ inline void colour_cell(int t, int logn, int color, int& i, int& j, int& k) {
   const int half_log = logn - 1;
-  const int m = (int)(t & ((1 << half_log) - 1));
-  const int64_t row = t >> half_log;
+  const int m = t & ((1 << half_log) - 1);
+  const int row = t >> half_log;
   const int mask = (1 << logn) - 1;
-  j = (int)(row & mask);
-  k = DIM == 3 ? (int)(row >> logn) : 0;
+  j = row & mask;
+  k = DIM == 3 ? (row >> logn) : 0;
   i = 2 * m + ((j + k + color) & 1);
 }
 
+__device__ inline int flat_thread(unsigned nblocks) {
+  return (int)xcd_block(nblocks) * (int)blockDim.x + (int)threadIdx.x;
+}
+
 // ---------------------------------------------------------------- fine-level kernels
-// One red-black half sweep.  from_zero: x is treated as 0 on entry (first red
-// pass of pre-smoothing): red cells get b/diag and black cells 0.
-// FINE marks the finest level (same code; a separate symbol for profiling).
+// One red-black half sweep.  FINE marks the finest level (same code; a
+// separate symbol for profiling).
 template <typename T, int DIM, bool FINE>
 __global__ void __launch_bounds__(256) k_rb(T* __restrict__ x, const T* __restrict__ b, int logn, T c0, T c1,
-                                            int color, int from_zero) {
-  const int64_t C = (int64_t)1 << (DIM * logn);
-  const int64_t t = xcd_block(gridDim.x) * blockDim.x + threadIdx.x;
+                                            int color) {
+  const int C = 1 << (DIM * logn);
+  const int t = flat_thread(gridDim.x);
   if (t >= C / 2) return;
   const int64_t f = blockIdx.y;
   x += f * C;
   b += f * C;
   int i, j, k;
   colour_cell<DIM>(t, logn, color, i, j, k);
-  const int64_t c = cell_index<DIM>(i, j, k, logn);
+  const int c = cell_index<DIM>(i, j, k, logn);
   const T inv_diag = T(1) / (c0 + T(2 * DIM) * c1);
-  if (from_zero) {
+  x[c] = (b[c] + c1 * nbr_sum<T, DIM>(x, i, j, k, logn)) * inv_diag;
+}
+
+// The first red-black sweep from a zero guess in one pass: red cells take
+// b/diag, black cells (all of whose neighbours are red) take
+// (b + c1 * sum of the neighbours' b/diag)/diag.  Same arithmetic, in the same
+// order, as a red then a black half sweep from x = 0.
+template <typename T, int DIM, bool FINE>
+__global__ void __launch_bounds__(256) k_rb_first(T* __restrict__ x, const T* __restrict__ b, int logn, T c0,
+                                                  T c1) {
+  const int C = 1 << (DIM * logn);
+  const int c = flat_thread(gridDim.x);
+  if (c >= C) return;
+  const int64_t f = blockIdx.y;
+  x += f * C;
+  b += f * C;
+  int i, j, k;
+  cell_coords<DIM>(c, logn, i, j, k);
+  const T inv_diag = T(1) / (c0 + T(2 * DIM) * c1);
+  if (((i + j + k) & 1) == 0) {
     x[c] = b[c] * inv_diag;
-    x[cell_index<DIM>(i ^ 1, j, k, logn)] = T(0);
   } else {
-    x[c] = (b[c] + c1 * nbr_sum<T, DIM>(x, i, j, k, logn)) * inv_diag;
+    T s = b[cell_index<DIM>(i - 1, j, k, logn)] * inv_diag + b[cell_index<DIM>(i + 1, j, k, logn)] * inv_diag +
+          b[cell_index<DIM>(i, j - 1, k, logn)] * inv_diag + b[cell_index<DIM>(i, j + 1, k, logn)] * inv_diag;
+    if (DIM == 3)
+      s += b[cell_index<DIM>(i, j, k - 1, logn)] * inv_diag + b[cell_index<DIM>(i, j, k + 1, logn)] * inv_diag;
+    x[c] = (b[c] + c1 * s) * inv_diag;
   }
 }
 
@@ -89,9 +135,9 @@ template <typename T, int DIM>
 __global__ void __launch_bounds__(256) k_resid_restrict(const T* __restrict__ x, const T* __restrict__ b,
                                                         T* __restrict__ bc, int logn, T c0, T c1) {
   const int lognc = logn - 1;
-  const int64_t Cc = (int64_t)1 << (DIM * lognc);
-  const int64_t C = (int64_t)1 << (DIM * logn);
-  const int64_t t = xcd_block(gridDim.x) * blockDim.x + threadIdx.x;
+  const int Cc = 1 << (DIM * lognc);
+  const int C = 1 << (DIM * logn);
+  const int t = flat_thread(gridDim.x);
   if (t >= Cc) return;
   const int64_t f = blockIdx.y;
   x += f * C;
@@ -107,7 +153,7 @@ __global__ void __launch_bounds__(256) k_resid_restrict(const T* __restrict__ x,
 #pragma unroll
       for (int di = 0; di < 2; ++di) {
         const int i = 2 * I + di, j = 2 * J + dj, k = 2 * K + dk;
-        const int64_t c = cell_index<DIM>(i, j, k, logn);
+        const int c = cell_index<DIM>(i, j, k, logn);
         acc += b[c] - (diag * x[c] - c1 * nbr_sum<T, DIM>(x, i, j, k, logn));
       }
   bc[f * Cc + t] = acc * (DIM == 3 ? T(0.125) : T(0.25));
@@ -116,10 +162,10 @@ __global__ void __launch_bounds__(256) k_resid_restrict(const T* __restrict__ x,
 // x += P e (multilinear, cell-centred).
 template <typename T, int DIM>
 __global__ void __launch_bounds__(256) k_prolong_add(T* __restrict__ x, const T* __restrict__ e, int logn) {
-  const int64_t C = (int64_t)1 << (DIM * logn);
+  const int C = 1 << (DIM * logn);
   const int lognc = logn - 1;
-  const int64_t Cc = (int64_t)1 << (DIM * lognc);
-  const int64_t c = xcd_block(gridDim.x) * blockDim.x + threadIdx.x;
+  const int Cc = 1 << (DIM * lognc);
+  const int c = flat_thread(gridDim.x);
   if (c >= C) return;
   const int64_t f = blockIdx.y;
   x += f * C;
@@ -151,18 +197,18 @@ __global__ void __launch_bounds__(256) k_prolong_add(T* __restrict__ x, const T*
 // ---------------------------------------------------------------- one-workgroup tail
 template <typename T, int DIM>
 __device__ void lds_rb_sweeps(T* x, const T* b, int logn, T c0, T c1, int sweeps, bool from_zero) {
-  const int64_t C = (int64_t)1 << (DIM * logn);
+  const int C = 1 << (DIM * logn);
   const T inv_diag = T(1) / (c0 + T(2 * DIM) * c1);
   if (from_zero) {
-    for (int64_t c = threadIdx.x; c < C; c += blockDim.x) x[c] = T(0);
+    for (int c = threadIdx.x; c < C; c += blockDim.x) x[c] = T(0);
     __syncthreads();
   }
   for (int s = 0; s < sweeps; ++s) {
     for (int color = 0; color < 2; ++color) {
-      for (int64_t t = threadIdx.x; t < C / 2; t += blockDim.x) {
+      for (int t = threadIdx.x; t < C / 2; t += blockDim.x) {
         int i, j, k;
         colour_cell<DIM>(t, logn, color, i, j, k);
-        const int64_t c = cell_index<DIM>(i, j, k, logn);
+        const int c = cell_index<DIM>(i, j, k, logn);
         x[c] = (b[c] + c1 * nbr_sum<T, DIM>(x, i, j, k, logn)) * inv_diag;
       }
       __syncthreads();
@@ -173,9 +219,9 @@ __device__ void lds_rb_sweeps(T* x, const T* b, int logn, T c0, T c1, int sweeps
 template <typename T, int DIM>
 __device__ void lds_resid_restrict(const T* x, const T* b, T* bc, int logn, T c0, T c1) {
   const int lognc = logn - 1;
-  const int64_t Cc = (int64_t)1 << (DIM * lognc);
+  const int Cc = 1 << (DIM * lognc);
   const T diag = c0 + T(2 * DIM) * c1;
-  for (int64_t t = threadIdx.x; t < Cc; t += blockDim.x) {
+  for (int t = threadIdx.x; t < Cc; t += blockDim.x) {
     int I, J, K;
     cell_coords<DIM>(t, lognc, I, J, K);
     T acc = 0;
@@ -183,7 +229,7 @@ __device__ void lds_resid_restrict(const T* x, const T* b, T* bc, int logn, T c0
       for (int dj = 0; dj < 2; ++dj)
         for (int di = 0; di < 2; ++di) {
           const int i = 2 * I + di, j = 2 * J + dj, k = 2 * K + dk;
-          const int64_t c = cell_index<DIM>(i, j, k, logn);
+          const int c = cell_index<DIM>(i, j, k, logn);
           acc += b[c] - (diag * x[c] - c1 * nbr_sum<T, DIM>(x, i, j, k, logn));
         }
     bc[t] = acc * (DIM == 3 ? T(0.125) : T(0.25));
@@ -193,10 +239,10 @@ __device__ void lds_resid_restrict(const T* x, const T* b, T* bc, int logn, T c0
 
 template <typename T, int DIM>
 __device__ void lds_prolong_add(T* x, const T* e, int logn) {
-  const int64_t C = (int64_t)1 << (DIM * logn);
+  const int C = 1 << (DIM * logn);
   const int lognc = logn - 1;
   const T w0 = T(0.75), w1 = T(0.25);
-  for (int64_t c = threadIdx.x; c < C; c += blockDim.x) {
+  for (int c = threadIdx.x; c < C; c += blockDim.x) {
     int i, j, k;
     cell_coords<DIM>(c, logn, i, j, k);
     const int I = i >> 1, J = j >> 1, K = k >> 1;
@@ -222,76 +268,88 @@ __device__ void lds_prolong_add(T* x, const T* e, int logn) {
 }
 
 template <typename T>
-__device__ void lds_remove_mean(T* b, int64_t C, T* red) {
+__device__ void lds_remove_mean(T* b, int C, T* red) {
   T s = 0;
-  for (int64_t c = threadIdx.x; c < C; c += blockDim.x) s += b[c];
+  for (int c = threadIdx.x; c < C; c += blockDim.x) s += b[c];
   s = block_sum(s, red);
   const T m = s / T(C);
   __syncthreads();
-  for (int64_t c = threadIdx.x; c < C; c += blockDim.x) b[c] -= m;
+  for (int c = threadIdx.x; c < C; c += blockDim.x) b[c] -= m;
   __syncthreads();
 }
 
-// V-cycle from a level of at most kLdsCells cells down to n = 4, one field per
-// workgroup.  b is read from global memory (kept in L2), every other array of
-// the tail lives in LDS.  c1 is the coefficient at the entry level.
+// V-cycle from a level of at most lds_max_cells cells down to n = 4, one field
+// per workgroup.  The entry level's b is read from global memory (kept in L2),
+// as are the right-hand sides too large for LDS (bscr, C/2^dim cells per
+// field); every other array of the tail lives in LDS.  c1 is the coefficient
+// at the entry level.
 template <typename T, int DIM>
-__global__ void __launch_bounds__(kLdsThreads) k_vcycle_lds(const T* __restrict__ bg, T* __restrict__ xg, int logn,
-                                                            T c0, T c1, int nu_pre, int nu_post, int nu_coarse) {
-  // x of every level back to back (entry level first); b of levels >= 1.
-  __shared__ T xs[kLdsCells * 4 / 3 + 64];
-  __shared__ T bs[kLdsCells / 3 + 64];
+__global__ void __launch_bounds__(kLdsThreads) k_vcycle_lds(const T* __restrict__ bg, T* __restrict__ xg,
+                                                            T* __restrict__ bscr, int logn, T c0, T c1, int nu_pre,
+                                                            int nu_post, int nu_coarse) {
+  constexpr int64_t kX = pyramid_cells<DIM>(lds_max_cells<T, DIM>()) + 64;
+  constexpr int64_t kB = pyramid_cells<DIM>(lds_b_max_cells<T, DIM>()) + 64;
+  // x of every level back to back (entry level first); b of the levels >= 1 that fit.
+  __shared__ T xs[kX];
+  __shared__ T bs[kB];
   __shared__ T red[kLdsThreads / kWave];
-  const int64_t C0 = (int64_t)1 << (DIM * logn);
-  const T* b0 = bg + blockIdx.x * C0;
-  T* x0 = xg + blockIdx.x * C0;
+  const int C0 = 1 << (DIM * logn);
+  const T* b0 = bg + (int64_t)blockIdx.x * C0;
+  T* x0 = xg + (int64_t)blockIdx.x * C0;
   const bool singular = c0 == T(0);
 
   const int nlev = logn - 1;  // entry level down to n = 4
-  int64_t xoff[8], boff[8];
+  int xoff[10];
+  T* bptr[10];
   {
-    int64_t xo = 0, bo = 0;
+    int xo = 0, bo = 0;
     for (int l = 0; l < nlev; ++l) {
-      const int64_t Cl = (int64_t)1 << (DIM * (logn - l));
+      const int Cl = 1 << (DIM * (logn - l));
       xoff[l] = xo;
       xo += Cl;
-      boff[l] = bo;
-      if (l >= 1) bo += Cl;
+      bptr[l] = nullptr;
+      if (l >= 1) {
+        if (Cl <= lds_b_max_cells<T, DIM>()) {
+          bptr[l] = bs + bo;
+          bo += Cl;
+        } else {
+          bptr[l] = bscr + (int64_t)blockIdx.x * Cl;
+        }
+      }
     }
   }
   auto xlev = [&](int l) -> T* { return xs + xoff[l]; };
-  auto blev = [&](int l) -> T* { return bs + boff[l]; };
 
   // The entry level reads b from global memory.
   T cl = c1;
   for (int l = 0; l < nlev - 1; ++l) {
     const int lg = logn - l;
-    const T* bl = l == 0 ? b0 : blev(l);
+    const T* bl = l == 0 ? b0 : bptr[l];
     lds_rb_sweeps<T, DIM>(xlev(l), bl, lg, c0, cl, nu_pre, true);
-    lds_resid_restrict<T, DIM>(xlev(l), bl, blev(l + 1), lg, c0, cl);
+    lds_resid_restrict<T, DIM>(xlev(l), bl, bptr[l + 1], lg, c0, cl);
     cl = cl * T(0.25);
   }
   {
     const int l = nlev - 1;
     const int lg = logn - l;
-    T* bl = l == 0 ? nullptr : blev(l);
+    T* bl = bptr[l];
     if (l == 0) {
-      // whole cycle is the coarsest grid: copy b to LDS scratch first
-      bl = xs + kLdsCells;  // C0 <= 64 here
-      for (int64_t c = threadIdx.x; c < C0; c += blockDim.x) bl[c] = b0[c];
+      // whole cycle is the coarsest grid: copy b to LDS first
+      bl = bs;  // C0 <= 64 here
+      for (int c = threadIdx.x; c < C0; c += blockDim.x) bl[c] = b0[c];
       __syncthreads();
     }
-    if (singular) lds_remove_mean<T>(bl, (int64_t)1 << (DIM * lg), red);
+    if (singular) lds_remove_mean<T>(bl, 1 << (DIM * lg), red);
     lds_rb_sweeps<T, DIM>(xlev(l), bl, lg, c0, cl, nu_coarse, true);
   }
   for (int l = nlev - 2; l >= 0; --l) {
     cl = cl * T(4);
     const int lg = logn - l;
-    const T* bl = l == 0 ? b0 : blev(l);
+    const T* bl = l == 0 ? b0 : bptr[l];
     lds_prolong_add<T, DIM>(xlev(l), xlev(l + 1), lg);
     lds_rb_sweeps<T, DIM>(xlev(l), bl, lg, c0, cl, nu_post, false);
   }
-  for (int64_t c = threadIdx.x; c < C0; c += blockDim.x) x0[c] = xs[c];
+  for (int c = threadIdx.x; c < C0; c += blockDim.x) x0[c] = xs[c];
 }
 
 // Per-field sums: partial[f][block] (deterministic two-pass reduction).
@@ -334,7 +392,6 @@ inline unsigned nblk(int64_t len, int bs = 256) { return (unsigned)((len + bs - 
 
 }  // namespace
 
-int mg_lds_cells() { return kLdsCells; }
 
 template <typename T>
 void launch_fill(T* x, int64_t len, T v, hipStream_t s) {
@@ -371,8 +428,9 @@ void MGHier<T>::init(int dim_, int logn_, int maxf) {
   nfmax = maxf;
   levels.clear();
   // multi-kernel levels: while the level has more cells than one workgroup holds
+  const int64_t cap = dim == 3 ? lds_max_cells<T, 3>() : lds_max_cells<T, 2>();
   int lg = logn;
-  while (((int64_t)1 << (dim * lg)) > kLdsCells) {
+  while (((int64_t)1 << (dim * lg)) > cap) {
     levels.push_back(lg);
     --lg;
   }
@@ -385,12 +443,18 @@ void MGHier<T>::init(int dim_, int logn_, int maxf) {
     bufs_x[l] = dev_alloc<T>(Cl * nfmax);
     bufs_b[l] = dev_alloc<T>(Cl * nfmax);
   }
+  // right-hand side of the tail's second level when it does not fit in LDS
+  const int64_t bmax = dim == 3 ? lds_b_max_cells<T, 3>() : lds_b_max_cells<T, 2>();
+  const int64_t c1 = lg >= 1 ? (int64_t)1 << (dim * (lg - 1)) : 0;
+  tail_b = c1 > bmax ? dev_alloc<T>(c1 * nfmax) : nullptr;
 }
 
 template <typename T>
 void MGHier<T>::release() {
   for (auto p : bufs_x) dev_free(p);
   for (auto p : bufs_b) dev_free(p);
+  dev_free(tail_b);
+  tail_b = nullptr;
   bufs_x.clear();
   bufs_b.clear();
 }
@@ -398,31 +462,54 @@ void MGHier<T>::release() {
 template <typename T>
 size_t MGHier<T>::bytes(int dim, int logn, int nf) {
   size_t tot = 0;
+  const int64_t cap = dim == 3 ? lds_max_cells<T, 3>() : lds_max_cells<T, 2>();
   int lg = logn;
-  while (((int64_t)1 << (dim * lg)) > kLdsCells) --lg;
+  while (((int64_t)1 << (dim * lg)) > cap) --lg;
   for (int l = logn - 1; l >= lg; --l) tot += 2 * ((size_t)1 << (dim * l)) * nf * sizeof(T);
+  const int64_t bmax = dim == 3 ? lds_b_max_cells<T, 3>() : lds_b_max_cells<T, 2>();
+  const int64_t c1 = lg >= 1 ? (int64_t)1 << (dim * (lg - 1)) : 0;
+  if (c1 > bmax) tot += (size_t)c1 * nf * sizeof(T);
   return tot;
 }
 
 template <typename T>
-void MGHier<T>::rb_half(T* x, const T* b, int lg, int nf, T c0, T c1, int color, bool from_zero, bool fine,
-                        hipStream_t s) {
+void MGHier<T>::rb_half(T* x, const T* b, int lg, int nf, T c0, T c1, int color, bool fine, hipStream_t s) {
   const int64_t Cl = (int64_t)1 << (dim * lg);
   const dim3 gh(nblk(Cl / 2), nf);
   if (fine) timer_begin(kTimerRbFine, s);
   if (dim == 3) {
     if (fine)
-      hipLaunchKernelGGL((k_rb<T, 3, true>), gh, dim3(256), 0, s, x, b, lg, c0, c1, color, from_zero ? 1 : 0);
+      hipLaunchKernelGGL((k_rb<T, 3, true>), gh, dim3(256), 0, s, x, b, lg, c0, c1, color);
     else
-      hipLaunchKernelGGL((k_rb<T, 3, false>), gh, dim3(256), 0, s, x, b, lg, c0, c1, color, from_zero ? 1 : 0);
+      hipLaunchKernelGGL((k_rb<T, 3, false>), gh, dim3(256), 0, s, x, b, lg, c0, c1, color);
   } else {
     if (fine)
-      hipLaunchKernelGGL((k_rb<T, 2, true>), gh, dim3(256), 0, s, x, b, lg, c0, c1, color, from_zero ? 1 : 0);
+      hipLaunchKernelGGL((k_rb<T, 2, true>), gh, dim3(256), 0, s, x, b, lg, c0, c1, color);
     else
-      hipLaunchKernelGGL((k_rb<T, 2, false>), gh, dim3(256), 0, s, x, b, lg, c0, c1, color, from_zero ? 1 : 0);
+      hipLaunchKernelGGL((k_rb<T, 2, false>), gh, dim3(256), 0, s, x, b, lg, c0, c1, color);
   }
   // algorithmic traffic of a half sweep: b and x of one colour, x of the other
   if (fine) timer_end(kTimerRbFine, s, 1.5 * (double)Cl * nf * sizeof(T));
+}
+
+template <typename T>
+void MGHier<T>::rb_first(T* x, const T* b, int lg, int nf, T c0, T c1, bool fine, hipStream_t s) {
+  const int64_t Cl = (int64_t)1 << (dim * lg);
+  const dim3 g(nblk(Cl), nf);
+  if (fine) timer_begin(kTimerRbFine, s);
+  if (dim == 3) {
+    if (fine)
+      hipLaunchKernelGGL((k_rb_first<T, 3, true>), g, dim3(256), 0, s, x, b, lg, c0, c1);
+    else
+      hipLaunchKernelGGL((k_rb_first<T, 3, false>), g, dim3(256), 0, s, x, b, lg, c0, c1);
+  } else {
+    if (fine)
+      hipLaunchKernelGGL((k_rb_first<T, 2, true>), g, dim3(256), 0, s, x, b, lg, c0, c1);
+    else
+      hipLaunchKernelGGL((k_rb_first<T, 2, false>), g, dim3(256), 0, s, x, b, lg, c0, c1);
+  }
+  // algorithmic traffic of the first sweep from zero: b read once, x written once
+  if (fine) timer_end(kTimerRbFine, s, 2.0 * (double)Cl * nf * sizeof(T));
 }
 
 template <typename T>
@@ -437,11 +524,12 @@ void MGHier<T>::vcycle(int nf, const T* b, T* x, double c0, double c1, int nu_pr
     const int64_t Cl = (int64_t)1 << (dim * lg);
     T* xl = l == 0 ? x : bufs_x[l];
     const T* bl = l == 0 ? b : bufs_b[l];
-    if (nu_pre <= 0) {
+    if (nu_pre <= 0)
       launch_fill<T>(xl, Cl * nf, T(0), s);
-    }
-    for (int sw = 0; sw < nu_pre; ++sw)
-      for (int color = 0; color < 2; ++color) rb_half(xl, bl, lg, nf, tc0, cl, color, sw == 0 && color == 0, l == 0, s);
+    else
+      rb_first(xl, bl, lg, nf, tc0, cl, l == 0, s);
+    for (int sw = 1; sw < nu_pre; ++sw)
+      for (int color = 0; color < 2; ++color) rb_half(xl, bl, lg, nf, tc0, cl, color, l == 0, s);
     const int64_t Cc = Cl >> dim;
     if (three)
       hipLaunchKernelGGL((k_resid_restrict<T, 3>), dim3(nblk(Cc), nf), dim3(256), 0, s, xl, bl, bufs_b[l + 1], lg,
@@ -455,11 +543,11 @@ void MGHier<T>::vcycle(int nf, const T* b, T* x, double c0, double c1, int nu_pr
     const T* bl = nml == 0 ? b : bufs_b[nml];
     T* xl = nml == 0 ? x : bufs_x[nml];
     if (three)
-      hipLaunchKernelGGL((k_vcycle_lds<T, 3>), dim3(nf), dim3(kLdsThreads), 0, s, bl, xl, lds_logn, tc0, cl, nu_pre,
-                         nu_post, nu_coarse);
+      hipLaunchKernelGGL((k_vcycle_lds<T, 3>), dim3(nf), dim3(kLdsThreads), 0, s, bl, xl, tail_b, lds_logn, tc0, cl,
+                         nu_pre, nu_post, nu_coarse);
     else
-      hipLaunchKernelGGL((k_vcycle_lds<T, 2>), dim3(nf), dim3(kLdsThreads), 0, s, bl, xl, lds_logn, tc0, cl, nu_pre,
-                         nu_post, nu_coarse);
+      hipLaunchKernelGGL((k_vcycle_lds<T, 2>), dim3(nf), dim3(kLdsThreads), 0, s, bl, xl, tail_b, lds_logn, tc0, cl,
+                         nu_pre, nu_post, nu_coarse);
   }
   for (int l = nml - 1; l >= 0; --l) {
     cl = cl * T(4);
@@ -472,7 +560,7 @@ void MGHier<T>::vcycle(int nf, const T* b, T* x, double c0, double c1, int nu_pr
     else
       hipLaunchKernelGGL((k_prolong_add<T, 2>), dim3(nblk(Cl), nf), dim3(256), 0, s, xl, bufs_x[l + 1], lg);
     for (int sw = 0; sw < nu_post; ++sw)
-      for (int color = 0; color < 2; ++color) rb_half(xl, bl, lg, nf, tc0, cl, color, false, l == 0, s);
+      for (int color = 0; color < 2; ++color) rb_half(xl, bl, lg, nf, tc0, cl, color, l == 0, s);
   }
 }
 

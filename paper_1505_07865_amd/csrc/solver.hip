@@ -204,6 +204,14 @@ void ps_inv(ibr_ctx* c, const T* in, T* out) {
 
 // Inner right-preconditioned GMRES(N_s) on the Stokes block, zero initial
 // guess: out (fluid part, T) = approx [[A, G], [-D, 0]]^-1 rhs.
+//
+// For N_s <= 3 the Krylov space span{r, K P r, ...} is taken in its power
+// basis: z_j = P p_j, w_j = K z_j, p_{j+1} = w_j, and the minimiser of
+// ||r - W y|| comes from the normal equations (one reduction over W and r,
+// one tiny Cholesky).  That is the GMRES(N_s) iterate in exact arithmetic
+// (same space, same minimised norm) at a third of the vector passes; with
+// K P close to I the few columns stay well separated.  Larger N_s use the
+// Arnoldi process, whose orthonormal basis keeps the problem conditioned.
 template <typename T>
 void inner_gmres(ibr_ctx* c, const T* rhs, T* out) {
   hipStream_t s = c->stream;
@@ -212,6 +220,19 @@ void inner_gmres(ibr_ctx* c, const T* rhs, T* out) {
   const int d = c->dim;
   T* Q = (T*)c->Qi;
   T* Z = (T*)c->Zi;
+  if (ns <= 3) {
+    for (int j = 0; j < ns; ++j) {
+      const T* pj = j == 0 ? rhs : Q + (int64_t)(j - 1) * NF;
+      T* Zj = Z + (int64_t)j * NF;
+      T* Wj = Q + (int64_t)j * NF;
+      ps_inv<T>(c, pj, Zj);
+      launch_stokes_apply<T, T>(d, c->logn, Zj, Zj + (int64_t)d * c->C, Wj, Wj + (int64_t)d * c->C, c->c0, c->ch2,
+                                c->inv_h, nullptr, s);
+    }
+    launch_gram_solve<T>(Q, NF, ns, rhs, NF, c->part, c->part_blocks, c->yi, s);
+    launch_combine<T, T>(Z, NF, ns, c->yi, out, NF, s, true);
+    return;
+  }
   const int ldh = ns + 1;
   launch_sumsq_partial<T>(rhs, NF, c->part, c->part_blocks, s);
   launch_norm_finish(c->part, c->part_blocks, c->betai, s);

@@ -86,16 +86,23 @@ def test_vcycle_matches_oracle_fp64(dim, n, c0, c1):
     s.close()
 
 
-@pytest.mark.parametrize("dim,n", [(3, 32), (2, 64)])
-def test_vcycle_mixed_precision(dim, n):
+@pytest.mark.parametrize("dim,n", [(3, 16), (3, 32), (3, 64), (2, 64), (2, 128), (2, 256)])
+@pytest.mark.parametrize("c0,c1", [(0.0, 1.0), (2.5, 0.7)])
+def test_vcycle_mixed_precision(dim, n, c0, c1):
+    """fp32 V-cycles: multi-kernel levels above the one-workgroup tail (32^3 /
+    128^2 in fp32), the tail alone, and the tail with its second level's
+    right-hand side outside LDS (3D from 32^3 down)."""
     from paper_1505_07865_amd import ibr
     s = ibr.Solver(dim=dim, n=n, h=1.0 / n, precision=ibr.MIXED)
     rng = np.random.default_rng(3)
-    b = rng.standard_normal((1,) + (n,) * dim)
-    b -= b.mean()
-    x = s.vcycle(0.0, 1.0, b)
-    xe = multigrid.vcycle(b[0], 0.0, 1.0)
-    assert _rel(x[0], xe) < 1e-5
+    nf = dim
+    b = rng.standard_normal((nf,) + (n,) * dim)
+    if c0 == 0.0:
+        b -= b.reshape(nf, -1).mean(axis=1).reshape((nf,) + (1,) * dim)
+    x = s.vcycle(c0, c1, b)
+    for f in range(nf):
+        xe = multigrid.vcycle(b[f], c0, c1)
+        assert _rel(x[f], xe) < 1e-5, (f, _rel(x[f], xe))
     s.close()
 
 
@@ -132,6 +139,30 @@ def test_preconditioner_matches_oracle(case, full):
     assert _rel(gv, zv) < 1e-9
     assert _rel(gp - gp.mean(), zp - zp.mean()) < 1e-9
     assert _rel(gl, zl) < 1e-9
+    s.close()
+
+
+@pytest.mark.parametrize("ns", [1, 2, 3, 4])
+@pytest.mark.parametrize("name", ["3d32_steady", "2d32_unsteady"])
+def test_preconditioner_inner_ns(name, ns):
+    """Inner GMRES(N_s): normal equations over the power basis for N_s <= 3,
+    Arnoldi for larger N_s; both must give the oracle's GMRES(N_s) iterate."""
+    from paper_1505_07865_amd import ibr
+    prob = small_problem(21, **CASES[name])
+    s = _solver(prob, pc=ibr.PC_LOWER, n_s=ns)
+    sysm = constrained.System.from_problem(prob)
+    P = precond.for_problem(prob, sysm, ns=ns, full=False)
+    rng = np.random.default_rng(10 + ns)
+    d, n, N = prob.dim, prob.n, prob.nmarkers
+    r = dense.apply_operator(sysm, rng.standard_normal(s.NV))
+    z = s.precondition(r)
+    nv, npr = d * n ** d, n ** d
+    zv, zp, zl = P.apply(r[:nv].reshape((d,) + (n,) * d), r[nv:nv + npr].reshape((n,) * d),
+                         r[nv + npr:].reshape(N, d))
+    assert _rel(z[:nv].reshape(zv.shape), zv) < 1e-9
+    assert _rel(z[nv + npr:].reshape(zl.shape), zl) < 1e-9
+    # a zero residual maps to exactly zero (rank-deficient normal equations)
+    assert not np.any(s.precondition(np.zeros(s.NV)))
     s.close()
 
 
