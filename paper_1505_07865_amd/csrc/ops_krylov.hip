@@ -2,6 +2,8 @@
 // combination and the Givens-rotation Hessenberg least squares of GMRES.
 // All reductions are two-pass with a fixed partition, so results are
 // bitwise reproducible run to run.
+#include <algorithm>
+
 #include "kernels.h"
 
 namespace ibr {
@@ -264,31 +266,36 @@ __global__ void k_dgks_finish(double* __restrict__ hcol, int k, const double* __
 // the passes over the basis.
 
 // part[(2 j + r) * nblocks + block]: r = 0 against V_k, r = 1 against w.
-template <typename T>
-__global__ void __launch_bounds__(256) k_dual_dot(const T* __restrict__ V, int64_t ld, int ncols, int kx,
-                                                  int64_t len, double* __restrict__ part) {
-  __shared__ double red[2 * kDotCols][256 / kWave];
-  const int j0 = blockIdx.y * kDotCols;
-  const int nj = min(kDotCols, ncols - j0);
-  const T* x1 = V + (int64_t)kx * ld;
-  const T* x2 = V + (int64_t)(kx + 1) * ld;
-  double a1[kDotCols], a2[kDotCols];
+// Up to kDualCols basis vectors per workgroup row (blockIdx.y), so the two
+// vectors being orthogonalised are read once per chunk.  Element offsets are
+// 32-bit (len < 2^28) on top of uniform column base addresses.
+constexpr int kDualCols = 16;
+// (4 waves per SIMD: room for all the loads of one element in flight)
+template <typename T, int NJ>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) k_dual_dot(const T* __restrict__ V, int64_t ld, int j0, int kx, int len,
+                                                  double* __restrict__ part) {
+  __shared__ double red[2 * NJ][256 / kWave];
+  const T* __restrict__ x1 = V + (int64_t)kx * ld;
+  const T* __restrict__ x2 = x1 + ld;
+  const T* __restrict__ Vj = V + (int64_t)j0 * ld;
+  double a1[NJ], a2[NJ];
 #pragma unroll
-  for (int q = 0; q < kDotCols; ++q) a1[q] = a2[q] = 0.0;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += stride) {
+  for (int q = 0; q < NJ; ++q) a1[q] = a2[q] = 0.0;
+  const unsigned stride = gridDim.x * blockDim.x;
+  for (unsigned i = blockIdx.x * blockDim.x + threadIdx.x; i < (unsigned)len; i += stride) {
+    double v[NJ];
+#pragma unroll
+    for (int q = 0; q < NJ; ++q) v[q] = (double)Vj[(int64_t)q * ld + i];
     const double u = (double)x1[i], w = (double)x2[i];
 #pragma unroll
-    for (int q = 0; q < kDotCols; ++q)
-      if (q < nj) {
-        const double v = (double)V[(int64_t)(j0 + q) * ld + i];
-        a1[q] += v * u;
-        a2[q] += v * w;
-      }
+    for (int q = 0; q < NJ; ++q) {
+      a1[q] += v[q] * u;
+      a2[q] += v[q] * w;
+    }
   }
   const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
 #pragma unroll
-  for (int q = 0; q < kDotCols; ++q) {
+  for (int q = 0; q < NJ; ++q) {
     const double s1 = wave_sum(a1[q]);
     const double s2 = wave_sum(a2[q]);
     if (lane == 0) {
@@ -297,19 +304,31 @@ __global__ void __launch_bounds__(256) k_dual_dot(const T* __restrict__ V, int64
     }
   }
   __syncthreads();
-  if (threadIdx.x < 2 * nj) {
+  if ((int)threadIdx.x < 2 * NJ) {
     double t = 0;
     for (int u = 0; u < (int)(blockDim.x / kWave); ++u) t += red[threadIdx.x][u];
     part[(int64_t)(2 * j0 + threadIdx.x) * gridDim.x + blockIdx.x] = t;
   }
 }
 
-// Coefficients of the delayed step.  G[2j] = <V_j, V_k>, G[2j+1] = <V_j, w>.
+// Sums the 2(k+2) rows of partials (one wavefront per row, rows round-robin
+// over the 4 wavefronts, fixed order) into G, then computes the coefficients
+// of the delayed step.  G[2j] = <V_j, V_k>, G[2j+1] = <V_j, w>.
 // coef[0..k) = s (re-orthogonalisation of V_k), coef[k] = nu, coef[k+1 .. 2k+1] = c.
 // Column k-1 of H is corrected (its pending vector is now resolved) and the
 // provisional column k is written.
-__global__ void k_dcgs2_coef(const double* __restrict__ G, int k, double* __restrict__ H, int ldh,
-                             double* __restrict__ coef) {
+__global__ void __launch_bounds__(256) k_dcgs2_coef(const double* __restrict__ part, int nblocks,
+                                                    double* __restrict__ G, int k, double* __restrict__ H, int ldh,
+                                                    double* __restrict__ coef) {
+  const int rows = 2 * (k + 2);
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+  for (int r = wv; r < rows; r += (int)(blockDim.x / kWave)) {
+    double v = 0;
+    for (int i = lane; i < nblocks; i += kWave) v += part[(int64_t)r * nblocks + i];
+    v = wave_sum(v);
+    if (lane == 0) G[r] = v;
+  }
+  __syncthreads();
   if (threadIdx.x != 0) return;
   double* colk = H + (int64_t)k * ldh;
   if (k == 0) {
@@ -346,19 +365,30 @@ __global__ void k_dcgs2_coef(const double* __restrict__ G, int k, double* __rest
 // part[block] = partial sums of the new w^2.
 template <typename T>
 __global__ void __launch_bounds__(256) k_dcgs2_axpy(T* __restrict__ V, int64_t ld, int k,
-                                                    const double* __restrict__ coef, int64_t len,
+                                                    const double* __restrict__ coef, int len,
                                                     double* __restrict__ part) {
   __shared__ double red[256 / kWave];
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  T* vk = V + (int64_t)k * ld;
-  T* w = V + (int64_t)(k + 1) * ld;
+  const unsigned stride = gridDim.x * blockDim.x;
+  T* __restrict__ vk = V + (int64_t)k * ld;
+  T* __restrict__ w = vk + ld;
   const double inv_nu = 1.0 / coef[k];
   const double* c = coef + k + 1;
   double ss = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += stride) {
+  for (unsigned i = blockIdx.x * blockDim.x + threadIdx.x; i < (unsigned)len; i += stride) {
     double q = (double)vk[i];
     double a = (double)w[i];
-    for (int j = 0; j < k; ++j) {
+    int j = 0;
+    for (; j + 8 <= k; j += 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = (double)V[(int64_t)(j + u) * ld + i];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        q -= coef[j + u] * v[u];
+        a -= c[j + u] * v[u];
+      }
+    }
+    for (; j < k; ++j) {
       const double v = (double)V[(int64_t)j * ld + i];
       q -= coef[j] * v;
       a -= c[j] * v;
@@ -606,16 +636,28 @@ void launch_axpby(const double* x, double* y, int64_t len, double a, double b, h
 template <typename T>
 void dcgs2_step(T* V, int64_t ld, int k, double* H, int ldh, double* G, double* coef, double* part, int nblocks,
                 double* cs, double* sn, double* g, double* resid, hipStream_t s, bool timed) {
+  if (ld >= ((int64_t)1 << 28)) throw DeviceError("dcgs2_step: vectors longer than 2^28 entries");
   const int ncols = k + 2;
-  const int nchunk = (ncols + kDotCols - 1) / kDotCols;
   const double vb = (double)ld * sizeof(T);
   if (timed) timer_begin(kTimerOrthoDot, s);
-  hipLaunchKernelGGL((k_dual_dot<T>), dim3(nblocks, nchunk), dim3(256), 0, s, V, ld, ncols, k, ld, part);
-  if (timed) timer_end(kTimerOrthoDot, s, ncols * vb);
-  hipLaunchKernelGGL(k_dot_finish, dim3(2 * ncols), dim3(256), 0, s, part, nblocks, G, 0, (const int*)nullptr);
-  hipLaunchKernelGGL(k_dcgs2_coef, dim3(1), dim3(64), 0, s, G, k, H, ldh, coef);
+  for (int j0 = 0; j0 < ncols; j0 += kDualCols) {
+    const int nj = std::min(kDualCols, ncols - j0);
+    switch (nj) {
+#define IBR_DUAL(NJ)                                                                                              \
+  case NJ:                                                                                                        \
+    hipLaunchKernelGGL((k_dual_dot<T, NJ>), dim3(nblocks), dim3(256), 0, s, V, ld, j0, k, (int)ld, part);         \
+    break;
+      IBR_DUAL(1) IBR_DUAL(2) IBR_DUAL(3) IBR_DUAL(4) IBR_DUAL(5) IBR_DUAL(6) IBR_DUAL(7) IBR_DUAL(8)
+      IBR_DUAL(9) IBR_DUAL(10) IBR_DUAL(11) IBR_DUAL(12) IBR_DUAL(13) IBR_DUAL(14) IBR_DUAL(15) IBR_DUAL(16)
+#undef IBR_DUAL
+    }
+  }
+  // bytes of the whole reduction (all chunks): the k+2 columns once, plus the
+  // two vectors being orthogonalised once per extra chunk
+  if (timed) timer_end(kTimerOrthoDot, s, (ncols + 2 * ((ncols - 1) / kDualCols)) * vb);
+  hipLaunchKernelGGL(k_dcgs2_coef, dim3(1), dim3(256), 0, s, part, nblocks, G, k, H, ldh, coef);
   if (timed) timer_begin(kTimerOrthoAxpy, s);
-  hipLaunchKernelGGL((k_dcgs2_axpy<T>), dim3(nblocks), dim3(256), 0, s, V, ld, k, coef, ld, part);
+  hipLaunchKernelGGL((k_dcgs2_axpy<T>), dim3(nblocks), dim3(256), 0, s, V, ld, k, coef, (int)ld, part);
   if (timed) timer_end(kTimerOrthoAxpy, s, (ncols + 2) * vb);
   hipLaunchKernelGGL(k_dcgs2_finish, dim3(1), dim3(256), 0, s, part, nblocks, H, ldh, k, cs, sn, g, resid);
 }

@@ -85,49 +85,124 @@ __device__ inline int flat_thread(unsigned nblocks) {
 }
 
 // ---------------------------------------------------------------- fine-level kernels
-// One red-black half sweep.  FINE marks the finest level (same code; a
-// separate symbol for profiling).
+// Four consecutive cells of one x-row, loaded and stored as one vector.
+template <typename T>
+struct alignas(4 * sizeof(T)) Quad {
+  T v[4];
+};
+
+// One red-black half sweep.  Each thread owns 4 consecutive cells of an
+// x-row, 2 of them of the colour being updated: the row and its y/z
+// neighbour rows are read as 4-wide vectors, plus the one x-neighbour outside
+// the segment.  The 2 cells of the other colour are written back unchanged
+// (no thread changes them during this half sweep).  FINE marks the finest
+// level (same code; a separate symbol for profiling).  Needs n >= 4.
 template <typename T, int DIM, bool FINE>
 __global__ void __launch_bounds__(256) k_rb(T* __restrict__ x, const T* __restrict__ b, int logn, T c0, T c1,
                                             int color) {
   const int C = 1 << (DIM * logn);
   const int t = flat_thread(gridDim.x);
-  if (t >= C / 2) return;
+  if (t >= (C >> 2)) return;
   const int64_t f = blockIdx.y;
   x += f * C;
   b += f * C;
-  int i, j, k;
-  colour_cell<DIM>(t, logn, color, i, j, k);
-  const int c = cell_index<DIM>(i, j, k, logn);
+  const int mask = (1 << logn) - 1;
+  const int qlog = logn - 2;  // segments per row = n/4
+  const int i0 = (t & ((1 << qlog) - 1)) << 2;
+  const int row = t >> qlog;
+  const int j = row & mask;
+  const int k = DIM == 3 ? (row >> logn) : 0;
+  const int p = (j + k + color) & 1;  // first cell of the colour in the segment
+  const int o = (row << logn) + i0;
+  Quad<T> xc = *reinterpret_cast<const Quad<T>*>(x + o);
+  const Quad<T> bc = *reinterpret_cast<const Quad<T>*>(b + o);
+  const int ry0 = (((j - 1) & mask) + (k << logn)) << logn, ry1 = (((j + 1) & mask) + (k << logn)) << logn;
+  const Quad<T> ym = *reinterpret_cast<const Quad<T>*>(x + ry0 + i0);
+  const Quad<T> yp = *reinterpret_cast<const Quad<T>*>(x + ry1 + i0);
+  Quad<T> zm, zp;
+  if (DIM == 3) {
+    const int rz0 = (j + (((k - 1) & mask) << logn)) << logn, rz1 = (j + (((k + 1) & mask) << logn)) << logn;
+    zm = *reinterpret_cast<const Quad<T>*>(x + rz0 + i0);
+    zp = *reinterpret_cast<const Quad<T>*>(x + rz1 + i0);
+  }
+  // the x-neighbour outside the segment: left of cell 0 or right of cell 3
+  const T ext = x[(row << logn) + ((p == 0 ? i0 - 1 : i0 + 4) & mask)];
   const T inv_diag = T(1) / (c0 + T(2 * DIM) * c1);
-  x[c] = (b[c] + c1 * nbr_sum<T, DIM>(x, i, j, k, logn)) * inv_diag;
+  // the two cells of the colour are (0, 2) or (1, 3); static indices and a
+  // select keep the four-cell vectors in registers
+  const bool odd = p != 0;
+  const T l0 = odd ? xc.v[0] : ext, r0 = odd ? xc.v[2] : xc.v[1];
+  const T l1 = odd ? xc.v[2] : xc.v[1], r1 = odd ? ext : xc.v[3];
+  T s0 = l0 + r0 + (odd ? ym.v[1] : ym.v[0]) + (odd ? yp.v[1] : yp.v[0]);
+  T s1 = l1 + r1 + (odd ? ym.v[3] : ym.v[2]) + (odd ? yp.v[3] : yp.v[2]);
+  if (DIM == 3) {
+    s0 += (odd ? zm.v[1] : zm.v[0]) + (odd ? zp.v[1] : zp.v[0]);
+    s1 += (odd ? zm.v[3] : zm.v[2]) + (odd ? zp.v[3] : zp.v[2]);
+  }
+  const T n0 = ((odd ? bc.v[1] : bc.v[0]) + c1 * s0) * inv_diag;
+  const T n1 = ((odd ? bc.v[3] : bc.v[2]) + c1 * s1) * inv_diag;
+  xc.v[0] = odd ? xc.v[0] : n0;
+  xc.v[1] = odd ? n0 : xc.v[1];
+  xc.v[2] = odd ? xc.v[2] : n1;
+  xc.v[3] = odd ? n1 : xc.v[3];
+  *reinterpret_cast<Quad<T>*>(x + o) = xc;
 }
 
 // The first red-black sweep from a zero guess in one pass: red cells take
 // b/diag, black cells (all of whose neighbours are red) take
 // (b + c1 * sum of the neighbours' b/diag)/diag.  Same arithmetic, in the same
-// order, as a red then a black half sweep from x = 0.
+// order, as a red then a black half sweep from x = 0.  Four cells of a row
+// per thread, as in k_rb.
 template <typename T, int DIM, bool FINE>
 __global__ void __launch_bounds__(256) k_rb_first(T* __restrict__ x, const T* __restrict__ b, int logn, T c0,
                                                   T c1) {
   const int C = 1 << (DIM * logn);
-  const int c = flat_thread(gridDim.x);
-  if (c >= C) return;
+  const int t = flat_thread(gridDim.x);
+  if (t >= (C >> 2)) return;
   const int64_t f = blockIdx.y;
   x += f * C;
   b += f * C;
-  int i, j, k;
-  cell_coords<DIM>(c, logn, i, j, k);
-  const T inv_diag = T(1) / (c0 + T(2 * DIM) * c1);
-  if (((i + j + k) & 1) == 0) {
-    x[c] = b[c] * inv_diag;
-  } else {
-    T s = b[cell_index<DIM>(i - 1, j, k, logn)] * inv_diag + b[cell_index<DIM>(i + 1, j, k, logn)] * inv_diag +
-          b[cell_index<DIM>(i, j - 1, k, logn)] * inv_diag + b[cell_index<DIM>(i, j + 1, k, logn)] * inv_diag;
-    if (DIM == 3)
-      s += b[cell_index<DIM>(i, j, k - 1, logn)] * inv_diag + b[cell_index<DIM>(i, j, k + 1, logn)] * inv_diag;
-    x[c] = (b[c] + c1 * s) * inv_diag;
+  const int mask = (1 << logn) - 1;
+  const int qlog = logn - 2;
+  const int i0 = (t & ((1 << qlog) - 1)) << 2;
+  const int row = t >> qlog;
+  const int j = row & mask;
+  const int k = DIM == 3 ? (row >> logn) : 0;
+  const int p = (j + k + 1) & 1;  // first black cell of the segment
+  const int o = (row << logn) + i0;
+  const Quad<T> bc = *reinterpret_cast<const Quad<T>*>(b + o);
+  const int ry0 = (((j - 1) & mask) + (k << logn)) << logn, ry1 = (((j + 1) & mask) + (k << logn)) << logn;
+  const Quad<T> ym = *reinterpret_cast<const Quad<T>*>(b + ry0 + i0);
+  const Quad<T> yp = *reinterpret_cast<const Quad<T>*>(b + ry1 + i0);
+  Quad<T> zm, zp;
+  if (DIM == 3) {
+    const int rz0 = (j + (((k - 1) & mask) << logn)) << logn, rz1 = (j + (((k + 1) & mask) << logn)) << logn;
+    zm = *reinterpret_cast<const Quad<T>*>(b + rz0 + i0);
+    zp = *reinterpret_cast<const Quad<T>*>(b + rz1 + i0);
   }
+  const T ext = b[(row << logn) + ((p == 0 ? i0 - 1 : i0 + 4) & mask)];
+  const T inv_diag = T(1) / (c0 + T(2 * DIM) * c1);
+  // black cells are (0, 2) or (1, 3); static indices and a select keep the
+  // four-cell vectors in registers
+  const bool odd = p != 0;
+  const T l0 = odd ? bc.v[0] : ext, r0 = odd ? bc.v[2] : bc.v[1];
+  const T l1 = odd ? bc.v[2] : bc.v[1], r1 = odd ? ext : bc.v[3];
+  T s0 = l0 * inv_diag + r0 * inv_diag + (odd ? ym.v[1] : ym.v[0]) * inv_diag +
+         (odd ? yp.v[1] : yp.v[0]) * inv_diag;
+  T s1 = l1 * inv_diag + r1 * inv_diag + (odd ? ym.v[3] : ym.v[2]) * inv_diag +
+         (odd ? yp.v[3] : yp.v[2]) * inv_diag;
+  if (DIM == 3) {
+    s0 += (odd ? zm.v[1] : zm.v[0]) * inv_diag + (odd ? zp.v[1] : zp.v[0]) * inv_diag;
+    s1 += (odd ? zm.v[3] : zm.v[2]) * inv_diag + (odd ? zp.v[3] : zp.v[2]) * inv_diag;
+  }
+  const T n0 = ((odd ? bc.v[1] : bc.v[0]) + c1 * s0) * inv_diag;
+  const T n1 = ((odd ? bc.v[3] : bc.v[2]) + c1 * s1) * inv_diag;
+  Quad<T> xo;
+  xo.v[0] = odd ? bc.v[0] * inv_diag : n0;
+  xo.v[1] = odd ? n0 : bc.v[1] * inv_diag;
+  xo.v[2] = odd ? bc.v[2] * inv_diag : n1;
+  xo.v[3] = odd ? n1 : bc.v[3] * inv_diag;
+  *reinterpret_cast<Quad<T>*>(x + o) = xo;
 }
 
 // Coarse right-hand side = average over the 2^dim children of the residual.
@@ -390,6 +465,13 @@ __global__ void k_fill(T* __restrict__ x, int64_t len, T v) {
 
 inline unsigned nblk(int64_t len, int bs = 256) { return (unsigned)((len + bs - 1) / bs); }
 
+// The sweeps read and write 4 consecutive cells as one vector.
+template <typename T>
+void check_quad_aligned(const T* x, const T* b) {
+  if (((uintptr_t)x | (uintptr_t)b) % (4 * sizeof(T)) != 0)
+    throw DeviceError("multigrid: field arrays must be aligned to 4 elements");
+}
+
 }  // namespace
 
 
@@ -475,7 +557,8 @@ size_t MGHier<T>::bytes(int dim, int logn, int nf) {
 template <typename T>
 void MGHier<T>::rb_half(T* x, const T* b, int lg, int nf, T c0, T c1, int color, bool fine, hipStream_t s) {
   const int64_t Cl = (int64_t)1 << (dim * lg);
-  const dim3 gh(nblk(Cl / 2), nf);
+  check_quad_aligned(x, b);
+  const dim3 gh(nblk(Cl / 4), nf);
   if (fine) timer_begin(kTimerRbFine, s);
   if (dim == 3) {
     if (fine)
@@ -495,7 +578,8 @@ void MGHier<T>::rb_half(T* x, const T* b, int lg, int nf, T c0, T c1, int color,
 template <typename T>
 void MGHier<T>::rb_first(T* x, const T* b, int lg, int nf, T c0, T c1, bool fine, hipStream_t s) {
   const int64_t Cl = (int64_t)1 << (dim * lg);
-  const dim3 g(nblk(Cl), nf);
+  check_quad_aligned(x, b);
+  const dim3 g(nblk(Cl / 4), nf);
   if (fine) timer_begin(kTimerRbFine, s);
   if (dim == 3) {
     if (fine)
