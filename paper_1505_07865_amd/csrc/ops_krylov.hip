@@ -317,15 +317,23 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))
 // coef[0..k) = s (re-orthogonalisation of V_k), coef[k] = nu, coef[k+1 .. 2k+1] = c.
 // Column k-1 of H is corrected (its pending vector is now resolved) and the
 // provisional column k is written.
-__global__ void __launch_bounds__(256) k_dcgs2_coef(const double* __restrict__ part, int nblocks,
-                                                    double* __restrict__ G, int k, double* __restrict__ H, int ldh,
-                                                    double* __restrict__ coef) {
+__global__ void __launch_bounds__(1024) k_dcgs2_coef(const double* __restrict__ part, int nblocks,
+                                                     double* __restrict__ G, int k, double* __restrict__ H, int ldh,
+                                                     double* __restrict__ coef) {
   const int rows = 2 * (k + 2);
   const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
   for (int r = wv; r < rows; r += (int)(blockDim.x / kWave)) {
-    double v = 0;
-    for (int i = lane; i < nblocks; i += kWave) v += part[(int64_t)r * nblocks + i];
-    v = wave_sum(v);
+    const double* pr = part + (int64_t)r * nblocks;
+    double v0 = 0, v1 = 0, v2 = 0, v3 = 0;
+    int i = lane;
+    for (; i + 3 * kWave < nblocks; i += 4 * kWave) {
+      v0 += pr[i];
+      v1 += pr[i + kWave];
+      v2 += pr[i + 2 * kWave];
+      v3 += pr[i + 3 * kWave];
+    }
+    for (; i < nblocks; i += kWave) v0 += pr[i];
+    const double v = wave_sum((v0 + v1) + (v2 + v3));
     if (lane == 0) G[r] = v;
   }
   __syncthreads();
@@ -655,7 +663,7 @@ void dcgs2_step(T* V, int64_t ld, int k, double* H, int ldh, double* G, double* 
   // bytes of the whole reduction (all chunks): the k+2 columns once, plus the
   // two vectors being orthogonalised once per extra chunk
   if (timed) timer_end(kTimerOrthoDot, s, (ncols + 2 * ((ncols - 1) / kDualCols)) * vb);
-  hipLaunchKernelGGL(k_dcgs2_coef, dim3(1), dim3(256), 0, s, part, nblocks, G, k, H, ldh, coef);
+  hipLaunchKernelGGL(k_dcgs2_coef, dim3(1), dim3(1024), 0, s, part, nblocks, G, k, H, ldh, coef);
   if (timed) timer_begin(kTimerOrthoAxpy, s);
   hipLaunchKernelGGL((k_dcgs2_axpy<T>), dim3(nblocks), dim3(256), 0, s, V, ld, k, coef, (int)ld, part);
   if (timed) timer_end(kTimerOrthoAxpy, s, (ncols + 2) * vb);

@@ -205,7 +205,18 @@ __global__ void __launch_bounds__(256) k_rb_first(T* __restrict__ x, const T* __
   *reinterpret_cast<Quad<T>*>(x + o) = xo;
 }
 
-// Coarse right-hand side = average over the 2^dim children of the residual.
+template <typename T>
+struct alignas(2 * sizeof(T)) Pair {
+  T v[2];
+};
+
+// Coarse right-hand side = average over the 2^dim children of the residual
+// r = b - (diag x - c1 sum_nbr x).  Summed over a 2^dim block, each child's
+// neighbour along each axis inside the block is a sibling, so
+//   sum r = sum b - (diag - dim c1) sum x + c1 (sum of the 4^(dim-1) 2 dim
+//           face neighbours outside the block).
+// Each thread makes two coarse cells (four fine cells along x) from 4-wide
+// row vectors.  Needs n >= 4.
 template <typename T, int DIM>
 __global__ void __launch_bounds__(256) k_resid_restrict(const T* __restrict__ x, const T* __restrict__ b,
                                                         T* __restrict__ bc, int logn, T c0, T c1) {
@@ -213,60 +224,115 @@ __global__ void __launch_bounds__(256) k_resid_restrict(const T* __restrict__ x,
   const int Cc = 1 << (DIM * lognc);
   const int C = 1 << (DIM * logn);
   const int t = flat_thread(gridDim.x);
-  if (t >= Cc) return;
+  if (t >= (Cc >> 1)) return;
   const int64_t f = blockIdx.y;
   x += f * C;
   b += f * C;
-  int I, J, K;
-  cell_coords<DIM>(t, lognc, I, J, K);
-  const T diag = c0 + T(2 * DIM) * c1;
-  T acc = 0;
+  const int mask = (1 << logn) - 1;
+  const int qlog = logn - 2;  // coarse-cell pairs per coarse row
+  const int q = t & ((1 << qlog) - 1);
+  const int rowc = t >> qlog;
+  const int J = rowc & ((1 << lognc) - 1);
+  const int K = DIM == 3 ? (rowc >> lognc) : 0;
+  const int i0 = q << 2;
+  T sx0 = 0, sx1 = 0, sb0 = 0, sb1 = 0, sf0 = 0, sf1 = 0;
 #pragma unroll
-  for (int dk = 0; dk < (DIM == 3 ? 2 : 1); ++dk)
+  for (int dz = 0; dz < (DIM == 3 ? 2 : 1); ++dz)
 #pragma unroll
-    for (int dj = 0; dj < 2; ++dj)
+    for (int dy = 0; dy < 2; ++dy) {
+      const int ro = (((2 * J + dy) & mask) + (((2 * K + dz) & mask) << logn)) << logn;
+      const Quad<T> xq = *reinterpret_cast<const Quad<T>*>(x + ro + i0);
+      const Quad<T> bq = *reinterpret_cast<const Quad<T>*>(b + ro + i0);
+      const T xl = x[ro + ((i0 - 1) & mask)], xr = x[ro + ((i0 + 4) & mask)];
+      sx0 += xq.v[0] + xq.v[1];
+      sx1 += xq.v[2] + xq.v[3];
+      sb0 += bq.v[0] + bq.v[1];
+      sb1 += bq.v[2] + bq.v[3];
+      sf0 += xl + xq.v[2];
+      sf1 += xq.v[1] + xr;
+    }
+  // y faces: rows 2J-1 and 2J+2
 #pragma unroll
-      for (int di = 0; di < 2; ++di) {
-        const int i = 2 * I + di, j = 2 * J + dj, k = 2 * K + dk;
-        const int c = cell_index<DIM>(i, j, k, logn);
-        acc += b[c] - (diag * x[c] - c1 * nbr_sum<T, DIM>(x, i, j, k, logn));
+  for (int dz = 0; dz < (DIM == 3 ? 2 : 1); ++dz)
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int y = e == 0 ? 2 * J - 1 : 2 * J + 2;
+      const int ro = ((y & mask) + (((2 * K + dz) & mask) << logn)) << logn;
+      const Quad<T> yq = *reinterpret_cast<const Quad<T>*>(x + ro + i0);
+      sf0 += yq.v[0] + yq.v[1];
+      sf1 += yq.v[2] + yq.v[3];
+    }
+  if (DIM == 3) {
+    // z faces: planes 2K-1 and 2K+2
+#pragma unroll
+    for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const int z = e == 0 ? 2 * K - 1 : 2 * K + 2;
+        const int ro = (((2 * J + dy) & mask) + ((z & mask) << logn)) << logn;
+        const Quad<T> zq = *reinterpret_cast<const Quad<T>*>(x + ro + i0);
+        sf0 += zq.v[0] + zq.v[1];
+        sf1 += zq.v[2] + zq.v[3];
       }
-  bc[f * Cc + t] = acc * (DIM == 3 ? T(0.125) : T(0.25));
+  }
+  const T diag = c0 + T(2 * DIM) * c1;
+  const T inner = diag - T(DIM) * c1;
+  const T avg = DIM == 3 ? T(0.125) : T(0.25);
+  Pair<T> out;
+  out.v[0] = (sb0 - inner * sx0 + c1 * sf0) * avg;
+  out.v[1] = (sb1 - inner * sx1 + c1 * sf1) * avg;
+  *reinterpret_cast<Pair<T>*>(bc + f * Cc + (rowc << lognc) + 2 * q) = out;
 }
 
-// x += P e (multilinear, cell-centred).
+// x += P e (multilinear, cell-centred: weights 3/4 and 1/4 per axis).  Each
+// thread owns four fine cells of an x-row; each of the 2^(dim-1) coarse rows
+// it needs is interpolated along x once (a pair load and two scalars).
 template <typename T, int DIM>
 __global__ void __launch_bounds__(256) k_prolong_add(T* __restrict__ x, const T* __restrict__ e, int logn) {
   const int C = 1 << (DIM * logn);
   const int lognc = logn - 1;
   const int Cc = 1 << (DIM * lognc);
-  const int c = flat_thread(gridDim.x);
-  if (c >= C) return;
+  const int t = flat_thread(gridDim.x);
+  if (t >= (C >> 2)) return;
   const int64_t f = blockIdx.y;
   x += f * C;
   e += f * Cc;
-  int i, j, k;
-  cell_coords<DIM>(c, logn, i, j, k);
-  const int I = i >> 1, J = j >> 1, K = k >> 1;
-  const int si = (i & 1) ? 1 : -1, sj = (j & 1) ? 1 : -1, sk = (k & 1) ? 1 : -1;
-  T v;
-  if (DIM == 3) {
-    const T w0 = T(0.75), w1 = T(0.25);
-    T a00 = w0 * e[cell_index<DIM>(I, J, K, lognc)] + w1 * e[cell_index<DIM>(I + si, J, K, lognc)];
-    T a10 = w0 * e[cell_index<DIM>(I, J + sj, K, lognc)] + w1 * e[cell_index<DIM>(I + si, J + sj, K, lognc)];
-    T a01 = w0 * e[cell_index<DIM>(I, J, K + sk, lognc)] + w1 * e[cell_index<DIM>(I + si, J, K + sk, lognc)];
-    T a11 = w0 * e[cell_index<DIM>(I, J + sj, K + sk, lognc)] +
-            w1 * e[cell_index<DIM>(I + si, J + sj, K + sk, lognc)];
-    T b0 = w0 * a00 + w1 * a10;
-    T b1 = w0 * a01 + w1 * a11;
-    v = w0 * b0 + w1 * b1;
-  } else {
-    const T w0 = T(0.75), w1 = T(0.25);
-    T a0 = w0 * e[cell_index<DIM>(I, J, 0, lognc)] + w1 * e[cell_index<DIM>(I + si, J, 0, lognc)];
-    T a1 = w0 * e[cell_index<DIM>(I, J + sj, 0, lognc)] + w1 * e[cell_index<DIM>(I + si, J + sj, 0, lognc)];
-    v = w0 * a0 + w1 * a1;
+  const int mask = (1 << logn) - 1, maskc = (1 << lognc) - 1;
+  const int qlog = logn - 2;
+  const int i0 = (t & ((1 << qlog) - 1)) << 2;
+  const int row = t >> qlog;
+  const int j = row & mask;
+  const int k = DIM == 3 ? (row >> logn) : 0;
+  const int J = j >> 1, K = k >> 1;
+  const int sj = (j & 1) ? 1 : -1, sk = (k & 1) ? 1 : -1;
+  const int I0 = i0 >> 1;
+  const T w0 = T(0.75), w1 = T(0.25);
+  T a[4][4];  // [coarse row: (J,K), (J+sj,K), (J,K+sk), (J+sj,K+sk)][fine cell]
+#pragma unroll
+  for (int r = 0; r < (DIM == 3 ? 4 : 2); ++r) {
+    const int Jr = J + ((r & 1) ? sj : 0), Kr = K + ((r & 2) ? sk : 0);
+    const int ro = ((Jr & maskc) + ((Kr & maskc) << lognc)) << lognc;
+    const Pair<T> p = *reinterpret_cast<const Pair<T>*>(e + ro + I0);
+    const T em = e[ro + ((I0 - 1) & maskc)], ep = e[ro + ((I0 + 2) & maskc)];
+    a[r][0] = w0 * p.v[0] + w1 * em;
+    a[r][1] = w0 * p.v[0] + w1 * p.v[1];
+    a[r][2] = w0 * p.v[1] + w1 * p.v[0];
+    a[r][3] = w0 * p.v[1] + w1 * ep;
   }
-  x[c] += v;
+  Quad<T> xq = *reinterpret_cast<const Quad<T>*>(x + (row << logn) + i0);
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    T v;
+    if (DIM == 3) {
+      const T b0 = w0 * a[0][u] + w1 * a[1][u];
+      const T b1 = w0 * a[2][u] + w1 * a[3][u];
+      v = w0 * b0 + w1 * b1;
+    } else {
+      v = w0 * a[0][u] + w1 * a[1][u];
+    }
+    xq.v[u] += v;
+  }
+  *reinterpret_cast<Quad<T>*>(x + (row << logn) + i0) = xq;
 }
 
 // ---------------------------------------------------------------- one-workgroup tail
@@ -616,11 +682,11 @@ void MGHier<T>::vcycle(int nf, const T* b, T* x, double c0, double c1, int nu_pr
       for (int color = 0; color < 2; ++color) rb_half(xl, bl, lg, nf, tc0, cl, color, l == 0, s);
     const int64_t Cc = Cl >> dim;
     if (three)
-      hipLaunchKernelGGL((k_resid_restrict<T, 3>), dim3(nblk(Cc), nf), dim3(256), 0, s, xl, bl, bufs_b[l + 1], lg,
-                         tc0, cl);
+      hipLaunchKernelGGL((k_resid_restrict<T, 3>), dim3(nblk(Cc / 2), nf), dim3(256), 0, s, xl, bl, bufs_b[l + 1],
+                         lg, tc0, cl);
     else
-      hipLaunchKernelGGL((k_resid_restrict<T, 2>), dim3(nblk(Cc), nf), dim3(256), 0, s, xl, bl, bufs_b[l + 1], lg,
-                         tc0, cl);
+      hipLaunchKernelGGL((k_resid_restrict<T, 2>), dim3(nblk(Cc / 2), nf), dim3(256), 0, s, xl, bl, bufs_b[l + 1],
+                         lg, tc0, cl);
     cl = cl * T(0.25);
   }
   {
@@ -640,9 +706,9 @@ void MGHier<T>::vcycle(int nf, const T* b, T* x, double c0, double c1, int nu_pr
     T* xl = l == 0 ? x : bufs_x[l];
     const T* bl = l == 0 ? b : bufs_b[l];
     if (three)
-      hipLaunchKernelGGL((k_prolong_add<T, 3>), dim3(nblk(Cl), nf), dim3(256), 0, s, xl, bufs_x[l + 1], lg);
+      hipLaunchKernelGGL((k_prolong_add<T, 3>), dim3(nblk(Cl / 4), nf), dim3(256), 0, s, xl, bufs_x[l + 1], lg);
     else
-      hipLaunchKernelGGL((k_prolong_add<T, 2>), dim3(nblk(Cl), nf), dim3(256), 0, s, xl, bufs_x[l + 1], lg);
+      hipLaunchKernelGGL((k_prolong_add<T, 2>), dim3(nblk(Cl / 4), nf), dim3(256), 0, s, xl, bufs_x[l + 1], lg);
     for (int sw = 0; sw < nu_post; ++sw)
       for (int color = 0; color < 2; ++color) rb_half(xl, bl, lg, nf, tc0, cl, color, l == 0, s);
   }
