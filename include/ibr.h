@@ -58,7 +58,7 @@ typedef enum { IBR_PC_LOWER = 0, IBR_PC_FULL = 1 } ibr_pc;
  * <v> = 0).  Sec. 5 defines the solver knobs. */
 typedef struct {
   int dim;            /* 2 or 3 */
-  int n;              /* cells per direction: power of two, 16..1024 (3D: 8..512) */
+  int n;              /* cells per direction: power of two, 2D 16..4096, 3D 8..512 */
   double h;           /* grid spacing (> 0); the box side is n*h */
   double rho;         /* density; 0 = steady Stokes */
   double eta;         /* viscosity (> 0) */
@@ -125,6 +125,12 @@ ibr_status ibr_set_velocities(ibr_ctx* ctx, const double* U, const double* Omega
  * paper's consistency assumption <g> = 0, Sec. 3.4). */
 ibr_status ibr_set_rhs(ibr_ctx* ctx, const double* g, const double* hp);
 
+/* ibr_set_rhs with device pointers (double, same layouts) on the context's
+ * GPU, e.g. the data of torch tensors: the right-hand side never crosses
+ * PCIe.  The copies run on the context's stream and are complete on return.
+ * IBR_EINVAL if a non-NULL pointer is not device memory of that GPU. */
+ibr_status ibr_set_rhs_dev(ibr_ctx* ctx, const void* g, const void* hp);
+
 /* Solve eq. constrained_Stokes (eq. constrained_periodic when steady) by
  * FGMRES with the Schur-complement preconditioner of Sec. 5.1.  warm_start
  * != 0 starts from the context's previous solution.  info may be NULL. */
@@ -139,6 +145,11 @@ ibr_status ibr_step(ibr_ctx* ctx, ibr_info* info);
  * u[dim][n^dim], p[n^dim], lambda[N][dim], F[nb][dim], T[nb][3 or 1]. */
 ibr_status ibr_get_solution(ibr_ctx* ctx, double* u, double* p, double* lambda, double* F,
                             double* T);
+
+/* ibr_get_solution into device arrays of the context's GPU (any may be
+ * NULL), complete on return; IBR_EINVAL if a pointer is not device memory of
+ * that GPU. */
+ibr_status ibr_get_solution_dev(ibr_ctx* ctx, void* u, void* p, void* lambda, void* F, void* T);
 
 /* Current marker positions R[N][dim] and centres X[nb][dim] (they move in ibr_step). */
 ibr_status ibr_get_markers(ibr_ctx* ctx, double* R, double* centres);

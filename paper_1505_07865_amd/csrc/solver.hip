@@ -950,29 +950,82 @@ ibr_status ibr_set_velocities(ibr_ctx* c, const double* U, const double* Omega) 
   });
 }
 
+}  // extern "C"
+
+namespace {
+
+// A caller pointer passed to a device-pointer entry point must be device
+// memory of the context's GPU (hipMalloc'd, e.g. a torch tensor's data).
+void require_device_ptr(const ibr_ctx* c, const void* ptr, const char* what) {
+  if (!ptr) return;
+  hipPointerAttribute_t a;
+  if (hipPointerGetAttributes(&a, ptr) != hipSuccess) {
+    (void)hipGetLastError();
+    throw Status(IBR_EINVAL, std::string(what) + " is not device memory");
+  }
+  if (a.type != hipMemoryTypeDevice || a.device != c->p.device)
+    throw Status(IBR_EINVAL, std::string(what) + " is not device memory of the context's GPU");
+}
+
+void set_rhs_impl(ibr_ctx* c, const double* gh, const double* hp, hipMemcpyKind kind) {
+  require_bodies(c);
+  const int d = c->dim;
+  hipStream_t s = c->stream;
+  IBR_HIP(hipSetDevice(c->p.device));
+  if (gh)
+    IBR_HIP(hipMemcpyAsync(c->Bs, gh, (size_t)d * c->C * sizeof(double), kind, s));
+  else
+    launch_fill<double>(c->Bs, (int64_t)d * c->C, 0.0, s);
+  if (hp)
+    IBR_HIP(hipMemcpyAsync(c->Bs + (int64_t)d * c->C, hp, (size_t)c->C * sizeof(double), kind, s));
+  else
+    launch_fill<double>(c->Bs + (int64_t)d * c->C, c->C, 0.0, s);
+  // consistency: <h> = 0 always, <g> = 0 for periodic steady Stokes (Sec. 3.4)
+  launch_field_means<double>(c->Bs + (int64_t)d * c->C, 1, c->C, c->mpart, 256, c->vmean, s);
+  launch_sub_field_mean<double>(c->Bs + (int64_t)d * c->C, 1, c->C, c->vmean, s);
+  if (c->steady) {
+    launch_field_means<double>(c->Bs, d, c->C, c->mpart, 256, c->vmean, s);
+    launch_sub_field_mean<double>(c->Bs, d, c->C, c->vmean, s);
+  }
+  sync(c);
+}
+
+void get_solution_impl(ibr_ctx* c, double* u, double* pr, double* lambda, double* F, double* T,
+                       hipMemcpyKind kind) {
+  require_bodies(c);
+  IBR_HIP(hipSetDevice(c->p.device));
+  hipStream_t s = c->stream;
+  const int d = c->dim;
+  double* pdev = c->Xs + (int64_t)d * c->C;
+  launch_field_means<double>(pdev, 1, c->C, c->mpart, 256, c->vmean, s);
+  launch_sub_field_mean<double>(pdev, 1, c->C, c->vmean, s);
+  if (u) IBR_HIP(hipMemcpyAsync(u, c->Xs, (size_t)d * c->C * sizeof(double), kind, s));
+  if (pr) IBR_HIP(hipMemcpyAsync(pr, pdev, (size_t)c->C * sizeof(double), kind, s));
+  if (lambda) IBR_HIP(hipMemcpyAsync(lambda, c->Xs + c->NF, (size_t)c->N * d * sizeof(double), kind, s));
+  if (F || T) {
+    const int nt = d == 3 ? 3 : 1;
+    launch_body_force_torque(d, c->nb, c->off_d, c->R, c->X, c->L, c->Xs + c->NF, c->T1, c->T1 + c->nb * 3, s);
+    if (F) IBR_HIP(hipMemcpyAsync(F, c->T1, (size_t)c->nb * d * sizeof(double), kind, s));
+    if (T) IBR_HIP(hipMemcpyAsync(T, c->T1 + c->nb * 3, (size_t)c->nb * nt * sizeof(double), kind, s));
+  }
+  sync(c);
+}
+
+}  // namespace
+
+extern "C" {
+
 ibr_status ibr_set_rhs(ibr_ctx* c, const double* gh, const double* hp) {
   if (!c) return IBR_EINVAL;
+  return guard(c, [&] { set_rhs_impl(c, gh, hp, hipMemcpyHostToDevice); });
+}
+
+ibr_status ibr_set_rhs_dev(ibr_ctx* c, const void* g, const void* hp) {
+  if (!c) return IBR_EINVAL;
   return guard(c, [&] {
-    require_bodies(c);
-    const int d = c->dim;
-    hipStream_t s = c->stream;
-    IBR_HIP(hipSetDevice(c->p.device));
-    if (gh)
-      IBR_HIP(hipMemcpyAsync(c->Bs, gh, (size_t)d * c->C * sizeof(double), hipMemcpyHostToDevice, s));
-    else
-      launch_fill<double>(c->Bs, (int64_t)d * c->C, 0.0, s);
-    if (hp)
-      IBR_HIP(hipMemcpyAsync(c->Bs + (int64_t)d * c->C, hp, (size_t)c->C * sizeof(double), hipMemcpyHostToDevice, s));
-    else
-      launch_fill<double>(c->Bs + (int64_t)d * c->C, c->C, 0.0, s);
-    // consistency: <h> = 0 always, <g> = 0 for periodic steady Stokes (Sec. 3.4)
-    launch_field_means<double>(c->Bs + (int64_t)d * c->C, 1, c->C, c->mpart, 256, c->vmean, s);
-    launch_sub_field_mean<double>(c->Bs + (int64_t)d * c->C, 1, c->C, c->vmean, s);
-    if (c->steady) {
-      launch_field_means<double>(c->Bs, d, c->C, c->mpart, 256, c->vmean, s);
-      launch_sub_field_mean<double>(c->Bs, d, c->C, c->vmean, s);
-    }
-    sync(c);
+    require_device_ptr(c, g, "g");
+    require_device_ptr(c, hp, "h");
+    set_rhs_impl(c, (const double*)g, (const double*)hp, hipMemcpyDeviceToDevice);
   });
 }
 
@@ -1022,26 +1075,19 @@ ibr_status ibr_step(ibr_ctx* c, ibr_info* info) {
 
 ibr_status ibr_get_solution(ibr_ctx* c, double* u, double* pr, double* lambda, double* F, double* T) {
   if (!c) return IBR_EINVAL;
+  return guard(c, [&] { get_solution_impl(c, u, pr, lambda, F, T, hipMemcpyDeviceToHost); });
+}
+
+ibr_status ibr_get_solution_dev(ibr_ctx* c, void* u, void* pr, void* lambda, void* F, void* T) {
+  if (!c) return IBR_EINVAL;
   return guard(c, [&] {
-    require_bodies(c);
-    IBR_HIP(hipSetDevice(c->p.device));
-    hipStream_t s = c->stream;
-    const int d = c->dim;
-    double* pdev = c->Xs + (int64_t)d * c->C;
-    launch_field_means<double>(pdev, 1, c->C, c->mpart, 256, c->vmean, s);
-    launch_sub_field_mean<double>(pdev, 1, c->C, c->vmean, s);
-    if (u) IBR_HIP(hipMemcpyAsync(u, c->Xs, (size_t)d * c->C * sizeof(double), hipMemcpyDeviceToHost, s));
-    if (pr) IBR_HIP(hipMemcpyAsync(pr, pdev, (size_t)c->C * sizeof(double), hipMemcpyDeviceToHost, s));
-    if (lambda)
-      IBR_HIP(hipMemcpyAsync(lambda, c->Xs + c->NF, (size_t)c->N * d * sizeof(double), hipMemcpyDeviceToHost, s));
-    if (F || T) {
-      const int nt = d == 3 ? 3 : 1;
-      launch_body_force_torque(d, c->nb, c->off_d, c->R, c->X, c->L, c->Xs + c->NF, c->T1, c->T1 + c->nb * 3, s);
-      if (F) IBR_HIP(hipMemcpyAsync(F, c->T1, (size_t)c->nb * d * sizeof(double), hipMemcpyDeviceToHost, s));
-      if (T)
-        IBR_HIP(hipMemcpyAsync(T, c->T1 + c->nb * 3, (size_t)c->nb * nt * sizeof(double), hipMemcpyDeviceToHost, s));
-    }
-    sync(c);
+    require_device_ptr(c, u, "u");
+    require_device_ptr(c, pr, "p");
+    require_device_ptr(c, lambda, "lambda");
+    require_device_ptr(c, F, "F");
+    require_device_ptr(c, T, "T");
+    get_solution_impl(c, (double*)u, (double*)pr, (double*)lambda, (double*)F, (double*)T,
+                      hipMemcpyDeviceToDevice);
   });
 }
 

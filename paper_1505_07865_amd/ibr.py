@@ -51,12 +51,36 @@ EXPORTS = ["ibr_default_params", "ibr_status_string", "ibr_create", "ibr_destroy
            "ibr_footprint_bytes", "ibr_set_bodies", "ibr_set_velocities", "ibr_set_rhs", "ibr_solve",
            "ibr_step", "ibr_get_solution", "ibr_get_markers", "ibr_apply_operator", "ibr_spread",
            "ibr_interp", "ibr_vcycle", "ibr_precondition", "ibr_mobility_block", "ibr_advect",
-           "ibr_timer_enable", "ibr_timer_read", "ibr_mobility_inverse"]
+           "ibr_timer_enable", "ibr_timer_read", "ibr_mobility_inverse", "ibr_set_rhs_dev",
+           "ibr_get_solution_dev"]
+
+
+def _devptr(x):
+    """Device address of x: None, an int, or an object with data_ptr() (a
+    float64 contiguous tensor).  The library checks that it is device memory."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    if hasattr(x, "data_ptr"):
+        if str(getattr(x, "dtype", "torch.float64")) != "torch.float64":
+            raise TypeError("device arrays must be float64")
+        if hasattr(x, "is_contiguous") and not x.is_contiguous():
+            raise ValueError("device arrays must be contiguous")
+        return x.data_ptr()
+    raise TypeError("expected a device tensor or address, got %r" % type(x))
 
 
 def load(path=LIB_PATH):
     if not os.path.exists(path):
         raise ImportError("libibr.so not built (run __graft_entry__.build()): %s" % path)
+    # torch ships its own HIP runtime under the same soname; loading torch first
+    # makes the library bind to that copy, so the process has one runtime and
+    # torch's device memory and streams are valid handles for the library
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     P = ctypes.POINTER
     d = ctypes.c_double
@@ -73,9 +97,11 @@ def load(path=LIB_PATH):
         "ibr_set_bodies": (ctypes.c_int, [vp, ctypes.c_int, ip, dp, dp]),
         "ibr_set_velocities": (ctypes.c_int, [vp, dp, dp]),
         "ibr_set_rhs": (ctypes.c_int, [vp, dp, dp]),
+        "ibr_set_rhs_dev": (ctypes.c_int, [vp, vp, vp]),
         "ibr_solve": (ctypes.c_int, [vp, ctypes.c_int, P(Info)]),
         "ibr_step": (ctypes.c_int, [vp, P(Info)]),
         "ibr_get_solution": (ctypes.c_int, [vp, dp, dp, dp, dp, dp]),
+        "ibr_get_solution_dev": (ctypes.c_int, [vp, vp, vp, vp, vp, vp]),
         "ibr_get_markers": (ctypes.c_int, [vp, dp, dp]),
         "ibr_apply_operator": (ctypes.c_int, [vp, dp, dp]),
         "ibr_spread": (ctypes.c_int, [vp, dp, dp]),
@@ -201,6 +227,16 @@ class Solver:
         g = None if g is None else _f64(g)
         hp = None if hp is None else _f64(hp)
         self._check(self._lib.ibr_set_rhs(self._ctx, _dptr(g), _dptr(hp)), "ibr_set_rhs")
+
+    def set_rhs_dev(self, g=None, hp=None):
+        """set_rhs from device arrays: float64 contiguous tensors on the
+        context's GPU (anything with data_ptr()), or raw device addresses."""
+        self._check(self._lib.ibr_set_rhs_dev(self._ctx, _devptr(g), _devptr(hp)), "ibr_set_rhs_dev")
+
+    def solution_dev(self, u=None, p=None, lam=None, F=None, T=None):
+        """Copy the solution into caller-owned device arrays (see set_rhs_dev)."""
+        self._check(self._lib.ibr_get_solution_dev(self._ctx, _devptr(u), _devptr(p), _devptr(lam), _devptr(F),
+                                                   _devptr(T)), "ibr_get_solution_dev")
 
     def solve(self, warm_start=False, check=True):
         info = Info()

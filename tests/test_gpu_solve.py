@@ -174,3 +174,51 @@ def test_graph_replay_matches_stream_launches():
         s.close()
     for a, b in zip(*out):
         assert np.array_equal(a.u, b.u) and np.array_equal(a.lam, b.lam) and np.array_equal(a.p, b.p)
+
+
+def test_device_pointer_rhs_and_solution():
+    """ibr_set_rhs_dev / ibr_get_solution_dev (torch tensors on the GPU) give
+    bitwise the host-pointer results; host memory is rejected."""
+    import torch
+    from paper_1505_07865_amd import ibr
+    prob = small_problem(31, 3, 16, nbodies=2, radius_h=2.5)
+    d, n = prob.dim, prob.n
+    rng = np.random.default_rng(4)
+    g = rng.standard_normal((d,) + (n,) * d)
+    hp = rng.standard_normal((n,) * d)
+    s = ibr.from_problem(prob, rtol=1e-10)
+    s.set_rhs(g, hp)
+    s.solve()
+    a = s.solution()
+    gd = torch.from_numpy(g).cuda()
+    hd = torch.from_numpy(hp).cuda()
+    s.set_rhs(None, None)
+    s.set_rhs_dev(gd, hd)
+    s.solve()
+    u = torch.zeros((d,) + (n,) * d, dtype=torch.float64, device="cuda")
+    p = torch.zeros((n,) * d, dtype=torch.float64, device="cuda")
+    lam = torch.zeros((prob.nmarkers, d), dtype=torch.float64, device="cuda")
+    F = torch.zeros((prob.nbodies, d), dtype=torch.float64, device="cuda")
+    T = torch.zeros((prob.nbodies, 3), dtype=torch.float64, device="cuda")
+    s.solution_dev(u, p, lam, F, T)
+    assert np.array_equal(u.cpu().numpy(), a.u) and np.array_equal(p.cpu().numpy(), a.p)
+    assert np.array_equal(lam.cpu().numpy(), a.lam)
+    assert np.array_equal(F.cpu().numpy(), a.F) and np.array_equal(T.cpu().numpy(), a.T)
+    # the oracle's exact solution of the same system with this fluid forcing
+    sysm = constrained.System.from_problem(prob)
+    V = ib.marker_velocities(prob.R, prob.offsets, prob.centres, prob.U, prob.Omega, prob.L)
+    gm = g - g.reshape(d, -1).mean(axis=1).reshape((d,) + (1,) * d)
+    ex = constrained.solve(sysm, gm, hp - hp.mean(), -V, prob.offsets, prob.centres)
+    assert _rel(a.u, ex.v) < 1e-8 and _rel(a.F, ex.F) < 1e-8
+    with pytest.raises(ibr.IbrError) as e:
+        s.set_rhs_dev(torch.zeros((d,) + (n,) * d, dtype=torch.float64), None)
+    assert e.value.status == 1
+    s.close()
+    # the same solve on a caller's stream (a torch stream at default priority)
+    side = torch.cuda.Stream()
+    s2 = ibr.from_problem(prob, rtol=1e-10, stream=side.cuda_stream)
+    s2.set_rhs_dev(gd, hd)
+    s2.solve()
+    b = s2.solution()
+    assert np.array_equal(a.u, b.u) and np.array_equal(a.lam, b.lam)
+    s2.close()
