@@ -48,6 +48,10 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", choices=["both", "mixed", "fp64"], default="both")
+    ap.add_argument("--serving", action="store_true",
+                    help="serving workload instead: Poisson arrivals of mixed-size steady solves")
+    ap.add_argument("--nreq", type=int, default=2000, help="serving: requests in the trace")
+    ap.add_argument("--workers", type=int, default=4, help="serving: host worker threads")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (scale for the HBM byte counters)")
     return ap.parse_args()
@@ -171,6 +175,55 @@ def cpu_baseline(prob):
                       "single-threaded NumPy" % (sol.cg_iters, dt)}
 
 
+def serving(args, torch):
+    """Serving workload: a seeded trace of independent steady constrained solves
+    (grids 32^2, 128^2, 256^2, 32^3, 64^3, 128^3; 1-8 bodies of radius 4h-8h with
+    markers at ~2h; U, Omega ~ U[-1,1]; rtol 1e-8) offered to the request
+    server, first all at once (saturation: solves/s), then as Poisson arrivals
+    at 0.7 x the measured fp64 capacity (p50/p99 latency, queueing included),
+    for the mixed-precision and the fp64 solver on the same trace."""
+    from paper_1505_07865_amd import serve
+    from synthetic import serving_trace
+    trace = serving_trace(args.seed, args.nreq, 1.0)
+    res = {}
+    for prec in ("fp64", "mixed"):
+        with serve.Server(precision=prec, workers=args.workers) as srv:
+            srv.prewarm([r["problem"] for r in trace])
+            print("bench: serving %s, %d requests at saturation" % (prec, len(trace)), file=sys.stderr,
+                  flush=True)
+            sat = serve.replay(trace, srv, qps=None)
+            res[prec] = {"saturation": {k: v for k, v in sat.items() if k != "results"}}
+            res[prec]["iters_mean"] = sum(r["info"]["iters"] for r in sat["results"]) / len(trace)
+            res[prec]["max_rel_residual"] = max(r["info"]["rel_residual"] for r in sat["results"])
+    qps = 0.7 * res["fp64"]["saturation"]["solves_per_s"]
+    for prec in ("fp64", "mixed"):
+        with serve.Server(precision=prec, workers=args.workers) as srv:
+            srv.prewarm([r["problem"] for r in trace])
+            print("bench: serving %s, Poisson arrivals at %.1f req/s" % (prec, qps), file=sys.stderr, flush=True)
+            lat = serve.replay(trace, srv, qps=qps)
+            res[prec]["at_0.7x_fp64_capacity"] = {k: v for k, v in lat.items() if k != "results"}
+    line = {
+        "metric": "serving: solves/s at saturation and p50/p99 latency at 0.7x fp64 capacity, mixed vs fp64",
+        "value": round(res["mixed"]["saturation"]["solves_per_s"], 3),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "vs_baseline": None,
+        "dtype": "f32 preconditioner + f64 outer",
+        "data": "synthetic",
+        "config": {"workload": "steady constrained solves, seeded Poisson trace of %d requests over grids "
+                               "32^2/128^2/256^2/32^3/64^3/128^3 with 1-8 bodies, rtol 1e-8, %d workers"
+                               % (len(trace), args.workers), "seed": args.seed},
+        "p50_ms": round(res["mixed"]["at_0.7x_fp64_capacity"]["p50_ms"], 3),
+        "p99_ms": round(res["mixed"]["at_0.7x_fp64_capacity"]["p99_ms"], 3),
+        "mixed": res["mixed"],
+        "fp64": res["fp64"],
+        "mixed_over_fp64": round(res["mixed"]["saturation"]["solves_per_s"] /
+                                 res["fp64"]["saturation"]["solves_per_s"], 3),
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -184,6 +237,9 @@ def main():
     torch.cuda.init()
     if args.calibrate_copy:
         calibrate_copy(torch)
+        return
+    if args.serving:
+        serving(args, torch)
         return
     prob = config2_spheres_ns(args.seed, re=args.re)
     precs = ["fp64", "mixed"] if args.precision == "both" else [args.precision]

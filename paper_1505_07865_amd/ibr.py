@@ -263,6 +263,14 @@ class Solver:
                     "ibr_get_solution")
         return Solution(u, p, lam, F, T)
 
+    def forces(self):
+        """Force F[nb][dim] and torque T[nb][3 or 1] on the bodies (no field copies)."""
+        F = np.zeros((self.nb, self.dim))
+        T = np.zeros((self.nb, 3 if self.dim == 3 else 1))
+        self._check(self._lib.ibr_get_solution(self._ctx, None, None, None, _dptr(F), _dptr(T)),
+                    "ibr_get_solution")
+        return F, T
+
     def markers(self):
         R = np.zeros((self.N, self.dim))
         X = np.zeros((self.nb, self.dim))
@@ -341,6 +349,12 @@ def timer_read(kernel):
     if st != 0:
         raise IbrError(st, "ibr_timer_read(%r)" % kernel)
     return {"ms": ms.value, "launches": n.value, "bytes": b.value}
+
+
+def footprint_bytes(nbodies, nmarkers, **params):
+    """Device bytes a context with these parameters and markers would hold."""
+    p = default_params(**params)
+    return int(lib().ibr_footprint_bytes(ctypes.byref(p), int(nbodies), int(nmarkers)))
 
 
 def from_problem(prob, **kw):

@@ -1,0 +1,213 @@
+"""Request server for independent steady constrained solves on one GPU.
+
+A request is one rigid-body problem (grid, bodies, prescribed velocities);
+the answer is the drag force and torque on every body (and the solve report).
+Requests are independent, so the server scales by data parallelism over
+requests: several host worker threads each own resident solver contexts (one
+per grid size, every context with its own HIP stream) and take requests from
+one FIFO queue.  Small grids then overlap with large ones on the GPU, and no
+request pays for allocating or tearing down a context.
+
+Admission: before a worker creates a context it checks the context's device
+footprint (``ibr_footprint_bytes``) against the free device memory minus a
+reserve, evicting its least recently used idle contexts first; a request that
+cannot fit even then fails with MemoryError.
+
+Every solve starts from a zero initial guess, so a request's result does not
+depend on what the context solved before: served alone or in a mix, it is
+bitwise the same.
+"""
+import collections
+import queue
+import threading
+import time
+
+__all__ = ["Server", "replay"]
+
+
+class _Worker(threading.Thread):
+    def __init__(self, server, wid):
+        super().__init__(name="ibr-serve-%d" % wid, daemon=True)
+        self.server = server
+        self.wid = wid
+        self.contexts = collections.OrderedDict()   # (dim, n) -> solver, LRU order
+
+    def _context(self, prob):
+        key = (prob.dim, prob.n)
+        if key in self.contexts:
+            self.contexts.move_to_end(key)
+            return self.contexts[key]
+        srv = self.server
+        need = srv.footprint(prob)
+        while srv.free_bytes() - srv.reserve_bytes < need and self.contexts:
+            _, old = self.contexts.popitem(last=False)
+            old.close()
+        if srv.free_bytes() - srv.reserve_bytes < need:
+            raise MemoryError("request of %d bytes does not fit on the device" % need)
+        s = srv.factory(prob)
+        self.contexts[key] = s
+        return s
+
+    def run(self):
+        srv = self.server
+        while True:
+            item = srv.queue.get()
+            if item is None:
+                break
+            rid, prob, t_arrive, fut = item
+            try:
+                s = self._context(prob)
+                s.set_bodies(prob.R, prob.offsets, prob.centres)
+                s.set_velocities(prob.U, prob.Omega)
+                info = s.solve(warm_start=False)
+                F, T = s.forces()
+                fut._finish(result={"id": rid, "info": info, "F": F, "T": T, "worker": self.wid})
+            except BaseException as e:   # reported through the future
+                fut._finish(error=e)
+        for s in self.contexts.values():
+            s.close()
+        self.contexts.clear()
+
+
+class Future:
+    def __init__(self, t_arrive):
+        self.t_arrive = t_arrive
+        self.t_done = None
+        self._ev = threading.Event()
+        self._result = None
+        self._error = None
+
+    def _finish(self, result=None, error=None):
+        self.t_done = time.perf_counter()
+        self._result = result
+        self._error = error
+        self._ev.set()
+
+    def result(self, timeout=None):
+        if not self._ev.wait(timeout):
+            raise TimeoutError("request not finished")
+        if self._error is not None:
+            raise self._error
+        return self._result
+
+    @property
+    def latency(self):
+        return None if self.t_done is None else self.t_done - self.t_arrive
+
+
+class Server:
+    """FIFO request server over ``workers`` threads with resident contexts.
+
+    factory(problem) -> solver object with set_bodies, set_velocities,
+    solve(warm_start), forces() and close(); the default builds
+    ``ibr.Solver`` contexts for steady Stokes with the given precision.
+    footprint(problem) and free_bytes() default to the library's footprint
+    query and the device's free memory.
+    """
+
+    def __init__(self, precision="mixed", workers=4, rtol=1e-8, device=0, reserve_bytes=8 << 30,
+                 factory=None, footprint=None, free_bytes=None, **solver_kw):
+        self.precision = precision
+        self.rtol = rtol
+        self.device = device
+        self.reserve_bytes = reserve_bytes
+        self.solver_kw = solver_kw
+        self.factory = factory or self._default_factory
+        self.footprint = footprint or self._default_footprint
+        self.free_bytes = free_bytes or self._default_free_bytes
+        self.queue = queue.Queue()
+        self.next_id = 0
+        self.workers = [_Worker(self, w) for w in range(workers)]
+        for w in self.workers:
+            w.start()
+
+    # ---------------------------------------------------------------- defaults
+    def _params(self, prob):
+        from . import ibr
+        return dict(dim=prob.dim, n=prob.n, h=prob.h, rho=0.0, eta=prob.eta, rtol=self.rtol,
+                    precision=ibr.MIXED if self.precision == "mixed" else ibr.FP64, device=self.device,
+                    graphs=0, **self.solver_kw)
+
+    def _default_factory(self, prob):
+        from . import ibr
+        return ibr.Solver(**self._params(prob))
+
+    def _default_footprint(self, prob):
+        from . import ibr
+        return ibr.footprint_bytes(prob.nbodies, prob.nmarkers, **self._params(prob))
+
+    def _default_free_bytes(self):
+        import torch
+        free, _ = torch.cuda.mem_get_info(self.device)
+        return free
+
+    # ---------------------------------------------------------------- requests
+    def submit(self, prob, t_arrive=None):
+        fut = Future(time.perf_counter() if t_arrive is None else t_arrive)
+        self.queue.put((self.next_id, prob, fut.t_arrive, fut))
+        self.next_id += 1
+        return fut
+
+    def close(self):
+        for _ in self.workers:
+            self.queue.put(None)
+        for w in self.workers:
+            w.join()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def prewarm(self, problems):
+        """Give every worker a resident context for each grid size among these
+        problems (created here, with one solve each, before any measured
+        request) so that no measured request pays for a context."""
+        seen = {}
+        for p in problems:
+            seen.setdefault((p.dim, p.n), p)
+        for w in self.workers:
+            for key, p in seen.items():
+                if key not in w.contexts:
+                    s = w._context(p)
+                    s.set_bodies(p.R, p.offsets, p.centres)
+                    s.set_velocities(p.U, p.Omega)
+                    s.solve(warm_start=False)
+
+
+def _percentile(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    k = (len(xs) - 1) * q / 100.0
+    lo = int(k)
+    hi = min(lo + 1, len(xs) - 1)
+    return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
+
+
+def replay(trace, server, qps=None):
+    """Offer the trace's requests at their arrival times scaled to ``qps``
+    (None = all at once, saturation) and wait for all of them.
+
+    trace: list of {"t": arrival time at rate 1, "problem": Problem}.
+    Returns throughput (requests / makespan), p50/p99 latency (arrival to
+    completion, queueing included) and per-request results in trace order.
+    """
+    t0 = time.perf_counter()
+    futs = []
+    for req in trace:
+        if qps is not None:
+            t_arr = t0 + req["t"] / qps
+            dt = t_arr - time.perf_counter()
+            if dt > 0:
+                time.sleep(dt)
+        else:
+            t_arr = t0
+        futs.append(server.submit(req["problem"], t_arrive=t_arr))
+    results = [f.result() for f in futs]
+    t_end = max(f.t_done for f in futs)
+    lat = [f.latency * 1e3 for f in futs]
+    return {"requests": len(trace), "makespan_s": t_end - t0, "solves_per_s": len(trace) / (t_end - t0),
+            "p50_ms": _percentile(lat, 50), "p99_ms": _percentile(lat, 99), "qps_offered": qps,
+            "results": results}

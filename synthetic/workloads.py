@@ -255,7 +255,7 @@ def serving_trace(seed: int = 0, nreq: int = 2000, qps: float = 50.0) -> List[di
         radii_h = rng.uniform(4.0, 8.0, size=nb)
         while True:
             try:
-                centres = sample_centres(rng, radii_h[:nb] * h, 1.0, dim, 4.0 * h, max_tries=2000)
+                centres = sample_centres(rng, radii_h[:nb] * h, 1.0, dim, 4.0 * h, max_tries=200)
                 break
             except RuntimeError:
                 nb -= 1

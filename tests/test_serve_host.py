@@ -1,0 +1,103 @@
+"""Host logic of the request server (queue, resident contexts, admission),
+with stand-in solvers: no GPU needed."""
+import threading
+import time
+from types import SimpleNamespace
+
+import numpy as np
+import pytest
+
+from paper_1505_07865_amd import serve
+
+
+class FakeSolver:
+    created = []
+
+    def __init__(self, prob, delay=0.0):
+        self.key = (prob.dim, prob.n)
+        self.delay = delay
+        self.closed = False
+        self.prob = None
+        FakeSolver.created.append(self)
+
+    def set_bodies(self, R, offsets, centres):
+        self.prob_R = R
+
+    def set_velocities(self, U, Om):
+        self.U = U
+
+    def solve(self, warm_start=False):
+        assert not warm_start
+        time.sleep(self.delay)
+        return {"iters": 1, "rel_residual": 0.0}
+
+    def forces(self):
+        return self.U * 2.0, np.zeros((len(self.U), 1))
+
+    def close(self):
+        self.closed = True
+
+
+def _prob(dim, n, nb=1, u=1.0):
+    return SimpleNamespace(dim=dim, n=n, h=1.0 / n, eta=1.0, nbodies=nb, nmarkers=4 * nb,
+                           R=np.zeros((4 * nb, dim)), offsets=np.arange(0, 4 * nb + 1, 4),
+                           centres=np.zeros((nb, dim)), U=np.full((nb, dim), u),
+                           Omega=np.zeros((nb, 1)))
+
+
+def test_fifo_results_and_resident_contexts():
+    FakeSolver.created = []
+    probs = [_prob(2, 32, u=i) for i in range(10)] + [_prob(3, 16, u=100 + i) for i in range(10)]
+    with serve.Server(workers=2, factory=lambda p: FakeSolver(p), footprint=lambda p: 1,
+                      free_bytes=lambda: 1 << 40, reserve_bytes=0) as srv:
+        futs = [srv.submit(p) for p in probs]
+        res = [f.result(timeout=10) for f in futs]
+    for p, r in zip(probs, res):
+        assert np.array_equal(r["F"], p.U * 2.0)
+    assert [r["id"] for r in res] == list(range(20))
+    # at most one context per (worker, grid size), all closed at shutdown
+    assert len(FakeSolver.created) <= 4
+    assert all(s.closed for s in FakeSolver.created)
+
+
+def test_admission_evicts_lru_then_refuses():
+    FakeSolver.created = []
+    free = {"b": 100}
+    sizes = {(2, 32): 30, (2, 64): 60, (3, 64): 500}
+
+    def factory(p):
+        s = FakeSolver(p)
+        free["b"] -= sizes[(p.dim, p.n)]
+        orig = s.close
+
+        def close():
+            free["b"] += sizes[(p.dim, p.n)]
+            orig()
+        s.close = close
+        return s
+
+    with serve.Server(workers=1, factory=factory, footprint=lambda p: sizes[(p.dim, p.n)],
+                      free_bytes=lambda: free["b"], reserve_bytes=0) as srv:
+        a = srv.submit(_prob(2, 32)).result(timeout=10)
+        b = srv.submit(_prob(2, 64)).result(timeout=10)   # 30 + 60 fit in 100
+        assert free["b"] == 10
+        c = srv.submit(_prob(2, 32)).result(timeout=10)   # resident, no new context
+        assert len(FakeSolver.created) == 2
+        f = srv.submit(_prob(3, 64))                      # 500 never fits: evicts both, then refuses
+        with pytest.raises(MemoryError):
+            f.result(timeout=10)
+        assert free["b"] == 100
+        d = srv.submit(_prob(2, 64)).result(timeout=10)   # still serves afterwards
+    assert a and b and c and d
+
+
+def test_replay_latency_and_throughput():
+    trace = [{"t": 0.01 * i, "problem": _prob(2, 32)} for i in range(20)]
+    with serve.Server(workers=2, factory=lambda p: FakeSolver(p, delay=0.002), footprint=lambda p: 1,
+                      free_bytes=lambda: 1 << 40, reserve_bytes=0) as srv:
+        out = serve.replay(trace, srv, qps=2.0)     # arrivals every 5 ms
+        assert out["requests"] == 20
+        assert out["makespan_s"] >= 0.095 * 0.99
+        assert 0 < out["p50_ms"] <= out["p99_ms"] < 1000
+        sat = serve.replay(trace, srv, qps=None)
+        assert sat["solves_per_s"] > 0
