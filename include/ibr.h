@@ -138,7 +138,8 @@ ibr_status ibr_solve(ibr_ctx* ctx, int warm_start, ibr_info* info);
 
 /* One unsteady step (rho > 0): explicit advection right-hand side
  * (Adams-Bashforth 2, forward Euler on the first step), markers moved by
- * dt U_p, warm-started constrained solve.  Requires Omega == 0. */
+ * dt U_p, constrained solve warm-started from the previous step's solution.
+ * Bodies translate only: IBR_EINVAL if some Omega is nonzero. */
 ibr_status ibr_step(ibr_ctx* ctx, ibr_info* info);
 
 /* Copy the current solution to host arrays (any pointer may be NULL):

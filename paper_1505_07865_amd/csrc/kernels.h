@@ -41,14 +41,26 @@ void timer_end(int id, hipStream_t s, double bytes);
 bool timers_any();  // some timer is enabled
 
 // ---------------------------------------------------------------- grid stencils
+// Cell lattices are in natural storage (x fastest, the public layout) or, with
+// split, in split storage (red half, black half; see split_index in common.h).
 template <typename TI, typename TO>
 void launch_stokes_apply(int dim, int logn, const TI* v, const TI* p, TO* yv, TO* yp, double c0, double ch2,
-                         double inv_h, const double* addc, hipStream_t s);
+                         double inv_h, const double* addc, hipStream_t s, bool split = false);
 template <typename T>
-void launch_div_q(int dim, int logn, const T* v, const T* hp, T* q, double inv_h, hipStream_t s);
+void launch_div_q(int dim, int logn, const T* v, const T* hp, T* q, double inv_h, hipStream_t s,
+                  bool split = false);
 template <typename T>
 void launch_ps_finish(int dim, int logn, T* v, const T* phi, const T* q, T* pi, double h, double c0h2, double eta,
-                      const double* vmean, hipStream_t s);
+                      const double* vmean, hipStream_t s, bool split = false);
+// nf fields: natural -> split storage (with conversion TS -> TD), and back
+template <typename TS, typename TD>
+void launch_to_split(int dim, int logn, const TS* src, TD* dst, int nf, hipStream_t s);
+template <typename TS, typename TD>
+void launch_from_split(int dim, int logn, const TS* src, TD* dst, int nf, hipStream_t s);
+// x (natural, nf fields) = [x +] sum_j y[j] Z_j (split, stride ld)
+template <typename TZ, typename TX>
+void launch_combine_from_split(int dim, int logn, const TZ* Z, int64_t ld, int k, const double* y, TX* x, int nf,
+                               bool assign, hipStream_t s);
 void launch_advect(int dim, int logn, const double* v, double* N, double inv_2h, hipStream_t s);
 void launch_ns_rhs(const double* v, const double* N1, const double* N0, double* g, int64_t len, double rdt,
                    double rho, double w1, double w0, hipStream_t s);
@@ -66,11 +78,11 @@ struct MGHier {
   int dim = 3, logn = 0, nfmax = 0, lds_logn = 0;
   std::vector<int> levels;          // log2 n of the multi-kernel levels (finest first)
   std::vector<T*> bufs_x, bufs_b;   // per level >= 1, nfmax fields each
-  T* tail_b = nullptr;              // global right-hand side of the tail's second level
   void init(int dim, int logn, int nfmax);
   void release();
   static size_t bytes(int dim, int logn, int nf);
-  // One V-cycle for nf fields: x = V(b).  x and b hold nf fields of n^dim.
+  // One V-cycle for nf fields: x = V(b).  x and b hold nf fields of n^dim in
+  // split (red half, black half) storage; see launch_to_split.
   void vcycle(int nf, const T* b, T* x, double c0, double c1, int nu_pre, int nu_post, int nu_coarse,
               hipStream_t s);
   void rb_half(T* x, const T* b, int lg, int nf, T c0, T c1, int color, bool fine, hipStream_t s);
@@ -101,13 +113,14 @@ void launch_bin_markers(int N, int ntiles, const int* tile_of, int* counts, int*
 void launch_active_tiles(int dim, int tiles_log, const int* offsets, int* flags, int* active_list,
                          int* active_count, hipStream_t s);
 
-// y_face[a] += scale * sum_i lam[i][a] * w  over the active tiles.  The grid
+// y_face[a] += scale * sum_i lam[i][a] * w  over the active tiles (y in natural
+// storage, or in split storage with split).  The grid
 // holds grid_cap workgroups per component; the number of active tiles is read
 // on the device from *nactive (<= grid_cap), so the launch needs no host sync.
 template <typename TL, typename TY>
 void launch_spread(int dim, int logn, int tile_log, int grid_cap, const int* active_list, const int* nactive,
                    const int* offsets, const int* perm, MarkerTaps taps, const TL* lam, TY* y, double scale,
-                   hipStream_t s);
+                   hipStream_t s, bool split = false);
 // out[i][a] = alpha * (J v)[i][a] + beta * add[i][a]   (add may be null)
 template <typename TV>
 void launch_interp(int dim, int logn, int N, MarkerTaps taps, const TV* v, double alpha, const double* add,

@@ -36,64 +36,144 @@ __device__ inline Nbr neighbours(int64_t c, int logn) {
   return r;
 }
 
+// Storage policy of a cell lattice: natural (x fastest, the public layout)
+// or split by colour (the preconditioner's private vectors).
+template <int DIM, bool SPLIT>
+struct Lat {
+  int logn;
+  __device__ void coords(int t, int& i, int& j, int& k) const {
+    if (SPLIT) {
+      split_coords<DIM>(t, logn, i, j, k);
+    } else {
+      const int mask = (1 << logn) - 1;
+      i = t & mask;
+      j = (t >> logn) & mask;
+      k = DIM == 3 ? (t >> (2 * logn)) : 0;
+    }
+  }
+  __device__ int index(int i, int j, int k) const {
+    return SPLIT ? split_index<DIM>(i, j, k, logn) : natural_index<DIM>(i, j, k, logn);
+  }
+};
+
 // yv = A v + G p + addc, yp = -D v.   A = c0 I - ch2 L,  G, D with 1/h.
 // TI: storage type of the input, TO: of the output (arithmetic in TO).
-template <typename TI, typename TO, int DIM>
+// One thread per storage position (own values coalesced).
+template <typename TI, typename TO, int DIM, bool SPLIT>
 __global__ void __launch_bounds__(256) k_stokes_apply(const TI* __restrict__ v, const TI* __restrict__ p,
                                                       TO* __restrict__ yv, TO* __restrict__ yp, int logn,
                                                       TO c0, TO ch2, TO inv_h,
                                                       const double* __restrict__ addc) {
   const int64_t C = (int64_t)1 << (DIM * logn);
-  const int64_t c = xcd_block(gridDim.x) * blockDim.x + threadIdx.x;
-  if (c >= C) return;
-  const Nbr nb = neighbours<DIM>(c, logn);
-  const TO pc = (TO)p[c];
+  const int64_t t64 = xcd_block(gridDim.x) * blockDim.x + threadIdx.x;
+  if (t64 >= C) return;
+  const int t = (int)t64;
+  const Lat<DIM, SPLIT> L{logn};
+  int i, j, k;
+  L.coords(t, i, j, k);
+  int m[3], pl[3];
+  m[0] = L.index(i - 1, j, k);
+  pl[0] = L.index(i + 1, j, k);
+  m[1] = L.index(i, j - 1, k);
+  pl[1] = L.index(i, j + 1, k);
+  m[2] = DIM == 3 ? L.index(i, j, k - 1) : t;
+  pl[2] = DIM == 3 ? L.index(i, j, k + 1) : t;
+  const TO pc = (TO)p[t];
   TO div = 0;
 #pragma unroll
   for (int a = 0; a < DIM; ++a) {
     const TI* va = v + a * C;
-    const TO vc = (TO)va[c];
-    TO s = (TO)va[nb.m[0]] + (TO)va[nb.p[0]] + (TO)va[nb.m[1]] + (TO)va[nb.p[1]];
-    if (DIM == 3) s += (TO)va[nb.m[2]] + (TO)va[nb.p[2]];
+    const TO vc = (TO)va[t];
+    TO s = (TO)va[m[0]] + (TO)va[pl[0]] + (TO)va[m[1]] + (TO)va[pl[1]];
+    if (DIM == 3) s += (TO)va[m[2]] + (TO)va[pl[2]];
     const TO lap = s - TO(2 * DIM) * vc;
-    TO out = c0 * vc - ch2 * lap + (pc - (TO)p[nb.m[a]]) * inv_h;
+    TO out = c0 * vc - ch2 * lap + (pc - (TO)p[m[a]]) * inv_h;
     if (addc) out += (TO)addc[a];
-    yv[a * C + c] = out;
-    div += ((TO)va[nb.p[a]] - vc) * inv_h;
+    yv[a * C + t] = out;
+    div += ((TO)va[pl[a]] - vc) * inv_h;
   }
-  yp[c] = -div;
+  yp[t] = -div;
 }
 
 // q = -D v - hp  (hp may be null).
-template <typename T, int DIM>
+template <typename T, int DIM, bool SPLIT>
 __global__ void __launch_bounds__(256) k_div_q(const T* __restrict__ v, const T* __restrict__ hp,
                                                T* __restrict__ q, int logn, T inv_h) {
   const int64_t C = (int64_t)1 << (DIM * logn);
-  const int64_t c = xcd_block(gridDim.x) * blockDim.x + threadIdx.x;
-  if (c >= C) return;
-  const Nbr nb = neighbours<DIM>(c, logn);
+  const int64_t t64 = xcd_block(gridDim.x) * blockDim.x + threadIdx.x;
+  if (t64 >= C) return;
+  const int t = (int)t64;
+  const Lat<DIM, SPLIT> L{logn};
+  int i, j, k;
+  L.coords(t, i, j, k);
+  const int pl[3] = {L.index(i + 1, j, k), L.index(i, j + 1, k), DIM == 3 ? L.index(i, j, k + 1) : t};
   T div = 0;
 #pragma unroll
-  for (int a = 0; a < DIM; ++a) div += (v[a * C + nb.p[a]] - v[a * C + c]) * inv_h;
-  q[c] = -div - (hp ? hp[c] : T(0));
+  for (int a = 0; a < DIM; ++a) div += (v[a * C + pl[a]] - v[a * C + t]) * inv_h;
+  q[t] = -div - (hp ? hp[t] : T(0));
 }
 
 // v <- v - vmean + h (phi_c - phi_{c-e_a});  pi = -c0 h^2 phi + eta q.
-template <typename T, int DIM>
+template <typename T, int DIM, bool SPLIT>
 __global__ void __launch_bounds__(256) k_ps_finish(T* __restrict__ v, const T* __restrict__ phi,
                                                    const T* __restrict__ q, T* __restrict__ pi, int logn,
                                                    T h, T c0h2, T eta, const double* __restrict__ vmean) {
   const int64_t C = (int64_t)1 << (DIM * logn);
-  const int64_t c = xcd_block(gridDim.x) * blockDim.x + threadIdx.x;
-  if (c >= C) return;
-  const Nbr nb = neighbours<DIM>(c, logn);
-  const T ph = phi[c];
+  const int64_t t64 = xcd_block(gridDim.x) * blockDim.x + threadIdx.x;
+  if (t64 >= C) return;
+  const int t = (int)t64;
+  const Lat<DIM, SPLIT> L{logn};
+  int i, j, k;
+  L.coords(t, i, j, k);
+  const int m[3] = {L.index(i - 1, j, k), L.index(i, j - 1, k), DIM == 3 ? L.index(i, j, k - 1) : t};
+  const T ph = phi[t];
 #pragma unroll
   for (int a = 0; a < DIM; ++a) {
-    T m = vmean ? (T)vmean[a] : T(0);
-    v[a * C + c] = v[a * C + c] - m + h * (ph - phi[nb.m[a]]);
+    T mv = vmean ? (T)vmean[a] : T(0);
+    v[a * C + t] = v[a * C + t] - mv + h * (ph - phi[m[a]]);
   }
-  pi[c] = -c0h2 * ph + eta * q[c];
+  pi[t] = -c0h2 * ph + eta * q[t];
+}
+
+// Layout conversions between the public (natural) and the split storage of
+// nf fields; one thread per natural cell.
+template <typename TS, typename TD, int DIM>
+__global__ void __launch_bounds__(256) k_to_split(const TS* __restrict__ src, TD* __restrict__ dst, int logn) {
+  const int64_t C = (int64_t)1 << (DIM * logn);
+  const int64_t c = xcd_block(gridDim.x) * blockDim.x + threadIdx.x;
+  if (c >= C) return;
+  const int64_t f = blockIdx.y;
+  const int mask = (1 << logn) - 1;
+  const int i = (int)c & mask, j = ((int)c >> logn) & mask, k = DIM == 3 ? ((int)c >> (2 * logn)) : 0;
+  dst[f * C + split_index<DIM>(i, j, k, logn)] = (TD)src[f * C + c];
+}
+
+template <typename TS, typename TD, int DIM>
+__global__ void __launch_bounds__(256) k_from_split(const TS* __restrict__ src, TD* __restrict__ dst, int logn) {
+  const int64_t C = (int64_t)1 << (DIM * logn);
+  const int64_t c = xcd_block(gridDim.x) * blockDim.x + threadIdx.x;
+  if (c >= C) return;
+  const int64_t f = blockIdx.y;
+  const int mask = (1 << logn) - 1;
+  const int i = (int)c & mask, j = ((int)c >> logn) & mask, k = DIM == 3 ? ((int)c >> (2 * logn)) : 0;
+  dst[f * C + c] = (TD)src[f * C + split_index<DIM>(i, j, k, logn)];
+}
+
+// x (natural) = [x +] sum_j y[j] Z_j (split), fields f < nf of every Z_j.
+template <typename TZ, typename TX, int DIM>
+__global__ void __launch_bounds__(256) k_combine_from_split(const TZ* __restrict__ Z, int64_t ld, int kk,
+                                                            const double* __restrict__ y, TX* __restrict__ x,
+                                                            int logn, int assign) {
+  const int64_t C = (int64_t)1 << (DIM * logn);
+  const int64_t c = xcd_block(gridDim.x) * blockDim.x + threadIdx.x;
+  if (c >= C) return;
+  const int64_t f = blockIdx.y;
+  const int mask = (1 << logn) - 1;
+  const int i = (int)c & mask, j = ((int)c >> logn) & mask, k = DIM == 3 ? ((int)c >> (2 * logn)) : 0;
+  const int64_t si = f * C + split_index<DIM>(i, j, k, logn);
+  double acc = assign ? 0.0 : (double)x[f * C + c];
+  for (int q = 0; q < kk; ++q) acc += y[q] * (double)Z[(int64_t)q * ld + si];
+  x[f * C + c] = (TX)acc;
 }
 
 // Centred advective term N(v)^a = sum_b vbar^b (v^a_{c+e_b} - v^a_{c-e_b}) / (2h),
@@ -146,49 +226,97 @@ inline unsigned nblk(int64_t len, int bs = 256) { return (unsigned)((len + bs - 
 }  // namespace
 
 template <typename TI, typename TO>
-void launch_stokes_apply(int dim, int logn, const TI* v, const TI* p, TO* yv, TO* yp, double c0,
-                         double ch2, double inv_h, const double* addc, hipStream_t s) {
+void launch_stokes_apply(int dim, int logn, const TI* v, const TI* p, TO* yv, TO* yp, double c0, double ch2,
+                         double inv_h, const double* addc, hipStream_t s, bool split) {
   const int64_t C = (int64_t)1 << (dim * logn);
-  if (dim == 3)
-    hipLaunchKernelGGL((k_stokes_apply<TI, TO, 3>), dim3(nblk(C)), dim3(256), 0, s, v, p, yv, yp, logn, (TO)c0,
-                       (TO)ch2, (TO)inv_h, addc);
-  else
-    hipLaunchKernelGGL((k_stokes_apply<TI, TO, 2>), dim3(nblk(C)), dim3(256), 0, s, v, p, yv, yp, logn, (TO)c0,
-                       (TO)ch2, (TO)inv_h, addc);
+#define IBR_STOKES(D, S)                                                                                       \
+  hipLaunchKernelGGL((k_stokes_apply<TI, TO, D, S>), dim3(nblk(C)), dim3(256), 0, s, v, p, yv, yp, logn, (TO)c0, \
+                     (TO)ch2, (TO)inv_h, addc)
+  if (dim == 3) {
+    if (split) IBR_STOKES(3, true); else IBR_STOKES(3, false);
+  } else {
+    if (split) IBR_STOKES(2, true); else IBR_STOKES(2, false);
+  }
+#undef IBR_STOKES
 }
 template void launch_stokes_apply<double, double>(int, int, const double*, const double*, double*, double*,
-                                                  double, double, double, const double*, hipStream_t);
+                                                  double, double, double, const double*, hipStream_t, bool);
 template void launch_stokes_apply<float, double>(int, int, const float*, const float*, double*, double*,
-                                                 double, double, double, const double*, hipStream_t);
+                                                 double, double, double, const double*, hipStream_t, bool);
 template void launch_stokes_apply<float, float>(int, int, const float*, const float*, float*, float*, double,
-                                                double, double, const double*, hipStream_t);
+                                                double, double, const double*, hipStream_t, bool);
 
 template <typename T>
-void launch_div_q(int dim, int logn, const T* v, const T* hp, T* q, double inv_h, hipStream_t s) {
+void launch_div_q(int dim, int logn, const T* v, const T* hp, T* q, double inv_h, hipStream_t s, bool split) {
   const int64_t C = (int64_t)1 << (dim * logn);
-  if (dim == 3)
-    hipLaunchKernelGGL((k_div_q<T, 3>), dim3(nblk(C)), dim3(256), 0, s, v, hp, q, logn, (T)inv_h);
-  else
-    hipLaunchKernelGGL((k_div_q<T, 2>), dim3(nblk(C)), dim3(256), 0, s, v, hp, q, logn, (T)inv_h);
+#define IBR_DIVQ(D, S) \
+  hipLaunchKernelGGL((k_div_q<T, D, S>), dim3(nblk(C)), dim3(256), 0, s, v, hp, q, logn, (T)inv_h)
+  if (dim == 3) {
+    if (split) IBR_DIVQ(3, true); else IBR_DIVQ(3, false);
+  } else {
+    if (split) IBR_DIVQ(2, true); else IBR_DIVQ(2, false);
+  }
+#undef IBR_DIVQ
 }
-template void launch_div_q<double>(int, int, const double*, const double*, double*, double, hipStream_t);
-template void launch_div_q<float>(int, int, const float*, const float*, float*, double, hipStream_t);
+template void launch_div_q<double>(int, int, const double*, const double*, double*, double, hipStream_t, bool);
+template void launch_div_q<float>(int, int, const float*, const float*, float*, double, hipStream_t, bool);
 
 template <typename T>
 void launch_ps_finish(int dim, int logn, T* v, const T* phi, const T* q, T* pi, double h, double c0h2,
-                      double eta, const double* vmean, hipStream_t s) {
+                      double eta, const double* vmean, hipStream_t s, bool split) {
   const int64_t C = (int64_t)1 << (dim * logn);
-  if (dim == 3)
-    hipLaunchKernelGGL((k_ps_finish<T, 3>), dim3(nblk(C)), dim3(256), 0, s, v, phi, q, pi, logn, (T)h, (T)c0h2,
-                       (T)eta, vmean);
-  else
-    hipLaunchKernelGGL((k_ps_finish<T, 2>), dim3(nblk(C)), dim3(256), 0, s, v, phi, q, pi, logn, (T)h, (T)c0h2,
-                       (T)eta, vmean);
+#define IBR_PSF(D, S)                                                                                          \
+  hipLaunchKernelGGL((k_ps_finish<T, D, S>), dim3(nblk(C)), dim3(256), 0, s, v, phi, q, pi, logn, (T)h, (T)c0h2, \
+                     (T)eta, vmean)
+  if (dim == 3) {
+    if (split) IBR_PSF(3, true); else IBR_PSF(3, false);
+  } else {
+    if (split) IBR_PSF(2, true); else IBR_PSF(2, false);
+  }
+#undef IBR_PSF
 }
 template void launch_ps_finish<double>(int, int, double*, const double*, const double*, double*, double, double,
-                                       double, const double*, hipStream_t);
+                                       double, const double*, hipStream_t, bool);
 template void launch_ps_finish<float>(int, int, float*, const float*, const float*, float*, double, double,
-                                      double, const double*, hipStream_t);
+                                      double, const double*, hipStream_t, bool);
+
+template <typename TS, typename TD>
+void launch_to_split(int dim, int logn, const TS* src, TD* dst, int nf, hipStream_t s) {
+  const int64_t C = (int64_t)1 << (dim * logn);
+  if (dim == 3)
+    hipLaunchKernelGGL((k_to_split<TS, TD, 3>), dim3(nblk(C), nf), dim3(256), 0, s, src, dst, logn);
+  else
+    hipLaunchKernelGGL((k_to_split<TS, TD, 2>), dim3(nblk(C), nf), dim3(256), 0, s, src, dst, logn);
+}
+template void launch_to_split<double, double>(int, int, const double*, double*, int, hipStream_t);
+template void launch_to_split<double, float>(int, int, const double*, float*, int, hipStream_t);
+
+template <typename TS, typename TD>
+void launch_from_split(int dim, int logn, const TS* src, TD* dst, int nf, hipStream_t s) {
+  const int64_t C = (int64_t)1 << (dim * logn);
+  if (dim == 3)
+    hipLaunchKernelGGL((k_from_split<TS, TD, 3>), dim3(nblk(C), nf), dim3(256), 0, s, src, dst, logn);
+  else
+    hipLaunchKernelGGL((k_from_split<TS, TD, 2>), dim3(nblk(C), nf), dim3(256), 0, s, src, dst, logn);
+}
+template void launch_from_split<double, double>(int, int, const double*, double*, int, hipStream_t);
+template void launch_from_split<float, double>(int, int, const float*, double*, int, hipStream_t);
+
+template <typename TZ, typename TX>
+void launch_combine_from_split(int dim, int logn, const TZ* Z, int64_t ld, int k, const double* y, TX* x, int nf,
+                               bool assign, hipStream_t s) {
+  const int64_t C = (int64_t)1 << (dim * logn);
+  if (dim == 3)
+    hipLaunchKernelGGL((k_combine_from_split<TZ, TX, 3>), dim3(nblk(C), nf), dim3(256), 0, s, Z, ld, k, y, x, logn,
+                       assign ? 1 : 0);
+  else
+    hipLaunchKernelGGL((k_combine_from_split<TZ, TX, 2>), dim3(nblk(C), nf), dim3(256), 0, s, Z, ld, k, y, x, logn,
+                       assign ? 1 : 0);
+}
+template void launch_combine_from_split<double, double>(int, int, const double*, int64_t, int, const double*,
+                                                        double*, int, bool, hipStream_t);
+template void launch_combine_from_split<float, float>(int, int, const float*, int64_t, int, const double*, float*,
+                                                      int, bool, hipStream_t);
 
 void launch_advect(int dim, int logn, const double* v, double* N, double inv_2h, hipStream_t s) {
   const int64_t C = (int64_t)1 << (dim * logn);

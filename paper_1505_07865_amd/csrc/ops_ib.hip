@@ -197,7 +197,7 @@ __global__ void k_active_tiles(int dim, int tiles_log, const int* __restrict__ o
 // 4^3 taps (distinct faces) and add into that wavefront's own accumulator.  The
 // four accumulators are summed in a fixed order at the end: no atomics, and
 // the result is bitwise reproducible.  2D uses 16 lanes per marker.
-template <typename TL, typename TY, int DIM>
+template <typename TL, typename TY, int DIM, bool SPLIT>
 __global__ void __launch_bounds__(256) k_spread(int logn, int tile_log, const int* __restrict__ active,
                                                 const int* __restrict__ nactive, const int* __restrict__ off,
                                                 const int* __restrict__ perm, const int* __restrict__ tbase,
@@ -306,7 +306,8 @@ __global__ void __launch_bounds__(256) k_spread(int logn, int tile_log, const in
   for (int q = tid; q < cells; q += 256) {
     const double v = ((acc[0][q] + acc[1][q]) + acc[2][q]) + acc[3][q];
     const int l0 = q & (tsz - 1), l1 = (q >> tile_log) & (tsz - 1), l2 = DIM == 3 ? (q >> (2 * tile_log)) : 0;
-    const int64_t c = (int64_t)(lo[0] + l0) + ((int64_t)(lo[1] + l1) << logn) + ((int64_t)(lo[2] + l2) << (2 * logn));
+    const int64_t c = SPLIT ? (int64_t)split_index<DIM>(lo[0] + l0, lo[1] + l1, lo[2] + l2, logn)
+                            : (int64_t)natural_index<DIM>(lo[0] + l0, lo[1] + l1, lo[2] + l2, logn);
     const int64_t idx = (int64_t)a * C + c;
     y[idx] = (TY)((double)y[idx] + scale * v);
   }
@@ -453,21 +454,24 @@ void launch_active_tiles(int dim, int tiles_log, const int* offsets, int* flags,
 template <typename TL, typename TY>
 void launch_spread(int dim, int logn, int tile_log, int grid_cap, const int* active_list, const int* nactive,
                    const int* offsets, const int* perm, MarkerTaps taps, const TL* lam, TY* y, double scale,
-                   hipStream_t s) {
+                   hipStream_t s, bool split) {
   if (grid_cap <= 0) return;
-  if (dim == 3)
-    hipLaunchKernelGGL((k_spread<TL, TY, 3>), dim3(grid_cap, 3), dim3(256), 0, s, logn, tile_log, active_list,
-                       nactive, offsets, perm, taps.base, taps.w64, lam, y, scale);
-  else
-    hipLaunchKernelGGL((k_spread<TL, TY, 2>), dim3(grid_cap, 2), dim3(256), 0, s, logn, tile_log, active_list,
-                       nactive, offsets, perm, taps.base, taps.w64, lam, y, scale);
+#define IBR_SPREAD(D, S)                                                                                        \
+  hipLaunchKernelGGL((k_spread<TL, TY, D, S>), dim3(grid_cap, D), dim3(256), 0, s, logn, tile_log, active_list, \
+                     nactive, offsets, perm, taps.base, taps.w64, lam, y, scale)
+  if (dim == 3) {
+    if (split) IBR_SPREAD(3, true); else IBR_SPREAD(3, false);
+  } else {
+    if (split) IBR_SPREAD(2, true); else IBR_SPREAD(2, false);
+  }
+#undef IBR_SPREAD
 }
 template void launch_spread<double, double>(int, int, int, int, const int*, const int*, const int*, const int*,
-                                            MarkerTaps, const double*, double*, double, hipStream_t);
+                                            MarkerTaps, const double*, double*, double, hipStream_t, bool);
 template void launch_spread<float, double>(int, int, int, int, const int*, const int*, const int*, const int*,
-                                           MarkerTaps, const float*, double*, double, hipStream_t);
+                                           MarkerTaps, const float*, double*, double, hipStream_t, bool);
 template void launch_spread<double, float>(int, int, int, int, const int*, const int*, const int*, const int*,
-                                           MarkerTaps, const double*, float*, double, hipStream_t);
+                                           MarkerTaps, const double*, float*, double, hipStream_t, bool);
 
 template <typename TV>
 void launch_interp(int dim, int logn, int N, MarkerTaps taps, const TV* v, double alpha, const double* add,

@@ -8,7 +8,9 @@
 // (c0 == 0) lose the mean of the coarsest right-hand side; the finest-level
 // mean of x is removed by the caller.
 //
-// Fine levels run one kernel per step with nfields batched in blockIdx.y.
+// Every level stores its fields split by colour (red half, black half; see
+// the split storage section).  Fine levels run one kernel per step with
+// nfields batched in blockIdx.y.
 // The coarse tail of the cycle runs inside ONE workgroup per field
 // (k_vcycle_lds) with every array of the tail levels in LDS: one launch
 // instead of ~10 per level.  The tail starts at 4096 cells (16^3, 64^2): one
@@ -32,12 +34,6 @@ constexpr int64_t pyramid_cells(int64_t C) {
   int64_t t = 0;
   for (int64_t c = C; c >= (DIM == 3 ? 64 : 16); c >>= DIM) t += c;
   return t;
-}
-// The right-hand sides of tail levels with more cells than this stay in a
-// global scratch array (written and re-read by the same workgroup).
-template <typename T, int DIM>
-constexpr int64_t lds_b_max_cells() {
-  return lds_max_cells<T, DIM>() >> DIM;
 }
 
 // ---------------------------------------------------------------- helpers
@@ -84,255 +80,288 @@ __device__ inline int flat_thread(unsigned nblocks) {
   return (int)xcd_block(nblocks) * (int)blockDim.x + (int)threadIdx.x;
 }
 
-// ---------------------------------------------------------------- fine-level kernels
-// Four consecutive cells of one x-row, loaded and stored as one vector.
+// ---------------------------------------------------------------- split (red/black) storage
+// Every multigrid level stores each field as two halves: the red cells
+// (i+j+k even) first, then the black cells, each half row-major over
+// (row = j + k n, i >> 1).  A half sweep then streams exactly the cells it
+// needs (one colour of x, the other colour's neighbours, one colour of b),
+// with 4-wide vector loads of consecutive same-colour cells.
+//   storage index = colour * C/2 + (row << (logn-1)) + (i >> 1)
+// In a row of parity q = (j+k) & 1 the cell of colour c with half-row index
+// m sits at i = 2m + ((c + q) & 1); its x-neighbours have the other colour
+// (indices m-1, m if c+q is even, m, m+1 otherwise) and its y/z neighbours
+// have the other colour at the same m.
 template <typename T>
 struct alignas(4 * sizeof(T)) Quad {
   T v[4];
 };
-
-// One red-black half sweep.  Each thread owns 4 consecutive cells of an
-// x-row, 2 of them of the colour being updated: the row and its y/z
-// neighbour rows are read as 4-wide vectors, plus the one x-neighbour outside
-// the segment.  The 2 cells of the other colour are written back unchanged
-// (no thread changes them during this half sweep).  FINE marks the finest
-// level (same code; a separate symbol for profiling).  Needs n >= 4.
-template <typename T, int DIM, bool FINE>
-__global__ void __launch_bounds__(256) k_rb(T* __restrict__ x, const T* __restrict__ b, int logn, T c0, T c1,
-                                            int color) {
-  const int C = 1 << (DIM * logn);
-  const int t = flat_thread(gridDim.x);
-  if (t >= (C >> 2)) return;
-  const int64_t f = blockIdx.y;
-  x += f * C;
-  b += f * C;
-  const int mask = (1 << logn) - 1;
-  const int qlog = logn - 2;  // segments per row = n/4
-  const int i0 = (t & ((1 << qlog) - 1)) << 2;
-  const int row = t >> qlog;
-  const int j = row & mask;
-  const int k = DIM == 3 ? (row >> logn) : 0;
-  const int p = (j + k + color) & 1;  // first cell of the colour in the segment
-  const int o = (row << logn) + i0;
-  Quad<T> xc = *reinterpret_cast<const Quad<T>*>(x + o);
-  const Quad<T> bc = *reinterpret_cast<const Quad<T>*>(b + o);
-  const int ry0 = (((j - 1) & mask) + (k << logn)) << logn, ry1 = (((j + 1) & mask) + (k << logn)) << logn;
-  const Quad<T> ym = *reinterpret_cast<const Quad<T>*>(x + ry0 + i0);
-  const Quad<T> yp = *reinterpret_cast<const Quad<T>*>(x + ry1 + i0);
-  Quad<T> zm, zp;
-  if (DIM == 3) {
-    const int rz0 = (j + (((k - 1) & mask) << logn)) << logn, rz1 = (j + (((k + 1) & mask) << logn)) << logn;
-    zm = *reinterpret_cast<const Quad<T>*>(x + rz0 + i0);
-    zp = *reinterpret_cast<const Quad<T>*>(x + rz1 + i0);
-  }
-  // the x-neighbour outside the segment: left of cell 0 or right of cell 3
-  const T ext = x[(row << logn) + ((p == 0 ? i0 - 1 : i0 + 4) & mask)];
-  const T inv_diag = T(1) / (c0 + T(2 * DIM) * c1);
-  // the two cells of the colour are (0, 2) or (1, 3); static indices and a
-  // select keep the four-cell vectors in registers
-  const bool odd = p != 0;
-  const T l0 = odd ? xc.v[0] : ext, r0 = odd ? xc.v[2] : xc.v[1];
-  const T l1 = odd ? xc.v[2] : xc.v[1], r1 = odd ? ext : xc.v[3];
-  T s0 = l0 + r0 + (odd ? ym.v[1] : ym.v[0]) + (odd ? yp.v[1] : yp.v[0]);
-  T s1 = l1 + r1 + (odd ? ym.v[3] : ym.v[2]) + (odd ? yp.v[3] : yp.v[2]);
-  if (DIM == 3) {
-    s0 += (odd ? zm.v[1] : zm.v[0]) + (odd ? zp.v[1] : zp.v[0]);
-    s1 += (odd ? zm.v[3] : zm.v[2]) + (odd ? zp.v[3] : zp.v[2]);
-  }
-  const T n0 = ((odd ? bc.v[1] : bc.v[0]) + c1 * s0) * inv_diag;
-  const T n1 = ((odd ? bc.v[3] : bc.v[2]) + c1 * s1) * inv_diag;
-  xc.v[0] = odd ? xc.v[0] : n0;
-  xc.v[1] = odd ? n0 : xc.v[1];
-  xc.v[2] = odd ? xc.v[2] : n1;
-  xc.v[3] = odd ? n1 : xc.v[3];
-  *reinterpret_cast<Quad<T>*>(x + o) = xc;
-}
-
-// The first red-black sweep from a zero guess in one pass: red cells take
-// b/diag, black cells (all of whose neighbours are red) take
-// (b + c1 * sum of the neighbours' b/diag)/diag.  Same arithmetic, in the same
-// order, as a red then a black half sweep from x = 0.  Four cells of a row
-// per thread, as in k_rb.
-template <typename T, int DIM, bool FINE>
-__global__ void __launch_bounds__(256) k_rb_first(T* __restrict__ x, const T* __restrict__ b, int logn, T c0,
-                                                  T c1) {
-  const int C = 1 << (DIM * logn);
-  const int t = flat_thread(gridDim.x);
-  if (t >= (C >> 2)) return;
-  const int64_t f = blockIdx.y;
-  x += f * C;
-  b += f * C;
-  const int mask = (1 << logn) - 1;
-  const int qlog = logn - 2;
-  const int i0 = (t & ((1 << qlog) - 1)) << 2;
-  const int row = t >> qlog;
-  const int j = row & mask;
-  const int k = DIM == 3 ? (row >> logn) : 0;
-  const int p = (j + k + 1) & 1;  // first black cell of the segment
-  const int o = (row << logn) + i0;
-  const Quad<T> bc = *reinterpret_cast<const Quad<T>*>(b + o);
-  const int ry0 = (((j - 1) & mask) + (k << logn)) << logn, ry1 = (((j + 1) & mask) + (k << logn)) << logn;
-  const Quad<T> ym = *reinterpret_cast<const Quad<T>*>(b + ry0 + i0);
-  const Quad<T> yp = *reinterpret_cast<const Quad<T>*>(b + ry1 + i0);
-  Quad<T> zm, zp;
-  if (DIM == 3) {
-    const int rz0 = (j + (((k - 1) & mask) << logn)) << logn, rz1 = (j + (((k + 1) & mask) << logn)) << logn;
-    zm = *reinterpret_cast<const Quad<T>*>(b + rz0 + i0);
-    zp = *reinterpret_cast<const Quad<T>*>(b + rz1 + i0);
-  }
-  const T ext = b[(row << logn) + ((p == 0 ? i0 - 1 : i0 + 4) & mask)];
-  const T inv_diag = T(1) / (c0 + T(2 * DIM) * c1);
-  // black cells are (0, 2) or (1, 3); static indices and a select keep the
-  // four-cell vectors in registers
-  const bool odd = p != 0;
-  const T l0 = odd ? bc.v[0] : ext, r0 = odd ? bc.v[2] : bc.v[1];
-  const T l1 = odd ? bc.v[2] : bc.v[1], r1 = odd ? ext : bc.v[3];
-  T s0 = l0 * inv_diag + r0 * inv_diag + (odd ? ym.v[1] : ym.v[0]) * inv_diag +
-         (odd ? yp.v[1] : yp.v[0]) * inv_diag;
-  T s1 = l1 * inv_diag + r1 * inv_diag + (odd ? ym.v[3] : ym.v[2]) * inv_diag +
-         (odd ? yp.v[3] : yp.v[2]) * inv_diag;
-  if (DIM == 3) {
-    s0 += (odd ? zm.v[1] : zm.v[0]) * inv_diag + (odd ? zp.v[1] : zp.v[0]) * inv_diag;
-    s1 += (odd ? zm.v[3] : zm.v[2]) * inv_diag + (odd ? zp.v[3] : zp.v[2]) * inv_diag;
-  }
-  const T n0 = ((odd ? bc.v[1] : bc.v[0]) + c1 * s0) * inv_diag;
-  const T n1 = ((odd ? bc.v[3] : bc.v[2]) + c1 * s1) * inv_diag;
-  Quad<T> xo;
-  xo.v[0] = odd ? bc.v[0] * inv_diag : n0;
-  xo.v[1] = odd ? n0 : bc.v[1] * inv_diag;
-  xo.v[2] = odd ? bc.v[2] * inv_diag : n1;
-  xo.v[3] = odd ? n1 : bc.v[3] * inv_diag;
-  *reinterpret_cast<Quad<T>*>(x + o) = xo;
-}
-
 template <typename T>
 struct alignas(2 * sizeof(T)) Pair {
   T v[2];
 };
 
+template <typename T>
+__device__ inline Quad<T> ldq(const T* p) {
+  return *reinterpret_cast<const Quad<T>*>(p);
+}
+template <typename T>
+__device__ inline void stq(T* p, const Quad<T>& q) {
+  *reinterpret_cast<Quad<T>*>(p) = q;
+}
+
+// One red-black half sweep on split storage: each thread updates 4
+// consecutive cells of colour `color` of one row.  FINE marks the finest level
+// (same code; a separate symbol for profiling).  Needs n >= 8.
+template <typename T, int DIM, bool FINE>
+__global__ void __launch_bounds__(256) k_rb(T* __restrict__ x, const T* __restrict__ b, int logn, T c0, T c1,
+                                            int color) {
+  const int C = 1 << (DIM * logn);
+  const int H = C >> 1;
+  const int hl = logn - 1;  // log2 of the half-row length
+  const int t = flat_thread(gridDim.x);
+  if (t >= (H >> 2)) return;
+  const int64_t f = blockIdx.y;
+  x += f * C;
+  b += f * C;
+  const int mask = (1 << logn) - 1, hmask = (1 << hl) - 1;
+  const int m0 = (t & ((1 << (hl - 2)) - 1)) << 2;
+  const int row = t >> (hl - 2);
+  const int j = row & mask;
+  const int k = DIM == 3 ? (row >> logn) : 0;
+  const bool odd = ((color + j + k) & 1) != 0;  // own cells at i = 2m + 1
+  T* own = x + color * H;
+  const T* oth = x + (1 - color) * H;
+  const Quad<T> o = ldq(oth + (row << hl) + m0);
+  const T ext = oth[(row << hl) + ((odd ? m0 + 4 : m0 - 1) & hmask)];
+  const int ry0 = ((j - 1) & mask) | (k << logn), ry1 = ((j + 1) & mask) | (k << logn);
+  const Quad<T> ym = ldq(oth + (ry0 << hl) + m0);
+  const Quad<T> yp = ldq(oth + (ry1 << hl) + m0);
+  Quad<T> zm, zp;
+  if (DIM == 3) {
+    const int rz0 = j | (((k - 1) & mask) << logn), rz1 = j | (((k + 1) & mask) << logn);
+    zm = ldq(oth + (rz0 << hl) + m0);
+    zp = ldq(oth + (rz1 << hl) + m0);
+  }
+  const Quad<T> bc = ldq(b + color * H + (row << hl) + m0);
+  const T inv_diag = T(1) / (c0 + T(2 * DIM) * c1);
+  Quad<T> out;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const T xl = odd ? o.v[u] : (u == 0 ? ext : o.v[u - 1]);
+    const T xr = odd ? (u == 3 ? ext : o.v[u + 1]) : o.v[u];
+    T sum = xl + xr + ym.v[u] + yp.v[u];
+    if (DIM == 3) sum += zm.v[u] + zp.v[u];
+    out.v[u] = (bc.v[u] + c1 * sum) * inv_diag;
+  }
+  stq(own + (row << hl) + m0, out);
+}
+
+// The first red-black sweep from a zero guess in one pass: red cells take
+// b/diag, black cells (all of whose neighbours are red) take
+// (b + c1 * sum of the neighbours' b/diag)/diag.  Same arithmetic, in the same
+// order, as a red then a black half sweep from x = 0.  Each thread writes 4
+// red and 4 black cells of one row.
+template <typename T, int DIM, bool FINE>
+__global__ void __launch_bounds__(256) k_rb_first(T* __restrict__ x, const T* __restrict__ b, int logn, T c0,
+                                                  T c1) {
+  const int C = 1 << (DIM * logn);
+  const int H = C >> 1;
+  const int hl = logn - 1;
+  const int t = flat_thread(gridDim.x);
+  if (t >= (H >> 2)) return;
+  const int64_t f = blockIdx.y;
+  x += f * C;
+  b += f * C;
+  const int mask = (1 << logn) - 1, hmask = (1 << hl) - 1;
+  const int m0 = (t & ((1 << (hl - 2)) - 1)) << 2;
+  const int row = t >> (hl - 2);
+  const int j = row & mask;
+  const int k = DIM == 3 ? (row >> logn) : 0;
+  const bool odd = ((1 + j + k) & 1) != 0;  // black cells at i = 2m + 1
+  const T* bred = b;
+  const T* bblk = b + H;
+  const T inv_diag = T(1) / (c0 + T(2 * DIM) * c1);
+  const Quad<T> rr = ldq(bred + (row << hl) + m0);
+  Quad<T> xr;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) xr.v[u] = rr.v[u] * inv_diag;
+  stq(x + (row << hl) + m0, xr);
+  const T ext = bred[(row << hl) + ((odd ? m0 + 4 : m0 - 1) & hmask)];
+  const int ry0 = ((j - 1) & mask) | (k << logn), ry1 = ((j + 1) & mask) | (k << logn);
+  const Quad<T> ym = ldq(bred + (ry0 << hl) + m0);
+  const Quad<T> yp = ldq(bred + (ry1 << hl) + m0);
+  Quad<T> zm, zp;
+  if (DIM == 3) {
+    const int rz0 = j | (((k - 1) & mask) << logn), rz1 = j | (((k + 1) & mask) << logn);
+    zm = ldq(bred + (rz0 << hl) + m0);
+    zp = ldq(bred + (rz1 << hl) + m0);
+  }
+  const Quad<T> bb = ldq(bblk + (row << hl) + m0);
+  Quad<T> xb;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const T xl = odd ? rr.v[u] : (u == 0 ? ext : rr.v[u - 1]);
+    const T xrr = odd ? (u == 3 ? ext : rr.v[u + 1]) : rr.v[u];
+    T sum = xl * inv_diag + xrr * inv_diag + ym.v[u] * inv_diag + yp.v[u] * inv_diag;
+    if (DIM == 3) sum += zm.v[u] * inv_diag + zp.v[u] * inv_diag;
+    xb.v[u] = (bb.v[u] + c1 * sum) * inv_diag;
+  }
+  stq(x + H + (row << hl) + m0, xb);
+}
+
 // Coarse right-hand side = average over the 2^dim children of the residual
 // r = b - (diag x - c1 sum_nbr x).  Summed over a 2^dim block, each child's
 // neighbour along each axis inside the block is a sibling, so
-//   sum r = sum b - (diag - dim c1) sum x + c1 (sum of the 4^(dim-1) 2 dim
-//           face neighbours outside the block).
-// Each thread makes two coarse cells (four fine cells along x) from 4-wide
-// row vectors.  Needs n >= 4.
+//   sum r = sum b - (diag - dim c1) sum x + c1 (sum of the face neighbours
+//           outside the block).
+// Each thread makes 4 consecutive coarse cells of one coarse row (split
+// storage on both levels): in fine row (2J+dj, 2K+dk) the children 2I and
+// 2I+1 are the two colours at half-row index I.  Needs n >= 8.
 template <typename T, int DIM>
 __global__ void __launch_bounds__(256) k_resid_restrict(const T* __restrict__ x, const T* __restrict__ b,
                                                         T* __restrict__ bc, int logn, T c0, T c1) {
   const int lognc = logn - 1;
-  const int Cc = 1 << (DIM * lognc);
-  const int C = 1 << (DIM * logn);
+  const int C = 1 << (DIM * logn), H = C >> 1, hl = logn - 1;
+  const int Cc = 1 << (DIM * lognc), Hc = Cc >> 1, hlc = lognc - 1;
   const int t = flat_thread(gridDim.x);
-  if (t >= (Cc >> 1)) return;
+  if (t >= (Cc >> 2)) return;
   const int64_t f = blockIdx.y;
   x += f * C;
   b += f * C;
-  const int mask = (1 << logn) - 1;
-  const int qlog = logn - 2;  // coarse-cell pairs per coarse row
-  const int q = t & ((1 << qlog) - 1);
+  const int mask = (1 << logn) - 1, hmask = (1 << hl) - 1, maskc = (1 << lognc) - 1;
+  const int qlog = lognc - 2;  // 4-cell groups per coarse row
+  const int I0 = (t & ((1 << qlog) - 1)) << 2;
   const int rowc = t >> qlog;
-  const int J = rowc & ((1 << lognc) - 1);
+  const int J = rowc & maskc;
   const int K = DIM == 3 ? (rowc >> lognc) : 0;
-  const int i0 = q << 2;
-  T sx0 = 0, sx1 = 0, sb0 = 0, sb1 = 0, sf0 = 0, sf1 = 0;
+  T sx[4] = {0, 0, 0, 0}, sb[4] = {0, 0, 0, 0}, sf[4] = {0, 0, 0, 0};
 #pragma unroll
   for (int dz = 0; dz < (DIM == 3 ? 2 : 1); ++dz)
 #pragma unroll
     for (int dy = 0; dy < 2; ++dy) {
-      const int ro = (((2 * J + dy) & mask) + (((2 * K + dz) & mask) << logn)) << logn;
-      const Quad<T> xq = *reinterpret_cast<const Quad<T>*>(x + ro + i0);
-      const Quad<T> bq = *reinterpret_cast<const Quad<T>*>(b + ro + i0);
-      const T xl = x[ro + ((i0 - 1) & mask)], xr = x[ro + ((i0 + 4) & mask)];
-      sx0 += xq.v[0] + xq.v[1];
-      sx1 += xq.v[2] + xq.v[3];
-      sb0 += bq.v[0] + bq.v[1];
-      sb1 += bq.v[2] + bq.v[3];
-      sf0 += xl + xq.v[2];
-      sf1 += xq.v[1] + xr;
+      const int row = ((2 * J + dy) & mask) | (((2 * K + dz) & mask) << logn);
+      const int ev = (dy + dz) & 1;  // colour of the even children 2I
+      const T* xe = x + ev * H + (row << hl);
+      const T* xo = x + (1 - ev) * H + (row << hl);
+      const Quad<T> A = ldq(xe + I0), B = ldq(xo + I0);
+      const Quad<T> bA = ldq(b + ev * H + (row << hl) + I0), bB = ldq(b + (1 - ev) * H + (row << hl) + I0);
+      const T left = xo[(I0 - 1) & hmask];   // fine 2 I0 - 1: odd child of coarse I0 - 1
+      const T right = xe[(I0 + 4) & hmask];  // fine 2 I0 + 8: even child of coarse I0 + 4
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        sx[u] += A.v[u] + B.v[u];
+        sb[u] += bA.v[u] + bB.v[u];
+        sf[u] += (u == 0 ? left : B.v[u - 1]) + (u == 3 ? right : A.v[u + 1]);
+      }
     }
-  // y faces: rows 2J-1 and 2J+2
+  // y faces: fine rows 2J-1 and 2J+2 (both children of every coarse cell)
 #pragma unroll
   for (int dz = 0; dz < (DIM == 3 ? 2 : 1); ++dz)
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
       const int y = e == 0 ? 2 * J - 1 : 2 * J + 2;
-      const int ro = ((y & mask) + (((2 * K + dz) & mask) << logn)) << logn;
-      const Quad<T> yq = *reinterpret_cast<const Quad<T>*>(x + ro + i0);
-      sf0 += yq.v[0] + yq.v[1];
-      sf1 += yq.v[2] + yq.v[3];
+      const int row = (y & mask) | (((2 * K + dz) & mask) << logn);
+      const Quad<T> P = ldq(x + (row << hl) + I0), Q = ldq(x + H + (row << hl) + I0);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) sf[u] += P.v[u] + Q.v[u];
     }
   if (DIM == 3) {
-    // z faces: planes 2K-1 and 2K+2
 #pragma unroll
     for (int dy = 0; dy < 2; ++dy)
 #pragma unroll
       for (int e = 0; e < 2; ++e) {
         const int z = e == 0 ? 2 * K - 1 : 2 * K + 2;
-        const int ro = (((2 * J + dy) & mask) + ((z & mask) << logn)) << logn;
-        const Quad<T> zq = *reinterpret_cast<const Quad<T>*>(x + ro + i0);
-        sf0 += zq.v[0] + zq.v[1];
-        sf1 += zq.v[2] + zq.v[3];
+        const int row = ((2 * J + dy) & mask) | ((z & mask) << logn);
+        const Quad<T> P = ldq(x + (row << hl) + I0), Q = ldq(x + H + (row << hl) + I0);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) sf[u] += P.v[u] + Q.v[u];
       }
   }
   const T diag = c0 + T(2 * DIM) * c1;
   const T inner = diag - T(DIM) * c1;
   const T avg = DIM == 3 ? T(0.125) : T(0.25);
-  Pair<T> out;
-  out.v[0] = (sb0 - inner * sx0 + c1 * sf0) * avg;
-  out.v[1] = (sb1 - inner * sx1 + c1 * sf1) * avg;
-  *reinterpret_cast<Pair<T>*>(bc + f * Cc + (rowc << lognc) + 2 * q) = out;
+  T r[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) r[u] = (sb[u] - inner * sx[u] + c1 * sf[u]) * avg;
+  // coarse cells I0, I0+2 have colour cp, I0+1, I0+3 the other, at half-row I0/2, I0/2+1
+  const int cp = (J + K) & 1;
+  T* out = bc + f * Cc;
+  const int o = (rowc << hlc) + (I0 >> 1);
+  *reinterpret_cast<Pair<T>*>(out + cp * Hc + o) = Pair<T>{{r[0], r[2]}};
+  *reinterpret_cast<Pair<T>*>(out + (1 - cp) * Hc + o) = Pair<T>{{r[1], r[3]}};
 }
 
-// x += P e (multilinear, cell-centred: weights 3/4 and 1/4 per axis).  Each
-// thread owns four fine cells of an x-row; each of the 2^(dim-1) coarse rows
-// it needs is interpolated along x once (a pair load and two scalars).
+// x += P e (multilinear, cell-centred: weights 3/4 and 1/4 per axis), split
+// storage on both levels.  Each thread owns 8 consecutive fine cells of a row
+// (4 of each colour); each of the 2^(dim-1) coarse rows it needs is
+// interpolated along x once from coarse cells I0-1 .. I0+4 (two pairs and two
+// scalars).  Needs n >= 16.
 template <typename T, int DIM>
 __global__ void __launch_bounds__(256) k_prolong_add(T* __restrict__ x, const T* __restrict__ e, int logn) {
-  const int C = 1 << (DIM * logn);
+  const int C = 1 << (DIM * logn), H = C >> 1, hl = logn - 1;
   const int lognc = logn - 1;
-  const int Cc = 1 << (DIM * lognc);
+  const int Cc = 1 << (DIM * lognc), Hc = Cc >> 1, hlc = lognc - 1;
   const int t = flat_thread(gridDim.x);
-  if (t >= (C >> 2)) return;
+  if (t >= (C >> 3)) return;
   const int64_t f = blockIdx.y;
   x += f * C;
   e += f * Cc;
-  const int mask = (1 << logn) - 1, maskc = (1 << lognc) - 1;
-  const int qlog = logn - 2;
-  const int i0 = (t & ((1 << qlog) - 1)) << 2;
-  const int row = t >> qlog;
+  const int mask = (1 << logn) - 1, maskc = (1 << lognc) - 1, hmaskc = (1 << hlc) - 1;
+  const int glog = logn - 3;  // 8-cell groups per fine row
+  const int g = t & ((1 << glog) - 1);
+  const int row = t >> glog;
   const int j = row & mask;
   const int k = DIM == 3 ? (row >> logn) : 0;
   const int J = j >> 1, K = k >> 1;
   const int sj = (j & 1) ? 1 : -1, sk = (k & 1) ? 1 : -1;
-  const int I0 = i0 >> 1;
+  const int I0 = g << 2;      // first coarse cell; fine cells 2 I0 .. 2 I0 + 7
+  const int mc = I0 >> 1;     // its half-row index
   const T w0 = T(0.75), w1 = T(0.25);
-  T a[4][4];  // [coarse row: (J,K), (J+sj,K), (J,K+sk), (J+sj,K+sk)][fine cell]
+  T a[4][8];  // [coarse row: (J,K), (J+sj,K), (J,K+sk), (J+sj,K+sk)][fine cell]
 #pragma unroll
   for (int r = 0; r < (DIM == 3 ? 4 : 2); ++r) {
-    const int Jr = J + ((r & 1) ? sj : 0), Kr = K + ((r & 2) ? sk : 0);
-    const int ro = ((Jr & maskc) + ((Kr & maskc) << lognc)) << lognc;
-    const Pair<T> p = *reinterpret_cast<const Pair<T>*>(e + ro + I0);
-    const T em = e[ro + ((I0 - 1) & maskc)], ep = e[ro + ((I0 + 2) & maskc)];
-    a[r][0] = w0 * p.v[0] + w1 * em;
-    a[r][1] = w0 * p.v[0] + w1 * p.v[1];
-    a[r][2] = w0 * p.v[1] + w1 * p.v[0];
-    a[r][3] = w0 * p.v[1] + w1 * ep;
-  }
-  Quad<T> xq = *reinterpret_cast<const Quad<T>*>(x + (row << logn) + i0);
+    const int Jr = (J + ((r & 1) ? sj : 0)) & maskc, Kr = (K + ((r & 2) ? sk : 0)) & maskc;
+    const int rowc = Jr | (Kr << lognc);
+    const int cq = (Jr + Kr) & 1;  // colour of the even coarse cells I0, I0+2
+    const T* ee = e + cq * Hc + (rowc << hlc);
+    const T* eo = e + (1 - cq) * Hc + (rowc << hlc);
+    const Pair<T> pe = *reinterpret_cast<const Pair<T>*>(ee + mc);
+    const Pair<T> po = *reinterpret_cast<const Pair<T>*>(eo + mc);
+    T E[6];  // coarse I0-1 .. I0+4
+    E[0] = eo[(mc - 1) & hmaskc];
+    E[1] = pe.v[0];
+    E[2] = po.v[0];
+    E[3] = pe.v[1];
+    E[4] = po.v[1];
+    E[5] = ee[(mc + 2) & hmaskc];
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    T v;
-    if (DIM == 3) {
-      const T b0 = w0 * a[0][u] + w1 * a[1][u];
-      const T b1 = w0 * a[2][u] + w1 * a[3][u];
-      v = w0 * b0 + w1 * b1;
-    } else {
-      v = w0 * a[0][u] + w1 * a[1][u];
+    for (int v = 0; v < 8; ++v) {
+      const int ci = 1 + (v >> 1);  // position of coarse I in E
+      a[r][v] = w0 * E[ci] + w1 * ((v & 1) ? E[ci + 1] : E[ci - 1]);
     }
-    xq.v[u] += v;
   }
-  *reinterpret_cast<Quad<T>*>(x + (row << logn) + i0) = xq;
+  // fine cells 2 I0 + v: colour fp for even v, the other for odd v; half-row index I0 + v/2
+  const int fp = (j + k) & 1;
+  T* xe = x + fp * H + (row << hl) + I0;
+  T* xo = x + (1 - fp) * H + (row << hl) + I0;
+  Quad<T> qe = ldq(xe), qo = ldq(xo);
+#pragma unroll
+  for (int v = 0; v < 8; ++v) {
+    T val;
+    if (DIM == 3) {
+      const T b0 = w0 * a[0][v] + w1 * a[1][v];
+      const T b1 = w0 * a[2][v] + w1 * a[3][v];
+      val = w0 * b0 + w1 * b1;
+    } else {
+      val = w0 * a[0][v] + w1 * a[1][v];
+    }
+    if (v & 1)
+      qo.v[v >> 1] += val;
+    else
+      qe.v[v >> 1] += val;
+  }
+  stq(xe, qe);
+  stq(xo, qo);
 }
 
 // ---------------------------------------------------------------- one-workgroup tail
@@ -419,20 +448,18 @@ __device__ void lds_remove_mean(T* b, int C, T* red) {
   __syncthreads();
 }
 
-// V-cycle from a level of at most lds_max_cells cells down to n = 4, one field
-// per workgroup.  The entry level's b is read from global memory (kept in L2),
-// as are the right-hand sides too large for LDS (bscr, C/2^dim cells per
-// field); every other array of the tail lives in LDS.  c1 is the coefficient
-// at the entry level.
+// V-cycle from a level of at most 4096 cells down to n = 4, one field per
+// workgroup, every array in LDS.  The entry level's b and x are in split
+// storage in global memory and are copied in (natural order) and out.  c1 is
+// the coefficient at the entry level.
 template <typename T, int DIM>
-__global__ void __launch_bounds__(kLdsThreads) k_vcycle_lds(const T* __restrict__ bg, T* __restrict__ xg,
-                                                            T* __restrict__ bscr, int logn, T c0, T c1, int nu_pre,
-                                                            int nu_post, int nu_coarse) {
-  constexpr int64_t kX = pyramid_cells<DIM>(lds_max_cells<T, DIM>()) + 64;
-  constexpr int64_t kB = pyramid_cells<DIM>(lds_b_max_cells<T, DIM>()) + 64;
-  // x of every level back to back (entry level first); b of the levels >= 1 that fit.
+__global__ void __launch_bounds__(kLdsThreads) k_vcycle_lds(const T* __restrict__ bg, T* __restrict__ xg, int logn,
+                                                            T c0, T c1, int nu_pre, int nu_post, int nu_coarse) {
+  constexpr int kMax = (int)lds_max_cells<T, DIM>();
+  constexpr int kX = (int)pyramid_cells<DIM>(kMax) + 64;
+  // x of every level back to back (entry level first); b of every level.
   __shared__ T xs[kX];
-  __shared__ T bs[kB];
+  __shared__ T bs[kX];
   __shared__ T red[kLdsThreads / kWave];
   const int C0 = 1 << (DIM * logn);
   const T* b0 = bg + (int64_t)blockIdx.x * C0;
@@ -440,57 +467,51 @@ __global__ void __launch_bounds__(kLdsThreads) k_vcycle_lds(const T* __restrict_
   const bool singular = c0 == T(0);
 
   const int nlev = logn - 1;  // entry level down to n = 4
-  int xoff[10];
-  T* bptr[10];
+  int off[10];
   {
-    int xo = 0, bo = 0;
+    int o = 0;
     for (int l = 0; l < nlev; ++l) {
-      const int Cl = 1 << (DIM * (logn - l));
-      xoff[l] = xo;
-      xo += Cl;
-      bptr[l] = nullptr;
-      if (l >= 1) {
-        if (Cl <= lds_b_max_cells<T, DIM>()) {
-          bptr[l] = bs + bo;
-          bo += Cl;
-        } else {
-          bptr[l] = bscr + (int64_t)blockIdx.x * Cl;
-        }
-      }
+      off[l] = o;
+      o += 1 << (DIM * (logn - l));
     }
   }
-  auto xlev = [&](int l) -> T* { return xs + xoff[l]; };
+  auto xlev = [&](int l) -> T* { return xs + off[l]; };
+  auto blev = [&](int l) -> T* { return bs + off[l]; };
+  {
+    const int mask = (1 << logn) - 1;
+    for (int c = threadIdx.x; c < C0; c += blockDim.x) {
+      const int i = c & mask, j = (c >> logn) & mask, k = DIM == 3 ? (c >> (2 * logn)) : 0;
+      bs[c] = b0[split_index<DIM>(i, j, k, logn)];
+    }
+    __syncthreads();
+  }
 
-  // The entry level reads b from global memory.
   T cl = c1;
   for (int l = 0; l < nlev - 1; ++l) {
     const int lg = logn - l;
-    const T* bl = l == 0 ? b0 : bptr[l];
-    lds_rb_sweeps<T, DIM>(xlev(l), bl, lg, c0, cl, nu_pre, true);
-    lds_resid_restrict<T, DIM>(xlev(l), bl, bptr[l + 1], lg, c0, cl);
+    lds_rb_sweeps<T, DIM>(xlev(l), blev(l), lg, c0, cl, nu_pre, true);
+    lds_resid_restrict<T, DIM>(xlev(l), blev(l), blev(l + 1), lg, c0, cl);
     cl = cl * T(0.25);
   }
   {
     const int l = nlev - 1;
     const int lg = logn - l;
-    T* bl = bptr[l];
-    if (l == 0) {
-      // whole cycle is the coarsest grid: copy b to LDS first
-      bl = bs;  // C0 <= 64 here
-      for (int c = threadIdx.x; c < C0; c += blockDim.x) bl[c] = b0[c];
-      __syncthreads();
-    }
-    if (singular) lds_remove_mean<T>(bl, 1 << (DIM * lg), red);
-    lds_rb_sweeps<T, DIM>(xlev(l), bl, lg, c0, cl, nu_coarse, true);
+    if (singular) lds_remove_mean<T>(blev(l), 1 << (DIM * lg), red);
+    lds_rb_sweeps<T, DIM>(xlev(l), blev(l), lg, c0, cl, nu_coarse, true);
   }
   for (int l = nlev - 2; l >= 0; --l) {
     cl = cl * T(4);
     const int lg = logn - l;
-    const T* bl = l == 0 ? b0 : bptr[l];
     lds_prolong_add<T, DIM>(xlev(l), xlev(l + 1), lg);
-    lds_rb_sweeps<T, DIM>(xlev(l), bl, lg, c0, cl, nu_post, false);
+    lds_rb_sweeps<T, DIM>(xlev(l), blev(l), lg, c0, cl, nu_post, false);
   }
-  for (int c = threadIdx.x; c < C0; c += blockDim.x) x0[c] = xs[c];
+  {
+    const int mask = (1 << logn) - 1;
+    for (int c = threadIdx.x; c < C0; c += blockDim.x) {
+      const int i = c & mask, j = (c >> logn) & mask, k = DIM == 3 ? (c >> (2 * logn)) : 0;
+      x0[split_index<DIM>(i, j, k, logn)] = xs[c];
+    }
+  }
 }
 
 // Per-field sums: partial[f][block] (deterministic two-pass reduction).
@@ -591,18 +612,12 @@ void MGHier<T>::init(int dim_, int logn_, int maxf) {
     bufs_x[l] = dev_alloc<T>(Cl * nfmax);
     bufs_b[l] = dev_alloc<T>(Cl * nfmax);
   }
-  // right-hand side of the tail's second level when it does not fit in LDS
-  const int64_t bmax = dim == 3 ? lds_b_max_cells<T, 3>() : lds_b_max_cells<T, 2>();
-  const int64_t c1 = lg >= 1 ? (int64_t)1 << (dim * (lg - 1)) : 0;
-  tail_b = c1 > bmax ? dev_alloc<T>(c1 * nfmax) : nullptr;
 }
 
 template <typename T>
 void MGHier<T>::release() {
   for (auto p : bufs_x) dev_free(p);
   for (auto p : bufs_b) dev_free(p);
-  dev_free(tail_b);
-  tail_b = nullptr;
   bufs_x.clear();
   bufs_b.clear();
 }
@@ -614,9 +629,6 @@ size_t MGHier<T>::bytes(int dim, int logn, int nf) {
   int lg = logn;
   while (((int64_t)1 << (dim * lg)) > cap) --lg;
   for (int l = logn - 1; l >= lg; --l) tot += 2 * ((size_t)1 << (dim * l)) * nf * sizeof(T);
-  const int64_t bmax = dim == 3 ? lds_b_max_cells<T, 3>() : lds_b_max_cells<T, 2>();
-  const int64_t c1 = lg >= 1 ? (int64_t)1 << (dim * (lg - 1)) : 0;
-  if (c1 > bmax) tot += (size_t)c1 * nf * sizeof(T);
   return tot;
 }
 
@@ -624,7 +636,7 @@ template <typename T>
 void MGHier<T>::rb_half(T* x, const T* b, int lg, int nf, T c0, T c1, int color, bool fine, hipStream_t s) {
   const int64_t Cl = (int64_t)1 << (dim * lg);
   check_quad_aligned(x, b);
-  const dim3 gh(nblk(Cl / 4), nf);
+  const dim3 gh(nblk(Cl / 8), nf);
   if (fine) timer_begin(kTimerRbFine, s);
   if (dim == 3) {
     if (fine)
@@ -645,7 +657,7 @@ template <typename T>
 void MGHier<T>::rb_first(T* x, const T* b, int lg, int nf, T c0, T c1, bool fine, hipStream_t s) {
   const int64_t Cl = (int64_t)1 << (dim * lg);
   check_quad_aligned(x, b);
-  const dim3 g(nblk(Cl / 4), nf);
+  const dim3 g(nblk(Cl / 8), nf);
   if (fine) timer_begin(kTimerRbFine, s);
   if (dim == 3) {
     if (fine)
@@ -682,10 +694,10 @@ void MGHier<T>::vcycle(int nf, const T* b, T* x, double c0, double c1, int nu_pr
       for (int color = 0; color < 2; ++color) rb_half(xl, bl, lg, nf, tc0, cl, color, l == 0, s);
     const int64_t Cc = Cl >> dim;
     if (three)
-      hipLaunchKernelGGL((k_resid_restrict<T, 3>), dim3(nblk(Cc / 2), nf), dim3(256), 0, s, xl, bl, bufs_b[l + 1],
+      hipLaunchKernelGGL((k_resid_restrict<T, 3>), dim3(nblk(Cc / 4), nf), dim3(256), 0, s, xl, bl, bufs_b[l + 1],
                          lg, tc0, cl);
     else
-      hipLaunchKernelGGL((k_resid_restrict<T, 2>), dim3(nblk(Cc / 2), nf), dim3(256), 0, s, xl, bl, bufs_b[l + 1],
+      hipLaunchKernelGGL((k_resid_restrict<T, 2>), dim3(nblk(Cc / 4), nf), dim3(256), 0, s, xl, bl, bufs_b[l + 1],
                          lg, tc0, cl);
     cl = cl * T(0.25);
   }
@@ -693,11 +705,11 @@ void MGHier<T>::vcycle(int nf, const T* b, T* x, double c0, double c1, int nu_pr
     const T* bl = nml == 0 ? b : bufs_b[nml];
     T* xl = nml == 0 ? x : bufs_x[nml];
     if (three)
-      hipLaunchKernelGGL((k_vcycle_lds<T, 3>), dim3(nf), dim3(kLdsThreads), 0, s, bl, xl, tail_b, lds_logn, tc0, cl,
-                         nu_pre, nu_post, nu_coarse);
+      hipLaunchKernelGGL((k_vcycle_lds<T, 3>), dim3(nf), dim3(kLdsThreads), 0, s, bl, xl, lds_logn, tc0, cl, nu_pre,
+                         nu_post, nu_coarse);
     else
-      hipLaunchKernelGGL((k_vcycle_lds<T, 2>), dim3(nf), dim3(kLdsThreads), 0, s, bl, xl, tail_b, lds_logn, tc0, cl,
-                         nu_pre, nu_post, nu_coarse);
+      hipLaunchKernelGGL((k_vcycle_lds<T, 2>), dim3(nf), dim3(kLdsThreads), 0, s, bl, xl, lds_logn, tc0, cl, nu_pre,
+                         nu_post, nu_coarse);
   }
   for (int l = nml - 1; l >= 0; --l) {
     cl = cl * T(4);
@@ -706,9 +718,9 @@ void MGHier<T>::vcycle(int nf, const T* b, T* x, double c0, double c1, int nu_pr
     T* xl = l == 0 ? x : bufs_x[l];
     const T* bl = l == 0 ? b : bufs_b[l];
     if (three)
-      hipLaunchKernelGGL((k_prolong_add<T, 3>), dim3(nblk(Cl / 4), nf), dim3(256), 0, s, xl, bufs_x[l + 1], lg);
+      hipLaunchKernelGGL((k_prolong_add<T, 3>), dim3(nblk(Cl / 8), nf), dim3(256), 0, s, xl, bufs_x[l + 1], lg);
     else
-      hipLaunchKernelGGL((k_prolong_add<T, 2>), dim3(nblk(Cl / 4), nf), dim3(256), 0, s, xl, bufs_x[l + 1], lg);
+      hipLaunchKernelGGL((k_prolong_add<T, 2>), dim3(nblk(Cl / 8), nf), dim3(256), 0, s, xl, bufs_x[l + 1], lg);
     for (int sw = 0; sw < nu_post; ++sw)
       for (int color = 0; color < 2; ++color) rb_half(xl, bl, lg, nf, tc0, cl, color, l == 0, s);
   }

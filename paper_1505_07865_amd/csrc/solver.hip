@@ -90,6 +90,7 @@ struct ibr_ctx {
   double *Nprev = nullptr, *Ncur = nullptr;
   bool have_prev = false;
   bool have_solution = false;
+  bool rotating = false;  // some body has Omega != 0
 
   // outer Krylov
   int m = 0;
@@ -194,10 +195,10 @@ void ps_inv(ibr_ctx* c, const T* in, T* out) {
     launch_field_means<T>(v, d, C, c->mpart, 256, c->vmean, s);
     vmean = c->vmean;
   }
-  launch_div_q<T>(d, c->logn, v, hp, q, c->inv_h, s);
+  launch_div_q<T>(d, c->logn, v, hp, q, c->inv_h, s, true);
   // L_p phi = q  <=>  (0 - (-1) L) phi = q
   mg.vcycle(1, q, phi, 0.0, -1.0, c->p.mg_pre, c->p.mg_post, c->p.mg_coarse, s);
-  launch_ps_finish<T>(d, c->logn, v, phi, q, pi, c->h, c->c0 * c->h * c->h, c->p.eta, vmean, s);
+  launch_ps_finish<T>(d, c->logn, v, phi, q, pi, c->h, c->c0 * c->h * c->h, c->p.eta, vmean, s, true);
   c->cnt_ps += 1;
   c->cnt_vc += d + 1;
 }
@@ -227,10 +228,10 @@ void inner_gmres(ibr_ctx* c, const T* rhs, T* out) {
       T* Wj = Q + (int64_t)j * NF;
       ps_inv<T>(c, pj, Zj);
       launch_stokes_apply<T, T>(d, c->logn, Zj, Zj + (int64_t)d * c->C, Wj, Wj + (int64_t)d * c->C, c->c0, c->ch2,
-                                c->inv_h, nullptr, s);
+                                c->inv_h, nullptr, s, true);
     }
     launch_gram_solve<T>(Q, NF, ns, rhs, NF, c->part, c->part_blocks, c->yi, s);
-    launch_combine<T, T>(Z, NF, ns, c->yi, out, NF, s, true);
+    launch_combine_from_split<T, T>(d, c->logn, Z, NF, ns, c->yi, out, d + 1, true, s);
     return;
   }
   const int ldh = ns + 1;
@@ -245,7 +246,7 @@ void inner_gmres(ibr_ctx* c, const T* rhs, T* out) {
     T* w = Q + (int64_t)(j + 1) * NF;
     ps_inv<T>(c, Qj, Zj);
     launch_stokes_apply<T, T>(d, c->logn, Zj, Zj + (int64_t)d * c->C, w, w + (int64_t)d * c->C, c->c0, c->ch2,
-                              c->inv_h, nullptr, s);
+                              c->inv_h, nullptr, s, true);
     double* hcol = c->Hi + (int64_t)j * ldh;
     // one Gram-Schmidt pass: the inner solve is only a preconditioner (FGMRES is flexible)
     arnoldi_step<T>(Q, NF, j, hcol, c->hc2i, c->part, c->part2, c->part_blocks, c->flag, s, false, false);
@@ -253,8 +254,7 @@ void inner_gmres(ibr_ctx* c, const T* rhs, T* out) {
     launch_givens_step(c->Hi, ldh, j, c->csi, c->sni, c->gi, c->residi, s);
   }
   launch_lsq_solve(c->Hi, ldh, ns, c->gi, c->yi, s);
-  launch_fill<T>(out, NF, T(0), s);
-  launch_combine<T, T>(Z, NF, ns, c->yi, out, NF, s);
+  launch_combine_from_split<T, T>(d, c->logn, Z, NF, ns, c->yi, out, d + 1, true, s);
 }
 
 // z = P r (Sec. 5.1).  r fp64 stacked; z stacked in T.
@@ -264,7 +264,7 @@ void precondition(ibr_ctx* c, const double* r, T* z) {
   const int d = c->dim;
   const int64_t NF = c->NF;
   T* rhs = (T*)c->rhsT;
-  launch_copy<double, T>(r, rhs, NF, s);
+  launch_to_split<double, T>(d, c->logn, r, rhs, d + 1, s);
   inner_gmres<T>(c, rhs, z);
   // slip dU = -(J v + r_L)
   launch_interp<T>(d, c->logn, c->N, c->taps, z, -1.0, r + NF, -1.0, c->dU, s);
@@ -272,7 +272,7 @@ void precondition(ibr_ctx* c, const double* r, T* z) {
   if (c->p.pc == IBR_PC_FULL) {
     // second fluid solve with r_v + S' Lambda
     launch_spread<double, T>(d, c->logn, c->tile_log, c->act_cap, c->active, c->nactive_d, c->toff, c->perm,
-                             c->taps, c->lamd, rhs, std::pow(c->h, -d), s);
+                             c->taps, c->lamd, rhs, std::pow(c->h, -d), s, true);
     if (c->steady) {
       launch_lambda_sums(d, c->N, c->lamd, c->lsum_part, c->addc, 1.0 / c->vol, s);
       launch_sub_field_mean<T>(rhs, d, c->C, c->addc, s);
@@ -940,8 +940,12 @@ ibr_status ibr_set_velocities(ibr_ctx* c, const double* U, const double* Omega) 
     const int no = d == 3 ? 3 : 1;
     for (int64_t i = 0; i < (int64_t)c->nb * d; ++i)
       if (!std::isfinite(U[i])) throw Status(IBR_EINVAL, "U must be finite");
-    for (int64_t i = 0; i < (int64_t)c->nb * no; ++i)
+    bool rot = false;
+    for (int64_t i = 0; i < (int64_t)c->nb * no; ++i) {
       if (!std::isfinite(Omega[i])) throw Status(IBR_EINVAL, "Omega must be finite");
+      rot = rot || Omega[i] != 0.0;
+    }
+    c->rotating = rot;
     IBR_HIP(hipSetDevice(c->p.device));
     IBR_HIP(hipMemcpyAsync(c->U, U, (size_t)c->nb * d * sizeof(double), hipMemcpyHostToDevice, c->stream));
     IBR_HIP(hipMemcpyAsync(c->Om, Omega, (size_t)c->nb * no * sizeof(double), hipMemcpyHostToDevice, c->stream));
@@ -1049,6 +1053,7 @@ ibr_status ibr_step(ibr_ctx* c, ibr_info* info) {
   ibr_status g = guard(c, [&] {
     require_bodies(c);
     if (c->steady) throw Status(IBR_ESTATE, "ibr_step needs rho > 0 (unsteady)");
+    if (c->rotating) throw Status(IBR_EINVAL, "ibr_step translates the bodies: Omega must be zero");
     IBR_HIP(hipSetDevice(c->p.device));
     hipStream_t s = c->stream;
     const int d = c->dim;
@@ -1162,22 +1167,27 @@ ibr_status ibr_vcycle(ibr_ctx* c, double c0, double c1, int nf, const double* b,
     double* bd = c->Nprev;
     double* xd = c->Ncur;
     IBR_HIP(hipMemcpyAsync(bd, b, (size_t)len * sizeof(double), hipMemcpyHostToDevice, s));
+    // the hierarchy works in split storage: convert in and out
     if (c->mixed) {
       float* bf = (float*)c->Qi;
       float* xf = (float*)c->Zi;
-      launch_copy<double, float>(bd, bf, len, s);
+      launch_to_split<double, float>(c->dim, c->logn, bd, bf, nf, s);
       c->mg32.vcycle(nf, bf, xf, c0, c1, c->p.mg_pre, c->p.mg_post, c->p.mg_coarse, s);
       if (c0 == 0.0) {
         launch_field_means<float>(xf, nf, c->C, c->mpart, 256, c->vmean, s);
         launch_sub_field_mean<float>(xf, nf, c->C, c->vmean, s);
       }
-      launch_copy<float, double>(xf, xd, len, s);
+      launch_from_split<float, double>(c->dim, c->logn, xf, xd, nf, s);
     } else {
-      c->mg64.vcycle(nf, bd, xd, c0, c1, c->p.mg_pre, c->p.mg_post, c->p.mg_coarse, s);
+      double* bs = (double*)c->Qi;
+      double* xs = (double*)c->Zi;
+      launch_to_split<double, double>(c->dim, c->logn, bd, bs, nf, s);
+      c->mg64.vcycle(nf, bs, xs, c0, c1, c->p.mg_pre, c->p.mg_post, c->p.mg_coarse, s);
       if (c0 == 0.0) {
-        launch_field_means<double>(xd, nf, c->C, c->mpart, 256, c->vmean, s);
-        launch_sub_field_mean<double>(xd, nf, c->C, c->vmean, s);
+        launch_field_means<double>(xs, nf, c->C, c->mpart, 256, c->vmean, s);
+        launch_sub_field_mean<double>(xs, nf, c->C, c->vmean, s);
       }
+      launch_from_split<double, double>(c->dim, c->logn, xs, xd, nf, s);
     }
     IBR_HIP(hipMemcpyAsync(x, xd, (size_t)len * sizeof(double), hipMemcpyDeviceToHost, s));
     c->have_prev = false;

@@ -152,8 +152,18 @@ def test_edge_cases():
     with pytest.raises(ibr.IbrError) as e:
         s2.set_bodies(np.array([[np.nan, 0, 0]]), [0, 1], R.copy())
     assert e.value.status == 1
+    # a time step translates the bodies: rotating bodies are refused
+    s3 = ibr.Solver(dim=3, n=16, h=1.0 / 16, rho=1.0, dt=0.01, rtol=1e-10)
+    s3.set_bodies(R, [0, 1], R.copy())
+    s3.set_velocities([[1.0, 0.0, 0.0]], [[0.0, 0.0, 1.0]])
+    with pytest.raises(ibr.IbrError) as e:
+        s3.step()
+    assert e.value.status == 1
+    s3.set_velocities([[1.0, 0.0, 0.0]], [[0.0, 0.0, 0.0]])
+    assert s3.step()["rel_residual"] <= 1e-10
     s.close()
     s2.close()
+    s3.close()
 
 
 def test_graph_replay_matches_stream_launches():
