@@ -71,7 +71,7 @@ typedef struct {
   double rtol;        /* stop when ||b - K x||_2 <= rtol ||b||_2 (default 1e-8) */
   int mg_pre;         /* red-black sweeps before coarsening (default 2) */
   int mg_post;        /* red-black sweeps after prolongation (default 2) */
-  int mg_coarse;      /* red-black sweeps on the 4^dim coarsest grid (default 16) */
+  int mg_coarse;      /* red-black sweeps on the 4^dim coarsest grid (default 4) */
   int device;         /* HIP device ordinal */
   void* stream;       /* hipStream_t to run on, or NULL for a library stream */
   int graphs;         /* 1 (default): replay each outer iteration as a captured

@@ -75,7 +75,7 @@ def prolong(e):
     return out
 
 
-def vcycle(b, c0, c1, nu_pre=2, nu_post=2, nu_coarse=16, _top=True):
+def vcycle(b, c0, c1, nu_pre=2, nu_post=2, nu_coarse=4, _top=True):
     b = np.asarray(b, dtype=np.float64)
     singular = c0 == 0.0
     n = b.shape[0]

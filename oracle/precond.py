@@ -28,7 +28,7 @@ from . import grid, mobility, multigrid, stokes
 class MGParams:
     """V-cycle sweeps; exact=True swaps each V-cycle for the exact periodic solve."""
 
-    def __init__(self, nu_pre=2, nu_post=2, nu_coarse=16, exact=False):
+    def __init__(self, nu_pre=2, nu_post=2, nu_coarse=4, exact=False):
         self.nu_pre = nu_pre
         self.nu_post = nu_post
         self.nu_coarse = nu_coarse

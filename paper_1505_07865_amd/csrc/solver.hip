@@ -740,7 +740,7 @@ void ibr_default_params(ibr_params* p) {
   p->rtol = 1e-8;
   p->mg_pre = 2;
   p->mg_post = 2;
-  p->mg_coarse = 16;
+  p->mg_coarse = 4;
   p->device = 0;
   p->stream = nullptr;
   p->graphs = 1;
