@@ -226,25 +226,36 @@ __global__ void __launch_bounds__(256) k_spread(int logn, int tile_log, const in
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
   const int cells = 1 << (DIM * tile_log);
+  __shared__ int rlen[27];
   for (int q = tid; q < kWaves * kCells; q += 256) (&acc[0][0])[q] = 0.0;
-  if (tid == 0) {
+  {
+    // neighbour tile r (in a fixed order) fetched by thread r
     int cx[3], cy[3], cz[3];
     const int nx = nbr_coords(tc[0], nt, cx);
     const int ny = nbr_coords(tc[1], nt, cy);
     int nz = 1;
     cz[0] = 0;
     if (DIM == 3) nz = nbr_coords(tc[2], nt, cz);
-    int r = 0, tot = 0;
-    for (int a3 = 0; a3 < nz; ++a3)
-      for (int b3 = 0; b3 < ny; ++b3)
-        for (int c3 = 0; c3 < nx; ++c3) {
-          const int tt = cx[c3] | (cy[b3] << tiles_log) | (cz[a3] << (2 * tiles_log));
-          rlo[r] = off[tt];
-          rpre[r] = tot;
-          tot += off[tt + 1] - off[tt];
-          ++r;
-        }
-    for (; r < 28; ++r) rpre[r] = tot;
+    if (tid < 27) {
+      int lo_r = 0, len = 0;
+      if (tid < nx * ny * nz) {
+        const int c3 = tid % nx, b3 = (tid / nx) % ny, a3 = tid / (nx * ny);
+        const int tt = cx[c3] | (cy[b3] << tiles_log) | (cz[a3] << (2 * tiles_log));
+        lo_r = off[tt];
+        len = off[tt + 1] - lo_r;
+      }
+      rlo[tid] = lo_r;
+      rlen[tid] = len;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int tot = 0;
+      for (int r = 0; r < 27; ++r) {
+        rpre[r] = tot;
+        tot += rlen[r];
+      }
+      rpre[27] = tot;
+    }
   }
   __syncthreads();
   const int total = rpre[27];
