@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--precision", choices=["both", "mixed", "fp64"], default="both")
     ap.add_argument("--serving", action="store_true",
                     help="serving workload instead: Poisson arrivals of mixed-size steady solves")
+    ap.add_argument("--ablation", action="store_true",
+                    help="solver study instead: preconditioner variant and N_s vs P_S^-1 applications")
     ap.add_argument("--nreq", type=int, default=2000, help="serving: requests in the trace")
     ap.add_argument("--workers", type=int, default=4, help="serving: host worker threads")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -226,6 +228,61 @@ def serving(args, torch):
     print(json.dumps(line), flush=True)
 
 
+def ablation(args, torch):
+    """The periodic half of the paper's solver study (Sec. 7.1): P_S^-1
+    applications (the paper's cost proxy) and FGMRES iterations to reach
+    relative residual 1e-8 (and 1e-6, 1e-10), for
+      (a) a 162-marker icosahedral shell, empty or filled, in 32^3, steady and
+          one Re = 10 step, N_s in {1, 2, 4, 8}, full and lower-triangular
+          Schur preconditioner;
+      (b) shells of 162 / 642 / 2562 markers in 32^3 / 64^3 / 128^3 (spacing
+          2h), steady, N_s = 4, full and lower-triangular;
+    fp64 and mixed precision, restart 100, with the solve time."""
+    from paper_1505_07865_amd import ibr
+    from synthetic import shell_problem
+    rows = []
+
+    def run(prob, pc, ns, prec, rtol):
+        s = ibr.from_problem(prob, rtol=rtol, pc=ibr.PC_FULL if pc == "full" else ibr.PC_LOWER, n_s=ns,
+                             precision=ibr.MIXED if prec == "mixed" else ibr.FP64, graphs=0, max_iters=2000)
+        s.solve()                      # first solve: warm caches / allocation
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = s.solve()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        s.close()
+        return {"case": prob.name, "markers": int(prob.nmarkers), "pc": pc, "n_s": ns, "precision": prec,
+                "rtol": rtol, "iters": info["iters"], "ps_applications": info["ps_applications"],
+                "rel_residual": info["rel_residual"], "ms": round(ms, 3)}
+
+    for filled in (False, True):
+        for re in (0.0, 10.0):
+            prob = shell_problem(args.seed, 32, 2, filled=filled, re=re)
+            for pc in ("full", "lower"):
+                for ns in (1, 2, 4, 8):
+                    for rtol in (1e-6, 1e-8, 1e-10):
+                        rows.append(run(prob, pc, ns, "fp64", rtol))
+                    rows.append(run(prob, pc, ns, "mixed", 1e-8))
+            print("bench: ablation %s done" % prob.name, file=sys.stderr, flush=True)
+    for level, n in ((2, 32), (3, 64), (4, 128)):
+        prob = shell_problem(args.seed, n, level)
+        for pc in ("full", "lower"):
+            for prec in ("fp64", "mixed"):
+                rows.append(run(prob, pc, 4, prec, 1e-8))
+        print("bench: ablation %s done" % prob.name, file=sys.stderr, flush=True)
+    best = min((r for r in rows if r["case"].startswith("shell_l2_empty_n32_re0") and r["rtol"] == 1e-8 and
+                r["precision"] == "fp64"), key=lambda r: r["ps_applications"])
+    line = {"metric": "P_S^-1 applications to relative residual 1e-8 (solver study, periodic)",
+            "value": best["ps_applications"], "unit": "P_S^-1 applications", "n_gpus": 1,
+            "higher_is_better": False, "vs_baseline": None, "data": "synthetic",
+            "config": {"workload": "icosahedral shells (162/642/2562 markers, spacing 2h, empty or filled), "
+                                   "periodic 32^3/64^3/128^3, steady and Re = 10, restart 100",
+                       "seed": args.seed, "best_case": best},
+            "rows": rows}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -242,6 +299,9 @@ def main():
         return
     if args.serving:
         serving(args, torch)
+        return
+    if args.ablation:
+        ablation(args, torch)
         return
     prob = config2_spheres_ns(args.seed, re=args.re)
     precs = ["fp64", "mixed"] if args.precision == "both" else [args.precision]

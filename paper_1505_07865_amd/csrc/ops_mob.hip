@@ -199,22 +199,81 @@ __global__ void __launch_bounds__(kCholThreads) k_chol(const int* __restrict__ o
   if (threadIdx.x == 0) fail[b] = s_fail;
 }
 
-// X = L^-1 (lower triangular), one workgroup per body, one column per thread.
-__global__ void __launch_bounds__(256) k_tri_inv(const int* __restrict__ off, int dim,
+// X = L^-1 (L lower triangular, 16x16 tiles).  First every diagonal tile is
+// inverted (one wavefront per tile, lane c < 16 solves for column c), then
+// each 16-column block J is filled by block forward substitution,
+//   X_IJ = -X_II sum_{K=J}^{I-1} L_IK X_KJ,   I = J+1, J+2, ...
+// with one workgroup per (J, body): its four wavefronts split the K-sum
+// (fp64 MFMA 16x16x4 tiles) and one of them applies -X_II.
+__global__ void __launch_bounds__(64) k_diag_inv(const int* __restrict__ off, int dim,
                                                  const int64_t* __restrict__ moff, const double* __restrict__ Lf,
                                                  double* __restrict__ X) {
-  const int b = blockIdx.x;
+  const int b = blockIdx.y;
   const int n = dim * (off[b + 1] - off[b]);
   const int ld = pad16(n);
+  const int I = blockIdx.x;
+  if (16 * I >= ld) return;
   const double* L = Lf + moff[b];
   double* Xb = X + moff[b];
-  for (int j = threadIdx.x; j < ld; j += blockDim.x) {
-    for (int i = 0; i < j; ++i) Xb[(int64_t)i * ld + j] = 0.0;
-    for (int i = j; i < ld; ++i) {
-      double s = i == j ? 1.0 : 0.0;
-      for (int k = j; k < i; ++k) s -= L[(int64_t)i * ld + k] * Xb[(int64_t)k * ld + j];
-      Xb[(int64_t)i * ld + j] = s / L[(int64_t)i * ld + i];
+  const int r0 = 16 * I;
+  const int c = threadIdx.x;
+  if (c >= 16) return;
+  double col[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    double v = i == c ? 1.0 : 0.0;
+#pragma unroll
+    for (int k = 0; k < i; ++k) v -= L[(int64_t)(r0 + i) * ld + r0 + k] * col[k];  // col[k] = 0 for k < c
+    col[i] = i < c ? 0.0 : v / L[(int64_t)(r0 + i) * ld + r0 + i];
+  }
+#pragma unroll
+  for (int i = 0; i < 16; ++i) Xb[(int64_t)(r0 + i) * ld + r0 + c] = col[i];
+}
+
+__global__ void __launch_bounds__(256) k_tri_inv_cols(const int* __restrict__ off, int dim,
+                                                      const int64_t* __restrict__ moff,
+                                                      const double* __restrict__ Lf, double* __restrict__ X) {
+  const int b = blockIdx.y;
+  const int n = dim * (off[b + 1] - off[b]);
+  const int ld = pad16(n);
+  const int nt = ld / 16;
+  const int J = blockIdx.x;
+  if (J >= nt) return;
+  const double* L = Lf + moff[b];
+  double* Xb = X + moff[b];
+  __shared__ double part[4][16][17];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wv = threadIdx.x / kWave;
+  const int ci = lane & 15, rq = lane >> 4;
+  const int j0 = 16 * J;
+  for (int I = J + 1; I < nt; ++I) {
+    const int i0 = 16 * I;
+    dvec4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int K = J + wv; K < I; K += 4) {
+      const int k0 = 16 * K;
+#pragma unroll
+      for (int kk = 0; kk < 16; kk += 4) {
+        const double a = L[(int64_t)(i0 + ci) * ld + k0 + kk + rq];
+        const double bb = Xb[(int64_t)(k0 + kk + rq) * ld + j0 + ci];
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc, 0, 0, 0);
+      }
     }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) part[wv][4 * r + rq][ci] = acc[r];
+    __syncthreads();
+    if (wv == 0) {
+      dvec4 res = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int kk = 0; kk < 16; kk += 4) {
+        const double a = -Xb[(int64_t)(i0 + ci) * ld + i0 + kk + rq];
+        const int sr = kk + rq;
+        const double bb = ((part[0][sr][ci] + part[1][sr][ci]) + part[2][sr][ci]) + part[3][sr][ci];
+        res = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, res, 0, 0, 0);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Xb[(int64_t)(i0 + 4 * r + rq) * ld + j0 + ci] = res[r];
+    }
+    __syncthreads();
   }
 }
 
@@ -282,8 +341,9 @@ void launch_chol(int nb, const int* offsets, int dim, const int64_t* moff, const
 
 void launch_chol_inverse(int nb, const int* offsets, int dim, const int64_t* moff, double* Lf, double* Minv,
                          double* X, int max_n, hipStream_t s) {
-  hipLaunchKernelGGL(k_tri_inv, dim3(nb), dim3(256), 0, s, offsets, dim, moff, Lf, X);
   const unsigned t = (unsigned)((max_n + 15) / 16);
+  hipLaunchKernelGGL(k_diag_inv, dim3(t, nb), dim3(64), 0, s, offsets, dim, moff, Lf, X);
+  hipLaunchKernelGGL(k_tri_inv_cols, dim3(t, nb), dim3(256), 0, s, offsets, dim, moff, Lf, X);
   hipLaunchKernelGGL(k_xtx, dim3(t, t, nb), dim3(64), 0, s, offsets, dim, moff, X, Minv);
 }
 

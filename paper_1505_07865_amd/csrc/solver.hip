@@ -34,7 +34,7 @@ constexpr double kPeriodic3D = 2.84;
 constexpr double kPivotTol = 1e-8;
 constexpr double kShifts[] = {0.0, 0.02, 0.05, 0.1, 0.15, 0.2, 0.3, 0.4, 0.5, 0.7, 1.0, 1.5, 2.0, 3.0, 5.0, 10.0};
 constexpr int kNumShifts = sizeof(kShifts) / sizeof(kShifts[0]);
-constexpr int kMaxBlockRows = 3072;
+constexpr int kMaxBlockRows = 8192;
 
 int ilog2(int n) {
   int l = 0;

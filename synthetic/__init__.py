@@ -17,4 +17,7 @@ from .workloads import (  # noqa: F401
     config4_spheres256,
     small_problem,
     serving_trace,
+    icosphere_unit,
+    icosphere_spacing,
+    shell_problem,
 )

@@ -80,6 +80,44 @@ def fibonacci_sphere(nmark: int, radius: float, centre) -> np.ndarray:
     return pts + np.asarray(centre, dtype=np.float64)[None, :]
 
 
+def icosphere_unit(level: int) -> np.ndarray:
+    """Vertices of the icosahedron with every face split ``level`` times into
+    four (edge midpoints pushed to the unit sphere): 10 * 4^level + 2 points
+    (12, 42, 162, 642, 2562, ...)."""
+    t = (1.0 + math.sqrt(5.0)) / 2.0
+    verts = [(-1, t, 0), (1, t, 0), (-1, -t, 0), (1, -t, 0), (0, -1, t), (0, 1, t), (0, -1, -t), (0, 1, -t),
+             (t, 0, -1), (t, 0, 1), (-t, 0, -1), (-t, 0, 1)]
+    verts = [np.asarray(v, dtype=np.float64) / np.linalg.norm(v) for v in verts]
+    faces = [(0, 11, 5), (0, 5, 1), (0, 1, 7), (0, 7, 10), (0, 10, 11), (1, 5, 9), (5, 11, 4), (11, 10, 2),
+             (10, 7, 6), (7, 1, 8), (3, 9, 4), (3, 4, 2), (3, 2, 6), (3, 6, 8), (3, 8, 9), (4, 9, 5),
+             (2, 4, 11), (6, 2, 10), (8, 6, 7), (9, 8, 1)]
+    for _ in range(level):
+        cache = {}
+
+        def mid(a, b):
+            key = (min(a, b), max(a, b))
+            if key not in cache:
+                m = verts[a] + verts[b]
+                verts.append(m / np.linalg.norm(m))
+                cache[key] = len(verts) - 1
+            return cache[key]
+
+        nf = []
+        for a, b, c in faces:
+            ab, bc, ca = mid(a, b), mid(b, c), mid(c, a)
+            nf += [(a, ab, ca), (b, bc, ab), (c, ca, bc), (ab, bc, ca)]
+        faces = nf
+    return np.asarray(verts)
+
+
+def icosphere_spacing(level: int) -> float:
+    """Mean nearest-neighbour distance of the unit icosphere of this level."""
+    v = icosphere_unit(level)
+    d = np.sqrt(((v[:, None, :] - v[None, :, :]) ** 2).sum(axis=2))
+    np.fill_diagonal(d, np.inf)
+    return float(d.min(axis=1).mean())
+
+
 def disk_ring(nmark: int, radius: float, centre, phase: float = 0.0) -> np.ndarray:
     """nmark equally spaced points on a circle, starting at angle ``phase``."""
     t = phase + 2.0 * math.pi * np.arange(nmark, dtype=np.float64) / nmark
@@ -232,6 +270,41 @@ def small_problem(seed: int, dim: int, n: int, nbodies: int = 1, radius_h: float
         bodies = [disk_ring(nm, rad, c, rng.uniform(0, 2 * math.pi)) for c in centres]
     return _assemble(dim, n, h, rho, eta, dt, bodies, centres, U, Om, [rad] * nbodies, nsteps,
                      "small_%dd_%d" % (dim, n))
+
+
+def shell_problem(seed: int = 0, n: int = 32, level: int = 2, filled: bool = False, re: float = 0.0,
+                  spacing_h: float = 2.0) -> Problem:
+    """One sphere in a periodic unit cube: an icosahedral shell of
+    10 * 4^level + 2 markers (162 at level 2) with mean marker spacing
+    ``spacing_h`` h, optionally filled with concentric shells of the same
+    spacing (interior shells are golden-angle point sets of round(N (r/R)^2)
+    markers at radii R - 2h, R - 4h, ... and a centre marker when the last
+    radius is below 2h).  Centre ~ U[0,1)^3, U ~ U[-1,1]^3.  re = 0: steady
+    Stokes, eta = 1, Omega ~ U[-1,1]^3; re > 0: one backward-Euler step of
+    the unsteady system, rho = 1, eta = R/re, dt = 0.5h, Omega = 0."""
+    rng = np.random.default_rng(seed)
+    h = 1.0 / n
+    R = spacing_h * h / icosphere_spacing(level)
+    centre = rng.uniform(0.0, 1.0, size=3)
+    shell = icosphere_unit(level)
+    pts = [shell * R + centre]
+    if filled:
+        r = R - spacing_h * h
+        while r > 0.5 * spacing_h * h:
+            pts.append(fibonacci_sphere(max(1, int(round(len(shell) * (r / R) ** 2))), r, centre))
+            r -= spacing_h * h
+        pts.append(centre[None, :].copy())
+    body = np.concatenate(pts, axis=0)
+    U = rng.uniform(-1.0, 1.0, size=(1, 3))
+    if re > 0:
+        rho, eta, dt = 1.0, R / re, 0.5 * h
+        Om = np.zeros((1, 3))
+    else:
+        rho, eta, dt = 0.0, 1.0, 0.0
+        Om = rng.uniform(-1.0, 1.0, size=(1, 3))
+    return _assemble(3, n, h, rho, eta, dt, [body], centre[None, :], U, Om, [R], 0,
+                     "shell_l%d_%s_n%d_re%g" % (level, "filled" if filled else "empty", n, re),
+                     meta={"radius_h": R / h, "markers": len(body)})
 
 
 SERVING_GRIDS = [(2, 32), (2, 128), (2, 256), (3, 32), (3, 64), (3, 128)]
