@@ -6,6 +6,8 @@
 #include <string>
 #include <vector>
 
+#include <hip/hip_ext.h>
+
 #include "common.h"
 
 namespace ibr {
@@ -35,9 +37,14 @@ inline void dev_free(void* p) {
 
 // ---------------------------------------------------------------- live kernel timers
 enum TimerId { kTimerRbFine = 0, kTimerOrthoDot = 1, kTimerOrthoAxpy = 2, kTimerStokes = 3, kTimerCount = 4 };
-bool timer_on(int id);
-void timer_begin(int id, hipStream_t s);
-void timer_end(int id, hipStream_t s, double bytes);
+// A launch of a timed class is sampled (every stride-th one): the sampled launch
+// gets a start and a stop event to pass to hipExtLaunchKernelGGL, which stamps
+// them with the kernel's own start and end; unsampled launches get null events
+// (a plain launch).  bytes: the launch's algorithmic bytes.
+struct TimerEvents {
+  hipEvent_t start = nullptr, stop = nullptr;
+};
+TimerEvents timer_sample(int id, double bytes);
 bool timers_any();  // some timer is enabled
 
 // ---------------------------------------------------------------- grid stencils
@@ -45,7 +52,8 @@ bool timers_any();  // some timer is enabled
 // split, in split storage (red half, black half; see split_index in common.h).
 template <typename TI, typename TO>
 void launch_stokes_apply(int dim, int logn, const TI* v, const TI* p, TO* yv, TO* yp, double c0, double ch2,
-                         double inv_h, const double* addc, hipStream_t s, bool split = false);
+                         double inv_h, const double* addc, hipStream_t s, bool split = false,
+                         TimerEvents ev = TimerEvents());
 template <typename T>
 void launch_div_q(int dim, int logn, const T* v, const T* hp, T* q, double inv_h, hipStream_t s,
                   bool split = false);
@@ -146,13 +154,14 @@ void launch_multi_axpy(const TV* V, int64_t ld, int k, const double* h, TW* w, i
 template <typename T>
 void arnoldi_step(const T* V, int64_t ld, int k, double* hcol, double* h2, double* part1, double* part2,
                   int nblocks, int* flag, hipStream_t s, bool timed = false, bool reorth = true);
-// One delayed-CGS2 Arnoldi step of the outer FGMRES (see ops_krylov.hip):
+// One delayed-CGS2 Arnoldi step of the outer FGMRES (see ops_krylov.hip);
+// basis vectors of length len at stride ld:
 // V_k pending on entry, w = V_{k+1}; afterwards V_k is final, V_{k+1} pending,
 // H column k-1 final and rotated, column k provisional, *resid the estimate.
 // G needs 2(k+2) doubles, coef 2k+2, part 2(k+2)*nblocks.
 template <typename T>
-void dcgs2_step(T* V, int64_t ld, int k, double* H, int ldh, double* G, double* coef, double* part, int nblocks,
-                double* cs, double* sn, double* g, double* resid, hipStream_t s, bool timed);
+void dcgs2_step(T* V, int64_t ld, int64_t len, int k, double* H, int ldh, double* G, double* coef, double* part,
+                int nblocks, double* cs, double* sn, double* g, double* resid, hipStream_t s, bool timed);
 // x += sum_j y[j] Z_j  (Z in TZ, x in TX); with assign, x = sum_j y[j] Z_j
 template <typename TZ, typename TX>
 void launch_combine(const TZ* Z, int64_t ld, int k, const double* y, TX* x, int64_t len, hipStream_t s,

@@ -4,6 +4,8 @@
 //
 // Layout: field f of a vector lives at base + f*C, C = n^dim, x fastest.
 // One thread per cell; blocks are remapped so each XCD walks a contiguous slab.
+#include <type_traits>
+
 #include "kernels.h"
 
 namespace ibr {
@@ -135,6 +137,179 @@ __global__ void __launch_bounds__(256) k_ps_finish(T* __restrict__ v, const T* _
   pi[t] = -c0h2 * ph + eta * q[t];
 }
 
+// ---------------------------------------------------------------- split storage, 4 cells per thread
+// Each thread takes 4 consecutive cells of one colour in one row (split
+// storage, see split_index): its own values and those of its neighbours come
+// as 4-wide vectors of the other colour's rows, plus one x-neighbour beyond
+// the group.  Arithmetic in the same order as the one-cell-per-thread kernels.
+// Needs n >= 8.
+template <typename T>
+struct alignas(4 * sizeof(T)) Q4 {
+  T v[4];
+};
+template <typename T>
+__device__ inline Q4<T> ld4(const T* p) {
+  return *reinterpret_cast<const Q4<T>*>(p);
+}
+template <typename T>
+__device__ inline void st4(T* p, const Q4<T>& q) {
+  *reinterpret_cast<Q4<T>*>(p) = q;
+}
+
+// Offsets of a 4-cell group t (colour c, row (j, k), half-row offset m0) and
+// of the rows and scalars its stencils read.
+template <int DIM>
+struct Group {
+  int H, own, oth, xl, xr, ym, yp, zm, zp;
+  bool odd;  // the group's cells sit at i = 2m + 1
+  __device__ Group(int t, int logn) {
+    const int C = 1 << (DIM * logn);
+    H = C >> 1;
+    const int hl = logn - 1;
+    const int mask = (1 << logn) - 1, hmask = (1 << hl) - 1;
+    const int per_colour = H >> 2;
+    const int c = t >= per_colour ? 1 : 0;
+    const int u = t - c * per_colour;
+    const int m0 = (u & ((1 << (hl - 2)) - 1)) << 2;
+    const int row = u >> (hl - 2);
+    const int j = row & mask;
+    const int k = DIM == 3 ? (row >> logn) : 0;
+    odd = ((c + j + k) & 1) != 0;
+    const int ob = (1 - c) * H;
+    own = c * H + (row << hl) + m0;
+    oth = ob + (row << hl) + m0;
+    xl = ob + (row << hl) + ((m0 - 1) & hmask);
+    xr = ob + (row << hl) + ((m0 + 4) & hmask);
+    ym = ob + ((((j - 1) & mask) | (k << logn)) << hl) + m0;
+    yp = ob + ((((j + 1) & mask) | (k << logn)) << hl) + m0;
+    zm = DIM == 3 ? ob + ((j | (((k - 1) & mask) << logn)) << hl) + m0 : own;
+    zp = DIM == 3 ? ob + ((j | (((k + 1) & mask) << logn)) << hl) + m0 : own;
+  }
+};
+
+// yv = A v + G p, yp = -D v on split storage (the preconditioner's operator).
+template <typename T, int DIM>
+__global__ void __launch_bounds__(256) k_stokes_split4(const T* __restrict__ v, const T* __restrict__ p,
+                                                       T* __restrict__ yv, T* __restrict__ yp, int logn, T c0, T ch2,
+                                                       T inv_h) {
+  const int64_t C = (int64_t)1 << (DIM * logn);
+  const int t = (int)(xcd_block(gridDim.x) * blockDim.x + threadIdx.x);
+  if (t >= (int)(C >> 2)) return;
+  const Group<DIM> g(t, logn);
+  const bool odd = g.odd;
+  const Q4<T> pc = ld4(p + g.own);
+  // p at c - e_a
+  Q4<T> pm[3];
+  {
+    const Q4<T> po = ld4(p + g.oth);
+    const T pe = p[g.xl];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) pm[0].v[u] = odd ? po.v[u] : (u == 0 ? pe : po.v[u - 1]);
+    pm[1] = ld4(p + g.ym);
+    if (DIM == 3) pm[2] = ld4(p + g.zm);
+  }
+  T div[4] = {0, 0, 0, 0};
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) {
+    const T* va = v + a * C;
+    const Q4<T> vc = ld4(va + g.own);
+    const Q4<T> vo = ld4(va + g.oth);
+    const T ve = va[odd ? g.xr : g.xl];
+    const Q4<T> vym = ld4(va + g.ym), vyp = ld4(va + g.yp);
+    Q4<T> vzm, vzp;
+    if (DIM == 3) {
+      vzm = ld4(va + g.zm);
+      vzp = ld4(va + g.zp);
+    }
+    Q4<T> out;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const T xl = odd ? vo.v[u] : (u == 0 ? ve : vo.v[u - 1]);
+      const T xr = odd ? (u == 3 ? ve : vo.v[u + 1]) : vo.v[u];
+      T s = xl + xr + vym.v[u] + vyp.v[u];
+      if (DIM == 3) s += vzm.v[u] + vzp.v[u];
+      const T lap = s - T(2 * DIM) * vc.v[u];
+      out.v[u] = c0 * vc.v[u] - ch2 * lap + (pc.v[u] - pm[a].v[u]) * inv_h;
+      const T vplus = a == 0 ? xr : (a == 1 ? vyp.v[u] : vzp.v[u]);
+      div[u] += (vplus - vc.v[u]) * inv_h;
+    }
+    st4(yv + a * C + g.own, out);
+  }
+  Q4<T> q;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) q.v[u] = -div[u];
+  st4(yp + g.own, q);
+}
+
+// q = -D v - hp on split storage (hp may be null).
+template <typename T, int DIM>
+__global__ void __launch_bounds__(256) k_div_q_split4(const T* __restrict__ v, const T* __restrict__ hp,
+                                                      T* __restrict__ q, int logn, T inv_h) {
+  const int64_t C = (int64_t)1 << (DIM * logn);
+  const int t = (int)(xcd_block(gridDim.x) * blockDim.x + threadIdx.x);
+  if (t >= (int)(C >> 2)) return;
+  const Group<DIM> g(t, logn);
+  const bool odd = g.odd;
+  T div[4] = {0, 0, 0, 0};
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) {
+    const T* va = v + a * C;
+    const Q4<T> vc = ld4(va + g.own);
+    Q4<T> vp;
+    if (a == 0) {
+      const Q4<T> vo = ld4(va + g.oth);
+      const T ve = va[g.xr];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) vp.v[u] = odd ? (u == 3 ? ve : vo.v[u + 1]) : vo.v[u];
+    } else {
+      vp = ld4(va + (a == 1 ? g.yp : g.zp));
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) div[u] += (vp.v[u] - vc.v[u]) * inv_h;
+  }
+  Q4<T> h4 = {{0, 0, 0, 0}};
+  if (hp) h4 = ld4(hp + g.own);
+  Q4<T> out;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) out.v[u] = -div[u] - h4.v[u];
+  st4(q + g.own, out);
+}
+
+// v <- v - vmean + h (phi_c - phi_{c-e_a});  pi = -c0 h^2 phi + eta q, split storage.
+template <typename T, int DIM>
+__global__ void __launch_bounds__(256) k_ps_finish_split4(T* __restrict__ v, const T* __restrict__ phi,
+                                                          const T* __restrict__ q, T* __restrict__ pi, int logn,
+                                                          T h, T c0h2, T eta, const double* __restrict__ vmean) {
+  const int64_t C = (int64_t)1 << (DIM * logn);
+  const int t = (int)(xcd_block(gridDim.x) * blockDim.x + threadIdx.x);
+  if (t >= (int)(C >> 2)) return;
+  const Group<DIM> g(t, logn);
+  const bool odd = g.odd;
+  const Q4<T> ph = ld4(phi + g.own);
+  Q4<T> pm[3];
+  {
+    const Q4<T> po = ld4(phi + g.oth);
+    const T pe = phi[g.xl];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) pm[0].v[u] = odd ? po.v[u] : (u == 0 ? pe : po.v[u - 1]);
+    pm[1] = ld4(phi + g.ym);
+    if (DIM == 3) pm[2] = ld4(phi + g.zm);
+  }
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) {
+    const T mv = vmean ? (T)vmean[a] : T(0);
+    Q4<T> va = ld4(v + a * C + g.own);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) va.v[u] = va.v[u] - mv + h * (ph.v[u] - pm[a].v[u]);
+    st4(v + a * C + g.own, va);
+  }
+  const Q4<T> qq = ld4(q + g.own);
+  Q4<T> out;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) out.v[u] = -c0h2 * ph.v[u] + eta * qq.v[u];
+  st4(pi + g.own, out);
+}
+
 // Layout conversions between the public (natural) and the split storage of
 // nf fields; one thread per natural cell.
 template <typename TS, typename TD, int DIM>
@@ -227,36 +402,63 @@ inline unsigned nblk(int64_t len, int bs = 256) { return (unsigned)((len + bs - 
 
 template <typename TI, typename TO>
 void launch_stokes_apply(int dim, int logn, const TI* v, const TI* p, TO* yv, TO* yp, double c0, double ch2,
-                         double inv_h, const double* addc, hipStream_t s, bool split) {
+                         double inv_h, const double* addc, hipStream_t s, bool split, TimerEvents ev) {
   const int64_t C = (int64_t)1 << (dim * logn);
 #define IBR_STOKES(D, S)                                                                                       \
   hipLaunchKernelGGL((k_stokes_apply<TI, TO, D, S>), dim3(nblk(C)), dim3(256), 0, s, v, p, yv, yp, logn, (TO)c0, \
                      (TO)ch2, (TO)inv_h, addc)
-  if (dim == 3) {
-    if (split) IBR_STOKES(3, true); else IBR_STOKES(3, false);
-  } else {
-    if (split) IBR_STOKES(2, true); else IBR_STOKES(2, false);
+  if (split) {
+    if constexpr (std::is_same<TI, TO>::value) {
+      if (!addc) {
+        if (dim == 3)
+          hipLaunchKernelGGL((k_stokes_split4<TO, 3>), dim3(nblk(C / 4)), dim3(256), 0, s, v, p, yv, yp, logn,
+                             (TO)c0, (TO)ch2, (TO)inv_h);
+        else
+          hipLaunchKernelGGL((k_stokes_split4<TO, 2>), dim3(nblk(C / 4)), dim3(256), 0, s, v, p, yv, yp, logn,
+                             (TO)c0, (TO)ch2, (TO)inv_h);
+        return;
+      }
+    }
   }
+  if (!split) {
+    // natural storage (the outer operator): the one launch a timer samples
+    if (dim == 3)
+      hipExtLaunchKernelGGL(k_stokes_apply<TI, TO, 3, false>, dim3(nblk(C)), dim3(256), 0, s, ev.start, ev.stop, 0,
+                            v, p, yv, yp, logn, (TO)c0, (TO)ch2, (TO)inv_h, addc);
+    else
+      hipExtLaunchKernelGGL(k_stokes_apply<TI, TO, 2, false>, dim3(nblk(C)), dim3(256), 0, s, ev.start, ev.stop, 0,
+                            v, p, yv, yp, logn, (TO)c0, (TO)ch2, (TO)inv_h, addc);
+    return;
+  }
+  if (dim == 3)
+    IBR_STOKES(3, true);
+  else
+    IBR_STOKES(2, true);
 #undef IBR_STOKES
 }
 template void launch_stokes_apply<double, double>(int, int, const double*, const double*, double*, double*,
-                                                  double, double, double, const double*, hipStream_t, bool);
+                                                  double, double, double, const double*, hipStream_t, bool,
+                                                  TimerEvents);
 template void launch_stokes_apply<float, double>(int, int, const float*, const float*, double*, double*,
-                                                 double, double, double, const double*, hipStream_t, bool);
+                                                 double, double, double, const double*, hipStream_t, bool,
+                                                 TimerEvents);
 template void launch_stokes_apply<float, float>(int, int, const float*, const float*, float*, float*, double,
-                                                double, double, const double*, hipStream_t, bool);
+                                                double, double, const double*, hipStream_t, bool, TimerEvents);
 
 template <typename T>
 void launch_div_q(int dim, int logn, const T* v, const T* hp, T* q, double inv_h, hipStream_t s, bool split) {
   const int64_t C = (int64_t)1 << (dim * logn);
-#define IBR_DIVQ(D, S) \
-  hipLaunchKernelGGL((k_div_q<T, D, S>), dim3(nblk(C)), dim3(256), 0, s, v, hp, q, logn, (T)inv_h)
-  if (dim == 3) {
-    if (split) IBR_DIVQ(3, true); else IBR_DIVQ(3, false);
-  } else {
-    if (split) IBR_DIVQ(2, true); else IBR_DIVQ(2, false);
+  if (split) {
+    if (dim == 3)
+      hipLaunchKernelGGL((k_div_q_split4<T, 3>), dim3(nblk(C / 4)), dim3(256), 0, s, v, hp, q, logn, (T)inv_h);
+    else
+      hipLaunchKernelGGL((k_div_q_split4<T, 2>), dim3(nblk(C / 4)), dim3(256), 0, s, v, hp, q, logn, (T)inv_h);
+    return;
   }
-#undef IBR_DIVQ
+  if (dim == 3)
+    hipLaunchKernelGGL((k_div_q<T, 3, false>), dim3(nblk(C)), dim3(256), 0, s, v, hp, q, logn, (T)inv_h);
+  else
+    hipLaunchKernelGGL((k_div_q<T, 2, false>), dim3(nblk(C)), dim3(256), 0, s, v, hp, q, logn, (T)inv_h);
 }
 template void launch_div_q<double>(int, int, const double*, const double*, double*, double, hipStream_t, bool);
 template void launch_div_q<float>(int, int, const float*, const float*, float*, double, hipStream_t, bool);
@@ -265,15 +467,21 @@ template <typename T>
 void launch_ps_finish(int dim, int logn, T* v, const T* phi, const T* q, T* pi, double h, double c0h2,
                       double eta, const double* vmean, hipStream_t s, bool split) {
   const int64_t C = (int64_t)1 << (dim * logn);
-#define IBR_PSF(D, S)                                                                                          \
-  hipLaunchKernelGGL((k_ps_finish<T, D, S>), dim3(nblk(C)), dim3(256), 0, s, v, phi, q, pi, logn, (T)h, (T)c0h2, \
-                     (T)eta, vmean)
-  if (dim == 3) {
-    if (split) IBR_PSF(3, true); else IBR_PSF(3, false);
-  } else {
-    if (split) IBR_PSF(2, true); else IBR_PSF(2, false);
+  if (split) {
+    if (dim == 3)
+      hipLaunchKernelGGL((k_ps_finish_split4<T, 3>), dim3(nblk(C / 4)), dim3(256), 0, s, v, phi, q, pi, logn, (T)h,
+                         (T)c0h2, (T)eta, vmean);
+    else
+      hipLaunchKernelGGL((k_ps_finish_split4<T, 2>), dim3(nblk(C / 4)), dim3(256), 0, s, v, phi, q, pi, logn, (T)h,
+                         (T)c0h2, (T)eta, vmean);
+    return;
   }
-#undef IBR_PSF
+  if (dim == 3)
+    hipLaunchKernelGGL((k_ps_finish<T, 3, false>), dim3(nblk(C)), dim3(256), 0, s, v, phi, q, pi, logn, (T)h,
+                       (T)c0h2, (T)eta, vmean);
+  else
+    hipLaunchKernelGGL((k_ps_finish<T, 2, false>), dim3(nblk(C)), dim3(256), 0, s, v, phi, q, pi, logn, (T)h,
+                       (T)c0h2, (T)eta, vmean);
 }
 template void launch_ps_finish<double>(int, int, double*, const double*, const double*, double*, double, double,
                                        double, const double*, hipStream_t, bool);

@@ -541,12 +541,8 @@ void arnoldi_step(const T* V, int64_t ld, int k, double* hcol, double* h2, doubl
   T* w = const_cast<T*>(V) + (int64_t)(k + 1) * ld;
   const double vb = (double)ld * sizeof(T);
   // pass 1: columns 0..k+1 (the last one is w itself, giving ||w||^2 in hcol[k+1])
-  if (timed) timer_begin(kTimerOrthoDot, s);
   launch_multi_dot<T, T>(V, ld, k + 2, w, ld, part1, nblocks, hcol, false, s, nullptr);
-  if (timed) timer_end(kTimerOrthoDot, s, (k + 2) * vb);
-  if (timed) timer_begin(kTimerOrthoAxpy, s);
   launch_multi_axpy<T, T>(V, ld, k + 1, hcol, w, ld, part1, nblocks, s, nullptr);
-  if (timed) timer_end(kTimerOrthoAxpy, s, (k + 3) * vb);
   if (!reorth) {
     launch_norm_finish(part1, nblocks, hcol + k + 1, s);
     return;
@@ -642,35 +638,39 @@ void launch_axpby(const double* x, double* y, int64_t len, double a, double b, h
 }
 
 template <typename T>
-void dcgs2_step(T* V, int64_t ld, int k, double* H, int ldh, double* G, double* coef, double* part, int nblocks,
-                double* cs, double* sn, double* g, double* resid, hipStream_t s, bool timed) {
-  if (ld >= ((int64_t)1 << 28)) throw DeviceError("dcgs2_step: vectors longer than 2^28 entries");
+void dcgs2_step(T* V, int64_t ld, int64_t len, int k, double* H, int ldh, double* G, double* coef, double* part,
+                int nblocks, double* cs, double* sn, double* g, double* resid, hipStream_t s, bool timed) {
+  if (len >= ((int64_t)1 << 28)) throw DeviceError("dcgs2_step: vectors longer than 2^28 entries");
   const int ncols = k + 2;
-  const double vb = (double)ld * sizeof(T);
-  if (timed) timer_begin(kTimerOrthoDot, s);
+  const double vb = (double)len * sizeof(T);
+  // the reduction's algorithmic bytes (all chunks): the k+2 columns once, plus
+  // the two vectors being orthogonalised once per extra chunk; the first chunk
+  // carries the start event, the last the stop event
+  const TimerEvents evd =
+      timed ? timer_sample(kTimerOrthoDot, (ncols + 2 * ((ncols - 1) / kDualCols)) * vb) : TimerEvents();
   for (int j0 = 0; j0 < ncols; j0 += kDualCols) {
     const int nj = std::min(kDualCols, ncols - j0);
+    const hipEvent_t e0 = j0 == 0 ? evd.start : nullptr;
+    const hipEvent_t e1 = j0 + kDualCols >= ncols ? evd.stop : nullptr;
     switch (nj) {
-#define IBR_DUAL(NJ)                                                                                              \
-  case NJ:                                                                                                        \
-    hipLaunchKernelGGL((k_dual_dot<T, NJ>), dim3(nblocks), dim3(256), 0, s, V, ld, j0, k, (int)ld, part);         \
+#define IBR_DUAL(NJ)                                                                                          \
+  case NJ:                                                                                                    \
+    hipExtLaunchKernelGGL(k_dual_dot<T, NJ>, dim3(nblocks), dim3(256), 0, s, e0, e1, 0, (const T*)V, ld, j0, k, \
+                          (int)len, part);                                                                    \
     break;
       IBR_DUAL(1) IBR_DUAL(2) IBR_DUAL(3) IBR_DUAL(4) IBR_DUAL(5) IBR_DUAL(6) IBR_DUAL(7) IBR_DUAL(8)
       IBR_DUAL(9) IBR_DUAL(10) IBR_DUAL(11) IBR_DUAL(12) IBR_DUAL(13) IBR_DUAL(14) IBR_DUAL(15) IBR_DUAL(16)
 #undef IBR_DUAL
     }
   }
-  // bytes of the whole reduction (all chunks): the k+2 columns once, plus the
-  // two vectors being orthogonalised once per extra chunk
-  if (timed) timer_end(kTimerOrthoDot, s, (ncols + 2 * ((ncols - 1) / kDualCols)) * vb);
   hipLaunchKernelGGL(k_dcgs2_coef, dim3(1), dim3(1024), 0, s, part, nblocks, G, k, H, ldh, coef);
-  if (timed) timer_begin(kTimerOrthoAxpy, s);
-  hipLaunchKernelGGL((k_dcgs2_axpy<T>), dim3(nblocks), dim3(256), 0, s, V, ld, k, coef, (int)ld, part);
-  if (timed) timer_end(kTimerOrthoAxpy, s, (ncols + 2) * vb);
+  const TimerEvents eva = timed ? timer_sample(kTimerOrthoAxpy, (ncols + 2) * vb) : TimerEvents();
+  hipExtLaunchKernelGGL(k_dcgs2_axpy<T>, dim3(nblocks), dim3(256), 0, s, eva.start, eva.stop, 0, V, ld, k,
+                        (const double*)coef, (int)len, part);
   hipLaunchKernelGGL(k_dcgs2_finish, dim3(1), dim3(256), 0, s, part, nblocks, H, ldh, k, cs, sn, g, resid);
 }
-template void dcgs2_step<double>(double*, int64_t, int, double*, int, double*, double*, double*, int, double*,
-                                 double*, double*, double*, hipStream_t, bool);
+template void dcgs2_step<double>(double*, int64_t, int64_t, int, double*, int, double*, double*, double*, int,
+                                 double*, double*, double*, double*, hipStream_t, bool);
 
 void launch_givens_step(double* H, int ldh, int k, double* cs, double* sn, double* g, double* resid,
                         hipStream_t s) {

@@ -637,20 +637,19 @@ void MGHier<T>::rb_half(T* x, const T* b, int lg, int nf, T c0, T c1, int color,
   const int64_t Cl = (int64_t)1 << (dim * lg);
   check_quad_aligned(x, b);
   const dim3 gh(nblk(Cl / 8), nf);
-  if (fine) timer_begin(kTimerRbFine, s);
+  // algorithmic traffic of a half sweep: x of one colour written, x of the other and b of this colour read
+  const TimerEvents ev = fine ? timer_sample(kTimerRbFine, 1.5 * (double)Cl * nf * sizeof(T)) : TimerEvents();
   if (dim == 3) {
     if (fine)
-      hipLaunchKernelGGL((k_rb<T, 3, true>), gh, dim3(256), 0, s, x, b, lg, c0, c1, color);
+      hipExtLaunchKernelGGL(k_rb<T, 3, true>, gh, dim3(256), 0, s, ev.start, ev.stop, 0, x, b, lg, c0, c1, color);
     else
       hipLaunchKernelGGL((k_rb<T, 3, false>), gh, dim3(256), 0, s, x, b, lg, c0, c1, color);
   } else {
     if (fine)
-      hipLaunchKernelGGL((k_rb<T, 2, true>), gh, dim3(256), 0, s, x, b, lg, c0, c1, color);
+      hipExtLaunchKernelGGL(k_rb<T, 2, true>, gh, dim3(256), 0, s, ev.start, ev.stop, 0, x, b, lg, c0, c1, color);
     else
       hipLaunchKernelGGL((k_rb<T, 2, false>), gh, dim3(256), 0, s, x, b, lg, c0, c1, color);
   }
-  // algorithmic traffic of a half sweep: b and x of one colour, x of the other
-  if (fine) timer_end(kTimerRbFine, s, 1.5 * (double)Cl * nf * sizeof(T));
 }
 
 template <typename T>
@@ -658,20 +657,19 @@ void MGHier<T>::rb_first(T* x, const T* b, int lg, int nf, T c0, T c1, bool fine
   const int64_t Cl = (int64_t)1 << (dim * lg);
   check_quad_aligned(x, b);
   const dim3 g(nblk(Cl / 8), nf);
-  if (fine) timer_begin(kTimerRbFine, s);
+  // algorithmic traffic of the first sweep from zero: b read once, x written once
+  const TimerEvents ev = fine ? timer_sample(kTimerRbFine, 2.0 * (double)Cl * nf * sizeof(T)) : TimerEvents();
   if (dim == 3) {
     if (fine)
-      hipLaunchKernelGGL((k_rb_first<T, 3, true>), g, dim3(256), 0, s, x, b, lg, c0, c1);
+      hipExtLaunchKernelGGL(k_rb_first<T, 3, true>, g, dim3(256), 0, s, ev.start, ev.stop, 0, x, b, lg, c0, c1);
     else
       hipLaunchKernelGGL((k_rb_first<T, 3, false>), g, dim3(256), 0, s, x, b, lg, c0, c1);
   } else {
     if (fine)
-      hipLaunchKernelGGL((k_rb_first<T, 2, true>), g, dim3(256), 0, s, x, b, lg, c0, c1);
+      hipExtLaunchKernelGGL(k_rb_first<T, 2, true>, g, dim3(256), 0, s, ev.start, ev.stop, 0, x, b, lg, c0, c1);
     else
       hipLaunchKernelGGL((k_rb_first<T, 2, false>), g, dim3(256), 0, s, x, b, lg, c0, c1);
   }
-  // algorithmic traffic of the first sweep from zero: b read once, x written once
-  if (fine) timer_end(kTimerRbFine, s, 2.0 * (double)Cl * nf * sizeof(T));
 }
 
 template <typename T>

@@ -85,6 +85,7 @@ struct ibr_ctx {
 
   // stacked vectors (fp64)
   int64_t NF = 0, NV = 0;
+  int64_t ldv = 0;  // stride of the Krylov basis vectors: NV rounded up to 64 entries
   double *Xs = nullptr, *Bs = nullptr, *T1 = nullptr, *T2 = nullptr;
   double *lamd = nullptr, *dU = nullptr, *addc = nullptr, *lsum_part = nullptr;
   double *Nprev = nullptr, *Ncur = nullptr;
@@ -168,9 +169,9 @@ void apply_K(ibr_ctx* c, const TI* x, double* y) {
     launch_lambda_sums(d, c->N, c->lamd, c->lsum_part, c->addc, 1.0 / c->vol, s);
     addc = c->addc;
   }
-  timer_begin(kTimerStokes, s);
-  launch_stokes_apply<TI, double>(d, c->logn, xv, xp, y, y + (int64_t)d * c->C, c->c0, c->ch2, c->inv_h, addc, s);
-  timer_end(kTimerStokes, s, (double)(d + 1) * c->C * (sizeof(TI) + sizeof(double)));
+  const TimerEvents ev = timer_sample(kTimerStokes, (double)(d + 1) * c->C * (sizeof(TI) + sizeof(double)));
+  launch_stokes_apply<TI, double>(d, c->logn, xv, xp, y, y + (int64_t)d * c->C, c->c0, c->ch2, c->inv_h, addc, s,
+                                  false, ev);
   launch_spread<double, double>(d, c->logn, c->tile_log, c->act_cap, c->active, c->nactive_d, c->toff, c->perm,
                                 c->taps, c->lamd, y, -std::pow(c->h, -d), s);
   launch_interp<TI>(d, c->logn, c->N, c->taps, xv, -1.0, nullptr, 0.0, y + c->NF, s);
@@ -286,15 +287,15 @@ void precondition(ibr_ctx* c, const double* r, T* z) {
 // One outer iteration k: z_k = P v_k, w = K z_k, delayed-CGS2 Arnoldi step.
 template <typename TZ>
 void iteration_body(ibr_ctx* c, int k) {
-  const int64_t NV = c->NV;
+  const int64_t NV = c->NV, ld = c->ldv;
   double* V = c->Vb;
   TZ* Z = (TZ*)c->Zb;
-  double* vk = V + (int64_t)k * NV;
-  double* w = V + (int64_t)(k + 1) * NV;
-  TZ* zk = Z + (int64_t)k * NV;
+  double* vk = V + (int64_t)k * ld;
+  double* w = V + (int64_t)(k + 1) * ld;
+  TZ* zk = Z + (int64_t)k * ld;
   precondition<TZ>(c, vk, zk);
   apply_K<TZ>(c, zk, w);
-  dcgs2_step<double>(V, NV, k, c->H, c->m + 1, c->G, c->coef, c->part, c->part_blocks, c->cs, c->sn, c->g,
+  dcgs2_step<double>(V, ld, NV, k, c->H, c->m + 1, c->G, c->coef, c->part, c->part_blocks, c->cs, c->sn, c->g,
                      c->resid, c->stream, true);
 }
 
@@ -417,7 +418,7 @@ ibr_status fgmres(ibr_ctx* c, ibr_info* info) {
       // the last column is still provisional: rotate it as it stands
       launch_givens_step(c->H, ldh, kused - 1, c->cs, c->sn, c->g, c->resid, s);
       launch_lsq_solve(c->H, ldh, kused, c->g, c->y, s);
-      launch_combine<TZ, double>(Z, NV, kused, c->y, c->Xs, NV, s);
+      launch_combine<TZ, double>(Z, c->ldv, kused, c->y, c->Xs, NV, s);
       if (stop) break;
     }
   }
@@ -708,13 +709,14 @@ void ibr_ctx::alloc_markers(int Nnew) {
   Bs = track<double>(NVc);
   T1 = track<double>(NVc);
   T2 = track<double>(NVc);
-  Vb = track<double>((int64_t)(m + 1) * NVc);
+  const int64_t ldc = (NVc + 63) & ~(int64_t)63;  // basis stride at capacity
+  Vb = track<double>((int64_t)(m + 1) * ldc);
   if (mixed) {
-    Zb = dev_alloc<float>((int64_t)m * NVc);
-    bytes += (int64_t)m * NVc * 4;
+    Zb = dev_alloc<float>((int64_t)m * ldc);
+    bytes += (int64_t)m * ldc * 4;
   } else {
-    Zb = dev_alloc<double>((int64_t)m * NVc);
-    bytes += (int64_t)m * NVc * 8;
+    Zb = dev_alloc<double>((int64_t)m * ldc);
+    bytes += (int64_t)m * ldc * 8;
   }
   launch_fill<double>(Xs, NVc, 0.0, stream);
   launch_fill<double>(Bs, NVc, 0.0, stream);
@@ -815,8 +817,9 @@ size_t ibr_footprint_bytes(const ibr_params* p, int nbodies, int nmarkers) {
   const int ns = p->n_s > 0 ? p->n_s : 2;
   const int64_t ts = p->precision == IBR_MIXED ? 4 : 8;
   size_t b = 0;
-  b += (size_t)(m + 1) * NV * 8;       // V basis
-  b += (size_t)m * NV * ts;            // Z basis
+  const int64_t ldv = (NV + 63) & ~(int64_t)63;
+  b += (size_t)(m + 1) * ldv * 8;      // V basis
+  b += (size_t)m * ldv * ts;           // Z basis
   b += (size_t)4 * NV * 8;             // x, b, two temporaries
   b += (size_t)2 * d * C * 8;          // advection history
   b += (size_t)((2 * ns + 2) * NF + 2 * C) * ts;  // inner bases and P_S^-1 scratch
@@ -881,6 +884,7 @@ ibr_status ibr_set_bodies(ibr_ctx* c, int nbodies, const int* offsets, const dou
     c->nb = nbodies;
     c->N = N;
     c->NV = c->NF + (int64_t)d * N;
+    c->ldv = (c->NV + 63) & ~(int64_t)63;
     c->off_h.assign(offsets, offsets + nbodies + 1);
     c->off_d = dev_alloc<int>(nbodies + 1);
     c->X = dev_alloc<double>((int64_t)nbodies * d);

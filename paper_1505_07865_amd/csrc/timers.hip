@@ -1,9 +1,11 @@
 // Live per-kernel timing with HIP events on the launching stream.
 //
-// A few kernel classes (the finest-level red-black sweep, the outer Arnoldi
-// passes, the outer Stokes stencil) can bracket every launch with a pair of
-// events and accumulate the algorithmic bytes the launch must move.  Disabled
-// timers cost one branch per launch.
+// A few kernel classes (the finest-level red-black sweeps, the outer Arnoldi
+// passes, the outer Stokes stencil) sample every stride-th launch: the sampled
+// launch goes through hipExtLaunchKernelGGL with a start and a stop event,
+// which the runtime stamps with the kernel's own start and end (the same
+// interval a kernel trace reports), and its algorithmic bytes are
+// accumulated.  Disabled timers cost one branch per launch.
 #include <cstring>
 #include <vector>
 
@@ -17,7 +19,6 @@ namespace {
 struct TimerState {
   int stride = 0;        // 0 = off; otherwise every stride-th launch is timed
   long seen = 0;         // launches of the class since enabling
-  bool pending = false;  // the current launch is being timed
   std::vector<hipEvent_t> pool;
   size_t used = 0;
   double bytes = 0.0;
@@ -46,26 +47,18 @@ hipEvent_t next_event(TimerState& t) {
 
 }  // namespace
 
-bool timer_on(int id) { return id >= 0 && id < kTimerCount && g_timers[id].stride > 0; }
-
-void timer_begin(int id, hipStream_t s) {
-  if (!timer_on(id)) return;
+TimerEvents timer_sample(int id, double bytes) {
+  TimerEvents ev;
+  if (id < 0 || id >= kTimerCount) return ev;
   TimerState& t = g_timers[id];
-  t.pending = (t.seen++ % t.stride) == 0;
-  if (!t.pending) return;
-  hipEvent_t e = next_event(t);
-  if (e) (void)hipEventRecord(e, s);
-}
-
-void timer_end(int id, hipStream_t s, double bytes) {
-  if (!timer_on(id)) return;
-  TimerState& t = g_timers[id];
-  if (!t.pending) return;
-  t.pending = false;
-  hipEvent_t e = next_event(t);
-  if (e) (void)hipEventRecord(e, s);
+  if (t.stride <= 0) return ev;
+  if ((t.seen++ % t.stride) != 0) return ev;
+  ev.start = next_event(t);
+  ev.stop = next_event(t);
+  if (!ev.start || !ev.stop) return TimerEvents();
   t.bytes += bytes;
   t.launches += 1;
+  return ev;
 }
 
 bool timers_any() {
@@ -84,7 +77,6 @@ int ibr_timer_enable(const char* kernel, int stride) {
   ibr::TimerState& t = ibr::g_timers[i];
   t.stride = stride;
   t.seen = 0;
-  t.pending = false;
   t.used = 0;
   t.bytes = 0.0;
   t.launches = 0;
