@@ -295,8 +295,10 @@ __global__ void __launch_bounds__(256) k_resid_restrict(const T* __restrict__ x,
 // storage on both levels.  Each thread owns 8 consecutive fine cells of a row
 // (4 of each colour); each of the 2^(dim-1) coarse rows it needs is
 // interpolated along x once from coarse cells I0-1 .. I0+4 (two pairs and two
-// scalars).  Needs n >= 16.
-template <typename T, int DIM>
+// scalars).  BLACK_ONLY: only the black cells are corrected, for when a red
+// half sweep follows (it overwrites the red cells without reading them), which
+// leaves the result unchanged and halves the fine-level traffic.  Needs n >= 16.
+template <typename T, int DIM, bool BLACK_ONLY>
 __global__ void __launch_bounds__(256) k_prolong_add(T* __restrict__ x, const T* __restrict__ e, int logn) {
   const int C = 1 << (DIM * logn), H = C >> 1, hl = logn - 1;
   const int lognc = logn - 1;
@@ -344,7 +346,11 @@ __global__ void __launch_bounds__(256) k_prolong_add(T* __restrict__ x, const T*
   const int fp = (j + k) & 1;
   T* xe = x + fp * H + (row << hl) + I0;
   T* xo = x + (1 - fp) * H + (row << hl) + I0;
-  Quad<T> qe = ldq(xe), qo = ldq(xo);
+  // even v: colour fp; odd v: the other colour.  Black is colour 1.
+  const bool even_black = fp == 1;
+  Quad<T> qe, qo;
+  if (!BLACK_ONLY || even_black) qe = ldq(xe);
+  if (!BLACK_ONLY || !even_black) qo = ldq(xo);
 #pragma unroll
   for (int v = 0; v < 8; ++v) {
     T val;
@@ -360,8 +366,8 @@ __global__ void __launch_bounds__(256) k_prolong_add(T* __restrict__ x, const T*
     else
       qe.v[v >> 1] += val;
   }
-  stq(xe, qe);
-  stq(xo, qo);
+  if (!BLACK_ONLY || even_black) stq(xe, qe);
+  if (!BLACK_ONLY || !even_black) stq(xo, qo);
 }
 
 // ---------------------------------------------------------------- one-workgroup tail
@@ -715,10 +721,19 @@ void MGHier<T>::vcycle(int nf, const T* b, T* x, double c0, double c1, int nu_pr
     const int64_t Cl = (int64_t)1 << (dim * lg);
     T* xl = l == 0 ? x : bufs_x[l];
     const T* bl = l == 0 ? b : bufs_b[l];
-    if (three)
-      hipLaunchKernelGGL((k_prolong_add<T, 3>), dim3(nblk(Cl / 8), nf), dim3(256), 0, s, xl, bufs_x[l + 1], lg);
-    else
-      hipLaunchKernelGGL((k_prolong_add<T, 2>), dim3(nblk(Cl / 8), nf), dim3(256), 0, s, xl, bufs_x[l + 1], lg);
+    // with post-smoothing the first (red) half sweep overwrites the red cells
+    const dim3 gp(nblk(Cl / 8), nf);
+    if (three) {
+      if (nu_post > 0)
+        hipLaunchKernelGGL((k_prolong_add<T, 3, true>), gp, dim3(256), 0, s, xl, bufs_x[l + 1], lg);
+      else
+        hipLaunchKernelGGL((k_prolong_add<T, 3, false>), gp, dim3(256), 0, s, xl, bufs_x[l + 1], lg);
+    } else {
+      if (nu_post > 0)
+        hipLaunchKernelGGL((k_prolong_add<T, 2, true>), gp, dim3(256), 0, s, xl, bufs_x[l + 1], lg);
+      else
+        hipLaunchKernelGGL((k_prolong_add<T, 2, false>), gp, dim3(256), 0, s, xl, bufs_x[l + 1], lg);
+    }
     for (int sw = 0; sw < nu_post; ++sw)
       for (int color = 0; color < 2; ++color) rb_half(xl, bl, lg, nf, tc0, cl, color, l == 0, s);
   }
