@@ -65,17 +65,6 @@ __device__ inline int split_index(int i, int j, int k, int logn) {
   const int row = DIM == 3 ? (j | (k << logn)) : j;
   return (((i + j + k) & 1) << (DIM * logn - 1)) | (row << (logn - 1)) | (i >> 1);
 }
-// Cell (i, j, k) at split storage index t.
-template <int DIM>
-__device__ inline void split_coords(int t, int logn, int& i, int& j, int& k) {
-  const int mask = (1 << logn) - 1;
-  const int col = t >> (DIM * logn - 1);
-  const int r = t & ((1 << (DIM * logn - 1)) - 1);
-  const int row = r >> (logn - 1);
-  j = row & mask;
-  k = DIM == 3 ? (row >> logn) : 0;
-  i = 2 * (r & ((1 << (logn - 1)) - 1)) + ((col + j + k) & 1);
-}
 // Natural (x-fastest) index of cell (i, j, k), wrapped.
 template <int DIM>
 __device__ inline int natural_index(int i, int j, int k, int logn) {

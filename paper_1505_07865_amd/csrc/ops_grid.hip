@@ -38,30 +38,23 @@ __device__ inline Nbr neighbours(int64_t c, int logn) {
   return r;
 }
 
-// Storage policy of a cell lattice: natural (x fastest, the public layout)
-// or split by colour (the preconditioner's private vectors).
-template <int DIM, bool SPLIT>
+// Natural (x fastest) storage of a cell lattice: cell <-> index.
+template <int DIM>
 struct Lat {
   int logn;
   __device__ void coords(int t, int& i, int& j, int& k) const {
-    if (SPLIT) {
-      split_coords<DIM>(t, logn, i, j, k);
-    } else {
-      const int mask = (1 << logn) - 1;
-      i = t & mask;
-      j = (t >> logn) & mask;
-      k = DIM == 3 ? (t >> (2 * logn)) : 0;
-    }
+    const int mask = (1 << logn) - 1;
+    i = t & mask;
+    j = (t >> logn) & mask;
+    k = DIM == 3 ? (t >> (2 * logn)) : 0;
   }
-  __device__ int index(int i, int j, int k) const {
-    return SPLIT ? split_index<DIM>(i, j, k, logn) : natural_index<DIM>(i, j, k, logn);
-  }
+  __device__ int index(int i, int j, int k) const { return natural_index<DIM>(i, j, k, logn); }
 };
 
 // yv = A v + G p + addc, yp = -D v.   A = c0 I - ch2 L,  G, D with 1/h.
 // TI: storage type of the input, TO: of the output (arithmetic in TO).
-// One thread per storage position (own values coalesced).
-template <typename TI, typename TO, int DIM, bool SPLIT>
+// Natural storage, one thread per cell.
+template <typename TI, typename TO, int DIM>
 __global__ void __launch_bounds__(256) k_stokes_apply(const TI* __restrict__ v, const TI* __restrict__ p,
                                                       TO* __restrict__ yv, TO* __restrict__ yp, int logn,
                                                       TO c0, TO ch2, TO inv_h,
@@ -70,7 +63,7 @@ __global__ void __launch_bounds__(256) k_stokes_apply(const TI* __restrict__ v, 
   const int64_t t64 = xcd_block(gridDim.x) * blockDim.x + threadIdx.x;
   if (t64 >= C) return;
   const int t = (int)t64;
-  const Lat<DIM, SPLIT> L{logn};
+  const Lat<DIM> L{logn};
   int i, j, k;
   L.coords(t, i, j, k);
   int m[3], pl[3];
@@ -97,15 +90,15 @@ __global__ void __launch_bounds__(256) k_stokes_apply(const TI* __restrict__ v, 
   yp[t] = -div;
 }
 
-// q = -D v - hp  (hp may be null).
-template <typename T, int DIM, bool SPLIT>
+// q = -D v - hp  (hp may be null), natural storage.
+template <typename T, int DIM>
 __global__ void __launch_bounds__(256) k_div_q(const T* __restrict__ v, const T* __restrict__ hp,
                                                T* __restrict__ q, int logn, T inv_h) {
   const int64_t C = (int64_t)1 << (DIM * logn);
   const int64_t t64 = xcd_block(gridDim.x) * blockDim.x + threadIdx.x;
   if (t64 >= C) return;
   const int t = (int)t64;
-  const Lat<DIM, SPLIT> L{logn};
+  const Lat<DIM> L{logn};
   int i, j, k;
   L.coords(t, i, j, k);
   const int pl[3] = {L.index(i + 1, j, k), L.index(i, j + 1, k), DIM == 3 ? L.index(i, j, k + 1) : t};
@@ -115,8 +108,8 @@ __global__ void __launch_bounds__(256) k_div_q(const T* __restrict__ v, const T*
   q[t] = -div - (hp ? hp[t] : T(0));
 }
 
-// v <- v - vmean + h (phi_c - phi_{c-e_a});  pi = -c0 h^2 phi + eta q.
-template <typename T, int DIM, bool SPLIT>
+// v <- v - vmean + h (phi_c - phi_{c-e_a});  pi = -c0 h^2 phi + eta q, natural storage.
+template <typename T, int DIM>
 __global__ void __launch_bounds__(256) k_ps_finish(T* __restrict__ v, const T* __restrict__ phi,
                                                    const T* __restrict__ q, T* __restrict__ pi, int logn,
                                                    T h, T c0h2, T eta, const double* __restrict__ vmean) {
@@ -124,7 +117,7 @@ __global__ void __launch_bounds__(256) k_ps_finish(T* __restrict__ v, const T* _
   const int64_t t64 = xcd_block(gridDim.x) * blockDim.x + threadIdx.x;
   if (t64 >= C) return;
   const int t = (int)t64;
-  const Lat<DIM, SPLIT> L{logn};
+  const Lat<DIM> L{logn};
   int i, j, k;
   L.coords(t, i, j, k);
   const int m[3] = {L.index(i - 1, j, k), L.index(i, j - 1, k), DIM == 3 ? L.index(i, j, k - 1) : t};
@@ -404,10 +397,8 @@ template <typename TI, typename TO>
 void launch_stokes_apply(int dim, int logn, const TI* v, const TI* p, TO* yv, TO* yp, double c0, double ch2,
                          double inv_h, const double* addc, hipStream_t s, bool split, TimerEvents ev) {
   const int64_t C = (int64_t)1 << (dim * logn);
-#define IBR_STOKES(D, S)                                                                                       \
-  hipLaunchKernelGGL((k_stokes_apply<TI, TO, D, S>), dim3(nblk(C)), dim3(256), 0, s, v, p, yv, yp, logn, (TO)c0, \
-                     (TO)ch2, (TO)inv_h, addc)
   if (split) {
+    // the preconditioner's operator: same storage type in and out, no added constant
     if constexpr (std::is_same<TI, TO>::value) {
       if (!addc) {
         if (dim == 3)
@@ -419,22 +410,15 @@ void launch_stokes_apply(int dim, int logn, const TI* v, const TI* p, TO* yv, TO
         return;
       }
     }
+    throw DeviceError("launch_stokes_apply: split storage needs equal input/output types and no added constant");
   }
-  if (!split) {
-    // natural storage (the outer operator): the one launch a timer samples
-    if (dim == 3)
-      hipExtLaunchKernelGGL(k_stokes_apply<TI, TO, 3, false>, dim3(nblk(C)), dim3(256), 0, s, ev.start, ev.stop, 0,
-                            v, p, yv, yp, logn, (TO)c0, (TO)ch2, (TO)inv_h, addc);
-    else
-      hipExtLaunchKernelGGL(k_stokes_apply<TI, TO, 2, false>, dim3(nblk(C)), dim3(256), 0, s, ev.start, ev.stop, 0,
-                            v, p, yv, yp, logn, (TO)c0, (TO)ch2, (TO)inv_h, addc);
-    return;
-  }
+  // natural storage (the outer operator): the one launch a timer samples
   if (dim == 3)
-    IBR_STOKES(3, true);
+    hipExtLaunchKernelGGL(k_stokes_apply<TI, TO, 3>, dim3(nblk(C)), dim3(256), 0, s, ev.start, ev.stop, 0, v, p, yv,
+                          yp, logn, (TO)c0, (TO)ch2, (TO)inv_h, addc);
   else
-    IBR_STOKES(2, true);
-#undef IBR_STOKES
+    hipExtLaunchKernelGGL(k_stokes_apply<TI, TO, 2>, dim3(nblk(C)), dim3(256), 0, s, ev.start, ev.stop, 0, v, p, yv,
+                          yp, logn, (TO)c0, (TO)ch2, (TO)inv_h, addc);
 }
 template void launch_stokes_apply<double, double>(int, int, const double*, const double*, double*, double*,
                                                   double, double, double, const double*, hipStream_t, bool,
@@ -456,9 +440,9 @@ void launch_div_q(int dim, int logn, const T* v, const T* hp, T* q, double inv_h
     return;
   }
   if (dim == 3)
-    hipLaunchKernelGGL((k_div_q<T, 3, false>), dim3(nblk(C)), dim3(256), 0, s, v, hp, q, logn, (T)inv_h);
+    hipLaunchKernelGGL((k_div_q<T, 3>), dim3(nblk(C)), dim3(256), 0, s, v, hp, q, logn, (T)inv_h);
   else
-    hipLaunchKernelGGL((k_div_q<T, 2, false>), dim3(nblk(C)), dim3(256), 0, s, v, hp, q, logn, (T)inv_h);
+    hipLaunchKernelGGL((k_div_q<T, 2>), dim3(nblk(C)), dim3(256), 0, s, v, hp, q, logn, (T)inv_h);
 }
 template void launch_div_q<double>(int, int, const double*, const double*, double*, double, hipStream_t, bool);
 template void launch_div_q<float>(int, int, const float*, const float*, float*, double, hipStream_t, bool);
@@ -477,11 +461,11 @@ void launch_ps_finish(int dim, int logn, T* v, const T* phi, const T* q, T* pi, 
     return;
   }
   if (dim == 3)
-    hipLaunchKernelGGL((k_ps_finish<T, 3, false>), dim3(nblk(C)), dim3(256), 0, s, v, phi, q, pi, logn, (T)h,
-                       (T)c0h2, (T)eta, vmean);
+    hipLaunchKernelGGL((k_ps_finish<T, 3>), dim3(nblk(C)), dim3(256), 0, s, v, phi, q, pi, logn, (T)h, (T)c0h2,
+                       (T)eta, vmean);
   else
-    hipLaunchKernelGGL((k_ps_finish<T, 2, false>), dim3(nblk(C)), dim3(256), 0, s, v, phi, q, pi, logn, (T)h,
-                       (T)c0h2, (T)eta, vmean);
+    hipLaunchKernelGGL((k_ps_finish<T, 2>), dim3(nblk(C)), dim3(256), 0, s, v, phi, q, pi, logn, (T)h, (T)c0h2,
+                       (T)eta, vmean);
 }
 template void launch_ps_finish<double>(int, int, double*, const double*, const double*, double*, double, double,
                                        double, const double*, hipStream_t, bool);

@@ -2,14 +2,17 @@
 //
 // Outer solver: right-preconditioned flexible GMRES (Sec. 5) on the stacked
 // fp64 vector x = [v (dim C), pi (C), Lambda (dim N)] with restart m; the
-// Arnoldi step is classical Gram-Schmidt with one re-orthogonalisation pass,
-// the Hessenberg least squares uses Givens rotations on the device, and the
-// host reads one residual estimate per iteration.
+// Arnoldi step is delayed classical Gram-Schmidt with re-orthogonalisation
+// (one reduction and one update pass per iteration), the Hessenberg least
+// squares uses Givens rotations on the device, and the host reads one
+// residual estimate per iteration.  Each iteration can be replayed as a
+// captured HIP graph.
 //
 // Preconditioner (Sec. 5.1): inner GMRES(N_s) on the Stokes block with
 // P_S^-1 (eq. P1_practical) in the working precision T (fp64, or fp32 in the
-// mixed mode), slip dU = -(J v + r_L), per-body Lambda = M~^-1 dU in fp64,
-// and for the full variant a second inner solve with r_v + S'Lambda.
+// mixed mode) on split (red/black) storage, slip dU = -(J v + r_L), per-body
+// Lambda = M~^-1 dU in fp64, and for the full variant a second inner solve
+// with r_v + S'Lambda.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
