@@ -12,22 +12,21 @@
 // the split storage section).  Fine levels run one kernel per step with
 // nfields batched in blockIdx.y.
 // The coarse tail of the cycle runs inside ONE workgroup per field
-// (k_vcycle_lds) with every array of the tail levels in LDS: one launch
-// instead of ~10 per level.  The tail starts at 4096 cells (16^3, 64^2): one
-// compute unit sweeping a 32^3 level costs more than the launches it saves.
+// (k_vcycle_lds), on the same split storage and the same per-group code as
+// the global levels, with every array of the tail levels in LDS: one launch
+// instead of ~10 per level.  The tail starts at 4096 cells (16^3, 64^2).
 #include "kernels.h"
 
 namespace ibr {
 
 namespace {
 
-constexpr int kLdsThreads = 1024;
+constexpr int kLdsThreads = 512;
 
-// Largest level (cells) handled inside one workgroup, per precision and dimension.
-template <typename T, int DIM>
-constexpr int64_t lds_max_cells() {
-  return 4096;
-}
+// Largest level (cells) the one-workgroup tail starts from.  A 32^3 fp32
+// pyramid would fit in LDS too, but one compute unit sweeping it is slower
+// than the launches it saves.
+constexpr int64_t kTailMaxCells = 4096;
 // Cells of all levels from C down to the 4^dim grid.
 template <int DIM>
 constexpr int64_t pyramid_cells(int64_t C) {
@@ -39,43 +38,6 @@ constexpr int64_t pyramid_cells(int64_t C) {
 // ---------------------------------------------------------------- helpers
 // Indices inside one field are 32-bit (n^dim <= 2^27 for the grids accepted);
 // field offsets are applied to the base pointers in 64-bit.
-template <int DIM>
-__device__ inline void cell_coords(int c, int logn, int& i, int& j, int& k) {
-  const int mask = (1 << logn) - 1;
-  i = c & mask;
-  j = (c >> logn) & mask;
-  k = DIM == 3 ? (c >> (2 * logn)) : 0;
-}
-
-template <int DIM>
-__device__ inline int cell_index(int i, int j, int k, int logn) {
-  const int mask = (1 << logn) - 1;
-  int c = (i & mask) | ((j & mask) << logn);
-  if (DIM == 3) c |= (k & mask) << (2 * logn);
-  return c;
-}
-
-template <typename T, int DIM>
-__device__ inline T nbr_sum(const T* x, int i, int j, int k, int logn) {
-  T s = x[cell_index<DIM>(i - 1, j, k, logn)] + x[cell_index<DIM>(i + 1, j, k, logn)] +
-        x[cell_index<DIM>(i, j - 1, k, logn)] + x[cell_index<DIM>(i, j + 1, k, logn)];
-  if (DIM == 3) s += x[cell_index<DIM>(i, j, k - 1, logn)] + x[cell_index<DIM>(i, j, k + 1, logn)];
-  return s;
-}
-
-// Cell of colour `color` with colour-local index t (half the cells): row-major
-// pairs, the colour picks the parity inside each pair.
-template <int DIM>
-__device__ inline void colour_cell(int t, int logn, int color, int& i, int& j, int& k) {
-  const int half_log = logn - 1;
-  const int m = t & ((1 << half_log) - 1);
-  const int row = t >> half_log;
-  const int mask = (1 << logn) - 1;
-  j = row & mask;
-  k = DIM == 3 ? (row >> logn) : 0;
-  i = 2 * m + ((j + k + color) & 1);
-}
-
 __device__ inline int flat_thread(unsigned nblocks) {
   return (int)xcd_block(nblocks) * (int)blockDim.x + (int)threadIdx.x;
 }
@@ -109,23 +71,21 @@ __device__ inline void stq(T* p, const Quad<T>& q) {
   *reinterpret_cast<Quad<T>*>(p) = q;
 }
 
-// One red-black half sweep on split storage: each thread updates 4
-// consecutive cells of colour `color` of one row.  FINE marks the finest level
-// (same code; a separate symbol for profiling).  Needs n >= 8.
-template <typename T, int DIM, bool FINE>
-__global__ void __launch_bounds__(256) k_rb(T* __restrict__ x, const T* __restrict__ b, int logn, T c0, T c1,
-                                            int color) {
+// ---- per-group building blocks on one field (x, b already at that field) ----
+// The global kernels below run one group per thread; the one-workgroup tail
+// loops over the groups of a level with its 1024 threads.
+
+// Half sweep of the 4 consecutive cells of colour `color` in group g of a row
+// (H/4 groups).  Needs n >= 8.
+template <typename T, int DIM>
+__device__ inline void rb_group(T* __restrict__ x, const T* __restrict__ b, int logn, T c0, T c1, int color,
+                                int g) {
   const int C = 1 << (DIM * logn);
   const int H = C >> 1;
   const int hl = logn - 1;  // log2 of the half-row length
-  const int t = flat_thread(gridDim.x);
-  if (t >= (H >> 2)) return;
-  const int64_t f = blockIdx.y;
-  x += f * C;
-  b += f * C;
   const int mask = (1 << logn) - 1, hmask = (1 << hl) - 1;
-  const int m0 = (t & ((1 << (hl - 2)) - 1)) << 2;
-  const int row = t >> (hl - 2);
+  const int m0 = (g & ((1 << (hl - 2)) - 1)) << 2;
+  const int row = g >> (hl - 2);
   const int j = row & mask;
   const int k = DIM == 3 ? (row >> logn) : 0;
   const bool odd = ((color + j + k) & 1) != 0;  // own cells at i = 2m + 1
@@ -159,22 +119,16 @@ __global__ void __launch_bounds__(256) k_rb(T* __restrict__ x, const T* __restri
 // The first red-black sweep from a zero guess in one pass: red cells take
 // b/diag, black cells (all of whose neighbours are red) take
 // (b + c1 * sum of the neighbours' b/diag)/diag.  Same arithmetic, in the same
-// order, as a red then a black half sweep from x = 0.  Each thread writes 4
-// red and 4 black cells of one row.
-template <typename T, int DIM, bool FINE>
-__global__ void __launch_bounds__(256) k_rb_first(T* __restrict__ x, const T* __restrict__ b, int logn, T c0,
-                                                  T c1) {
+// order, as a red then a black half sweep from x = 0.  Group g writes 4 red
+// and 4 black cells of one row (H/4 groups).  Needs n >= 8.
+template <typename T, int DIM>
+__device__ inline void rb_first_group(T* __restrict__ x, const T* __restrict__ b, int logn, T c0, T c1, int g) {
   const int C = 1 << (DIM * logn);
   const int H = C >> 1;
   const int hl = logn - 1;
-  const int t = flat_thread(gridDim.x);
-  if (t >= (H >> 2)) return;
-  const int64_t f = blockIdx.y;
-  x += f * C;
-  b += f * C;
   const int mask = (1 << logn) - 1, hmask = (1 << hl) - 1;
-  const int m0 = (t & ((1 << (hl - 2)) - 1)) << 2;
-  const int row = t >> (hl - 2);
+  const int m0 = (g & ((1 << (hl - 2)) - 1)) << 2;
+  const int row = g >> (hl - 2);
   const int j = row & mask;
   const int k = DIM == 3 ? (row >> logn) : 0;
   const bool odd = ((1 + j + k) & 1) != 0;  // black cells at i = 2m + 1
@@ -214,24 +168,19 @@ __global__ void __launch_bounds__(256) k_rb_first(T* __restrict__ x, const T* __
 // neighbour along each axis inside the block is a sibling, so
 //   sum r = sum b - (diag - dim c1) sum x + c1 (sum of the face neighbours
 //           outside the block).
-// Each thread makes 4 consecutive coarse cells of one coarse row (split
-// storage on both levels): in fine row (2J+dj, 2K+dk) the children 2I and
-// 2I+1 are the two colours at half-row index I.  Needs n >= 8.
+// Group g makes 4 consecutive coarse cells of one coarse row (Cc/4 groups):
+// in fine row (2J+dj, 2K+dk) the children 2I and 2I+1 are the two colours at
+// half-row index I.  bc is the coarse field.  Needs n >= 8.
 template <typename T, int DIM>
-__global__ void __launch_bounds__(256) k_resid_restrict(const T* __restrict__ x, const T* __restrict__ b,
-                                                        T* __restrict__ bc, int logn, T c0, T c1) {
+__device__ inline void restrict_group(const T* __restrict__ x, const T* __restrict__ b, T* __restrict__ bc, int logn,
+                                      T c0, T c1, int g) {
   const int lognc = logn - 1;
   const int C = 1 << (DIM * logn), H = C >> 1, hl = logn - 1;
   const int Cc = 1 << (DIM * lognc), Hc = Cc >> 1, hlc = lognc - 1;
-  const int t = flat_thread(gridDim.x);
-  if (t >= (Cc >> 2)) return;
-  const int64_t f = blockIdx.y;
-  x += f * C;
-  b += f * C;
   const int mask = (1 << logn) - 1, hmask = (1 << hl) - 1, maskc = (1 << lognc) - 1;
   const int qlog = lognc - 2;  // 4-cell groups per coarse row
-  const int I0 = (t & ((1 << qlog) - 1)) << 2;
-  const int rowc = t >> qlog;
+  const int I0 = (g & ((1 << qlog) - 1)) << 2;
+  const int rowc = g >> qlog;
   const int J = rowc & maskc;
   const int K = DIM == 3 ? (rowc >> lognc) : 0;
   T sx[4] = {0, 0, 0, 0}, sb[4] = {0, 0, 0, 0}, sf[4] = {0, 0, 0, 0};
@@ -285,38 +234,32 @@ __global__ void __launch_bounds__(256) k_resid_restrict(const T* __restrict__ x,
   for (int u = 0; u < 4; ++u) r[u] = (sb[u] - inner * sx[u] + c1 * sf[u]) * avg;
   // coarse cells I0, I0+2 have colour cp, I0+1, I0+3 the other, at half-row I0/2, I0/2+1
   const int cp = (J + K) & 1;
-  T* out = bc + f * Cc;
   const int o = (rowc << hlc) + (I0 >> 1);
-  *reinterpret_cast<Pair<T>*>(out + cp * Hc + o) = Pair<T>{{r[0], r[2]}};
-  *reinterpret_cast<Pair<T>*>(out + (1 - cp) * Hc + o) = Pair<T>{{r[1], r[3]}};
+  *reinterpret_cast<Pair<T>*>(bc + cp * Hc + o) = Pair<T>{{r[0], r[2]}};
+  *reinterpret_cast<Pair<T>*>(bc + (1 - cp) * Hc + o) = Pair<T>{{r[1], r[3]}};
 }
 
-// x += P e (multilinear, cell-centred: weights 3/4 and 1/4 per axis), split
-// storage on both levels.  Each thread owns 8 consecutive fine cells of a row
-// (4 of each colour); each of the 2^(dim-1) coarse rows it needs is
-// interpolated along x once from coarse cells I0-1 .. I0+4 (two pairs and two
-// scalars).  BLACK_ONLY: only the black cells are corrected, for when a red
-// half sweep follows (it overwrites the red cells without reading them), which
-// leaves the result unchanged and halves the fine-level traffic.  Needs n >= 16.
+// x += P e (multilinear, cell-centred: weights 3/4 and 1/4 per axis).  Group
+// g owns 8 consecutive fine cells of a row (4 of each colour; C/8 groups);
+// each of the 2^(dim-1) coarse rows it needs is interpolated along x once
+// from coarse cells I0-1 .. I0+4 (two pairs and two scalars).  BLACK_ONLY:
+// only the black cells are corrected, for when a red half sweep follows (it
+// overwrites the red cells without reading them), which leaves the result
+// unchanged and halves the traffic.  Needs n >= 8.
 template <typename T, int DIM, bool BLACK_ONLY>
-__global__ void __launch_bounds__(256) k_prolong_add(T* __restrict__ x, const T* __restrict__ e, int logn) {
+__device__ inline void prolong_group(T* __restrict__ x, const T* __restrict__ e, int logn, int g) {
   const int C = 1 << (DIM * logn), H = C >> 1, hl = logn - 1;
   const int lognc = logn - 1;
   const int Cc = 1 << (DIM * lognc), Hc = Cc >> 1, hlc = lognc - 1;
-  const int t = flat_thread(gridDim.x);
-  if (t >= (C >> 3)) return;
-  const int64_t f = blockIdx.y;
-  x += f * C;
-  e += f * Cc;
   const int mask = (1 << logn) - 1, maskc = (1 << lognc) - 1, hmaskc = (1 << hlc) - 1;
   const int glog = logn - 3;  // 8-cell groups per fine row
-  const int g = t & ((1 << glog) - 1);
-  const int row = t >> glog;
+  const int gi = g & ((1 << glog) - 1);
+  const int row = g >> glog;
   const int j = row & mask;
   const int k = DIM == 3 ? (row >> logn) : 0;
   const int J = j >> 1, K = k >> 1;
   const int sj = (j & 1) ? 1 : -1, sk = (k & 1) ? 1 : -1;
-  const int I0 = g << 2;      // first coarse cell; fine cells 2 I0 .. 2 I0 + 7
+  const int I0 = gi << 2;     // first coarse cell; fine cells 2 I0 .. 2 I0 + 7
   const int mc = I0 >> 1;     // its half-row index
   const T w0 = T(0.75), w1 = T(0.25);
   T a[4][8];  // [coarse row: (J,K), (J+sj,K), (J,K+sk), (J+sj,K+sk)][fine cell]
@@ -346,8 +289,7 @@ __global__ void __launch_bounds__(256) k_prolong_add(T* __restrict__ x, const T*
   const int fp = (j + k) & 1;
   T* xe = x + fp * H + (row << hl) + I0;
   T* xo = x + (1 - fp) * H + (row << hl) + I0;
-  // even v: colour fp; odd v: the other colour.  Black is colour 1.
-  const bool even_black = fp == 1;
+  const bool even_black = fp == 1;  // black is colour 1
   Quad<T> qe, qo;
   if (!BLACK_ONLY || even_black) qe = ldq(xe);
   if (!BLACK_ONLY || !even_black) qo = ldq(xo);
@@ -370,79 +312,76 @@ __global__ void __launch_bounds__(256) k_prolong_add(T* __restrict__ x, const T*
   if (!BLACK_ONLY || !even_black) stq(xo, qo);
 }
 
-// ---------------------------------------------------------------- one-workgroup tail
+// Half sweep of one cell of colour `color` (t < C/2), for the 4^dim coarsest
+// grid, whose half rows (2 cells) are shorter than a 4-cell group.
 template <typename T, int DIM>
-__device__ void lds_rb_sweeps(T* x, const T* b, int logn, T c0, T c1, int sweeps, bool from_zero) {
+__device__ inline void rb_cell(T* __restrict__ x, const T* __restrict__ b, int logn, T c0, T c1, int color, int t) {
   const int C = 1 << (DIM * logn);
+  const int H = C >> 1;
+  const int hl = logn - 1;
+  const int mask = (1 << logn) - 1, hmask = (1 << hl) - 1;
+  const int m = t & hmask;
+  const int row = t >> hl;
+  const int j = row & mask;
+  const int k = DIM == 3 ? (row >> logn) : 0;
+  const int i = 2 * m + ((color + j + k) & 1);
+  const T* oth = x + (1 - color) * H;
+  const int ry0 = ((j - 1) & mask) | (k << logn), ry1 = ((j + 1) & mask) | (k << logn);
+  T sum = oth[(row << hl) + (((i - 1) & mask) >> 1)] + oth[(row << hl) + (((i + 1) & mask) >> 1)] +
+          oth[(ry0 << hl) + m] + oth[(ry1 << hl) + m];
+  if (DIM == 3) {
+    const int rz0 = j | (((k - 1) & mask) << logn), rz1 = j | (((k + 1) & mask) << logn);
+    sum += oth[(rz0 << hl) + m] + oth[(rz1 << hl) + m];
+  }
   const T inv_diag = T(1) / (c0 + T(2 * DIM) * c1);
-  if (from_zero) {
-    for (int c = threadIdx.x; c < C; c += blockDim.x) x[c] = T(0);
-    __syncthreads();
-  }
-  for (int s = 0; s < sweeps; ++s) {
-    for (int color = 0; color < 2; ++color) {
-      for (int t = threadIdx.x; t < C / 2; t += blockDim.x) {
-        int i, j, k;
-        colour_cell<DIM>(t, logn, color, i, j, k);
-        const int c = cell_index<DIM>(i, j, k, logn);
-        x[c] = (b[c] + c1 * nbr_sum<T, DIM>(x, i, j, k, logn)) * inv_diag;
-      }
-      __syncthreads();
-    }
-  }
+  x[color * H + (row << hl) + m] = (b[color * H + (row << hl) + m] + c1 * sum) * inv_diag;
 }
 
-template <typename T, int DIM>
-__device__ void lds_resid_restrict(const T* x, const T* b, T* bc, int logn, T c0, T c1) {
-  const int lognc = logn - 1;
-  const int Cc = 1 << (DIM * lognc);
-  const T diag = c0 + T(2 * DIM) * c1;
-  for (int t = threadIdx.x; t < Cc; t += blockDim.x) {
-    int I, J, K;
-    cell_coords<DIM>(t, lognc, I, J, K);
-    T acc = 0;
-    for (int dk = 0; dk < (DIM == 3 ? 2 : 1); ++dk)
-      for (int dj = 0; dj < 2; ++dj)
-        for (int di = 0; di < 2; ++di) {
-          const int i = 2 * I + di, j = 2 * J + dj, k = 2 * K + dk;
-          const int c = cell_index<DIM>(i, j, k, logn);
-          acc += b[c] - (diag * x[c] - c1 * nbr_sum<T, DIM>(x, i, j, k, logn));
-        }
-    bc[t] = acc * (DIM == 3 ? T(0.125) : T(0.25));
-  }
-  __syncthreads();
-}
-
-template <typename T, int DIM>
-__device__ void lds_prolong_add(T* x, const T* e, int logn) {
+// ---------------------------------------------------------------- level kernels
+// One group per thread, nfields batched in blockIdx.y.  FINE marks the finest
+// level (same code; a separate symbol for profiling).
+template <typename T, int DIM, bool FINE>
+__global__ void __launch_bounds__(256) k_rb(T* __restrict__ x, const T* __restrict__ b, int logn, T c0, T c1,
+                                            int color) {
   const int C = 1 << (DIM * logn);
-  const int lognc = logn - 1;
-  const T w0 = T(0.75), w1 = T(0.25);
-  for (int c = threadIdx.x; c < C; c += blockDim.x) {
-    int i, j, k;
-    cell_coords<DIM>(c, logn, i, j, k);
-    const int I = i >> 1, J = j >> 1, K = k >> 1;
-    const int si = (i & 1) ? 1 : -1, sj = (j & 1) ? 1 : -1, sk = (k & 1) ? 1 : -1;
-    T v;
-    if (DIM == 3) {
-      T a00 = w0 * e[cell_index<DIM>(I, J, K, lognc)] + w1 * e[cell_index<DIM>(I + si, J, K, lognc)];
-      T a10 = w0 * e[cell_index<DIM>(I, J + sj, K, lognc)] + w1 * e[cell_index<DIM>(I + si, J + sj, K, lognc)];
-      T a01 = w0 * e[cell_index<DIM>(I, J, K + sk, lognc)] + w1 * e[cell_index<DIM>(I + si, J, K + sk, lognc)];
-      T a11 = w0 * e[cell_index<DIM>(I, J + sj, K + sk, lognc)] +
-              w1 * e[cell_index<DIM>(I + si, J + sj, K + sk, lognc)];
-      T b0 = w0 * a00 + w1 * a10;
-      T b1 = w0 * a01 + w1 * a11;
-      v = w0 * b0 + w1 * b1;
-    } else {
-      T a0 = w0 * e[cell_index<DIM>(I, J, 0, lognc)] + w1 * e[cell_index<DIM>(I + si, J, 0, lognc)];
-      T a1 = w0 * e[cell_index<DIM>(I, J + sj, 0, lognc)] + w1 * e[cell_index<DIM>(I + si, J + sj, 0, lognc)];
-      v = w0 * a0 + w1 * a1;
-    }
-    x[c] += v;
-  }
-  __syncthreads();
+  const int g = flat_thread(gridDim.x);
+  if (g >= (C >> 3)) return;
+  const int64_t f = blockIdx.y;
+  rb_group<T, DIM>(x + f * C, b + f * C, logn, c0, c1, color, g);
 }
 
+template <typename T, int DIM, bool FINE>
+__global__ void __launch_bounds__(256) k_rb_first(T* __restrict__ x, const T* __restrict__ b, int logn, T c0,
+                                                  T c1) {
+  const int C = 1 << (DIM * logn);
+  const int g = flat_thread(gridDim.x);
+  if (g >= (C >> 3)) return;
+  const int64_t f = blockIdx.y;
+  rb_first_group<T, DIM>(x + f * C, b + f * C, logn, c0, c1, g);
+}
+
+template <typename T, int DIM>
+__global__ void __launch_bounds__(256) k_resid_restrict(const T* __restrict__ x, const T* __restrict__ b,
+                                                        T* __restrict__ bc, int logn, T c0, T c1) {
+  const int C = 1 << (DIM * logn);
+  const int Cc = C >> DIM;
+  const int g = flat_thread(gridDim.x);
+  if (g >= (Cc >> 2)) return;
+  const int64_t f = blockIdx.y;
+  restrict_group<T, DIM>(x + f * C, b + f * C, bc + f * Cc, logn, c0, c1, g);
+}
+
+template <typename T, int DIM, bool BLACK_ONLY>
+__global__ void __launch_bounds__(256) k_prolong_add(T* __restrict__ x, const T* __restrict__ e, int logn) {
+  const int C = 1 << (DIM * logn);
+  const int Cc = C >> DIM;
+  const int g = flat_thread(gridDim.x);
+  if (g >= (C >> 3)) return;
+  const int64_t f = blockIdx.y;
+  prolong_group<T, DIM, BLACK_ONLY>(x + f * C, e + f * Cc, logn, g);
+}
+
+// ---------------------------------------------------------------- one-workgroup tail
 template <typename T>
 __device__ void lds_remove_mean(T* b, int C, T* red) {
   T s = 0;
@@ -454,19 +393,22 @@ __device__ void lds_remove_mean(T* b, int C, T* red) {
   __syncthreads();
 }
 
-// V-cycle from a level of at most 4096 cells down to n = 4, one field per
-// workgroup, every array in LDS.  The entry level's b and x are in split
-// storage in global memory and are copied in (natural order) and out.  c1 is
-// the coefficient at the entry level.
+// V-cycle from the tail's entry level down to n = 4, one field per workgroup
+// of kLdsThreads threads, on split storage like the global levels: the
+// iterates of every tail level and the right-hand sides below the entry level
+// live in LDS; the entry level's right-hand side is read from global memory.
+// c1 is the coefficient at the entry level.
 template <typename T, int DIM>
 __global__ void __launch_bounds__(kLdsThreads) k_vcycle_lds(const T* __restrict__ bg, T* __restrict__ xg, int logn,
                                                             T c0, T c1, int nu_pre, int nu_post, int nu_coarse) {
-  constexpr int kMax = (int)lds_max_cells<T, DIM>();
-  constexpr int kX = (int)pyramid_cells<DIM>(kMax) + 64;
-  // x of every level back to back (entry level first); b of every level.
-  __shared__ T xs[kX];
-  __shared__ T bs[kX];
+  constexpr int kX = (int)pyramid_cells<DIM>(kTailMaxCells) + 64;
+  constexpr int kB = (int)pyramid_cells<DIM>(kTailMaxCells >> DIM) + 64;
+  __shared__ Quad<T> xs4[kX / 4];  // x of every level back to back, entry level first
+  __shared__ Quad<T> bs4[kB / 4];  // b of the levels below the entry level
   __shared__ T red[kLdsThreads / kWave];
+  T* xs = &xs4[0].v[0];
+  T* bs = &bs4[0].v[0];
+  const int tid = threadIdx.x, nt = blockDim.x;
   const int C0 = 1 << (DIM * logn);
   const T* b0 = bg + (int64_t)blockIdx.x * C0;
   T* x0 = xg + (int64_t)blockIdx.x * C0;
@@ -474,50 +416,82 @@ __global__ void __launch_bounds__(kLdsThreads) k_vcycle_lds(const T* __restrict_
 
   const int nlev = logn - 1;  // entry level down to n = 4
   int off[10];
+  T* bl[10];
   {
-    int o = 0;
+    int xo = 0, bo = 0;
     for (int l = 0; l < nlev; ++l) {
-      off[l] = o;
-      o += 1 << (DIM * (logn - l));
+      const int Cl = 1 << (DIM * (logn - l));
+      off[l] = xo;
+      xo += Cl;
+      bl[l] = nullptr;
+      if (l == 0 && nlev > 1) continue;  // the entry level reads b0
+      bl[l] = bs + bo;
+      bo += Cl;
     }
   }
-  auto xlev = [&](int l) -> T* { return xs + off[l]; };
-  auto blev = [&](int l) -> T* { return bs + off[l]; };
-  {
-    const int mask = (1 << logn) - 1;
-    for (int c = threadIdx.x; c < C0; c += blockDim.x) {
-      const int i = c & mask, j = (c >> logn) & mask, k = DIM == 3 ? (c >> (2 * logn)) : 0;
-      bs[c] = b0[split_index<DIM>(i, j, k, logn)];
-    }
+  if (nlev == 1) {
+    // the whole cycle is the coarsest grid: its b is modified (mean removal), take a copy
+    for (int c = tid; c < C0; c += nt) bl[0][c] = b0[c];
     __syncthreads();
   }
 
   T cl = c1;
   for (int l = 0; l < nlev - 1; ++l) {
     const int lg = logn - l;
-    lds_rb_sweeps<T, DIM>(xlev(l), blev(l), lg, c0, cl, nu_pre, true);
-    lds_resid_restrict<T, DIM>(xlev(l), blev(l), blev(l + 1), lg, c0, cl);
+    const int Cl = 1 << (DIM * lg);
+    T* x = xs + off[l];
+    const T* b = l == 0 ? b0 : bl[l];
+    if (nu_pre > 0) {
+      for (int g = tid; g < (Cl >> 3); g += nt) rb_first_group<T, DIM>(x, b, lg, c0, cl, g);
+      __syncthreads();
+      for (int sw = 1; sw < nu_pre; ++sw)
+        for (int color = 0; color < 2; ++color) {
+          for (int g = tid; g < (Cl >> 3); g += nt) rb_group<T, DIM>(x, b, lg, c0, cl, color, g);
+          __syncthreads();
+        }
+    } else {
+      for (int c = tid; c < Cl; c += nt) x[c] = T(0);
+      __syncthreads();
+    }
+    for (int g = tid; g < ((Cl >> DIM) >> 2); g += nt) restrict_group<T, DIM>(x, b, bl[l + 1], lg, c0, cl, g);
+    __syncthreads();
     cl = cl * T(0.25);
   }
   {
+    // coarsest grid (n = 4): nu_coarse sweeps from zero
     const int l = nlev - 1;
     const int lg = logn - l;
-    if (singular) lds_remove_mean<T>(blev(l), 1 << (DIM * lg), red);
-    lds_rb_sweeps<T, DIM>(xlev(l), blev(l), lg, c0, cl, nu_coarse, true);
+    const int Cl = 1 << (DIM * lg);
+    T* x = xs + off[l];
+    T* b = bl[l];
+    if (singular) lds_remove_mean<T>(b, Cl, red);
+    for (int c = tid; c < Cl; c += nt) x[c] = T(0);
+    __syncthreads();
+    for (int sw = 0; sw < nu_coarse; ++sw)
+      for (int color = 0; color < 2; ++color) {
+        for (int t = tid; t < (Cl >> 1); t += nt) rb_cell<T, DIM>(x, b, lg, c0, cl, color, t);
+        __syncthreads();
+      }
   }
   for (int l = nlev - 2; l >= 0; --l) {
     cl = cl * T(4);
     const int lg = logn - l;
-    lds_prolong_add<T, DIM>(xlev(l), xlev(l + 1), lg);
-    lds_rb_sweeps<T, DIM>(xlev(l), blev(l), lg, c0, cl, nu_post, false);
-  }
-  {
-    const int mask = (1 << logn) - 1;
-    for (int c = threadIdx.x; c < C0; c += blockDim.x) {
-      const int i = c & mask, j = (c >> logn) & mask, k = DIM == 3 ? (c >> (2 * logn)) : 0;
-      x0[split_index<DIM>(i, j, k, logn)] = xs[c];
+    const int Cl = 1 << (DIM * lg);
+    T* x = xs + off[l];
+    const T* b = l == 0 ? b0 : bl[l];
+    if (nu_post > 0) {
+      for (int g = tid; g < (Cl >> 3); g += nt) prolong_group<T, DIM, true>(x, xs + off[l + 1], lg, g);
+    } else {
+      for (int g = tid; g < (Cl >> 3); g += nt) prolong_group<T, DIM, false>(x, xs + off[l + 1], lg, g);
     }
+    __syncthreads();
+    for (int sw = 0; sw < nu_post; ++sw)
+      for (int color = 0; color < 2; ++color) {
+        for (int g = tid; g < (Cl >> 3); g += nt) rb_group<T, DIM>(x, b, lg, c0, cl, color, g);
+        __syncthreads();
+      }
   }
+  for (int q = tid; q < (C0 >> 2); q += nt) stq(x0 + 4 * q, ldq(xs + 4 * q));
 }
 
 // Per-field sums: partial[f][block] (deterministic two-pass reduction).
@@ -602,10 +576,9 @@ void MGHier<T>::init(int dim_, int logn_, int maxf) {
   logn = logn_;
   nfmax = maxf;
   levels.clear();
-  // multi-kernel levels: while the level has more cells than one workgroup holds
-  const int64_t cap = dim == 3 ? lds_max_cells<T, 3>() : lds_max_cells<T, 2>();
+  // multi-kernel levels: while the level has more cells than the tail starts from
   int lg = logn;
-  while (((int64_t)1 << (dim * lg)) > cap) {
+  while (((int64_t)1 << (dim * lg)) > kTailMaxCells) {
     levels.push_back(lg);
     --lg;
   }
@@ -631,9 +604,8 @@ void MGHier<T>::release() {
 template <typename T>
 size_t MGHier<T>::bytes(int dim, int logn, int nf) {
   size_t tot = 0;
-  const int64_t cap = dim == 3 ? lds_max_cells<T, 3>() : lds_max_cells<T, 2>();
   int lg = logn;
-  while (((int64_t)1 << (dim * lg)) > cap) --lg;
+  while (((int64_t)1 << (dim * lg)) > kTailMaxCells) --lg;
   for (int l = logn - 1; l >= lg; --l) tot += 2 * ((size_t)1 << (dim * l)) * nf * sizeof(T);
   return tot;
 }
