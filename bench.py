@@ -11,7 +11,11 @@ field).  Inputs are resident in HBM when the timed region starts.
 
 The headline value is the mixed-precision solver's solves/s (fp32
 preconditioner, fp64 outer FGMRES/Arnoldi/Hessenberg/mobility blocks); the
-plain fp64 solver runs the same trajectory for comparison.
+plain fp64 solver runs the same trajectory for comparison.  The ``served``
+object gives the served form: 8 independent simulations of the workload (one
+per seed, 20 steps each from rest) offered at once to the request server,
+with 4 workers whose solves overlap on the device, and with 1 worker (the
+plain solver), in both precisions.
 
     python bench.py [--steps K] [--warmup W] [--re 10] [--seed 0] [--no-cpu-baseline]
 """
@@ -53,7 +57,10 @@ def parse():
     ap.add_argument("--ablation", action="store_true",
                     help="solver study instead: preconditioner variant and N_s vs P_S^-1 applications")
     ap.add_argument("--nreq", type=int, default=2000, help="serving: requests in the trace")
-    ap.add_argument("--workers", type=int, default=4, help="serving: host worker threads")
+    ap.add_argument("--workers", type=int, default=4, help="serving and served form: host worker threads")
+    ap.add_argument("--served-trajectories", type=int, default=8,
+                    help="served form: independent simulations of the workload offered at once")
+    ap.add_argument("--no-served", action="store_true", help="skip the served-form leg")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (scale for the HBM byte counters)")
     return ap.parse_args()
@@ -172,6 +179,44 @@ def cpu_baseline(prob, nsteps=2):
                       "right-hand side, Fourier Stokes solves + CG on the 5280x5280 mobility system to 1e-8, "
                       "%s CG iterations), %.1f s single-threaded NumPy" %
                       (nsteps, "+".join(str(q.cg_iters) for q in sols), dt)}
+
+
+def served(args, torch):
+    """The served form of the 128^3 workload: independent simulations (seeds
+    seed .. seed + T - 1, each a trajectory of warmup + steps time steps from
+    rest) offered at once to the request server.  With W workers their
+    solves overlap on the device (one context and stream per worker); with
+    one worker the server is the plain solver, one simulation after another.
+    Every context is created before the timed region (prewarm)."""
+    from paper_1505_07865_amd import serve
+    from synthetic import config2_spheres_ns
+    nsteps = args.warmup + args.steps
+    probs = [config2_spheres_ns(args.seed + i, re=args.re) for i in range(args.served_trajectories)]
+    out = {"trajectories": len(probs), "steps_each": nsteps, "workers": args.workers}
+    for prec, workers, tag in (("fp64", 1, "fp64_plain"), ("mixed", 1, "mixed_plain"),
+                               ("fp64", args.workers, "fp64_served"), ("mixed", args.workers, "mixed_served")):
+        print("bench: served form, %s, %d worker(s), %d trajectories x %d steps" % (prec, workers, len(probs),
+                                                                                    nsteps),
+              file=sys.stderr, flush=True)
+        with serve.Server(precision=prec, workers=workers) as srv:
+            srv.prewarm(probs[:1])
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            futs = [srv.submit_trajectory(p, nsteps) for p in probs]
+            res = [f.result() for f in futs]
+            torch.cuda.synchronize()
+            total = time.perf_counter() - t0
+        steps = [st for r in res for st in r["steps"]]
+        lat = [st["wall_ms"] for st in steps]
+        out[tag] = {"solves_per_s": round(len(steps) / total, 3), "p50_step_ms": round(percentile(lat, 50), 3),
+                    "p99_step_ms": round(percentile(lat, 99), 3),
+                    "fgmres_iters_mean": round(sum(st["iters"] for st in steps) / len(steps), 2),
+                    "max_rel_residual": float("%.4g" % max(st["rel_residual"] for st in steps))}
+    out["mixed_served_over_fp64_plain"] = round(out["mixed_served"]["solves_per_s"] /
+                                                out["fp64_plain"]["solves_per_s"], 3)
+    out["mixed_served_over_fp64_served"] = round(out["mixed_served"]["solves_per_s"] /
+                                                 out["fp64_served"]["solves_per_s"], 3)
+    return out
 
 
 def serving(args, torch):
@@ -339,6 +384,8 @@ def main():
         line[p] = {k: (float("%.4g" % v) if isinstance(v, float) else v) for k, v in res[p].items() if k != "timers"}
     if "mixed" in res and "fp64" in res:
         line["mixed_over_fp64"] = round(res["mixed"]["solves_per_s"] / res["fp64"]["solves_per_s"], 3)
+    if args.precision == "both" and not args.no_served:
+        line["served"] = served(args, torch)
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle on the workload's first two steps", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(prob)

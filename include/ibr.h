@@ -142,6 +142,12 @@ ibr_status ibr_solve(ibr_ctx* ctx, int warm_start, ibr_info* info);
  * Bodies translate only: IBR_EINVAL if some Omega is nonzero. */
 ibr_status ibr_step(ibr_ctx* ctx, ibr_info* info);
 
+/* Start a new unsteady run (Sec. 7.6): the fluid at rest (v, pi and lambda
+ * zero) and no advection history, so the next ibr_step is the first step of
+ * a simulation (forward Euler advection).  Bodies, their current positions
+ * and velocities are kept.  No device allocation; IBR_EINVAL for NULL. */
+ibr_status ibr_reset(ibr_ctx* ctx);
+
 /* Copy the current solution to host arrays (any pointer may be NULL):
  * u[dim][n^dim], p[n^dim], lambda[N][dim], F[nb][dim], T[nb][3 or 1]. */
 ibr_status ibr_get_solution(ibr_ctx* ctx, double* u, double* p, double* lambda, double* F,

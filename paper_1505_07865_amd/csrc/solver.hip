@@ -1085,6 +1085,17 @@ ibr_status ibr_step(ibr_ctx* c, ibr_info* info) {
   return g != IBR_OK ? g : st;
 }
 
+ibr_status ibr_reset(ibr_ctx* c) {
+  if (!c) return IBR_EINVAL;
+  return guard(c, [&] {
+    IBR_HIP(hipSetDevice(c->p.device));
+    launch_fill<double>(c->Xs, c->NV, 0.0, c->stream);
+    c->have_solution = false;
+    c->have_prev = false;
+    sync(c);
+  });
+}
+
 ibr_status ibr_get_solution(ibr_ctx* c, double* u, double* pr, double* lambda, double* F, double* T) {
   if (!c) return IBR_EINVAL;
   return guard(c, [&] { get_solution_impl(c, u, pr, lambda, F, T, hipMemcpyDeviceToHost); });

@@ -52,7 +52,7 @@ EXPORTS = ["ibr_default_params", "ibr_status_string", "ibr_create", "ibr_destroy
            "ibr_step", "ibr_get_solution", "ibr_get_markers", "ibr_apply_operator", "ibr_spread",
            "ibr_interp", "ibr_vcycle", "ibr_precondition", "ibr_mobility_block", "ibr_advect",
            "ibr_timer_enable", "ibr_timer_read", "ibr_mobility_inverse", "ibr_set_rhs_dev",
-           "ibr_get_solution_dev"]
+           "ibr_get_solution_dev", "ibr_reset"]
 
 
 def _devptr(x):
@@ -100,6 +100,7 @@ def load(path=LIB_PATH):
         "ibr_set_rhs_dev": (ctypes.c_int, [vp, vp, vp]),
         "ibr_solve": (ctypes.c_int, [vp, ctypes.c_int, P(Info)]),
         "ibr_step": (ctypes.c_int, [vp, P(Info)]),
+        "ibr_reset": (ctypes.c_int, [vp]),
         "ibr_get_solution": (ctypes.c_int, [vp, dp, dp, dp, dp, dp]),
         "ibr_get_solution_dev": (ctypes.c_int, [vp, vp, vp, vp, vp, vp]),
         "ibr_get_markers": (ctypes.c_int, [vp, dp, dp]),
@@ -251,6 +252,10 @@ class Solver:
         if check:
             self._check(st, "ibr_step")
         return info.as_dict()
+
+    def reset(self):
+        """Fluid at rest and no advection history: the next step() starts a new run."""
+        self._check(self._lib.ibr_reset(self._ctx), "ibr_reset")
 
     def solution(self) -> Solution:
         d, n = self.dim, self.n

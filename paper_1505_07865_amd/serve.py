@@ -1,21 +1,25 @@
-"""Request server for independent steady constrained solves on one GPU.
+"""Request server for independent constrained solves on one GPU.
 
-A request is one rigid-body problem (grid, bodies, prescribed velocities);
-the answer is the drag force and torque on every body (and the solve report).
-Requests are independent, so the server scales by data parallelism over
-requests: several host worker threads each own resident solver contexts (one
-per grid size, every context with its own HIP stream) and take requests from
-one FIFO queue.  Small grids then overlap with large ones on the GPU, and no
-request pays for allocating or tearing down a context.
+A request is one rigid-body problem (grid, fluid parameters, bodies,
+prescribed velocities) and asks either for one steady solve (``submit``) or
+for an unsteady trajectory of several time steps from rest
+(``submit_trajectory``); the answer is the drag force and torque on every body
+and the solve reports.  Requests are independent, so the server scales by data
+parallelism over requests: several host worker threads each own resident
+solver contexts (one per grid size and fluid parameters, every context with
+its own HIP stream) and take requests from one FIFO queue as they arrive.
+While one request's solve waits on its stream, the others' kernels run: work
+of different requests overlaps on the device, small grids with large ones,
+and no request pays for allocating or tearing down a context.
 
 Admission: before a worker creates a context it checks the context's device
 footprint (``ibr_footprint_bytes``) against the free device memory minus a
 reserve, evicting its least recently used idle contexts first; a request that
 cannot fit even then fails with MemoryError.
 
-Every solve starts from a zero initial guess, so a request's result does not
-depend on what the context solved before: served alone or in a mix, it is
-bitwise the same.
+Every steady solve starts from a zero initial guess and every trajectory from
+a fluid at rest, so a request's result does not depend on what the context
+solved before: served alone or in a mix, it is bitwise the same.
 """
 import collections
 import queue
@@ -33,7 +37,7 @@ class _Worker(threading.Thread):
         self.contexts = collections.OrderedDict()   # (dim, n) -> solver, LRU order
 
     def _context(self, prob):
-        key = (prob.dim, prob.n)
+        key = _context_key(prob)
         if key in self.contexts:
             self.contexts.move_to_end(key)
             return self.contexts[key]
@@ -54,19 +58,35 @@ class _Worker(threading.Thread):
             item = srv.queue.get()
             if item is None:
                 break
-            rid, prob, t_arrive, fut = item
+            rid, prob, nsteps, fut = item
             try:
                 s = self._context(prob)
                 s.set_bodies(prob.R, prob.offsets, prob.centres)
                 s.set_velocities(prob.U, prob.Omega)
-                info = s.solve(warm_start=False)
-                F, T = s.forces()
-                fut._finish(result={"id": rid, "info": info, "F": F, "T": T, "worker": self.wid})
+                if nsteps is None:
+                    info = s.solve(warm_start=False)
+                    F, T = s.forces()
+                    fut._finish(result={"id": rid, "info": info, "F": F, "T": T, "worker": self.wid})
+                else:
+                    s.reset()
+                    steps = []
+                    for _ in range(nsteps):
+                        t0 = time.perf_counter()
+                        info = s.step()
+                        info["wall_ms"] = (time.perf_counter() - t0) * 1e3
+                        steps.append(info)
+                    F, T = s.forces()
+                    fut._finish(result={"id": rid, "steps": steps, "F": F, "T": T, "worker": self.wid})
             except BaseException as e:   # reported through the future
                 fut._finish(error=e)
         for s in self.contexts.values():
             s.close()
         self.contexts.clear()
+
+
+def _context_key(prob):
+    # contexts are shared by requests with the same grid and fluid parameters
+    return (prob.dim, prob.n, prob.h, prob.rho, prob.eta, prob.dt if prob.rho > 0 else 0.0)
 
 
 class Future:
@@ -101,6 +121,7 @@ class Server:
     factory(problem) -> solver object with set_bodies, set_velocities,
     solve(warm_start), forces() and close(); the default builds
     ``ibr.Solver`` contexts for steady Stokes with the given precision.
+    A trajectory request additionally needs reset() and step().
     footprint(problem) and free_bytes() default to the library's footprint
     query and the device's free memory.
     """
@@ -124,7 +145,7 @@ class Server:
     # ---------------------------------------------------------------- defaults
     def _params(self, prob):
         from . import ibr
-        return dict(dim=prob.dim, n=prob.n, h=prob.h, rho=0.0, eta=prob.eta, rtol=self.rtol,
+        return dict(dim=prob.dim, n=prob.n, h=prob.h, rho=prob.rho, eta=prob.eta, dt=prob.dt, rtol=self.rtol,
                     precision=ibr.MIXED if self.precision == "mixed" else ibr.FP64, device=self.device,
                     graphs=0, **self.solver_kw)
 
@@ -143,8 +164,19 @@ class Server:
 
     # ---------------------------------------------------------------- requests
     def submit(self, prob, t_arrive=None):
+        """One steady solve of prob from a zero initial guess (prob.rho == 0)."""
+        return self._put(prob, None, t_arrive)
+
+    def submit_trajectory(self, prob, nsteps, t_arrive=None):
+        """nsteps unsteady time steps of prob (prob.rho > 0) from a fluid at
+        rest; the result holds every step's solve report and the final forces."""
+        if nsteps < 1:
+            raise ValueError("a trajectory needs at least one step")
+        return self._put(prob, int(nsteps), t_arrive)
+
+    def _put(self, prob, nsteps, t_arrive):
         fut = Future(time.perf_counter() if t_arrive is None else t_arrive)
-        self.queue.put((self.next_id, prob, fut.t_arrive, fut))
+        self.queue.put((self.next_id, prob, nsteps, fut))
         self.next_id += 1
         return fut
 
@@ -166,14 +198,18 @@ class Server:
         request) so that no measured request pays for a context."""
         seen = {}
         for p in problems:
-            seen.setdefault((p.dim, p.n), p)
+            seen.setdefault(_context_key(p), p)
         for w in self.workers:
             for key, p in seen.items():
                 if key not in w.contexts:
                     s = w._context(p)
                     s.set_bodies(p.R, p.offsets, p.centres)
                     s.set_velocities(p.U, p.Omega)
-                    s.solve(warm_start=False)
+                    if p.rho > 0:
+                        s.reset()
+                        s.step()
+                    else:
+                        s.solve(warm_start=False)
 
 
 def _percentile(xs, q):

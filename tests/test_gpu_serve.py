@@ -28,3 +28,30 @@ def test_served_equals_alone(precision):
         assert r["info"]["rel_residual"] <= 1e-8
         assert r["info"]["iters"] == info["iters"]
         assert np.array_equal(r["F"], F) and np.array_equal(r["T"], T)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_served_trajectories_equal_alone(precision):
+    """Unsteady trajectories (from rest, 4 steps) served by 2 workers among
+    steady requests, with contexts reused between trajectories (ibr_reset),
+    equal the same trajectories run alone in fresh contexts, bitwise."""
+    from paper_1505_07865_amd import ibr, serve
+    from synthetic import config2_spheres_ns
+    probs = [config2_spheres_ns(seed, re=10.0, n=32, nbodies=3, radius_h=4.0, nmark=50, nsteps=4)
+             for seed in range(4)]
+    steady = [r["problem"] for r in serving_trace(2, 3, 1.0)]
+    print("trajectories", precision, [p.nmarkers for p in probs], "steady", [(p.dim, p.n) for p in steady],
+          flush=True)
+    with serve.Server(precision=precision, workers=2, reserve_bytes=1 << 30) as srv:
+        futs = [srv.submit_trajectory(p, 4) for p in probs[:2]] + [srv.submit(p) for p in steady] + \
+               [srv.submit_trajectory(p, 4) for p in probs[2:]]
+        res = [f.result() for f in futs]
+    traj = res[:2] + res[-2:]
+    for p, r in zip(probs, traj):
+        s = ibr.from_problem(p, rtol=1e-8, precision=ibr.MIXED if precision == "mixed" else ibr.FP64, graphs=0)
+        infos = [s.step() for _ in range(4)]
+        F, T = s.forces()
+        s.close()
+        assert [st["iters"] for st in r["steps"]] == [i["iters"] for i in infos]
+        assert all(st["rel_residual"] <= 1e-8 for st in r["steps"])
+        assert np.array_equal(r["F"], F) and np.array_equal(r["T"], T)

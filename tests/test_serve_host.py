@@ -32,14 +32,22 @@ class FakeSolver:
         return {"iters": 1, "rel_residual": 0.0}
 
     def forces(self):
-        return self.U * 2.0, np.zeros((len(self.U), 1))
+        return self.U * 2.0 + getattr(self, "t", 0), np.zeros((len(self.U), 1))
+
+    def reset(self):
+        self.t = 0
+
+    def step(self):
+        self.t += 1
+        time.sleep(self.delay)
+        return {"iters": 1, "rel_residual": 0.0}
 
     def close(self):
         self.closed = True
 
 
-def _prob(dim, n, nb=1, u=1.0):
-    return SimpleNamespace(dim=dim, n=n, h=1.0 / n, eta=1.0, nbodies=nb, nmarkers=4 * nb,
+def _prob(dim, n, nb=1, u=1.0, rho=0.0, dt=0.0):
+    return SimpleNamespace(dim=dim, n=n, h=1.0 / n, rho=rho, eta=1.0, dt=dt, nbodies=nb, nmarkers=4 * nb,
                            R=np.zeros((4 * nb, dim)), offsets=np.arange(0, 4 * nb + 1, 4),
                            centres=np.zeros((nb, dim)), U=np.full((nb, dim), u),
                            Omega=np.zeros((nb, 1)))
@@ -101,3 +109,23 @@ def test_replay_latency_and_throughput():
         assert 0 < out["p50_ms"] <= out["p99_ms"] < 1000
         sat = serve.replay(trace, srv, qps=None)
         assert sat["solves_per_s"] > 0
+
+
+def test_trajectories_restart_from_rest_on_shared_contexts():
+    FakeSolver.created = []
+    probs = [_prob(3, 16, u=i, rho=1.0, dt=0.5 / 16) for i in range(6)]
+    with serve.Server(workers=2, factory=lambda p: FakeSolver(p, delay=0.001), footprint=lambda p: 1,
+                      free_bytes=lambda: 1 << 40, reserve_bytes=0) as srv:
+        futs = [srv.submit_trajectory(p, 3 + i % 2) for i, p in enumerate(probs)]
+        steady = srv.submit(_prob(3, 16, u=7)).result(timeout=10)
+        res = [f.result(timeout=10) for f in futs]
+        with pytest.raises(ValueError):
+            srv.submit_trajectory(probs[0], 0)
+    for i, (p, r) in enumerate(zip(probs, res)):
+        # every trajectory starts from rest, whatever its context ran before
+        assert len(r["steps"]) == 3 + i % 2
+        assert np.array_equal(r["F"], p.U * 2.0 + 3 + i % 2)
+        assert all(st["wall_ms"] >= 0 for st in r["steps"])
+    assert np.array_equal(steady["F"], np.full((1, 3), 14.0))
+    # unsteady and steady problems of one grid use different contexts: at most 2 per worker
+    assert len(FakeSolver.created) <= 4
