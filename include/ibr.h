@@ -142,6 +142,26 @@ ibr_status ibr_solve(ibr_ctx* ctx, int warm_start, ibr_info* info);
  * Bodies translate only: IBR_EINVAL if some Omega is nonzero. */
 ibr_status ibr_step(ibr_ctx* ctx, ibr_info* info);
 
+/* Free kinematics (Sec. 2 poses it; Sec. 8 names the enlarged system and its
+ * body mobility (K* M^-1 K)^-1, approximated here per body): free[p] != 0
+ * makes body p move under the applied force F[p][dim] and torque
+ * T[p][1 or 3] instead of its prescribed velocity (which is ignored); its
+ * linear and angular velocities become unknowns of the solve, and at the
+ * solution the body hands exactly (F_p, T_p) to the fluid.  The stacked
+ * vector of ibr_apply_operator and ibr_precondition then gains a body block
+ * after lambda: U[nb][dim], then Omega[nb][1 or 3] (identity rows for the
+ * prescribed bodies).  free == NULL (or all zero) returns every body to
+ * prescribed motion.  Call after ibr_set_bodies, which resets it.  Steady or
+ * unsteady ibr_solve only: ibr_step refuses free bodies (IBR_EINVAL).
+ * IBR_EFACTOR if a body's approximate body mobility is not positive definite
+ * (the bodies are then all prescribed again).  Allocates device memory. */
+ibr_status ibr_set_free_bodies(ibr_ctx* ctx, const int* free, const double* F, const double* T);
+
+/* Rigid velocities of every body: U[nb][dim], Omega[nb][1 or 3] (either may
+ * be NULL).  Free bodies: the velocities of the last solve; prescribed
+ * bodies: the ones set by ibr_set_velocities. */
+ibr_status ibr_get_velocities(ibr_ctx* ctx, double* U, double* Omega);
+
 /* Start a new unsteady run (Sec. 7.6): the fluid at rest (v, pi and lambda
  * zero) and no advection history, so the next ibr_step is the first step of
  * a simulation (forward Euler advection).  Bodies, their current positions
@@ -164,7 +184,9 @@ ibr_status ibr_get_markers(ibr_ctx* ctx, double* R, double* centres);
 /* ---- single-operator entry points (same layouts; used for kernel parity) ---- */
 
 /* y = K x for the stacked vector x = [u (dim n^dim), p (n^dim), lambda (N dim)],
- * K the matrix of eq. constrained_Stokes (S' when steady). */
+ * K the matrix of eq. constrained_Stokes (S' when steady); with free bodies
+ * (ibr_set_free_bodies) x and y end with the body block, and K is the
+ * enlarged free-kinematics matrix. */
 ibr_status ibr_apply_operator(ibr_ctx* ctx, const double* x, double* y);
 
 /* f = S lambda (Sec. 3.1, eq. S_unweighted; no mean removal): f[dim][n^dim]. */

@@ -19,9 +19,15 @@ Schur-complement preconditioner for a residual (r_v, r_p, r_L), Sec. 5.1:
     2. dU = -(J v + r_L)
     3. Lambda = M~^-1 dU, block by block (per body)
     4. (full variant only) re-solve the fluid problem with r_v + S' Lambda
+With free bodies (module ``free``) step 3 becomes, for each free body, the
+per-body block Sec. 8 proposes: the small saddle problem
+M~ Lambda - K U = dU, K* Lambda = r_U, solved as U = N~ (r_U - K* M~^-1 dU),
+Lambda = M~^-1 (dU + K U) with N~ = (K* M~^-1 K)^-1; prescribed bodies pass
+their body rows through (z_U = r_U).
 """
 import numpy as np
 
+from . import free as free_mod
 from . import grid, mobility, multigrid, stokes
 
 
@@ -97,7 +103,8 @@ def stokes_gmres(g, hp, c0, eta, h, ns, mg=None):
 class SchurPreconditioner:
     """Sec. 5.1 preconditioner for one problem (steady periodic uses S')."""
 
-    def __init__(self, sysm, offsets, mob_blocks, mob_params, ns=2, full=False, mg=None):
+    def __init__(self, sysm, offsets, mob_blocks, mob_params, ns=2, full=False, mg=None, free=None,
+                 centres=None):
         self.s = sysm
         self.offsets = offsets
         self.ns = ns
@@ -110,6 +117,20 @@ class SchurPreconditioner:
             Lc, sh = mobility.factor_block(M, f0)
             self.factors.append(Lc)
             self.shifts.append(sh)
+        # free bodies: K_p, Y_p = M~_p^-1 K_p and N~_p = (K_p* Y_p)^-1
+        self.free = None if free is None or not np.any(free) else [bool(f) for f in free]
+        self.body_blocks = {}
+        if self.free:
+            L = sysm.n * sysm.h
+            for b, fr in enumerate(self.free):
+                if not fr:
+                    continue
+                lo, hi = offsets[b], offsets[b + 1]
+                d = sysm.d
+                Kb = free_mod.rigid_matrix(sysm.R, offsets, centres, L, [b])[lo * d:hi * d]
+                Lc = self.factors[b]
+                Y = np.linalg.solve(Lc.T, np.linalg.solve(Lc, Kb))
+                self.body_blocks[b] = (Kb, Y, np.linalg.inv(Kb.T @ Y))
 
     def mobility_solve(self, dU):
         lam = np.zeros_like(dU)
@@ -121,17 +142,33 @@ class SchurPreconditioner:
             lam[lo:hi] = np.linalg.solve(Lc.T, y).reshape(-1, d)
         return lam
 
-    def apply(self, rv, rp, rl):
+    def apply(self, rv, rp, rl, ru=None):
+        """z = P r.  With free bodies ru [nb, d + rotations] holds the body
+        rows of r (force then torque rows per body) and the body rows of z
+        are returned as a fourth value in the same layout."""
         s = self.s
         v, p = stokes_gmres(rv, rp, s.c0, s.eta, s.h, self.ns, self.mg)
         dU = -(s.interp(v) + rl)
         lam = self.mobility_solve(dU)
+        zu = None
+        if self.free:
+            zu = np.array(ru, dtype=np.float64, copy=True)
+            d = s.d
+            for b, (Kb, Y, Nb) in self.body_blocks.items():
+                lo, hi = self.offsets[b], self.offsets[b + 1]
+                t = lam[lo:hi].reshape(-1)
+                U = Nb @ (ru[b] - Kb.T @ t)
+                lam[lo:hi] = (t + Y @ U).reshape(-1, d)
+                zu[b] = U
         if self.full:
             v, p = stokes_gmres(rv + s.spread(lam), rp, s.c0, s.eta, s.h, self.ns, self.mg)
+        if self.free:
+            return v, p, lam, zu
         return v, p, lam
 
 
-def for_problem(prob, sysm, ns=2, full=False, mg=None, R=None):
+def for_problem(prob, sysm, ns=2, full=False, mg=None, R=None, free=None):
     blocks, p = mobility.blocks_for_problem(prob, R=R)
-    return SchurPreconditioner(sysm, prob.offsets, blocks, p, ns=ns, full=full, mg=mg)
+    return SchurPreconditioner(sysm, prob.offsets, blocks, p, ns=ns, full=full, mg=mg, free=free,
+                               centres=prob.centres)
 

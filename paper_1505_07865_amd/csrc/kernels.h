@@ -98,6 +98,24 @@ struct MGHier {
   void rb_first(T* x, const T* b, int lg, int nf, T c0, T c1, bool fine, hipStream_t s);
 };
 
+// ---------------------------------------------------------------- free kinematics
+// Body block of the stacked vector: U[nb][dim] then Omega[nb][1 or 3].
+// y_L += K U on free bodies' markers; y_U = K* lam (free) or x_U (prescribed).
+template <typename TI>
+void launch_free_apply(int dim, int N, int nb, const int* off, const int* body, const double* R, const double* X,
+                       double L, const int* free_b, const double* lam, const TI* xu, const TI* xo, double* yl,
+                       double* yu, double* yo, hipStream_t s);
+// Y = M~^-1 K and N~ = (K* Y)^-1 per free body; fail[b] set when K* Y is not SPD.
+void launch_free_setup(int dim, int nb, const int* off, const int64_t* moff, const double* Minv, const double* R,
+                       const double* X, double L, const int* free_b, const int64_t* yoff, double* Y, double* Nm,
+                       int* fail, hipStream_t s);
+// Per-body step of the preconditioner (lam = M~^-1 dU on entry).
+template <typename TZ>
+void launch_free_precond(int dim, int nb, const int* off, const double* R, const double* X, double L,
+                         const int* free_b, const int64_t* yoff, const double* Y, const double* Nm, const double* ru,
+                         const double* ro, double* lam, TZ* zu, TZ* zo, hipStream_t s);
+void launch_free_zero_markers(int dim, int N, const int* body, const int* free_b, double* W, hipStream_t s);
+
 // ---------------------------------------------------------------- markers / IB
 // Per-marker interpolation data: for every dimension beta the first tap index
 // (not wrapped) and the 4 weights, for the cell-centred (c) and the face (f)

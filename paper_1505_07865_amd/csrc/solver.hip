@@ -96,6 +96,15 @@ struct ibr_ctx {
   bool have_solution = false;
   bool rotating = false;  // some body has Omega != 0
 
+  // free kinematics: bodies moving under applied loads (body block after Lambda)
+  std::vector<int> free_h;
+  int nfree = 0;
+  int64_t nq = 0;  // length of the body block: nb (dim + rotations) once some body is free, else 0
+  int* free_d = nullptr;
+  int64_t* yoff_d = nullptr;
+  double *Yf = nullptr, *Nf = nullptr;
+  std::vector<double> load_h;  // applied loads in the body-block layout (0 for prescribed bodies)
+
   // outer Krylov
   int m = 0;
   double* Vb = nullptr;
@@ -134,6 +143,7 @@ struct ibr_ctx {
   void alloc_grid();
   void alloc_markers(int Nnew);
   void free_markers();
+  void clear_free();
   template <typename T>
   T* track(int64_t count) {
     bytes += count * (int64_t)sizeof(T);
@@ -178,6 +188,11 @@ void apply_K(ibr_ctx* c, const TI* x, double* y) {
   launch_spread<double, double>(d, c->logn, c->tile_log, c->act_cap, c->active, c->nactive_d, c->toff, c->perm,
                                 c->taps, c->lamd, y, -std::pow(c->h, -d), s);
   launch_interp<TI>(d, c->logn, c->N, c->taps, xv, -1.0, nullptr, 0.0, y + c->NF, s);
+  if (c->nq) {
+    const int64_t ub = c->NF + (int64_t)d * c->N;
+    launch_free_apply<TI>(d, c->N, c->nb, c->off_d, c->body_d, c->R, c->X, c->L, c->free_d, c->lamd, x + ub,
+                          x + ub + (int64_t)c->nb * d, y + c->NF, y + ub, y + ub + (int64_t)c->nb * d, s);
+  }
 }
 
 // ---------------------------------------------------------------- P_S^-1
@@ -273,6 +288,12 @@ void precondition(ibr_ctx* c, const double* r, T* z) {
   // slip dU = -(J v + r_L)
   launch_interp<T>(d, c->logn, c->N, c->taps, z, -1.0, r + NF, -1.0, c->dU, s);
   launch_mob_apply(c->nb, c->off_d, d, c->moff_d, c->Minv, c->dU, c->lamd, c->max_rows, s);
+  if (c->nq) {
+    // free bodies: U = N~ (r_U - K* Lambda), Lambda += Y U; the body block of z
+    const int64_t ub = NF + (int64_t)d * c->N;
+    launch_free_precond<T>(d, c->nb, c->off_d, c->R, c->X, c->L, c->free_d, c->yoff_d, c->Yf, c->Nf, r + ub,
+                           r + ub + (int64_t)c->nb * d, c->lamd, z + ub, z + ub + (int64_t)c->nb * d, s);
+  }
   if (c->p.pc == IBR_PC_FULL) {
     // second fluid solve with r_v + S' Lambda
     launch_spread<double, T>(d, c->logn, c->tile_log, c->act_cap, c->active, c->nactive_d, c->toff, c->perm,
@@ -549,6 +570,12 @@ void build_rhs_markers(ibr_ctx* c) {
   launch_marker_velocity(c->dim, c->N, c->R, c->body_d, c->X, c->U, c->Om, c->L, c->Vm, c->stream);
   launch_copy<double, double>(c->Vm, c->Bs + c->NF, (int64_t)c->N * c->dim, c->stream);
   launch_axpby(c->Vm, c->Bs + c->NF, (int64_t)c->N * c->dim, -1.0, 0.0, c->stream);
+  if (c->nq) {
+    // free bodies: no prescribed marker velocity; their rows of the body block carry the applied load
+    launch_free_zero_markers(c->dim, c->N, c->body_d, c->free_d, c->Bs + c->NF, c->stream);
+    IBR_HIP(hipMemcpyAsync(c->Bs + c->NF + (int64_t)c->dim * c->N, c->load_h.data(), c->nq * sizeof(double),
+                           hipMemcpyHostToDevice, c->stream));
+  }
 }
 
 template <typename F>
@@ -604,7 +631,22 @@ ibr_ctx::~ibr_ctx() {
   if (own_stream && stream) (void)hipStreamDestroy(stream);
 }
 
+void ibr_ctx::clear_free() {
+  dev_free(free_d);
+  dev_free(yoff_d);
+  dev_free(Yf);
+  dev_free(Nf);
+  free_d = nullptr;
+  yoff_d = nullptr;
+  Yf = Nf = nullptr;
+  free_h.clear();
+  load_h.clear();
+  nfree = 0;
+  nq = 0;
+}
+
 void ibr_ctx::free_markers() {
+  clear_free();
   for (void* q : {(void*)off_d, (void*)body_d, (void*)R, (void*)X, (void*)U, (void*)Om, (void*)Vm, (void*)taps.base,
                   (void*)taps.w64, (void*)taps.w32, (void*)tile_of, (void*)counts, (void*)toff, (void*)cursor,
                   (void*)perm, (void*)flags, (void*)active, (void*)nactive_d, (void*)moff_d, (void*)Mb, (void*)Lb,
@@ -697,7 +739,9 @@ void ibr_ctx::alloc_markers(int Nnew) {
   Zb = nullptr;
   Ncap = 0;
   Ncap = cap;
-  const int64_t NVc = NF + (int64_t)d * cap;
+  // Lambda (dim per marker) and room for the body block of free kinematics
+  // (dim + rotations per body, at most one body per marker)
+  const int64_t NVc = NF + (int64_t)(d + d + (d == 3 ? 3 : 1)) * cap;
   R = track<double>((int64_t)cap * d);
   Vm = track<double>((int64_t)cap * d);
   body_d = track<int>(cap);
@@ -815,7 +859,7 @@ size_t ibr_footprint_bytes(const ibr_params* p, int nbodies, int nmarkers) {
   const int d = p->dim;
   const int64_t C = (int64_t)1 << (d * ilog2(p->n));
   const int64_t NF = (int64_t)(d + 1) * C;
-  const int64_t NV = NF + (int64_t)d * std::max(nmarkers, 16);
+  const int64_t NV = NF + (int64_t)(d + d + (d == 3 ? 3 : 1)) * std::max(nmarkers, 16);
   const int m = p->restart > 0 ? p->restart : 100;
   const int ns = p->n_s > 0 ? p->n_s : 2;
   const int64_t ts = p->precision == IBR_MIXED ? 4 : 8;
@@ -879,6 +923,7 @@ ibr_status ibr_set_bodies(ibr_ctx* c, int nbodies, const int* offsets, const dou
     drop(c->act_d);
     drop(c->fail_d);
     c->N = 0;
+    c->clear_free();
     c->drop_graphs();
     ++c->graph_version;
     c->act_cap = 0;
@@ -1061,6 +1106,7 @@ ibr_status ibr_step(ibr_ctx* c, ibr_info* info) {
     require_bodies(c);
     if (c->steady) throw Status(IBR_ESTATE, "ibr_step needs rho > 0 (unsteady)");
     if (c->rotating) throw Status(IBR_EINVAL, "ibr_step translates the bodies: Omega must be zero");
+    if (c->nfree) throw Status(IBR_EINVAL, "ibr_step moves bodies with prescribed velocities only: no free bodies");
     IBR_HIP(hipSetDevice(c->p.device));
     hipStream_t s = c->stream;
     const int d = c->dim;
@@ -1083,6 +1129,102 @@ ibr_status ibr_step(ibr_ctx* c, ibr_info* info) {
     c->have_prev = true;
   });
   return g != IBR_OK ? g : st;
+}
+
+ibr_status ibr_set_free_bodies(ibr_ctx* c, const int* free_mask, const double* F, const double* T) {
+  if (!c) return IBR_EINVAL;
+  return guard(c, [&] {
+    require_bodies(c);
+    const int d = c->dim, nb = c->nb;
+    const int nr = d == 3 ? 3 : 1;
+    int nfree = 0;
+    if (free_mask) {
+      for (int b = 0; b < nb; ++b) nfree += free_mask[b] != 0;
+      if (nfree && (!F || !T)) throw Status(IBR_EINVAL, "F and T are required for free bodies");
+      for (int b = 0; b < nb && nfree; ++b) {
+        if (!free_mask[b]) continue;
+        for (int a = 0; a < d; ++a)
+          if (!std::isfinite(F[b * d + a])) throw Status(IBR_EINVAL, "F must be finite");
+        for (int a = 0; a < nr; ++a)
+          if (!std::isfinite(T[b * nr + a])) throw Status(IBR_EINVAL, "T must be finite");
+      }
+    }
+    IBR_HIP(hipSetDevice(c->p.device));
+    hipStream_t s = c->stream;
+    sync(c);
+    c->clear_free();
+    c->drop_graphs();
+    ++c->graph_version;
+    if (nfree) {
+      c->free_h.assign(free_mask, free_mask + nb);
+      for (int& f : c->free_h) f = f != 0;
+      c->nfree = nfree;
+      c->nq = (int64_t)nb * (d + nr);
+      c->load_h.assign(c->nq, 0.0);
+      std::vector<int64_t> yoff(nb + 1, 0);
+      for (int b = 0; b < nb; ++b) {
+        const int64_t rows = c->free_h[b] ? (int64_t)d * (c->off_h[b + 1] - c->off_h[b]) : 0;
+        yoff[b + 1] = yoff[b] + rows * (d + nr);
+        if (c->free_h[b]) {
+          for (int a = 0; a < d; ++a) c->load_h[b * d + a] = F[b * d + a];
+          for (int a = 0; a < nr; ++a) c->load_h[(int64_t)nb * d + b * nr + a] = T[b * nr + a];
+        }
+      }
+      c->free_d = dev_alloc<int>(nb);
+      c->yoff_d = dev_alloc<int64_t>(nb + 1);
+      c->Yf = dev_alloc<double>(std::max<int64_t>(yoff[nb], 1));
+      c->Nf = dev_alloc<double>((int64_t)nb * (d + nr) * (d + nr));
+      IBR_HIP(hipMemcpyAsync(c->free_d, c->free_h.data(), nb * sizeof(int), hipMemcpyHostToDevice, s));
+      IBR_HIP(hipMemcpyAsync(c->yoff_d, yoff.data(), (nb + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+      launch_fill<int>(c->fail_d, nb, 0, s);
+      launch_free_setup(d, nb, c->off_d, c->moff_d, c->Minv, c->R, c->X, c->L, c->free_d, c->yoff_d, c->Yf, c->Nf,
+                        c->fail_d, s);
+      std::vector<int> fail(nb, 0);
+      IBR_HIP(hipMemcpyAsync(fail.data(), c->fail_d, nb * sizeof(int), hipMemcpyDeviceToHost, s));
+      sync(c);
+      for (int b = 0; b < nb; ++b)
+        if (c->free_h[b] && fail[b]) {
+          c->clear_free();
+          c->NV = c->NF + (int64_t)d * c->N;
+          build_rhs_markers(c);
+          sync(c);
+          throw Status(IBR_EFACTOR, "body mobility of free body " + std::to_string(b) + " is not positive definite");
+        }
+    }
+    c->NV = c->NF + (int64_t)d * c->N + c->nq;
+    c->ldv = (c->NV + 63) & ~(int64_t)63;
+    // a new unknown set: no warm start across it
+    launch_fill<double>(c->Xs, c->NV, 0.0, s);
+    c->have_solution = false;
+    build_rhs_markers(c);
+    sync(c);
+  });
+}
+
+ibr_status ibr_get_velocities(ibr_ctx* c, double* U, double* Omega) {
+  if (!c) return IBR_EINVAL;
+  return guard(c, [&] {
+    require_bodies(c);
+    if (!U && !Omega) return;
+    IBR_HIP(hipSetDevice(c->p.device));
+    const int d = c->dim, nb = c->nb;
+    const int nr = d == 3 ? 3 : 1;
+    hipStream_t s = c->stream;
+    std::vector<double> u((size_t)nb * d), w((size_t)nb * nr), q((size_t)c->nq);
+    IBR_HIP(hipMemcpyAsync(u.data(), c->U, u.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    IBR_HIP(hipMemcpyAsync(w.data(), c->Om, w.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    if (c->nq)
+      IBR_HIP(hipMemcpyAsync(q.data(), c->Xs + c->NF + (int64_t)d * c->N, q.size() * sizeof(double),
+                             hipMemcpyDeviceToHost, s));
+    sync(c);
+    for (int b = 0; b < nb; ++b) {
+      const bool fr = c->nq && c->free_h[b];
+      for (int a = 0; a < d; ++a)
+        if (U) U[b * d + a] = fr ? q[b * d + a] : u[b * d + a];
+      for (int a = 0; a < nr; ++a)
+        if (Omega) Omega[b * nr + a] = fr ? q[(size_t)nb * d + b * nr + a] : w[b * nr + a];
+    }
+  });
 }
 
 ibr_status ibr_reset(ibr_ctx* c) {

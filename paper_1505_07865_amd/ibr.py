@@ -52,7 +52,7 @@ EXPORTS = ["ibr_default_params", "ibr_status_string", "ibr_create", "ibr_destroy
            "ibr_step", "ibr_get_solution", "ibr_get_markers", "ibr_apply_operator", "ibr_spread",
            "ibr_interp", "ibr_vcycle", "ibr_precondition", "ibr_mobility_block", "ibr_advect",
            "ibr_timer_enable", "ibr_timer_read", "ibr_mobility_inverse", "ibr_set_rhs_dev",
-           "ibr_get_solution_dev", "ibr_reset"]
+           "ibr_get_solution_dev", "ibr_reset", "ibr_set_free_bodies", "ibr_get_velocities"]
 
 
 def _devptr(x):
@@ -101,6 +101,8 @@ def load(path=LIB_PATH):
         "ibr_solve": (ctypes.c_int, [vp, ctypes.c_int, P(Info)]),
         "ibr_step": (ctypes.c_int, [vp, P(Info)]),
         "ibr_reset": (ctypes.c_int, [vp]),
+        "ibr_set_free_bodies": (ctypes.c_int, [vp, ip, dp, dp]),
+        "ibr_get_velocities": (ctypes.c_int, [vp, dp, dp]),
         "ibr_get_solution": (ctypes.c_int, [vp, dp, dp, dp, dp, dp]),
         "ibr_get_solution_dev": (ctypes.c_int, [vp, vp, vp, vp, vp, vp]),
         "ibr_get_markers": (ctypes.c_int, [vp, dp, dp]),
@@ -176,6 +178,7 @@ class Solver:
         self.C = self.n ** self.dim
         self.N = 0
         self.nb = 0
+        self.nq = 0
 
     def close(self):
         if self._ctx:
@@ -201,7 +204,7 @@ class Solver:
 
     @property
     def NV(self):
-        return (self.dim + 1) * self.C + self.dim * self.N
+        return (self.dim + 1) * self.C + self.dim * self.N + self.nq
 
     # ------------------------------------------------------------ problem
     def set_bodies(self, R, offsets, centres):
@@ -213,7 +216,31 @@ class Solver:
                                              _dptr(R), _dptr(X)), "ibr_set_bodies")
         self.N = int(off[-1])
         self.nb = nb
+        self.nq = 0
         self._offsets = off.copy()
+
+    def set_free_bodies(self, free=None, F=None, T=None):
+        """Bodies with free[p] move under the applied force F[p] and torque
+        T[p] (their velocities become unknowns); free=None makes every body
+        prescribed again."""
+        nr = 3 if self.dim == 3 else 1
+        if free is None or not np.any(free):
+            self._check(self._lib.ibr_set_free_bodies(self._ctx, None, None, None), "ibr_set_free_bodies")
+            self.nq = 0
+            return
+        fm = np.ascontiguousarray(np.asarray(free) != 0, dtype=np.int32)
+        F = _f64(F).reshape(self.nb, self.dim)
+        T = _f64(T).reshape(self.nb, nr)
+        self._check(self._lib.ibr_set_free_bodies(self._ctx, fm.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                                                  _dptr(F), _dptr(T)), "ibr_set_free_bodies")
+        self.nq = self.nb * (self.dim + nr)
+
+    def velocities(self):
+        """(U [nb, dim], Omega [nb, 1 or 3]): solved for free bodies, prescribed otherwise."""
+        U = np.zeros((self.nb, self.dim))
+        Om = np.zeros((self.nb, 3 if self.dim == 3 else 1))
+        self._check(self._lib.ibr_get_velocities(self._ctx, _dptr(U), _dptr(Om)), "ibr_get_velocities")
+        return U, Om
 
     def set_velocities(self, U, Omega):
         U = _f64(U).reshape(self.nb, self.dim)

@@ -130,3 +130,38 @@ def test_cg_route_equals_dense_route(rng):
     assert np.abs(a.lam - b.lam).max() <= 1e-9 * np.abs(a.lam).max()
     assert np.abs(np.concatenate([Ua, Oa], 1) - np.concatenate([Ub, Ob], 1)).max() <= \
         1e-9 * np.abs(np.concatenate([Ua, Oa], 1)).max()
+
+
+@pytest.mark.parametrize("case", [dict(dim=2, n=32, radius_h=4.0, nbodies=3),
+                                  dict(dim=3, n=16, radius_h=2.5, nbodies=2)])
+def test_preconditioner_body_step_solves_its_saddle_problem(case, rng):
+    """The per-body step of the preconditioner with free bodies solves
+    M~_p Lambda_p - K_p U_p = dU_p and K_p* Lambda_p = r_U,p exactly, and
+    passes prescribed bodies' rows through."""
+    from oracle import mobility, precond
+    prob = small_problem(19, **case)
+    nb, d = prob.nbodies, prob.dim
+    mask = [1, 0] + [1] * (nb - 2)
+    sysm = constrained.System.from_problem(prob)
+    P = precond.for_problem(prob, sysm, ns=2, free=mask)
+    rv = rng.standard_normal((d,) + (prob.n,) * d)
+    rv -= rv.reshape(d, -1).mean(axis=1).reshape((d,) + (1,) * d)
+    rp = rng.standard_normal((prob.n,) * d)
+    rp -= rp.mean()
+    rl = rng.standard_normal((prob.nmarkers, d))
+    ru = rng.standard_normal((nb, d + (3 if d == 3 else 1)))
+    v, p, lam, zu = P.apply(rv, rp, rl, ru)
+    dU = -(sysm.interp(v) + rl)
+    blocks, mp = mobility.blocks_for_problem(prob)
+    f0 = mobility.self_term(mp)
+    for b in range(nb):
+        lo, hi = prob.offsets[b], prob.offsets[b + 1]
+        if not mask[b]:
+            assert np.array_equal(zu[b], ru[b])
+            continue
+        Kb = free.rigid_matrix(prob.R, prob.offsets, prob.centres, prob.L, [b])[lo * d:hi * d]
+        Mb = blocks[b] + P.shifts[b] * f0 * np.eye(blocks[b].shape[0])    # the block M~ the factor is of
+        res1 = Mb @ lam[lo:hi].reshape(-1) - Kb @ zu[b] - dU[lo:hi].reshape(-1)
+        assert np.abs(res1).max() <= 1e-9 * np.abs(dU[lo:hi]).max()
+        F, T = ib.body_force_torque(lam, prob.R, prob.offsets, prob.centres, prob.L)
+        assert np.abs(np.concatenate([F[b], T[b]]) - ru[b]).max() <= 1e-10 * np.abs(ru[b]).max()
