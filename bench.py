@@ -18,12 +18,15 @@ with 4 workers whose solves overlap on the device, and with 1 worker (the
 plain solver), in both precisions.
 
     python bench.py [--steps K] [--warmup W] [--re 10] [--seed 0] [--no-cpu-baseline]
+    python bench.py --serving | --ablation | --free    (other workloads, one JSON line each)
 """
 import argparse
 import json
 import os
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
@@ -61,6 +64,9 @@ def parse():
     ap.add_argument("--served-trajectories", type=int, default=8,
                     help="served form: independent simulations of the workload offered at once")
     ap.add_argument("--no-served", action="store_true", help="skip the served-form leg")
+    ap.add_argument("--free", action="store_true",
+                    help="free-kinematics workload instead: a sedimenting suspension of 16 free spheres at 128^3")
+    ap.add_argument("--free-solves", type=int, default=5, help="free kinematics: timed solves per precision")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (scale for the HBM byte counters)")
     return ap.parse_args()
@@ -268,6 +274,71 @@ def serving(args, torch):
     print(json.dumps(line), flush=True)
 
 
+def free_kinematics(args, torch):
+    """Free kinematics (bodies under applied loads): a sedimenting suspension
+    of 16 spheres (radius 6h, 110 markers each) in a periodic 128^3 box,
+    steady Stokes, every body free under the same weight along -z and zero
+    torque.  Per precision: the set-up of the free bodies (body mobilities),
+    repeated solves from a zero initial guess to relative residual 1e-8, and
+    beside them the prescribed-motion solve at the velocities the free solve
+    returned (the same fields), so the difference is the cost of the free
+    rows."""
+    from paper_1505_07865_amd import ibr
+    from synthetic import sedimentation_problem
+    prob, F, T = sedimentation_problem(args.seed)
+    mask = [1] * prob.nbodies
+    out = {}
+    for prec in ("fp64", "mixed"):
+        s = ibr.from_problem(prob, rtol=1e-8, precision=ibr.MIXED if prec == "mixed" else ibr.FP64, graphs=0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.set_free_bodies(mask, F, T)
+        setup_ms = (time.perf_counter() - t0) * 1e3
+        s.solve()
+
+        def timed(nrep):
+            infos, wall = [], []
+            for _ in range(nrep):
+                t1 = time.perf_counter()
+                infos.append(s.solve())
+                wall.append((time.perf_counter() - t1) * 1e3)
+            return infos, wall
+
+        infos, wall = timed(args.free_solves)
+        U, Om = s.velocities()
+        sol = s.solution()
+        s.set_free_bodies(None)
+        s.set_velocities(U, Om)
+        s.solve()
+        pinfos, pwall = timed(args.free_solves)
+        s.close()
+        out[prec] = {
+            "free": {"solves_per_s": round(len(wall) / (sum(wall) / 1e3), 3), "p50_ms": round(percentile(wall, 50), 3),
+                     "p99_ms": round(percentile(wall, 99), 3), "iters": infos[-1]["iters"],
+                     "ps_applications": infos[-1]["ps_applications"],
+                     "max_rel_residual": float("%.4g" % max(i["rel_residual"] for i in infos)),
+                     "setup_ms": round(setup_ms, 3)},
+            "prescribed_same_motion": {"solves_per_s": round(len(pwall) / (sum(pwall) / 1e3), 3),
+                                       "iters": pinfos[-1]["iters"],
+                                       "ps_applications": pinfos[-1]["ps_applications"]},
+            "mean_settling_velocity_z": float("%.6g" % U[:, 2].mean()),
+            "max_load_mismatch": float("%.3g" % np.abs(sol.F - F).max()),
+        }
+        print("bench: free kinematics %s: %.2f solves/s, %d iterations (prescribed at the same motion: %d)"
+              % (prec, out[prec]["free"]["solves_per_s"], out[prec]["free"]["iters"],
+                 out[prec]["prescribed_same_motion"]["iters"]), file=sys.stderr, flush=True)
+    line = {"metric": "free-kinematics solves/s at 1e-8 residual, sedimenting suspension, mixed vs FP64, 3D 128^3",
+            "value": out["mixed"]["free"]["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
+            "higher_is_better": True, "vs_baseline": None, "dtype": "f32 preconditioner + f64 outer",
+            "data": "synthetic",
+            "config": {"workload": "3D steady Stokes, periodic 128^3, 16 free spheres R=6h x 110 markers under "
+                                   "weight 1 along -z, zero torque, rtol 1e-8, solves from rest",
+                       "seed": args.seed, "solves": args.free_solves},
+            "mixed": out["mixed"], "fp64": out["fp64"],
+            "mixed_over_fp64": round(out["mixed"]["free"]["solves_per_s"] / out["fp64"]["free"]["solves_per_s"], 3)}
+    print(json.dumps(line), flush=True)
+
+
 def ablation(args, torch):
     """The periodic half of the paper's solver study (Sec. 7.1): P_S^-1
     applications (the paper's cost proxy) and FGMRES iterations to reach
@@ -342,6 +413,9 @@ def main():
         return
     if args.ablation:
         ablation(args, torch)
+        return
+    if args.free:
+        free_kinematics(args, torch)
         return
     prob = config2_spheres_ns(args.seed, re=args.re)
     precs = ["fp64", "mixed"] if args.precision == "both" else [args.precision]

@@ -20,4 +20,5 @@ from .workloads import (  # noqa: F401
     icosphere_unit,
     icosphere_spacing,
     shell_problem,
+    sedimentation_problem,
 )

@@ -250,6 +250,25 @@ def config4_spheres256(seed: int = 0, n: int = 256, nbodies: int = 100, radius_h
                      "spheres_%d" % n)
 
 
+def sedimentation_problem(seed: int = 0, n: int = 128, nbodies: int = 16, radius_h: float = 6.0,
+                          nmark: int = 110, weight: float = 1.0):
+    """3D steady Stokes, periodic unit cube, spheres of radius 6h (110
+    Fibonacci markers each) at seeded non-overlapping positions, all free and
+    pulled by the same weight along -z with zero torque (a sedimenting
+    suspension).  Returns (problem, F [nb, 3], T [nb, 3]); the problem's
+    prescribed velocities are zero (unused for free bodies)."""
+    rng = np.random.default_rng(seed)
+    h = 1.0 / n
+    rad = radius_h * h
+    centres = sample_centres(rng, [rad] * nbodies, 1.0, 3, 4.0 * h)
+    bodies = [fibonacci_sphere(nmark, rad, c) for c in centres]
+    prob = _assemble(3, n, h, 0.0, 1.0, 0.0, bodies, centres, np.zeros((nbodies, 3)), np.zeros((nbodies, 3)),
+                     [rad] * nbodies, 0, "sediment_%d" % n)
+    F = np.zeros((nbodies, 3))
+    F[:, 2] = -weight
+    return prob, F, np.zeros((nbodies, 3))
+
+
 def small_problem(seed: int, dim: int, n: int, nbodies: int = 1, radius_h: float = 3.0,
                   rho: float = 0.0, eta: float = 1.0, dt: float = 0.0, gap_h: float = 4.0,
                   rotate: bool = True, nsteps: int = 0, L: float = 1.0) -> Problem:

@@ -36,3 +36,16 @@ def test_shell_problem_spacing(filled):
     np.fill_diagonal(d, np.inf)
     assert abs(d[:162, :162].min(axis=1).mean() / p.h - 2.0) < 1e-9
     assert (p.nmarkers > 162) == filled
+
+
+def test_sedimentation_problem_shapes():
+    from synthetic import sedimentation_problem
+    prob, F, T = sedimentation_problem(0)
+    assert prob.steady and prob.n == 128 and prob.nbodies == 16 and prob.nmarkers == 16 * 110
+    assert F.shape == (16, 3) and np.all(F[:, 2] == -1.0) and not np.any(F[:, :2]) and not np.any(T)
+    # surface gap of at least 4h between spheres (periodic distance)
+    c = prob.centres
+    dc = c[:, None, :] - c[None, :, :]
+    dc -= np.round(dc)
+    dist = np.sqrt((dc ** 2).sum(-1)) + np.eye(16) * 10
+    assert dist.min() >= 2 * 6 * prob.h + 4 * prob.h - 1e-12
