@@ -81,11 +81,28 @@ void launch_field_means(const T* x, int nf, int64_t C, double* part, int part_bl
 template <typename T>
 void launch_sub_field_mean(T* x, int nf, int64_t C, const double* mean, hipStream_t s);
 
+// Fused 3D fp32 level kernels (one workgroup per tile and field, LDS
+// temporal blocking): pre = first sweep from zero + nu - 1 sweeps + residual
+// restriction into bc; post = black-cell prolongation of e + nu sweeps, from
+// xi into xo (neighbouring tiles read xi around their own tile, so it cannot
+// be updated in place).
+bool fused_level_ok(int dim, int logn, int nu);
+void launch_mg_pre_fused(const float* b, float* x, float* bc, int logn, int nf, float c0, float c1, int nu,
+                         hipStream_t s, TimerEvents ev = TimerEvents());
+void launch_mg_post_fused(const float* b, const float* xi, float* xo, const float* e, int logn, int nf, float c0,
+                          float c1, int nu, hipStream_t s, TimerEvents ev = TimerEvents());
+
 template <typename T>
 struct MGHier {
   int dim = 3, logn = 0, nfmax = 0, lds_logn = 0;
   std::vector<int> levels;          // log2 n of the multi-kernel levels (finest first)
   std::vector<T*> bufs_x, bufs_b;   // per level >= 1, nfmax fields each
+  // fused fp32 3D levels: the post kernel reads the pre-smoothed x around its
+  // tile and so writes the result to a second buffer (bufs_xo, level >= 1;
+  // x0_tmp holds the pre-smoothed finest level when that level is fused)
+  std::vector<T*> bufs_xo;
+  T* x0_tmp = nullptr;
+  bool fused(int lg, int nu, int nf) const;
   void init(int dim, int logn, int nfmax);
   void release();
   static size_t bytes(int dim, int logn, int nf);

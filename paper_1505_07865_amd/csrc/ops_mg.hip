@@ -27,6 +27,16 @@ constexpr int kLdsThreads = 512;
 // pyramid would fit in LDS too, but one compute unit sweeping it is slower
 // than the launches it saves.
 constexpr int64_t kTailMaxCells = 4096;
+// Levels above the tail whose fields (cells x fields) number at most this
+// many run the fused LDS-tiled kernels in fp32 3D: there the chain of small
+// dependent launches costs more than one workgroup per tile doing a whole
+// smoothing phase; on larger levels the per-step kernels stream HBM faster.
+constexpr int64_t kFusedMaxWork = (int64_t)1 << 18;
+
+template <typename T>
+bool may_fuse(int dim, int lg) {
+  return sizeof(T) == 4 && dim == 3 && lg >= 4 && ((int64_t)1 << (dim * lg)) <= kFusedMaxWork;
+}
 // Cells of all levels from C down to the 4^dim grid.
 template <int DIM>
 constexpr int64_t pyramid_cells(int64_t C) {
@@ -585,20 +595,32 @@ void MGHier<T>::init(int dim_, int logn_, int maxf) {
   lds_logn = lg;
   bufs_x.assign(levels.size() + 1, nullptr);
   bufs_b.assign(levels.size() + 1, nullptr);
+  bufs_xo.assign(levels.size() + 1, nullptr);
   for (size_t l = 1; l <= levels.size(); ++l) {
     const int lgl = logn - (int)l;
     const int64_t Cl = (int64_t)1 << (dim * lgl);
     bufs_x[l] = dev_alloc<T>(Cl * nfmax);
     bufs_b[l] = dev_alloc<T>(Cl * nfmax);
+    if (l < levels.size() && may_fuse<T>(dim, lgl)) bufs_xo[l] = dev_alloc<T>(Cl * nfmax);
   }
+  x0_tmp = (!levels.empty() && may_fuse<T>(dim, logn)) ? dev_alloc<T>(((int64_t)1 << (dim * logn)) * nfmax) : nullptr;
+}
+
+template <typename T>
+bool MGHier<T>::fused(int lg, int nu, int nf) const {
+  return may_fuse<T>(dim, lg) && fused_level_ok(dim, lg, nu) && ((int64_t)nf << (dim * lg)) <= kFusedMaxWork;
 }
 
 template <typename T>
 void MGHier<T>::release() {
   for (auto p : bufs_x) dev_free(p);
   for (auto p : bufs_b) dev_free(p);
+  for (auto p : bufs_xo) dev_free(p);
+  dev_free(x0_tmp);
+  x0_tmp = nullptr;
   bufs_x.clear();
   bufs_b.clear();
+  bufs_xo.clear();
 }
 
 template <typename T>
@@ -607,6 +629,9 @@ size_t MGHier<T>::bytes(int dim, int logn, int nf) {
   int lg = logn;
   while (((int64_t)1 << (dim * lg)) > kTailMaxCells) --lg;
   for (int l = logn - 1; l >= lg; --l) tot += 2 * ((size_t)1 << (dim * l)) * nf * sizeof(T);
+  for (int l = logn - 1; l > lg; --l)
+    if (may_fuse<T>(dim, l)) tot += ((size_t)1 << (dim * l)) * nf * sizeof(T);
+  if (logn > lg && may_fuse<T>(dim, logn)) tot += ((size_t)1 << (dim * logn)) * nf * sizeof(T);
   return tot;
 }
 
@@ -657,11 +682,32 @@ void MGHier<T>::vcycle(int nf, const T* b, T* x, double c0, double c1, int nu_pr
   T cl = (T)c1;
   const T tc0 = (T)c0;
   const int nml = (int)levels.size();
+  // Where each level keeps x: xin (pre-smoothing result, input of the
+  // post-smoothing) and xout (the level's result, the correction the finer
+  // level interpolates).  They differ only on levels whose post-smoothing runs
+  // the fused kernel, which cannot update x in place.
+  auto post_fused = [&](int l) { return nu_post > 0 && fused(logn - l, nu_post, nf); };
+  auto xin = [&](int l) -> T* {
+    if (l == 0) return post_fused(0) ? x0_tmp : x;
+    return bufs_x[l];
+  };
+  auto xout = [&](int l) -> T* {
+    if (l == nml) return nml == 0 ? x : bufs_x[l];
+    if (l == 0) return x;
+    return post_fused(l) ? bufs_xo[l] : bufs_x[l];
+  };
   for (int l = 0; l < nml; ++l) {
     const int lg = logn - l;
     const int64_t Cl = (int64_t)1 << (dim * lg);
-    T* xl = l == 0 ? x : bufs_x[l];
+    T* xl = xin(l);
     const T* bl = l == 0 ? b : bufs_b[l];
+    if (fused(lg, nu_pre, nf)) {
+      check_quad_aligned(xl, bl);
+      launch_mg_pre_fused((const float*)bl, (float*)xl, (float*)bufs_b[l + 1], lg, nf, (float)tc0, (float)cl, nu_pre,
+                          s, l == 0 ? timer_sample(kTimerRbFine, 2.125 * (double)Cl * nf * sizeof(T)) : TimerEvents());
+      cl = cl * T(0.25);
+      continue;
+    }
     if (nu_pre <= 0)
       launch_fill<T>(xl, Cl * nf, T(0), s);
     else
@@ -679,7 +725,7 @@ void MGHier<T>::vcycle(int nf, const T* b, T* x, double c0, double c1, int nu_pr
   }
   {
     const T* bl = nml == 0 ? b : bufs_b[nml];
-    T* xl = nml == 0 ? x : bufs_x[nml];
+    T* xl = xout(nml);
     if (three)
       hipLaunchKernelGGL((k_vcycle_lds<T, 3>), dim3(nf), dim3(kLdsThreads), 0, s, bl, xl, lds_logn, tc0, cl, nu_pre,
                          nu_post, nu_coarse);
@@ -691,20 +737,27 @@ void MGHier<T>::vcycle(int nf, const T* b, T* x, double c0, double c1, int nu_pr
     cl = cl * T(4);
     const int lg = logn - l;
     const int64_t Cl = (int64_t)1 << (dim * lg);
-    T* xl = l == 0 ? x : bufs_x[l];
     const T* bl = l == 0 ? b : bufs_b[l];
+    const T* e = xout(l + 1);
+    if (post_fused(l)) {
+      launch_mg_post_fused((const float*)bl, (const float*)xin(l), (float*)xout(l), (const float*)e, lg, nf,
+                           (float)tc0, (float)cl, nu_post, s,
+                           l == 0 ? timer_sample(kTimerRbFine, 3.125 * (double)Cl * nf * sizeof(T)) : TimerEvents());
+      continue;
+    }
+    T* xl = xin(l);  // == xout(l): updated in place
     // with post-smoothing the first (red) half sweep overwrites the red cells
     const dim3 gp(nblk(Cl / 8), nf);
     if (three) {
       if (nu_post > 0)
-        hipLaunchKernelGGL((k_prolong_add<T, 3, true>), gp, dim3(256), 0, s, xl, bufs_x[l + 1], lg);
+        hipLaunchKernelGGL((k_prolong_add<T, 3, true>), gp, dim3(256), 0, s, xl, e, lg);
       else
-        hipLaunchKernelGGL((k_prolong_add<T, 3, false>), gp, dim3(256), 0, s, xl, bufs_x[l + 1], lg);
+        hipLaunchKernelGGL((k_prolong_add<T, 3, false>), gp, dim3(256), 0, s, xl, e, lg);
     } else {
       if (nu_post > 0)
-        hipLaunchKernelGGL((k_prolong_add<T, 2, true>), gp, dim3(256), 0, s, xl, bufs_x[l + 1], lg);
+        hipLaunchKernelGGL((k_prolong_add<T, 2, true>), gp, dim3(256), 0, s, xl, e, lg);
       else
-        hipLaunchKernelGGL((k_prolong_add<T, 2, false>), gp, dim3(256), 0, s, xl, bufs_x[l + 1], lg);
+        hipLaunchKernelGGL((k_prolong_add<T, 2, false>), gp, dim3(256), 0, s, xl, e, lg);
     }
     for (int sw = 0; sw < nu_post; ++sw)
       for (int color = 0; color < 2; ++color) rb_half(xl, bl, lg, nf, tc0, cl, color, l == 0, s);
