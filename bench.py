@@ -18,7 +18,7 @@ with 4 workers whose solves overlap on the device, and with 1 worker (the
 plain solver), in both precisions.
 
     python bench.py [--steps K] [--warmup W] [--re 10] [--seed 0] [--no-cpu-baseline]
-    python bench.py --serving | --ablation | --free    (other workloads, one JSON line each)
+    python bench.py --serving | --ablation | --free | --blocks    (other workloads, one JSON line each)
 """
 import argparse
 import json
@@ -67,6 +67,9 @@ def parse():
     ap.add_argument("--free", action="store_true",
                     help="free-kinematics workload instead: a sedimenting suspension of 16 free spheres at 128^3")
     ap.add_argument("--free-solves", type=int, default=5, help="free kinematics: timed solves per precision")
+    ap.add_argument("--blocks", action="store_true",
+                    help="per-body mobility set-up of the 256^3 configuration (100 blocks of 600 x 600, fp64 MFMA)")
+    ap.add_argument("--block-reps", type=int, default=5, help="blocks: timed set-ups")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (scale for the HBM byte counters)")
     return ap.parse_args()
@@ -339,6 +342,39 @@ def free_kinematics(args, torch):
     print(json.dumps(line), flush=True)
 
 
+def blocks(args, torch):
+    """Per-body mobility set-up (assembly, shifted Cholesky on fp64 MFMA
+    tiles, triangular inverse, M~^-1 = X^T X) for the 256^3 configuration's
+    100 spheres of 200 markers (100 blocks of 600 x 600): the synchronous
+    ibr_set_bodies call timed by the host clock; the flop count is the dense
+    one, n^3/3 each for the factor, the triangular inverse and X^T X."""
+    from paper_1505_07865_amd import ibr
+    from synthetic import config4_spheres256
+    prob = config4_spheres256(args.seed)
+    s = ibr.from_problem(prob, rtol=1e-8, precision=ibr.MIXED, graphs=0)
+    sizes = np.diff(prob.offsets) * prob.dim
+    flops = float(np.sum(sizes.astype(np.float64) ** 3))
+    wall = []
+    for _ in range(args.block_reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.set_bodies(prob.R, prob.offsets, prob.centres)
+        wall.append((time.perf_counter() - t0) * 1e3)
+    s.close()
+    ms = percentile(wall, 50)
+    tf = flops / (ms * 1e-3) / 1e12
+    line = {"metric": "per-body mobility set-up (assembly + Cholesky + inverse), 100 blocks of 600 x 600",
+            "value": round(ms, 3), "unit": "ms", "n_gpus": 1, "higher_is_better": False, "vs_baseline": None,
+            "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "3D 256^3 steady, 100 spheres R=8h x 200 markers (config of the 256^3 solve)",
+                       "seed": args.seed, "reps": args.block_reps},
+            "wall_ms": [round(w, 3) for w in wall],
+            "roofline": {"bound": "mfma", "achieved": round(tf, 4), "peak": 78.6, "unit": "TFLOP/s",
+                         "frac": round(tf / 78.6, 5), "traffic": None, "flops": flops,
+                         "note": "end-to-end set-up time (host marker checks, binning and the block kernels)"}}
+    print(json.dumps(line), flush=True)
+
+
 def ablation(args, torch):
     """The periodic half of the paper's solver study (Sec. 7.1): P_S^-1
     applications (the paper's cost proxy) and FGMRES iterations to reach
@@ -416,6 +452,9 @@ def main():
         return
     if args.free:
         free_kinematics(args, torch)
+        return
+    if args.blocks:
+        blocks(args, torch)
         return
     prob = config2_spheres_ns(args.seed, re=args.re)
     precs = ["fp64", "mixed"] if args.precision == "both" else [args.precision]

@@ -81,23 +81,25 @@ void launch_field_means(const T* x, int nf, int64_t C, double* part, int part_bl
 template <typename T>
 void launch_sub_field_mean(T* x, int nf, int64_t C, const double* mean, hipStream_t s);
 
-// Fused 3D fp32 level kernels (one workgroup per tile and field, LDS
-// temporal blocking): pre = first sweep from zero + nu - 1 sweeps + residual
+// Fused 3D level kernels (one workgroup per 8^3 tile and field, LDS temporal
+// blocking): pre = first sweep from zero + nu - 1 sweeps + residual
 // restriction into bc; post = black-cell prolongation of e + nu sweeps, from
 // xi into xo (neighbouring tiles read xi around their own tile, so it cannot
 // be updated in place).
 bool fused_level_ok(int dim, int logn, int nu);
-void launch_mg_pre_fused(const float* b, float* x, float* bc, int logn, int nf, float c0, float c1, int nu,
-                         hipStream_t s, TimerEvents ev = TimerEvents());
-void launch_mg_post_fused(const float* b, const float* xi, float* xo, const float* e, int logn, int nf, float c0,
-                          float c1, int nu, hipStream_t s, TimerEvents ev = TimerEvents());
+template <typename V>
+void launch_mg_pre_fused(const V* b, V* x, V* bc, int logn, int nf, V c0, V c1, int nu, hipStream_t s,
+                         TimerEvents ev = TimerEvents());
+template <typename V>
+void launch_mg_post_fused(const V* b, const V* xi, V* xo, const V* e, int logn, int nf, V c0, V c1, int nu,
+                          hipStream_t s, TimerEvents ev = TimerEvents());
 
 template <typename T>
 struct MGHier {
   int dim = 3, logn = 0, nfmax = 0, lds_logn = 0;
   std::vector<int> levels;          // log2 n of the multi-kernel levels (finest first)
   std::vector<T*> bufs_x, bufs_b;   // per level >= 1, nfmax fields each
-  // fused fp32 3D levels: the post kernel reads the pre-smoothed x around its
+  // fused 3D levels: the post kernel reads the pre-smoothed x around its
   // tile and so writes the result to a second buffer (bufs_xo, level >= 1;
   // x0_tmp holds the pre-smoothed finest level when that level is fused)
   std::vector<T*> bufs_xo;
@@ -237,7 +239,7 @@ struct MobParams {
 void launch_mob_assemble(int dim, int nb, const int* offsets, const int64_t* moff, const double* R, MobParams p,
                          double* M, int max_np, hipStream_t s);
 void launch_chol(int nb, const int* offsets, int dim, const int64_t* moff, const double* M, double* Lf,
-                 const int* active, const double* shift, double f0, double pivot_tol, int* fail,
+                 const int* active, const double* shift, double f0, double pivot_tol, int* fail, int max_rows,
                  hipStream_t s);
 void launch_chol_inverse(int nb, const int* offsets, int dim, const int64_t* moff, double* Lf, double* Minv,
                          double* X, int max_n, hipStream_t s);

@@ -28,14 +28,14 @@ constexpr int kLdsThreads = 512;
 // than the launches it saves.
 constexpr int64_t kTailMaxCells = 4096;
 // Levels above the tail whose fields (cells x fields) number at most this
-// many run the fused LDS-tiled kernels in fp32 3D: there the chain of small
+// many run the fused LDS-tiled kernels in 3D: there the chain of small
 // dependent launches costs more than one workgroup per tile doing a whole
 // smoothing phase; on larger levels the per-step kernels stream HBM faster.
 constexpr int64_t kFusedMaxWork = (int64_t)1 << 18;
 
 template <typename T>
 bool may_fuse(int dim, int lg) {
-  return sizeof(T) == 4 && dim == 3 && lg >= 4 && ((int64_t)1 << (dim * lg)) <= kFusedMaxWork;
+  return dim == 3 && lg >= 4 && ((int64_t)1 << (dim * lg)) <= kFusedMaxWork;
 }
 // Cells of all levels from C down to the 4^dim grid.
 template <int DIM>
@@ -703,8 +703,8 @@ void MGHier<T>::vcycle(int nf, const T* b, T* x, double c0, double c1, int nu_pr
     const T* bl = l == 0 ? b : bufs_b[l];
     if (fused(lg, nu_pre, nf)) {
       check_quad_aligned(xl, bl);
-      launch_mg_pre_fused((const float*)bl, (float*)xl, (float*)bufs_b[l + 1], lg, nf, (float)tc0, (float)cl, nu_pre,
-                          s, l == 0 ? timer_sample(kTimerRbFine, 2.125 * (double)Cl * nf * sizeof(T)) : TimerEvents());
+      launch_mg_pre_fused<T>(bl, xl, bufs_b[l + 1], lg, nf, tc0, cl, nu_pre, s,
+                             l == 0 ? timer_sample(kTimerRbFine, 2.125 * (double)Cl * nf * sizeof(T)) : TimerEvents());
       cl = cl * T(0.25);
       continue;
     }
@@ -740,9 +740,8 @@ void MGHier<T>::vcycle(int nf, const T* b, T* x, double c0, double c1, int nu_pr
     const T* bl = l == 0 ? b : bufs_b[l];
     const T* e = xout(l + 1);
     if (post_fused(l)) {
-      launch_mg_post_fused((const float*)bl, (const float*)xin(l), (float*)xout(l), (const float*)e, lg, nf,
-                           (float)tc0, (float)cl, nu_post, s,
-                           l == 0 ? timer_sample(kTimerRbFine, 3.125 * (double)Cl * nf * sizeof(T)) : TimerEvents());
+      launch_mg_post_fused<T>(bl, xin(l), xout(l), e, lg, nf, tc0, cl, nu_post, s,
+                              l == 0 ? timer_sample(kTimerRbFine, 3.125 * (double)Cl * nf * sizeof(T)) : TimerEvents());
       continue;
     }
     T* xl = xin(l);  // == xout(l): updated in place

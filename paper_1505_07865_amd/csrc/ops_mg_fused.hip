@@ -1,10 +1,10 @@
-// Fused multigrid level kernels for 3D fp32 levels (the mixed-precision
-// preconditioner's V-cycles, Sec. 5.2): temporal blocking in LDS.
+// Fused multigrid level kernels for small 3D levels of the preconditioner's
+// V-cycles (Sec. 5.2), in fp32 or fp64: temporal blocking in LDS.
 //
 // The unfused level runs one kernel per half sweep, one for the residual and
 // restriction and one for the prolongation: nine dependent launches per level
 // and cycle, each paying the kernel boundary (dispatch, drain, cache
-// write-back between XCDs).  Here one workgroup owns a 16^3 tile of a level
+// write-back between XCDs).  Here one workgroup owns an 8^3 tile of a level
 // plus a halo of H = 2 nu cells, brings x and b of the whole block into LDS,
 // runs every half sweep of one smoothing phase on a block that shrinks by
 // one cell per half sweep (each half sweep reads the other colour one cell
@@ -52,13 +52,13 @@ __device__ inline int gsplit(int i, int j, int k, int logn) {
 // Load a field of the block (E^3 cells around the tile at i0, j0, k0) into LDS.
 // Every thread issues all of its global loads before its first LDS store, so
 // they are in flight together.
-template <int NU, int TT>
-__device__ inline void load_block(float* s, const float* __restrict__ g, int i0, int j0, int k0, int logn) {
+template <typename V, int NU, int TT>
+__device__ inline void load_block(V* s, const V* __restrict__ g, int i0, int j0, int k0, int logn) {
   using G = FTile<NU, TT>;
   constexpr int N = 2 * G::HALF;
   constexpr int PER = (N + G::NT - 1) / G::NT;
   const int mask = (1 << logn) - 1;
-  float v[PER];
+  V v[PER];
 #pragma unroll
   for (int u = 0; u < PER; ++u) {
     const int t = threadIdx.x + u * G::NT;
@@ -81,8 +81,8 @@ __device__ inline void load_block(float* s, const float* __restrict__ g, int i0,
 }
 
 // Write the interior tile of x back to global memory.
-template <int NU, int TT>
-__device__ inline void store_interior(const float* s, float* __restrict__ g, int i0, int j0, int k0, int logn) {
+template <typename V, int NU, int TT>
+__device__ inline void store_interior(const V* s, V* __restrict__ g, int i0, int j0, int k0, int logn) {
   using G = FTile<NU, TT>;
   constexpr int IH = TT / 2;
   constexpr int N = TT * TT * TT;
@@ -106,17 +106,17 @@ __device__ inline void store_interior(const float* s, float* __restrict__ g, int
 // reads all of its cells' neighbours before it writes any result (the two
 // colours never alias, but the compiler cannot tell), so the LDS reads of its
 // cells overlap.
-template <int NU, int TT, int A, int C, bool FIRST>
-__device__ inline void block_half_sweep(float* xs, const float* bs, float c1, float inv_diag) {
+template <typename V, int NU, int TT, int A, int C, bool FIRST>
+__device__ inline void block_half_sweep(V* xs, const V* bs, V c1, V inv_diag) {
   using G = FTile<NU, TT>;
   constexpr int W = G::E - 2 * A;
   constexpr int WH = W / 2;
   constexpr int CELLS = W * W * WH;
   constexpr int PER = (CELLS + G::NT - 1) / G::NT;
-  const float* o = xs + (1 - C) * G::HALF;
-  float* own = xs + C * G::HALF;
-  const float* bo = bs + C * G::HALF;
-  float res[PER];
+  const V* o = xs + (1 - C) * G::HALF;
+  V* own = xs + C * G::HALF;
+  const V* bo = bs + C * G::HALF;
+  V res[PER];
   int at[PER];
 #pragma unroll
   for (int u = 0; u < PER; ++u) {
@@ -133,7 +133,7 @@ __device__ inline void block_half_sweep(float* xs, const float* bs, float c1, fl
       if (FIRST && C == 0) {
         res[u] = bo[self] * inv_diag;
       } else {
-        float sum = o[row * G::HR + ((li - 1) >> 1)] + o[row * G::HR + ((li + 1) >> 1)] + o[self - G::HR] +
+        V sum = o[row * G::HR + ((li - 1) >> 1)] + o[row * G::HR + ((li + 1) >> 1)] + o[self - G::HR] +
                     o[self + G::HR];
         sum += o[self - G::E * G::HR] + o[self + G::E * G::HR];
         res[u] = (bo[self] + c1 * sum) * inv_diag;
@@ -145,25 +145,25 @@ __device__ inline void block_half_sweep(float* xs, const float* bs, float c1, fl
     if (at[u] >= 0) own[at[u]] = res[u];
 }
 
-template <int NU, int TT, int S>
-__device__ inline void pre_sweeps(float* xs, const float* bs, float c1, float inv_diag) {
+template <typename V, int NU, int TT, int S>
+__device__ inline void pre_sweeps(V* xs, const V* bs, V c1, V inv_diag) {
   if constexpr (S < NU) {
-    block_half_sweep<NU, TT, 2 * S, 0, false>(xs, bs, c1, inv_diag);
+    block_half_sweep<V, NU, TT, 2 * S, 0, false>(xs, bs, c1, inv_diag);
     __syncthreads();
-    block_half_sweep<NU, TT, 2 * S + 1, 1, false>(xs, bs, c1, inv_diag);
+    block_half_sweep<V, NU, TT, 2 * S + 1, 1, false>(xs, bs, c1, inv_diag);
     __syncthreads();
-    pre_sweeps<NU, TT, S + 1>(xs, bs, c1, inv_diag);
+    pre_sweeps<V, NU, TT, S + 1>(xs, bs, c1, inv_diag);
   }
 }
 
-template <int NU, int TT, int S>
-__device__ inline void post_sweeps(float* xs, const float* bs, float c1, float inv_diag) {
+template <typename V, int NU, int TT, int S>
+__device__ inline void post_sweeps(V* xs, const V* bs, V c1, V inv_diag) {
   if constexpr (S < NU) {
-    block_half_sweep<NU, TT, 2 * S + 1, 0, false>(xs, bs, c1, inv_diag);
+    block_half_sweep<V, NU, TT, 2 * S + 1, 0, false>(xs, bs, c1, inv_diag);
     __syncthreads();
-    block_half_sweep<NU, TT, 2 * S + 2, 1, false>(xs, bs, c1, inv_diag);
+    block_half_sweep<V, NU, TT, 2 * S + 2, 1, false>(xs, bs, c1, inv_diag);
     __syncthreads();
-    post_sweeps<NU, TT, S + 1>(xs, bs, c1, inv_diag);
+    post_sweeps<V, NU, TT, S + 1>(xs, bs, c1, inv_diag);
   }
 }
 
@@ -178,12 +178,12 @@ __device__ inline void tile_origin(int logn, int& i0, int& j0, int& k0) {
   k0 = (t >> (2 * tl)) << LT;
 }
 
-template <int NU, int TT>
-__global__ void __launch_bounds__((FTile<NU, TT>::NT)) k_mg_pre(const float* __restrict__ b, float* __restrict__ x,
-                                                          float* __restrict__ bc, int logn, float c0, float c1) {
+template <typename V, int NU, int TT>
+__global__ void __launch_bounds__((FTile<NU, TT>::NT)) k_mg_pre(const V* __restrict__ b, V* __restrict__ x,
+                                                          V* __restrict__ bc, int logn, V c0, V c1) {
   using G = FTile<NU, TT>;
-  __shared__ float xs[2 * G::HALF];
-  __shared__ float bs[2 * G::HALF];
+  __shared__ V xs[2 * G::HALF];
+  __shared__ V bs[2 * G::HALF];
   const int64_t C = (int64_t)1 << (3 * logn);
   const int64_t f = blockIdx.y;
   b += f * C;
@@ -191,16 +191,16 @@ __global__ void __launch_bounds__((FTile<NU, TT>::NT)) k_mg_pre(const float* __r
   bc += f * (C >> 3);
   int i0, j0, k0;
   tile_origin<G::LT>(logn, i0, j0, k0);
-  load_block<NU, TT>(bs, b, i0, j0, k0, logn);
+  load_block<V, NU, TT>(bs, b, i0, j0, k0, logn);
   __syncthreads();
-  const float diag = c0 + 6.0f * c1;
-  const float inv_diag = 1.0f / diag;
-  block_half_sweep<NU, TT, 0, 0, true>(xs, bs, c1, inv_diag);
+  const V diag = c0 + V(6) * c1;
+  const V inv_diag = V(1) / diag;
+  block_half_sweep<V, NU, TT, 0, 0, true>(xs, bs, c1, inv_diag);
   __syncthreads();
-  block_half_sweep<NU, TT, 1, 1, true>(xs, bs, c1, inv_diag);
+  block_half_sweep<V, NU, TT, 1, 1, true>(xs, bs, c1, inv_diag);
   __syncthreads();
-  pre_sweeps<NU, TT, 1>(xs, bs, c1, inv_diag);
-  store_interior<NU, TT>(xs, x, i0, j0, k0, logn);
+  pre_sweeps<V, NU, TT, 1>(xs, bs, c1, inv_diag);
+  store_interior<V, NU, TT>(xs, x, i0, j0, k0, logn);
   // residual summed over each 2^3 block of the tile, averaged into the coarse level
   constexpr int CT = TT / 2;
   constexpr int LC = G::LT - 1;
@@ -214,7 +214,7 @@ __global__ void __launch_bounds__((FTile<NU, TT>::NT)) k_mg_pre(const float* __r
     auto B = [&](int li, int lj, int lk) {
       return bs[((li + lj + lk) & 1) * G::HALF + (lj + G::E * lk) * G::HR + (li >> 1)];
     };
-    float sx = 0.f, sb = 0.f, sf = 0.f;
+    V sx = V(0), sb = V(0), sf = V(0);
 #pragma unroll
     for (int dk = 0; dk < 2; ++dk)
 #pragma unroll
@@ -234,21 +234,21 @@ __global__ void __launch_bounds__((FTile<NU, TT>::NT)) k_mg_pre(const float* __r
     for (int dj = 0; dj < 2; ++dj)
 #pragma unroll
       for (int di = 0; di < 2; ++di) sf += X(fi + di, fj + dj, fk - 1) + X(fi + di, fj + dj, fk + 2);
-    const float r = (sb - (diag - 3.0f * c1) * sx + c1 * sf) * 0.125f;
+    const V r = (sb - (diag - V(3) * c1) * sx + c1 * sf) * V(0.125);
     bc[gsplit((i0 >> 1) + ci, (j0 >> 1) + cj, (k0 >> 1) + ck, lognc)] = r;
   }
 }
 
-template <int NU, int TT>
-__global__ void __launch_bounds__((FTile<NU, TT>::NT)) k_mg_post(const float* __restrict__ b,
-                                                                 const float* __restrict__ xi,
-                                                                 float* __restrict__ xo,
-                                                                 const float* __restrict__ e, int logn, float c0,
-                                                                 float c1) {
+template <typename V, int NU, int TT>
+__global__ void __launch_bounds__((FTile<NU, TT>::NT)) k_mg_post(const V* __restrict__ b,
+                                                                 const V* __restrict__ xi,
+                                                                 V* __restrict__ xo,
+                                                                 const V* __restrict__ e, int logn, V c0,
+                                                                 V c1) {
   using G = FTile<NU, TT>;
-  __shared__ float xs[2 * G::HALF];
-  __shared__ float bs[2 * G::HALF];
-  __shared__ float es[G::CE * G::CE * G::CE];
+  __shared__ V xs[2 * G::HALF];
+  __shared__ V bs[2 * G::HALF];
+  __shared__ V es[G::CE * G::CE * G::CE];
   const int64_t C = (int64_t)1 << (3 * logn);
   const int64_t f = blockIdx.y;
   b += f * C;
@@ -257,8 +257,8 @@ __global__ void __launch_bounds__((FTile<NU, TT>::NT)) k_mg_post(const float* __
   e += f * (C >> 3);
   int i0, j0, k0;
   tile_origin<G::LT>(logn, i0, j0, k0);
-  load_block<NU, TT>(xs, xi, i0, j0, k0, logn);
-  load_block<NU, TT>(bs, b, i0, j0, k0, logn);
+  load_block<V, NU, TT>(xs, xi, i0, j0, k0, logn);
+  load_block<V, NU, TT>(bs, b, i0, j0, k0, logn);
   // coarse block: coarse cells (i0 - H)/2 - 1 ... + CE - 1 on each axis
   const int lognc = logn - 1;
   const int maskc = (1 << lognc) - 1;
@@ -266,7 +266,7 @@ __global__ void __launch_bounds__((FTile<NU, TT>::NT)) k_mg_post(const float* __
   {
     constexpr int NE = G::CE * G::CE * G::CE;
     constexpr int PER = (NE + G::NT - 1) / G::NT;
-    float v[PER];
+    V v[PER];
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
       const int t = threadIdx.x + u * G::NT;
@@ -285,8 +285,8 @@ __global__ void __launch_bounds__((FTile<NU, TT>::NT)) k_mg_post(const float* __
   __syncthreads();
   // x += P e on the black cells of the block (weights 3/4, 1/4 per axis; x, then y, then z)
   {
-    const float w0 = 0.75f, w1 = 0.25f;
-    float* xb = xs + G::HALF;
+    const V w0 = V(0.75), w1 = V(0.25);
+    V* xb = xs + G::HALF;
 #pragma unroll 4
     for (int t = threadIdx.x; t < G::HALF; t += blockDim.x) {
       const int row = t / G::HR;
@@ -298,68 +298,73 @@ __global__ void __launch_bounds__((FTile<NU, TT>::NT)) k_mg_post(const float* __
       const int ci = ((li - 0) >> 1) + 1, cj = (lj >> 1) + 1, ck = (lk >> 1) + 1;
       const int si = (li & 1) ? 1 : -1, sj = (lj & 1) ? 1 : -1, sk = (lk & 1) ? 1 : -1;
       auto Ec = [&](int a, int bq, int cq) { return es[a + G::CE * (bq + G::CE * cq)]; };
-      const float a0 = w0 * Ec(ci, cj, ck) + w1 * Ec(ci + si, cj, ck);
-      const float a1 = w0 * Ec(ci, cj + sj, ck) + w1 * Ec(ci + si, cj + sj, ck);
-      const float a2 = w0 * Ec(ci, cj, ck + sk) + w1 * Ec(ci + si, cj, ck + sk);
-      const float a3 = w0 * Ec(ci, cj + sj, ck + sk) + w1 * Ec(ci + si, cj + sj, ck + sk);
-      const float b0 = w0 * a0 + w1 * a1;
-      const float b1 = w0 * a2 + w1 * a3;
+      const V a0 = w0 * Ec(ci, cj, ck) + w1 * Ec(ci + si, cj, ck);
+      const V a1 = w0 * Ec(ci, cj + sj, ck) + w1 * Ec(ci + si, cj + sj, ck);
+      const V a2 = w0 * Ec(ci, cj, ck + sk) + w1 * Ec(ci + si, cj, ck + sk);
+      const V a3 = w0 * Ec(ci, cj + sj, ck + sk) + w1 * Ec(ci + si, cj + sj, ck + sk);
+      const V b0 = w0 * a0 + w1 * a1;
+      const V b1 = w0 * a2 + w1 * a3;
       xb[t] += w0 * b0 + w1 * b1;
     }
   }
   __syncthreads();
-  const float inv_diag = 1.0f / (c0 + 6.0f * c1);
-  post_sweeps<NU, TT, 0>(xs, bs, c1, inv_diag);
-  store_interior<NU, TT>(xs, xo, i0, j0, k0, logn);
+  const V inv_diag = V(1) / (c0 + V(6) * c1);
+  post_sweeps<V, NU, TT, 0>(xs, bs, c1, inv_diag);
+  store_interior<V, NU, TT>(xs, xo, i0, j0, k0, logn);
+}
+
+
+bool fused_level_ok(int dim, int logn, int nu) { return dim == 3 && logn >= 4 && (nu == 1 || nu == 2); }
+
+template <typename V, int TT>
+static void pre_tt(const V* b, V* x, V* bc, int logn, int nf, V c0, V c1, int nu, hipStream_t s, TimerEvents ev) {
+  const unsigned tiles = 1u << (3 * (logn - FTile<1, TT>::LT));
+  if (nu == 2)
+    hipExtLaunchKernelGGL((k_mg_pre<V, 2, TT>), dim3(tiles, nf), dim3(FTile<2, TT>::NT), 0, s, ev.start, ev.stop, 0,
+                          b, x, bc, logn, c0, c1);
+  else
+    hipExtLaunchKernelGGL((k_mg_pre<V, 1, TT>), dim3(tiles, nf), dim3(FTile<1, TT>::NT), 0, s, ev.start, ev.stop, 0,
+                          b, x, bc, logn, c0, c1);
+}
+
+template <typename V, int TT>
+static void post_tt(const V* b, const V* xi, V* xo, const V* e, int logn, int nf, V c0, V c1, int nu, hipStream_t s,
+                    TimerEvents ev) {
+  const unsigned tiles = 1u << (3 * (logn - FTile<1, TT>::LT));
+  if (nu == 2)
+    hipExtLaunchKernelGGL((k_mg_post<V, 2, TT>), dim3(tiles, nf), dim3(FTile<2, TT>::NT), 0, s, ev.start, ev.stop, 0,
+                          b, xi, xo, e, logn, c0, c1);
+  else
+    hipExtLaunchKernelGGL((k_mg_post<V, 1, TT>), dim3(tiles, nf), dim3(FTile<1, TT>::NT), 0, s, ev.start, ev.stop, 0,
+                          b, xi, xo, e, logn, c0, c1);
 }
 
 }  // namespace
 
 bool fused_level_ok(int dim, int logn, int nu) { return dim == 3 && logn >= 4 && (nu == 1 || nu == 2); }
 
-// 8^3 tiles (more, smaller workgroups: shorter per-tile latency) below
-// fused_big_logn, 16^3 tiles from there up.
-int fused_big_logn = 30;
-
-template <int TT>
-static void pre_tt(const float* b, float* x, float* bc, int logn, int nf, float c0, float c1, int nu, hipStream_t s,
-                   TimerEvents ev) {
-  const unsigned tiles = 1u << (3 * (logn - FTile<1, TT>::LT));
-  if (nu == 2)
-    hipExtLaunchKernelGGL((k_mg_pre<2, TT>), dim3(tiles, nf), dim3(FTile<2, TT>::NT), 0, s, ev.start, ev.stop, 0, b,
-                          x, bc, logn, c0, c1);
-  else
-    hipExtLaunchKernelGGL((k_mg_pre<1, TT>), dim3(tiles, nf), dim3(FTile<1, TT>::NT), 0, s, ev.start, ev.stop, 0, b,
-                          x, bc, logn, c0, c1);
+// 8^3 tiles: 16^3 tiles (a 24^3 block, one workgroup of 1024 threads per
+// compute unit) measured slower on every level, a block that large runs too
+// long in one compute unit.
+template <typename V>
+void launch_mg_pre_fused(const V* b, V* x, V* bc, int logn, int nf, V c0, V c1, int nu, hipStream_t s,
+                         TimerEvents ev) {
+  pre_tt<V, 8>(b, x, bc, logn, nf, c0, c1, nu, s, ev);
 }
+template void launch_mg_pre_fused<float>(const float*, float*, float*, int, int, float, float, int, hipStream_t,
+                                         TimerEvents);
+template void launch_mg_pre_fused<double>(const double*, double*, double*, int, int, double, double, int,
+                                          hipStream_t, TimerEvents);
 
-template <int TT>
-static void post_tt(const float* b, const float* xi, float* xo, const float* e, int logn, int nf, float c0, float c1,
-                    int nu, hipStream_t s, TimerEvents ev) {
-  const unsigned tiles = 1u << (3 * (logn - FTile<1, TT>::LT));
-  if (nu == 2)
-    hipExtLaunchKernelGGL((k_mg_post<2, TT>), dim3(tiles, nf), dim3(FTile<2, TT>::NT), 0, s, ev.start, ev.stop, 0,
-                          b, xi, xo, e, logn, c0, c1);
-  else
-    hipExtLaunchKernelGGL((k_mg_post<1, TT>), dim3(tiles, nf), dim3(FTile<1, TT>::NT), 0, s, ev.start, ev.stop, 0,
-                          b, xi, xo, e, logn, c0, c1);
-}
-
-void launch_mg_pre_fused(const float* b, float* x, float* bc, int logn, int nf, float c0, float c1, int nu,
-                         hipStream_t s, TimerEvents ev) {
-  if (logn >= fused_big_logn)
-    pre_tt<16>(b, x, bc, logn, nf, c0, c1, nu, s, ev);
-  else
-    pre_tt<8>(b, x, bc, logn, nf, c0, c1, nu, s, ev);
-}
-
-void launch_mg_post_fused(const float* b, const float* xi, float* xo, const float* e, int logn, int nf, float c0,
-                          float c1, int nu, hipStream_t s, TimerEvents ev) {
+template <typename V>
+void launch_mg_post_fused(const V* b, const V* xi, V* xo, const V* e, int logn, int nf, V c0, V c1, int nu,
+                          hipStream_t s, TimerEvents ev) {
   if (xi == xo) throw DeviceError("fused post-smoothing needs separate input and output x");
-  if (logn >= fused_big_logn)
-    post_tt<16>(b, xi, xo, e, logn, nf, c0, c1, nu, s, ev);
-  else
-    post_tt<8>(b, xi, xo, e, logn, nf, c0, c1, nu, s, ev);
+  post_tt<V, 8>(b, xi, xo, e, logn, nf, c0, c1, nu, s, ev);
 }
+template void launch_mg_post_fused<float>(const float*, const float*, float*, const float*, int, int, float, float,
+                                          int, hipStream_t, TimerEvents);
+template void launch_mg_post_fused<double>(const double*, const double*, double*, const double*, int, int, double,
+                                           double, int, hipStream_t, TimerEvents);
 
 }  // namespace ibr

@@ -106,97 +106,164 @@ typedef double dvec4 __attribute__((ext_vector_type(4)));
 
 __device__ inline int pad16(int n) { return (n + 15) & ~15; }
 
-constexpr int kCholThreads = 256;
+// Batched blocked right-looking Cholesky of M_p + shift_p f0 I over all
+// bodies, 16x16 tiles.  Per 16-column panel p two launches cover every body:
+//   panel:  one wavefront per (row tile I > p, body) factors the diagonal
+//           tile in registers (lane r holds row r, shuffles broadcast the
+//           pivot column) and solves L_Ip L_pp^T = A_Ip row by row (lane
+//           r < 16 owns row r of the tile);
+//   update: one wavefront per lower tile (I, J), p < J <= I, of every body:
+//           L_IJ -= L_Ip L_Jp^T on fp64 MFMA 16x16x4; one more per body
+//           writes the factored diagonal tile (after the panel launch has
+//           read the unfactored one).
+// So the work of a panel spreads over every compute unit instead of one
+// workgroup per body walking all panels.  A pivot <= pivot_tol f0 marks the
+// body failed (it is factored again with a larger shift).
 
-// Blocked right-looking Cholesky of M_p + shift_p f0 I, one workgroup per body:
-// 16-column panels factored with scalar code, trailing updates
-// C -= P_I P_J^T as 16x16 fp64 MFMA tiles spread over the waves.
-__global__ void __launch_bounds__(kCholThreads) k_chol(const int* __restrict__ off, int dim,
-                                                       const int64_t* __restrict__ moff, const double* __restrict__ M,
-                                                       double* __restrict__ Lf, const int* __restrict__ active,
-                                                       const double* __restrict__ shift, double f0, double pivot_tol,
-                                                       int* __restrict__ fail) {
-  const int b = blockIdx.x;
+// L = lower(M) + shift on the diagonal, identity on the padding rows.
+__global__ void __launch_bounds__(64) k_chol_init(const int* __restrict__ off, int dim,
+                                                  const int64_t* __restrict__ moff, const double* __restrict__ M,
+                                                  double* __restrict__ Lf, const int* __restrict__ active,
+                                                  const double* __restrict__ shift, double f0, int* __restrict__ fail) {
+  const int b = blockIdx.y;
+  if (!active[b]) return;
+  const int n = dim * (off[b + 1] - off[b]);
+  const int ld = pad16(n);
+  const int i = blockIdx.x;
+  if (i >= ld) return;
+  if (i == 0 && threadIdx.x == 0) fail[b] = 0;
+  const double* A = M + moff[b];
+  double* L = Lf + moff[b];
+  const double sh = shift[b] * f0;
+  for (int j = threadIdx.x; j < ld; j += blockDim.x) {
+    double v = 0.0;
+    if (j <= i) {
+      if (i < n) v = A[(int64_t)i * ld + j] + (i == j ? sh : 0.0);
+      else if (i == j) v = 1.0;
+    }
+    L[(int64_t)i * ld + j] = v;
+  }
+}
+
+// The diagonal tile (p, p) factored in registers: lane r (mod 16) holds row
+// r; shuffles within each group of 16 lanes broadcast the pivot column.
+// bad = some pivot <= pivot_tol f0.
+__device__ inline void factor_diag_tile(const double* L, int ld, int c0, double row[16], bool& bad, double f0,
+                                        double pivot_tol) {
+  const int r = threadIdx.x & 15;
+#pragma unroll
+  for (int c = 0; c < 16; ++c) row[c] = (c <= r) ? L[(int64_t)(c0 + r) * ld + c0 + c] : 0.0;
+  bad = false;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const double d = __shfl(row[j], j, 16);
+    bad = bad || !(d > pivot_tol * f0);
+    const double sd = sqrt(d > 0.0 ? d : 1.0);
+    if (r == j) row[j] = sd;
+    else if (r > j) row[j] = row[j] / sd;
+#pragma unroll
+    for (int c = j + 1; c < 16; ++c) {
+      const double lc = __shfl(row[j], c, 16);  // L[c][j]
+      if (r >= c) row[c] -= row[j] * lc;
+    }
+  }
+}
+
+// Row tiles I > p of the panel: L_Ip = A_Ip L_pp^-T.  Every workgroup factors
+// the diagonal tile itself from the still unfactored L_pp (it is written back
+// by the update launch, after all of them have read it).
+__global__ void __launch_bounds__(64) k_chol_panel(const int* __restrict__ off, int dim,
+                                                   const int64_t* __restrict__ moff, double* __restrict__ Lf,
+                                                   const int* __restrict__ active, int p, double f0, double pivot_tol) {
+  __shared__ double D[16][17];
+  const int b = blockIdx.y;
   if (!active[b]) return;
   const int n = dim * (off[b + 1] - off[b]);
   const int ld = pad16(n);
   const int nt = ld / 16;
-  const double* A = M + moff[b];
+  const int I = p + 1 + blockIdx.x;
+  if (I >= nt) return;
   double* L = Lf + moff[b];
-  const double sh = shift[b] * f0;
-  for (int64_t q = threadIdx.x; q < (int64_t)ld * ld; q += blockDim.x) {
-    const int i = (int)(q / ld), j = (int)(q - (int64_t)i * ld);
-    double v = 0.0;
-    if (j <= i) {
-      if (i < n) v = A[q] + (i == j ? sh : 0.0);
-      else if (i == j) v = 1.0;
-    }
-    L[q] = v;
+  const int lane = threadIdx.x;
+  const int r = lane & 15;
+  const int c0 = 16 * p;
+  double row[16];
+  bool bad;
+  factor_diag_tile(L, ld, c0, row, bad, f0, pivot_tol);
+  if (lane < 16) {
+#pragma unroll
+    for (int c = 0; c < 16; ++c) D[r][c] = row[c];
   }
-  __shared__ double s_piv;
-  __shared__ int s_fail;
-  if (threadIdx.x == 0) s_fail = 0;
   __syncthreads();
-  const int lane = threadIdx.x & (kWave - 1);
-  const int wv = threadIdx.x / kWave;
-  const int nw = blockDim.x / kWave;
-  for (int p = 0; p < nt; ++p) {
-    const int c0 = 16 * p;
-    // panel: columns c0..c0+15, rows c0..ld-1, unblocked right-looking
-    for (int jj = 0; jj < 16; ++jj) {
-      const int col = c0 + jj;
-      if (threadIdx.x == 0) {
-        const double d = L[(int64_t)col * ld + col];
-        if (!(d > pivot_tol * f0)) s_fail = 1;
-        s_piv = sqrt(d > 0 ? d : 1.0);
-        L[(int64_t)col * ld + col] = s_piv;
-      }
-      __syncthreads();
-      if (s_fail) break;
-      const double inv = 1.0 / s_piv;
-      for (int i = col + 1 + threadIdx.x; i < ld; i += blockDim.x) L[(int64_t)i * ld + col] *= inv;
-      __syncthreads();
-      const int ncol = 15 - jj;  // remaining panel columns
-      if (ncol > 0) {
-        const int nrow = ld - col - 1;
-        for (int q = threadIdx.x; q < nrow * ncol; q += blockDim.x) {
-          const int i = col + 1 + q / ncol;
-          const int c = col + 1 + q % ncol;
-          if (c <= i) L[(int64_t)i * ld + c] -= L[(int64_t)i * ld + col] * L[(int64_t)c * ld + col];
-        }
-      }
-      __syncthreads();
-    }
-    if (s_fail) break;
-    // trailing update of the lower tiles (I, J), p < J <= I < nt
-    const int T = nt - p - 1;
-    const int ntiles = T * (T + 1) / 2;
-    for (int t = wv; t < ntiles; t += nw) {
-      // unrank t -> (I, J) in row-major lower-triangular order
-      int I = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
-      while ((I + 1) * (I + 2) / 2 <= t) ++I;
-      while (I * (I + 1) / 2 > t) --I;
-      const int J = t - I * (I + 1) / 2;
-      const int r0 = 16 * (p + 1 + I), q0 = 16 * (p + 1 + J);
-      dvec4 acc;
-      const int ci = lane & 15, rq = lane >> 4;
+  if (lane >= 16) return;
+  // row r of tile I: x L_pp^T = a, forward substitution over the 16 columns
+  double* Lr = L + (int64_t)(16 * I + r) * ld + c0;
+  double x[16];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) acc[r] = L[(int64_t)(r0 + 4 * r + rq) * ld + q0 + ci];
+  for (int c = 0; c < 16; ++c) x[c] = Lr[c];
 #pragma unroll
-      for (int k0 = 0; k0 < 16; k0 += 4) {
-        const double a = -L[(int64_t)(r0 + ci) * ld + c0 + k0 + rq];
-        const double bb = L[(int64_t)(q0 + ci) * ld + c0 + k0 + rq];
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc, 0, 0, 0);
-      }
+  for (int c = 0; c < 16; ++c) {
+    double t = x[c];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = r0 + 4 * r + rq, cc = q0 + ci;
-        if (I != J || cc <= row) L[(int64_t)row * ld + cc] = acc[r];
-      }
-    }
-    __syncthreads();
+    for (int k = 0; k < c; ++k) t -= x[k] * D[c][k];
+    x[c] = t / D[c][c];
   }
-  if (threadIdx.x == 0) fail[b] = s_fail;
+#pragma unroll
+  for (int c = 0; c < 16; ++c) Lr[c] = x[c];
+}
+
+// Block 0: write the factored diagonal tile (p, p) and the pivot verdict.
+// Blocks 1..: the trailing tiles (I, J), p < J <= I: L_IJ -= L_Ip L_Jp^T.
+__global__ void __launch_bounds__(64) k_chol_update(const int* __restrict__ off, int dim,
+                                                    const int64_t* __restrict__ moff, double* __restrict__ Lf,
+                                                    const int* __restrict__ active, int p, double f0,
+                                                    double pivot_tol, int* __restrict__ fail) {
+  const int b = blockIdx.y;
+  if (!active[b]) return;
+  const int n = dim * (off[b + 1] - off[b]);
+  const int ld = pad16(n);
+  const int nt = ld / 16;
+  if (p >= nt) return;
+  double* L = Lf + moff[b];
+  const int c0 = 16 * p;
+  const int lane = threadIdx.x;
+  if (blockIdx.x == 0) {
+    double row[16];
+    bool bad;
+    factor_diag_tile(L, ld, c0, row, bad, f0, pivot_tol);
+    if (lane < 16) {
+      const int r = lane;
+#pragma unroll
+      for (int c = 0; c < 16; ++c)
+        if (c <= r) L[(int64_t)(c0 + r) * ld + c0 + c] = row[c];
+    }
+    if (lane == 0 && bad) fail[b] = 1;
+    return;
+  }
+  const int T = nt - p - 1;
+  const int t = blockIdx.x - 1;
+  if (t >= T * (T + 1) / 2) return;
+  // unrank t -> (I, J) in row-major lower-triangular order
+  int I = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+  while ((I + 1) * (I + 2) / 2 <= t) ++I;
+  while (I * (I + 1) / 2 > t) --I;
+  const int J = t - I * (I + 1) / 2;
+  const int r0 = 16 * (p + 1 + I), q0 = 16 * (p + 1 + J);
+  const int ci = lane & 15, rq = lane >> 4;
+  dvec4 acc;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) acc[k] = L[(int64_t)(r0 + 4 * k + rq) * ld + q0 + ci];
+#pragma unroll
+  for (int k0 = 0; k0 < 16; k0 += 4) {
+    const double a = -L[(int64_t)(r0 + ci) * ld + c0 + k0 + rq];
+    const double bb = L[(int64_t)(q0 + ci) * ld + c0 + k0 + rq];
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc, 0, 0, 0);
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int row = r0 + 4 * k + rq, cc = q0 + ci;
+    if (I != J || cc <= row) L[(int64_t)row * ld + cc] = acc[k];
+  }
 }
 
 // X = L^-1 (L lower triangular, 16x16 tiles).  First every diagonal tile is
@@ -334,9 +401,20 @@ void launch_mob_assemble(int dim, int nb, const int* offsets, const int64_t* mof
 }
 
 void launch_chol(int nb, const int* offsets, int dim, const int64_t* moff, const double* M, double* Lf,
-                 const int* active, const double* shift, double f0, double pivot_tol, int* fail, hipStream_t s) {
-  hipLaunchKernelGGL(k_chol, dim3(nb), dim3(kCholThreads), 0, s, offsets, dim, moff, M, Lf, active, shift, f0,
-                     pivot_tol, fail);
+                 const int* active, const double* shift, double f0, double pivot_tol, int* fail, int max_rows,
+                 hipStream_t s) {
+  const int ldmax = (max_rows + 15) & ~15;
+  const int ntmax = ldmax / 16;
+  hipLaunchKernelGGL(k_chol_init, dim3(ldmax, nb), dim3(64), 0, s, offsets, dim, moff, M, Lf, active, shift, f0,
+                     fail);
+  for (int p = 0; p < ntmax; ++p) {
+    const int T = ntmax - p - 1;
+    if (T > 0)
+      hipLaunchKernelGGL(k_chol_panel, dim3(T, nb), dim3(64), 0, s, offsets, dim, moff, Lf, active, p, f0,
+                         pivot_tol);
+    hipLaunchKernelGGL(k_chol_update, dim3(T * (T + 1) / 2 + 1, nb), dim3(64), 0, s, offsets, dim, moff, Lf, active,
+                       p, f0, pivot_tol, fail);
+  }
 }
 
 void launch_chol_inverse(int nb, const int* offsets, int dim, const int64_t* moff, double* Lf, double* Minv,

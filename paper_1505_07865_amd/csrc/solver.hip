@@ -546,7 +546,8 @@ void factor_blocks(ibr_ctx* c) {
     for (int b = 0; b < nb; ++b) c->shift_h[b] = kShifts[idx[b]];
     IBR_HIP(hipMemcpyAsync(c->shift_d, c->shift_h.data(), nb * sizeof(double), hipMemcpyHostToDevice, s));
     IBR_HIP(hipMemcpyAsync(c->act_d, act.data(), nb * sizeof(int), hipMemcpyHostToDevice, s));
-    launch_chol(nb, c->off_d, c->dim, c->moff_d, c->Mb, c->Lb, c->act_d, c->shift_d, c->f0, kPivotTol, c->fail_d, s);
+    launch_chol(nb, c->off_d, c->dim, c->moff_d, c->Mb, c->Lb, c->act_d, c->shift_d, c->f0, kPivotTol, c->fail_d,
+                c->max_rows, s);
     IBR_HIP(hipMemcpyAsync(fail.data(), c->fail_d, nb * sizeof(int), hipMemcpyDeviceToHost, s));
     sync(c);
     bool any = false;
