@@ -42,8 +42,12 @@ MEASURED_TRAFFIC = {
     "rb_fine": {"bytes_per_launch": 25980544.0, "file": "paper_1505_07865_amd/csrc/ops_mg.hip",
                 "sha256_16": "a0aacda458ee2a37", "summary": "profiles/rb_fine_128cube_mixed_hbm_counters.md"},
 }
-# strides coprime with the launch pattern (16 finest-level sweeps per P_S^-1) so the samples cycle
-TIMER_STRIDE = {"rb_fine": 13, "ortho_dot": 3, "ortho_axpy": 3, "stokes_apply": 3}
+# strides coprime with the launch pattern (12 finest-level sweeps per P_S^-1, 2 V-cycle calls
+# per P_S^-1) so the samples cycle through it; sparse enough that the sampled launches' events
+# cost about 1% of the step
+TIMER_STRIDE = {"rb_fine": 29, "ortho_dot": 7, "ortho_axpy": 7, "stokes_apply": 7, "vcycle": 9}
+# composite classes (several kernels per sample): reported, never the roofline kernel
+COMPOSITE_TIMERS = ("vcycle",)
 
 
 def parse():
@@ -114,13 +118,14 @@ def run_precision(prob, prec, steps, warmup, torch):
         ibr.timer_enable(t, TIMER_STRIDE[t])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    lat, its, ps, res = [], [], [], []
+    lat, its, ps, vc, res = [], [], [], [], []
     for _ in range(steps):
         t1 = time.perf_counter()
         info = s.step()
         lat.append((time.perf_counter() - t1) * 1e3)
         its.append(info["iters"])
         ps.append(info["ps_applications"])
+        vc.append(info["vcycles"])
         res.append(info["rel_residual"])
     torch.cuda.synchronize()
     total = time.perf_counter() - t0
@@ -135,6 +140,7 @@ def run_precision(prob, prec, steps, warmup, torch):
         "p99_ms": percentile(lat, 99),
         "fgmres_iters_mean": sum(its) / len(its),
         "ps_applications_mean": sum(ps) / len(ps),
+        "vcycles_mean": sum(vc) / len(vc),
         "max_rel_residual": max(res),
         "timers": timers,
     }
@@ -156,7 +162,8 @@ def roofline(timers):
 
     Classes are sampled with different strides, so the dominant one is chosen
     by the estimated total time (sampled time x stride)."""
-    best = max(timers.items(), key=lambda kv: kv[1]["ms"] * TIMER_STRIDE[kv[0]])
+    best = max(((k, v) for k, v in timers.items() if k not in COMPOSITE_TIMERS),
+               key=lambda kv: kv[1]["ms"] * TIMER_STRIDE[kv[0]])
     name, t = best
     if t["launches"] == 0 or t["ms"] <= 0:
         return None, {}
@@ -493,6 +500,11 @@ def main():
         "roofline": roof,
         "kernels": others,
     }
+    if "vcycle" in others:
+        # whole V-cycle calls: each P_S^-1 makes one on the 3 velocity fields and one on the pressure
+        line["ms_per_vcycle_call"] = round(others["vcycle"]["us_per_launch"] / 1e3, 4)
+        line["vcycle_calls_per_step"] = round(2 * head["ps_applications_mean"], 2)
+        line["field_vcycles_per_step"] = round(head["vcycles_mean"], 2)
     for p in precs:
         line[p] = {k: (float("%.4g" % v) if isinstance(v, float) else v) for k, v in res[p].items() if k != "timers"}
     if "mixed" in res and "fp64" in res:

@@ -36,7 +36,14 @@ inline void dev_free(void* p) {
 }
 
 // ---------------------------------------------------------------- live kernel timers
-enum TimerId { kTimerRbFine = 0, kTimerOrthoDot = 1, kTimerOrthoAxpy = 2, kTimerStokes = 3, kTimerCount = 4 };
+enum TimerId {
+  kTimerRbFine = 0,
+  kTimerOrthoDot = 1,
+  kTimerOrthoAxpy = 2,
+  kTimerStokes = 3,
+  kTimerVcycle = 4,  // whole V-cycles (events recorded around all of their kernels)
+  kTimerCount = 5
+};
 // A launch of a timed class is sampled (every stride-th one): the sampled launch
 // gets a start and a stop event to pass to hipExtLaunchKernelGGL, which stamps
 // them with the kernel's own start and end; unsampled launches get null events

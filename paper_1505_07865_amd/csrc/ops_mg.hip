@@ -686,6 +686,14 @@ void MGHier<T>::vcycle(int nf, const T* b, T* x, double c0, double c1, int nu_pr
   // post-smoothing) and xout (the level's result, the correction the finer
   // level interpolates).  They differ only on levels whose post-smoothing runs
   // the fused kernel, which cannot update x in place.
+  // whole-cycle timer; algorithmic bytes: per level of C cells and field the
+  // per-step kernels' (first sweep 2, each further sweep 3, residual and
+  // restriction 2 + 1/8, black prolongation 1 + 1/8, words of w per cell),
+  // over the levels about 8/7 of the finest one
+  const double words_per_cell = 2.0 + 3.0 * (nu_pre > 0 ? nu_pre - 1 : 0) + 2.125 + 1.125 + 3.0 * nu_post;
+  const TimerEvents evc =
+      timer_sample(kTimerVcycle, words_per_cell * 8.0 / 7.0 * (double)((int64_t)1 << (dim * logn)) * nf * sizeof(T));
+  if (evc.start) IBR_HIP(hipEventRecord(evc.start, s));
   auto post_fused = [&](int l) { return nu_post > 0 && fused(logn - l, nu_post, nf); };
   auto xin = [&](int l) -> T* {
     if (l == 0) return post_fused(0) ? x0_tmp : x;
@@ -761,6 +769,7 @@ void MGHier<T>::vcycle(int nf, const T* b, T* x, double c0, double c1, int nu_pr
     for (int sw = 0; sw < nu_post; ++sw)
       for (int color = 0; color < 2; ++color) rb_half(xl, bl, lg, nf, tc0, cl, color, l == 0, s);
   }
+  if (evc.stop) IBR_HIP(hipEventRecord(evc.stop, s));
 }
 
 template struct MGHier<double>;

@@ -5,7 +5,9 @@
 // launch goes through hipExtLaunchKernelGGL with a start and a stop event,
 // which the runtime stamps with the kernel's own start and end (the same
 // interval a kernel trace reports), and its algorithmic bytes are
-// accumulated.  Disabled timers cost one branch per launch.
+// accumulated.  The "vcycle" class times whole V-cycles instead, with events
+// recorded on the stream before the first and after the last of their kernels.
+// Disabled timers cost one branch per launch.
 #include <cstring>
 #include <vector>
 
@@ -27,7 +29,7 @@ struct TimerState {
 
 TimerState g_timers[kTimerCount];
 
-const char* const kTimerNames[kTimerCount] = {"rb_fine", "ortho_dot", "ortho_axpy", "stokes_apply"};
+const char* const kTimerNames[kTimerCount] = {"rb_fine", "ortho_dot", "ortho_axpy", "stokes_apply", "vcycle"};
 
 int timer_index(const char* name) {
   if (!name) return -1;

@@ -363,7 +363,7 @@ class Solver:
         return N
 
 
-TIMERS = ("rb_fine", "ortho_dot", "ortho_axpy", "stokes_apply")
+TIMERS = ("rb_fine", "ortho_dot", "ortho_axpy", "stokes_apply", "vcycle")
 
 
 def timer_enable(kernel, stride=1):
