@@ -112,8 +112,13 @@ def run_precision(prob, prec, steps, warmup, torch):
     # again before the timed region resets the counters
     for t in ibr.TIMERS:
         ibr.timer_enable(t, TIMER_STRIDE[t])
-    for _ in range(warmup):
+    ref_state = None
+    for w in range(warmup):
         s.step()
+        if w == 1:
+            # state after the first two steps (outside the timed region), for the error against the oracle
+            sol = s.solution()
+            ref_state = {"u": sol.u, "F": sol.F}
     for t in ibr.TIMERS:
         ibr.timer_enable(t, TIMER_STRIDE[t])
     torch.cuda.synchronize()
@@ -143,6 +148,7 @@ def run_precision(prob, prec, steps, warmup, torch):
         "vcycles_mean": sum(vc) / len(vc),
         "max_rel_residual": max(res),
         "timers": timers,
+        "state_after_2_steps": ref_state,
     }
 
 
@@ -183,18 +189,21 @@ def roofline(timers):
 
 
 def cpu_baseline(prob, nsteps=2):
-    """The oracle's exact solves of the workload's first time steps, timed on the host."""
+    """The oracle's exact solves of the workload's first time steps, timed on
+    the host.  Returns the baseline record and the oracle's solution of the
+    last of those steps (the reference the GPU solutions are compared with)."""
     from oracle import navier
     from threadpoolctl import threadpool_limits
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
-        sols = navier.run(prob, nsteps, dense_limit=0, tol=1e-8)
+        sols = navier.run(prob, nsteps, dense_limit=0, tol=1e-10)
         dt = time.perf_counter() - t0
-    return {"value": round(nsteps / dt, 5), "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": "exact constrained solves of the workload's first %d time steps (explicit advection "
-                      "right-hand side, Fourier Stokes solves + CG on the 5280x5280 mobility system to 1e-8, "
-                      "%s CG iterations), %.1f s single-threaded NumPy" %
-                      (nsteps, "+".join(str(q.cg_iters) for q in sols), dt)}
+    rec = {"value": round(nsteps / dt, 5), "unit": "solves/s", "cores": 1, "kind": "oracle",
+           "sample": "exact constrained solves of the workload's first %d time steps (explicit advection "
+                     "right-hand side, Fourier Stokes solves + CG on the 5280x5280 mobility system to 1e-10, "
+                     "%s CG iterations), %.1f s single-threaded NumPy" %
+                     (nsteps, "+".join(str(q.cg_iters) for q in sols), dt)}
+    return rec, sols[-1]
 
 
 def served(args, torch):
@@ -506,14 +515,24 @@ def main():
         line["vcycle_calls_per_step"] = round(2 * head["ps_applications_mean"], 2)
         line["field_vcycles_per_step"] = round(head["vcycles_mean"], 2)
     for p in precs:
-        line[p] = {k: (float("%.4g" % v) if isinstance(v, float) else v) for k, v in res[p].items() if k != "timers"}
+        line[p] = {k: (float("%.4g" % v) if isinstance(v, float) else v) for k, v in res[p].items()
+                   if k not in ("timers", "state_after_2_steps")}
     if "mixed" in res and "fp64" in res:
         line["mixed_over_fp64"] = round(res["mixed"]["solves_per_s"] / res["fp64"]["solves_per_s"], 3)
     if args.precision == "both" and not args.no_served:
         line["served"] = served(args, torch)
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle on the workload's first two steps", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(prob)
+        line["cpu_baseline"], ref = cpu_baseline(prob)
+        err = {}
+        for p in precs:
+            st = res[p]["state_after_2_steps"]
+            if st is not None:
+                err[p] = {"u": float("%.3g" % (np.linalg.norm(st["u"] - ref.v) / np.linalg.norm(ref.v))),
+                          "F": float("%.3g" % (np.linalg.norm(st["F"] - ref.F) / np.linalg.norm(ref.F)))}
+        if err:
+            err["reference"] = "the oracle's exact solution of the second time step (CG to 1e-10); relative L2"
+            line["err_vs_oracle"] = err
     print(json.dumps(line), flush=True)
 
 
