@@ -21,4 +21,6 @@ from .workloads import (  # noqa: F401
     icosphere_spacing,
     shell_problem,
     sedimentation_problem,
+    concentric_shells,
+    single_shell,
 )

@@ -269,6 +269,37 @@ def sedimentation_problem(seed: int = 0, n: int = 128, nbodies: int = 16, radius
     return prob, F, np.zeros((nbodies, 3))
 
 
+def concentric_shells(n: int = 64, level: int = 1, V: float = 1.0, box_over_outer: float = 4.15) -> Problem:
+    """Two concentric icosahedral shells in a periodic unit cube, 3D steady
+    Stokes, eta = 1 (the setting of the paper's concentric-shells study):
+    outer radius R2 = 1 / box_over_outer, inner radius R1 = R2 / 4; inner shell
+    of 10 * 4^level + 2 markers (body 0) translating with -V along x, outer
+    shell two refinement levels finer (about 16 times the markers, similar
+    spacing) at rest (body 1), both centred in the box.  This is the paper's
+    configuration (cavity moving with V around a sphere at rest) seen from the
+    cavity, so that the fluid outside the outer shell stays nearly at rest in
+    the periodic box, as the paper's boundary conditions make it.  Levels 0, 1,
+    2 give 12/162, 42/642 and 162/2562 markers, spaced about 2h at n = 32, 64,
+    128."""
+    h = 1.0 / n
+    R2 = 1.0 / box_over_outer
+    R1 = R2 / 4.0
+    c = np.array([0.5, 0.5, 0.5])
+    bodies = [icosphere_unit(level) * R1 + c, icosphere_unit(level + 2) * R2 + c]
+    U = np.array([[-V, 0.0, 0.0], [0.0, 0.0, 0.0]])
+    return _assemble(3, n, h, 0.0, 1.0, 0.0, bodies, np.stack([c, c]), U, np.zeros((2, 3)), [R1, R2], 0,
+                     "shells_%d_l%d" % (n, level))
+
+
+def single_shell(n: int = 64, level: int = 1, V: float = 1.0, box_over_outer: float = 4.15) -> Problem:
+    """The inner shell of ``concentric_shells`` alone in the periodic unit cube,
+    translating with V along x (its drag gives its hydrodynamic radius)."""
+    R1 = 1.0 / box_over_outer / 4.0
+    c = np.array([0.5, 0.5, 0.5])
+    return _assemble(3, n, 1.0 / n, 0.0, 1.0, 0.0, [icosphere_unit(level) * R1 + c], c[None, :].copy(),
+                     np.array([[V, 0.0, 0.0]]), np.zeros((1, 3)), [R1], 0, "shell_alone_%d_l%d" % (n, level))
+
+
 def small_problem(seed: int, dim: int, n: int, nbodies: int = 1, radius_h: float = 3.0,
                   rho: float = 0.0, eta: float = 1.0, dt: float = 0.0, gap_h: float = 4.0,
                   rotate: bool = True, nsteps: int = 0, L: float = 1.0) -> Problem:
