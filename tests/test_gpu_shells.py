@@ -7,7 +7,10 @@ the inner shell alone in the periodic box gives its hydrodynamic radius R1
 from its drag (periodic drag law, ``oracle.hasimoto``); the drag on it inside
 the cavity gives the cavity's radius R2 through the drag law of the paper's
 appendix; then the velocity and pressure errors against the analytic flow
-with those radii.  fp64, rtol 1e-10.
+with those radii.  fp64, rtol 1e-8 (the errors are of order 1e-2; an
+isolated 162-marker shell at 128^3 cannot reach 1e-10: with its small
+right-hand side, rounding in the h^-2-scaled operator leaves a relative
+residual of about 1.3e-10).
 
 Checks: at 32^3 the GPU numbers equal the oracle's exact solve's; under
 refinement R1/R1_geometric falls and R2/R2_geometric rises toward 1, and the
@@ -53,7 +56,7 @@ def test_concentric_shells_accuracy_table():
     from paper_1505_07865_amd import ibr
 
     def solver(prob):
-        return ibr.from_problem(prob, rtol=1e-10, restart=100, max_iters=3000, graphs=0)
+        return ibr.from_problem(prob, rtol=1e-8, restart=100, max_iters=3000, graphs=0)
 
     rows = []
     for n, level in LEVELS:
