@@ -79,9 +79,11 @@ __global__ void __launch_bounds__(256) k_stokes_apply(const TI* __restrict__ v, 
   for (int a = 0; a < DIM; ++a) {
     const TI* va = v + a * C;
     const TO vc = (TO)va[t];
-    TO s = (TO)va[m[0]] + (TO)va[pl[0]] + (TO)va[m[1]] + (TO)va[pl[1]];
-    if (DIM == 3) s += (TO)va[m[2]] + (TO)va[pl[2]];
-    const TO lap = s - TO(2 * DIM) * vc;
+    // the Laplacian as a sum of neighbour differences: each difference of two
+    // nearby values is exact, so a smooth field keeps its digits (the form
+    // sum - 2 dim vc loses about log10(n^2) of them to cancellation)
+    TO lap = (((TO)va[m[0]] - vc) + ((TO)va[pl[0]] - vc)) + (((TO)va[m[1]] - vc) + ((TO)va[pl[1]] - vc));
+    if (DIM == 3) lap += ((TO)va[m[2]] - vc) + ((TO)va[pl[2]] - vc);
     TO out = c0 * vc - ch2 * lap + (pc - (TO)p[m[a]]) * inv_h;
     if (addc) out += (TO)addc[a];
     yv[a * C + t] = out;
@@ -219,9 +221,10 @@ __global__ void __launch_bounds__(256) k_stokes_split4(const T* __restrict__ v, 
     for (int u = 0; u < 4; ++u) {
       const T xl = odd ? vo.v[u] : (u == 0 ? ve : vo.v[u - 1]);
       const T xr = odd ? (u == 3 ? ve : vo.v[u + 1]) : vo.v[u];
-      T s = xl + xr + vym.v[u] + vyp.v[u];
-      if (DIM == 3) s += vzm.v[u] + vzp.v[u];
-      const T lap = s - T(2 * DIM) * vc.v[u];
+      // neighbour differences (exact for nearby values; no cancellation of a sum)
+      const T c = vc.v[u];
+      T lap = ((xl - c) + (xr - c)) + ((vym.v[u] - c) + (vyp.v[u] - c));
+      if (DIM == 3) lap += (vzm.v[u] - c) + (vzp.v[u] - c);
       out.v[u] = c0 * vc.v[u] - ch2 * lap + (pc.v[u] - pm[a].v[u]) * inv_h;
       const T vplus = a == 0 ? xr : (a == 1 ? vyp.v[u] : vzp.v[u]);
       div[u] += (vplus - vc.v[u]) * inv_h;
