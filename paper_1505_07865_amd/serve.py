@@ -127,11 +127,12 @@ class Server:
     """
 
     def __init__(self, precision="mixed", workers=4, rtol=1e-8, device=0, reserve_bytes=8 << 30,
-                 factory=None, footprint=None, free_bytes=None, **solver_kw):
+                 factory=None, footprint=None, free_bytes=None, graphs=0, **solver_kw):
         self.precision = precision
         self.rtol = rtol
         self.device = device
         self.reserve_bytes = reserve_bytes
+        self.graphs = graphs
         self.solver_kw = solver_kw
         self.factory = factory or self._default_factory
         self.footprint = footprint or self._default_footprint
@@ -147,7 +148,7 @@ class Server:
         from . import ibr
         return dict(dim=prob.dim, n=prob.n, h=prob.h, rho=prob.rho, eta=prob.eta, dt=prob.dt, rtol=self.rtol,
                     precision=ibr.MIXED if self.precision == "mixed" else ibr.FP64, device=self.device,
-                    graphs=0, **self.solver_kw)
+                    graphs=self.graphs, **self.solver_kw)
 
     def _default_factory(self, prob):
         from . import ibr
