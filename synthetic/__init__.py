@@ -23,4 +23,6 @@ from .workloads import (  # noqa: F401
     sedimentation_problem,
     concentric_shells,
     single_shell,
+    slit_problem,
+    slit_shell,
 )

@@ -35,6 +35,8 @@ class Problem:
     Omega      [nb][1 or 3] prescribed angular velocities (1 component in 2D)
     radius     [nb] geometric radii (for reporting only)
     nsteps     number of time steps the trajectory was checked for
+    walls      0: periodic box; 1: no-slip walls at both ends of the last axis
+               (z in 3D, y in 2D), periodic along the others
     """
 
     dim: int
@@ -52,6 +54,7 @@ class Problem:
     nsteps: int = 0
     name: str = ""
     meta: dict = field(default_factory=dict)
+    walls: int = 0     # 1: no-slip walls at both ends of the last axis (slit channel)
 
     @property
     def L(self) -> float:
@@ -396,3 +399,54 @@ def serving_trace(seed: int = 0, nreq: int = 2000, qps: float = 50.0) -> List[di
                          "serve_%d_%dd_%d" % (r, dim, n))
         out.append({"t": t, "problem": prob})
     return out
+
+
+def slit_problem(seed: int = 0, dim: int = 3, n: int = 32, nbodies: int = 2, radius_h: float = 3.0,
+                 eta: float = 1.0, gap_h: float = 4.0, wall_gap_h: float = 2.0, rotate: bool = True,
+                 L: float = 1.0) -> Problem:
+    """Steady Stokes in a slit channel: no-slip walls at z = 0 and z = L (y in
+    2D), periodic along the other axes; bodies as in ``small_problem``, with
+    centres drawn so that every surface keeps ``wall_gap_h`` cells from the
+    walls."""
+    rng = np.random.default_rng(seed)
+    h = L / n
+    rad = radius_h * h
+    U = rng.uniform(-1.0, 1.0, size=(nbodies, dim))
+    lo = rad + wall_gap_h * h
+    centres = np.zeros((nbodies, dim))
+    placed = 0
+    tries = 0
+    while placed < nbodies:
+        tries += 1
+        if tries > 200000:
+            raise RuntimeError("could not place %d bodies in the slit" % nbodies)
+        c = rng.uniform(0.0, L, size=dim)
+        c[-1] = rng.uniform(lo, L - lo)
+        if all(np.sqrt((_min_image(c - centres[q], L) ** 2).sum()) >= 2 * rad + gap_h * h for q in range(placed)):
+            centres[placed] = c
+            placed += 1
+    if dim == 3:
+        Om = rng.uniform(-1.0, 1.0, size=(nbodies, 3)) if rotate else np.zeros((nbodies, 3))
+        bodies = [fibonacci_sphere(sphere_markers_for(radius_h), rad, c) for c in centres]
+    else:
+        Om = rng.uniform(-1.0, 1.0, size=(nbodies, 1)) if rotate else np.zeros((nbodies, 1))
+        bodies = [disk_ring(disk_markers_for(radius_h), rad, c, rng.uniform(0, 2 * math.pi)) for c in centres]
+    prob = _assemble(dim, n, h, 0.0, eta, 0.0, bodies, centres, U, Om, [rad] * nbodies, 0,
+                     "slit_%dd_%d" % (dim, n))
+    prob.walls = 1
+    return prob
+
+
+def slit_shell(n: int = 32, level: int = 0, height: float = 0.5, radius: float = 0.0625, V: float = 1.0) -> Problem:
+    """One icosahedral shell (10 * 4^level + 2 markers) in the slit channel of
+    the paper's slit study: unit cube, no-slip walls at z = 0 and z = 1,
+    periodic along x and y, centre at height ``height`` (0.5: midplane, 0.25:
+    quarter), translating with V along x, parallel to the walls; steady
+    Stokes, eta = 1."""
+    h = 1.0 / n
+    c = np.array([0.5, 0.5, height])
+    prob = _assemble(3, n, h, 0.0, 1.0, 0.0, [icosphere_unit(level) * radius + c], c[None, :].copy(),
+                     np.array([[V, 0.0, 0.0]]), np.zeros((1, 3)), [radius], 0,
+                     "slit_shell_%d_l%d_h%g" % (n, level, height))
+    prob.walls = 1
+    return prob
