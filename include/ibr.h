@@ -14,7 +14,10 @@
  *
  * Layouts (all host arrays are row-major, double precision):
  *   grid      periodic box [0, n h)^dim, cells indexed (k, j, i) with i (x)
- *             fastest; cell centres at ((i+1/2)h, (j+1/2)h, (k+1/2)h).
+ *             fastest; cell centres at ((i+1/2)h, (j+1/2)h, (k+1/2)h).  With
+ *             walls = IBR_WALLS_NOSLIP the last axis (z in 3D, y in 2D) ends
+ *             at no-slip walls at 0 and n h instead of wrapping; the normal
+ *             velocity's faces with index 0 along it lie on the wall and hold 0.
  *   velocity  u[dim][n^dim]: component a of cell c lives on the a-face half a
  *             cell below the centre along a (the MAC grid of Sec. 3).
  *   pressure  p[n^dim] at cell centres, returned with zero mean.
@@ -51,6 +54,10 @@ typedef enum {
 
 typedef enum { IBR_FP64 = 0, IBR_MIXED = 1 } ibr_precision;
 typedef enum { IBR_PC_LOWER = 0, IBR_PC_FULL = 1 } ibr_pc;
+/* Boundaries along the last axis: periodic, or no-slip walls at both ends
+ * (the slit channel of Sec. 7; boundary rules of the appendix on physical
+ * boundary conditions). */
+typedef enum { IBR_WALLS_NONE = 0, IBR_WALLS_NOSLIP = 1 } ibr_walls;
 
 /* Problem and solver parameters.  Sec. 3.2 (eq. A_def) defines
  * A = (rho/dt) I - eta h^-2 L; rho == 0 selects steady Stokes, where the
@@ -76,6 +83,18 @@ typedef struct {
   void* stream;       /* hipStream_t to run on, or NULL for a library stream */
   int graphs;         /* 1 (default): replay each outer iteration as a captured
                          HIP graph; 0: plain stream launches (same kernels) */
+  int walls;          /* IBR_WALLS_NONE (default) or IBR_WALLS_NOSLIP: no-slip
+                         walls at both ends of the last axis, periodic along the
+                         others.  The tangential velocity's ghost values beyond
+                         a wall are its mirror image with the sign reversed,
+                         the pressure's (inside the preconditioner) with the
+                         sign kept; interpolation and spreading fold kernel taps
+                         beyond a wall the same way (J = J0 E, S = E^T S0).
+                         Steady Stokes then needs no mean-velocity condition
+                         and uses S as is.  Markers must lie strictly between
+                         the walls (ibr_set_bodies returns IBR_EINVAL
+                         otherwise); ibr_step (explicit advection) is periodic
+                         only and returns IBR_EINVAL with walls. */
 } ibr_params;
 
 /* Per-solve report.  ps_applications counts P_S^-1 applications, the cost
@@ -197,7 +216,11 @@ ibr_status ibr_interp(ibr_ctx* ctx, const double* u, double* V);
 
 /* One V-cycle (Sec. 5.2) for (c0 - c1 L) x = b on nfields independent
  * fields b[nfields][n^dim], x[nfields][n^dim]; c0 == 0 is the restricted
- * (mean-zero) inverse.  Runs in the context's precision. */
+ * (mean-zero) inverse.  Runs in the context's precision.  With walls,
+ * nfields == dim is the velocity cycle (components 0..dim-2 tangential, the
+ * last one normal, its wall faces pinned to 0) and nfields == 1 the pressure
+ * cycle (mirror with the sign kept; c0 == 0 is then the mean-zero inverse);
+ * other counts return IBR_EINVAL. */
 ibr_status ibr_vcycle(ibr_ctx* ctx, double c0, double c1, int nfields, const double* b,
                       double* x);
 

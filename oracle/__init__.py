@@ -39,8 +39,13 @@ What it computes, and from which passage of Kallemov, Bhalla, Griffith & Donev,
                   Sec. 7.6).
 * ``hasimoto``    periodic drag formulas used as pins (eqs. drag_periodic and
                   drag_periodic_2D).
+* ``walls``       the slit channel: no-slip walls at both ends of the last
+                  axis with the mirror extension of the appendix on physical
+                  boundary conditions (operators, folded interpolation and
+                  spreading, exact per-mode Stokes solve, V-cycle); Sec. 7
+                  studies a sphere in such a channel.
 * ``free``        free kinematics (Sec. 2 poses it, Sec. 8 names the enlarged
                   system and its body mobility N = (K* M^-1 K)^-1): bodies
                   moving under applied forces and torques, solved exactly.
 """
-from . import kernel, grid, ib, stokes, constrained, dense, mobility, multigrid, precond, navier, hasimoto, free  # noqa: F401
+from . import kernel, grid, ib, stokes, constrained, dense, mobility, multigrid, precond, navier, hasimoto, free, walls  # noqa: F401

@@ -60,13 +60,13 @@ bool timers_any();  // some timer is enabled
 template <typename TI, typename TO>
 void launch_stokes_apply(int dim, int logn, const TI* v, const TI* p, TO* yv, TO* yp, double c0, double ch2,
                          double inv_h, const double* addc, hipStream_t s, bool split = false,
-                         TimerEvents ev = TimerEvents());
+                         TimerEvents ev = TimerEvents(), int walls = 0);
 template <typename T>
 void launch_div_q(int dim, int logn, const T* v, const T* hp, T* q, double inv_h, hipStream_t s,
                   bool split = false);
 template <typename T>
 void launch_ps_finish(int dim, int logn, T* v, const T* phi, const T* q, T* pi, double h, double c0h2, double eta,
-                      const double* vmean, hipStream_t s, bool split = false);
+                      const double* vmean, hipStream_t s, bool split = false, int walls = 0);
 // nf fields: natural -> split storage (with conversion TS -> TD), and back
 template <typename TS, typename TD>
 void launch_to_split(int dim, int logn, const TS* src, TD* dst, int nf, hipStream_t s);
@@ -111,18 +111,30 @@ struct MGHier {
   // x0_tmp holds the pre-smoothed finest level when that level is fused)
   std::vector<T*> bufs_xo;
   T* x0_tmp = nullptr;
+  // slit channel (no-slip walls at both ends of the last axis): every level
+  // below the finest down to 4^dim in global memory (index 1 .. logn-2)
+  std::vector<T*> wall_x, wall_b;
   bool fused(int lg, int nu, int nf) const;
-  void init(int dim, int logn, int nfmax);
+  void init(int dim, int logn, int nfmax, bool walls = false);
   void release();
-  static size_t bytes(int dim, int logn, int nf);
+  static size_t bytes(int dim, int logn, int nf, bool walls = false);
   // One V-cycle for nf fields: x = V(b).  x and b hold nf fields of n^dim in
-  // split (red half, black half) storage; see launch_to_split.
+  // split (red half, black half) storage; see launch_to_split.  wall_mode 0:
+  // periodic; with walls 1: the velocity cycle (nf = dim: tangential
+  // components, then the normal one), 2: the pressure cycle (nf = 1).
   void vcycle(int nf, const T* b, T* x, double c0, double c1, int nu_pre, int nu_post, int nu_coarse,
-              hipStream_t s);
+              hipStream_t s, int wall_mode = 0);
   void rb_half(T* x, const T* b, int lg, int nf, T c0, T c1, int color, bool fine, hipStream_t s);
   // first sweep (red then black) from a zero guess, in one pass
   void rb_first(T* x, const T* b, int lg, int nf, T c0, T c1, bool fine, hipStream_t s);
 };
+
+// V-cycle with no-slip walls at both ends of the last axis (mode as in
+// MGHier::vcycle); wx, wb: per-level buffers 1 .. logn-2 (nf fields each).
+template <typename T>
+void launch_wall_vcycle(int dim, int logn, int nf, const T* b, T* x, const std::vector<T*>& wx,
+                        const std::vector<T*>& wb, double c0, double c1, int nu_pre, int nu_post, int nu_coarse,
+                        int mode, hipStream_t s);
 
 // ---------------------------------------------------------------- free kinematics
 // Body block of the stacked vector: U[nb][dim] then Omega[nb][1 or 3].
@@ -153,7 +165,7 @@ struct MarkerTaps {
 };
 
 void launch_marker_setup(int dim, int logn, int N, double h, double L, const double* R, MarkerTaps taps,
-                         int* tile_of, int tile_log, hipStream_t s);
+                         int* tile_of, int tile_log, hipStream_t s, int walls = 0);
 void launch_marker_velocity(int dim, int N, const double* R, const int* body, const double* centres,
                             const double* U, const double* Om, double L, double* V, hipStream_t s);
 void launch_move_markers(int dim, int N, int nb, double* R, double* centres, const int* body, const double* U,

@@ -54,11 +54,15 @@ struct Lat {
 // yv = A v + G p + addc, yp = -D v.   A = c0 I - ch2 L,  G, D with 1/h.
 // TI: storage type of the input, TO: of the output (arithmetic in TO).
 // Natural storage, one thread per cell.
+// walls: no-slip walls at both ends of the last axis (w = its coordinate):
+// a tangential component's neighbour beyond a wall is its mirror image with
+// the sign reversed (the cell itself, negated), the normal component's wall
+// faces hold 0 and are not equations (their rows are 0).
 template <typename TI, typename TO, int DIM>
 __global__ void __launch_bounds__(256) k_stokes_apply(const TI* __restrict__ v, const TI* __restrict__ p,
                                                       TO* __restrict__ yv, TO* __restrict__ yp, int logn,
                                                       TO c0, TO ch2, TO inv_h,
-                                                      const double* __restrict__ addc) {
+                                                      const double* __restrict__ addc, int walls) {
   const int64_t C = (int64_t)1 << (DIM * logn);
   const int64_t t64 = xcd_block(gridDim.x) * blockDim.x + threadIdx.x;
   if (t64 >= C) return;
@@ -74,20 +78,39 @@ __global__ void __launch_bounds__(256) k_stokes_apply(const TI* __restrict__ v, 
   m[2] = DIM == 3 ? L.index(i, j, k - 1) : t;
   pl[2] = DIM == 3 ? L.index(i, j, k + 1) : t;
   const TO pc = (TO)p[t];
+  const int w = DIM == 3 ? k : j;
+  const int n = 1 << logn;
   TO div = 0;
 #pragma unroll
   for (int a = 0; a < DIM; ++a) {
     const TI* va = v + a * C;
-    const TO vc = (TO)va[t];
+    TO vc = (TO)va[t];
+    TO nb[3][2];
+#pragma unroll
+    for (int q = 0; q < DIM; ++q) {
+      nb[q][0] = (TO)va[m[q]];
+      nb[q][1] = (TO)va[pl[q]];
+    }
+    if (walls) {
+      if (a == DIM - 1) {
+        if (w == 0) vc = TO(0);
+        if (w == 1) nb[DIM - 1][0] = TO(0);
+        if (w == n - 1) nb[DIM - 1][1] = TO(0);
+      } else {
+        if (w == 0) nb[DIM - 1][0] = -vc;
+        if (w == n - 1) nb[DIM - 1][1] = -vc;
+      }
+    }
     // the Laplacian as a sum of neighbour differences: each difference of two
     // nearby values is exact, so a smooth field keeps its digits (the form
     // sum - 2 dim vc loses about log10(n^2) of them to cancellation)
-    TO lap = (((TO)va[m[0]] - vc) + ((TO)va[pl[0]] - vc)) + (((TO)va[m[1]] - vc) + ((TO)va[pl[1]] - vc));
-    if (DIM == 3) lap += ((TO)va[m[2]] - vc) + ((TO)va[pl[2]] - vc);
+    TO lap = ((nb[0][0] - vc) + (nb[0][1] - vc)) + ((nb[1][0] - vc) + (nb[1][1] - vc));
+    if (DIM == 3) lap += (nb[2][0] - vc) + (nb[2][1] - vc);
     TO out = c0 * vc - ch2 * lap + (pc - (TO)p[m[a]]) * inv_h;
     if (addc) out += (TO)addc[a];
+    if (walls && a == DIM - 1 && w == 0) out = TO(0);
     yv[a * C + t] = out;
-    div += ((TO)va[pl[a]] - vc) * inv_h;
+    div += (nb[a][1] - vc) * inv_h;
   }
   yp[t] = -div;
 }
@@ -114,7 +137,8 @@ __global__ void __launch_bounds__(256) k_div_q(const T* __restrict__ v, const T*
 template <typename T, int DIM>
 __global__ void __launch_bounds__(256) k_ps_finish(T* __restrict__ v, const T* __restrict__ phi,
                                                    const T* __restrict__ q, T* __restrict__ pi, int logn,
-                                                   T h, T c0h2, T eta, const double* __restrict__ vmean) {
+                                                   T h, T c0h2, T eta, const double* __restrict__ vmean,
+                                                   int walls) {
   const int64_t C = (int64_t)1 << (DIM * logn);
   const int64_t t64 = xcd_block(gridDim.x) * blockDim.x + threadIdx.x;
   if (t64 >= C) return;
@@ -124,10 +148,11 @@ __global__ void __launch_bounds__(256) k_ps_finish(T* __restrict__ v, const T* _
   L.coords(t, i, j, k);
   const int m[3] = {L.index(i - 1, j, k), L.index(i, j - 1, k), DIM == 3 ? L.index(i, j, k - 1) : t};
   const T ph = phi[t];
+  const bool wall_face = walls && (DIM == 3 ? k : j) == 0;
 #pragma unroll
   for (int a = 0; a < DIM; ++a) {
     T mv = vmean ? (T)vmean[a] : T(0);
-    v[a * C + t] = v[a * C + t] - mv + h * (ph - phi[m[a]]);
+    v[a * C + t] = (wall_face && a == DIM - 1) ? T(0) : v[a * C + t] - mv + h * (ph - phi[m[a]]);
   }
   pi[t] = -c0h2 * ph + eta * q[t];
 }
@@ -156,6 +181,7 @@ __device__ inline void st4(T* p, const Q4<T>& q) {
 template <int DIM>
 struct Group {
   int H, own, oth, xl, xr, ym, yp, zm, zp;
+  int w;     // coordinate along the last axis (the walls' axis)
   bool odd;  // the group's cells sit at i = 2m + 1
   __device__ Group(int t, int logn) {
     const int C = 1 << (DIM * logn);
@@ -170,6 +196,7 @@ struct Group {
     const int j = row & mask;
     const int k = DIM == 3 ? (row >> logn) : 0;
     odd = ((c + j + k) & 1) != 0;
+    w = DIM == 3 ? k : j;
     const int ob = (1 - c) * H;
     own = c * H + (row << hl) + m0;
     oth = ob + (row << hl) + m0;
@@ -186,7 +213,7 @@ struct Group {
 template <typename T, int DIM>
 __global__ void __launch_bounds__(256) k_stokes_split4(const T* __restrict__ v, const T* __restrict__ p,
                                                        T* __restrict__ yv, T* __restrict__ yp, int logn, T c0, T ch2,
-                                                       T inv_h) {
+                                                       T inv_h, int walls) {
   const int64_t C = (int64_t)1 << (DIM * logn);
   const int t = (int)(xcd_block(gridDim.x) * blockDim.x + threadIdx.x);
   if (t >= (int)(C >> 2)) return;
@@ -207,14 +234,33 @@ __global__ void __launch_bounds__(256) k_stokes_split4(const T* __restrict__ v, 
 #pragma unroll
   for (int a = 0; a < DIM; ++a) {
     const T* va = v + a * C;
-    const Q4<T> vc = ld4(va + g.own);
+    Q4<T> vc = ld4(va + g.own);
     const Q4<T> vo = ld4(va + g.oth);
     const T ve = va[odd ? g.xr : g.xl];
-    const Q4<T> vym = ld4(va + g.ym), vyp = ld4(va + g.yp);
+    Q4<T> vym = ld4(va + g.ym), vyp = ld4(va + g.yp);
     Q4<T> vzm, vzp;
     if (DIM == 3) {
       vzm = ld4(va + g.zm);
       vzp = ld4(va + g.zp);
+    }
+    bool zero_row = false;
+    if (walls) {
+      // neighbours along the walls' axis: mirror images, or the wall faces' zeros
+      Q4<T>& wm = DIM == 3 ? vzm : vym;
+      Q4<T>& wp = DIM == 3 ? vzp : vyp;
+      const int n = 1 << logn;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (a == DIM - 1) {
+          if (g.w == 0) vc.v[u] = T(0);
+          if (g.w == 1) wm.v[u] = T(0);
+          if (g.w == n - 1) wp.v[u] = T(0);
+        } else {
+          if (g.w == 0) wm.v[u] = -vc.v[u];
+          if (g.w == n - 1) wp.v[u] = -vc.v[u];
+        }
+      }
+      zero_row = a == DIM - 1 && g.w == 0;
     }
     Q4<T> out;
 #pragma unroll
@@ -225,7 +271,7 @@ __global__ void __launch_bounds__(256) k_stokes_split4(const T* __restrict__ v, 
       const T c = vc.v[u];
       T lap = ((xl - c) + (xr - c)) + ((vym.v[u] - c) + (vyp.v[u] - c));
       if (DIM == 3) lap += (vzm.v[u] - c) + (vzp.v[u] - c);
-      out.v[u] = c0 * vc.v[u] - ch2 * lap + (pc.v[u] - pm[a].v[u]) * inv_h;
+      out.v[u] = zero_row ? T(0) : c0 * vc.v[u] - ch2 * lap + (pc.v[u] - pm[a].v[u]) * inv_h;
       const T vplus = a == 0 ? xr : (a == 1 ? vyp.v[u] : vzp.v[u]);
       div[u] += (vplus - vc.v[u]) * inv_h;
     }
@@ -275,11 +321,13 @@ __global__ void __launch_bounds__(256) k_div_q_split4(const T* __restrict__ v, c
 template <typename T, int DIM>
 __global__ void __launch_bounds__(256) k_ps_finish_split4(T* __restrict__ v, const T* __restrict__ phi,
                                                           const T* __restrict__ q, T* __restrict__ pi, int logn,
-                                                          T h, T c0h2, T eta, const double* __restrict__ vmean) {
+                                                          T h, T c0h2, T eta, const double* __restrict__ vmean,
+                                                          int walls) {
   const int64_t C = (int64_t)1 << (DIM * logn);
   const int t = (int)(xcd_block(gridDim.x) * blockDim.x + threadIdx.x);
   if (t >= (int)(C >> 2)) return;
   const Group<DIM> g(t, logn);
+  const bool wall_face = walls && g.w == 0;  // the normal component's wall faces stay 0
   const bool odd = g.odd;
   const Q4<T> ph = ld4(phi + g.own);
   Q4<T> pm[3];
@@ -296,7 +344,8 @@ __global__ void __launch_bounds__(256) k_ps_finish_split4(T* __restrict__ v, con
     const T mv = vmean ? (T)vmean[a] : T(0);
     Q4<T> va = ld4(v + a * C + g.own);
 #pragma unroll
-    for (int u = 0; u < 4; ++u) va.v[u] = va.v[u] - mv + h * (ph.v[u] - pm[a].v[u]);
+    for (int u = 0; u < 4; ++u)
+      va.v[u] = (wall_face && a == DIM - 1) ? T(0) : va.v[u] - mv + h * (ph.v[u] - pm[a].v[u]);
     st4(v + a * C + g.own, va);
   }
   const Q4<T> qq = ld4(q + g.own);
@@ -398,7 +447,8 @@ inline unsigned nblk(int64_t len, int bs = 256) { return (unsigned)((len + bs - 
 
 template <typename TI, typename TO>
 void launch_stokes_apply(int dim, int logn, const TI* v, const TI* p, TO* yv, TO* yp, double c0, double ch2,
-                         double inv_h, const double* addc, hipStream_t s, bool split, TimerEvents ev) {
+                         double inv_h, const double* addc, hipStream_t s, bool split, TimerEvents ev,
+                         int walls) {
   const int64_t C = (int64_t)1 << (dim * logn);
   if (split) {
     // the preconditioner's operator: same storage type in and out, no added constant
@@ -406,10 +456,10 @@ void launch_stokes_apply(int dim, int logn, const TI* v, const TI* p, TO* yv, TO
       if (!addc) {
         if (dim == 3)
           hipLaunchKernelGGL((k_stokes_split4<TO, 3>), dim3(nblk(C / 4)), dim3(256), 0, s, v, p, yv, yp, logn,
-                             (TO)c0, (TO)ch2, (TO)inv_h);
+                             (TO)c0, (TO)ch2, (TO)inv_h, walls);
         else
           hipLaunchKernelGGL((k_stokes_split4<TO, 2>), dim3(nblk(C / 4)), dim3(256), 0, s, v, p, yv, yp, logn,
-                             (TO)c0, (TO)ch2, (TO)inv_h);
+                             (TO)c0, (TO)ch2, (TO)inv_h, walls);
         return;
       }
     }
@@ -418,19 +468,19 @@ void launch_stokes_apply(int dim, int logn, const TI* v, const TI* p, TO* yv, TO
   // natural storage (the outer operator): the one launch a timer samples
   if (dim == 3)
     hipExtLaunchKernelGGL(k_stokes_apply<TI, TO, 3>, dim3(nblk(C)), dim3(256), 0, s, ev.start, ev.stop, 0, v, p, yv,
-                          yp, logn, (TO)c0, (TO)ch2, (TO)inv_h, addc);
+                          yp, logn, (TO)c0, (TO)ch2, (TO)inv_h, addc, walls);
   else
     hipExtLaunchKernelGGL(k_stokes_apply<TI, TO, 2>, dim3(nblk(C)), dim3(256), 0, s, ev.start, ev.stop, 0, v, p, yv,
-                          yp, logn, (TO)c0, (TO)ch2, (TO)inv_h, addc);
+                          yp, logn, (TO)c0, (TO)ch2, (TO)inv_h, addc, walls);
 }
 template void launch_stokes_apply<double, double>(int, int, const double*, const double*, double*, double*,
                                                   double, double, double, const double*, hipStream_t, bool,
-                                                  TimerEvents);
+                                                  TimerEvents, int);
 template void launch_stokes_apply<float, double>(int, int, const float*, const float*, double*, double*,
                                                  double, double, double, const double*, hipStream_t, bool,
-                                                 TimerEvents);
+                                                 TimerEvents, int);
 template void launch_stokes_apply<float, float>(int, int, const float*, const float*, float*, float*, double,
-                                                double, double, const double*, hipStream_t, bool, TimerEvents);
+                                                double, double, const double*, hipStream_t, bool, TimerEvents, int);
 
 template <typename T>
 void launch_div_q(int dim, int logn, const T* v, const T* hp, T* q, double inv_h, hipStream_t s, bool split) {
@@ -452,28 +502,28 @@ template void launch_div_q<float>(int, int, const float*, const float*, float*, 
 
 template <typename T>
 void launch_ps_finish(int dim, int logn, T* v, const T* phi, const T* q, T* pi, double h, double c0h2,
-                      double eta, const double* vmean, hipStream_t s, bool split) {
+                      double eta, const double* vmean, hipStream_t s, bool split, int walls) {
   const int64_t C = (int64_t)1 << (dim * logn);
   if (split) {
     if (dim == 3)
       hipLaunchKernelGGL((k_ps_finish_split4<T, 3>), dim3(nblk(C / 4)), dim3(256), 0, s, v, phi, q, pi, logn, (T)h,
-                         (T)c0h2, (T)eta, vmean);
+                         (T)c0h2, (T)eta, vmean, walls);
     else
       hipLaunchKernelGGL((k_ps_finish_split4<T, 2>), dim3(nblk(C / 4)), dim3(256), 0, s, v, phi, q, pi, logn, (T)h,
-                         (T)c0h2, (T)eta, vmean);
+                         (T)c0h2, (T)eta, vmean, walls);
     return;
   }
   if (dim == 3)
     hipLaunchKernelGGL((k_ps_finish<T, 3>), dim3(nblk(C)), dim3(256), 0, s, v, phi, q, pi, logn, (T)h, (T)c0h2,
-                       (T)eta, vmean);
+                       (T)eta, vmean, walls);
   else
     hipLaunchKernelGGL((k_ps_finish<T, 2>), dim3(nblk(C)), dim3(256), 0, s, v, phi, q, pi, logn, (T)h, (T)c0h2,
-                       (T)eta, vmean);
+                       (T)eta, vmean, walls);
 }
 template void launch_ps_finish<double>(int, int, double*, const double*, const double*, double*, double, double,
-                                       double, const double*, hipStream_t, bool);
+                                       double, const double*, hipStream_t, bool, int);
 template void launch_ps_finish<float>(int, int, float*, const float*, const float*, float*, double, double,
-                                      double, const double*, hipStream_t, bool);
+                                      double, const double*, hipStream_t, bool, int);
 
 template <typename TS, typename TD>
 void launch_to_split(int dim, int logn, const TS* src, TD* dst, int nf, hipStream_t s) {

@@ -17,9 +17,45 @@ inline unsigned nblk(int64_t len, int bs = 256) { return (unsigned)((len + bs - 
 __device__ inline int tap_base_index(int m, int s, int beta) { return (m * 2 + s) * 3 + beta; }
 
 // ---------------------------------------------------------------- marker set-up
+// walls: along the last axis the taps beyond a no-slip wall fold back onto
+// their mirror images with the sign reversed and taps on the wall faces of
+// the normal component are dropped (J = J0 E, S = E^T S0 with the extension
+// E of the appendix on physical boundary conditions); the folded taps are
+// kept as 4 consecutive points inside the lattice, so interpolation and
+// spreading use them unchanged.
+__device__ inline void fold_wall_taps(int& b0, double* w, int n, bool face) {
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  const int nb0 = b0 < 0 ? 0 : (b0 > n - 4 ? n - 4 : b0);
+  for (int t = 0; t < 4; ++t) {
+    int j = b0 + t;
+    double wt = w[t];
+    if (face) {
+      if (j == 0 || j == n) continue;
+      if (j < 0) {
+        j = -j;
+        wt = -wt;
+      } else if (j > n) {
+        j = 2 * n - j;
+        wt = -wt;
+      }
+    } else {
+      if (j < 0) {
+        j = -1 - j;
+        wt = -wt;
+      } else if (j >= n) {
+        j = 2 * n - 1 - j;
+        wt = -wt;
+      }
+    }
+    acc[j - nb0] += wt;
+  }
+  b0 = nb0;
+  for (int t = 0; t < 4; ++t) w[t] = acc[t];
+}
+
 __global__ void k_marker_setup(int dim, int logn, int N, double h, double L, const double* __restrict__ R,
                                int* __restrict__ base, double* __restrict__ w64, float* __restrict__ w32,
-                               int* __restrict__ tile_of, int tile_log) {
+                               int* __restrict__ tile_of, int tile_log, int walls) {
   const int m = blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= N) return;
   const int n = 1 << logn;
@@ -31,13 +67,15 @@ __global__ void k_marker_setup(int dim, int logn, int N, double h, double L, con
     for (int s = 0; s < 2; ++s) {
       const double sc = x / h - (s == 0 ? 0.5 : 0.0);
       const double fl = floor(sc);
-      const int b0 = (int)fl - 1;
+      int b0 = (int)fl - 1;
       const int bi = tap_base_index(m, s, beta);
+      double w[4];
+      for (int t = 0; t < 4; ++t) w[t] = phi4<double>(sc - (double)(b0 + t));
+      if (walls && beta == dim - 1) fold_wall_taps(b0, w, n, s == 1);
       base[bi] = b0;
       for (int t = 0; t < 4; ++t) {
-        const double w = phi4<double>(sc - (double)(b0 + t));
-        w64[bi * 4 + t] = w;
-        w32[bi * 4 + t] = (float)w;
+        w64[bi * 4 + t] = w[t];
+        w32[bi * 4 + t] = (float)w[t];
       }
     }
     const int cell = ((int)floor(x / h)) & (n - 1);
@@ -425,10 +463,10 @@ __global__ void __launch_bounds__(256) k_body_ft(int dim, const int* __restrict_
 }  // namespace
 
 void launch_marker_setup(int dim, int logn, int N, double h, double L, const double* R, MarkerTaps taps,
-                         int* tile_of, int tile_log, hipStream_t s) {
+                         int* tile_of, int tile_log, hipStream_t s, int walls) {
   if (N <= 0) return;
   hipLaunchKernelGGL(k_marker_setup, dim3(nblk(N)), dim3(256), 0, s, dim, logn, N, h, L, R, taps.base, taps.w64,
-                     taps.w32, tile_of, tile_log);
+                     taps.w32, tile_of, tile_log, walls);
 }
 
 void launch_marker_velocity(int dim, int N, const double* R, const int* body, const double* centres,

@@ -581,7 +581,7 @@ template void launch_sub_field_mean<double>(double*, int, int64_t, const double*
 template void launch_sub_field_mean<float>(float*, int, int64_t, const double*, hipStream_t);
 
 template <typename T>
-void MGHier<T>::init(int dim_, int logn_, int maxf) {
+void MGHier<T>::init(int dim_, int logn_, int maxf, bool walls) {
   dim = dim_;
   logn = logn_;
   nfmax = maxf;
@@ -604,6 +604,14 @@ void MGHier<T>::init(int dim_, int logn_, int maxf) {
     if (l < levels.size() && may_fuse<T>(dim, lgl)) bufs_xo[l] = dev_alloc<T>(Cl * nfmax);
   }
   x0_tmp = (!levels.empty() && may_fuse<T>(dim, logn)) ? dev_alloc<T>(((int64_t)1 << (dim * logn)) * nfmax) : nullptr;
+  wall_x.assign(logn > 2 ? logn - 1 : 1, nullptr);
+  wall_b.assign(logn > 2 ? logn - 1 : 1, nullptr);
+  if (walls)
+    for (int l = 1; l <= logn - 2; ++l) {
+      const int64_t Cl = (int64_t)1 << (dim * (logn - l));
+      wall_x[l] = dev_alloc<T>(Cl * nfmax);
+      wall_b[l] = dev_alloc<T>(Cl * nfmax);
+    }
 }
 
 template <typename T>
@@ -618,14 +626,20 @@ void MGHier<T>::release() {
   for (auto p : bufs_xo) dev_free(p);
   dev_free(x0_tmp);
   x0_tmp = nullptr;
+  for (auto p : wall_x) dev_free(p);
+  for (auto p : wall_b) dev_free(p);
+  wall_x.clear();
+  wall_b.clear();
   bufs_x.clear();
   bufs_b.clear();
   bufs_xo.clear();
 }
 
 template <typename T>
-size_t MGHier<T>::bytes(int dim, int logn, int nf) {
+size_t MGHier<T>::bytes(int dim, int logn, int nf, bool walls) {
   size_t tot = 0;
+  if (walls)
+    for (int l = logn - 1; l >= 2; --l) tot += 2 * ((size_t)1 << (dim * l)) * nf * sizeof(T);
   int lg = logn;
   while (((int64_t)1 << (dim * lg)) > kTailMaxCells) --lg;
   for (int l = logn - 1; l >= lg; --l) tot += 2 * ((size_t)1 << (dim * l)) * nf * sizeof(T);
@@ -677,7 +691,11 @@ void MGHier<T>::rb_first(T* x, const T* b, int lg, int nf, T c0, T c1, bool fine
 
 template <typename T>
 void MGHier<T>::vcycle(int nf, const T* b, T* x, double c0, double c1, int nu_pre, int nu_post, int nu_coarse,
-                       hipStream_t s) {
+                       hipStream_t s, int wall_mode) {
+  if (wall_mode != 0) {
+    launch_wall_vcycle<T>(dim, logn, nf, b, x, wall_x, wall_b, c0, c1, nu_pre, nu_post, nu_coarse, wall_mode, s);
+    return;
+  }
   const bool three = dim == 3;
   T cl = (T)c1;
   const T tc0 = (T)c0;

@@ -58,6 +58,11 @@ struct ibr_ctx {
   int64_t C = 0;
   double h = 0, L = 0, c0 = 0, ch2 = 0, inv_h = 0, vol = 0;
   bool steady = true;
+  // no-slip walls at both ends of the last axis (slit channel); the velocity
+  // then has no null space, so only periodic steady Stokes (vnull) carries
+  // the mean-velocity condition and S'
+  bool walls = false;
+  bool vnull = true;
   bool mixed = false;
   hipStream_t stream = nullptr;
   bool own_stream = false;
@@ -177,14 +182,14 @@ void apply_K(ibr_ctx* c, const TI* x, double* y) {
   const TI* xl = x + c->NF;
   launch_copy<TI, double>(xl, c->lamd, (int64_t)c->N * d, s);
   const double* addc = nullptr;
-  if (c->steady) {
+  if (c->vnull) {
     // -S' Lambda = -S Lambda + vol^-1 sum Lambda
     launch_lambda_sums(d, c->N, c->lamd, c->lsum_part, c->addc, 1.0 / c->vol, s);
     addc = c->addc;
   }
   const TimerEvents ev = timer_sample(kTimerStokes, (double)(d + 1) * c->C * (sizeof(TI) + sizeof(double)));
   launch_stokes_apply<TI, double>(d, c->logn, xv, xp, y, y + (int64_t)d * c->C, c->c0, c->ch2, c->inv_h, addc, s,
-                                  false, ev);
+                                  false, ev, c->walls ? 1 : 0);
   launch_spread<double, double>(d, c->logn, c->tile_log, c->act_cap, c->active, c->nactive_d, c->toff, c->perm,
                                 c->taps, c->lamd, y, -std::pow(c->h, -d), s);
   launch_interp<TI>(d, c->logn, c->N, c->taps, xv, -1.0, nullptr, 0.0, y + c->NF, s);
@@ -208,16 +213,17 @@ void ps_inv(ibr_ctx* c, const T* in, T* out) {
   T* pi = out + (int64_t)d * C;
   T* q = (T*)c->qT;
   T* phi = (T*)c->phiT;
-  mg.vcycle(d, g, v, c->c0, c->ch2, c->p.mg_pre, c->p.mg_post, c->p.mg_coarse, s);
+  const int wv = c->walls ? 1 : 0, wp = c->walls ? 2 : 0;
+  mg.vcycle(d, g, v, c->c0, c->ch2, c->p.mg_pre, c->p.mg_post, c->p.mg_coarse, s, wv);
   const double* vmean = nullptr;
-  if (c->steady) {
+  if (c->vnull) {
     launch_field_means<T>(v, d, C, c->mpart, 256, c->vmean, s);
     vmean = c->vmean;
   }
   launch_div_q<T>(d, c->logn, v, hp, q, c->inv_h, s, true);
   // L_p phi = q  <=>  (0 - (-1) L) phi = q
-  mg.vcycle(1, q, phi, 0.0, -1.0, c->p.mg_pre, c->p.mg_post, c->p.mg_coarse, s);
-  launch_ps_finish<T>(d, c->logn, v, phi, q, pi, c->h, c->c0 * c->h * c->h, c->p.eta, vmean, s, true);
+  mg.vcycle(1, q, phi, 0.0, -1.0, c->p.mg_pre, c->p.mg_post, c->p.mg_coarse, s, wp);
+  launch_ps_finish<T>(d, c->logn, v, phi, q, pi, c->h, c->c0 * c->h * c->h, c->p.eta, vmean, s, true, wv);
   c->cnt_ps += 1;
   c->cnt_vc += d + 1;
 }
@@ -247,7 +253,7 @@ void inner_gmres(ibr_ctx* c, const T* rhs, T* out) {
       T* Wj = Q + (int64_t)j * NF;
       ps_inv<T>(c, pj, Zj);
       launch_stokes_apply<T, T>(d, c->logn, Zj, Zj + (int64_t)d * c->C, Wj, Wj + (int64_t)d * c->C, c->c0, c->ch2,
-                                c->inv_h, nullptr, s, true);
+                                c->inv_h, nullptr, s, true, TimerEvents(), c->walls ? 1 : 0);
     }
     launch_gram_solve<T>(Q, NF, ns, rhs, NF, c->part, c->part_blocks, c->yi, s);
     launch_combine_from_split<T, T>(d, c->logn, Z, NF, ns, c->yi, out, d + 1, true, s);
@@ -265,7 +271,7 @@ void inner_gmres(ibr_ctx* c, const T* rhs, T* out) {
     T* w = Q + (int64_t)(j + 1) * NF;
     ps_inv<T>(c, Qj, Zj);
     launch_stokes_apply<T, T>(d, c->logn, Zj, Zj + (int64_t)d * c->C, w, w + (int64_t)d * c->C, c->c0, c->ch2,
-                              c->inv_h, nullptr, s, true);
+                              c->inv_h, nullptr, s, true, TimerEvents(), c->walls ? 1 : 0);
     double* hcol = c->Hi + (int64_t)j * ldh;
     // one Gram-Schmidt pass: the inner solve is only a preconditioner (FGMRES is flexible)
     arnoldi_step<T>(Q, NF, j, hcol, c->hc2i, c->part, c->part2, c->part_blocks, c->flag, s, false, false);
@@ -298,7 +304,7 @@ void precondition(ibr_ctx* c, const double* r, T* z) {
     // second fluid solve with r_v + S' Lambda
     launch_spread<double, T>(d, c->logn, c->tile_log, c->act_cap, c->active, c->nactive_d, c->toff, c->perm,
                              c->taps, c->lamd, rhs, std::pow(c->h, -d), s, true);
-    if (c->steady) {
+    if (c->vnull) {
       launch_lambda_sums(d, c->N, c->lamd, c->lsum_part, c->addc, 1.0 / c->vol, s);
       launch_sub_field_mean<T>(rhs, d, c->C, c->addc, s);
     }
@@ -487,6 +493,7 @@ void validate(const ibr_params* p) {
   if (p->mg_pre < 0 || p->mg_post < 0 || p->mg_coarse < 1 || p->mg_pre > 16 || p->mg_post > 16 ||
       p->mg_coarse > 256)
     throw Status(IBR_EINVAL, "bad multigrid sweep counts");
+  if (p->walls != IBR_WALLS_NONE && p->walls != IBR_WALLS_NOSLIP) throw Status(IBR_EINVAL, "bad walls");
 }
 
 MobParams mob_params(const ibr_ctx* c) {
@@ -519,7 +526,8 @@ double self_term(const MobParams& mp) {
 
 void setup_markers(ibr_ctx* c) {
   hipStream_t s = c->stream;
-  launch_marker_setup(c->dim, c->logn, c->N, c->h, c->L, c->R, c->taps, c->tile_of, c->tile_log, s);
+  launch_marker_setup(c->dim, c->logn, c->N, c->h, c->L, c->R, c->taps, c->tile_of, c->tile_log, s,
+                      c->walls ? 1 : 0);
   launch_bin_markers(c->N, c->ntiles, c->tile_of, c->counts, c->toff, c->cursor, c->perm, s);
   launch_active_tiles(c->dim, c->tiles_log, c->toff, c->flags, c->active, c->nactive_d, s);
   int na = 0;
@@ -710,11 +718,11 @@ void ibr_ctx::alloc_grid() {
   qT = talloc(C);
   phiT = talloc(C);
   if (mixed) {
-    mg32.init(d, logn, d);
-    bytes += MGHier<float>::bytes(d, logn, d);
+    mg32.init(d, logn, d, walls);
+    bytes += MGHier<float>::bytes(d, logn, d, walls);
   } else {
-    mg64.init(d, logn, d);
-    bytes += MGHier<double>::bytes(d, logn, d);
+    mg64.init(d, logn, d, walls);
+    bytes += MGHier<double>::bytes(d, logn, d, walls);
   }
   IBR_HIP(hipHostMalloc((void**)&hres, 64, hipHostMallocDefault));
   IBR_HIP(hipEventCreate(&ev0));
@@ -827,6 +835,8 @@ ibr_status ibr_create(const ibr_params* params, ibr_ctx** out) {
     c->L = params->n * params->h;
     c->vol = std::pow(c->L, c->dim);
     c->steady = params->rho == 0.0;
+    c->walls = params->walls == IBR_WALLS_NOSLIP;
+    c->vnull = c->steady && !c->walls;
     c->c0 = c->steady ? 0.0 : params->rho / params->dt;
     c->ch2 = params->eta / (c->h * c->h);
     c->inv_h = 1.0 / c->h;
@@ -871,7 +881,8 @@ size_t ibr_footprint_bytes(const ibr_params* p, int nbodies, int nmarkers) {
   b += (size_t)4 * NV * 8;             // x, b, two temporaries
   b += (size_t)2 * d * C * 8;          // advection history
   b += (size_t)((2 * ns + 2) * NF + 2 * C) * ts;  // inner bases and P_S^-1 scratch
-  b += ts == 4 ? MGHier<float>::bytes(d, ilog2(p->n), d) : MGHier<double>::bytes(d, ilog2(p->n), d);
+  const bool w = p->walls == IBR_WALLS_NOSLIP;
+  b += ts == 4 ? MGHier<float>::bytes(d, ilog2(p->n), d, w) : MGHier<double>::bytes(d, ilog2(p->n), d, w);
   // mobility blocks (4 buffers of sum (d N_p)^2), bounded by one block of all markers per body
   const int64_t per = nbodies > 0 ? (int64_t)d * nmarkers / nbodies : 0;
   b += (size_t)4 * nbodies * per * per * 8;
@@ -898,6 +909,11 @@ ibr_status ibr_set_bodies(ibr_ctx* c, int nbodies, const int* offsets, const dou
       if (!std::isfinite(R[i])) throw Status(IBR_EINVAL, "marker positions must be finite");
     for (int64_t i = 0; i < (int64_t)nbodies * d; ++i)
       if (!std::isfinite(centres[i])) throw Status(IBR_EINVAL, "centres must be finite");
+    if (c->walls)
+      for (int64_t m = 0; m < N; ++m) {
+        const double z = R[m * d + d - 1];
+        if (!(z > 0.0 && z < c->L)) throw Status(IBR_EINVAL, "markers must lie strictly between the walls");
+      }
     IBR_HIP(hipSetDevice(c->p.device));
     sync(c);
     // body-sized buffers are rebuilt every call (set-up, not the solve path)
@@ -1040,7 +1056,9 @@ void set_rhs_impl(ibr_ctx* c, const double* gh, const double* hp, hipMemcpyKind 
   // consistency: <h> = 0 always, <g> = 0 for periodic steady Stokes (Sec. 3.4)
   launch_field_means<double>(c->Bs + (int64_t)d * c->C, 1, c->C, c->mpart, 256, c->vmean, s);
   launch_sub_field_mean<double>(c->Bs + (int64_t)d * c->C, 1, c->C, c->vmean, s);
-  if (c->steady) {
+  // with walls the normal component's wall faces are not unknowns: no momentum there
+  if (c->walls) launch_fill<double>(c->Bs + (int64_t)(d - 1) * c->C, c->C >> c->logn, 0.0, s);
+  if (c->vnull) {
     launch_field_means<double>(c->Bs, d, c->C, c->mpart, 256, c->vmean, s);
     launch_sub_field_mean<double>(c->Bs, d, c->C, c->vmean, s);
   }
@@ -1106,6 +1124,7 @@ ibr_status ibr_step(ibr_ctx* c, ibr_info* info) {
   ibr_status g = guard(c, [&] {
     require_bodies(c);
     if (c->steady) throw Status(IBR_ESTATE, "ibr_step needs rho > 0 (unsteady)");
+    if (c->walls) throw Status(IBR_EINVAL, "ibr_step: the advection term is periodic only (no walls)");
     if (c->rotating) throw Status(IBR_EINVAL, "ibr_step translates the bodies: Omega must be zero");
     if (c->nfree) throw Status(IBR_EINVAL, "ibr_step moves bodies with prescribed velocities only: no free bodies");
     IBR_HIP(hipSetDevice(c->p.device));
@@ -1320,6 +1339,11 @@ ibr_status ibr_vcycle(ibr_ctx* c, double c0, double c1, int nf, const double* b,
   return guard(c, [&] {
     if (!b || !x) throw Status(IBR_EINVAL, "b and x are required");
     if (nf < 1 || nf > c->dim) throw Status(IBR_EINVAL, "nfields must be in [1, dim]");
+    if (c->walls && nf != 1 && nf != c->dim)
+      throw Status(IBR_EINVAL, "with walls nfields is dim (velocity) or 1 (pressure)");
+    // with walls: the velocity cycle (tangential components, then the normal one) or the Neumann pressure cycle
+    const int wm = c->walls ? (nf == 1 ? 2 : 1) : 0;
+    const bool singular = c0 == 0.0 && wm != 1;
     if (!(c0 >= 0) || !std::isfinite(c1) || c1 == 0.0) throw Status(IBR_EINVAL, "need c0 >= 0 and c1 != 0");
     IBR_HIP(hipSetDevice(c->p.device));
     hipStream_t s = c->stream;
@@ -1333,8 +1357,8 @@ ibr_status ibr_vcycle(ibr_ctx* c, double c0, double c1, int nf, const double* b,
       float* bf = (float*)c->Qi;
       float* xf = (float*)c->Zi;
       launch_to_split<double, float>(c->dim, c->logn, bd, bf, nf, s);
-      c->mg32.vcycle(nf, bf, xf, c0, c1, c->p.mg_pre, c->p.mg_post, c->p.mg_coarse, s);
-      if (c0 == 0.0) {
+      c->mg32.vcycle(nf, bf, xf, c0, c1, c->p.mg_pre, c->p.mg_post, c->p.mg_coarse, s, wm);
+      if (singular) {
         launch_field_means<float>(xf, nf, c->C, c->mpart, 256, c->vmean, s);
         launch_sub_field_mean<float>(xf, nf, c->C, c->vmean, s);
       }
@@ -1343,8 +1367,8 @@ ibr_status ibr_vcycle(ibr_ctx* c, double c0, double c1, int nf, const double* b,
       double* bs = (double*)c->Qi;
       double* xs = (double*)c->Zi;
       launch_to_split<double, double>(c->dim, c->logn, bd, bs, nf, s);
-      c->mg64.vcycle(nf, bs, xs, c0, c1, c->p.mg_pre, c->p.mg_post, c->p.mg_coarse, s);
-      if (c0 == 0.0) {
+      c->mg64.vcycle(nf, bs, xs, c0, c1, c->p.mg_pre, c->p.mg_post, c->p.mg_coarse, s, wm);
+      if (singular) {
         launch_field_means<double>(xs, nf, c->C, c->mpart, 256, c->vmean, s);
         launch_sub_field_mean<double>(xs, nf, c->C, c->vmean, s);
       }

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libibr.so")
 
 FP64, MIXED = 0, 1
 PC_LOWER, PC_FULL = 0, 1
+WALLS_NONE, WALLS_NOSLIP = 0, 1
 
 STATUS = {0: "IBR_OK", 1: "IBR_EINVAL", 2: "IBR_ENOMEM", 3: "IBR_ENOCONV", 4: "IBR_EBREAKDOWN",
           5: "IBR_EFACTOR", 6: "IBR_ENUMERIC", 7: "IBR_EDEVICE", 8: "IBR_ESTATE"}
@@ -35,7 +36,8 @@ class Params(ctypes.Structure):
                 ("precision", ctypes.c_int), ("pc", ctypes.c_int), ("n_s", ctypes.c_int),
                 ("restart", ctypes.c_int), ("max_iters", ctypes.c_int), ("rtol", ctypes.c_double),
                 ("mg_pre", ctypes.c_int), ("mg_post", ctypes.c_int), ("mg_coarse", ctypes.c_int),
-                ("device", ctypes.c_int), ("stream", ctypes.c_void_p), ("graphs", ctypes.c_int)]
+                ("device", ctypes.c_int), ("stream", ctypes.c_void_p), ("graphs", ctypes.c_int),
+                ("walls", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):
@@ -391,7 +393,8 @@ def footprint_bytes(nbodies, nmarkers, **params):
 
 def from_problem(prob, **kw):
     """Solver for a synthetic Problem (grid parameters taken from it)."""
-    params = dict(dim=prob.dim, n=prob.n, h=prob.h, rho=prob.rho, eta=prob.eta, dt=prob.dt)
+    params = dict(dim=prob.dim, n=prob.n, h=prob.h, rho=prob.rho, eta=prob.eta, dt=prob.dt,
+                  walls=getattr(prob, "walls", 0))
     params.update(kw)
     s = Solver(**params)
     s.set_bodies(prob.R, prob.offsets, prob.centres)

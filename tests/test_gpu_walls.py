@@ -1,0 +1,191 @@
+"""GPU parity of the slit channel (no-slip walls at both ends of the last
+axis, periodic along the others) against ``oracle.walls``, through the C ABI.
+
+* operator: K x of the wall-bounded constrained system on random vectors
+  (wall faces of the normal component zero) equals the oracle's stencils,
+  spreading and interpolation with the folded taps, to rounding (1e-12);
+* spread / interp alone (1e-13), markers within a kernel width of both walls;
+* V-cycles: the velocity cycle (tangential components and the normal one,
+  vertex-centred along the walls' axis) and the Neumann pressure cycle equal
+  the oracle's cycle (fp64 1e-11, mixed 1e-5);
+* solves: fp64 at rtol 1e-10 equals the oracle's exact solution (v, pi,
+  Lambda, F, T within 1e-8 relative L2), mixed precision at rtol 1e-8 within
+  1e-6, lower and full preconditioner;
+* free bodies between the walls solve to the oracle's free-kinematics answer;
+* set-up checks: markers outside the channel and ibr_step with walls are
+  refused.
+"""
+import numpy as np
+import pytest
+
+from oracle import free, walls
+from synthetic import slit_problem, slit_shell
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    "3d16_two": dict(dim=3, n=16, nbodies=2, radius_h=2.5, wall_gap_h=0.3, gap_h=2.0),
+    "3d32_three": dict(dim=3, n=32, nbodies=3, radius_h=3.0, wall_gap_h=0.5),
+    "2d32_two": dict(dim=2, n=32, nbodies=2, radius_h=4.0, wall_gap_h=0.3),
+    "2d64_three": dict(dim=2, n=64, nbodies=3, radius_h=5.0, wall_gap_h=1.0),
+}
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+@pytest.fixture(params=sorted(CASES))
+def case(request):
+    return slit_problem(7, **CASES[request.param]), request.param
+
+
+def _sysm(prob):
+    return walls.System(prob.dim, prob.n, prob.h, 0.0, prob.eta, prob.R)
+
+
+def test_walls_operator_matches_oracle(case):
+    from paper_1505_07865_amd import ibr
+    prob, name = case
+    print("case", name, flush=True)
+    s = ibr.from_problem(prob)
+    d, n, N = prob.dim, prob.n, prob.nmarkers
+    C = n ** d
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal(s.NV)
+    x[(d - 1) * C:(d - 1) * C + C // n] = 0.0          # the normal component's wall faces
+    y = s.apply_operator(x)
+    sysm = _sysm(prob)
+    v = x[:d * C].reshape((d,) + (n,) * d)
+    p = x[d * C:(d + 1) * C].reshape((n,) * d)
+    lam = x[(d + 1) * C:].reshape(N, d)
+    rm, rc = walls.stokes_apply(v, p, 0.0, prob.eta, prob.h)
+    rm = rm - sysm.spread(lam)
+    rm[d - 1][0] = 0.0
+    ye = np.concatenate([rm.reshape(-1), rc.reshape(-1), -sysm.interp(v).reshape(-1)])
+    assert _rel(y, ye) < 1e-12, _rel(y, ye)
+    s.close()
+
+
+def test_walls_spread_interp_match_oracle(case):
+    from paper_1505_07865_amd import ibr
+    prob, name = case
+    print("case", name, flush=True)
+    s = ibr.from_problem(prob)
+    d, n, N = prob.dim, prob.n, prob.nmarkers
+    rng = np.random.default_rng(2)
+    lam = rng.standard_normal((N, d))
+    u = rng.standard_normal((d,) + (n,) * d)
+    u[d - 1][0] = 0.0
+    sysm = _sysm(prob)
+    f = s.spread(lam)
+    assert _rel(f, sysm.spread(lam)) < 1e-13
+    assert np.abs(f[d - 1][0]).max() == 0.0
+    assert _rel(s.interp(u), sysm.interp(u)) < 1e-13
+    s.close()
+
+
+@pytest.mark.parametrize("dim,n", [(3, 16), (3, 32), (3, 64), (2, 32), (2, 128)])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_walls_vcycle_matches_oracle(dim, n, precision):
+    from paper_1505_07865_amd import ibr
+    print("vcycle", dim, n, precision, flush=True)
+    s = ibr.Solver(dim=dim, n=n, h=1.0 / n, walls=ibr.WALLS_NOSLIP,
+                   precision=ibr.MIXED if precision == "mixed" else ibr.FP64)
+    tol = 1e-11 if precision == "fp64" else 1e-5
+    rng = np.random.default_rng(n + dim)
+    ks = walls.kinds(dim)
+    for c0, c1 in ((0.0, 3.0), (40.0, 0.7)):
+        b = rng.standard_normal((dim,) + (n,) * dim)
+        b[dim - 1][0] = 0.0
+        x = s.vcycle(c0, c1, b)
+        for f in range(dim):
+            xe = walls.vcycle(b[f], c0, c1, ks[f])
+            assert _rel(x[f], xe) < tol, (c0, f, _rel(x[f], xe))
+        assert np.abs(x[dim - 1][0]).max() == 0.0
+    # the pressure cycle: Neumann, singular at c0 = 0 (zero-mean right-hand side)
+    for c0, c1 in ((0.0, -1.0), (2.0, 0.5)):
+        b = rng.standard_normal((n,) * dim)
+        b -= b.mean()
+        x = s.vcycle(c0, c1, b)
+        xe = walls.vcycle(b, c0, c1, walls.CELL_NEU)
+        assert _rel(x, xe) < tol, (c0, _rel(x, xe))
+    s.close()
+
+
+@pytest.mark.parametrize("precision,pc", [("fp64", "lower"), ("mixed", "lower"), ("fp64", "full")])
+def test_walls_solve_matches_oracle(case, precision, pc):
+    from paper_1505_07865_amd import ibr
+    prob, name = case
+    print("case", name, precision, pc, flush=True)
+    fp64 = precision == "fp64"
+    s = ibr.from_problem(prob, precision=ibr.FP64 if fp64 else ibr.MIXED, rtol=1e-10 if fp64 else 1e-8,
+                         pc=ibr.PC_FULL if pc == "full" else ibr.PC_LOWER)
+    info = s.solve()
+    sol = s.solution()
+    s.close()
+    ex = walls.solve_problem(prob)
+    tol = 1e-8 if fp64 else 1e-6
+    print(name, info["iters"], info["rel_residual"], flush=True)
+    assert info["rel_residual"] <= (1e-10 if fp64 else 1e-8)
+    assert _rel(sol.u, ex.v) < tol, _rel(sol.u, ex.v)
+    assert _rel(sol.p, ex.p) < tol * 10, _rel(sol.p, ex.p)
+    assert _rel(sol.F, ex.F) < tol, _rel(sol.F, ex.F)
+    assert _rel(sol.T, ex.T) < tol * 10, _rel(sol.T, ex.T)
+    assert np.abs(sol.u[prob.dim - 1][0]).max() == 0.0
+
+
+def test_walls_free_bodies_match_oracle():
+    from paper_1505_07865_amd import ibr
+    prob = slit_problem(11, dim=3, n=32, nbodies=2, radius_h=3.0, wall_gap_h=1.0)
+    rng = np.random.default_rng(4)
+    F = rng.uniform(-1, 1, (2, 3))
+    T = rng.uniform(-1, 1, (2, 3))
+    s = ibr.from_problem(prob, rtol=1e-10)
+    s.set_free_bodies([1, 1], F, T)
+    s.solve()
+    U, Om = s.velocities()
+    sol = s.solution()
+    s.close()
+    sysm = _sysm(prob)
+    W = free.constraint_rhs(prob.R, prob.offsets, prob.centres, prob.U, prob.Omega, prob.L, [1, 1])
+    ex, Ue, Oe = free.solve(sysm, None, None, W, prob.offsets, prob.centres, [1, 1], F, T)
+    assert _rel(U, Ue) < 1e-8, _rel(U, Ue)
+    assert _rel(Om, Oe) < 1e-8, _rel(Om, Oe)
+    assert _rel(sol.u, ex.v) < 1e-8
+
+
+def test_walls_refusals():
+    from paper_1505_07865_amd import ibr
+    prob = slit_problem(1, dim=3, n=16, nbodies=1, radius_h=2.5)
+    bad = prob.R.copy()
+    bad[0, 2] = 0.0
+    s = ibr.Solver(dim=3, n=16, h=1.0 / 16, walls=ibr.WALLS_NOSLIP)
+    with pytest.raises(ibr.IbrError):
+        s.set_bodies(bad, prob.offsets, prob.centres)
+    s.close()
+    s = ibr.Solver(dim=3, n=16, h=1.0 / 16, rho=1.0, dt=0.01, walls=ibr.WALLS_NOSLIP)
+    s.set_bodies(prob.R, prob.offsets, prob.centres)
+    s.set_velocities(prob.U, prob.Omega)
+    with pytest.raises(ibr.IbrError):
+        s.step()
+    s.close()
+
+
+def test_slit_shell_drag_symmetry_and_wall_effect():
+    """A shell at height 0.25 and one at 0.75 feel the same drag along the
+    walls (mirror symmetry, to the solve's tolerance); at the quarter height
+    the drag exceeds the midplane's (the nearer wall), as Faxen's series for
+    the slit says (mobility 1 - 0.6526 R/H ... at H = d/4 against
+    1 - 1.004 R/H ... at H = d/2 with H the distance to the nearer wall)."""
+    from paper_1505_07865_amd import ibr
+    drag = {}
+    for hgt in (0.25, 0.5, 0.75):
+        s = ibr.from_problem(slit_shell(32, 1, height=hgt), rtol=1e-10)
+        s.solve()
+        F, _ = s.forces()
+        s.close()
+        drag[hgt] = F[0, 0]       # force the shell applies to the fluid along its motion: the drag
+    print("slit drag", drag, flush=True)
+    assert abs(drag[0.25] - drag[0.75]) < 1e-7 * drag[0.5]
+    assert drag[0.25] > drag[0.5] > 0
