@@ -45,7 +45,7 @@ MEASURED_TRAFFIC = {
 # strides coprime with the launch pattern (12 finest-level sweeps per P_S^-1, 2 V-cycle calls
 # per P_S^-1) so the samples cycle through it; sparse enough that the sampled launches' events
 # cost about 1% of the step
-TIMER_STRIDE = {"rb_fine": 29, "ortho_dot": 7, "ortho_axpy": 7, "stokes_apply": 7, "vcycle": 9}
+TIMER_STRIDE = {"rb_fine": 29, "ortho_dot": 7, "ortho_axpy": 7, "stokes_apply": 7, "vcycle": 9, "wall_rb_fine": 29}
 # composite classes (several kernels per sample): reported, never the roofline kernel
 COMPOSITE_TIMERS = ("vcycle",)
 
@@ -71,6 +71,9 @@ def parse():
     ap.add_argument("--free", action="store_true",
                     help="free-kinematics workload instead: a sedimenting suspension of 16 free spheres at 128^3")
     ap.add_argument("--free-solves", type=int, default=5, help="free kinematics: timed solves per precision")
+    ap.add_argument("--walls", action="store_true",
+                    help="slit channel (no-slip walls along z) at 128^3 against the same bodies in the periodic box")
+    ap.add_argument("--slit-solves", type=int, default=5, help="slit channel: timed solves per precision and box")
     ap.add_argument("--blocks", action="store_true",
                     help="per-body mobility set-up of the 256^3 configuration (100 blocks of 600 x 600, fp64 MFMA)")
     ap.add_argument("--block-reps", type=int, default=5, help="blocks: timed set-ups")
@@ -358,6 +361,78 @@ def free_kinematics(args, torch):
     print(json.dumps(line), flush=True)
 
 
+def slit_channel(args, torch):
+    """Slit channel: steady Stokes between no-slip walls at z = 0 and z = L
+    (periodic along x and y), 3D 128^3, 16 spheres of radius 6h (113 markers
+    each) with prescribed velocities U ~ U[-1, 1]^3, every surface at least 2h
+    from the walls.  Per precision: repeated solves from a zero initial guess
+    to relative residual 1e-8 (host clock around each synchronous solve) with
+    N_s = 4 and N_s = 2 inner iterations, and beside them the same bodies in
+    the periodic box (N_s = 2), so the difference is the cost of the walls:
+    their multigrid is the plain one-cell-per-thread cycle, not the
+    bandwidth-tuned periodic one, and P_S^-1 approximates the wall-bounded
+    Stokes operator less well than the periodic one, as Sec. 7.1 notes (which
+    also finds N_s = 4 the robust choice there).  The headline value is the
+    mixed-precision N_s = 4 rate; its roofline is the finest-level wall half
+    sweep (timed live with HIP events, every 29th launch)."""
+    from paper_1505_07865_amd import ibr
+    from synthetic import slit_problem
+    prob = slit_problem(args.seed, dim=3, n=128, nbodies=16, radius_h=6.0, wall_gap_h=2.0, rotate=False)
+    out = {}
+    roof = None
+    for prec in ("fp64", "mixed"):
+        res = {}
+        for walls, ns in ((1, 4), (1, 2), (0, 2)):
+            s = ibr.from_problem(prob, rtol=1e-8, precision=ibr.MIXED if prec == "mixed" else ibr.FP64,
+                                 walls=walls, n_s=ns)
+            s.solve()
+            timed = prec == "mixed" and walls and ns == 4
+            if timed:
+                ibr.timer_enable("wall_rb_fine", TIMER_STRIDE["wall_rb_fine"])
+            infos, wall = [], []
+            for _ in range(args.slit_solves):
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                infos.append(s.solve())
+                wall.append((time.perf_counter() - t1) * 1e3)
+            if timed:
+                t = ibr.timer_read("wall_rb_fine")
+                ibr.timer_enable("wall_rb_fine", 0)
+                if t["launches"] and t["ms"] > 0:
+                    per_s = t["ms"] / 1e3 / t["launches"]
+                    gbs = t["bytes"] / t["launches"] / per_s / 1e9
+                    roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "wall_rb_fine",
+                            "us_per_launch": round(per_s * 1e6, 3), "bytes_per_launch": t["bytes"] / t["launches"]}
+            F, _ = s.forces()
+            s.close()
+            key = ("walls_ns%d" % ns) if walls else "periodic_same_bodies"
+            res[key] = {
+                "solves_per_s": round(len(wall) / (sum(wall) / 1e3), 3), "p50_ms": round(percentile(wall, 50), 3),
+                "p99_ms": round(percentile(wall, 99), 3), "iters": infos[-1]["iters"],
+                "ps_applications": infos[-1]["ps_applications"],
+                "max_rel_residual": float("%.4g" % max(i["rel_residual"] for i in infos)),
+                "mean_abs_force": float("%.6g" % np.abs(F).mean())}
+        out[prec] = res
+        print("bench: slit channel %s: N_s = 4 %.2f solves/s, %d iterations; N_s = 2 %.2f, %d; periodic box %.2f "
+              "solves/s, %d iterations"
+              % (prec, res["walls_ns4"]["solves_per_s"], res["walls_ns4"]["iters"], res["walls_ns2"]["solves_per_s"],
+                 res["walls_ns2"]["iters"], res["periodic_same_bodies"]["solves_per_s"],
+                 res["periodic_same_bodies"]["iters"]),
+              file=sys.stderr, flush=True)
+    line = {"metric": "slit-channel solves/s at 1e-8 residual, mixed vs FP64, 3D 128^3",
+            "value": out["mixed"]["walls_ns4"]["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
+            "higher_is_better": True, "vs_baseline": None, "dtype": "f32 preconditioner + f64 outer",
+            "data": "synthetic",
+            "config": {"workload": "3D steady Stokes, 128^3, no-slip walls at z = 0 and z = L, periodic x and y, "
+                                   "16 spheres R=6h x 113 markers, U ~ U[-1,1]^3, N_s = 4, rtol 1e-8, solves "
+                                   "from rest", "seed": args.seed, "solves": args.slit_solves},
+            "roofline": roof, "mixed": out["mixed"], "fp64": out["fp64"],
+            "mixed_over_fp64": round(out["mixed"]["walls_ns4"]["solves_per_s"] /
+                                     out["fp64"]["walls_ns4"]["solves_per_s"], 3)}
+    print(json.dumps(line), flush=True)
+
+
 def blocks(args, torch):
     """Per-body mobility set-up (assembly, shifted Cholesky on fp64 MFMA
     tiles, triangular inverse, M~^-1 = X^T X) for the 256^3 configuration's
@@ -471,6 +546,9 @@ def main():
         return
     if args.blocks:
         blocks(args, torch)
+        return
+    if args.walls:
+        slit_channel(args, torch)
         return
     prob = config2_spheres_ns(args.seed, re=args.re)
     precs = ["fp64", "mixed"] if args.precision == "both" else [args.precision]

@@ -47,6 +47,7 @@ vertex-centred along z for the normal component (whose values sit on the
 walls' lattice planes).
 """
 import itertools
+import math
 from dataclasses import dataclass
 
 import numpy as np
@@ -514,3 +515,31 @@ def ps_inv(g, hp, c0, eta, h, mg=None):
     v = v + h * gp
     pi = -c0 * h * h * phi + eta * q
     return v, pi
+
+
+# ---------------------------------------------------------------- Faxen's slit mobility
+# Series of Sec. 7 (eq. Faxen_slit) for a sphere of hydrodynamic radius R
+# translating parallel to the walls of an infinite slit of width d, at the
+# midplane (H = d/2) and at the quarter plane (H = d/4), H the distance to the
+# nearer wall: mobility = (6 pi eta R)^-1 (1 + c1 x + c3 x^3 + c4 x^4 + c5 x^5),
+# x = R / H.
+FAXEN = {"half": (-1.004, 0.418, 0.21, -0.169), "quarter": (-0.6526, 0.1475, -0.131, -0.0644)}
+
+
+def faxen_mobility(R, H, where, eta=1.0):
+    c1, c3, c4, c5 = FAXEN[where]
+    x = R / H
+    return (1.0 + c1 * x + c3 * x ** 3 + c4 * x ** 4 + c5 * x ** 5) / (6.0 * math.pi * eta * R)
+
+
+def radius_from_slit_drag(F, V, H, where, eta=1.0):
+    """Effective radius R_L for which Faxen's series gives drag F at speed V
+    (the drag F / V = 1 / mobility grows with R; bisection)."""
+    lo, hi = 1e-9 * H, 0.6 * H
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if 1.0 / faxen_mobility(mid, H, where, eta) < F / V:
+            lo = mid
+        else:
+            hi = mid
+    return 0.5 * (lo + hi)

@@ -42,7 +42,8 @@ enum TimerId {
   kTimerOrthoAxpy = 2,
   kTimerStokes = 3,
   kTimerVcycle = 4,  // whole V-cycles (events recorded around all of their kernels)
-  kTimerCount = 5
+  kTimerWallRbFine = 5,  // finest-level half sweeps of the slit channel's V-cycle
+  kTimerCount = 6
 };
 // A launch of a timed class is sampled (every stride-th one): the sampled launch
 // gets a start and a stop event to pass to hipExtLaunchKernelGGL, which stamps

@@ -271,10 +271,14 @@ void launch_wall_vcycle(int dim, int logn, int nf, const T* b, T* x, const std::
     const int lg = logn - l;
     const int64_t Cl = (int64_t)1 << (dim * lg);
     const dim3 g(nblk(Cl / 2), nf);
+    // finest level: a live-timed class (algorithmic traffic as the periodic half sweep's)
+    const TimerEvents ev = l == 0 ? timer_sample(kTimerWallRbFine, 1.5 * (double)Cl * nf * sizeof(T)) : TimerEvents();
     if (three)
-      hipLaunchKernelGGL((k_wrb<T, 3>), g, dim3(256), 0, s, xl(l), bl(l), lg, tc0, cl, color, mode);
+      hipExtLaunchKernelGGL(k_wrb<T, 3>, g, dim3(256), 0, s, ev.start, ev.stop, 0, xl(l), bl(l), lg, tc0, cl, color,
+                            mode);
     else
-      hipLaunchKernelGGL((k_wrb<T, 2>), g, dim3(256), 0, s, xl(l), bl(l), lg, tc0, cl, color, mode);
+      hipExtLaunchKernelGGL(k_wrb<T, 2>, g, dim3(256), 0, s, ev.start, ev.stop, 0, xl(l), bl(l), lg, tc0, cl, color,
+                            mode);
   };
   for (int l = 0; l < L; ++l) {
     const int lg = logn - l;

@@ -29,7 +29,8 @@ struct TimerState {
 
 TimerState g_timers[kTimerCount];
 
-const char* const kTimerNames[kTimerCount] = {"rb_fine", "ortho_dot", "ortho_axpy", "stokes_apply", "vcycle"};
+const char* const kTimerNames[kTimerCount] = {"rb_fine", "ortho_dot", "ortho_axpy", "stokes_apply", "vcycle",
+                                              "wall_rb_fine"};
 
 int timer_index(const char* name) {
   if (!name) return -1;

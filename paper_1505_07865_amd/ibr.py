@@ -365,7 +365,7 @@ class Solver:
         return N
 
 
-TIMERS = ("rb_fine", "ortho_dot", "ortho_axpy", "stokes_apply", "vcycle")
+TIMERS = ("rb_fine", "ortho_dot", "ortho_axpy", "stokes_apply", "vcycle", "wall_rb_fine")
 
 
 def timer_enable(kernel, stride=1):

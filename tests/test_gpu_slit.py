@@ -1,0 +1,85 @@
+"""Sphere in a slit channel on the GPU (the slit study of Sec. 7): an
+icosahedral shell translating parallel to no-slip walls at z = 0 and z = d,
+periodic along x and y with period L = d.
+
+Per resolution (32^3, 64^3, 128^3 with 12, 42, 162 markers, spacing about
+2h): the shell alone in the periodic box gives its hydrodynamic radius R_h
+(periodic drag law, ``oracle.hasimoto``); in the channel, at the midplane
+(H = d/2) and at the quarter plane (H = d/4), its drag gives the effective
+radius R_L for which Faxen's series for the infinite slit (eq. Faxen_slit)
+reproduces it.  R_L / R_h - 1 measures what the finite period L adds to the
+infinite slit: the images' net force drives a mean channel flow along the
+motion, so the drag is lower than the infinite slit's and R_L < R_h, by an
+amount that vanishes as R_h / L -> 0.  The paper plots R_L / R_h - 1 against
+R_h / L and finds the resolutions consistent with one curve per height, the
+two heights different.  R_h / R_g changes with resolution, so the three
+resolutions sample the curve at different R_h / L; near R_h / L ~ 0.07-0.09
+the curve is close to a line through the origin, so the check is on the
+slope (R_L / R_h - 1) / (R_h / L): negative, equal across the three
+resolutions to within 5% at each height, and different between the heights.
+At 32^3 the drags also equal the oracle's exact solve.  The table is printed
+and written to gpurun_out/slit_table.json.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import hasimoto, walls
+from synthetic import slit_shell
+
+pytestmark = pytest.mark.gpu
+
+LEVELS = ((32, 0), (64, 1), (128, 2))
+HEIGHTS = (("half", 0.5), ("quarter", 0.25))
+
+
+def _drag(prob, solver):
+    s = solver(prob)
+    info = s.solve()
+    F, _ = s.forces()
+    s.close()
+    return F[0, 0], info
+
+
+def _row(n, level, solver):
+    p = slit_shell(n, level, height=0.5)
+    p.walls = 0
+    Fp, _ = _drag(p, solver)
+    Rh = hasimoto.radius3d(abs(Fp), 1.0)
+    row = {"n": n, "markers": int(p.nmarkers), "Rh_over_Rg": Rh / p.radius[0], "Rh_over_L": Rh}
+    for where, hgt in HEIGHTS:
+        F, info = _drag(slit_shell(n, level, height=hgt), solver)
+        RL = walls.radius_from_slit_drag(F, 1.0, min(hgt, 1 - hgt), where)
+        row[where] = {"drag": F, "RL_over_Rh_minus_1": RL / Rh - 1, "iters": info["iters"]}
+    return row
+
+
+def test_slit_sphere_table():
+    from paper_1505_07865_amd import ibr
+
+    def solver(prob):
+        return ibr.from_problem(prob, rtol=1e-9, restart=100, max_iters=3000, graphs=0)
+
+    rows = []
+    for n, level in LEVELS:
+        print("slit sphere", n, level, flush=True)
+        rows.append(_row(n, level, solver))
+        print(json.dumps(rows[-1]), flush=True)
+    # 32^3 against the oracle's exact solve in the channel
+    for where, hgt in HEIGHTS:
+        ex = walls.solve_problem(slit_shell(32, 0, height=hgt))
+        assert abs(rows[0][where]["drag"] - ex.F[0, 0]) < 1e-7 * abs(ex.F[0, 0])
+    out = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
+    os.makedirs(out, exist_ok=True)
+    with open(os.path.join(out, "slit_table.json"), "w") as f:
+        json.dump(rows, f, indent=1)
+    slope = {}
+    for where, _ in HEIGHTS:
+        sl = [r[where]["RL_over_Rh_minus_1"] / r["Rh_over_L"] for r in rows]
+        print(where, "slope", sl, flush=True)
+        assert max(sl) < 0, (where, sl)
+        assert (max(sl) - min(sl)) < 0.05 * abs(np.mean(sl)), (where, sl)
+        slope[where] = np.mean(sl)
+    assert abs(slope["half"] - slope["quarter"]) > 0.2 * abs(slope["quarter"]), slope

@@ -278,3 +278,22 @@ def test_ps_inv_projects():
         after = np.abs(-walls.div(v, h) - hp).max()
         assert after < 0.5 * before
         assert np.abs(v[d - 1][0]).max() == 0.0
+
+
+def test_faxen_series_limits_and_inverse():
+    """Faxen's slit series: Stokes' law far from the walls, the drag grows
+    with R at fixed H, a sphere at the quarter plane (nearer wall) is less
+    mobile than one of the same size at the midplane of the same slit, and
+    radius_from_slit_drag inverts the drag."""
+    d = 1.0
+    for where, H in (("half", d / 2), ("quarter", d / 4)):
+        R = 1e-7
+        assert abs(walls.faxen_mobility(R, H, where) * 6 * math.pi * R - 1) < 1e-5
+        Rs = np.linspace(0.01, 0.3, 30) * H
+        drag = [1 / walls.faxen_mobility(r, H, where) for r in Rs]
+        assert np.all(np.diff(drag) > 0)
+        for r in (0.05 * H, 0.2 * H, 0.4 * H):
+            F = 1 / walls.faxen_mobility(r, H, where)
+            assert abs(walls.radius_from_slit_drag(F, 1.0, H, where) - r) < 1e-12
+    for R in (0.02, 0.06, 0.1):
+        assert walls.faxen_mobility(R, d / 4, "quarter") < walls.faxen_mobility(R, d / 2, "half")
