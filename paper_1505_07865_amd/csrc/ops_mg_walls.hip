@@ -23,7 +23,9 @@
 // Fields are in split (red half, black half) storage like the periodic
 // hierarchy; these kernels take one cell per thread and address neighbours
 // through split_index: the walls change the stencil only in the two boundary
-// layers, and the slit path is not the bandwidth-tuned periodic one.
+// layers, and the slit path is not the bandwidth-tuned periodic one.  From
+// 4096 cells (16^3, 64^2) down, the cycle runs in one workgroup per field
+// with the levels in LDS (k_wvcycle_lds), on the same per-cell steps.
 #include "kernels.h"
 
 namespace ibr {
@@ -99,45 +101,33 @@ __device__ inline T resid_at(const T* x, const T* b, int i, int j, int k, int lo
   return at<T, DIM>(b, i, j, k, logn) - (diag * at<T, DIM>(x, i, j, k, logn) - c1 * sum);
 }
 
-// Half sweep of colour `color`: one cell per thread, fields in blockIdx.y.
+// ---- per-cell steps (global kernels: one cell per thread; the tail: loops)
+// Half sweep at cell t of colour `color`.
 template <typename T, int DIM>
-__global__ void __launch_bounds__(256) k_wrb(T* __restrict__ x, const T* __restrict__ b, int logn, T c0, T c1,
-                                             int color, int mode) {
+__device__ inline void wrb_cell(T* x, const T* b, int logn, T c0, T c1, int color, int t, int kind) {
   const int C = 1 << (DIM * logn);
-  const int t = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-  if (t >= (C >> 1)) return;
-  const int f = blockIdx.y;
-  const int kind = wall_kind<DIM>(mode, f);
-  T* xf = x + (int64_t)f * C;
-  const T* bf = b + (int64_t)f * C;
   int i, j, k;
   colour_cell<DIM>(t, color, logn, i, j, k);
   const int own = color * (C >> 1) + t;
   const int w = DIM == 3 ? k : j;
   if (kind == kFaceDir && w == 0) {
-    xf[own] = T(0);
+    x[own] = T(0);
     return;
   }
   T diag;
-  const T sum = nbr_sum<T, DIM>(xf, i, j, k, logn, kind, c0, c1, diag);
-  xf[own] = (bf[own] + c1 * sum) / diag;
+  const T sum = nbr_sum<T, DIM>(x, i, j, k, logn, kind, c0, c1, diag);
+  x[own] = (b[own] + c1 * sum) / diag;
 }
 
-// Coarse right-hand side from the fine residual; one coarse cell per thread.
+// Coarse right-hand side of coarse cell t (natural index) from the fine
+// residual: its split index on the coarse level is returned in *at_c.
 template <typename T, int DIM>
-__global__ void __launch_bounds__(256) k_wresid_restrict(const T* __restrict__ x, const T* __restrict__ b,
-                                                         T* __restrict__ bc, int logn, T c0, T c1, int mode) {
+__device__ inline T wrestrict_cell(const T* x, const T* b, int logn, T c0, T c1, int t, int kind, int* at_c) {
   const int lognc = logn - 1;
-  const int C = 1 << (DIM * logn), Cc = 1 << (DIM * lognc);
-  const int t = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-  if (t >= Cc) return;
-  const int f = blockIdx.y;
-  const int kind = wall_kind<DIM>(mode, f);
-  const T* xf = x + (int64_t)f * C;
-  const T* bf = b + (int64_t)f * C;
   const int maskc = (1 << lognc) - 1;
   const int I = t & maskc, J = (t >> lognc) & maskc, K = DIM == 3 ? (t >> (2 * lognc)) : 0;
   const int W = DIM == 3 ? K : J;
+  *at_c = split_index<DIM>(I, J, K, lognc);
   T out = T(0);
   if (kind == kFaceDir) {
     if (W > 0) {
@@ -149,10 +139,10 @@ __global__ void __launch_bounds__(256) k_wresid_restrict(const T* __restrict__ x
         if (DIM == 3) {
           for (int dy = 0; dy < 2; ++dy)
             for (int dx = 0; dx < 2; ++dx)
-              acc += resid_at<T, DIM>(xf, bf, 2 * I + dx, 2 * J + dy, wf, logn, kind, c0, c1);
+              acc += resid_at<T, DIM>(x, b, 2 * I + dx, 2 * J + dy, wf, logn, kind, c0, c1);
           acc *= T(0.25);
         } else {
-          for (int dx = 0; dx < 2; ++dx) acc += resid_at<T, DIM>(xf, bf, 2 * I + dx, wf, 0, logn, kind, c0, c1);
+          for (int dx = 0; dx < 2; ++dx) acc += resid_at<T, DIM>(x, b, 2 * I + dx, wf, 0, logn, kind, c0, c1);
           acc *= T(0.5);
         }
         out += wz[q] * acc;
@@ -162,10 +152,10 @@ __global__ void __launch_bounds__(256) k_wresid_restrict(const T* __restrict__ x
     for (int dz = 0; dz < (DIM == 3 ? 2 : 1); ++dz)
       for (int dy = 0; dy < 2; ++dy)
         for (int dx = 0; dx < 2; ++dx)
-          out += resid_at<T, DIM>(xf, bf, 2 * I + dx, 2 * J + dy, 2 * K + dz, logn, kind, c0, c1);
+          out += resid_at<T, DIM>(x, b, 2 * I + dx, 2 * J + dy, 2 * K + dz, logn, kind, c0, c1);
     out *= DIM == 3 ? T(0.125) : T(0.25);
   }
-  bc[(int64_t)f * Cc + split_index<DIM>(I, J, K, lognc)] = out;
+  return out;
 }
 
 // Coarse value used by the prolongation at coarse wall-axis index Wn (may be
@@ -183,17 +173,10 @@ __device__ inline T coarse_at(const T* e, int I, int J, int Wn, int Wp, int logn
   return DIM == 3 ? s * at<T, DIM>(e, I, J, Wu, lognc) : s * at<T, DIM>(e, I, Wu, 0, lognc);
 }
 
-// x += P e, one fine cell per thread.
+// x += P e at fine cell t (natural index).
 template <typename T, int DIM>
-__global__ void __launch_bounds__(256) k_wprolong(T* __restrict__ x, const T* __restrict__ e, int logn, int mode) {
+__device__ inline void wprolong_cell(T* x, const T* e, int logn, int t, int kind) {
   const int lognc = logn - 1;
-  const int C = 1 << (DIM * logn), Cc = 1 << (DIM * lognc);
-  const int t = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-  if (t >= C) return;
-  const int f = blockIdx.y;
-  const int kind = wall_kind<DIM>(mode, f);
-  T* xf = x + (int64_t)f * C;
-  const T* ef = e + (int64_t)f * Cc;
   const int mask = (1 << logn) - 1;
   const int i = t & mask, j = (t >> logn) & mask, k = DIM == 3 ? (t >> (2 * logn)) : 0;
   const int w = DIM == 3 ? k : j;
@@ -227,30 +210,145 @@ __global__ void __launch_bounds__(256) k_wprolong(T* __restrict__ x, const T* __
     if (aq == T(0)) continue;
     T plane;
     if (DIM == 3) {
-      const T r0 = T(0.75) * coarse_at<T, DIM>(ef, I, J, Wq, Wp, lognc, kind) +
-                   T(0.25) * coarse_at<T, DIM>(ef, In, J, Wq, Wp, lognc, kind);
-      const T r1 = T(0.75) * coarse_at<T, DIM>(ef, I, Jn, Wq, Wp, lognc, kind) +
-                   T(0.25) * coarse_at<T, DIM>(ef, In, Jn, Wq, Wp, lognc, kind);
+      const T r0 = T(0.75) * coarse_at<T, DIM>(e, I, J, Wq, Wp, lognc, kind) +
+                   T(0.25) * coarse_at<T, DIM>(e, In, J, Wq, Wp, lognc, kind);
+      const T r1 = T(0.75) * coarse_at<T, DIM>(e, I, Jn, Wq, Wp, lognc, kind) +
+                   T(0.25) * coarse_at<T, DIM>(e, In, Jn, Wq, Wp, lognc, kind);
       plane = T(0.75) * r0 + T(0.25) * r1;
     } else {
-      plane = T(0.75) * coarse_at<T, DIM>(ef, I, 0, Wq, Wp, lognc, kind) +
-              T(0.25) * coarse_at<T, DIM>(ef, In, 0, Wq, Wp, lognc, kind);
+      plane = T(0.75) * coarse_at<T, DIM>(e, I, 0, Wq, Wp, lognc, kind) +
+              T(0.25) * coarse_at<T, DIM>(e, In, 0, Wq, Wp, lognc, kind);
     }
     val += aq * plane;
   }
-  xf[split_index<DIM>(i, j, k, logn)] += val;
+  x[split_index<DIM>(i, j, k, logn)] += val;
 }
 
-// b -= mean(b) per field (the coarsest grid of the singular Neumann cycle).
-template <typename T>
-__global__ void __launch_bounds__(256) k_wremove_mean(T* __restrict__ b, int C) {
-  __shared__ T red[256 / kWave];
-  T* bf = b + (int64_t)blockIdx.x * C;
-  T s = T(0);
-  for (int c = threadIdx.x; c < C; c += blockDim.x) s += bf[c];
-  s = block_sum(s, red);
-  const T m = s / T(C);
-  for (int c = threadIdx.x; c < C; c += blockDim.x) bf[c] -= m;
+// ---- global kernels: fields in blockIdx.y
+template <typename T, int DIM>
+__global__ void __launch_bounds__(256) k_wrb(T* __restrict__ x, const T* __restrict__ b, int logn, T c0, T c1,
+                                             int color, int mode) {
+  const int C = 1 << (DIM * logn);
+  const int t = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (t >= (C >> 1)) return;
+  const int f = blockIdx.y;
+  wrb_cell<T, DIM>(x + (int64_t)f * C, b + (int64_t)f * C, logn, c0, c1, color, t, wall_kind<DIM>(mode, f));
+}
+
+template <typename T, int DIM>
+__global__ void __launch_bounds__(256) k_wresid_restrict(const T* __restrict__ x, const T* __restrict__ b,
+                                                         T* __restrict__ bc, int logn, T c0, T c1, int mode) {
+  const int C = 1 << (DIM * logn), Cc = C >> DIM;
+  const int t = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (t >= Cc) return;
+  const int f = blockIdx.y;
+  int at_c;
+  const T r = wrestrict_cell<T, DIM>(x + (int64_t)f * C, b + (int64_t)f * C, logn, c0, c1, t,
+                                     wall_kind<DIM>(mode, f), &at_c);
+  bc[(int64_t)f * Cc + at_c] = r;
+}
+
+template <typename T, int DIM>
+__global__ void __launch_bounds__(256) k_wprolong(T* __restrict__ x, const T* __restrict__ e, int logn, int mode) {
+  const int C = 1 << (DIM * logn), Cc = C >> DIM;
+  const int t = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (t >= C) return;
+  const int f = blockIdx.y;
+  wprolong_cell<T, DIM>(x + (int64_t)f * C, e + (int64_t)f * Cc, logn, t, wall_kind<DIM>(mode, f));
+}
+
+// ---- the coarse tail in one workgroup per field
+// Levels from the tail's entry (at most kWallTailCells cells) down to 4^dim
+// run inside one workgroup with every level's x, and b below the entry, in
+// LDS: the same per-cell steps as the global kernels, one launch instead of
+// about eleven per level.
+constexpr int kWallTailThreads = 512;
+constexpr int kWallTailCells = 4096;
+template <int DIM>
+constexpr int wall_pyramid(int C) {
+  int t = 0;
+  for (int c = C; c >= (DIM == 3 ? 64 : 16); c >>= DIM) t += c;
+  return t;
+}
+
+template <typename T, int DIM>
+__global__ void __launch_bounds__(kWallTailThreads) k_wvcycle_lds(const T* __restrict__ bg, T* __restrict__ xg,
+                                                                  int logn, T c0, T c1, int nu_pre, int nu_post,
+                                                                  int nu_coarse, int mode) {
+  constexpr int kX = wall_pyramid<DIM>(kWallTailCells);
+  constexpr int kB = wall_pyramid<DIM>(kWallTailCells >> DIM) + 1;
+  __shared__ T xs[kX];
+  __shared__ T bs[kB];
+  __shared__ T red[kWallTailThreads / kWave];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int f = blockIdx.x;
+  const int kind = wall_kind<DIM>(mode, f);
+  const int C0 = 1 << (DIM * logn);
+  const T* b0 = bg + (int64_t)f * C0;
+  T* x0 = xg + (int64_t)f * C0;
+  const int nlev = logn - 1;  // entry level down to n = 4
+  int off[12], boff[12];
+  {
+    int xo = 0, bo = 0;
+    for (int l = 0; l < nlev; ++l) {
+      const int Cl = 1 << (DIM * (logn - l));
+      off[l] = xo;
+      xo += Cl;
+      boff[l] = bo;
+      if (l > 0) bo += Cl;
+    }
+  }
+  auto bl = [&](int l) -> const T* { return l == 0 ? b0 : bs + boff[l]; };
+  T cl = c1;
+  auto sweeps = [&](int l, T cc, int nsw) {
+    const int lg = logn - l;
+    const int H = 1 << (DIM * lg - 1);
+    for (int sw = 0; sw < nsw; ++sw)
+      for (int color = 0; color < 2; ++color) {
+        for (int t = tid; t < H; t += nt) wrb_cell<T, DIM>(xs + off[l], bl(l), lg, c0, cc, color, t, kind);
+        __syncthreads();
+      }
+  };
+  for (int l = 0; l < nlev - 1; ++l) {
+    const int lg = logn - l;
+    const int Cl = 1 << (DIM * lg);
+    for (int c = tid; c < Cl; c += nt) xs[off[l] + c] = T(0);
+    __syncthreads();
+    sweeps(l, cl, nu_pre);
+    for (int t = tid; t < (Cl >> DIM); t += nt) {
+      int at_c;
+      const T r = wrestrict_cell<T, DIM>(xs + off[l], bl(l), lg, c0, cl, t, kind, &at_c);
+      bs[boff[l + 1] + at_c] = r;
+    }
+    __syncthreads();
+    cl = cl * T(0.25);
+  }
+  {
+    const int l = nlev - 1;
+    const int Cl = 1 << (DIM * (logn - l));
+    if (mode == 2 && c0 == T(0)) {
+      // the singular Neumann problem: the coarsest right-hand side loses its mean
+      T* b = bs + boff[l];
+      T sm = T(0);
+      for (int c = tid; c < Cl; c += nt) sm += b[c];
+      sm = block_sum(sm, red);
+      const T mean = sm / T(Cl);
+      __syncthreads();
+      for (int c = tid; c < Cl; c += nt) b[c] -= mean;
+    }
+    for (int c = tid; c < Cl; c += nt) xs[off[l] + c] = T(0);
+    __syncthreads();
+    sweeps(l, cl, nu_coarse);
+  }
+  for (int l = nlev - 2; l >= 0; --l) {
+    cl = cl * T(4);
+    const int lg = logn - l;
+    const int Cl = 1 << (DIM * lg);
+    for (int t = tid; t < Cl; t += nt) wprolong_cell<T, DIM>(xs + off[l], xs + off[l + 1], lg, t, kind);
+    __syncthreads();
+    sweeps(l, cl, nu_post);
+  }
+  for (int c = tid; c < C0; c += nt) x0[c] = xs[c];
 }
 
 }  // namespace
@@ -259,9 +357,11 @@ template <typename T>
 void launch_wall_vcycle(int dim, int logn, int nf, const T* b, T* x, const std::vector<T*>& wx,
                         const std::vector<T*>& wb, double c0, double c1, int nu_pre, int nu_post, int nu_coarse,
                         int mode, hipStream_t s) {
-  if (logn < 2) throw DeviceError("walls: grids need n >= 4");
-  const int L = logn - 2;  // level of the 4^dim grid
-  if ((int)wx.size() <= L || (int)wb.size() <= L) throw DeviceError("walls: multigrid buffers missing");
+  if (logn < 3) throw DeviceError("walls: grids need n >= 8");
+  // levels above the tail run the global kernels; the tail starts at <= kWallTailCells cells
+  int lt = 0;
+  while (((int64_t)1 << (dim * (logn - lt))) > kWallTailCells) ++lt;
+  if ((int)wx.size() <= lt || (int)wb.size() <= lt) throw DeviceError("walls: multigrid buffers missing");
   const bool three = dim == 3;
   const T tc0 = (T)c0;
   T cl = (T)c1;
@@ -280,7 +380,7 @@ void launch_wall_vcycle(int dim, int logn, int nf, const T* b, T* x, const std::
       hipExtLaunchKernelGGL(k_wrb<T, 2>, g, dim3(256), 0, s, ev.start, ev.stop, 0, xl(l), bl(l), lg, tc0, cl, color,
                             mode);
   };
-  for (int l = 0; l < L; ++l) {
+  for (int l = 0; l < lt; ++l) {
     const int lg = logn - l;
     const int64_t Cl = (int64_t)1 << (dim * lg);
     launch_fill<T>(xl(l), Cl * nf, T(0), s);
@@ -293,17 +393,13 @@ void launch_wall_vcycle(int dim, int logn, int nf, const T* b, T* x, const std::
       hipLaunchKernelGGL((k_wresid_restrict<T, 2>), g, dim3(256), 0, s, xl(l), bl(l), wb[l + 1], lg, tc0, cl, mode);
     cl = cl * T(0.25);
   }
-  {
-    const int64_t Cl = (int64_t)1 << (dim * 2);
-    if (mode == 2 && c0 == 0.0) {
-      if (L == 0) throw DeviceError("walls: the singular cycle needs n >= 8");
-      hipLaunchKernelGGL(k_wremove_mean<T>, dim3(nf), dim3(256), 0, s, wb[L], (int)Cl);
-    }
-    launch_fill<T>(xl(L), Cl * nf, T(0), s);
-    for (int sw = 0; sw < nu_coarse; ++sw)
-      for (int color = 0; color < 2; ++color) half(L, color);
-  }
-  for (int l = L - 1; l >= 0; --l) {
+  if (three)
+    hipLaunchKernelGGL((k_wvcycle_lds<T, 3>), dim3(nf), dim3(kWallTailThreads), 0, s, bl(lt), xl(lt), logn - lt,
+                       tc0, cl, nu_pre, nu_post, nu_coarse, mode);
+  else
+    hipLaunchKernelGGL((k_wvcycle_lds<T, 2>), dim3(nf), dim3(kWallTailThreads), 0, s, bl(lt), xl(lt), logn - lt,
+                       tc0, cl, nu_pre, nu_post, nu_coarse, mode);
+  for (int l = lt - 1; l >= 0; --l) {
     cl = cl * T(4);
     const int lg = logn - l;
     const int64_t Cl = (int64_t)1 << (dim * lg);
