@@ -85,8 +85,9 @@ class _Worker(threading.Thread):
 
 
 def _context_key(prob):
-    # contexts are shared by requests with the same grid and fluid parameters
-    return (prob.dim, prob.n, prob.h, prob.rho, prob.eta, prob.dt if prob.rho > 0 else 0.0)
+    # contexts are shared by requests with the same grid, boundaries and fluid parameters
+    return (prob.dim, prob.n, prob.h, getattr(prob, "walls", 0), prob.rho, prob.eta,
+            prob.dt if prob.rho > 0 else 0.0)
 
 
 class Future:
@@ -146,7 +147,8 @@ class Server:
     # ---------------------------------------------------------------- defaults
     def _params(self, prob):
         from . import ibr
-        return dict(dim=prob.dim, n=prob.n, h=prob.h, rho=prob.rho, eta=prob.eta, dt=prob.dt, rtol=self.rtol,
+        return dict(dim=prob.dim, n=prob.n, h=prob.h, rho=prob.rho, eta=prob.eta, dt=prob.dt,
+                    walls=getattr(prob, "walls", 0), rtol=self.rtol,
                     precision=ibr.MIXED if self.precision == "mixed" else ibr.FP64, device=self.device,
                     graphs=self.graphs, **self.solver_kw)
 

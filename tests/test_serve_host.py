@@ -129,3 +129,30 @@ def test_trajectories_restart_from_rest_on_shared_contexts():
     assert np.array_equal(steady["F"], np.full((1, 3), 14.0))
     # unsteady and steady problems of one grid use different contexts: at most 2 per worker
     assert len(FakeSolver.created) <= 4
+
+
+def test_walls_get_their_own_contexts():
+    """A slit-channel request never lands on a periodic context of the same
+    grid (and the other way round), and the solver is built with its walls."""
+    FakeSolver.created = []
+    made = []
+
+    def factory(p):
+        made.append(getattr(p, "walls", 0))
+        return FakeSolver(p)
+
+    per = _prob(3, 16)
+    slit = _prob(3, 16)
+    slit.walls = 1
+    with serve.Server(workers=1, factory=factory, footprint=lambda p: 1,
+                      free_bytes=lambda: 1 << 40, reserve_bytes=0) as srv:
+        for p in (per, slit, per, slit):
+            srv.submit(p).result(timeout=10)
+    assert sorted(made) == [0, 1]
+    assert serve._context_key(per) != serve._context_key(slit)
+    srv2 = serve.Server(workers=1, factory=factory, footprint=lambda p: 1, free_bytes=lambda: 1 << 40,
+                        reserve_bytes=0)
+    try:
+        assert srv2._params(slit)["walls"] == 1 and srv2._params(per)["walls"] == 0
+    finally:
+        srv2.close()
