@@ -284,8 +284,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))
   const unsigned stride = gridDim.x * blockDim.x;
   for (unsigned i = blockIdx.x * blockDim.x + threadIdx.x; i < (unsigned)len; i += stride) {
     double v[NJ];
+    // the basis columns are streamed once per pass (a basis of 15 columns is
+    // about 1 GB at 128^3, beyond every cache): non-temporal loads keep them
+    // from evicting the two vectors the next pass reads again
 #pragma unroll
-    for (int q = 0; q < NJ; ++q) v[q] = (double)Vj[(int64_t)q * ld + i];
+    for (int q = 0; q < NJ; ++q) v[q] = (double)__builtin_nontemporal_load(&Vj[(int64_t)q * ld + i]);
     const double u = (double)x1[i], w = (double)x2[i];
 #pragma unroll
     for (int q = 0; q < NJ; ++q) {
@@ -389,7 +392,7 @@ __global__ void __launch_bounds__(256) k_dcgs2_axpy(T* __restrict__ V, int64_t l
     for (; j + 8 <= k; j += 8) {
       double v[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = (double)V[(int64_t)(j + u) * ld + i];
+      for (int u = 0; u < 8; ++u) v[u] = (double)__builtin_nontemporal_load(&V[(int64_t)(j + u) * ld + i]);
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         q -= coef[j + u] * v[u];
@@ -397,7 +400,7 @@ __global__ void __launch_bounds__(256) k_dcgs2_axpy(T* __restrict__ V, int64_t l
       }
     }
     for (; j < k; ++j) {
-      const double v = (double)V[(int64_t)j * ld + i];
+      const double v = (double)__builtin_nontemporal_load(&V[(int64_t)j * ld + i]);
       q -= coef[j] * v;
       a -= c[j] * v;
     }
