@@ -93,8 +93,9 @@ typedef struct {
                          Steady Stokes then needs no mean-velocity condition
                          and uses S as is.  Markers must lie strictly between
                          the walls (ibr_set_bodies returns IBR_EINVAL
-                         otherwise); ibr_step (explicit advection) is periodic
-                         only and returns IBR_EINVAL with walls. */
+                         otherwise); ibr_step's advection uses the same
+                         mirror rules, and it returns IBR_EINVAL (moving
+                         nothing) when a body would cross a wall. */
 } ibr_params;
 
 /* Per-solve report.  ps_applications counts P_S^-1 applications, the cost
@@ -158,7 +159,8 @@ ibr_status ibr_solve(ibr_ctx* ctx, int warm_start, ibr_info* info);
 /* One unsteady step (rho > 0): explicit advection right-hand side
  * (Adams-Bashforth 2, forward Euler on the first step), markers moved by
  * dt U_p, constrained solve warm-started from the previous step's solution.
- * Bodies translate only: IBR_EINVAL if some Omega is nonzero. */
+ * Bodies translate only: IBR_EINVAL if some Omega is nonzero.  With walls,
+ * IBR_EINVAL (nothing moved) if a body's markers would reach a wall. */
 ibr_status ibr_step(ibr_ctx* ctx, ibr_info* info);
 
 /* Free kinematics (Sec. 2 poses it; Sec. 8 names the enlarged system and its

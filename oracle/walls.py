@@ -543,3 +543,63 @@ def radius_from_slit_drag(F, V, H, where, eta=1.0):
         else:
             hi = mid
     return 0.5 * (lo + hi)
+
+
+# ---------------------------------------------------------------- unsteady steps between the walls
+def advection(v, h):
+    """The centred advective form of ``navier.advection`` with the walls'
+    extension: a tangential component's neighbour across a wall is its mirror
+    image with the sign reversed, the normal component's wall faces hold 0
+    (so the averaged normal velocity and its differences need no ghost), and
+    the normal component's rows on the wall faces are 0 (not equations)."""
+    d = v.shape[0]
+    ks = kinds(d)
+    out = np.zeros_like(v)
+    for a in range(d):
+        axa = d - 1 - a
+        acc = np.zeros_like(v[a])
+
+        def nb(x, off, ax, kind):
+            return znbr(x, off, kind) if ax == 0 else pnbr(x, off, ax)
+
+        for b in range(d):
+            axb = d - 1 - b
+            if b == a:
+                vb = v[a]
+            else:
+                # v^b at c, c + e_b, c - e_a, c - e_a + e_b; along the wall axis these
+                # stay inside the lattice or land on a wall face (value 0)
+                vm = nb(v[b], -1, axa, ks[b])
+                vb = 0.25 * (v[b] + nb(v[b], 1, axb, ks[b]) + vm + nb(vm, 1, axb, ks[b]))
+            acc += vb * (nb(v[a], 1, axb, ks[a]) - nb(v[a], -1, axb, ks[a])) / (2.0 * h)
+        out[a] = acc
+    out[d - 1][0] = 0.0
+    return out
+
+
+def run(prob, nsteps, **kw):
+    """Exact constrained solves along a trajectory between the walls (the
+    steps of ``navier.run``: AB2 advection, backward Euler viscosity, bodies
+    translated before each solve)."""
+    from . import navier
+    d, n, h = prob.dim, prob.n, prob.h
+    v = np.zeros((d,) + (n,) * d)
+    N_prev = None
+    R = prob.R.copy()
+    centres = prob.centres.copy()
+    out = []
+    b = ib.body_of(prob.offsets)
+    c0 = prob.rho / prob.dt
+    for step in range(nsteps):
+        N_n = advection(v, h)
+        g = navier.rhs(v, N_n, N_prev, prob.rho, prob.dt, first=(step == 0))
+        g[d - 1][0] = 0.0
+        R = R + prob.dt * prob.U[b]
+        centres = centres + prob.dt * prob.U
+        sysm = System(d, n, h, c0, prob.eta, R)
+        V = ib.marker_velocities(R, prob.offsets, centres, prob.U, prob.Omega, prob.L)
+        sol = constrained.solve(sysm, g, None, -V, prob.offsets, centres, **kw)
+        out.append(sol)
+        N_prev = N_n
+        v = sol.v
+    return out

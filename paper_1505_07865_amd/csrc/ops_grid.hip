@@ -398,18 +398,26 @@ __global__ void __launch_bounds__(256) k_combine_from_split(const TZ* __restrict
 
 // Centred advective term N(v)^a = sum_b vbar^b (v^a_{c+e_b} - v^a_{c-e_b}) / (2h),
 // vbar^b the average of the four b-faces around the a-face (b != a).
+// walls: along the last axis a tangential component's neighbour beyond a
+// wall is its negated self; the normal component's wall faces hold 0, so the
+// averaged normal velocity and the normal component's own differences need
+// no ghost, and its rows on the wall faces are 0.
 template <int DIM>
 __global__ void __launch_bounds__(256) k_advect(const double* __restrict__ v, double* __restrict__ N, int logn,
-                                                double inv_2h) {
+                                                double inv_2h, int walls) {
   const int64_t C = (int64_t)1 << (DIM * logn);
   const int64_t c = xcd_block(gridDim.x) * blockDim.x + threadIdx.x;
   if (c >= C) return;
   const int n = 1 << logn;
-  const int mask = n - 1;
   const Nbr nb = neighbours<DIM>(c, logn);
+  const int w = (int)(c >> ((DIM - 1) * logn));  // coordinate along the last axis
 #pragma unroll
   for (int a = 0; a < DIM; ++a) {
     const double* va = v + a * C;
+    if (walls && a == DIM - 1 && w == 0) {
+      N[a * C + c] = 0.0;
+      continue;
+    }
     double acc = 0;
 #pragma unroll
     for (int b = 0; b < DIM; ++b) {
@@ -417,17 +425,21 @@ __global__ void __launch_bounds__(256) k_advect(const double* __restrict__ v, do
       if (b == a) {
         vb = va[c];
       } else {
-        const double* w = v + b * C;
+        const double* wv = v + b * C;
         const int64_t cm = nb.m[a];  // c - e_a
         // (c - e_a) + e_b
         const Nbr nm = neighbours<DIM>(cm, logn);
-        vb = 0.25 * (w[c] + w[nb.p[b]] + w[cm] + w[nm.p[b]]);
+        vb = 0.25 * (wv[c] + wv[nb.p[b]] + wv[cm] + wv[nm.p[b]]);
       }
-      acc += vb * (va[nb.p[b]] - va[nb.m[b]]) * inv_2h;
+      double up = va[nb.p[b]], dn = va[nb.m[b]];
+      if (walls && b == DIM - 1 && a != DIM - 1) {
+        if (w == n - 1) up = -va[c];
+        if (w == 0) dn = -va[c];
+      }
+      acc += vb * (up - dn) * inv_2h;
     }
     N[a * C + c] = acc;
   }
-  (void)mask;
 }
 
 // g = (rho/dt) v - rho (w1 N1 + w0 N0)   (N0 may be null)
@@ -563,12 +575,12 @@ template void launch_combine_from_split<double, double>(int, int, const double*,
 template void launch_combine_from_split<float, float>(int, int, const float*, int64_t, int, const double*, float*,
                                                       int, bool, hipStream_t);
 
-void launch_advect(int dim, int logn, const double* v, double* N, double inv_2h, hipStream_t s) {
+void launch_advect(int dim, int logn, const double* v, double* N, double inv_2h, hipStream_t s, int walls) {
   const int64_t C = (int64_t)1 << (dim * logn);
   if (dim == 3)
-    hipLaunchKernelGGL((k_advect<3>), dim3(nblk(C)), dim3(256), 0, s, v, N, logn, inv_2h);
+    hipLaunchKernelGGL((k_advect<3>), dim3(nblk(C)), dim3(256), 0, s, v, N, logn, inv_2h, walls);
   else
-    hipLaunchKernelGGL((k_advect<2>), dim3(nblk(C)), dim3(256), 0, s, v, N, logn, inv_2h);
+    hipLaunchKernelGGL((k_advect<2>), dim3(nblk(C)), dim3(256), 0, s, v, N, logn, inv_2h, walls);
 }
 
 void launch_ns_rhs(const double* v, const double* N1, const double* N0, double* g, int64_t len, double rdt,

@@ -63,6 +63,9 @@ struct ibr_ctx {
   // the mean-velocity condition and S'
   bool walls = false;
   bool vnull = true;
+  // per body along the walls' axis (host): centre, marker extent below and
+  // above it, prescribed velocity; ibr_step checks the next position
+  std::vector<double> wall_z, wall_lo, wall_hi, wall_uz;
   bool mixed = false;
   hipStream_t stream = nullptr;
   bool own_stream = false;
@@ -909,11 +912,27 @@ ibr_status ibr_set_bodies(ibr_ctx* c, int nbodies, const int* offsets, const dou
       if (!std::isfinite(R[i])) throw Status(IBR_EINVAL, "marker positions must be finite");
     for (int64_t i = 0; i < (int64_t)nbodies * d; ++i)
       if (!std::isfinite(centres[i])) throw Status(IBR_EINVAL, "centres must be finite");
-    if (c->walls)
+    if (c->walls) {
       for (int64_t m = 0; m < N; ++m) {
         const double z = R[m * d + d - 1];
         if (!(z > 0.0 && z < c->L)) throw Status(IBR_EINVAL, "markers must lie strictly between the walls");
       }
+      c->wall_z.assign(nbodies, 0.0);
+      c->wall_lo.assign(nbodies, 0.0);
+      c->wall_hi.assign(nbodies, 0.0);
+      c->wall_uz.assign(nbodies, 0.0);
+      for (int b = 0; b < nbodies; ++b) {
+        const double zc = centres[b * d + d - 1];
+        double lo = 0.0, hi = 0.0;
+        for (int m = offsets[b]; m < offsets[b + 1]; ++m) {
+          lo = std::min(lo, R[(int64_t)m * d + d - 1] - zc);
+          hi = std::max(hi, R[(int64_t)m * d + d - 1] - zc);
+        }
+        c->wall_z[b] = zc;
+        c->wall_lo[b] = lo;
+        c->wall_hi[b] = hi;
+      }
+    }
     IBR_HIP(hipSetDevice(c->p.device));
     sync(c);
     // body-sized buffers are rebuilt every call (set-up, not the solve path)
@@ -1015,6 +1034,8 @@ ibr_status ibr_set_velocities(ibr_ctx* c, const double* U, const double* Omega) 
       rot = rot || Omega[i] != 0.0;
     }
     c->rotating = rot;
+    if (c->walls)
+      for (int b = 0; b < c->nb; ++b) c->wall_uz[b] = U[b * d + d - 1];
     IBR_HIP(hipSetDevice(c->p.device));
     IBR_HIP(hipMemcpyAsync(c->U, U, (size_t)c->nb * d * sizeof(double), hipMemcpyHostToDevice, c->stream));
     IBR_HIP(hipMemcpyAsync(c->Om, Omega, (size_t)c->nb * no * sizeof(double), hipMemcpyHostToDevice, c->stream));
@@ -1124,7 +1145,15 @@ ibr_status ibr_step(ibr_ctx* c, ibr_info* info) {
   ibr_status g = guard(c, [&] {
     require_bodies(c);
     if (c->steady) throw Status(IBR_ESTATE, "ibr_step needs rho > 0 (unsteady)");
-    if (c->walls) throw Status(IBR_EINVAL, "ibr_step: the advection term is periodic only (no walls)");
+    if (c->walls) {
+      // bodies translate with their prescribed velocity: every marker must stay between the walls
+      for (int b = 0; b < c->nb; ++b) {
+        const double zc = c->wall_z[b] + c->p.dt * c->wall_uz[b];
+        if (!(zc + c->wall_lo[b] > 0.0 && zc + c->wall_hi[b] < c->L))
+          throw Status(IBR_EINVAL, "ibr_step: body " + std::to_string(b) + " would cross a wall");
+      }
+      for (int b = 0; b < c->nb; ++b) c->wall_z[b] += c->p.dt * c->wall_uz[b];
+    }
     if (c->rotating) throw Status(IBR_EINVAL, "ibr_step translates the bodies: Omega must be zero");
     if (c->nfree) throw Status(IBR_EINVAL, "ibr_step moves bodies with prescribed velocities only: no free bodies");
     IBR_HIP(hipSetDevice(c->p.device));
@@ -1133,7 +1162,7 @@ ibr_status ibr_step(ibr_ctx* c, ibr_info* info) {
     const int64_t len = (int64_t)d * c->C;
     if (!c->have_solution) launch_fill<double>(c->Xs, c->NV, 0.0, s);
     // explicit advection (AB2, forward Euler on the first step)
-    launch_advect(d, c->logn, c->Xs, c->Ncur, 0.5 / c->h, s);
+    launch_advect(d, c->logn, c->Xs, c->Ncur, 0.5 / c->h, s, c->walls ? 1 : 0);
     const double rho = c->p.rho;
     if (c->have_prev)
       launch_ns_rhs(c->Xs, c->Ncur, c->Nprev, c->Bs, len, c->c0, rho, 1.5, -0.5, s);
@@ -1438,7 +1467,7 @@ ibr_status ibr_advect(ibr_ctx* c, const double* u, double* N) {
     const int d = c->dim;
     hipStream_t s = c->stream;
     IBR_HIP(hipMemcpyAsync(c->Nprev, u, (size_t)d * c->C * sizeof(double), hipMemcpyHostToDevice, s));
-    launch_advect(d, c->logn, c->Nprev, c->Ncur, 0.5 / c->h, s);
+    launch_advect(d, c->logn, c->Nprev, c->Ncur, 0.5 / c->h, s, c->walls ? 1 : 0);
     IBR_HIP(hipMemcpyAsync(N, c->Ncur, (size_t)d * c->C * sizeof(double), hipMemcpyDeviceToHost, s));
     c->have_prev = false;
     sync(c);

@@ -403,11 +403,11 @@ def serving_trace(seed: int = 0, nreq: int = 2000, qps: float = 50.0) -> List[di
 
 def slit_problem(seed: int = 0, dim: int = 3, n: int = 32, nbodies: int = 2, radius_h: float = 3.0,
                  eta: float = 1.0, gap_h: float = 4.0, wall_gap_h: float = 2.0, rotate: bool = True,
-                 L: float = 1.0) -> Problem:
-    """Steady Stokes in a slit channel: no-slip walls at z = 0 and z = L (y in
-    2D), periodic along the other axes; bodies as in ``small_problem``, with
-    centres drawn so that every surface keeps ``wall_gap_h`` cells from the
-    walls."""
+                 L: float = 1.0, rho: float = 0.0, dt: float = 0.0) -> Problem:
+    """Stokes (rho = 0) or unsteady (rho, dt > 0) flow in a slit channel:
+    no-slip walls at z = 0 and z = L (y in 2D), periodic along the other
+    axes; bodies as in ``small_problem``, with centres drawn so that every
+    surface keeps ``wall_gap_h`` cells from the walls."""
     rng = np.random.default_rng(seed)
     h = L / n
     rad = radius_h * h
@@ -431,7 +431,7 @@ def slit_problem(seed: int = 0, dim: int = 3, n: int = 32, nbodies: int = 2, rad
     else:
         Om = rng.uniform(-1.0, 1.0, size=(nbodies, 1)) if rotate else np.zeros((nbodies, 1))
         bodies = [disk_ring(disk_markers_for(radius_h), rad, c, rng.uniform(0, 2 * math.pi)) for c in centres]
-    prob = _assemble(dim, n, h, 0.0, eta, 0.0, bodies, centres, U, Om, [rad] * nbodies, 0,
+    prob = _assemble(dim, n, h, rho, eta, dt, bodies, centres, U, Om, [rad] * nbodies, 0,
                      "slit_%dd_%d" % (dim, n))
     prob.walls = 1
     return prob

@@ -12,8 +12,10 @@ axis, periodic along the others) against ``oracle.walls``, through the C ABI.
   Lambda, F, T within 1e-8 relative L2), mixed precision at rtol 1e-8 within
   1e-6, lower and full preconditioner;
 * free bodies between the walls solve to the oracle's free-kinematics answer;
-* set-up checks: markers outside the channel and ibr_step with walls are
-  refused.
+* unsteady: the advection term with the mirror rules (1e-13) and three
+  steps of moving bodies (fp64 1e-8, mixed 1e-6) equal the oracle's;
+* set-up checks: markers outside the channel, and a step that would carry a
+  body to a wall, are refused.
 """
 import numpy as np
 import pytest
@@ -156,20 +158,61 @@ def test_walls_free_bodies_match_oracle():
 
 
 def test_walls_refusals():
+    """Markers outside the channel are refused at set-up, and a step that
+    would carry a body's markers to a wall is refused before anything moves."""
     from paper_1505_07865_amd import ibr
-    prob = slit_problem(1, dim=3, n=16, nbodies=1, radius_h=2.5)
+    prob = slit_problem(1, dim=3, n=16, nbodies=1, radius_h=2.5, rotate=False)
     bad = prob.R.copy()
     bad[0, 2] = 0.0
     s = ibr.Solver(dim=3, n=16, h=1.0 / 16, walls=ibr.WALLS_NOSLIP)
     with pytest.raises(ibr.IbrError):
         s.set_bodies(bad, prob.offsets, prob.centres)
     s.close()
-    s = ibr.Solver(dim=3, n=16, h=1.0 / 16, rho=1.0, dt=0.01, walls=ibr.WALLS_NOSLIP)
+    s = ibr.Solver(dim=3, n=16, h=1.0 / 16, rho=1.0, dt=0.01, eta=0.05, walls=ibr.WALLS_NOSLIP)
     s.set_bodies(prob.R, prob.offsets, prob.centres)
-    s.set_velocities(prob.U, prob.Omega)
+    U = np.zeros((1, 3))
+    U[0, 2] = -100.0                                    # a whole channel width per step
+    s.set_velocities(U, prob.Omega)
+    R0, X0 = s.markers()
     with pytest.raises(ibr.IbrError):
         s.step()
+    R1, X1 = s.markers()
+    assert np.array_equal(R0, R1) and np.array_equal(X0, X1)
     s.close()
+
+
+@pytest.mark.parametrize("dim,n", [(2, 32), (3, 16)])
+def test_walls_advection_matches_oracle(dim, n):
+    from paper_1505_07865_amd import ibr
+    s = ibr.Solver(dim=dim, n=n, h=1.0 / n, rho=1.0, dt=0.01, walls=ibr.WALLS_NOSLIP)
+    rng = np.random.default_rng(9)
+    u = rng.standard_normal((dim,) + (n,) * dim)
+    u[dim - 1][0] = 0.0
+    N = s.advect(u)
+    s.close()
+    Ne = walls.advection(u, 1.0 / n)
+    assert _rel(N, Ne) < 1e-13, _rel(N, Ne)
+
+
+@pytest.mark.parametrize("dim,n,precision", [(2, 32, "fp64"), (3, 16, "fp64"), (3, 16, "mixed")])
+def test_walls_steps_match_oracle(dim, n, precision):
+    """Unsteady steps between the walls (advection with the mirror rules,
+    bodies translating) equal the oracle's exact trajectory."""
+    from paper_1505_07865_amd import ibr
+    prob = slit_problem(5, dim=dim, n=n, nbodies=2, radius_h=2.5 if dim == 3 else 4.0, wall_gap_h=2.0,
+                        gap_h=2.0, rotate=False, rho=1.0, dt=0.5 / n, eta=0.05)
+    fp64 = precision == "fp64"
+    s = ibr.from_problem(prob, precision=ibr.FP64 if fp64 else ibr.MIXED, rtol=1e-10 if fp64 else 1e-8)
+    sols = []
+    for _ in range(3):
+        s.step()
+        sols.append(s.solution())
+    s.close()
+    ex = walls.run(prob, 3)
+    tol = 1e-8 if fp64 else 1e-6
+    for k in range(3):
+        assert _rel(sols[k].u, ex[k].v) < tol, (k, _rel(sols[k].u, ex[k].v))
+        assert _rel(sols[k].F, ex[k].F) < tol, (k, _rel(sols[k].F, ex[k].F))
 
 
 def test_slit_shell_drag_symmetry_and_wall_effect():

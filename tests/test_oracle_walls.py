@@ -297,3 +297,63 @@ def test_faxen_series_limits_and_inverse():
             assert abs(walls.radius_from_slit_drag(F, 1.0, H, where) - r) < 1e-12
     for R in (0.02, 0.06, 0.1):
         assert walls.faxen_mobility(R, d / 4, "quarter") < walls.faxen_mobility(R, d / 2, "half")
+
+
+def _mirror(v):
+    """Mirror image of a face field about the midplane between the walls:
+    tangential rows k -> n-1-k, normal faces k -> n-k with the sign reversed
+    (face 0 is its own image, the walls swapping)."""
+    d, n = v.shape[0], v.shape[1]
+    out = v.copy()
+    for a in range(d - 1):
+        out[a] = v[a][::-1]
+    out[d - 1] = 0.0
+    out[d - 1][1:] = -v[d - 1][1:][::-1]
+    return out
+
+
+@pytest.mark.parametrize("d,n", [(2, 16), (3, 8)])
+def test_wall_advection_interior_rows_and_mirror(d, n):
+    """Away from the tangential components' boundary rows the wall advection
+    equals the periodic one (the normal component's wall faces hold 0 in
+    both), and it commutes with the mirror image about the midplane."""
+    from oracle import navier
+    h = 1.0 / n
+    rng = np.random.default_rng(8)
+    v = rng.standard_normal((d,) + (n,) * d)
+    v[d - 1][0] = 0.0
+    Nw = walls.advection(v, h)
+    Np = navier.advection(v, h)
+    for a in range(d - 1):
+        assert np.abs(Nw[a][1:-1] - Np[a][1:-1]).max() < 1e-13
+        assert np.abs(Nw[a][[0, -1]] - Np[a][[0, -1]]).max() > 1e-3
+    assert np.abs(Nw[d - 1][1:] - Np[d - 1][1:]).max() < 1e-13 and np.abs(Nw[d - 1][0]).max() == 0.0
+    assert np.abs(walls.advection(_mirror(v), h) - _mirror(Nw)).max() < 1e-12
+
+
+def test_wall_advection_converges_to_the_continuum():
+    """A no-slip, divergence-free 2D flow between the walls (stream function
+    sin(2 pi x) z^2 (1 - z)^2): the discrete advection term converges at
+    second order to (u . grad) u, the boundary rows included."""
+    def ux(x, z):
+        return np.sin(2 * np.pi * x) * 2 * z * (1 - z) * (1 - 2 * z)
+
+    def uz(x, z):
+        return -2 * np.pi * np.cos(2 * np.pi * x) * z ** 2 * (1 - z) ** 2
+
+    e = 1e-6
+
+    def conv(f, x, z):
+        return ux(x, z) * (f(x + e, z) - f(x - e, z)) / (2 * e) + uz(x, z) * (f(x, z + e) - f(x, z - e)) / (2 * e)
+
+    errs = []
+    for n in (16, 32, 64):
+        h = 1.0 / n
+        i = np.arange(n)
+        Zx, Xx = np.meshgrid((i + 0.5) * h, i * h, indexing="ij")
+        Zz, Xz = np.meshgrid(i * h, (i + 0.5) * h, indexing="ij")
+        v = np.stack([ux(Xx, Zx), uz(Xz, Zz)])
+        ex = np.stack([conv(ux, Xx, Zx), conv(uz, Xz, Zz)])
+        ex[1][0] = 0.0
+        errs.append(np.abs(walls.advection(v, h) - ex).max())
+    assert np.log2(errs[0] / errs[1]) > 1.8 and np.log2(errs[1] / errs[2]) > 1.8, errs
