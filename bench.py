@@ -74,6 +74,9 @@ def parse():
     ap.add_argument("--walls", action="store_true",
                     help="slit channel (no-slip walls along z) at 128^3 against the same bodies in the periodic box")
     ap.add_argument("--slit-solves", type=int, default=5, help="slit channel: timed solves per precision and box")
+    ap.add_argument("--large", action="store_true",
+                    help="the 256^3 configuration (100 spheres, steady), mixed and fp64 solves")
+    ap.add_argument("--large-solves", type=int, default=2, help="large: timed solves per precision")
     ap.add_argument("--blocks", action="store_true",
                     help="per-body mobility set-up of the 256^3 configuration (100 blocks of 600 x 600, fp64 MFMA)")
     ap.add_argument("--block-reps", type=int, default=5, help="blocks: timed set-ups")
@@ -433,6 +436,54 @@ def slit_channel(args, torch):
     print(json.dumps(line), flush=True)
 
 
+def large(args, torch):
+    """The 256^3 configuration: steady Stokes in a periodic 256^3 box with 100
+    spheres of radius 8h (200 markers each, 20 000 markers, 100 mobility
+    blocks of 600 x 600), restart 50, rtol 1e-8.  Per precision: the
+    context's set-up and one untimed solve, then timed solves from a zero
+    initial guess (host clock around each synchronous solve).  The mixed
+    run carries the live kernel timers; its roofline is that of the dominant
+    timed class, as in the default line."""
+    from paper_1505_07865_amd import ibr
+    from synthetic import config4_spheres256
+    prob = config4_spheres256(args.seed)
+    out, roof, others = {}, None, {}
+    for prec in ("fp64", "mixed"):
+        s = ibr.from_problem(prob, rtol=1e-8, restart=50, precision=ibr.MIXED if prec == "mixed" else ibr.FP64,
+                             graphs=0)
+        s.solve()
+        if prec == "mixed":
+            for t in ibr.TIMERS:
+                ibr.timer_enable(t, TIMER_STRIDE[t])
+        infos, wall = [], []
+        for _ in range(args.large_solves):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            infos.append(s.solve())
+            wall.append((time.perf_counter() - t1) * 1e3)
+        if prec == "mixed":
+            timers = {t: ibr.timer_read(t) for t in ibr.TIMERS}
+            for t in ibr.TIMERS:
+                ibr.timer_enable(t, 0)
+            _, roof, others = roofline(timers)
+        s.close()
+        out[prec] = {"solves_per_s": round(len(wall) / (sum(wall) / 1e3), 4), "p50_ms": round(percentile(wall, 50), 2),
+                     "iters": infos[-1]["iters"], "restarts": infos[-1]["restarts"],
+                     "ps_applications": infos[-1]["ps_applications"],
+                     "max_rel_residual": float("%.4g" % max(i["rel_residual"] for i in infos))}
+        print("bench: 256^3 %s: %.3f solves/s (%.0f ms), %d iterations" % (prec, out[prec]["solves_per_s"],
+              out[prec]["p50_ms"], out[prec]["iters"]), file=sys.stderr, flush=True)
+    line = {"metric": "solves/s at 1e-8 residual, mixed vs FP64, 3D 256^3 steady, 100 spheres",
+            "value": out["mixed"]["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "higher_is_better": True,
+            "vs_baseline": None, "dtype": "f32 preconditioner + f64 outer", "data": "synthetic",
+            "config": {"workload": "3D steady Stokes, periodic 256^3, 100 spheres R=8h x 200 markers, "
+                                   "U, Omega ~ U[-1,1]^3, restart 50, rtol 1e-8, solves from rest",
+                       "seed": args.seed, "solves": args.large_solves},
+            "roofline": roof, "kernels": others, "mixed": out["mixed"], "fp64": out["fp64"],
+            "mixed_over_fp64": round(out["mixed"]["solves_per_s"] / out["fp64"]["solves_per_s"], 3)}
+    print(json.dumps(line), flush=True)
+
+
 def blocks(args, torch):
     """Per-body mobility set-up (assembly, shifted Cholesky on fp64 MFMA
     tiles, triangular inverse, M~^-1 = X^T X) for the 256^3 configuration's
@@ -549,6 +600,9 @@ def main():
         return
     if args.walls:
         slit_channel(args, torch)
+        return
+    if args.large:
+        large(args, torch)
         return
     prob = config2_spheres_ns(args.seed, re=args.re)
     precs = ["fp64", "mixed"] if args.precision == "both" else [args.precision]

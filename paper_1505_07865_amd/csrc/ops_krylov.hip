@@ -389,12 +389,13 @@ __global__ void __launch_bounds__(256) k_dcgs2_axpy(T* __restrict__ V, int64_t l
     double q = (double)vk[i];
     double a = (double)w[i];
     int j = 0;
-    for (; j + 8 <= k; j += 8) {
-      double v[8];
+    // 4 columns per chunk: measured a little faster than 8 or 16 (occupancy)
+    for (; j + 4 <= k; j += 4) {
+      double v[4];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = (double)__builtin_nontemporal_load(&V[(int64_t)(j + u) * ld + i]);
+      for (int u = 0; u < 4; ++u) v[u] = (double)__builtin_nontemporal_load(&V[(int64_t)(j + u) * ld + i]);
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
+      for (int u = 0; u < 4; ++u) {
         q -= coef[j + u] * v[u];
         a -= c[j + u] * v[u];
       }
