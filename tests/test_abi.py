@@ -37,15 +37,43 @@ def test_default_params_and_status(lib):
     from paper_1505_07865_amd import ibr
     p = ibr.Params()
     lib.ibr_default_params(ctypes.byref(p))
-    assert p.dim == 3 and p.restart == 100 and p.n_s == 2 and p.rtol == 1e-8
+    assert p.dim == 3 and p.restart == 100 and p.n_s == 2 and p.rtol == 1e-8 and p.walls == 0
     assert lib.ibr_status_string(0) == b"ok"
     assert lib.ibr_status_string(5).startswith(b"mobility")
+
+
+def test_params_layout_matches_header(tmp_path):
+    """The binding's ibr_params / ibr_info mirror the header's structs: size
+    and every field offset, as a C compiler lays them out."""
+    import shutil
+    import subprocess
+    from paper_1505_07865_amd import ibr
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "ibr.h"', 'int main(void) {']
+    for st, cls in (("ibr_params", ibr.Params), ("ibr_info", ibr.Info)):
+        lines.append('  printf("%s %%zu\\n", sizeof(%s));' % (st, st))
+        for name, _ in cls._fields_:
+            lines.append('  printf("%s.%s %%zu\\n", offsetof(%s, %s));' % (st, name, st, name))
+    lines.append('  return 0; }')
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(root, "include"), str(src), "-o", str(exe)], check=True)
+    got = dict(l.split() for l in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                  text=True).stdout.splitlines())
+    for st, cls in (("ibr_params", ibr.Params), ("ibr_info", ibr.Info)):
+        assert int(got[st]) == ctypes.sizeof(cls), st
+        for name, _ in cls._fields_:
+            assert int(got[st + "." + name]) == getattr(cls, name).offset, (st, name)
 
 
 def test_invalid_params_rejected_before_device_work(lib):
     from paper_1505_07865_amd import ibr
     for bad in (dict(dim=4), dict(n=48), dict(h=0.0), dict(eta=-1.0), dict(rho=1.0, dt=0.0), dict(n_s=0),
-                dict(rtol=0.0), dict(precision=7)):
+                dict(rtol=0.0), dict(precision=7), dict(walls=2), dict(walls=-1)):
         p = ibr.default_params(**bad)
         ctx = ctypes.c_void_p()
         assert lib.ibr_create(ctypes.byref(p), ctypes.byref(ctx)) == 1, bad
@@ -58,6 +86,9 @@ def test_footprint_grows_with_grid(lib):
     assert f[0] < f[1] < f[2]
     fm = lib.ibr_footprint_bytes(ctypes.byref(ibr.default_params(n=128, h=1.0 / 128, precision=1)), 1, 200)
     assert fm < f[2]
+    # the slit channel keeps every multigrid level down to 4^3 in global memory as well
+    fw = lib.ibr_footprint_bytes(ctypes.byref(ibr.default_params(n=128, h=1.0 / 128, walls=1)), 1, 200)
+    assert fw > f[2]
 
 
 def test_oracle_is_not_imported_by_product():
