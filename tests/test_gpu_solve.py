@@ -254,3 +254,25 @@ def test_icosahedral_shell_matches_oracle(filled, re, pc, ns):
     assert np.linalg.norm(sol.T - ex.T) < 1e-8 * tscale
     per_iter = (2 if pc == "full" else 1) * ns
     assert info["ps_applications"] == per_iter * info["iters"]
+
+
+@pytest.mark.parametrize("dim,n,walls", [(3, 8, 0), (2, 16, 0), (3, 8, 1), (2, 16, 1)])
+def test_smallest_grids_match_oracle(dim, n, walls):
+    """The smallest grids the library accepts (8^3, 16^2: the whole V-cycle in
+    the one-workgroup tail, one spreading tile), periodic and between walls,
+    solve to the oracle's exact answer."""
+    from oracle import walls as owalls
+    from synthetic import slit_problem
+    from paper_1505_07865_amd import ibr
+    if walls:
+        prob = slit_problem(2, dim=dim, n=n, nbodies=1, radius_h=1.5 if dim == 3 else 2.5, wall_gap_h=0.5)
+        ex = owalls.solve_problem(prob)
+    else:
+        prob = small_problem(2, dim, n, nbodies=1, radius_h=1.5 if dim == 3 else 2.5)
+        ex = constrained.solve_problem(prob)
+    print("smallest", dim, n, walls, prob.nmarkers, flush=True)
+    s = ibr.from_problem(prob, rtol=1e-10)
+    s.solve()
+    sol = s.solution()
+    s.close()
+    assert _rel(sol.u, ex.v) < 1e-8 and _rel(sol.F, ex.F) < 1e-8
