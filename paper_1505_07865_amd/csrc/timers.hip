@@ -42,7 +42,10 @@ int timer_index(const char* name) {
 hipEvent_t next_event(TimerState& t) {
   if (t.used == t.pool.size()) {
     hipEvent_t e = nullptr;
-    if (hipEventCreateWithFlags(&e, hipEventDefault) != hipSuccess) return nullptr;
+    // timing only: no system-scope fence when the event is recorded (the
+    // fence's cache write-back would lengthen the timed interval and slow the
+    // kernels after it); the readout follows a device synchronisation
+    if (hipEventCreateWithFlags(&e, hipEventDefault | hipEventDisableSystemFence) != hipSuccess) return nullptr;
     t.pool.push_back(e);
   }
   return t.pool[t.used++];
