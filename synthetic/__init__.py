@@ -25,4 +25,5 @@ from .workloads import (  # noqa: F401
     single_shell,
     slit_problem,
     slit_shell,
+    array_shell,
 )

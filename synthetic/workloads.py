@@ -450,3 +450,15 @@ def slit_shell(n: int = 32, level: int = 0, height: float = 0.5, radius: float =
                      "slit_shell_%d_l%d_h%g" % (n, level, height))
     prob.walls = 1
     return prob
+
+
+def array_shell(n: int = 16, level: int = 2, radius: float = 0.47, L: float = 1.0, V: float = 1.0) -> Problem:
+    """One icosahedral shell (10 * 4^level + 2 markers) of the given radius at
+    the centre of a periodic cube of side L, translating with V along x:
+    with its periodic images, a simple-cubic array of spheres (the dense
+    arrays of Sec. 7); steady Stokes, eta = 1."""
+    h = L / n
+    c = np.full(3, 0.5 * L)
+    return _assemble(3, n, h, 0.0, 1.0, 0.0, [icosphere_unit(level) * radius + c], c[None, :].copy(),
+                     np.array([[V, 0.0, 0.0]]), np.zeros((1, 3)), [radius], 0,
+                     "array_shell_%d_l%d" % (n, level))
