@@ -101,14 +101,14 @@ __global__ void __launch_bounds__(256) k_free_body_rows(int dim, int nb, const i
   const int b = blockIdx.x;
   const int nr = dim == 3 ? 3 : 1;
   if (!free_b[b]) {
-    if (threadIdx.x < dim) yu[b * dim + threadIdx.x] = (double)xu[b * dim + threadIdx.x];
-    if (threadIdx.x < nr) yo[b * nr + threadIdx.x] = (double)xo[b * nr + threadIdx.x];
+    if ((int)threadIdx.x < dim) yu[b * dim + threadIdx.x] = (double)xu[b * dim + threadIdx.x];
+    if ((int)threadIdx.x < nr) yo[b * nr + threadIdx.x] = (double)xo[b * nr + threadIdx.x];
     return;
   }
   double f[3], t[3];
   body_sums(dim, off, R, X, L, lam, b, red, f, t);
-  if (threadIdx.x < dim) yu[b * dim + threadIdx.x] = f[threadIdx.x];
-  if (threadIdx.x < nr) yo[b * nr + threadIdx.x] = t[threadIdx.x];
+  if ((int)threadIdx.x < dim) yu[b * dim + threadIdx.x] = f[threadIdx.x];
+  if ((int)threadIdx.x < nr) yo[b * nr + threadIdx.x] = t[threadIdx.x];
 }
 
 // Per free body: Y = M~^-1 K (rows dim N_p, q = dim + rotations columns,
@@ -227,8 +227,8 @@ __global__ void __launch_bounds__(256) k_free_precond(int dim, int nb, const int
   const int nr = dim == 3 ? 3 : 1;
   const int q = dim + nr;
   if (!free_b[b]) {
-    if (threadIdx.x < dim) zu[b * dim + threadIdx.x] = (TZ)ru[b * dim + threadIdx.x];
-    if (threadIdx.x < nr) zo[b * nr + threadIdx.x] = (TZ)ro[b * nr + threadIdx.x];
+    if ((int)threadIdx.x < dim) zu[b * dim + threadIdx.x] = (TZ)ru[b * dim + threadIdx.x];
+    if ((int)threadIdx.x < nr) zo[b * nr + threadIdx.x] = (TZ)ro[b * nr + threadIdx.x];
     return;
   }
   double f[3], t[3];
@@ -253,8 +253,8 @@ __global__ void __launch_bounds__(256) k_free_precond(int dim, int nb, const int
     for (int col = 0; col < q; ++col) s += Yb[(int64_t)row * q + col] * Us[col];
     lam[(int64_t)lo * dim + row] += s;
   }
-  if (threadIdx.x < dim) zu[b * dim + threadIdx.x] = (TZ)Us[threadIdx.x];
-  if (threadIdx.x < nr) zo[b * nr + threadIdx.x] = (TZ)Us[dim + threadIdx.x];
+  if ((int)threadIdx.x < dim) zu[b * dim + threadIdx.x] = (TZ)Us[threadIdx.x];
+  if ((int)threadIdx.x < nr) zo[b * nr + threadIdx.x] = (TZ)Us[dim + threadIdx.x];
 }
 
 // Marker right-hand side W = 0 on the markers of free bodies.

@@ -40,7 +40,7 @@ __global__ void __launch_bounds__(256) k_multi_dot(const TV* __restrict__ V, int
     if (lane == 0) red[q][wv] = s;
   }
   __syncthreads();
-  if (threadIdx.x < nj) {
+  if ((int)threadIdx.x < nj) {
     double s = 0;
     for (int u = 0; u < (int)(blockDim.x / kWave); ++u) s += red[threadIdx.x][u];
     part[(int64_t)(j0 + threadIdx.x) * gridDim.x + blockIdx.x] = s;
@@ -543,7 +543,7 @@ template <typename T>
 void arnoldi_step(const T* V, int64_t ld, int k, double* hcol, double* h2, double* part1, double* part2,
                   int nblocks, int* flag, hipStream_t s, bool timed, bool reorth) {
   T* w = const_cast<T*>(V) + (int64_t)(k + 1) * ld;
-  const double vb = (double)ld * sizeof(T);
+  (void)timed;  // the inner Arnoldi passes are not a timed class
   // pass 1: columns 0..k+1 (the last one is w itself, giving ||w||^2 in hcol[k+1])
   launch_multi_dot<T, T>(V, ld, k + 2, w, ld, part1, nblocks, hcol, false, s, nullptr);
   launch_multi_axpy<T, T>(V, ld, k + 1, hcol, w, ld, part1, nblocks, s, nullptr);

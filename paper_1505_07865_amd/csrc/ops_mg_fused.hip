@@ -314,8 +314,6 @@ __global__ void __launch_bounds__((FTile<NU, TT>::NT)) k_mg_post(const V* __rest
 }
 
 
-bool fused_level_ok(int dim, int logn, int nu) { return dim == 3 && logn >= 4 && (nu == 1 || nu == 2); }
-
 template <typename V, int TT>
 static void pre_tt(const V* b, V* x, V* bc, int logn, int nf, V c0, V c1, int nu, hipStream_t s, TimerEvents ev) {
   const unsigned tiles = 1u << (3 * (logn - FTile<1, TT>::LT));
