@@ -526,6 +526,8 @@ def ablation(args, torch):
           Schur preconditioner;
       (b) shells of 162 / 642 / 2562 markers in 32^3 / 64^3 / 128^3 (spacing
           2h), steady, N_s = 4, full and lower-triangular;
+    and its non-periodic half in the slit channel (no-slip walls at z = 0
+    and z = 1): (a) for the empty 162-marker shell, steady, and (b);
     fp64 and mixed precision, restart 100, with the solve time."""
     from paper_1505_07865_amd import ibr
     from synthetic import shell_problem
@@ -560,13 +562,27 @@ def ablation(args, torch):
             for prec in ("fp64", "mixed"):
                 rows.append(run(prob, pc, 4, prec, 1e-8))
         print("bench: ablation %s done" % prob.name, file=sys.stderr, flush=True)
+    # the non-periodic half, in the slit channel (no-slip walls at z = 0 and z = 1)
+    prob = shell_problem(args.seed, 32, 2, walls=True)
+    for pc in ("full", "lower"):
+        for ns in (1, 2, 4, 8):
+            rows.append(run(prob, pc, ns, "fp64", 1e-8))
+            rows.append(run(prob, pc, ns, "mixed", 1e-8))
+    print("bench: ablation %s done" % prob.name, file=sys.stderr, flush=True)
+    for level, n in ((2, 32), (3, 64), (4, 128)):
+        prob = shell_problem(args.seed, n, level, walls=True)
+        for pc in ("full", "lower"):
+            for prec in ("fp64", "mixed"):
+                rows.append(run(prob, pc, 4, prec, 1e-8))
+        print("bench: ablation %s done" % prob.name, file=sys.stderr, flush=True)
     best = min((r for r in rows if r["case"].startswith("shell_l2_empty_n32_re0") and r["rtol"] == 1e-8 and
                 r["precision"] == "fp64"), key=lambda r: r["ps_applications"])
     line = {"metric": "P_S^-1 applications to relative residual 1e-8 (solver study, periodic)",
             "value": best["ps_applications"], "unit": "P_S^-1 applications", "n_gpus": 1,
             "higher_is_better": False, "vs_baseline": None, "data": "synthetic",
             "config": {"workload": "icosahedral shells (162/642/2562 markers, spacing 2h, empty or filled), "
-                                   "periodic 32^3/64^3/128^3, steady and Re = 10, restart 100",
+                                   "periodic 32^3/64^3/128^3, steady and Re = 10, and the same shells in the "
+                                   "slit channel, restart 100",
                        "seed": args.seed, "best_case": best},
             "rows": rows}
     print(json.dumps(line), flush=True)

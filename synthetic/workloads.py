@@ -326,7 +326,7 @@ def small_problem(seed: int, dim: int, n: int, nbodies: int = 1, radius_h: float
 
 
 def shell_problem(seed: int = 0, n: int = 32, level: int = 2, filled: bool = False, re: float = 0.0,
-                  spacing_h: float = 2.0) -> Problem:
+                  spacing_h: float = 2.0, walls: bool = False) -> Problem:
     """One sphere in a periodic unit cube: an icosahedral shell of
     10 * 4^level + 2 markers (162 at level 2) with mean marker spacing
     ``spacing_h`` h, optionally filled with concentric shells of the same
@@ -334,11 +334,15 @@ def shell_problem(seed: int = 0, n: int = 32, level: int = 2, filled: bool = Fal
     markers at radii R - 2h, R - 4h, ... and a centre marker when the last
     radius is below 2h).  Centre ~ U[0,1)^3, U ~ U[-1,1]^3.  re = 0: steady
     Stokes, eta = 1, Omega ~ U[-1,1]^3; re > 0: one backward-Euler step of
-    the unsteady system, rho = 1, eta = R/re, dt = 0.5h, Omega = 0."""
+    the unsteady system, rho = 1, eta = R/re, dt = 0.5h, Omega = 0.
+    walls: the slit channel (no-slip walls at z = 0 and z = 1); the centre's
+    z is then drawn so that the shell keeps 2h from both walls."""
     rng = np.random.default_rng(seed)
     h = 1.0 / n
     R = spacing_h * h / icosphere_spacing(level)
     centre = rng.uniform(0.0, 1.0, size=3)
+    if walls:
+        centre[2] = R + 2 * h + centre[2] * (1.0 - 2 * (R + 2 * h))
     shell = icosphere_unit(level)
     pts = [shell * R + centre]
     if filled:
@@ -355,9 +359,12 @@ def shell_problem(seed: int = 0, n: int = 32, level: int = 2, filled: bool = Fal
     else:
         rho, eta, dt = 0.0, 1.0, 0.0
         Om = rng.uniform(-1.0, 1.0, size=(1, 3))
-    return _assemble(3, n, h, rho, eta, dt, [body], centre[None, :], U, Om, [R], 0,
-                     "shell_l%d_%s_n%d_re%g" % (level, "filled" if filled else "empty", n, re),
+    prob = _assemble(3, n, h, rho, eta, dt, [body], centre[None, :], U, Om, [R], 0,
+                     "shell_l%d_%s_n%d_re%g%s" % (level, "filled" if filled else "empty", n, re,
+                                                  "_walls" if walls else ""),
                      meta={"radius_h": R / h, "markers": len(body)})
+    prob.walls = 1 if walls else 0
+    return prob
 
 
 SERVING_GRIDS = [(2, 32), (2, 128), (2, 256), (3, 32), (3, 64), (3, 128)]
