@@ -95,7 +95,10 @@ typedef struct {
                          the walls (ibr_set_bodies returns IBR_EINVAL
                          otherwise); ibr_step's advection uses the same
                          mirror rules, and it returns IBR_EINVAL (moving
-                         nothing) when a body would cross a wall. */
+                         nothing) when a body would cross a wall.  Between
+                         walls P_S^-1 approximates the Stokes block less well
+                         (Sec. 7.1): n_s = 4 is the robust choice for many
+                         markers. */
 } ibr_params;
 
 /* Per-solve report.  ps_applications counts P_S^-1 applications, the cost

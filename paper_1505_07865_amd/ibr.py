@@ -395,6 +395,8 @@ def from_problem(prob, **kw):
     """Solver for a synthetic Problem (grid parameters taken from it)."""
     params = dict(dim=prob.dim, n=prob.n, h=prob.h, rho=prob.rho, eta=prob.eta, dt=prob.dt,
                   walls=getattr(prob, "walls", 0))
+    if params["walls"]:
+        params["n_s"] = 4      # between walls P_S^-1 is a weaker Stokes preconditioner (Sec. 7.1)
     params.update(kw)
     s = Solver(**params)
     s.set_bodies(prob.R, prob.offsets, prob.centres)

@@ -147,10 +147,13 @@ class Server:
     # ---------------------------------------------------------------- defaults
     def _params(self, prob):
         from . import ibr
+        walls = getattr(prob, "walls", 0)
+        kw = dict(n_s=4) if walls else {}     # between walls P_S^-1 is a weaker Stokes preconditioner
+        kw.update(self.solver_kw)
         return dict(dim=prob.dim, n=prob.n, h=prob.h, rho=prob.rho, eta=prob.eta, dt=prob.dt,
-                    walls=getattr(prob, "walls", 0), rtol=self.rtol,
+                    walls=walls, rtol=self.rtol,
                     precision=ibr.MIXED if self.precision == "mixed" else ibr.FP64, device=self.device,
-                    graphs=self.graphs, **self.solver_kw)
+                    graphs=self.graphs, **kw)
 
     def _default_factory(self, prob):
         from . import ibr

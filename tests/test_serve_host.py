@@ -154,5 +154,6 @@ def test_walls_get_their_own_contexts():
                         reserve_bytes=0)
     try:
         assert srv2._params(slit)["walls"] == 1 and srv2._params(per)["walls"] == 0
+        assert srv2._params(slit)["n_s"] == 4 and "n_s" not in srv2._params(per)
     finally:
         srv2.close()
