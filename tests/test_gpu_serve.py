@@ -55,3 +55,25 @@ def test_served_trajectories_equal_alone(precision):
         assert [st["iters"] for st in r["steps"]] == [i["iters"] for i in infos]
         assert all(st["rel_residual"] <= 1e-8 for st in r["steps"])
         assert np.array_equal(r["F"], F) and np.array_equal(r["T"], T)
+
+
+def test_served_mix_with_walls_equals_alone():
+    """Slit-channel requests served among periodic requests of the same grid
+    sizes (their own contexts, N_s = 4 between walls) equal the same requests
+    solved alone, bitwise; so do the periodic ones."""
+    from paper_1505_07865_amd import ibr, serve
+    from synthetic import slit_problem, small_problem
+    probs = [slit_problem(s, dim=3, n=32, nbodies=2, radius_h=3.0) for s in range(2)] + \
+            [small_problem(s, 3, 32, nbodies=2, radius_h=3.0) for s in range(2)] + \
+            [slit_problem(7, dim=2, n=64, nbodies=2, radius_h=4.0)]
+    with serve.Server(precision="mixed", workers=3, reserve_bytes=1 << 30) as srv:
+        futs = [srv.submit(p) for p in probs]
+        res = [f.result() for f in futs]
+    for p, r in zip(probs, res):
+        kw = dict(n_s=4) if p.walls else {}
+        s = ibr.from_problem(p, rtol=1e-8, precision=ibr.MIXED, graphs=0, **kw)
+        info = s.solve()
+        F, T = s.forces()
+        s.close()
+        assert r["info"]["iters"] == info["iters"]
+        assert np.array_equal(r["F"], F) and np.array_equal(r["T"], T)
