@@ -577,10 +577,74 @@ def advection(v, h):
     return out
 
 
-def run(prob, nsteps, **kw):
+def face_velocity(v, a):
+    """``navier.face_velocity`` with the walls' extension: the averaged
+    components read their neighbours across a wall through E."""
+    d = v.shape[0]
+    ks = kinds(d)
+    axa = d - 1 - a
+
+    def nb(x, off, ax, kind):
+        return znbr(x, off, kind) if ax == 0 else pnbr(x, off, ax)
+
+    out = []
+    for b in range(d):
+        if b == a:
+            out.append(v[a])
+        else:
+            axb = d - 1 - b
+            vm = nb(v[b], -1, axa, ks[b])
+            out.append(0.25 * (v[b] + nb(v[b], 1, axb, ks[b]) + vm + nb(vm, 1, axb, ks[b])))
+    return out
+
+
+def _fold_along_z(kind, n):
+    """Index map of E for any integer z index (repeated mirroring has period
+    2n); periodic wrap along the other axes."""
+    def fold(ax, j):
+        if ax != 0:
+            return np.mod(j, n), np.ones(j.shape)
+        jm = np.mod(j, 2 * n)
+        if kind == FACE_DIR:
+            idx = np.where(jm <= n, jm, 2 * n - jm)
+            sgn = np.where(jm < n, 1.0, -1.0)
+            sgn = np.where((jm == 0) | (jm == n), 0.0, sgn)
+            return np.where(idx == n, 0, idx), sgn
+        idx = np.where(jm < n, jm, 2 * n - 1 - jm)
+        sgn = np.where(jm < n, 1.0, -1.0 if kind == CELL_DIR else 1.0)
+        return idx, sgn
+    return fold
+
+
+def departure_values(v, h, dt):
+    """``navier.departure_values`` between the walls: the face velocity with
+    the wall rules, and the interpolation reading the lattice through E along
+    z (a departure point beyond a wall reads the mirror image)."""
+    from . import navier
+    d, n = v.shape[0], v.shape[1]
+    ks = kinds(d)
+    out = np.zeros_like(v)
+    idx = np.indices(v.shape[1:]).astype(np.float64)
+    for a in range(d):
+        u = face_velocity(v, a)
+        sl = [idx[ax] - dt * u[d - 1 - ax] / h for ax in range(d)]
+        out[a] = navier.interp_lattice(v[a], sl, _fold_along_z(ks[a], n))
+    out[d - 1][0] = 0.0
+    return out
+
+
+def advection_sl(v, h, dt):
+    """N = (v - v_departure)/dt between the walls; the normal component's
+    wall rows are 0."""
+    N = (v - departure_values(v, h, dt)) / dt
+    N[v.shape[0] - 1][0] = 0.0
+    return N
+
+
+def run(prob, nsteps, scheme="centred", **kw):
     """Exact constrained solves along a trajectory between the walls (the
-    steps of ``navier.run``: AB2 advection, backward Euler viscosity, bodies
-    translated before each solve)."""
+    steps of ``navier.run``: AB2 advection or semi-Lagrangian transport,
+    backward Euler viscosity, bodies translated before each solve)."""
     from . import navier
     d, n, h = prob.dim, prob.n, prob.h
     v = np.zeros((d,) + (n,) * d)
@@ -591,8 +655,12 @@ def run(prob, nsteps, **kw):
     b = ib.body_of(prob.offsets)
     c0 = prob.rho / prob.dt
     for step in range(nsteps):
-        N_n = advection(v, h)
-        g = navier.rhs(v, N_n, N_prev, prob.rho, prob.dt, first=(step == 0))
+        if scheme == "sl":
+            N_n = advection_sl(v, h, prob.dt)
+            g = navier.rhs(v, N_n, None, prob.rho, prob.dt, first=True)
+        else:
+            N_n = advection(v, h)
+            g = navier.rhs(v, N_n, N_prev, prob.rho, prob.dt, first=(step == 0))
         g[d - 1][0] = 0.0
         R = R + prob.dt * prob.U[b]
         centres = centres + prob.dt * prob.U
