@@ -17,7 +17,8 @@ per seed, 20 steps each from rest) offered at once to the request server,
 with 4 workers whose solves overlap on the device, and with 1 worker (the
 plain solver), in both precisions.
 
-    python bench.py [--steps K] [--warmup W] [--re 10] [--seed 0] [--no-cpu-baseline]
+    python bench.py [--steps K] [--warmup W] [--re 10] [--advection auto|centred|sl] [--seed 0]
+                    [--no-cpu-baseline]
     python bench.py --serving | --ablation | --free | --blocks    (other workloads, one JSON line each)
 """
 import argparse
@@ -56,6 +57,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=18)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--re", type=float, default=10.0)
+    ap.add_argument("--advection", choices=("auto", "centred", "sl"), default="auto",
+                    help="centred advective form with AB2, or semi-Lagrangian transport; auto takes the "
+                         "centred form while the cell Reynolds number Re h/R is at most 8 (where it is stable)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", choices=["both", "mixed", "fp64"], default="both")
@@ -108,12 +112,21 @@ def percentile(xs, q):
     return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
 
 
-def run_precision(prob, prec, steps, warmup, torch):
+def advection_scheme(args):
+    """The advection form for the workload's Reynolds number: the centred
+    form with AB2 needs viscous damping per step and grows without bound at
+    cell Reynolds number Re h/R = Re/6 of about 17 (Re = 100)."""
+    if args.advection != "auto":
+        return args.advection
+    return "centred" if args.re / 6.0 <= 8.0 else "sl"
+
+
+def run_precision(prob, prec, steps, warmup, torch, scheme="centred"):
     from paper_1505_07865_amd import ibr
     # kernels go straight onto the stream (iteration graphs measured no faster,
     # and the live event timers bracket individual launches)
     s = ibr.from_problem(prob, rtol=1e-8, precision=ibr.MIXED if prec == "mixed" else ibr.FP64, device=0,
-                         graphs=0)
+                         graphs=0, advection=ibr.ADVECT_SL if scheme == "sl" else ibr.ADVECT_CENTRED)
     # sampled event timing keeps the instrumentation cost small; enabling
     # again before the timed region resets the counters
     for t in ibr.TIMERS:
@@ -194,7 +207,7 @@ def roofline(timers):
                   "bytes_per_launch": t["bytes"] / t["launches"]}, others
 
 
-def cpu_baseline(prob, nsteps=2):
+def cpu_baseline(prob, nsteps=2, scheme="centred"):
     """The oracle's exact solves of the workload's first time steps, timed on
     the host.  Returns the baseline record and the oracle's solution of the
     last of those steps (the reference the GPU solutions are compared with)."""
@@ -202,7 +215,7 @@ def cpu_baseline(prob, nsteps=2):
     from threadpoolctl import threadpool_limits
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
-        sols = navier.run(prob, nsteps, dense_limit=0, tol=1e-10)
+        sols = navier.run(prob, nsteps, scheme=scheme, dense_limit=0, tol=1e-10)
         dt = time.perf_counter() - t0
     rec = {"value": round(nsteps / dt, 5), "unit": "solves/s", "cores": 1, "kind": "oracle",
            "sample": "exact constrained solves of the workload's first %d time steps (explicit advection "
@@ -229,7 +242,8 @@ def served(args, torch):
         print("bench: served form, %s, %d worker(s), %d trajectories x %d steps" % (prec, workers, len(probs),
                                                                                     nsteps),
               file=sys.stderr, flush=True)
-        with serve.Server(precision=prec, workers=workers) as srv:
+        with serve.Server(precision=prec, workers=workers,
+                          advection=1 if advection_scheme(args) == "sl" else 0) as srv:
             srv.prewarm(probs[:1])
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -621,12 +635,13 @@ def main():
         large(args, torch)
         return
     prob = config2_spheres_ns(args.seed, re=args.re)
+    scheme = advection_scheme(args)
     precs = ["fp64", "mixed"] if args.precision == "both" else [args.precision]
     res = {}
     for p in precs:
         print("bench: %s, %d warmup + %d timed steps" % (p, args.warmup, args.steps), file=sys.stderr,
               flush=True)
-        res[p] = run_precision(prob, p, args.steps, args.warmup, torch)
+        res[p] = run_precision(prob, p, args.steps, args.warmup, torch, scheme)
         print("bench: %s %.2f solves/s, %.1f FGMRES iters/step" % (p, res[p]["solves_per_s"],
                                                                    res[p]["fgmres_iters_mean"]),
               file=sys.stderr, flush=True)
@@ -646,10 +661,10 @@ def main():
         "dtype": "f32 preconditioner + f64 outer" if "mixed" in res else "f64",
         "data": "synthetic",
         "config": {"workload": "3D unsteady NS, periodic 128^3 MAC grid, Re=%g, dt=0.5h, 16 moving spheres "
-                               "R=6h x 110 markers, rtol 1e-8, N_s=2, lower-triangular Schur preconditioner"
-                               % args.re,
+                               "R=6h x 110 markers, rtol 1e-8, N_s=2, lower-triangular Schur preconditioner, "
+                               "%s advection" % (args.re, "semi-Lagrangian" if scheme == "sl" else "centred AB2"),
                    "grid": 128, "bodies": 16, "markers": int(prob.nmarkers), "re": args.re, "seed": args.seed,
-                   "rtol": 1e-8},
+                   "rtol": 1e-8, "advection": scheme},
         "p50_ms": round(head["p50_ms"], 3),
         "p99_ms": round(head["p99_ms"], 3),
         "fgmres_iters_per_step": round(head["fgmres_iters_mean"], 2),
@@ -671,7 +686,7 @@ def main():
         line["served"] = served(args, torch)
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle on the workload's first two steps", file=sys.stderr, flush=True)
-        line["cpu_baseline"], ref = cpu_baseline(prob)
+        line["cpu_baseline"], ref = cpu_baseline(prob, scheme=scheme)
         err = {}
         for p in precs:
             st = res[p]["state_after_2_steps"]

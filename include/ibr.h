@@ -58,6 +58,12 @@ typedef enum { IBR_PC_LOWER = 0, IBR_PC_FULL = 1 } ibr_pc;
  * (the slit channel of Sec. 7; boundary rules of the appendix on physical
  * boundary conditions). */
 typedef enum { IBR_WALLS_NONE = 0, IBR_WALLS_NOSLIP = 1 } ibr_walls;
+/* Explicit advection of the unsteady step (Sec. 3; the paper cites an upwind
+ * scheme without stating it).  CENTRED: the second-order advective form on
+ * the MAC grid with Adams-Bashforth 2.  SL: semi-Lagrangian transport, each
+ * face's value taken from the departure point x - dt u(x) by multilinear
+ * interpolation; unconditionally bounded, first order. */
+typedef enum { IBR_ADVECT_CENTRED = 0, IBR_ADVECT_SL = 1 } ibr_advection;
 
 /* Problem and solver parameters.  Sec. 3.2 (eq. A_def) defines
  * A = (rho/dt) I - eta h^-2 L; rho == 0 selects steady Stokes, where the
@@ -99,6 +105,19 @@ typedef struct {
                          walls P_S^-1 approximates the Stokes block less well
                          (Sec. 7.1): n_s = 4 is the robust choice for many
                          markers. */
+  int advection;      /* IBR_ADVECT_CENTRED (default) or IBR_ADVECT_SL.
+                         CENTRED: N(v) = sum_b vbar^b (v^a_{c+e_b} -
+                         v^a_{c-e_b}) / 2h with vbar^b the average of the four
+                         b-faces around the a-face, and g = (rho/dt) v -
+                         rho (3/2 N^n - 1/2 N^{n-1}) (forward Euler on the
+                         first step); it needs viscous damping per step (cell
+                         Reynolds number |u| h rho / eta of a few) and grows
+                         without bound otherwise.  SL: v_d = v^a interpolated
+                         at x - dt vbar(x) on the a-face lattice (periodic
+                         wrap, E's mirror rules between walls), N = (v - v_d)/dt
+                         so that g = (rho/dt) v_d; stable at any cell Reynolds
+                         number and CFL number.  ibr_advect returns the
+                         selected form's N. */
 } ibr_params;
 
 /* Per-solve report.  ps_applications counts P_S^-1 applications, the cost
@@ -241,7 +260,10 @@ ibr_status ibr_mobility_block(ibr_ctx* ctx, int body, double* M, double* shift);
  * Minv[(dim Np)^2] row-major (Sec. 5.3 dense mobility solve). */
 ibr_status ibr_mobility_inverse(ibr_ctx* ctx, int body, double* Minv);
 
-/* Advection term N(u) of the unsteady step on the MAC grid: N[dim][n^dim]. */
+/* Advection term N(u) of the unsteady step on the MAC grid, host arrays
+ * u[dim][n^dim] in and N[dim][n^dim] out, in the form params.advection
+ * selects (the semi-Lagrangian one uses params.dt; IBR_EINVAL when the
+ * context is steady).  Resets the Adams-Bashforth history of ibr_step. */
 ibr_status ibr_advect(ibr_ctx* ctx, const double* u, double* N);
 
 /* ---- live kernel timing (measurement support) ---- */

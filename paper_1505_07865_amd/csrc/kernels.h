@@ -78,6 +78,8 @@ template <typename TZ, typename TX>
 void launch_combine_from_split(int dim, int logn, const TZ* Z, int64_t ld, int k, const double* y, TX* x, int nf,
                                bool assign, hipStream_t s);
 void launch_advect(int dim, int logn, const double* v, double* N, double inv_2h, hipStream_t s, int walls = 0);
+void launch_advect_sl(int dim, int logn, const double* v, double* N, double dtoh, double inv_dt, hipStream_t s,
+                      int walls = 0);
 void launch_ns_rhs(const double* v, const double* N1, const double* N0, double* g, int64_t len, double rdt,
                    double rho, double w1, double w0, hipStream_t s);
 

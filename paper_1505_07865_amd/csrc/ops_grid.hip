@@ -442,6 +442,96 @@ __global__ void __launch_bounds__(256) k_advect(const double* __restrict__ v, do
   }
 }
 
+// Index and sign that lattice index j (any integer) reads along the walls'
+// axis through the mirror extension: repeated mirroring has period 2n.  A
+// tangential component (cell-centred along the axis) is odd about each wall;
+// the normal component is odd about the wall faces 0 and n, which hold 0.
+__device__ inline int wall_fold(int j, int n, bool normal, double& sign) {
+  const int jm = j & (2 * n - 1);
+  if (normal) {
+    if (jm == 0 || jm == n) {
+      sign = 0.0;
+      return 0;
+    }
+    if (jm < n) return jm;
+    sign = -sign;
+    return 2 * n - jm;
+  }
+  if (jm < n) return jm;
+  sign = -sign;
+  return 2 * n - 1 - jm;
+}
+
+// Semi-Lagrangian advection term N = (v - v_d) / dt.  Each a-face backtracks
+// along the face velocity of the advective form (v^a itself and the four-face
+// averages of the other components) to x - dt u, in lattice units the face
+// index minus dtoh u, and v_d is v^a interpolated there multilinearly on the
+// a-face lattice.  Periodic axes wrap with the power-of-two mask; along the
+// walls' axis the taps read through the mirror extension.  The displacement
+// is clamped to +-2^20 cells so every index stays on the lattice whatever
+// the velocity (a non-finite velocity still yields a non-finite N through
+// v^a at the same face, or at the neighbour that carries it).
+template <int DIM>
+__global__ void __launch_bounds__(256) k_advect_sl(const double* __restrict__ v, double* __restrict__ N, int logn,
+                                                   double dtoh, double inv_dt, int walls) {
+  const int64_t C = (int64_t)1 << (DIM * logn);
+  const int64_t c = xcd_block(gridDim.x) * blockDim.x + threadIdx.x;
+  if (c >= C) return;
+  const int n = 1 << logn;
+  const int mask = n - 1;
+  const Nbr nb = neighbours<DIM>(c, logn);
+  int coord[3];
+  coord[0] = (int)(c & mask);
+  coord[1] = (int)((c >> logn) & mask);
+  coord[2] = DIM == 3 ? (int)(c >> (2 * logn)) : 0;
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) {
+    const double* va = v + a * C;
+    if (walls && a == DIM - 1 && coord[DIM - 1] == 0) {
+      N[a * C + c] = 0.0;
+      continue;
+    }
+    int lo[3];
+    double fr[3];
+#pragma unroll
+    for (int b = 0; b < DIM; ++b) {
+      double ub;
+      if (b == a) {
+        ub = va[c];
+      } else {
+        const double* wv = v + b * C;
+        const int64_t cm = nb.m[a];
+        const Nbr nm = neighbours<DIM>(cm, logn);
+        ub = 0.25 * (wv[c] + wv[nb.p[b]] + wv[cm] + wv[nm.p[b]]);
+      }
+      const double disp = fmin(fmax(dtoh * ub, -1048576.0), 1048576.0);
+      const double sb = (double)coord[b] - disp;
+      const double fl = floor(sb);
+      lo[b] = (int)fl;
+      fr[b] = sb - fl;
+    }
+    double acc = 0.0;
+#pragma unroll
+    for (int corner = 0; corner < (1 << DIM); ++corner) {
+      double w = 1.0, sign = 1.0;
+      int64_t idx = 0;
+#pragma unroll
+      for (int b = DIM - 1; b >= 0; --b) {
+        const int o = (corner >> b) & 1;
+        w *= o ? fr[b] : 1.0 - fr[b];
+        int j = lo[b] + o;
+        if (walls && b == DIM - 1)
+          j = wall_fold(j, n, a == DIM - 1, sign);
+        else
+          j &= mask;
+        idx = (idx << logn) | j;
+      }
+      acc += w * sign * va[idx];
+    }
+    N[a * C + c] = (va[c] - acc) * inv_dt;
+  }
+}
+
 // g = (rho/dt) v - rho (w1 N1 + w0 N0)   (N0 may be null)
 __global__ void k_ns_rhs(const double* __restrict__ v, const double* __restrict__ N1,
                          const double* __restrict__ N0, double* __restrict__ g, int64_t len, double rdt,
@@ -581,6 +671,15 @@ void launch_advect(int dim, int logn, const double* v, double* N, double inv_2h,
     hipLaunchKernelGGL((k_advect<3>), dim3(nblk(C)), dim3(256), 0, s, v, N, logn, inv_2h, walls);
   else
     hipLaunchKernelGGL((k_advect<2>), dim3(nblk(C)), dim3(256), 0, s, v, N, logn, inv_2h, walls);
+}
+
+void launch_advect_sl(int dim, int logn, const double* v, double* N, double dtoh, double inv_dt, hipStream_t s,
+                      int walls) {
+  const int64_t C = (int64_t)1 << (dim * logn);
+  if (dim == 3)
+    hipLaunchKernelGGL((k_advect_sl<3>), dim3(nblk(C)), dim3(256), 0, s, v, N, logn, dtoh, inv_dt, walls);
+  else
+    hipLaunchKernelGGL((k_advect_sl<2>), dim3(nblk(C)), dim3(256), 0, s, v, N, logn, dtoh, inv_dt, walls);
 }
 
 void launch_ns_rhs(const double* v, const double* N1, const double* N0, double* g, int64_t len, double rdt,

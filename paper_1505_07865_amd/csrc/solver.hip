@@ -497,6 +497,8 @@ void validate(const ibr_params* p) {
       p->mg_coarse > 256)
     throw Status(IBR_EINVAL, "bad multigrid sweep counts");
   if (p->walls != IBR_WALLS_NONE && p->walls != IBR_WALLS_NOSLIP) throw Status(IBR_EINVAL, "bad walls");
+  if (p->advection != IBR_ADVECT_CENTRED && p->advection != IBR_ADVECT_SL)
+    throw Status(IBR_EINVAL, "bad advection");
 }
 
 MobParams mob_params(const ibr_ctx* c) {
@@ -805,6 +807,8 @@ void ibr_default_params(ibr_params* p) {
   p->device = 0;
   p->stream = nullptr;
   p->graphs = 1;
+  p->walls = IBR_WALLS_NONE;
+  p->advection = IBR_ADVECT_CENTRED;
 }
 
 const char* ibr_status_string(int st) {
@@ -1161,13 +1165,19 @@ ibr_status ibr_step(ibr_ctx* c, ibr_info* info) {
     const int d = c->dim;
     const int64_t len = (int64_t)d * c->C;
     if (!c->have_solution) launch_fill<double>(c->Xs, c->NV, 0.0, s);
-    // explicit advection (AB2, forward Euler on the first step)
-    launch_advect(d, c->logn, c->Xs, c->Ncur, 0.5 / c->h, s, c->walls ? 1 : 0);
+    // explicit advection: semi-Lagrangian transport (g = (rho/dt) v_d), or the
+    // centred form with AB2 (forward Euler on the first step)
     const double rho = c->p.rho;
-    if (c->have_prev)
-      launch_ns_rhs(c->Xs, c->Ncur, c->Nprev, c->Bs, len, c->c0, rho, 1.5, -0.5, s);
-    else
+    if (c->p.advection == IBR_ADVECT_SL) {
+      launch_advect_sl(d, c->logn, c->Xs, c->Ncur, c->p.dt / c->h, 1.0 / c->p.dt, s, c->walls ? 1 : 0);
       launch_ns_rhs(c->Xs, c->Ncur, nullptr, c->Bs, len, c->c0, rho, 1.0, 0.0, s);
+    } else {
+      launch_advect(d, c->logn, c->Xs, c->Ncur, 0.5 / c->h, s, c->walls ? 1 : 0);
+      if (c->have_prev)
+        launch_ns_rhs(c->Xs, c->Ncur, c->Nprev, c->Bs, len, c->c0, rho, 1.5, -0.5, s);
+      else
+        launch_ns_rhs(c->Xs, c->Ncur, nullptr, c->Bs, len, c->c0, rho, 1.0, 0.0, s);
+    }
     launch_fill<double>(c->Bs + len, c->C, 0.0, s);
     // move the bodies, re-bin the markers (the mobility blocks are translation invariant)
     launch_move_markers(d, c->N, c->nb, c->R, c->X, c->body_d, c->U, c->p.dt, c->L, s);
@@ -1466,8 +1476,13 @@ ibr_status ibr_advect(ibr_ctx* c, const double* u, double* N) {
     IBR_HIP(hipSetDevice(c->p.device));
     const int d = c->dim;
     hipStream_t s = c->stream;
+    if (c->p.advection == IBR_ADVECT_SL && c->steady)
+      throw Status(IBR_EINVAL, "semi-Lagrangian advection needs dt > 0 (unsteady)");
     IBR_HIP(hipMemcpyAsync(c->Nprev, u, (size_t)d * c->C * sizeof(double), hipMemcpyHostToDevice, s));
-    launch_advect(d, c->logn, c->Nprev, c->Ncur, 0.5 / c->h, s, c->walls ? 1 : 0);
+    if (c->p.advection == IBR_ADVECT_SL)
+      launch_advect_sl(d, c->logn, c->Nprev, c->Ncur, c->p.dt / c->h, 1.0 / c->p.dt, s, c->walls ? 1 : 0);
+    else
+      launch_advect(d, c->logn, c->Nprev, c->Ncur, 0.5 / c->h, s, c->walls ? 1 : 0);
     IBR_HIP(hipMemcpyAsync(N, c->Ncur, (size_t)d * c->C * sizeof(double), hipMemcpyDeviceToHost, s));
     c->have_prev = false;
     sync(c);
