@@ -15,7 +15,9 @@ plain fp64 solver runs the same trajectory for comparison.  The ``served``
 object gives the served form: 8 independent simulations of the workload (one
 per seed, 20 steps each from rest) offered at once to the request server,
 with 4 workers whose solves overlap on the device, and with 1 worker (the
-plain solver), in both precisions.
+plain solver), in both precisions.  The ``second_re`` object runs the same
+workload at Re = 100, where the advection is the semi-Lagrangian transport
+(the centred form with AB2 is unstable at that cell Reynolds number).
 
     python bench.py [--steps K] [--warmup W] [--re 10] [--advection auto|centred|sl] [--seed 0]
                     [--no-cpu-baseline]
@@ -72,6 +74,9 @@ def parse():
     ap.add_argument("--served-trajectories", type=int, default=8,
                     help="served form: independent simulations of the workload offered at once")
     ap.add_argument("--no-served", action="store_true", help="skip the served-form leg")
+    ap.add_argument("--second-re", type=float, default=100.0,
+                    help="the workload's other Reynolds number, run after the headline one in both precisions "
+                         "(0 = skip)")
     ap.add_argument("--free", action="store_true",
                     help="free-kinematics workload instead: a sedimenting suspension of 16 free spheres at 128^3")
     ap.add_argument("--free-solves", type=int, default=5, help="free kinematics: timed solves per precision")
@@ -223,6 +228,36 @@ def cpu_baseline(prob, nsteps=2, scheme="centred"):
                      "%s CG iterations), %.1f s single-threaded NumPy" %
                      (nsteps, "+".join(str(q.cg_iters) for q in sols), dt)}
     return rec, sols[-1]
+
+
+def second_re(args, torch):
+    """The same workload at its other Reynolds number (both precisions, the
+    same steps), with the advection form chosen for it and the error of the
+    state after two steps against the oracle's exact solution."""
+    from synthetic import config2_spheres_ns
+    re = args.second_re
+    scheme = advection_scheme(argparse.Namespace(advection=args.advection, re=re))
+    prob = config2_spheres_ns(args.seed, re=re)
+    out = {"re": re, "advection": scheme}
+    res = {}
+    for p in ("fp64", "mixed"):
+        print("bench: Re %g, %s, %d warmup + %d timed steps" % (re, p, args.warmup, args.steps), file=sys.stderr,
+              flush=True)
+        res[p] = run_precision(prob, p, args.steps, args.warmup, torch, scheme)
+        out[p] = {"solves_per_s": round(res[p]["solves_per_s"], 3), "p50_ms": round(res[p]["p50_ms"], 3),
+                  "p99_ms": round(res[p]["p99_ms"], 3),
+                  "fgmres_iters_mean": round(res[p]["fgmres_iters_mean"], 2),
+                  "max_rel_residual": float("%.4g" % res[p]["max_rel_residual"])}
+    out["mixed_over_fp64"] = round(res["mixed"]["solves_per_s"] / res["fp64"]["solves_per_s"], 3)
+    if not args.no_cpu_baseline and args.warmup >= 2:
+        print("bench: the oracle's first two steps at Re %g" % re, file=sys.stderr, flush=True)
+        _, ref = cpu_baseline(prob, scheme=scheme)
+        out["err_vs_oracle"] = {
+            p: {"u": float("%.3g" % (np.linalg.norm(res[p]["state_after_2_steps"]["u"] - ref.v) /
+                                     np.linalg.norm(ref.v))),
+                "F": float("%.3g" % (np.linalg.norm(res[p]["state_after_2_steps"]["F"] - ref.F) /
+                                     np.linalg.norm(ref.F)))} for p in res}
+    return out
 
 
 def served(args, torch):
@@ -682,6 +717,8 @@ def main():
                    if k not in ("timers", "state_after_2_steps")}
     if "mixed" in res and "fp64" in res:
         line["mixed_over_fp64"] = round(res["mixed"]["solves_per_s"] / res["fp64"]["solves_per_s"], 3)
+    if args.precision == "both" and args.second_re > 0 and args.second_re != args.re:
+        line["second_re"] = second_re(args, torch)
     if args.precision == "both" and not args.no_served:
         line["served"] = served(args, torch)
     if not args.no_cpu_baseline:
