@@ -1,7 +1,8 @@
 """Full-size GPU runs checked against the oracle through properties that hold
 at any size (the oracle's own operator, not its solve, except where noted).
 
-* 3D 128^3 unsteady workload (16 spheres x 110 markers, Re = 10), in the
+* 3D 128^3 unsteady workload (16 spheres x 110 markers; Re = 10 with the
+  centred advection, Re = 100 with the semi-Lagrangian one), in the
   launch configuration the benchmark times (mixed precision, rtol 1e-8,
   direct stream launches): for every step, the true residual of the GPU
   solution in the system of that step (the oracle's MAC stencils, S, J and
@@ -32,11 +33,13 @@ def _true_relres(sysm, sol, g, W):
     return rn / bn
 
 
-def test_ns128_steps_true_residual():
+@pytest.mark.parametrize("re,scheme", [(10.0, "centred"), (100.0, "sl")])
+def test_ns128_steps_true_residual(re, scheme):
     from paper_1505_07865_amd import ibr
-    prob = config2_spheres_ns(0, re=10.0)
-    print("128^3 unsteady, 1760 markers, mixed, 3 steps", flush=True)
-    s = ibr.from_problem(prob, rtol=1e-8, precision=ibr.MIXED, graphs=0)
+    prob = config2_spheres_ns(0, re=re)
+    print("128^3 unsteady, Re %g, %s advection, 1760 markers, mixed, 3 steps" % (re, scheme), flush=True)
+    s = ibr.from_problem(prob, rtol=1e-8, precision=ibr.MIXED, graphs=0,
+                         advection=ibr.ADVECT_SL if scheme == "sl" else ibr.ADVECT_CENTRED)
     b = ib.body_of(prob.offsets)
     d, n = prob.dim, prob.n
     v = np.zeros((d,) + (n,) * d)
@@ -48,8 +51,12 @@ def test_ns128_steps_true_residual():
         t = (step + 1) * prob.dt
         assert np.abs(ib.min_image(R - np.mod(prob.R + t * prob.U[b], prob.L), prob.L)).max() < 1e-12
         assert np.abs(ib.min_image(X - np.mod(prob.centres + t * prob.U, prob.L), prob.L)).max() < 1e-12
-        N_n = navier.advection(v, prob.h)
-        g = navier.rhs(v, N_n, N_prev, prob.rho, prob.dt, first=(step == 0))
+        if scheme == "sl":
+            N_n = navier.advection_sl(v, prob.h, prob.dt)
+            g = navier.rhs(v, N_n, None, prob.rho, prob.dt, first=True)
+        else:
+            N_n = navier.advection(v, prob.h)
+            g = navier.rhs(v, N_n, N_prev, prob.rho, prob.dt, first=(step == 0))
         sysm = constrained.System.from_problem(prob, R=R)
         V = ib.marker_velocities(R, prob.offsets, X, prob.U, prob.Omega, prob.L)
         rr = _true_relres(sysm, sol, g, -V)
