@@ -21,7 +21,8 @@ workload at Re = 100, where the advection is the semi-Lagrangian transport
 
     python bench.py [--steps K] [--warmup W] [--re 10] [--advection auto|centred|sl] [--seed 0]
                     [--no-cpu-baseline]
-    python bench.py --serving | --ablation | --free | --blocks    (other workloads, one JSON line each)
+    python bench.py --serving | --ablation | --free | --blocks | --walls | --large | --small
+                                                                 (other workloads, one JSON line each)
 """
 import argparse
 import json
@@ -86,6 +87,10 @@ def parse():
     ap.add_argument("--large", action="store_true",
                     help="the 256^3 configuration (100 spheres, steady), mixed and fp64 solves")
     ap.add_argument("--large-solves", type=int, default=2, help="large: timed solves per precision")
+    ap.add_argument("--small", action="store_true",
+                    help="the 2D 64^2 disk and 3D 64^3 sphere configurations, per seed, beside the oracle")
+    ap.add_argument("--small-seeds", type=int, default=5, help="small: seeds 0 .. K-1 per configuration")
+    ap.add_argument("--small-solves", type=int, default=20, help="small: timed solves per seed and precision")
     ap.add_argument("--blocks", action="store_true",
                     help="per-body mobility set-up of the 256^3 configuration (100 blocks of 600 x 600, fp64 MFMA)")
     ap.add_argument("--block-reps", type=int, default=5, help="blocks: timed set-ups")
@@ -533,6 +538,79 @@ def large(args, torch):
     print(json.dumps(line), flush=True)
 
 
+def small(args, torch):
+    """The two small configurations, every seed: the 2D disk (64^2, eta = 1,
+    steady, one disk of radius 8h with 25 markers, U = (1, 0); fp64 to rtol
+    1e-10) and the 3D sphere (64^3, steady, one sphere of radius 8h with 200
+    markers, U, Omega ~ U[-1,1]^3; fp64 and mixed to rtol 1e-8).  Per seed and
+    precision: the context's set-up and one untimed solve, then timed solves
+    from a zero initial guess (host clock around each synchronous solve,
+    captured iteration graphs as a caller gets them by default); the error of
+    the solution against the oracle's exact solve (dense mobility solve for
+    the disk, CG to 1e-11 for the sphere), itself timed on the host
+    (single-threaded NumPy).  The disk's drag F_x/(eta V) is reported beside
+    the periodic drag law at the geometric radius."""
+    from oracle import constrained, hasimoto
+    from paper_1505_07865_amd import ibr
+    from synthetic import config0_disk2d, config1_sphere3d
+    from threadpoolctl import threadpool_limits
+    cases = (("disk2d_64", config0_disk2d, ("fp64",), 1e-10), ("sphere3d_64", config1_sphere3d, ("fp64", "mixed"), 1e-8))
+    out = {}
+    for name, make, precs, rtol in cases:
+        rec = {"rtol": rtol, "seeds": []}
+        for seed in range(args.small_seeds):
+            prob = make(seed)
+            with threadpool_limits(limits=1):
+                t0 = time.perf_counter()
+                ex = constrained.solve_problem(prob, **({} if prob.dim == 2 else dict(dense_limit=0, tol=1e-11)))
+                t_or = time.perf_counter() - t0
+            srec = {"seed": seed, "markers": int(prob.nmarkers), "oracle_ms": round(t_or * 1e3, 2)}
+            if prob.dim == 2:
+                srec["drag_oracle"] = round(float(ex.F[0, 0]), 4)
+            for prec in precs:
+                s = ibr.from_problem(prob, rtol=rtol, precision=ibr.MIXED if prec == "mixed" else ibr.FP64)
+                s.solve()
+                wall, infos = [], []
+                for _ in range(args.small_solves):
+                    torch.cuda.synchronize()
+                    t1 = time.perf_counter()
+                    infos.append(s.solve())
+                    wall.append((time.perf_counter() - t1) * 1e3)
+                sol = s.solution()
+                s.close()
+                r = {"solves_per_s": round(len(wall) / (sum(wall) / 1e3), 2),
+                     "p50_ms": round(percentile(wall, 50), 3), "p99_ms": round(percentile(wall, 99), 3),
+                     "iters": infos[-1]["iters"], "ps_applications": infos[-1]["ps_applications"],
+                     "max_rel_residual": float("%.4g" % max(i["rel_residual"] for i in infos)),
+                     "err_vs_oracle": {"u": float("%.3g" % (np.linalg.norm(sol.u - ex.v) / np.linalg.norm(ex.v))),
+                                       "F": float("%.3g" % (np.linalg.norm(sol.F - ex.F) / np.linalg.norm(ex.F)))}}
+                if prob.dim == 2:
+                    r["drag"] = round(float(sol.F[0, 0]), 4)
+                srec[prec] = r
+                print("bench: %s seed %d %s: %.1f solves/s, %d iterations, err u %.2g" %
+                      (name, seed, prec, r["solves_per_s"], r["iters"], r["err_vs_oracle"]["u"]),
+                      file=sys.stderr, flush=True)
+            rec["seeds"].append(srec)
+        for prec in precs:
+            rates = [x[prec]["solves_per_s"] for x in rec["seeds"]]
+            rec[prec + "_solves_per_s_mean"] = round(sum(rates) / len(rates), 2)
+        if "mixed" in precs:
+            rec["mixed_over_fp64"] = round(rec["mixed_solves_per_s_mean"] / rec["fp64_solves_per_s_mean"], 3)
+        if name.startswith("disk"):
+            rec["drag_law_at_geometric_radius"] = round(hasimoto.drag2d(8.0 / 64, 1.0), 4)
+        out[name] = rec
+    line = {"metric": "solves/s + p50/p99 latency, small steady configurations (2D 64^2 disk, 3D 64^3 sphere)",
+            "value": out["sphere3d_64"]["mixed_solves_per_s_mean"], "unit": "solves/s", "n_gpus": 1,
+            "higher_is_better": True, "vs_baseline": None, "dtype": "f64 (disk); f32 preconditioner + f64 outer "
+            "(sphere value)", "data": "synthetic",
+            "config": {"workload": "2D 64^2 disk R=8h x 25 markers (fp64, rtol 1e-10) and 3D 64^3 sphere R=8h x "
+                                   "200 markers (fp64 and mixed, rtol 1e-8), steady, seeds 0-%d" %
+                                   (args.small_seeds - 1), "solves": args.small_solves},
+            "cpu_baseline_kind": "oracle exact solve (Fourier Stokes + dense or CG mobility solve), single thread",
+            "cases": out}
+    print(json.dumps(line), flush=True)
+
+
 def blocks(args, torch):
     """Per-body mobility set-up (assembly, shifted Cholesky on fp64 MFMA
     tiles, triangular inverse, M~^-1 = X^T X) for the 256^3 configuration's
@@ -668,6 +746,9 @@ def main():
         return
     if args.large:
         large(args, torch)
+        return
+    if args.small:
+        small(args, torch)
         return
     prob = config2_spheres_ns(args.seed, re=args.re)
     scheme = advection_scheme(args)
