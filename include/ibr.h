@@ -178,9 +178,11 @@ ibr_status ibr_set_rhs_dev(ibr_ctx* ctx, const void* g, const void* hp);
  * != 0 starts from the context's previous solution.  info may be NULL. */
 ibr_status ibr_solve(ibr_ctx* ctx, int warm_start, ibr_info* info);
 
-/* One unsteady step (rho > 0): explicit advection right-hand side
- * (Adams-Bashforth 2, forward Euler on the first step), markers moved by
- * dt U_p, constrained solve warm-started from the previous step's solution.
+/* One unsteady step (rho > 0): explicit advection right-hand side in the
+ * form params.advection selects (centred with Adams-Bashforth 2, forward
+ * Euler on the first step; or semi-Lagrangian transport, g = (rho/dt) v_d),
+ * markers moved by dt U_p, constrained solve warm-started from the previous
+ * step's solution (Sec. 3).
  * Bodies translate only: IBR_EINVAL if some Omega is nonzero.  With walls,
  * IBR_EINVAL (nothing moved) if a body's markers would reach a wall. */
 ibr_status ibr_step(ibr_ctx* ctx, ibr_info* info);
