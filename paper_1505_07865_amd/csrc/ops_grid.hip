@@ -188,9 +188,13 @@ struct Group {
     H = C >> 1;
     const int hl = logn - 1;
     const int mask = (1 << logn) - 1, hmask = (1 << hl) - 1;
-    const int per_colour = H >> 2;
-    const int c = t >= per_colour ? 1 : 0;
-    const int u = t - c * per_colour;
+    // the colours alternate every wavefront (lb = log2 of min(64, groups per
+    // colour)), so one workgroup takes both colours of the same rows: what a
+    // group reads of the other colour is what its neighbour wavefront owns,
+    // still in cache, instead of a second pass over the field
+    const int lb = DIM * logn - 3 < 6 ? DIM * logn - 3 : 6;
+    const int c = (t >> lb) & 1;
+    const int u = ((t >> (lb + 1)) << lb) | (t & ((1 << lb) - 1));
     const int m0 = (u & ((1 << (hl - 2)) - 1)) << 2;
     const int row = u >> (hl - 2);
     const int j = row & mask;
