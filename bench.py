@@ -37,13 +37,17 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# HBM bytes per launch of a timed kernel class, from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE (KiB per dispatch, scaled by the same counters read on a plain
-# 1 GiB copy), averaged over the launches of one step.  A figure holds only
-# for the kernel source it was taken on: the digest of that file is checked
-# and the figure dropped (null) once the source differs.
+# HBM bytes per launch of a timed kernel class, from two rocprofv3 --pmc runs:
+# the L2's read requests to memory by size (TCC_EA0_RDREQ_32B/_64B/_128B x
+# 32/64/128 bytes), then its write requests (TCC_EA0_WRREQ_64B x 64 + the rest
+# x 32), averaged over the launches of one step.  On a plain 1 GiB device copy
+# both read 1.0000 of the bytes moved.  (FETCH_SIZE takes TCC_BUBBLE as its
+# 128-byte count, which reads half of the 128-byte requests here, so no single
+# scale factor fits kernels with different request sizes.)  A figure holds
+# only for the kernel source it was taken on: the digest of that file is
+# checked and the figure dropped (null) once the source differs.
 MEASURED_TRAFFIC = {
-    "rb_fine": {"bytes_per_launch": 25979907.0, "file": "paper_1505_07865_amd/csrc/ops_mg.hip",
+    "rb_fine": {"bytes_per_launch": 27426500.0, "file": "paper_1505_07865_amd/csrc/ops_mg.hip",
                 "sha256_16": "d00979b7fb12a1fb", "summary": "profiles/rb_fine_128cube_mixed_hbm_counters.md"},
 }
 # strides coprime with the launch pattern (12 finest-level sweeps per P_S^-1, 2 V-cycle calls
