@@ -117,12 +117,13 @@ def rhs(v_n, N_n, N_nm1, rho, dt, first):
     return (rho / dt) * v_n - rho * (1.5 * N_n - 0.5 * N_nm1)
 
 
-def run(prob, nsteps, scheme="centred", **kw):
+def run(prob, nsteps, scheme="centred", v0=None, **kw):
     """Exact constrained solves along the trajectory; returns the list of
     Solutions.  scheme: "centred" (advective form, AB2) or "sl"
-    (semi-Lagrangian transport, g = (rho/dt) v_departure)."""
+    (semi-Lagrangian transport, g = (rho/dt) v_departure).  v0: velocity at
+    t = 0 ([d, n..]; default: the fluid at rest)."""
     d, n, h = prob.dim, prob.n, prob.h
-    v = np.zeros((d,) + (n,) * d)
+    v = np.zeros((d,) + (n,) * d) if v0 is None else np.array(v0, dtype=np.float64)
     N_prev = None
     R = prob.R.copy()
     centres = prob.centres.copy()
