@@ -18,8 +18,12 @@ and for k != 0:  pi_hat = (A_hat hp_hat + D_hat . f_hat) / (D_hat . G_hat),
 At k = 0 the pressure mean is set to zero; the velocity mean is f_hat(0)/A_hat(0)
 when A is invertible and zero for steady Stokes (the restricted inverse of
 Sec. 5.1, acting on mean-zero data and returning mean-zero data).
+
+The transforms are SciPy's (pocketfft); they run on as many threads as the
+caller's ``scipy.fft.set_workers`` context gives (one by default).
 """
 import numpy as np
+import scipy.fft as sfft
 
 
 def _symbols(n, d, h):
@@ -57,20 +61,20 @@ def solve(f, hp, c0, eta, h, d):
     zero = DG == 0.0
     DG_safe = np.where(zero, 1.0, DG)
 
-    fh = np.fft.rfftn(f, axes=gaxes)
+    fh = sfft.rfftn(f, axes=gaxes)
     num = 0.0
     for a in range(d):
         num = num + Dh[a] * np.take(fh, a, axis=cax)
     if hp is not None:
-        num = num + Ah * np.fft.rfftn(hp, axes=tuple(range(hp.ndim - d, hp.ndim)))
+        num = num + Ah * sfft.rfftn(hp, axes=tuple(range(hp.ndim - d, hp.ndim)))
     ph = np.where(zero, 0.0, num / DG_safe)
     singular = Ah == 0.0
     A_safe = np.where(singular, 1.0, Ah)
     vh = np.stack([np.where(singular, 0.0, (np.take(fh, a, axis=cax) - Gh[a] * ph) / A_safe)
                    for a in range(d)], axis=cax)
     shape = f.shape[-d:]
-    v = np.fft.irfftn(vh, s=shape, axes=gaxes)
-    p = np.fft.irfftn(ph, s=shape, axes=tuple(range(ph.ndim - d, ph.ndim)))
+    v = sfft.irfftn(vh, s=shape, axes=gaxes)
+    p = sfft.irfftn(ph, s=shape, axes=tuple(range(ph.ndim - d, ph.ndim)))
     return v, p
 
 
@@ -81,6 +85,6 @@ def helmholtz_solve(b, c0, c1):
     th = _symbols(n, d, 1.0)
     sigma = sum(4.0 * np.sin(t / 2.0) ** 2 for t in th)
     sym = c0 + c1 * sigma
-    bh = np.fft.rfftn(b)
+    bh = sfft.rfftn(b)
     xh = np.where(sym == 0.0, 0.0, bh / np.where(sym == 0.0, 1.0, sym))
-    return np.fft.irfftn(xh, s=b.shape, axes=tuple(range(d)))
+    return sfft.irfftn(xh, s=b.shape, axes=tuple(range(d)))

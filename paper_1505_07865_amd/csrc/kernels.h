@@ -188,10 +188,12 @@ template <typename TL, typename TY>
 void launch_spread(int dim, int logn, int tile_log, int grid_cap, const int* active_list, const int* nactive,
                    const int* offsets, const int* perm, MarkerTaps taps, const TL* lam, TY* y, double scale,
                    hipStream_t s, bool split = false);
-// out[i][a] = alpha * (J v)[i][a] + beta * add[i][a]   (add may be null)
+// out[i][a] = alpha * (J (v - vshift))[i][a] + beta * add[i][a]   (add may be
+// null; vshift, if not null, is a constant per component a, vshift[a]: the
+// kernel weights sum to one, so J of a constant is that constant)
 template <typename TV>
 void launch_interp(int dim, int logn, int N, MarkerTaps taps, const TV* v, double alpha, const double* add,
-                   double beta, double* out, hipStream_t s);
+                   double beta, double* out, hipStream_t s, const double* vshift = nullptr);
 void launch_lambda_sums(int dim, int N, const double* lam, double* part, double* out, double scale,
                         hipStream_t s);
 void launch_body_force_torque(int dim, int nb, const int* offsets, const double* R, const double* centres,
@@ -221,10 +223,13 @@ void arnoldi_step(const T* V, int64_t ld, int k, double* hcol, double* h2, doubl
 template <typename T>
 void dcgs2_step(T* V, int64_t ld, int64_t len, int k, double* H, int ldh, double* G, double* coef, double* part,
                 int nblocks, double* cs, double* sn, double* g, double* resid, hipStream_t s, bool timed);
-// x += sum_j y[j] Z_j  (Z in TZ, x in TX); with assign, x = sum_j y[j] Z_j
+// x += sum_j y[j] Z_j  (Z in TZ, x in TX); with assign, x = sum_j y[j] Z_j.
+// With zmean (stride 4 per column), the first dim blocks of C entries of
+// column j are taken as Z_j - zmean[4j + a]: the velocity components of the
+// stored directions with their fp64 means removed.
 template <typename TZ, typename TX>
 void launch_combine(const TZ* Z, int64_t ld, int k, const double* y, TX* x, int64_t len, hipStream_t s,
-                    bool assign = false);
+                    bool assign = false, const double* zmean = nullptr, int64_t C = 0, int dim = 0);
 // y[0..ns) = argmin || r - sum_j y_j W_j ||  (W_j = W + j*ld, ns in 1..3) from the
 // normal equations: one reduction pass over W and r, one single-block solve.
 // part needs (ns(ns+1)/2 + ns) * nblocks doubles.

@@ -367,7 +367,7 @@ template <typename TV>
 __global__ void __launch_bounds__(256) k_interp(int dim, int logn, int N, const int* __restrict__ tbase,
                                                 const double* __restrict__ tw, const TV* __restrict__ v,
                                                 double alpha, const double* __restrict__ add, double beta,
-                                                double* __restrict__ out) {
+                                                double* __restrict__ out, const double* __restrict__ vshift) {
   const int wave = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
   const int lane = threadIdx.x & (kWave - 1);
   if (wave >= N) return;
@@ -394,6 +394,7 @@ __global__ void __launch_bounds__(256) k_interp(int dim, int logn, int N, const 
     }
     val = wave_sum(val);
     if (lane == 0) {
+      if (vshift) val -= vshift[a];
       double o = alpha * val;
       if (add) o += beta * add[m * dim + a];
       out[m * dim + a] = o;
@@ -524,16 +525,16 @@ template void launch_spread<double, float>(int, int, int, int, const int*, const
 
 template <typename TV>
 void launch_interp(int dim, int logn, int N, MarkerTaps taps, const TV* v, double alpha, const double* add,
-                   double beta, double* out, hipStream_t s) {
+                   double beta, double* out, hipStream_t s, const double* vshift) {
   if (N <= 0) return;
   const int64_t threads = (int64_t)N * kWave;
   hipLaunchKernelGGL((k_interp<TV>), dim3(nblk(threads)), dim3(256), 0, s, dim, logn, N, taps.base, taps.w64, v,
-                     alpha, add, beta, out);
+                     alpha, add, beta, out, vshift);
 }
 template void launch_interp<double>(int, int, int, MarkerTaps, const double*, double, const double*, double,
-                                    double*, hipStream_t);
+                                    double*, hipStream_t, const double*);
 template void launch_interp<float>(int, int, int, MarkerTaps, const float*, double, const double*, double,
-                                   double*, hipStream_t);
+                                   double*, hipStream_t, const double*);
 
 void launch_lambda_sums(int dim, int N, const double* lam, double* part, double* out, double scale,
                         hipStream_t s) {

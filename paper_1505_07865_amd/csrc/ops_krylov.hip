@@ -82,11 +82,17 @@ __global__ void __launch_bounds__(256) k_multi_axpy(const TV* __restrict__ V, in
 template <typename TZ, typename TX>
 __global__ void __launch_bounds__(256) k_combine(const TZ* __restrict__ Z, int64_t ld, int k,
                                                  const double* __restrict__ y, TX* __restrict__ x, int64_t len,
-                                                 int assign) {
+                                                 int assign, const double* __restrict__ zmean, int64_t C, int dim) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += stride) {
     double acc = assign ? 0.0 : (double)x[i];
     for (int j = 0; j < k; ++j) acc += y[j] * (double)Z[(int64_t)j * ld + i];
+    if (zmean && i < dim * C) {
+      const int a = (int)(i >= C) + (int)(i >= 2 * C);
+      double sh = 0.0;
+      for (int j = 0; j < k; ++j) sh += y[j] * zmean[4 * j + a];
+      acc -= sh;
+    }
     x[i] = (TX)acc;
   }
 }
@@ -564,18 +570,19 @@ template void arnoldi_step<float>(const float*, int64_t, int, double*, double*, 
 
 template <typename TZ, typename TX>
 void launch_combine(const TZ* Z, int64_t ld, int k, const double* y, TX* x, int64_t len, hipStream_t s,
-                    bool assign) {
+                    bool assign, const double* zmean, int64_t C, int dim) {
   if (k <= 0) return;
   unsigned g = nblk(len);
   if (g > 4096) g = 4096;
-  hipLaunchKernelGGL((k_combine<TZ, TX>), dim3(g), dim3(256), 0, s, Z, ld, k, y, x, len, assign ? 1 : 0);
+  hipLaunchKernelGGL((k_combine<TZ, TX>), dim3(g), dim3(256), 0, s, Z, ld, k, y, x, len, assign ? 1 : 0, zmean, C,
+                     dim);
 }
 template void launch_combine<double, double>(const double*, int64_t, int, const double*, double*, int64_t,
-                                             hipStream_t, bool);
+                                             hipStream_t, bool, const double*, int64_t, int);
 template void launch_combine<float, double>(const float*, int64_t, int, const double*, double*, int64_t,
-                                            hipStream_t, bool);
+                                            hipStream_t, bool, const double*, int64_t, int);
 template void launch_combine<float, float>(const float*, int64_t, int, const double*, float*, int64_t,
-                                           hipStream_t, bool);
+                                           hipStream_t, bool, const double*, int64_t, int);
 
 template <typename T>
 void launch_gram_solve(const T* W, int64_t ld, int ns, const T* r, int64_t len, double* part, int nblocks,

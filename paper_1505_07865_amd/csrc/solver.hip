@@ -119,6 +119,10 @@ struct ibr_ctx {
   void* Zb = nullptr;  // double or float
   double *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr, *y = nullptr, *resid = nullptr, *beta = nullptr,
          *hc2 = nullptr, *part = nullptr, *part2 = nullptr, *G = nullptr, *coef = nullptr;
+  // steady periodic: fp64 mean of each stored direction's velocity components
+  // (column k at zmean + 4k); the directions enter K and the solution with
+  // these means removed, so <v> = 0 holds in fp64 whatever Z's precision
+  double* zmean = nullptr;
   int* flag = nullptr;
   int part_blocks = 0;
   double* hres = nullptr;  // pinned
@@ -176,8 +180,10 @@ MGHier<float>& mg_of<float>(ibr_ctx* c) {
 
 // ---------------------------------------------------------------- operator K
 // y = K x,  x stored in TI (fp64, or fp32 for mixed Z vectors), y in fp64.
+// xmean (steady periodic, may be null): per-component constants taken off x's
+// velocity, which only J sees (the stencils and S' ignore constants).
 template <typename TI>
-void apply_K(ibr_ctx* c, const TI* x, double* y) {
+void apply_K(ibr_ctx* c, const TI* x, double* y, const double* xmean = nullptr) {
   hipStream_t s = c->stream;
   const int d = c->dim;
   const TI* xv = x;
@@ -195,7 +201,7 @@ void apply_K(ibr_ctx* c, const TI* x, double* y) {
                                   false, ev, c->walls ? 1 : 0);
   launch_spread<double, double>(d, c->logn, c->tile_log, c->act_cap, c->active, c->nactive_d, c->toff, c->perm,
                                 c->taps, c->lamd, y, -std::pow(c->h, -d), s);
-  launch_interp<TI>(d, c->logn, c->N, c->taps, xv, -1.0, nullptr, 0.0, y + c->NF, s);
+  launch_interp<TI>(d, c->logn, c->N, c->taps, xv, -1.0, nullptr, 0.0, y + c->NF, s, xmean);
   if (c->nq) {
     const int64_t ub = c->NF + (int64_t)d * c->N;
     launch_free_apply<TI>(d, c->N, c->nb, c->off_d, c->body_d, c->R, c->X, c->L, c->free_d, c->lamd, x + ub,
@@ -327,7 +333,16 @@ void iteration_body(ibr_ctx* c, int k) {
   double* w = V + (int64_t)(k + 1) * ld;
   TZ* zk = Z + (int64_t)k * ld;
   precondition<TZ>(c, vk, zk);
-  apply_K<TZ>(c, zk, w);
+  // Steady periodic Stokes (eq. constrained_periodic): K has d null vectors
+  // that carry a mean velocity (and a net force), invisible to the residual,
+  // so the gauge <v> = 0 is kept exactly: z_k counts as z_k - <z_k>, the
+  // means taken in fp64 from the stored (fp32 in mixed precision) values.
+  const double* zm = nullptr;
+  if (c->vnull) {
+    launch_field_means<TZ>(zk, c->dim, c->C, c->mpart, 256, c->zmean + 4 * k, c->stream);
+    zm = c->zmean + 4 * k;
+  }
+  apply_K<TZ>(c, zk, w, zm);
   dcgs2_step<double>(V, ld, NV, k, c->H, c->m + 1, c->G, c->coef, c->part, c->part_blocks, c->cs, c->sn, c->g,
                      c->resid, c->stream, true);
 }
@@ -451,7 +466,8 @@ ibr_status fgmres(ibr_ctx* c, ibr_info* info) {
       // the last column is still provisional: rotate it as it stands
       launch_givens_step(c->H, ldh, kused - 1, c->cs, c->sn, c->g, c->resid, s);
       launch_lsq_solve(c->H, ldh, kused, c->g, c->y, s);
-      launch_combine<TZ, double>(Z, c->ldv, kused, c->y, c->Xs, NV, s);
+      launch_combine<TZ, double>(Z, c->ldv, kused, c->y, c->Xs, NV, s, false, c->vnull ? c->zmean : nullptr, c->C,
+                                 c->dim);
       if (stop) break;
     }
   }
@@ -592,6 +608,64 @@ void build_rhs_markers(ibr_ctx* c) {
   }
 }
 
+// Bodies overlap (Sec. 2 takes them disjoint; Sec. 5.3: markers closer than
+// about h/2 make the mobility too ill-conditioned to solve) when a marker of
+// one body lies closer than h to a marker of another: the two kernels then
+// nearly coincide.  Host cell list of side h, minimum image along periodic
+// axes; throws IBR_EINVAL naming the two bodies.
+void check_overlap(int d, int n, double h, double L, bool walls, int nb, const int* off, const double* R) {
+  if (nb < 2) return;
+  const int N = off[nb];
+  std::vector<int> body(N);
+  for (int b = 0; b < nb; ++b)
+    for (int i = off[b]; i < off[b + 1]; ++i) body[i] = b;
+  auto cell_axis = [&](double x) {
+    double w = x - L * std::floor(x / L);
+    int ci = (int)std::floor(w / h);
+    return ci < 0 ? 0 : (ci >= n ? n - 1 : ci);
+  };
+  std::vector<std::pair<int64_t, int>> key(N);
+  for (int i = 0; i < N; ++i) {
+    int64_t k = 0;
+    for (int a = d - 1; a >= 0; --a) k = k * n + cell_axis(R[(int64_t)i * d + a]);
+    key[i] = {k, i};
+  }
+  std::sort(key.begin(), key.end());
+  const double h2 = h * h;
+  int cc[3];
+  for (int i = 0; i < N; ++i) {
+    for (int a = 0; a < d; ++a) cc[a] = cell_axis(R[(int64_t)i * d + a]);
+    const int nn = d == 3 ? 27 : 9;
+    for (int t = 0; t < nn; ++t) {
+      int o[3] = {t % 3 - 1, (t / 3) % 3 - 1, t / 9 - 1};
+      int64_t k = 0;
+      bool skip = false;
+      for (int a = d - 1; a >= 0; --a) {
+        int ci = cc[a] + o[a];
+        if (walls && a == d - 1 && (ci < 0 || ci >= n)) skip = true;
+        ci = (ci + n) % n;
+        k = k * n + ci;
+      }
+      if (skip) continue;
+      auto it = std::lower_bound(key.begin(), key.end(), std::make_pair(k, -1));
+      for (; it != key.end() && it->first == k; ++it) {
+        const int j = it->second;
+        if (j <= i || body[j] == body[i]) continue;
+        double r2 = 0;
+        for (int a = 0; a < d; ++a) {
+          double dx = R[(int64_t)i * d + a] - R[(int64_t)j * d + a];
+          if (!(walls && a == d - 1)) dx -= L * std::nearbyint(dx / L);
+          r2 += dx * dx;
+        }
+        if (r2 < h2)
+          throw Status(IBR_EINVAL, "bodies " + std::to_string(body[i]) + " and " + std::to_string(body[j]) +
+                                       " overlap: markers " + std::to_string(i) + " and " + std::to_string(j) +
+                                       " are closer than h");
+      }
+    }
+  }
+}
+
 template <typename F>
 ibr_status guard(ibr_ctx* c, F&& f) {
   try {
@@ -635,7 +709,7 @@ ibr_ctx::~ibr_ctx() {
                   (void*)sn, (void*)g, (void*)y, (void*)resid, (void*)beta, (void*)hc2, (void*)part, (void*)Qi,
                   (void*)Zi, (void*)rhsT, (void*)qT, (void*)phiT, (void*)Hi, (void*)csi, (void*)sni, (void*)gi,
                   (void*)yi, (void*)residi, (void*)betai, (void*)hc2i, (void*)vmean, (void*)mpart, (void*)addc,
-                  (void*)lsum_part})
+                  (void*)lsum_part, (void*)part2, (void*)G, (void*)coef, (void*)flag, (void*)zmean})
     dev_free(q);
   mg64.release();
   mg32.release();
@@ -699,6 +773,7 @@ void ibr_ctx::alloc_grid() {
   part2 = track<double>((int64_t)(m + 3) * part_blocks);
   G = track<double>(2 * m + 8);
   coef = track<double>(2 * m + 8);
+  zmean = track<double>(4 * (int64_t)m);
   flag = track<int>(4);
   Hi = track<double>((int64_t)(ns + 1) * ns);
   csi = track<double>(ns + 1);
@@ -916,6 +991,7 @@ ibr_status ibr_set_bodies(ibr_ctx* c, int nbodies, const int* offsets, const dou
       if (!std::isfinite(R[i])) throw Status(IBR_EINVAL, "marker positions must be finite");
     for (int64_t i = 0; i < (int64_t)nbodies * d; ++i)
       if (!std::isfinite(centres[i])) throw Status(IBR_EINVAL, "centres must be finite");
+    check_overlap(d, c->n, c->h, c->L, c->walls, nbodies, offsets, R);
     if (c->walls) {
       for (int64_t m = 0; m < N; ++m) {
         const double z = R[m * d + d - 1];
@@ -1137,10 +1213,12 @@ ibr_status ibr_solve(ibr_ctx* c, int warm_start, ibr_info* info) {
     IBR_HIP(hipSetDevice(c->p.device));
     if (!warm_start || !c->have_solution) launch_fill<double>(c->Xs, c->NV, 0.0, c->stream);
     st = c->mixed ? fgmres<float>(c, info) : fgmres<double>(c, info);
-    if (st == IBR_ENOCONV) c->err = "FGMRES did not reach rtol within max_iters";
-    if (st == IBR_ENUMERIC) c->err = "NaN or Inf in the FGMRES residual";
   });
-  return g != IBR_OK ? g : st;
+  if (g != IBR_OK) return g;
+  // guard() clears the message of a call that threw nothing: set it afterwards
+  if (st == IBR_ENOCONV) c->err = "FGMRES did not reach rtol within max_iters";
+  if (st == IBR_ENUMERIC) c->err = "NaN or Inf in the FGMRES residual";
+  return st;
 }
 
 ibr_status ibr_step(ibr_ctx* c, ibr_info* info) {
@@ -1148,7 +1226,10 @@ ibr_status ibr_step(ibr_ctx* c, ibr_info* info) {
   ibr_status st = IBR_OK;
   ibr_status g = guard(c, [&] {
     require_bodies(c);
+    // every check before any state changes: a refused step leaves the context as it was
     if (c->steady) throw Status(IBR_ESTATE, "ibr_step needs rho > 0 (unsteady)");
+    if (c->rotating) throw Status(IBR_EINVAL, "ibr_step translates the bodies: Omega must be zero");
+    if (c->nfree) throw Status(IBR_EINVAL, "ibr_step moves bodies with prescribed velocities only: no free bodies");
     if (c->walls) {
       // bodies translate with their prescribed velocity: every marker must stay between the walls
       for (int b = 0; b < c->nb; ++b) {
@@ -1156,10 +1237,7 @@ ibr_status ibr_step(ibr_ctx* c, ibr_info* info) {
         if (!(zc + c->wall_lo[b] > 0.0 && zc + c->wall_hi[b] < c->L))
           throw Status(IBR_EINVAL, "ibr_step: body " + std::to_string(b) + " would cross a wall");
       }
-      for (int b = 0; b < c->nb; ++b) c->wall_z[b] += c->p.dt * c->wall_uz[b];
     }
-    if (c->rotating) throw Status(IBR_EINVAL, "ibr_step translates the bodies: Omega must be zero");
-    if (c->nfree) throw Status(IBR_EINVAL, "ibr_step moves bodies with prescribed velocities only: no free bodies");
     IBR_HIP(hipSetDevice(c->p.device));
     hipStream_t s = c->stream;
     const int d = c->dim;
@@ -1181,13 +1259,18 @@ ibr_status ibr_step(ibr_ctx* c, ibr_info* info) {
     launch_fill<double>(c->Bs + len, c->C, 0.0, s);
     // move the bodies, re-bin the markers (the mobility blocks are translation invariant)
     launch_move_markers(d, c->N, c->nb, c->R, c->X, c->body_d, c->U, c->p.dt, c->L, s);
+    if (c->walls)
+      for (int b = 0; b < c->nb; ++b) c->wall_z[b] += c->p.dt * c->wall_uz[b];
     setup_markers(c);
     build_rhs_markers(c);
     st = c->mixed ? fgmres<float>(c, info) : fgmres<double>(c, info);
     std::swap(c->Nprev, c->Ncur);
     c->have_prev = true;
   });
-  return g != IBR_OK ? g : st;
+  if (g != IBR_OK) return g;
+  if (st == IBR_ENOCONV) c->err = "FGMRES did not reach rtol within max_iters";
+  if (st == IBR_ENUMERIC) c->err = "NaN or Inf in the FGMRES residual";
+  return st;
 }
 
 ibr_status ibr_set_free_bodies(ibr_ctx* c, const int* free_mask, const double* F, const double* T) {

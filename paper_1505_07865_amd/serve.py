@@ -12,10 +12,12 @@ While one request's solve waits on its stream, the others' kernels run: work
 of different requests overlaps on the device, small grids with large ones,
 and no request pays for allocating or tearing down a context.
 
-Admission: before a worker creates a context it checks the context's device
-footprint (``ibr_footprint_bytes``) against the free device memory minus a
-reserve, evicting its least recently used idle contexts first; a request that
-cannot fit even then fails with MemoryError.
+Admission: contexts are created under one server-wide lock.  A new context
+is admitted when its device footprint (``ibr_footprint_bytes``) fits in the
+free device memory minus a reserve; otherwise the least recently used idle
+context of any worker is closed first, and when every remaining context is
+in use the request waits until a worker releases one.  Only a request that
+does not fit with no context left on the device fails, with MemoryError.
 
 Every steady solve starts from a zero initial guess and every trajectory from
 a fluid at rest, so a request's result does not depend on what the context
@@ -34,23 +36,45 @@ class _Worker(threading.Thread):
         super().__init__(name="ibr-serve-%d" % wid, daemon=True)
         self.server = server
         self.wid = wid
-        self.contexts = collections.OrderedDict()   # (dim, n) -> solver, LRU order
+
+    @property
+    def contexts(self):
+        """This worker's resident contexts, key -> solver (a snapshot)."""
+        srv = self.server
+        with srv._adm:
+            return {k: s for (w, k), s in srv._lru.items() if w == self.wid}
 
     def _context(self, prob):
-        key = _context_key(prob)
-        if key in self.contexts:
-            self.contexts.move_to_end(key)
-            return self.contexts[key]
+        """The worker's context for prob's grid and fluid, marked in use;
+        admitted by footprint (see the module notes).  Release with _release."""
         srv = self.server
-        need = srv.footprint(prob)
-        while srv.free_bytes() - srv.reserve_bytes < need and self.contexts:
-            _, old = self.contexts.popitem(last=False)
-            old.close()
-        if srv.free_bytes() - srv.reserve_bytes < need:
-            raise MemoryError("request of %d bytes does not fit on the device" % need)
-        s = srv.factory(prob)
-        self.contexts[key] = s
-        return s
+        ck = (self.wid, _context_key(prob))
+        with srv._adm:
+            if ck in srv._lru:
+                srv._lru.move_to_end(ck)
+                srv._busy.add(ck)
+                return srv._lru[ck]
+            need = srv.footprint(prob)
+            while srv.free_bytes() - srv.reserve_bytes < need:
+                victim = next((k for k in srv._lru if k not in srv._busy), None)
+                if victim is not None:
+                    srv._lru.pop(victim).close()
+                    srv.evictions += 1
+                    continue
+                if not srv._busy:
+                    raise MemoryError("request of %d bytes does not fit on the device" % need)
+                srv.admission_waits += 1
+                srv._adm.wait()
+            s = srv.factory(prob)
+            srv._lru[ck] = s
+            srv._busy.add(ck)
+            return s
+
+    def _release(self, prob):
+        srv = self.server
+        with srv._adm:
+            srv._busy.discard((self.wid, _context_key(prob)))
+            srv._adm.notify_all()
 
     def run(self):
         srv = self.server
@@ -59,8 +83,10 @@ class _Worker(threading.Thread):
             if item is None:
                 break
             rid, prob, nsteps, fut = item
+            held = False
             try:
                 s = self._context(prob)
+                held = True
                 s.set_bodies(prob.R, prob.offsets, prob.centres)
                 s.set_velocities(prob.U, prob.Omega)
                 if nsteps is None:
@@ -79,9 +105,13 @@ class _Worker(threading.Thread):
                     fut._finish(result={"id": rid, "steps": steps, "F": F, "T": T, "worker": self.wid})
             except BaseException as e:   # reported through the future
                 fut._finish(error=e)
-        for s in self.contexts.values():
-            s.close()
-        self.contexts.clear()
+            finally:
+                if held:
+                    self._release(prob)
+        with srv._adm:
+            for ck in [k for k in srv._lru if k[0] == self.wid]:
+                srv._lru.pop(ck).close()
+            srv._adm.notify_all()
 
 
 def _context_key(prob):
@@ -140,6 +170,13 @@ class Server:
         self.free_bytes = free_bytes or self._default_free_bytes
         self.queue = queue.Queue()
         self.next_id = 0
+        # admission state, shared by all workers under _adm: resident contexts
+        # in least-recently-used order, (worker, key) -> solver, and those in use
+        self._adm = threading.Condition()
+        self._lru = collections.OrderedDict()
+        self._busy = set()
+        self.evictions = 0
+        self.admission_waits = 0
         self.workers = [_Worker(self, w) for w in range(workers)]
         for w in self.workers:
             w.start()
@@ -209,13 +246,16 @@ class Server:
             for key, p in seen.items():
                 if key not in w.contexts:
                     s = w._context(p)
-                    s.set_bodies(p.R, p.offsets, p.centres)
-                    s.set_velocities(p.U, p.Omega)
-                    if p.rho > 0:
-                        s.reset()
-                        s.step()
-                    else:
-                        s.solve(warm_start=False)
+                    try:
+                        s.set_bodies(p.R, p.offsets, p.centres)
+                        s.set_velocities(p.U, p.Omega)
+                        if p.rho > 0:
+                            s.reset()
+                            s.step()
+                        else:
+                            s.solve(warm_start=False)
+                    finally:
+                        w._release(p)
 
 
 def _percentile(xs, q):

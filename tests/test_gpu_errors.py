@@ -1,0 +1,193 @@
+"""Failure paths of the C ABI on the GPU (argument checks, Sec. 5.3's
+ill-conditioned mobility, non-finite data), each followed by a valid call on
+the same context, which must still give the oracle's answer.
+
+* Overlapping bodies (a marker of one body closer than h to a marker of
+  another) are refused with IBR_EINVAL before any device work.
+* Markers at about h spacing (half the usual 2h) make the approximate
+  mobility indefinite (Sec. 5.3): the block is factored shifted, the shift
+  equals the oracle's reading of the same rule, and the solve still reaches
+  the oracle's exact answer.  (At h/2 the true mobility itself is singular to
+  fp64 rounding, cond 1e10-1e16 here, which the paper also finds unsolvable
+  in double precision; then ibr_solve returns IBR_ENOCONV.)
+* A NaN right-hand side returns IBR_ENUMERIC; the next solve with finite data
+  succeeds.
+* A refused time step changes no state: after a step refused for a rotating
+  body, the slit channel's wall check still stops the body exactly where its
+  markers would reach the wall.
+"""
+import dataclasses
+import math
+
+import numpy as np
+import pytest
+
+from oracle import constrained, mobility
+from synthetic import small_problem
+from synthetic import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def _two_spheres(dist_h, n=32, radius_h=3.0):
+    h = 1.0 / n
+    c0 = np.array([0.5, 0.5, 0.5])
+    c1 = c0 + np.array([dist_h * h, 0.0, 0.0])
+    nm = W.sphere_markers_for(radius_h)
+    R = np.vstack([W.fibonacci_sphere(nm, radius_h * h, c0), W.fibonacci_sphere(nm, radius_h * h, c1)])
+    return R, np.array([0, nm, 2 * nm]), np.vstack([c0, c1])
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_overlapping_bodies_refused(dim):
+    from paper_1505_07865_amd import ibr
+    n = 32
+    h = 1.0 / n
+    if dim == 3:
+        R, off, X = _two_spheres(2.0)                          # surfaces interpenetrate
+        Rok, offok, Xok = _two_spheres(6.0 + 4.0)             # 4h surface gap
+    else:
+        c0, c1 = np.array([0.5, 0.5]), np.array([0.5 + 2 * h, 0.5])
+        nm = W.disk_markers_for(3.0)
+        R = np.vstack([W.disk_ring(nm, 3 * h, c0), W.disk_ring(nm, 3 * h, c1, 0.3)])
+        off, X = np.array([0, nm, 2 * nm]), np.vstack([c0, c1])
+        c1 = np.array([0.5 + 10 * h, 0.5])
+        Rok = np.vstack([W.disk_ring(nm, 3 * h, c0), W.disk_ring(nm, 3 * h, c1, 0.3)])
+        offok, Xok = off, np.vstack([c0, c1])
+    print("overlap refusal, %dD" % dim, flush=True)
+    s = ibr.Solver(dim=dim, n=n, h=h, rtol=1e-10)
+    with pytest.raises(ibr.IbrError) as e:
+        s.set_bodies(R, off, X)
+    assert e.value.status == 1 and "overlap" in str(e.value)
+    # the same two bodies across the periodic boundary: minimum image
+    shift = np.zeros(dim)
+    shift[0] = 0.5 - X[0, 0] - 1e-3
+    with pytest.raises(ibr.IbrError):
+        s.set_bodies(np.mod(R + shift + 0.5, 1.0), off, np.mod(X + shift + 0.5, 1.0))
+    # separated bodies are accepted and solve to the oracle's answer
+    s.set_bodies(Rok, offok, Xok)
+    U = np.array([[1.0] + [0.0] * (dim - 1), [0.0, 1.0] + [0.0] * (dim - 2)])
+    Om = np.zeros((2, 3 if dim == 3 else 1))
+    s.set_velocities(U, Om)
+    info = s.solve()
+    sol = s.solution()
+    s.close()
+    prob = W._assemble(dim, n, h, 0.0, 1.0, 0.0, [Rok[:offok[1]], Rok[offok[1]:]], Xok, U, Om, [3 * h] * 2, 0, "t")
+    ex = constrained.solve_problem(prob)
+    assert info["rel_residual"] <= 1e-10
+    assert _rel(sol.u, ex.v) < 1e-8 and _rel(sol.F, ex.F) < 1e-8
+
+
+def _dense_marker_problem(dim):
+    """One body with markers at about h spacing (Sec. 5.3's ill-conditioned
+    side): 2D steady disk, 25 markers on radius 4h in 32^2 (true mobility
+    cond 8e4); 3D unsteady sphere (Re 10, dt = h/2), 100 markers on radius 3h
+    in 16^3 (cond 2e4)."""
+    if dim == 2:
+        n, rad_h, nm, rho, dt = 32, 4.0, 25, 0.0, 0.0
+        h = 1.0 / n
+        c = np.array([0.46, 0.53])
+        R = W.disk_ring(nm, rad_h * h, c, 0.1)
+        eta = 1.0
+    else:
+        n, rad_h, nm = 16, 3.0, 100
+        h = 1.0 / n
+        rho, dt = 1.0, 0.5 * h
+        c = np.array([0.46, 0.53, 0.51])
+        R = W.fibonacci_sphere(nm, rad_h * h, c)
+        eta = rad_h * h / 10.0
+    U = np.array([[0.8, -0.3, 0.5][:dim]])
+    Om = np.zeros((1, 3 if dim == 3 else 1))
+    return W._assemble(dim, n, h, rho, eta, dt, [R], c[None, :].copy(), U, Om, [rad_h * h], 0, "dense")
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_shifted_factorisation_reaches_oracle(dim):
+    from paper_1505_07865_amd import ibr
+    prob = _dense_marker_problem(dim)
+    blocks, p = mobility.blocks_for_problem(prob)
+    _, shift_oracle = mobility.factor_block(blocks[0], mobility.self_term(p))
+    print("dense markers, %dD, oracle shift %g" % (dim, shift_oracle), flush=True)
+    assert shift_oracle > 0                                  # the fallback is exercised
+    s = ibr.from_problem(prob, rtol=1e-10)
+    M, shift = s.mobility_block(0)
+    info = s.solve()
+    sol = s.solution()
+    s.close()
+    assert shift == shift_oracle and info["max_mobility_shift"] == shift_oracle
+    ex = constrained.solve_problem(prob)
+    print("iters", info["iters"], "err v %.2e F %.2e" % (_rel(sol.u, ex.v), _rel(sol.F, ex.F)), flush=True)
+    assert info["rel_residual"] <= 1e-10
+    # error <= cond(K) rtol in the worst case; cond of the mobility is 1e4-1e5 here
+    assert _rel(sol.u, ex.v) < 1e-7 and _rel(sol.F, ex.F) < 1e-7
+    assert np.abs(M - blocks[0]).max() <= 1e-13 * np.abs(blocks[0]).max()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_nan_rhs_is_enumeric(precision):
+    from paper_1505_07865_amd import ibr
+    prob = small_problem(4, 3, 16, radius_h=2.5)
+    print("NaN right-hand side, precision", precision, flush=True)
+    s = ibr.from_problem(prob, rtol=1e-10, precision=precision)
+    g = np.zeros((3, 16, 16, 16))
+    g[1, 3, 4, 5] = np.nan
+    s.set_rhs(g)
+    with pytest.raises(ibr.IbrError) as e:
+        s.solve()
+    assert e.value.status == 6
+    g[1, 3, 4, 5] = np.inf
+    s.set_rhs(g)
+    with pytest.raises(ibr.IbrError) as e:
+        s.solve()
+    assert e.value.status == 6
+    # finite data again: the context still solves to the oracle's answer
+    s.set_rhs(None)
+    info = s.solve()
+    sol = s.solution()
+    s.close()
+    ex = constrained.solve_problem(prob)
+    assert info["rel_residual"] <= 1e-10
+    assert _rel(sol.u, ex.v) < 1e-6
+
+
+def test_refused_step_keeps_wall_state():
+    """ibr_step refused for a rotating body (Omega != 0) must not advance the
+    host copy of the bodies' positions along the walls' axis: afterwards the
+    body steps toward the top wall exactly as many times as its markers stay
+    inside the channel, then the step is refused with nothing moved."""
+    from paper_1505_07865_amd import ibr
+    from synthetic import slit_problem
+    prob = slit_problem(5, dim=3, n=16, nbodies=1, radius_h=2.5, rotate=False)
+    n, h = prob.n, prob.h
+    dt = 0.01
+    uz = 2.0 * h / dt                                          # two cells per step upward
+    s = ibr.Solver(dim=3, n=n, h=h, rho=1.0, dt=dt, eta=0.05, walls=ibr.WALLS_NOSLIP, n_s=4,
+                   advection=ibr.ADVECT_SL, rtol=1e-8)
+    s.set_bodies(prob.R, prob.offsets, prob.centres)
+    top = prob.R[:, 2].max()
+    allowed = 0
+    while top + (allowed + 1) * dt * uz < 1.0:
+        allowed += 1
+    assert allowed >= 2
+    U = np.array([[0.0, 0.0, uz]])
+    s.set_velocities(U, np.array([[0.0, 0.0, 1.0]]))
+    for _ in range(3):
+        with pytest.raises(ibr.IbrError) as e:
+            s.step()
+        assert e.value.status == 1
+    s.set_velocities(U, np.zeros((1, 3)))
+    print("slit: %d steps allowed before the top wall" % allowed, flush=True)
+    for k in range(allowed):
+        s.step()
+    R0, X0 = s.markers()
+    assert np.abs(R0 - (prob.R + allowed * dt * U)).max() < 1e-12
+    with pytest.raises(ibr.IbrError) as e:
+        s.step()
+    assert e.value.status == 1 and "wall" in str(e.value)
+    R1, X1 = s.markers()
+    assert np.array_equal(R0, R1) and np.array_equal(X0, X1)
+    s.close()

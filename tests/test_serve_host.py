@@ -157,3 +157,75 @@ def test_walls_get_their_own_contexts():
         assert srv2._params(slit)["n_s"] == 4 and "n_s" not in srv2._params(per)
     finally:
         srv2.close()
+
+
+def test_concurrent_admission_waits_for_memory():
+    """Four workers take requests for four grid sizes at once; each context
+    needs 40 of 100 bytes.  Admission is serialised: at no time do more than
+    two contexts exist, requests that do not fit yet wait for a context to be
+    released (then evict it) instead of failing, and every request is served."""
+    FakeSolver.created = []
+    lock = threading.Lock()
+    state = {"free": 100, "alive": 0, "max_alive": 0}
+
+    def factory(p):
+        s = FakeSolver(p, delay=0.02)
+        with lock:
+            state["free"] -= 40
+            state["alive"] += 1
+            state["max_alive"] = max(state["max_alive"], state["alive"])
+        assert state["free"] >= 0
+        orig = s.close
+
+        def close():
+            with lock:
+                state["free"] += 40
+                state["alive"] -= 1
+            orig()
+        s.close = close
+        return s
+
+    probs = [_prob(2, n, u=i) for i, n in enumerate((16, 32, 64, 128) * 4)]
+    with serve.Server(workers=4, factory=factory, footprint=lambda p: 40, free_bytes=lambda: state["free"],
+                      reserve_bytes=0) as srv:
+        futs = [srv.submit(p) for p in probs]
+        res = [f.result(timeout=20) for f in futs]
+        assert srv.admission_waits > 0 and srv.evictions > 0
+    for p, r in zip(probs, res):
+        assert np.array_equal(r["F"], p.U * 2.0)
+    assert state["max_alive"] <= 2
+    assert state["free"] == 100 and state["alive"] == 0
+
+
+def test_admission_evicts_other_workers_idle_contexts():
+    """An idle context held by one worker is evicted for another worker's
+    request when memory is short (least recently used first, any worker)."""
+    FakeSolver.created = []
+    state = {"free": 100}
+    gate = threading.Event()
+
+    class Slow(FakeSolver):
+        def solve(self, warm_start=False):
+            if self.key == (2, 64):
+                gate.wait(5)
+            return super().solve(warm_start)
+
+    def factory(p):
+        s = Slow(p)
+        state["free"] -= 60
+        orig = s.close
+
+        def close():
+            state["free"] += 60
+            orig()
+        s.close = close
+        return s
+
+    with serve.Server(workers=2, factory=factory, footprint=lambda p: 60, free_bytes=lambda: state["free"],
+                      reserve_bytes=0) as srv:
+        srv.submit(_prob(2, 32)).result(timeout=10)        # one worker now holds an idle 32^2 context
+        f = srv.submit(_prob(2, 64))                        # needs the 32^2 context's memory
+        gate.set()
+        f.result(timeout=10)
+        assert srv.evictions == 1
+        assert sum(len(w.contexts) for w in srv.workers) == 1
