@@ -268,6 +268,34 @@ ibr_status ibr_mobility_inverse(ibr_ctx* ctx, int body, double* Minv);
  * context is steady).  Resets the Adams-Bashforth history of ibr_step. */
 ibr_status ibr_advect(ibr_ctx* ctx, const double* u, double* N);
 
+/* ---- allocation-free spreading ---- */
+
+/* Size of the library's static device scratch array (per GPU, held until the
+ * process ends) used by ibr_spread_noalloc. */
+#define IBR_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The same
+ * f = S lambda as ibr_spread (Sec. 3.1, eq. S_unweighted, no mean removal),
+ * without a context: from params only dim, n, h, walls, device and stream are
+ * read.  R[nmarkers][dim] (marker positions, wrapped into the box as in
+ * ibr_set_bodies) and lambda[nmarkers][dim] are device arrays of
+ * params->device; f[dim][n^dim] is a device array that receives the field
+ * (it is overwritten, not accumulated).  Asynchronous on params->stream (NULL
+ * = the device's null stream): f is complete when the stream reaches the
+ * call, and R and lambda must stay valid until then.  Every temporary (kernel
+ * taps, tile bins) lives in the static scratch array of
+ * IBR_NOALLOC_SCRATCH_BYTES: no call allocates or frees device memory.  That
+ * array is shared by all calls on one GPU and keeps the last call's contents,
+ * so calls that overlap on one GPU (other streams or host threads) race.
+ * Sizes beyond the scratch (88 469 markers at n = 512 in 3D, 104 850 on
+ * grids of one tile) return IBR_EINVAL with the largest marker count
+ * that fits in msg.  msg (may be NULL) receives a message of at most msg_len
+ * - 1 characters on failure, "" on success.  No device work runs unless every
+ * argument is valid. */
+ibr_status ibr_spread_noalloc(const ibr_params* params, int nmarkers, const void* R, const void* lambda,
+                              void* f, char* msg, size_t msg_len);
+
 /* ---- live kernel timing (measurement support) ---- */
 
 /* Bracket every stride-th launch of one kernel class with HIP events on its

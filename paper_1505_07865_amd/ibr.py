@@ -55,7 +55,9 @@ EXPORTS = ["ibr_default_params", "ibr_status_string", "ibr_create", "ibr_destroy
            "ibr_step", "ibr_get_solution", "ibr_get_markers", "ibr_apply_operator", "ibr_spread",
            "ibr_interp", "ibr_vcycle", "ibr_precondition", "ibr_mobility_block", "ibr_advect",
            "ibr_timer_enable", "ibr_timer_read", "ibr_mobility_inverse", "ibr_set_rhs_dev",
-           "ibr_get_solution_dev", "ibr_reset", "ibr_set_free_bodies", "ibr_get_velocities"]
+           "ibr_get_solution_dev", "ibr_reset", "ibr_set_free_bodies", "ibr_get_velocities",
+           "ibr_spread_noalloc"]
+NOALLOC_SCRATCH_BYTES = 32 << 20
 
 
 def _devptr(x):
@@ -119,6 +121,8 @@ def load(path=LIB_PATH):
         "ibr_mobility_inverse": (ctypes.c_int, [vp, ctypes.c_int, dp]),
         "ibr_timer_enable": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_int]),
         "ibr_timer_read": (ctypes.c_int, [ctypes.c_char_p, dp, P(ctypes.c_long), dp]),
+        "ibr_spread_noalloc": (ctypes.c_int, [P(Params), ctypes.c_int, vp, vp, vp, ctypes.c_char_p,
+                                              ctypes.c_size_t]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -384,6 +388,22 @@ def timer_read(kernel):
     if st != 0:
         raise IbrError(st, "ibr_timer_read(%r)" % kernel)
     return {"ms": ms.value, "launches": n.value, "bytes": b.value}
+
+
+def spread_noalloc(R, lam, f, nmarkers=None, stream=None, **params):
+    """f = S lam without a context or any device allocation (ibr_spread_noalloc):
+    R [N, dim], lam [N, dim] and f [dim, n..] are float64 device arrays
+    (tensors, or addresses with nmarkers given) on params' device;
+    asynchronous on ``stream`` (a torch stream, a raw handle, or None for the
+    null stream).  params: dim, n, h, walls, device."""
+    p = default_params(**params)
+    if stream is not None:
+        p.stream = getattr(stream, "cuda_stream", stream)
+    nm = nmarkers if nmarkers is not None else (0 if R is None else int(R.shape[0]))
+    buf = ctypes.create_string_buffer(512)
+    st = lib().ibr_spread_noalloc(ctypes.byref(p), nm, _devptr(R), _devptr(lam), _devptr(f), buf, 512)
+    if st != 0:
+        raise IbrError(st, "ibr_spread_noalloc: " + buf.value.decode())
 
 
 def footprint_bytes(nbodies, nmarkers, **params):
