@@ -17,7 +17,11 @@ per seed, 20 steps each from rest) offered at once to the request server,
 with 4 workers whose solves overlap on the device, and with 1 worker (the
 plain solver), in both precisions.  The ``second_re`` object runs the same
 workload at Re = 100, where the advection is the semi-Lagrangian transport
-(the centred form with AB2 is unstable at that cell Reynolds number).
+(the centred form with AB2 is unstable at that cell Reynolds number).  The
+``serving_mix`` object runs the first requests of the serving trace (steady
+solves of mixed grid sizes and body counts) through the request server, at
+saturation and as Poisson arrivals at 0.7x the fp64 capacity, in both
+precisions.
 
     python bench.py [--steps K] [--warmup W] [--re 10] [--advection auto|centred|sl] [--seed 0]
                     [--no-cpu-baseline]
@@ -75,6 +79,8 @@ def parse():
     ap.add_argument("--ablation", action="store_true",
                     help="solver study instead: preconditioner variant and N_s vs P_S^-1 applications")
     ap.add_argument("--nreq", type=int, default=2000, help="serving: requests in the trace")
+    ap.add_argument("--mix-requests", type=int, default=300,
+                    help="default line: requests of the serving trace run as its serving_mix leg (0 = skip)")
     ap.add_argument("--workers", type=int, default=4, help="serving and served form: host worker threads")
     ap.add_argument("--served-trajectories", type=int, default=8,
                     help="served form: independent simulations of the workload offered at once")
@@ -340,16 +346,17 @@ def served(args, torch):
     return out
 
 
-def serving(args, torch):
-    """Serving workload: a seeded trace of independent steady constrained solves
-    (grids 32^2, 128^2, 256^2, 32^3, 64^3, 128^3; 1-8 bodies of radius 4h-8h with
-    markers at ~2h; U, Omega ~ U[-1,1]; rtol 1e-8) offered to the request
-    server, first all at once (saturation: solves/s), then as Poisson arrivals
-    at 0.7 x the measured fp64 capacity (p50/p99 latency, queueing included),
-    for the mixed-precision and the fp64 solver on the same trace."""
+def serving_leg(args, torch, nreq):
+    """Serving workload: a seeded trace of nreq independent steady constrained
+    solves (grids 32^2, 128^2, 256^2, 32^3, 64^3, 128^3; 1-8 bodies of radius
+    4h-8h with markers at ~2h; U, Omega ~ U[-1,1]; rtol 1e-8) offered to the
+    request server, first all at once (saturation: solves/s), then as Poisson
+    arrivals at 0.7 x the measured fp64 capacity (p50/p99 latency, queueing
+    included), for the mixed-precision and the fp64 solver on the same trace.
+    Returns the per-precision results."""
     from paper_1505_07865_amd import serve
     from synthetic import serving_trace
-    trace = serving_trace(args.seed, args.nreq, 1.0)
+    trace = serving_trace(args.seed, nreq, 1.0)
     res = {}
     for prec in ("fp64", "mixed"):
         with serve.Server(precision=prec, workers=args.workers) as srv:
@@ -367,6 +374,30 @@ def serving(args, torch):
             print("bench: serving %s, Poisson arrivals at %.1f req/s" % (prec, qps), file=sys.stderr, flush=True)
             lat = serve.replay(trace, srv, qps=qps)
             res[prec]["at_0.7x_fp64_capacity"] = {k: v for k, v in lat.items() if k != "results"}
+    return res
+
+
+def serving_summary(res, nreq, workers):
+    return {"requests": nreq, "workers": workers,
+            "mixed_solves_per_s": round(res["mixed"]["saturation"]["solves_per_s"], 3),
+            "fp64_solves_per_s": round(res["fp64"]["saturation"]["solves_per_s"], 3),
+            "mixed_over_fp64": round(res["mixed"]["saturation"]["solves_per_s"] /
+                                     res["fp64"]["saturation"]["solves_per_s"], 3),
+            "qps_at_0.7x_fp64": round(res["mixed"]["at_0.7x_fp64_capacity"]["qps_offered"], 3),
+            "mixed_p50_ms": round(res["mixed"]["at_0.7x_fp64_capacity"]["p50_ms"], 3),
+            "mixed_p99_ms": round(res["mixed"]["at_0.7x_fp64_capacity"]["p99_ms"], 3),
+            "fp64_p50_ms": round(res["fp64"]["at_0.7x_fp64_capacity"]["p50_ms"], 3),
+            "fp64_p99_ms": round(res["fp64"]["at_0.7x_fp64_capacity"]["p99_ms"], 3),
+            "mixed_iters_mean": round(res["mixed"]["iters_mean"], 2),
+            "fp64_iters_mean": round(res["fp64"]["iters_mean"], 2),
+            "max_rel_residual": float("%.4g" % max(res["mixed"]["max_rel_residual"],
+                                                   res["fp64"]["max_rel_residual"]))}
+
+
+def serving(args, torch):
+    """The serving workload alone, on the whole trace (``--nreq``)."""
+    res = serving_leg(args, torch, args.nreq)
+    trace_len = args.nreq
     line = {
         "metric": "serving: solves/s at saturation and p50/p99 latency at 0.7x fp64 capacity, mixed vs fp64",
         "value": round(res["mixed"]["saturation"]["solves_per_s"], 3),
@@ -378,7 +409,7 @@ def serving(args, torch):
         "data": "synthetic",
         "config": {"workload": "steady constrained solves, seeded Poisson trace of %d requests over grids "
                                "32^2/128^2/256^2/32^3/64^3/128^3 with 1-8 bodies, rtol 1e-8, %d workers"
-                               % (len(trace), args.workers), "seed": args.seed},
+                               % (trace_len, args.workers), "seed": args.seed},
         "p50_ms": round(res["mixed"]["at_0.7x_fp64_capacity"]["p50_ms"], 3),
         "p99_ms": round(res["mixed"]["at_0.7x_fp64_capacity"]["p99_ms"], 3),
         "mixed": res["mixed"],
@@ -838,6 +869,11 @@ def main():
         line["second_re"] = second_re(args, torch)
     if args.precision == "both" and not args.no_served:
         line["served"] = served(args, torch)
+    if args.precision == "both" and args.mix_requests > 0:
+        # the serving trace (mixed grid sizes and body counts, Poisson arrivals), a short prefix of it
+        print("bench: serving mix, %d requests" % args.mix_requests, file=sys.stderr, flush=True)
+        line["serving_mix"] = serving_summary(serving_leg(args, torch, args.mix_requests), args.mix_requests,
+                                              args.workers)
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle on the workload's first two steps", file=sys.stderr, flush=True)
         line["cpu_baseline"], ref = cpu_baseline(prob, scheme=scheme)

@@ -106,6 +106,34 @@ def test_vcycle_mixed_precision(dim, n, c0, c1):
     s.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("n,nf", [(64, 3), (64, 1), (128, 1), (128, 3)])
+@pytest.mark.parametrize("c0,c1", [(0.0, 1.0), (2.5, 0.7)])
+def test_vcycle_large_levels_match_oracle(precision, n, nf, c0, c1):
+    """The V-cycle shapes of the 128^3 workload and its 64^3 level: the
+    velocity cycle (3 fields: per-step kernels on 128^3 and 64^3, fused LDS
+    tiles from 32^3) and the pressure cycle (1 field: the 64^3 level fused
+    too) equal the oracle's cycle (fp64 1e-11, fp32 1e-5) and repeat bitwise
+    (the fused post-smoothing writes a second array; an in-place version
+    raced)."""
+    from paper_1505_07865_amd import ibr
+    print("V-cycle %s %d^3 nf %d c0 %g" % (precision, n, nf, c0), flush=True)
+    s = ibr.Solver(dim=3, n=n, h=1.0 / n, precision=ibr.MIXED if precision == "mixed" else ibr.FP64)
+    rng = np.random.default_rng(7 * n + nf)
+    b = rng.standard_normal((nf,) + (n,) * 3)
+    if c0 == 0.0:
+        b -= b.reshape(nf, -1).mean(axis=1).reshape((nf, 1, 1, 1))
+    x = s.vcycle(c0, c1, b if nf > 1 else b[0])
+    x = x.reshape((nf,) + (n,) * 3)
+    bar = 1e-11 if precision == "fp64" else 1e-5
+    for f in range(nf):
+        xe = multigrid.vcycle(b[f], c0, c1)
+        assert _rel(x[f], xe) < bar, (f, _rel(x[f], xe))
+    x2 = s.vcycle(c0, c1, b if nf > 1 else b[0]).reshape(x.shape)
+    assert np.array_equal(x, x2)
+    s.close()
+
+
 def test_mobility_blocks_match_oracle(case):
     prob, name = case
     s = _solver(prob)
