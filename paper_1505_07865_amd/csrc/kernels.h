@@ -265,7 +265,9 @@ struct MobParams {
 };
 void launch_mob_assemble(int dim, int nb, const int* offsets, const int64_t* moff, const double* R, MobParams p,
                          double* M, int max_np, hipStream_t s);
-void launch_chol(int nb, const int* offsets, int dim, const int64_t* moff, const double* M, double* Lf,
+// Xf receives the inverses of the 64 x 64 diagonal blocks of each factor
+// (the diagonal blocks of L^-1), which launch_chol_inverse completes.
+void launch_chol(int nb, const int* offsets, int dim, const int64_t* moff, const double* M, double* Lf, double* Xf,
                  const int* active, const double* shift, double f0, double pivot_tol, int* fail, int max_rows,
                  hipStream_t s);
 void launch_chol_inverse(int nb, const int* offsets, int dim, const int64_t* moff, double* Lf, double* Minv,

@@ -5,6 +5,8 @@
 // application is one batched matrix-vector product.
 //
 // Block p is row-major dN_p x dN_p at M + moff[p].
+#include <algorithm>
+
 #include "kernels.h"
 
 namespace ibr {
@@ -107,18 +109,21 @@ typedef double dvec4 __attribute__((ext_vector_type(4)));
 __device__ inline int pad16(int n) { return (n + 15) & ~15; }
 
 // Batched blocked right-looking Cholesky of M_p + shift_p f0 I over all
-// bodies, 16x16 tiles.  Per 16-column panel p two launches cover every body:
-//   panel:  one wavefront per (row tile I > p, body) factors the diagonal
-//           tile in registers (lane r holds row r, shuffles broadcast the
-//           pivot column) and solves L_Ip L_pp^T = A_Ip row by row (lane
-//           r < 16 owns row r of the tile);
-//   update: one wavefront per lower tile (I, J), p < J <= I, of every body:
-//           L_IJ -= L_Ip L_Jp^T on fp64 MFMA 16x16x4; one more per body
-//           writes the factored diagonal tile (after the panel launch has
-//           read the unfactored one).
-// So the work of a panel spreads over every compute unit instead of one
-// workgroup per body walking all panels.  A pivot <= pivot_tol f0 marks the
-// body failed (it is factored again with a larger shift).
+// bodies with 64-column panels; per panel three launches cover every body:
+//   diag:  one workgroup per body factors the 64 x 64 diagonal block in LDS
+//          (16 x 16 tiles: register factor of the diagonal tile, row tiles by
+//          substitution, trailing tiles on MFMA) and inverts it (the
+//          diagonal block of X = L^-1);
+//   trsm:  one workgroup per 64-row block below: L_Ip = A_Ip (L_pp^-1)^T on
+//          MFMA with both operands in LDS;
+//   syrk:  one workgroup per pair of 64-row blocks I >= J below: A_IJ -=
+//          L_Ip L_Jp^T on MFMA, each wavefront a 32 x 32 quadrant (2 x 2
+//          tiles, 16 k-steps per tile).
+// A pivot <= pivot_tol f0 marks the body failed (it is factored again with a
+// larger shift).  The inverse then needs only the off-diagonal blocks of X
+// and Minv = X^T X, both as 64 x 64 block products on MFMA.
+constexpr int kBlk = 64;   // block edge
+constexpr int kSld = 66;   // LDS row stride in doubles (MFMA operand reads 2-way at most per bank)
 
 // L = lower(M) + shift on the diagonal, identity on the padding rows.
 __global__ void __launch_bounds__(64) k_chol_init(const int* __restrict__ off, int dim,
@@ -145,231 +150,484 @@ __global__ void __launch_bounds__(64) k_chol_init(const int* __restrict__ off, i
   }
 }
 
-// The diagonal tile (p, p) factored in registers: lane r (mod 16) holds row
-// r; shuffles within each group of 16 lanes broadcast the pivot column.
-// bad = some pivot <= pivot_tol f0.
-__device__ inline void factor_diag_tile(const double* L, int ld, int c0, double row[16], bool& bad, double f0,
-                                        double pivot_tol) {
-  const int r = threadIdx.x & 15;
+// A kBlk x kBlk block of the row-major matrix G (leading dimension ld) from
+// row r0, column c0 into LDS S (stride kSld); entries outside rows < rmax,
+// columns < cmax (and, with lower, above the diagonal) are zero.
+// 256 threads: each issues its 16 global loads before its LDS stores, so
+// they are in flight together.  block_fetch / block_put split the two halves
+// so that the loads of the next block can overlap the products on this one.
+constexpr int kPer = kBlk * kBlk / 256;
+__device__ inline void block_fetch(double v[kPer], const double* __restrict__ G, int ld, int r0, int c0, int rmax,
+                                   int cmax, bool lower = false) {
 #pragma unroll
-  for (int c = 0; c < 16; ++c) row[c] = (c <= r) ? L[(int64_t)(c0 + r) * ld + c0 + c] : 0.0;
-  bad = false;
+  for (int u = 0; u < kPer; ++u) {
+    const int idx = threadIdx.x + 256 * u;
+    const int i = idx >> 6, j = idx & 63;
+    v[u] = 0.0;
+    if (r0 + i < rmax && c0 + j < cmax && (!lower || c0 + j <= r0 + i)) v[u] = G[(int64_t)(r0 + i) * ld + c0 + j];
+  }
+}
+__device__ inline void block_put(double* S, const double v[kPer]) {
 #pragma unroll
-  for (int j = 0; j < 16; ++j) {
-    const double d = __shfl(row[j], j, 16);
-    bad = bad || !(d > pivot_tol * f0);
-    const double sd = sqrt(d > 0.0 ? d : 1.0);
-    if (r == j) row[j] = sd;
-    else if (r > j) row[j] = row[j] / sd;
-#pragma unroll
-    for (int c = j + 1; c < 16; ++c) {
-      const double lc = __shfl(row[j], c, 16);  // L[c][j]
-      if (r >= c) row[c] -= row[j] * lc;
-    }
+  for (int u = 0; u < kPer; ++u) {
+    const int idx = threadIdx.x + 256 * u;
+    S[(idx >> 6) * kSld + (idx & 63)] = v[u];
+  }
+}
+__device__ inline void lds_load_block(double* S, const double* __restrict__ G, int ld, int r0, int c0, int rmax,
+                                      int cmax, bool lower = false) {
+  double v[kPer];
+  block_fetch(v, G, ld, r0, c0, rmax, cmax, lower);
+  block_put(S, v);
+}
+
+// Workgroup -> (body, item) so that all workgroups of one body run on one
+// XCD (the hardware hands consecutive workgroups to the 8 XCDs in turn): a
+// body's panel and blocks are then re-read from that XCD's L2.  Grid:
+// 8 * ceil(nb / 8) * nitems workgroups in x; false for the padding ones.
+__device__ inline bool body_item(int nb, int nitems, int& body, int& item) {
+  const int id = blockIdx.x;
+  const int xcd = id % kXcds, k = id / kXcds;
+  body = xcd + kXcds * (k / nitems);
+  item = k % nitems;
+  return body < nb;
+}
+
+// acc += A B^T on the 16 x 16 tile (ti, tj): A[i][k] = A[i * kSld + k],
+// B^T given as Bt[j][k] = Bt[j * kSld + k]; K a multiple of 4.
+__device__ inline dvec4 mma_abt(dvec4 acc, const double* A, const double* Bt, int ti, int tj, int K) {
+  const int lane = threadIdx.x & 63, r = lane & 15, kq = lane >> 4;
+  const double* a = A + (ti * 16 + r) * kSld + kq;
+  const double* bt = Bt + (tj * 16 + r) * kSld + kq;
+  for (int k0 = 0; k0 < K; k0 += 4) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[k0], bt[k0], acc, 0, 0, 0);
+  return acc;
+}
+// acc += A B on the tile (ti, tj): A[i][k] = A[i * kSld + k], B[k][j] = B[k * kSld + j].
+__device__ inline dvec4 mma_ab(dvec4 acc, const double* A, const double* B, int ti, int tj, int K) {
+  const int lane = threadIdx.x & 63, r = lane & 15, kq = lane >> 4;
+  const double* a = A + (ti * 16 + r) * kSld + kq;
+  const double* bb = B + kq * kSld + tj * 16 + r;
+  for (int k0 = 0; k0 < K; k0 += 4) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[k0], bb[k0 * kSld], acc, 0, 0, 0);
+  return acc;
+}
+// acc += A^T B on the tile (ti, tj): A[k][i] = A[k * kSld + i], B[k][j] = B[k * kSld + j].
+__device__ inline dvec4 mma_atb(dvec4 acc, const double* A, const double* B, int ti, int tj, int K) {
+  const int lane = threadIdx.x & 63, r = lane & 15, kq = lane >> 4;
+  const double* a = A + kq * kSld + ti * 16 + r;
+  const double* bb = B + kq * kSld + tj * 16 + r;
+  for (int k0 = 0; k0 < K; k0 += 4)
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[k0 * kSld], bb[k0 * kSld], acc, 0, 0, 0);
+  return acc;
+}
+// The same products on a 2 x 2 quadrant of tiles (ti0, ti0+1) x (tj0, tj0+1):
+// per k-step two A and two B operands feed four independent accumulators.
+__device__ inline void mma_abt_2x2(dvec4 acc[2][2], const double* A, const double* Bt, int ti0, int tj0, int K) {
+  const int lane = threadIdx.x & 63, r = lane & 15, kq = lane >> 4;
+  const double* a0 = A + (ti0 * 16 + r) * kSld + kq;
+  const double* a1 = a0 + 16 * kSld;
+  const double* b0 = Bt + (tj0 * 16 + r) * kSld + kq;
+  const double* b1 = b0 + 16 * kSld;
+  for (int k0 = 0; k0 < K; k0 += 4) {
+    const double x0 = a0[k0], x1 = a1[k0], y0 = b0[k0], y1 = b1[k0];
+    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, y0, acc[0][0], 0, 0, 0);
+    acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, y1, acc[0][1], 0, 0, 0);
+    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, y0, acc[1][0], 0, 0, 0);
+    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, y1, acc[1][1], 0, 0, 0);
+  }
+}
+__device__ inline void mma_ab_2x2(dvec4 acc[2][2], const double* A, const double* B, int ti0, int tj0, int K) {
+  const int lane = threadIdx.x & 63, r = lane & 15, kq = lane >> 4;
+  const double* a0 = A + (ti0 * 16 + r) * kSld + kq;
+  const double* a1 = a0 + 16 * kSld;
+  const double* b0 = B + kq * kSld + tj0 * 16 + r;
+  const double* b1 = b0 + 16;
+  for (int k0 = 0; k0 < K; k0 += 4) {
+    const double x0 = a0[k0], x1 = a1[k0], y0 = b0[k0 * kSld], y1 = b1[k0 * kSld];
+    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, y0, acc[0][0], 0, 0, 0);
+    acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, y1, acc[0][1], 0, 0, 0);
+    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, y0, acc[1][0], 0, 0, 0);
+    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, y1, acc[1][1], 0, 0, 0);
+  }
+}
+__device__ inline void mma_atb_2x2(dvec4 acc[2][2], const double* A, const double* B, int ti0, int tj0, int K) {
+  const int lane = threadIdx.x & 63, r = lane & 15, kq = lane >> 4;
+  const double* a0 = A + kq * kSld + ti0 * 16 + r;
+  const double* a1 = a0 + 16;
+  const double* b0 = B + kq * kSld + tj0 * 16 + r;
+  const double* b1 = b0 + 16;
+  for (int k0 = 0; k0 < K; k0 += 4) {
+    const double x0 = a0[k0 * kSld], x1 = a1[k0 * kSld], y0 = b0[k0 * kSld], y1 = b1[k0 * kSld];
+    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, y0, acc[0][0], 0, 0, 0);
+    acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, y1, acc[0][1], 0, 0, 0);
+    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, y0, acc[1][0], 0, 0, 0);
+    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, y1, acc[1][1], 0, 0, 0);
   }
 }
 
-// Row tiles I > p of the panel: L_Ip = A_Ip L_pp^-T.  Every workgroup factors
-// the diagonal tile itself from the still unfactored L_pp (it is written back
-// by the update launch, after all of them have read it).
-__global__ void __launch_bounds__(64) k_chol_panel(const int* __restrict__ off, int dim,
-                                                   const int64_t* __restrict__ moff, double* __restrict__ Lf,
-                                                   const int* __restrict__ active, int p, double f0, double pivot_tol) {
-  __shared__ double D[16][17];
-  const int b = blockIdx.y;
-  if (!active[b]) return;
-  const int n = dim * (off[b + 1] - off[b]);
-  const int ld = pad16(n);
-  const int nt = ld / 16;
-  const int I = p + 1 + blockIdx.x;
-  if (I >= nt) return;
-  double* L = Lf + moff[b];
-  const int lane = threadIdx.x;
-  const int r = lane & 15;
-  const int c0 = 16 * p;
-  double row[16];
-  bool bad;
-  factor_diag_tile(L, ld, c0, row, bad, f0, pivot_tol);
-  if (lane < 16) {
+// Tile (ti, tj) of a 16 x 16 accumulator to / from LDS (stride kSld).
+__device__ inline void tile_store(double* S, int ti, int tj, dvec4 acc) {
+  const int lane = threadIdx.x & 63, c = lane & 15, rq = lane >> 4;
 #pragma unroll
-    for (int c = 0; c < 16; ++c) D[r][c] = row[c];
-  }
-  __syncthreads();
-  if (lane >= 16) return;
-  // row r of tile I: x L_pp^T = a, forward substitution over the 16 columns
-  double* Lr = L + (int64_t)(16 * I + r) * ld + c0;
-  double x[16];
-#pragma unroll
-  for (int c = 0; c < 16; ++c) x[c] = Lr[c];
-#pragma unroll
-  for (int c = 0; c < 16; ++c) {
-    double t = x[c];
-#pragma unroll
-    for (int k = 0; k < c; ++k) t -= x[k] * D[c][k];
-    x[c] = t / D[c][c];
-  }
-#pragma unroll
-  for (int c = 0; c < 16; ++c) Lr[c] = x[c];
+  for (int q = 0; q < 4; ++q) S[(ti * 16 + 4 * q + rq) * kSld + tj * 16 + c] = acc[q];
 }
-
-// Block 0: write the factored diagonal tile (p, p) and the pivot verdict.
-// Blocks 1..: the trailing tiles (I, J), p < J <= I: L_IJ -= L_Ip L_Jp^T.
-__global__ void __launch_bounds__(64) k_chol_update(const int* __restrict__ off, int dim,
-                                                    const int64_t* __restrict__ moff, double* __restrict__ Lf,
-                                                    const int* __restrict__ active, int p, double f0,
-                                                    double pivot_tol, int* __restrict__ fail) {
-  const int b = blockIdx.y;
-  if (!active[b]) return;
-  const int n = dim * (off[b + 1] - off[b]);
-  const int ld = pad16(n);
-  const int nt = ld / 16;
-  if (p >= nt) return;
-  double* L = Lf + moff[b];
-  const int c0 = 16 * p;
-  const int lane = threadIdx.x;
-  if (blockIdx.x == 0) {
-    double row[16];
-    bool bad;
-    factor_diag_tile(L, ld, c0, row, bad, f0, pivot_tol);
-    if (lane < 16) {
-      const int r = lane;
-#pragma unroll
-      for (int c = 0; c < 16; ++c)
-        if (c <= r) L[(int64_t)(c0 + r) * ld + c0 + c] = row[c];
-    }
-    if (lane == 0 && bad) fail[b] = 1;
-    return;
-  }
-  const int T = nt - p - 1;
-  const int t = blockIdx.x - 1;
-  if (t >= T * (T + 1) / 2) return;
-  // unrank t -> (I, J) in row-major lower-triangular order
-  int I = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
-  while ((I + 1) * (I + 2) / 2 <= t) ++I;
-  while (I * (I + 1) / 2 > t) --I;
-  const int J = t - I * (I + 1) / 2;
-  const int r0 = 16 * (p + 1 + I), q0 = 16 * (p + 1 + J);
-  const int ci = lane & 15, rq = lane >> 4;
+__device__ inline dvec4 tile_load(const double* S, int ti, int tj) {
+  const int lane = threadIdx.x & 63, c = lane & 15, rq = lane >> 4;
   dvec4 acc;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) acc[k] = L[(int64_t)(r0 + 4 * k + rq) * ld + q0 + ci];
-#pragma unroll
-  for (int k0 = 0; k0 < 16; k0 += 4) {
-    const double a = -L[(int64_t)(r0 + ci) * ld + c0 + k0 + rq];
-    const double bb = L[(int64_t)(q0 + ci) * ld + c0 + k0 + rq];
-    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc, 0, 0, 0);
-  }
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const int row = r0 + 4 * k + rq, cc = q0 + ci;
-    if (I != J || cc <= row) L[(int64_t)row * ld + cc] = acc[k];
-  }
+  for (int q = 0; q < 4; ++q) acc[q] = S[(ti * 16 + 4 * q + rq) * kSld + tj * 16 + c];
+  return acc;
 }
 
-// X = L^-1 (L lower triangular, 16x16 tiles).  First every diagonal tile is
-// inverted (one wavefront per tile, lane c < 16 solves for column c), then
-// each 16-column block J is filled by block forward substitution,
-//   X_IJ = -X_II sum_{K=J}^{I-1} L_IK X_KJ,   I = J+1, J+2, ...
-// with one workgroup per (J, body): its four wavefronts split the K-sum
-// (fp64 MFMA 16x16x4 tiles) and one of them applies -X_II.
-__global__ void __launch_bounds__(64) k_diag_inv(const int* __restrict__ off, int dim,
-                                                 const int64_t* __restrict__ moff, const double* __restrict__ Lf,
-                                                 double* __restrict__ X) {
-  const int b = blockIdx.y;
+// Diagonal block of panel c0 (width W = min(64, ld - c0)): factor and invert.
+// 256 threads.  LDS: D (the block, then L_pp; its strictly upper tiles are
+// the wavefronts' scratch tiles of the inversion), X (the inverse).
+__global__ void __launch_bounds__(256) k_chol_diag(const int* __restrict__ off, int dim,
+                                                   const int64_t* __restrict__ moff, double* __restrict__ Lf,
+                                                   double* __restrict__ Xf, const int* __restrict__ active, int c0,
+                                                   double f0, double pivot_tol, int* __restrict__ fail) {
+  __shared__ double D[kBlk * kSld];
+  __shared__ double X[kBlk * kSld];
+  __shared__ int bad_s;
+  const int b = blockIdx.x;
+  if (!active[b]) return;
   const int n = dim * (off[b + 1] - off[b]);
   const int ld = pad16(n);
-  const int I = blockIdx.x;
-  if (16 * I >= ld) return;
-  const double* L = Lf + moff[b];
-  double* Xb = X + moff[b];
-  const int r0 = 16 * I;
-  const int c = threadIdx.x;
-  if (c >= 16) return;
-  double col[16];
-#pragma unroll
-  for (int i = 0; i < 16; ++i) {
-    double v = i == c ? 1.0 : 0.0;
-#pragma unroll
-    for (int k = 0; k < i; ++k) v -= L[(int64_t)(r0 + i) * ld + r0 + k] * col[k];  // col[k] = 0 for k < c
-    col[i] = i < c ? 0.0 : v / L[(int64_t)(r0 + i) * ld + r0 + i];
-  }
-#pragma unroll
-  for (int i = 0; i < 16; ++i) Xb[(int64_t)(r0 + i) * ld + r0 + c] = col[i];
-}
-
-__global__ void __launch_bounds__(256) k_tri_inv_cols(const int* __restrict__ off, int dim,
-                                                      const int64_t* __restrict__ moff,
-                                                      const double* __restrict__ Lf, double* __restrict__ X) {
-  const int b = blockIdx.y;
-  const int n = dim * (off[b + 1] - off[b]);
-  const int ld = pad16(n);
-  const int nt = ld / 16;
-  const int J = blockIdx.x;
-  if (J >= nt) return;
-  const double* L = Lf + moff[b];
-  double* Xb = X + moff[b];
-  __shared__ double part[4][16][17];
-  const int lane = threadIdx.x & (kWave - 1);
-  const int wv = threadIdx.x / kWave;
-  const int ci = lane & 15, rq = lane >> 4;
-  const int j0 = 16 * J;
-  for (int I = J + 1; I < nt; ++I) {
-    const int i0 = 16 * I;
-    dvec4 acc = {0.0, 0.0, 0.0, 0.0};
-    for (int K = J + wv; K < I; K += 4) {
-      const int k0 = 16 * K;
-#pragma unroll
-      for (int kk = 0; kk < 16; kk += 4) {
-        const double a = L[(int64_t)(i0 + ci) * ld + k0 + kk + rq];
-        const double bb = Xb[(int64_t)(k0 + kk + rq) * ld + j0 + ci];
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc, 0, 0, 0);
-      }
-    }
-#pragma unroll
-    for (int r = 0; r < 4; ++r) part[wv][4 * r + rq][ci] = acc[r];
-    __syncthreads();
+  if (c0 >= ld) return;
+  const int W = min(kBlk, ld - c0);
+  const int nt = W / 16;
+  double* L = Lf + moff[b];
+  double* Xg = Xf + moff[b];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, r16 = lane & 15;
+  if (threadIdx.x == 0) bad_s = 0;
+  lds_load_block(D, L, ld, c0, c0, c0 + W, c0 + W, true);
+  for (int idx = threadIdx.x; idx < kBlk * kSld; idx += blockDim.x) X[idx] = 0.0;
+  __syncthreads();
+  for (int q = 0; q < nt; ++q) {
+    const int q0 = 16 * q;
+    // diagonal tile in registers of wavefront 0: lane r (mod 16) holds row r
     if (wv == 0) {
-      dvec4 res = {0.0, 0.0, 0.0, 0.0};
+      double row[16];
 #pragma unroll
-      for (int kk = 0; kk < 16; kk += 4) {
-        const double a = -Xb[(int64_t)(i0 + ci) * ld + i0 + kk + rq];
-        const int sr = kk + rq;
-        const double bb = ((part[0][sr][ci] + part[1][sr][ci]) + part[2][sr][ci]) + part[3][sr][ci];
-        res = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, res, 0, 0, 0);
+      for (int c = 0; c < 16; ++c) row[c] = c <= r16 ? D[(q0 + r16) * kSld + q0 + c] : 0.0;
+      bool bad = false;
+#pragma unroll
+      for (int jj = 0; jj < 16; ++jj) {
+        const double d = __shfl(row[jj], jj, 16);
+        bad = bad || !(d > pivot_tol * f0);
+        const double sd = sqrt(d > 0.0 ? d : 1.0);
+        if (r16 == jj) row[jj] = sd;
+        else if (r16 > jj) row[jj] = row[jj] / sd;
+#pragma unroll
+        for (int c = jj + 1; c < 16; ++c) {
+          const double lc = __shfl(row[jj], c, 16);
+          if (r16 >= c) row[c] -= row[jj] * lc;
+        }
+      }
+      if (lane < 16) {
+#pragma unroll
+        for (int c = 0; c < 16; ++c) D[(q0 + r16) * kSld + q0 + c] = c <= r16 ? row[c] : 0.0;
+      }
+      if (lane == 0 && bad) bad_s = 1;
+    }
+    __syncthreads();
+    // row tiles below: x L_qq^T = a, one row per lane (16 lanes of a wavefront per tile)
+    for (int rt = q + 1 + wv; rt < nt; rt += 4) {
+      if (lane < 16) {
+        double* Lr = D + (16 * rt + lane) * kSld + q0;
+        double x[16];
+#pragma unroll
+        for (int c = 0; c < 16; ++c) x[c] = Lr[c];
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+          double t = x[c];
+#pragma unroll
+          for (int k = 0; k < c; ++k) t -= x[k] * D[(q0 + c) * kSld + q0 + k];
+          x[c] = t / D[(q0 + c) * kSld + q0 + c];
+        }
+#pragma unroll
+        for (int c = 0; c < 16; ++c) Lr[c] = x[c];
+      }
+    }
+    __syncthreads();
+    // trailing tiles (rt, st), q < st <= rt < nt: D -= L_rt,q L_st,q^T (K = 16 at column q0)
+    int cnt = 0;
+    for (int rt = q + 1; rt < nt; ++rt)
+      for (int st = q + 1; st <= rt; ++st, ++cnt) {
+        if (cnt % 4 != wv) continue;
+        dvec4 acc = tile_load(D, rt, st);
+        dvec4 m = {0.0, 0.0, 0.0, 0.0};
+        m = mma_abt(m, D + q0, D + q0, rt, st, 16);
+        acc -= m;
+        tile_store(D, rt, st, acc);
+      }
+    __syncthreads();
+  }
+  // inverse of the lower-triangular L_pp: diagonal tiles (lane c < 16 solves column c)
+  for (int q = wv; q < nt; q += 4) {
+    if (lane < 16) {
+      const int q0 = 16 * q, c = lane;
+      double col[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        double v = i == c ? 1.0 : 0.0;
+#pragma unroll
+        for (int k = 0; k < i; ++k) v -= D[(q0 + i) * kSld + q0 + k] * col[k];
+        col[i] = i < c ? 0.0 : v / D[(q0 + i) * kSld + q0 + i];
       }
 #pragma unroll
-      for (int r = 0; r < 4; ++r) Xb[(int64_t)(i0 + 4 * r + rq) * ld + j0 + ci] = res[r];
+      for (int i = 0; i < 16; ++i) X[(q0 + i) * kSld + q0 + c] = col[i];
+    }
+  }
+  __syncthreads();
+  // X_rs = -X_rr sum_{k=s}^{r-1} L_rk X_ks, row tile by row tile.  Scratch
+  // tile of wavefront w: the strictly upper tile (0, w+1) of D, or (1, 3).
+  const int sti = wv == 3 ? 1 : 0, stj = wv == 3 ? 3 : wv + 1;
+  double* scratch = D + 16 * sti * kSld + 16 * stj;
+  for (int rt = 1; rt < nt; ++rt) {
+    for (int st = wv; st < rt; st += 4) {
+      dvec4 acc = {0.0, 0.0, 0.0, 0.0};
+      for (int k = st; k < rt; ++k) {
+        // L_rk X_ks: A = D tile (rt, k), B = X tile (k, st), K = 16
+        acc = mma_ab(acc, D + 16 * k, X + 16 * k * kSld, rt, st, 16);
+      }
+      tile_store(scratch, 0, 0, acc);
+      dvec4 res = {0.0, 0.0, 0.0, 0.0};
+      res = mma_ab(res, X + 16 * rt, scratch, rt, 0, 16);
+      tile_store(X, rt, st, -res);
     }
     __syncthreads();
   }
+  for (int idx = threadIdx.x; idx < W * W; idx += blockDim.x) {
+    const int i = idx / W, j = idx - (idx / W) * W;
+    if (j <= i) {
+      L[(int64_t)(c0 + i) * ld + c0 + j] = D[i * kSld + j];
+      Xg[(int64_t)(c0 + i) * ld + c0 + j] = X[i * kSld + j];
+    } else {
+      Xg[(int64_t)(c0 + i) * ld + c0 + j] = 0.0;
+    }
+  }
+  if (threadIdx.x == 0 && bad_s) fail[b] = 1;
 }
 
-// Minv = X^T X for X = L^-1 lower triangular: one wave per 16x16 tile (I >= J),
-// fp64 MFMA over 4-row slabs of X, mirrored into the upper triangle.
-__global__ void __launch_bounds__(64) k_xtx(const int* __restrict__ off, int dim, const int64_t* __restrict__ moff,
-                                            const double* __restrict__ X, double* __restrict__ Minv) {
-  const int b = blockIdx.z;
+// Panel rows below the diagonal block: L_Ip = A_Ip (L_pp^-1)^T, one workgroup
+// per 64-row block I (rows c0 + W + 64 blockIdx.x ..), each wavefront 16 rows.
+__global__ void __launch_bounds__(256) k_chol_trsm(const int* __restrict__ off, int dim,
+                                                   const int64_t* __restrict__ moff, double* __restrict__ Lf,
+                                                   const double* __restrict__ Xf, const int* __restrict__ active,
+                                                   int c0, int nb, int nitems) {
+  __shared__ double A[kBlk * kSld];
+  __shared__ double Xs[kBlk * kSld];
+  int b, item;
+  if (!body_item(nb, nitems, b, item)) return;
+  if (!active[b]) return;
   const int n = dim * (off[b + 1] - off[b]);
   const int ld = pad16(n);
-  const int I = blockIdx.y, J = blockIdx.x;
-  if (16 * I >= ld || J > I) return;
-  const double* Xb = X + moff[b];
-  const int lane = threadIdx.x;
-  const int ci = lane & 15, rq = lane >> 4;
-  const int i0 = 16 * I, j0 = 16 * J;
-  dvec4 acc = {0.0, 0.0, 0.0, 0.0};
-  for (int k0 = i0; k0 < ld; k0 += 4) {
-    const double a = Xb[(int64_t)(k0 + rq) * ld + i0 + ci];
-    const double bb = Xb[(int64_t)(k0 + rq) * ld + j0 + ci];
-    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc, 0, 0, 0);
-  }
-  double* Mb = Minv + moff[b];
+  if (c0 >= ld) return;
+  const int W = min(kBlk, ld - c0);
+  const int r0 = c0 + W + kBlk * item;
+  if (r0 >= ld) return;
+  double* L = Lf + moff[b];
+  const double* Xg = Xf + moff[b];
+  lds_load_block(A, L, ld, r0, c0, ld, c0 + W);
+  lds_load_block(Xs, Xg, ld, c0, c0, c0 + W, c0 + W, true);
+  __syncthreads();
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, c = lane & 15, rq = lane >> 4;
+  // wavefront w: the 2 x 2 quadrant (rows 32 (w >> 1), columns 32 (w & 1)) of the 64 x W product
+  const int qi = wv >> 1, qj = wv & 1;
+  if (32 * qj >= W) return;
+  dvec4 acc[2][2];
+  for (int a = 0; a < 2; ++a)
+    for (int e = 0; e < 2; ++e) acc[a][e] = dvec4{0.0, 0.0, 0.0, 0.0};
+  mma_abt_2x2(acc, A, Xs, 2 * qi, 2 * qj, W);
+  for (int a = 0; a < 2; ++a)
+    for (int e = 0; e < 2; ++e) {
+      const int ti = 2 * qi + a, tj = 2 * qj + e;
+      if (r0 + 16 * ti >= ld || 16 * tj >= W) continue;
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int row = i0 + 4 * r + rq, col = j0 + ci;
-    Mb[(int64_t)row * ld + col] = acc[r];
-    Mb[(int64_t)col * ld + row] = acc[r];
+      for (int q = 0; q < 4; ++q) L[(int64_t)(r0 + 16 * ti + 4 * q + rq) * ld + c0 + 16 * tj + c] = acc[a][e][q];
+    }
+}
+
+// Unrank t -> (I, J), 0 <= J <= I, in row-major lower-triangular order.
+__device__ inline void unrank_lower(int t, int& I, int& J) {
+  I = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+  while ((I + 1) * (I + 2) / 2 <= t) ++I;
+  while (I * (I + 1) / 2 > t) --I;
+  J = t - I * (I + 1) / 2;
+}
+
+// Trailing update: A_IJ -= L_Ip L_Jp^T for 64-row blocks I >= J below the
+// panel; each wavefront a 32 x 32 quadrant, the lower triangle only on I == J.
+__global__ void __launch_bounds__(256) k_chol_syrk(const int* __restrict__ off, int dim,
+                                                   const int64_t* __restrict__ moff, double* __restrict__ Lf,
+                                                   const int* __restrict__ active, int c0, int nb, int nitems) {
+  __shared__ double Ai[kBlk * kSld];
+  __shared__ double Aj[kBlk * kSld];
+  int b, item;
+  if (!body_item(nb, nitems, b, item)) return;
+  if (!active[b]) return;
+  const int n = dim * (off[b + 1] - off[b]);
+  const int ld = pad16(n);
+  if (c0 >= ld) return;
+  const int W = min(kBlk, ld - c0);
+  const int base = c0 + W;
+  const int nblk = (ld - base + kBlk - 1) / kBlk;
+  if (item >= nblk * (nblk + 1) / 2) return;
+  int I, J;
+  unrank_lower(item, I, J);
+  const int ri = base + kBlk * I, rj = base + kBlk * J;
+  double* L = Lf + moff[b];
+  lds_load_block(Ai, L, ld, ri, c0, ld, c0 + W);
+  if (I != J) lds_load_block(Aj, L, ld, rj, c0, ld, c0 + W);
+  __syncthreads();
+  const double* Bj = I != J ? Aj : Ai;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, c = lane & 15, rq = lane >> 4;
+  const int qi = wv >> 1, qj = wv & 1;  // quadrant
+  if (I == J && qj > qi) return;        // strictly upper quadrant of a diagonal block
+  dvec4 m[2][2];
+  for (int a = 0; a < 2; ++a)
+    for (int e = 0; e < 2; ++e) m[a][e] = dvec4{0.0, 0.0, 0.0, 0.0};
+  mma_abt_2x2(m, Ai, Bj, 2 * qi, 2 * qj, W);
+  for (int a = 0; a < 2; ++a)
+    for (int e = 0; e < 2; ++e) {
+      const int ti = 2 * qi + a, tj = 2 * qj + e;
+      if (I == J && tj > ti) continue;
+      const int row0 = ri + 16 * ti, col0 = rj + 16 * tj;
+      if (row0 >= ld || col0 >= ld) continue;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int row = row0 + 4 * q + rq, col = col0 + c;
+        if (I != J || ti != tj || col <= row) L[(int64_t)row * ld + col] -= m[a][e][q];
+      }
+    }
+}
+
+// X = L^-1 below the diagonal blocks (those were inverted by k_chol_diag):
+// one workgroup per 64-column block J and body walks the row blocks
+//   X_IJ = -X_II sum_{K=J}^{I-1} L_IK X_KJ,   I = J+1, J+2, ...
+// as a chain of steps (each product L_IK X_KJ, then the product with X_II),
+// each wavefront a 32 x 32 quadrant of the 64 x 64 products.  The operands
+// of the next step are loaded into registers while this step's products run
+// (the X_KJ a step needs was written by an earlier step, before a barrier).
+__global__ void __launch_bounds__(256) k_tri_inv(const int* __restrict__ off, int dim,
+                                                 const int64_t* __restrict__ moff, const double* __restrict__ Lf,
+                                                 double* __restrict__ Xf, int nb, int nitems) {
+  __shared__ double A[kBlk * kSld];
+  __shared__ double B[kBlk * kSld];
+  int b, J;
+  if (!body_item(nb, nitems, b, J)) return;
+  const int n = dim * (off[b + 1] - off[b]);
+  const int ld = pad16(n);
+  const int nblk = (ld + kBlk - 1) / kBlk;
+  if (J + 1 >= nblk) return;
+  const double* L = Lf + moff[b];
+  double* X = Xf + moff[b];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, c = lane & 15, rq = lane >> 4;
+  const int qi = wv >> 1, qj = wv & 1;
+  const int cj = kBlk * J;
+  // step (I, K): K < I is the product L_IK X_KJ, K == I the product with X_II
+  double va[kPer], vb[kPer];
+  auto fetch = [&](int I, int K) {
+    if (K < I) {
+      block_fetch(va, L, ld, kBlk * I, kBlk * K, ld, ld);
+      block_fetch(vb, X, ld, kBlk * K, cj, ld, ld);
+    } else {
+      block_fetch(va, X, ld, kBlk * I, kBlk * I, ld, ld, true);
+    }
+  };
+  int I = J + 1, K = J;
+  fetch(I, K);
+  block_put(A, va);
+  block_put(B, vb);
+  __syncthreads();
+  dvec4 acc[2][2];
+  for (int a = 0; a < 2; ++a)
+    for (int e = 0; e < 2; ++e) acc[a][e] = dvec4{0.0, 0.0, 0.0, 0.0};
+  while (true) {
+    int In = I, Kn = K + 1;
+    if (K == I) {
+      In = I + 1;
+      Kn = J;
+    }
+    const bool next = In < nblk;
+    if (next) fetch(In, Kn);
+    if (K < I) {
+      mma_ab_2x2(acc, A, B, 2 * qi, 2 * qj, kBlk);
+    } else {
+      // the sum into LDS B (its last operand was read before the previous barrier), times X_II
+      for (int a = 0; a < 2; ++a)
+        for (int e = 0; e < 2; ++e) tile_store(B, 2 * qi + a, 2 * qj + e, acc[a][e]);
+      __syncthreads();
+      dvec4 res[2][2];
+      for (int a = 0; a < 2; ++a)
+        for (int e = 0; e < 2; ++e) res[a][e] = dvec4{0.0, 0.0, 0.0, 0.0};
+      mma_ab_2x2(res, A, B, 2 * qi, 2 * qj, kBlk);
+      const int ri = kBlk * I;
+      for (int a = 0; a < 2; ++a)
+        for (int e = 0; e < 2; ++e) {
+          acc[a][e] = dvec4{0.0, 0.0, 0.0, 0.0};
+          const int row0 = ri + 16 * (2 * qi + a), col0 = cj + 16 * (2 * qj + e);
+          if (row0 >= ld || col0 >= ld) continue;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) X[(int64_t)(row0 + 4 * q + rq) * ld + col0 + c] = -res[a][e][q];
+        }
+    }
+    if (!next) break;
+    // every wavefront has read this step's LDS operands (and the X_IJ just
+    // stored is visible to the loads of later steps)
+    __syncthreads();
+    block_put(A, va);
+    if (Kn < In) block_put(B, vb);
+    __syncthreads();
+    I = In;
+    K = Kn;
   }
+}
+
+// Minv = X^T X for X = L^-1 lower triangular: one workgroup per 64 x 64 block
+// (I >= J), sum over K >= I of X_KI^T X_KJ, mirrored into the upper triangle.
+// (Loading the next K's blocks during the products, as k_tri_inv does, took
+// 254 registers and ran 2.2 times slower here: the plain loop stays.)
+__global__ void __launch_bounds__(256) k_xtx(const int* __restrict__ off, int dim, const int64_t* __restrict__ moff,
+                                             const double* __restrict__ Xf, double* __restrict__ Minv, int nb,
+                                             int nitems) {
+  __shared__ double A[kBlk * kSld];
+  __shared__ double B[kBlk * kSld];
+  int b, item;
+  if (!body_item(nb, nitems, b, item)) return;
+  const int n = dim * (off[b + 1] - off[b]);
+  const int ld = pad16(n);
+  const int nblk = (ld + kBlk - 1) / kBlk;
+  if (item >= nblk * (nblk + 1) / 2) return;
+  int I, J;
+  unrank_lower(item, I, J);
+  const double* X = Xf + moff[b];
+  double* Mb = Minv + moff[b];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, c = lane & 15, rq = lane >> 4;
+  const int qi = wv >> 1, qj = wv & 1;
+  const int ri = kBlk * I, rj = kBlk * J;
+  dvec4 acc[2][2];
+  for (int a = 0; a < 2; ++a)
+    for (int e = 0; e < 2; ++e) acc[a][e] = dvec4{0.0, 0.0, 0.0, 0.0};
+  for (int K = I; K < nblk; ++K) {
+    const int rk = kBlk * K;
+    __syncthreads();
+    lds_load_block(A, X, ld, rk, ri, ld, ld);
+    lds_load_block(B, X, ld, rk, rj, ld, ld);
+    __syncthreads();
+    mma_atb_2x2(acc, A, B, 2 * qi, 2 * qj, kBlk);
+  }
+  for (int a = 0; a < 2; ++a)
+    for (int e = 0; e < 2; ++e) {
+      const int row0 = ri + 16 * (2 * qi + a), col0 = rj + 16 * (2 * qj + e);
+      if (row0 >= ld || col0 >= ld) continue;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int row = row0 + 4 * q + rq, col = col0 + c;
+        Mb[(int64_t)row * ld + col] = acc[a][e][q];
+        Mb[(int64_t)col * ld + row] = acc[a][e][q];
+      }
+    }
 }
 
 // lam_p = Minv_p dU_p: one wavefront per row.
@@ -400,29 +658,39 @@ void launch_mob_assemble(int dim, int nb, const int* offsets, const int64_t* mof
                      moff, R, p, M);
 }
 
-void launch_chol(int nb, const int* offsets, int dim, const int64_t* moff, const double* M, double* Lf,
+// Workgroups of a body_item grid: 8 * ceil(nb / 8) * nitems.
+static unsigned body_grid(int nb, int nitems) { return (unsigned)(kXcds * ((nb + kXcds - 1) / kXcds) * nitems); }
+
+void launch_chol(int nb, const int* offsets, int dim, const int64_t* moff, const double* M, double* Lf, double* Xf,
                  const int* active, const double* shift, double f0, double pivot_tol, int* fail, int max_rows,
                  hipStream_t s) {
   const int ldmax = (max_rows + 15) & ~15;
-  const int ntmax = ldmax / 16;
   hipLaunchKernelGGL(k_chol_init, dim3(ldmax, nb), dim3(64), 0, s, offsets, dim, moff, M, Lf, active, shift, f0,
                      fail);
-  for (int p = 0; p < ntmax; ++p) {
-    const int T = ntmax - p - 1;
-    if (T > 0)
-      hipLaunchKernelGGL(k_chol_panel, dim3(T, nb), dim3(64), 0, s, offsets, dim, moff, Lf, active, p, f0,
-                         pivot_tol);
-    hipLaunchKernelGGL(k_chol_update, dim3(T * (T + 1) / 2 + 1, nb), dim3(64), 0, s, offsets, dim, moff, Lf, active,
-                       p, f0, pivot_tol, fail);
+  for (int c0 = 0; c0 < ldmax; c0 += kBlk) {
+    const int W = std::min(kBlk, ldmax - c0);
+    const int rows = ldmax - c0 - W;
+    const int nblk = (rows + kBlk - 1) / kBlk;
+    hipLaunchKernelGGL(k_chol_diag, dim3(nb), dim3(256), 0, s, offsets, dim, moff, Lf, Xf, active, c0, f0, pivot_tol,
+                       fail);
+    if (nblk > 0) {
+      const int np = nblk * (nblk + 1) / 2;
+      hipLaunchKernelGGL(k_chol_trsm, dim3(body_grid(nb, nblk)), dim3(256), 0, s, offsets, dim, moff, Lf, Xf, active,
+                         c0, nb, nblk);
+      hipLaunchKernelGGL(k_chol_syrk, dim3(body_grid(nb, np)), dim3(256), 0, s, offsets, dim, moff, Lf, active, c0,
+                         nb, np);
+    }
   }
 }
 
 void launch_chol_inverse(int nb, const int* offsets, int dim, const int64_t* moff, double* Lf, double* Minv,
                          double* X, int max_n, hipStream_t s) {
-  const unsigned t = (unsigned)((max_n + 15) / 16);
-  hipLaunchKernelGGL(k_diag_inv, dim3(t, nb), dim3(64), 0, s, offsets, dim, moff, Lf, X);
-  hipLaunchKernelGGL(k_tri_inv_cols, dim3(t, nb), dim3(256), 0, s, offsets, dim, moff, Lf, X);
-  hipLaunchKernelGGL(k_xtx, dim3(t, t, nb), dim3(64), 0, s, offsets, dim, moff, X, Minv);
+  const int nblk = (max_n + kBlk - 1) / kBlk;
+  if (nblk > 1)
+    hipLaunchKernelGGL(k_tri_inv, dim3(body_grid(nb, nblk - 1)), dim3(256), 0, s, offsets, dim, moff, Lf, X, nb,
+                       nblk - 1);
+  const int np = nblk * (nblk + 1) / 2;
+  hipLaunchKernelGGL(k_xtx, dim3(body_grid(nb, np)), dim3(256), 0, s, offsets, dim, moff, X, Minv, nb, np);
 }
 
 void launch_mob_apply(int nb, const int* offsets, int dim, const int64_t* moff, const double* Minv,

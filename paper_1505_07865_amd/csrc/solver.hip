@@ -575,7 +575,7 @@ void factor_blocks(ibr_ctx* c) {
     for (int b = 0; b < nb; ++b) c->shift_h[b] = kShifts[idx[b]];
     IBR_HIP(hipMemcpyAsync(c->shift_d, c->shift_h.data(), nb * sizeof(double), hipMemcpyHostToDevice, s));
     IBR_HIP(hipMemcpyAsync(c->act_d, act.data(), nb * sizeof(int), hipMemcpyHostToDevice, s));
-    launch_chol(nb, c->off_d, c->dim, c->moff_d, c->Mb, c->Lb, c->act_d, c->shift_d, c->f0, kPivotTol, c->fail_d,
+    launch_chol(nb, c->off_d, c->dim, c->moff_d, c->Mb, c->Lb, c->Xb, c->act_d, c->shift_d, c->f0, kPivotTol, c->fail_d,
                 c->max_rows, s);
     IBR_HIP(hipMemcpyAsync(fail.data(), c->fail_d, nb * sizeof(int), hipMemcpyDeviceToHost, s));
     sync(c);
@@ -611,59 +611,49 @@ void build_rhs_markers(ibr_ctx* c) {
 // Bodies overlap (Sec. 2 takes them disjoint; Sec. 5.3: markers closer than
 // about h/2 make the mobility too ill-conditioned to solve) when a marker of
 // one body lies closer than h to a marker of another: the two kernels then
-// nearly coincide.  Host cell list of side h, minimum image along periodic
-// axes; throws IBR_EINVAL naming the two bodies.
-void check_overlap(int d, int n, double h, double L, bool walls, int nb, const int* off, const double* R) {
+// nearly coincide.  Only pairs of bodies whose bounding spheres (about the
+// given centres, minimum image along periodic axes) come within h of each
+// other are compared marker by marker.  Throws IBR_EINVAL naming the bodies.
+void check_overlap(int d, double h, double L, bool walls, int nb, const int* off, const double* R,
+                   const double* X) {
   if (nb < 2) return;
-  const int N = off[nb];
-  std::vector<int> body(N);
-  for (int b = 0; b < nb; ++b)
-    for (int i = off[b]; i < off[b + 1]; ++i) body[i] = b;
-  auto cell_axis = [&](double x) {
-    double w = x - L * std::floor(x / L);
-    int ci = (int)std::floor(w / h);
-    return ci < 0 ? 0 : (ci >= n ? n - 1 : ci);
+  auto delta = [&](const double* a, const double* b, int ax) {
+    double dx = a[ax] - b[ax];
+    if (!(walls && ax == d - 1)) dx -= L * std::nearbyint(dx / L);
+    return dx;
   };
-  std::vector<std::pair<int64_t, int>> key(N);
-  for (int i = 0; i < N; ++i) {
-    int64_t k = 0;
-    for (int a = d - 1; a >= 0; --a) k = k * n + cell_axis(R[(int64_t)i * d + a]);
-    key[i] = {k, i};
-  }
-  std::sort(key.begin(), key.end());
-  const double h2 = h * h;
-  int cc[3];
-  for (int i = 0; i < N; ++i) {
-    for (int a = 0; a < d; ++a) cc[a] = cell_axis(R[(int64_t)i * d + a]);
-    const int nn = d == 3 ? 27 : 9;
-    for (int t = 0; t < nn; ++t) {
-      int o[3] = {t % 3 - 1, (t / 3) % 3 - 1, t / 9 - 1};
-      int64_t k = 0;
-      bool skip = false;
-      for (int a = d - 1; a >= 0; --a) {
-        int ci = cc[a] + o[a];
-        if (walls && a == d - 1 && (ci < 0 || ci >= n)) skip = true;
-        ci = (ci + n) % n;
-        k = k * n + ci;
+  std::vector<double> rad(nb, 0.0);
+  for (int p = 0; p < nb; ++p)
+    for (int i = off[p]; i < off[p + 1]; ++i) {
+      double r2 = 0;
+      for (int a = 0; a < d; ++a) {
+        const double dx = delta(R + (int64_t)i * d, X + (int64_t)p * d, a);
+        r2 += dx * dx;
       }
-      if (skip) continue;
-      auto it = std::lower_bound(key.begin(), key.end(), std::make_pair(k, -1));
-      for (; it != key.end() && it->first == k; ++it) {
-        const int j = it->second;
-        if (j <= i || body[j] == body[i]) continue;
-        double r2 = 0;
-        for (int a = 0; a < d; ++a) {
-          double dx = R[(int64_t)i * d + a] - R[(int64_t)j * d + a];
-          if (!(walls && a == d - 1)) dx -= L * std::nearbyint(dx / L);
-          r2 += dx * dx;
-        }
-        if (r2 < h2)
-          throw Status(IBR_EINVAL, "bodies " + std::to_string(body[i]) + " and " + std::to_string(body[j]) +
-                                       " overlap: markers " + std::to_string(i) + " and " + std::to_string(j) +
-                                       " are closer than h");
-      }
+      rad[p] = std::max(rad[p], std::sqrt(r2));
     }
-  }
+  const double h2 = h * h;
+  for (int p = 0; p < nb; ++p)
+    for (int q = p + 1; q < nb; ++q) {
+      double c2 = 0;
+      for (int a = 0; a < d; ++a) {
+        const double dx = delta(X + (int64_t)p * d, X + (int64_t)q * d, a);
+        c2 += dx * dx;
+      }
+      if (std::sqrt(c2) > rad[p] + rad[q] + h) continue;
+      for (int i = off[p]; i < off[p + 1]; ++i)
+        for (int j = off[q]; j < off[q + 1]; ++j) {
+          double r2 = 0;
+          for (int a = 0; a < d; ++a) {
+            const double dx = delta(R + (int64_t)i * d, R + (int64_t)j * d, a);
+            r2 += dx * dx;
+          }
+          if (r2 < h2)
+            throw Status(IBR_EINVAL, "bodies " + std::to_string(p) + " and " + std::to_string(q) +
+                                         " overlap: markers " + std::to_string(i) + " and " + std::to_string(j) +
+                                         " are closer than h");
+        }
+    }
 }
 
 template <typename F>
@@ -991,7 +981,7 @@ ibr_status ibr_set_bodies(ibr_ctx* c, int nbodies, const int* offsets, const dou
       if (!std::isfinite(R[i])) throw Status(IBR_EINVAL, "marker positions must be finite");
     for (int64_t i = 0; i < (int64_t)nbodies * d; ++i)
       if (!std::isfinite(centres[i])) throw Status(IBR_EINVAL, "centres must be finite");
-    check_overlap(d, c->n, c->h, c->L, c->walls, nbodies, offsets, R);
+    check_overlap(d, c->h, c->L, c->walls, nbodies, offsets, R, centres);
     if (c->walls) {
       for (int64_t m = 0; m < N; ++m) {
         const double z = R[m * d + d - 1];
@@ -1085,7 +1075,7 @@ ibr_status ibr_set_bodies(ibr_ctx* c, int nbodies, const int* offsets, const dou
     IBR_HIP(hipMemcpyAsync(c->X, centres, (size_t)nbodies * d * sizeof(double), hipMemcpyHostToDevice, s));
     IBR_HIP(hipMemcpyAsync(c->body_d, body.data(), N * sizeof(int), hipMemcpyHostToDevice, s));
     IBR_HIP(hipMemcpyAsync(c->moff_d, c->moff_h.data(), (nbodies + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
-    launch_fill<double>(c->Mb, mtot, 0.0, s);
+    // (the blocks' padding rows and columns are never read: no fill)
     launch_fill<double>(c->U, (int64_t)nbodies * d, 0.0, s);
     launch_fill<double>(c->Om, (int64_t)nbodies * 3, 0.0, s);
     // positions are wrapped into the box by the marker set-up kernel's taps; keep R itself wrapped too
