@@ -91,6 +91,8 @@ struct ibr_ctx {
   int *act_d = nullptr, *fail_d = nullptr;
   std::vector<double> shift_h;
   int max_np = 0, max_rows = 0;
+  int nbcap = 0;      // bodies the body-sized buffers hold
+  int64_t mcap = 0;   // doubles each mobility-block buffer holds
   double f0 = 1.0;
   MobParams mp{};
 
@@ -741,6 +743,8 @@ void ibr_ctx::free_markers() {
   Vb = nullptr;
   Zb = nullptr;
   lamd = dU = nullptr;
+  nbcap = 0;
+  mcap = 0;
 }
 
 void ibr_ctx::alloc_grid() {
@@ -1005,29 +1009,37 @@ ibr_status ibr_set_bodies(ibr_ctx* c, int nbodies, const int* offsets, const dou
     }
     IBR_HIP(hipSetDevice(c->p.device));
     sync(c);
-    // body-sized buffers are rebuilt every call (set-up, not the solve path)
+    // body-sized buffers grow with the body count and the blocks' size and are
+    // reused otherwise (a served request brings new bodies: no allocation
+    // unless they need more room than any before); tile buffers depend on
+    // the grid only
     auto drop = [](auto*& q) {
       dev_free((void*)q);
       q = nullptr;
     };
-    drop(c->off_d);
-    drop(c->X);
-    drop(c->U);
-    drop(c->Om);
-    drop(c->counts);
-    drop(c->toff);
-    drop(c->cursor);
-    drop(c->flags);
-    drop(c->active);
-    drop(c->nactive_d);
-    drop(c->moff_d);
-    drop(c->Mb);
-    drop(c->Lb);
-    drop(c->Xb);
-    drop(c->Minv);
-    drop(c->shift_d);
-    drop(c->act_d);
-    drop(c->fail_d);
+    int64_t mtot = 0;
+    for (int b = 0; b < nbodies; ++b) {
+      const int64_t ld = ((int64_t)d * (offsets[b + 1] - offsets[b]) + 15) & ~(int64_t)15;
+      mtot += ld * ld;
+    }
+    if (nbodies > c->nbcap) {
+      drop(c->off_d);
+      drop(c->X);
+      drop(c->U);
+      drop(c->Om);
+      drop(c->moff_d);
+      drop(c->shift_d);
+      drop(c->act_d);
+      drop(c->fail_d);
+      c->nbcap = 0;
+    }
+    if (mtot > c->mcap) {
+      drop(c->Mb);
+      drop(c->Lb);
+      drop(c->Xb);
+      drop(c->Minv);
+      c->mcap = 0;
+    }
     c->N = 0;
     c->clear_free();
     c->drop_graphs();
@@ -1040,16 +1052,25 @@ ibr_status ibr_set_bodies(ibr_ctx* c, int nbodies, const int* offsets, const dou
     c->NV = c->NF + (int64_t)d * N;
     c->ldv = (c->NV + 63) & ~(int64_t)63;
     c->off_h.assign(offsets, offsets + nbodies + 1);
-    c->off_d = dev_alloc<int>(nbodies + 1);
-    c->X = dev_alloc<double>((int64_t)nbodies * d);
-    c->U = dev_alloc<double>((int64_t)nbodies * d);
-    c->Om = dev_alloc<double>((int64_t)nbodies * 3);
-    c->counts = dev_alloc<int>(c->ntiles);
-    c->toff = dev_alloc<int>(c->ntiles + 1);
-    c->cursor = dev_alloc<int>(c->ntiles);
-    c->flags = dev_alloc<int>(c->ntiles);
-    c->active = dev_alloc<int>(c->ntiles);
-    c->nactive_d = dev_alloc<int>(1);
+    if (c->nbcap == 0) {
+      c->off_d = dev_alloc<int>(nbodies + 1);
+      c->X = dev_alloc<double>((int64_t)nbodies * d);
+      c->U = dev_alloc<double>((int64_t)nbodies * d);
+      c->Om = dev_alloc<double>((int64_t)nbodies * 3);
+      c->moff_d = dev_alloc<int64_t>(nbodies + 1);
+      c->shift_d = dev_alloc<double>(nbodies);
+      c->act_d = dev_alloc<int>(nbodies);
+      c->fail_d = dev_alloc<int>(nbodies);
+      c->nbcap = nbodies;
+    }
+    if (!c->counts) {
+      c->counts = dev_alloc<int>(c->ntiles);
+      c->toff = dev_alloc<int>(c->ntiles + 1);
+      c->cursor = dev_alloc<int>(c->ntiles);
+      c->flags = dev_alloc<int>(c->ntiles);
+      c->active = dev_alloc<int>(c->ntiles);
+      c->nactive_d = dev_alloc<int>(1);
+    }
     std::vector<int> body(N);
     for (int b = 0; b < nbodies; ++b)
       for (int i = offsets[b]; i < offsets[b + 1]; ++i) body[i] = b;
@@ -1060,15 +1081,13 @@ ibr_status ibr_set_bodies(ibr_ctx* c, int nbodies, const int* offsets, const dou
       const int64_t ld = ((int64_t)d * (offsets[b + 1] - offsets[b]) + 15) & ~(int64_t)15;
       c->moff_h[b + 1] = c->moff_h[b] + ld * ld;
     }
-    const int64_t mtot = c->moff_h[nbodies];
-    c->moff_d = dev_alloc<int64_t>(nbodies + 1);
-    c->Mb = dev_alloc<double>(mtot);
-    c->Lb = dev_alloc<double>(mtot);
-    c->Xb = dev_alloc<double>(mtot);
-    c->Minv = dev_alloc<double>(mtot);
-    c->shift_d = dev_alloc<double>(nbodies);
-    c->act_d = dev_alloc<int>(nbodies);
-    c->fail_d = dev_alloc<int>(nbodies);
+    if (c->mcap == 0) {
+      c->Mb = dev_alloc<double>(mtot);
+      c->Lb = dev_alloc<double>(mtot);
+      c->Xb = dev_alloc<double>(mtot);
+      c->Minv = dev_alloc<double>(mtot);
+      c->mcap = mtot;
+    }
     hipStream_t s = c->stream;
     IBR_HIP(hipMemcpyAsync(c->off_d, offsets, (nbodies + 1) * sizeof(int), hipMemcpyHostToDevice, s));
     IBR_HIP(hipMemcpyAsync(c->R, R, (size_t)N * d * sizeof(double), hipMemcpyHostToDevice, s));
