@@ -543,3 +543,120 @@ def ps_inv(g, hp, c0, eta, h, walls, nu_pre=2, nu_post=2, nu_coarse=4):
     v = v + h * grad(phi, 1.0, walls)
     pi = -c0 * h * h * phi + eta * q
     return v, pi
+
+
+# ---------------------------------------------------------------- unsteady steps in the box
+def advection(v, h, walls):
+    """The centred advective form of ``navier.advection`` with the walls'
+    extension on every walled axis: a tangential component's neighbour across
+    a wall is its mirror image with the sign reversed; the normal components'
+    wall faces hold 0 (so the averaged normal velocities and their own
+    differences need no ghost); the normal components' rows on their wall
+    faces are 0."""
+    d = v.shape[0]
+    n = v.shape[-1]
+    out = np.zeros_like(v)
+    for a in range(d):
+        ka = field_kinds(d, walls, a)
+        axa = d - 1 - a
+        acc = np.zeros_like(v[a])
+        for b in range(d):
+            axb = d - 1 - b
+            if b == a:
+                vb = v[a]
+            else:
+                kb = field_kinds(d, walls, b)
+                # v^b at c, c + e_b, c - e_a, c - e_a + e_b
+                vm = nbr(v[b], -1, axa, kb[axa])
+                vb = 0.25 * (v[b] + nbr(v[b], 1, axb, kb[axb]) + vm + nbr(vm, 1, axb, kb[axb]))
+            acc += vb * (nbr(v[a], 1, axb, ka[axb]) - nbr(v[a], -1, axb, ka[axb])) / (2.0 * h)
+        acc[wall_mask(n, d, walls, a)] = 0.0
+        out[a] = acc
+    return out
+
+
+def face_velocity(v, a, walls):
+    """``navier.face_velocity`` with the walls' extension."""
+    d = v.shape[0]
+    axa = d - 1 - a
+    out = []
+    for b in range(d):
+        if b == a:
+            out.append(v[a])
+        else:
+            kb = field_kinds(d, walls, b)
+            axb = d - 1 - b
+            vm = nbr(v[b], -1, axa, kb[axa])
+            out.append(0.25 * (v[b] + nbr(v[b], 1, axb, kb[axb]) + vm + nbr(vm, 1, axb, kb[axb])))
+    return out
+
+
+def _fold(kinds, n):
+    """Index map of E along each array axis for any integer index (repeated
+    mirroring has period 2n; periodic axes wrap)."""
+    def fold(ax, j):
+        kind = kinds[ax]
+        if kind == PER:
+            return np.mod(j, n), np.ones(j.shape)
+        jm = np.mod(j, 2 * n)
+        if kind == FACE_DIR:
+            idx = np.where(jm <= n, jm, 2 * n - jm)
+            sgn = np.where(jm < n, 1.0, -1.0)
+            sgn = np.where((jm == 0) | (jm == n), 0.0, sgn)
+            return np.where(idx == n, 0, idx), sgn
+        idx = np.where(jm < n, jm, 2 * n - 1 - jm)
+        sgn = np.where(jm < n, 1.0, -1.0 if kind == CELL_DIR else 1.0)
+        return idx, sgn
+    return fold
+
+
+def advection_sl(v, h, dt, walls):
+    """N = (v - v_departure) / dt in the box: the departure point of each face
+    from its face velocity (wall rules), the interpolation reading the lattice
+    through E on every walled axis; the wall rows are 0."""
+    from . import navier
+    d, n = v.shape[0], v.shape[-1]
+    vd = np.zeros_like(v)
+    idx = np.indices(v.shape[1:]).astype(np.float64)
+    for a in range(d):
+        u = face_velocity(v, a, walls)
+        sl = [idx[ax] - dt * u[d - 1 - ax] / h for ax in range(d)]
+        vd[a] = navier.interp_lattice(v[a], sl, _fold(field_kinds(d, walls, a), n))
+    N = (v - vd) / dt
+    for a in range(d):
+        N[a][wall_mask(n, d, walls, a)] = 0.0
+    return N
+
+
+def run(prob, nsteps, walls=None, scheme="centred", **kw):
+    """Exact constrained solves along a trajectory in the box (the steps of
+    ``navier.run``: AB2 advection or semi-Lagrangian transport, backward
+    Euler viscosity, bodies translated before each solve)."""
+    from . import navier
+    d, n, h = prob.dim, prob.n, prob.h
+    walls = all_walls(d) if walls is None else normalise(walls, d)
+    v = np.zeros((d,) + (n,) * d)
+    N_prev = None
+    R = prob.R.copy()
+    centres = prob.centres.copy()
+    out = []
+    b = ib.body_of(prob.offsets)
+    c0 = prob.rho / prob.dt
+    for step in range(nsteps):
+        if scheme == "sl":
+            N_n = advection_sl(v, h, prob.dt, walls)
+            g = navier.rhs(v, N_n, None, prob.rho, prob.dt, first=True)
+        else:
+            N_n = advection(v, h, walls)
+            g = navier.rhs(v, N_n, N_prev, prob.rho, prob.dt, first=(step == 0))
+        for a in range(d):
+            g[a][wall_mask(n, d, walls, a)] = 0.0
+        R = R + prob.dt * prob.U[b]
+        centres = centres + prob.dt * prob.U
+        sysm = System(d, n, h, c0, prob.eta, R, walls)
+        V = ib.marker_velocities(R, prob.offsets, centres, prob.U, prob.Omega, prob.L)
+        sol = constrained.solve(sysm, g, None, -V, prob.offsets, centres, **kw)
+        out.append(sol)
+        N_prev = N_n
+        v = sol.v
+    return out

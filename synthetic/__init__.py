@@ -25,5 +25,7 @@ from .workloads import (  # noqa: F401
     single_shell,
     slit_problem,
     slit_shell,
+    box_problem,
+    box_shell,
     array_shell,
 )

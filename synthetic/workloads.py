@@ -36,7 +36,8 @@ class Problem:
     radius     [nb] geometric radii (for reporting only)
     nsteps     number of time steps the trajectory was checked for
     walls      0: periodic box; 1: no-slip walls at both ends of the last axis
-               (z in 3D, y in 2D), periodic along the others
+               (z in 3D, y in 2D), periodic along the others; 2: no-slip
+               walls on every side
     """
 
     dim: int
@@ -54,7 +55,7 @@ class Problem:
     nsteps: int = 0
     name: str = ""
     meta: dict = field(default_factory=dict)
-    walls: int = 0     # 1: no-slip walls at both ends of the last axis (slit channel)
+    walls: int = 0     # 1: walls at both ends of the last axis (slit channel); 2: every side
 
     @property
     def L(self) -> float:
@@ -272,7 +273,8 @@ def sedimentation_problem(seed: int = 0, n: int = 128, nbodies: int = 16, radius
     return prob, F, np.zeros((nbodies, 3))
 
 
-def concentric_shells(n: int = 64, level: int = 1, V: float = 1.0, box_over_outer: float = 4.15) -> Problem:
+def concentric_shells(n: int = 64, level: int = 1, V: float = 1.0, box_over_outer: float = 4.15,
+                      walls: bool = False) -> Problem:
     """Two concentric icosahedral shells in a periodic unit cube, 3D steady
     Stokes, eta = 1 (the setting of the paper's concentric-shells study):
     outer radius R2 = 1 / box_over_outer, inner radius R1 = R2 / 4; inner shell
@@ -283,15 +285,19 @@ def concentric_shells(n: int = 64, level: int = 1, V: float = 1.0, box_over_oute
     cavity, so that the fluid outside the outer shell stays nearly at rest in
     the periodic box, as the paper's boundary conditions make it.  Levels 0, 1,
     2 give 12/162, 42/642 and 162/2562 markers, spaced about 2h at n = 32, 64,
-    128."""
+    128.  walls: the closed box of the paper's study instead (no-slip walls on
+    every side; its walls move with the cavity, so they rest in the cavity's
+    frame)."""
     h = 1.0 / n
     R2 = 1.0 / box_over_outer
     R1 = R2 / 4.0
     c = np.array([0.5, 0.5, 0.5])
     bodies = [icosphere_unit(level) * R1 + c, icosphere_unit(level + 2) * R2 + c]
     U = np.array([[-V, 0.0, 0.0], [0.0, 0.0, 0.0]])
-    return _assemble(3, n, h, 0.0, 1.0, 0.0, bodies, np.stack([c, c]), U, np.zeros((2, 3)), [R1, R2], 0,
-                     "shells_%d_l%d" % (n, level))
+    prob = _assemble(3, n, h, 0.0, 1.0, 0.0, bodies, np.stack([c, c]), U, np.zeros((2, 3)), [R1, R2], 0,
+                     "shells_%d_l%d%s" % (n, level, "_box" if walls else ""))
+    prob.walls = 2 if walls else 0
+    return prob
 
 
 def single_shell(n: int = 64, level: int = 1, V: float = 1.0, box_over_outer: float = 4.15) -> Problem:
@@ -441,6 +447,68 @@ def slit_problem(seed: int = 0, dim: int = 3, n: int = 32, nbodies: int = 2, rad
     prob = _assemble(dim, n, h, rho, eta, dt, bodies, centres, U, Om, [rad] * nbodies, 0,
                      "slit_%dd_%d" % (dim, n))
     prob.walls = 1
+    return prob
+
+
+def box_problem(seed: int = 0, dim: int = 3, n: int = 16, nbodies: int = 2, radius_h: float = 2.5,
+                eta: float = 1.0, gap_h: float = 3.0, wall_gap_h: float = 1.0, rotate: bool = True,
+                L: float = 1.0, rho: float = 0.0, dt: float = 0.0) -> Problem:
+    """Stokes (rho = 0) or unsteady (rho, dt > 0) flow in a closed box: no-slip
+    walls on every side; bodies as in ``small_problem``, every surface at
+    least ``wall_gap_h`` cells from every wall and ``gap_h`` cells from the
+    other bodies (plain distances: nothing wraps)."""
+    rng = np.random.default_rng(seed)
+    h = L / n
+    rad = radius_h * h
+    U = rng.uniform(-1.0, 1.0, size=(nbodies, dim))
+    lo = rad + wall_gap_h * h
+    centres = np.zeros((nbodies, dim))
+    placed = 0
+    tries = 0
+    while placed < nbodies:
+        tries += 1
+        if tries > 200000:
+            raise RuntimeError("could not place %d bodies in the box" % nbodies)
+        c = rng.uniform(lo, L - lo, size=dim)
+        if all(np.sqrt(((c - centres[q]) ** 2).sum()) >= 2 * rad + gap_h * h for q in range(placed)):
+            centres[placed] = c
+            placed += 1
+    if dim == 3:
+        Om = rng.uniform(-1.0, 1.0, size=(nbodies, 3)) if rotate else np.zeros((nbodies, 3))
+        bodies = [fibonacci_sphere(sphere_markers_for(radius_h), rad, c) for c in centres]
+    else:
+        Om = rng.uniform(-1.0, 1.0, size=(nbodies, 1)) if rotate else np.zeros((nbodies, 1))
+        bodies = [disk_ring(disk_markers_for(radius_h), rad, c, rng.uniform(0, 2 * math.pi)) for c in centres]
+    prob = _assemble(dim, n, h, rho, eta, dt, bodies, centres, U, Om, [rad] * nbodies, 0,
+                     "box_%dd_%d" % (dim, n))
+    prob.walls = 2
+    return prob
+
+
+def box_shell(n: int = 32, level: int = 2, box_over_radius: float = 4.35, V: float = 1.0,
+              filled: bool = False) -> Problem:
+    """The non-periodic runs of Sec. 7.1: one sphere of markers (an
+    icosahedral shell of 10 * 4^level + 2 markers, optionally filled with
+    interior shells like ``shell_problem``) at the centre of a closed box of
+    side about 4.35 sphere radii, no-slip walls on every side, translating
+    with V along x through the stationary fluid; steady Stokes, eta = 1."""
+    h = 1.0 / n
+    radius = 1.0 / box_over_radius
+    c = np.full(3, 0.5)
+    shell = icosphere_unit(level)
+    pts = [shell * radius + c]
+    if filled:
+        # interior shells as in shell_problem: the surface's mean spacing apart
+        spacing = icosphere_spacing(level) * radius
+        r = radius - spacing
+        while r > 0.5 * spacing:
+            pts.append(fibonacci_sphere(max(1, int(round(len(shell) * (r / radius) ** 2))), r, c))
+            r -= spacing
+        pts.append(c[None, :].copy())
+    prob = _assemble(3, n, h, 0.0, 1.0, 0.0, [np.concatenate(pts)], c[None, :].copy(),
+                     np.array([[V, 0.0, 0.0]]), np.zeros((1, 3)), [radius], 0,
+                     "box_shell_%d_l%d%s" % (n, level, "_filled" if filled else ""))
+    prob.walls = 2
     return prob
 
 

@@ -230,3 +230,38 @@ def test_constrained_solve_meets_the_system(d):
     assert np.abs(u[:, 1:]).max() < 1e-9 * np.abs(v).max()   # tangential components vanish
     with pytest.raises(ValueError):
         box.System(d, n, h, c0, 1.0, R - 0.5, wl)
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_advection_reproduces_the_slit_and_follows_the_axes(d):
+    rng = np.random.default_rng(8)
+    n = 8
+    h, dt = 1.0 / n, 0.02
+    wl = (False,) * (d - 1) + (True,)
+    v = rng.standard_normal((d,) + (n,) * d)
+    v[d - 1][0] = 0.0
+    assert np.abs(box.advection(v, h, wl) - walls.advection(v, h)).max() < 1e-13 * np.abs(v).max() ** 2 / h
+    assert np.abs(box.advection_sl(v, h, dt, wl) - walls.advection_sl(v, h, dt)).max() < 1e-12 / dt
+    if d == 3:
+        # walls on x and z; swapping x and y maps the terms onto themselves
+        wa, wb = (True, False, True), (False, True, True)
+        v = rng.standard_normal((d,) + (n,) * d)
+        for a in range(d):
+            v[a][box.wall_mask(n, d, wa, a)] = 0.0
+        vs = np.swapaxes(v[[1, 0, 2]], 2, 3)
+        for fa, fb in ((box.advection(v, h, wa), box.advection(vs, h, wb)),
+                       (box.advection_sl(v, h, dt, wa), box.advection_sl(vs, h, dt, wb))):
+            assert np.abs(np.swapaxes(fb[[1, 0, 2]], 2, 3) - fa).max() < 1e-12 * np.abs(fa).max()
+
+
+def test_box_steps_reproduce_the_slit():
+    """Two unsteady steps with walls on the last axis only equal the slit
+    oracle's trajectory (the box's stepping adds nothing of its own)."""
+    from synthetic import slit_problem
+    prob = slit_problem(5, dim=2, n=16, nbodies=1, radius_h=3.0, wall_gap_h=2.0, rotate=False,
+                        rho=1.0, dt=0.5 / 16, eta=0.05)
+    a = box.run(prob, 2, walls=(False, True))
+    b = walls.run(prob, 2)
+    for sa, sb in zip(a, b):
+        assert np.abs(sa.v - sb.v).max() < 1e-10 * np.abs(sb.v).max()
+        assert np.abs(sa.F - sb.F).max() < 1e-10 * np.abs(sb.F).max()
