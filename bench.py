@@ -76,6 +76,10 @@ def parse():
     ap.add_argument("--precision", choices=["both", "mixed", "fp64"], default="both")
     ap.add_argument("--serving", action="store_true",
                     help="serving workload instead: Poisson arrivals of mixed-size steady solves")
+    ap.add_argument("--ablation-parts", default="periodic,slit,box",
+                    help="ablation: comma-separated subset of periodic, slit, box")
+    ap.add_argument("--mobility-study", action="store_true",
+                    help="fitted vs analytic approximate mobility: P_S^-1 applications (not the headline)")
     ap.add_argument("--ablation", action="store_true",
                     help="solver study instead: preconditioner variant and N_s vs P_S^-1 applications")
     ap.add_argument("--nreq", type=int, default=2000, help="serving: requests in the trace")
@@ -721,10 +725,13 @@ def ablation(args, torch):
       (b) shells of 162 / 642 / 2562 markers in 32^3 / 64^3 / 128^3 (spacing
           2h), steady, N_s = 4, full and lower-triangular;
     and its non-periodic half in the slit channel (no-slip walls at z = 0
-    and z = 1): (a) for the empty 162-marker shell, steady, and (b);
-    fp64 and mixed precision, restart 100, with the solve time."""
+    and z = 1): (a) for the empty 162-marker shell, steady, and (b); and in
+    the paper's closed box (no-slip walls on every side, side 4.35 sphere
+    radii, the sphere at its centre): (a) for the empty and the filled
+    sphere, steady, and (b); fp64 and mixed precision, restart 100, with the
+    solve time."""
     from paper_1505_07865_amd import ibr
-    from synthetic import shell_problem
+    from synthetic import box_shell, shell_problem
     rows = []
 
     def run(prob, pc, ns, prec, rtol):
@@ -741,7 +748,8 @@ def ablation(args, torch):
                 "rtol": rtol, "iters": info["iters"], "ps_applications": info["ps_applications"],
                 "rel_residual": info["rel_residual"], "ms": round(ms, 3)}
 
-    for filled in (False, True):
+    parts = set(args.ablation_parts.split(","))
+    for filled in (False, True) if "periodic" in parts else ():
         for re in (0.0, 10.0):
             prob = shell_problem(args.seed, 32, 2, filled=filled, re=re)
             for pc in ("full", "lower"):
@@ -750,34 +758,108 @@ def ablation(args, torch):
                         rows.append(run(prob, pc, ns, "fp64", rtol))
                     rows.append(run(prob, pc, ns, "mixed", 1e-8))
             print("bench: ablation %s done" % prob.name, file=sys.stderr, flush=True)
-    for level, n in ((2, 32), (3, 64), (4, 128)):
+    for level, n in ((2, 32), (3, 64), (4, 128)) if "periodic" in parts else ():
         prob = shell_problem(args.seed, n, level)
         for pc in ("full", "lower"):
             for prec in ("fp64", "mixed"):
                 rows.append(run(prob, pc, 4, prec, 1e-8))
         print("bench: ablation %s done" % prob.name, file=sys.stderr, flush=True)
     # the non-periodic half, in the slit channel (no-slip walls at z = 0 and z = 1)
-    prob = shell_problem(args.seed, 32, 2, walls=True)
-    for pc in ("full", "lower"):
+    for pc in ("full", "lower") if "slit" in parts else ():
+        prob = shell_problem(args.seed, 32, 2, walls=True)
         for ns in (1, 2, 4, 8):
             rows.append(run(prob, pc, ns, "fp64", 1e-8))
             rows.append(run(prob, pc, ns, "mixed", 1e-8))
-    print("bench: ablation %s done" % prob.name, file=sys.stderr, flush=True)
-    for level, n in ((2, 32), (3, 64), (4, 128)):
+        print("bench: ablation %s %s done" % (prob.name, pc), file=sys.stderr, flush=True)
+    for level, n in ((2, 32), (3, 64), (4, 128)) if "slit" in parts else ():
         prob = shell_problem(args.seed, n, level, walls=True)
         for pc in ("full", "lower"):
             for prec in ("fp64", "mixed"):
                 rows.append(run(prob, pc, 4, prec, 1e-8))
         print("bench: ablation %s done" % prob.name, file=sys.stderr, flush=True)
-    best = min((r for r in rows if r["case"].startswith("shell_l2_empty_n32_re0") and r["rtol"] == 1e-8 and
-                r["precision"] == "fp64"), key=lambda r: r["ps_applications"])
+    # ... and in the paper's own non-periodic domain: the closed box (no-slip walls on every side, 4.35 radii)
+    for filled in (False, True) if "box" in parts else ():
+        prob = box_shell(32, 2, filled=filled)
+        for pc in ("full", "lower"):
+            for ns in (1, 2, 4, 8):
+                rows.append(run(prob, pc, ns, "fp64", 1e-8))
+                rows.append(run(prob, pc, ns, "mixed", 1e-8))
+        print("bench: ablation %s done" % prob.name, file=sys.stderr, flush=True)
+    for level, n in ((2, 32), (3, 64), (4, 128)) if "box" in parts else ():
+        prob = box_shell(n, level)
+        for pc in ("full", "lower"):
+            for prec in ("fp64", "mixed"):
+                rows.append(run(prob, pc, 4, prec, 1e-8))
+        print("bench: ablation %s done" % prob.name, file=sys.stderr, flush=True)
+    cand = [r for r in rows if r["rtol"] == 1e-8 and r["precision"] == "fp64"]
+    best = min([r for r in cand if r["case"].startswith("shell_l2_empty_n32_re0")] or cand,
+               key=lambda r: r["ps_applications"])
     line = {"metric": "P_S^-1 applications to relative residual 1e-8 (solver study, periodic)",
             "value": best["ps_applications"], "unit": "P_S^-1 applications", "n_gpus": 1,
             "higher_is_better": False, "vs_baseline": None, "data": "synthetic",
             "config": {"workload": "icosahedral shells (162/642/2562 markers, spacing 2h, empty or filled), "
                                    "periodic 32^3/64^3/128^3, steady and Re = 10, and the same shells in the "
-                                   "slit channel, restart 100",
+                                   "slit channel and in the closed box, restart 100",
                        "seed": args.seed, "best_case": best},
+            "rows": rows}
+    print(json.dumps(line), flush=True)
+
+
+def mobility_study(args, torch):
+    """The approximate mobility's effect on the solver (Secs. 4.2 and 5.3):
+    P_S^-1 applications and FGMRES iterations to relative residual 1e-8,
+    fp64, with the analytic M~ (RPY / Brinkmanlet readings) and with the
+    fitted M~ of Appendix A's forms, on
+      the solver study's shells (162 markers in 32^3, empty or filled,
+      steady and one Re = 10 step, beta = 0.36; lower-triangular
+      preconditioner, N_s = 2 and 4) and Sec. 7.1's shell in the closed box;
+      the 128^3 moving-spheres workload at Re = 10 (beta = 0.3): the first
+      three time steps, mixed precision as benchmarked;
+      the 256^3 configuration (steady, 100 spheres of 200 markers): one
+      solve from rest, mixed precision, restart 50."""
+    from paper_1505_07865_amd import ibr
+    from synthetic import box_shell, config2_spheres_ns, config4_spheres256, shell_problem
+    rows = []
+    mobs = (("analytic", ibr.MOB_ANALYTIC), ("fitted", ibr.MOB_FITTED))
+
+    def solve_row(prob, label, **kw):
+        for name, mob in mobs:
+            s = ibr.from_problem(prob, mobility=mob, graphs=0, **kw)
+            info = s.solve()
+            s.close()
+            rows.append({"case": label, "mobility": name, "iters": info["iters"],
+                         "ps_applications": info["ps_applications"], "rel_residual": info["rel_residual"],
+                         **{k: v for k, v in kw.items() if k in ("n_s", "precision")}})
+
+    for filled in (False, True):
+        for re in (0.0, 10.0):
+            prob = shell_problem(args.seed, 32, 2, filled=filled, re=re)
+            for ns in (2, 4):
+                solve_row(prob, prob.name, rtol=1e-8, pc=ibr.PC_LOWER, n_s=ns, max_iters=2000)
+            print("bench: mobility study %s done" % prob.name, file=sys.stderr, flush=True)
+    for filled in (False, True) if "box" in parts else ():
+        prob = box_shell(32, 2, filled=filled)
+        solve_row(prob, prob.name, rtol=1e-8, pc=ibr.PC_LOWER, n_s=4, max_iters=2000)
+    print("bench: mobility study box shells done", file=sys.stderr, flush=True)
+    prob = config2_spheres_ns(args.seed, re=10.0, n=128)
+    for name, mob in mobs:
+        s = ibr.from_problem(prob, mobility=mob, rtol=1e-8, precision=ibr.MIXED)
+        its, aps = [], []
+        for _ in range(3):
+            info = s.step()
+            its.append(info["iters"])
+            aps.append(info["ps_applications"])
+        s.close()
+        rows.append({"case": "spheres_ns_128_re10_steps1-3", "mobility": name, "iters": its, "ps_applications": aps,
+                     "precision": ibr.MIXED})
+    print("bench: mobility study 128^3 done", file=sys.stderr, flush=True)
+    prob = config4_spheres256(args.seed)
+    solve_row(prob, "spheres_256_steady", rtol=1e-8, precision=ibr.MIXED, restart=50, max_iters=400)
+    line = {"metric": "P_S^-1 applications to relative residual 1e-8, fitted vs analytic approximate mobility",
+            "value": None, "unit": "P_S^-1 applications", "n_gpus": 1, "higher_is_better": False,
+            "vs_baseline": None, "data": "synthetic",
+            "config": {"workload": "solver-study shells (periodic 32^3, closed box 32^3), 128^3 spheres at Re 10, "
+                                   "256^3 steady spheres", "seed": args.seed},
             "rows": rows}
     print(json.dumps(line), flush=True)
 
@@ -801,6 +883,9 @@ def main():
         return
     if args.ablation:
         ablation(args, torch)
+        return
+    if args.mobility_study:
+        mobility_study(args, torch)
         return
     if args.free:
         free_kinematics(args, torch)

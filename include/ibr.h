@@ -16,8 +16,10 @@
  *   grid      periodic box [0, n h)^dim, cells indexed (k, j, i) with i (x)
  *             fastest; cell centres at ((i+1/2)h, (j+1/2)h, (k+1/2)h).  With
  *             walls = IBR_WALLS_NOSLIP the last axis (z in 3D, y in 2D) ends
- *             at no-slip walls at 0 and n h instead of wrapping; the normal
- *             velocity's faces with index 0 along it lie on the wall and hold 0.
+ *             at no-slip walls at 0 and n h instead of wrapping; with
+ *             IBR_WALLS_BOX every axis does.  Along a walled axis the faces
+ *             of the velocity component normal to it with index 0 lie on the
+ *             wall and hold 0.
  *   velocity  u[dim][n^dim]: component a of cell c lives on the a-face half a
  *             cell below the centre along a (the MAC grid of Sec. 3).
  *   pressure  p[n^dim] at cell centres, returned with zero mean.
@@ -54,16 +56,25 @@ typedef enum {
 
 typedef enum { IBR_FP64 = 0, IBR_MIXED = 1 } ibr_precision;
 typedef enum { IBR_PC_LOWER = 0, IBR_PC_FULL = 1 } ibr_pc;
-/* Boundaries along the last axis: periodic, or no-slip walls at both ends
- * (the slit channel of Sec. 7; boundary rules of the appendix on physical
- * boundary conditions). */
-typedef enum { IBR_WALLS_NONE = 0, IBR_WALLS_NOSLIP = 1 } ibr_walls;
+/* Boundaries: periodic; no-slip walls at both ends of the last axis (the
+ * slit channel of Sec. 7); or no-slip walls on every side (the closed box of
+ * the non-periodic runs of Sec. 7.1 and of Sec. 7.3).  Boundary rules of the
+ * appendix on physical boundary conditions. */
+typedef enum { IBR_WALLS_NONE = 0, IBR_WALLS_NOSLIP = 1, IBR_WALLS_BOX = 2 } ibr_walls;
 /* Explicit advection of the unsteady step (Sec. 3; the paper cites an upwind
  * scheme without stating it).  CENTRED: the second-order advective form on
  * the MAC grid with Adams-Bashforth 2.  SL: semi-Lagrangian transport, each
  * face's value taken from the departure point x - dt u(x) by multilinear
  * interpolation; unconditionally bounded, first order. */
 typedef enum { IBR_ADVECT_CENTRED = 0, IBR_ADVECT_SL = 1 } ibr_advection;
+/* Approximate mobility M~ of the preconditioner (Sec. 4).  ANALYTIC: the RPY
+ * tensor with the periodic shift (steady 3D), the Brinkmanlet with a blended
+ * self term (finite beta), regularised logarithms (2D).  FITTED (3D only):
+ * the forms of Appendix A fitted to pair mobilities of the four-point kernel
+ * measured with this solver (the Sec. 4.2 procedure); at viscous CFL number
+ * beta = eta dt / (rho h^2) the table rows around beta are interpolated
+ * linearly, and beta above the last row uses the steady fit. */
+typedef enum { IBR_MOB_ANALYTIC = 0, IBR_MOB_FITTED = 1 } ibr_mobility;
 
 /* Problem and solver parameters.  Sec. 3.2 (eq. A_def) defines
  * A = (rho/dt) I - eta h^-2 L; rho == 0 selects steady Stokes, where the
@@ -89,9 +100,11 @@ typedef struct {
   void* stream;       /* hipStream_t to run on, or NULL for a library stream */
   int graphs;         /* 1 (default): replay each outer iteration as a captured
                          HIP graph; 0: plain stream launches (same kernels) */
-  int walls;          /* IBR_WALLS_NONE (default) or IBR_WALLS_NOSLIP: no-slip
+  int walls;          /* IBR_WALLS_NONE (default); IBR_WALLS_NOSLIP: no-slip
                          walls at both ends of the last axis, periodic along the
-                         others.  The tangential velocity's ghost values beyond
+                         others; IBR_WALLS_BOX: no-slip walls on every side.
+                         Along a walled axis the tangential velocity's ghost
+                         values beyond
                          a wall are its mirror image with the sign reversed,
                          the pressure's (inside the preconditioner) with the
                          sign kept; interpolation and spreading fold kernel taps
@@ -104,7 +117,9 @@ typedef struct {
                          nothing) when a body would cross a wall.  Between
                          walls P_S^-1 approximates the Stokes block less well
                          (Sec. 7.1): n_s = 4 is the robust choice for many
-                         markers. */
+                         markers.  Wall velocities are zero: a moving box is
+                         solved in its own frame (Stokes flow has no inertia
+                         to change with the frame). */
   int advection;      /* IBR_ADVECT_CENTRED (default) or IBR_ADVECT_SL.
                          CENTRED: N(v) = sum_b vbar^b (v^a_{c+e_b} -
                          v^a_{c-e_b}) / 2h with vbar^b the average of the four
@@ -118,6 +133,8 @@ typedef struct {
                          so that g = (rho/dt) v_d; stable at any cell Reynolds
                          number and CFL number.  ibr_advect returns the
                          selected form's N. */
+  int mobility;       /* IBR_MOB_ANALYTIC (default) or IBR_MOB_FITTED (3D only;
+                         IBR_EINVAL otherwise) */
 } ibr_params;
 
 /* Per-solve report.  ps_applications counts P_S^-1 applications, the cost
@@ -243,10 +260,10 @@ ibr_status ibr_interp(ibr_ctx* ctx, const double* u, double* V);
 /* One V-cycle (Sec. 5.2) for (c0 - c1 L) x = b on nfields independent
  * fields b[nfields][n^dim], x[nfields][n^dim]; c0 == 0 is the restricted
  * (mean-zero) inverse.  Runs in the context's precision.  With walls,
- * nfields == dim is the velocity cycle (components 0..dim-2 tangential, the
- * last one normal, its wall faces pinned to 0) and nfields == 1 the pressure
- * cycle (mirror with the sign kept; c0 == 0 is then the mean-zero inverse);
- * other counts return IBR_EINVAL. */
+ * nfields == dim is the velocity cycle (field a is component a: normal to the
+ * walls of axis a, its wall faces pinned to 0, and tangential to any other
+ * walls) and nfields == 1 the pressure cycle (mirror with the sign kept;
+ * c0 == 0 is then the mean-zero inverse); other counts return IBR_EINVAL. */
 ibr_status ibr_vcycle(ibr_ctx* ctx, double c0, double c1, int nfields, const double* b,
                       double* x);
 

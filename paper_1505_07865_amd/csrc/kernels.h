@@ -77,6 +77,8 @@ void launch_from_split(int dim, int logn, const TS* src, TD* dst, int nf, hipStr
 template <typename TZ, typename TX>
 void launch_combine_from_split(int dim, int logn, const TZ* Z, int64_t ld, int k, const double* y, TX* x, int nf,
                                bool assign, hipStream_t s);
+// walls: bit a = no-slip walls at both ends of axis a (0: periodic box)
+void launch_zero_wall_faces(int dim, int logn, double* v, int walls, hipStream_t s);
 void launch_advect(int dim, int logn, const double* v, double* N, double inv_2h, hipStream_t s, int walls = 0);
 void launch_advect_sl(int dim, int logn, const double* v, double* N, double dtoh, double inv_dt, hipStream_t s,
                       int walls = 0);
@@ -114,17 +116,18 @@ struct MGHier {
   // x0_tmp holds the pre-smoothed finest level when that level is fused)
   std::vector<T*> bufs_xo;
   T* x0_tmp = nullptr;
-  // slit channel (no-slip walls at both ends of the last axis): every level
-  // below the finest down to 4^dim in global memory (index 1 .. logn-2)
+  // no-slip walls (wall_mask bit b: walls at both ends of axis b): every
+  // level below the finest down to 4^dim in global memory (index 1 .. logn-2)
+  int wall_mask = 0;
   std::vector<T*> wall_x, wall_b;
   bool fused(int lg, int nu, int nf) const;
-  void init(int dim, int logn, int nfmax, bool walls = false);
+  void init(int dim, int logn, int nfmax, int wall_mask = 0);
   void release();
   static size_t bytes(int dim, int logn, int nf, bool walls = false);
   // One V-cycle for nf fields: x = V(b).  x and b hold nf fields of n^dim in
   // split (red half, black half) storage; see launch_to_split.  wall_mode 0:
-  // periodic; with walls 1: the velocity cycle (nf = dim: tangential
-  // components, then the normal one), 2: the pressure cycle (nf = 1).
+  // periodic; with walls 1: the velocity cycle (nf = dim: field f is
+  // component f), 2: the pressure cycle (nf = 1).
   void vcycle(int nf, const T* b, T* x, double c0, double c1, int nu_pre, int nu_post, int nu_coarse,
               hipStream_t s, int wall_mode = 0);
   void rb_half(T* x, const T* b, int lg, int nf, T c0, T c1, int color, bool fine, hipStream_t s);
@@ -132,12 +135,13 @@ struct MGHier {
   void rb_first(T* x, const T* b, int lg, int nf, T c0, T c1, bool fine, hipStream_t s);
 };
 
-// V-cycle with no-slip walls at both ends of the last axis (mode as in
-// MGHier::vcycle); wx, wb: per-level buffers 1 .. logn-2 (nf fields each).
+// V-cycle with no-slip walls at both ends of the axes in wm (bit b: axis b;
+// mode as in MGHier::vcycle); wx, wb: per-level buffers 1 .. logn-2 (nf
+// fields each).
 template <typename T>
 void launch_wall_vcycle(int dim, int logn, int nf, const T* b, T* x, const std::vector<T*>& wx,
                         const std::vector<T*>& wb, double c0, double c1, int nu_pre, int nu_post, int nu_coarse,
-                        int mode, hipStream_t s);
+                        int mode, int wm, hipStream_t s);
 
 // ---------------------------------------------------------------- free kinematics
 // Body block of the stacked vector: U[nb][dim] then Omega[nb][1 or 3].
@@ -262,6 +266,13 @@ struct MobParams {
   int dim;
   int steady;
   double a, eta, L, finf0, f00, alpha, dt_rho, periodic_shift;
+  // fitted forms (3D): 0 = the analytic readings; 1 = the steady fit (ah =
+  // a/h, fs = b0..b6); 2 = the finite-beta fit at viscous CFL number beta
+  // (phi0, fa = a0..a9, fb = b0..b5, interpolated between table rows)
+  // mean_mode: dt / (rho l^3), the uniform velocity a unit force gives the
+  // fluid of an unsteady periodic box, added to f by the fitted forms
+  int fit;
+  double h, beta, phi0, ah, mean_mode, fs[7], fa[10], fb[6];
 };
 void launch_mob_assemble(int dim, int nb, const int* offsets, const int64_t* moff, const double* R, MobParams p,
                          double* M, int max_np, hipStream_t s);

@@ -123,7 +123,8 @@ extern "C" ibr_status ibr_spread_noalloc(const ibr_params* p, int nmarkers, cons
       throw NoallocError{IBR_EINVAL, "n must be a power of two in [" + std::to_string(lo) + ", " +
                                          std::to_string(hi) + "]"};
     if (!(p->h > 0) || !std::isfinite(p->h)) throw NoallocError{IBR_EINVAL, "h must be > 0"};
-    if (p->walls != IBR_WALLS_NONE && p->walls != IBR_WALLS_NOSLIP) throw NoallocError{IBR_EINVAL, "bad walls"};
+    if (p->walls != IBR_WALLS_NONE && p->walls != IBR_WALLS_NOSLIP && p->walls != IBR_WALLS_BOX)
+      throw NoallocError{IBR_EINVAL, "bad walls"};
     if (p->device < 0 || p->device >= kMaxDevices) throw NoallocError{IBR_EINVAL, "bad device"};
     if (nmarkers < 0) throw NoallocError{IBR_EINVAL, "nmarkers must be >= 0"};
     if (!f) throw NoallocError{IBR_EINVAL, "f is required"};
@@ -168,8 +169,9 @@ extern "C" ibr_status ibr_spread_noalloc(const ibr_params* p, int nmarkers, cons
     int* active = (int*)(sc + L.active);
     int* nactive = (int*)(sc + L.nactive);
     const double len = p->n * p->h;
-    launch_marker_setup(d, logn, nmarkers, p->h, len, (const double*)R, taps, tile_of, tile_log, s,
-                        p->walls == IBR_WALLS_NOSLIP ? 1 : 0);
+    // walls along the last axis (slit) or every axis (box): one bit per axis
+    const int wm = p->walls == IBR_WALLS_NOSLIP ? 1 << (d - 1) : (p->walls == IBR_WALLS_BOX ? (1 << d) - 1 : 0);
+    launch_marker_setup(d, logn, nmarkers, p->h, len, (const double*)R, taps, tile_of, tile_log, s, wm);
     launch_bin_markers(nmarkers, (int)ntiles, tile_of, counts, toff, cursor, perm, s);
     launch_active_tiles(d, tiles_log, toff, flags, active, nactive, s);
     // a tile is active when one of its 3^d neighbours holds a marker: at most

@@ -54,10 +54,11 @@ struct Lat {
 // yv = A v + G p + addc, yp = -D v.   A = c0 I - ch2 L,  G, D with 1/h.
 // TI: storage type of the input, TO: of the output (arithmetic in TO).
 // Natural storage, one thread per cell.
-// walls: no-slip walls at both ends of the last axis (w = its coordinate):
-// a tangential component's neighbour beyond a wall is its mirror image with
-// the sign reversed (the cell itself, negated), the normal component's wall
-// faces hold 0 and are not equations (their rows are 0).
+// walls: bit b set = no-slip walls at both ends of axis b.  Along a walled
+// axis a tangential component's neighbour beyond a wall is its mirror image
+// with the sign reversed (the cell itself, negated); the normal component's
+// wall faces (index 0 along its own axis) hold 0 and are not equations
+// (their rows are 0), and face n is the other wall.
 template <typename TI, typename TO, int DIM>
 __global__ void __launch_bounds__(256) k_stokes_apply(const TI* __restrict__ v, const TI* __restrict__ p,
                                                       TO* __restrict__ yv, TO* __restrict__ yp, int logn,
@@ -70,6 +71,7 @@ __global__ void __launch_bounds__(256) k_stokes_apply(const TI* __restrict__ v, 
   const Lat<DIM> L{logn};
   int i, j, k;
   L.coords(t, i, j, k);
+  const int co[3] = {i, j, k};
   int m[3], pl[3];
   m[0] = L.index(i - 1, j, k);
   pl[0] = L.index(i + 1, j, k);
@@ -78,7 +80,6 @@ __global__ void __launch_bounds__(256) k_stokes_apply(const TI* __restrict__ v, 
   m[2] = DIM == 3 ? L.index(i, j, k - 1) : t;
   pl[2] = DIM == 3 ? L.index(i, j, k + 1) : t;
   const TO pc = (TO)p[t];
-  const int w = DIM == 3 ? k : j;
   const int n = 1 << logn;
   TO div = 0;
 #pragma unroll
@@ -91,14 +92,22 @@ __global__ void __launch_bounds__(256) k_stokes_apply(const TI* __restrict__ v, 
       nb[q][0] = (TO)va[m[q]];
       nb[q][1] = (TO)va[pl[q]];
     }
+    bool zero_row = false;
     if (walls) {
-      if (a == DIM - 1) {
-        if (w == 0) vc = TO(0);
-        if (w == 1) nb[DIM - 1][0] = TO(0);
-        if (w == n - 1) nb[DIM - 1][1] = TO(0);
-      } else {
-        if (w == 0) nb[DIM - 1][0] = -vc;
-        if (w == n - 1) nb[DIM - 1][1] = -vc;
+#pragma unroll
+      for (int b = 0; b < DIM; ++b) {
+        if (!((walls >> b) & 1)) continue;
+        if (b == a) {
+          if (co[b] == 0) {
+            vc = TO(0);
+            zero_row = true;
+          }
+          if (co[b] == 1) nb[b][0] = TO(0);
+          if (co[b] == n - 1) nb[b][1] = TO(0);
+        } else {
+          if (co[b] == 0) nb[b][0] = -vc;
+          if (co[b] == n - 1) nb[b][1] = -vc;
+        }
       }
     }
     // the Laplacian as a sum of neighbour differences: each difference of two
@@ -108,7 +117,7 @@ __global__ void __launch_bounds__(256) k_stokes_apply(const TI* __restrict__ v, 
     if (DIM == 3) lap += (nb[2][0] - vc) + (nb[2][1] - vc);
     TO out = c0 * vc - ch2 * lap + (pc - (TO)p[m[a]]) * inv_h;
     if (addc) out += (TO)addc[a];
-    if (walls && a == DIM - 1 && w == 0) out = TO(0);
+    if (zero_row) out = TO(0);
     yv[a * C + t] = out;
     div += (nb[a][1] - vc) * inv_h;
   }
@@ -133,7 +142,8 @@ __global__ void __launch_bounds__(256) k_div_q(const T* __restrict__ v, const T*
   q[t] = -div - (hp ? hp[t] : T(0));
 }
 
-// v <- v - vmean + h (phi_c - phi_{c-e_a});  pi = -c0 h^2 phi + eta q, natural storage.
+// v <- v - vmean + h (phi_c - phi_{c-e_a});  pi = -c0 h^2 phi + eta q, natural
+// storage; the normal components' wall faces stay 0 (walls: axis bits).
 template <typename T, int DIM>
 __global__ void __launch_bounds__(256) k_ps_finish(T* __restrict__ v, const T* __restrict__ phi,
                                                    const T* __restrict__ q, T* __restrict__ pi, int logn,
@@ -146,13 +156,14 @@ __global__ void __launch_bounds__(256) k_ps_finish(T* __restrict__ v, const T* _
   const Lat<DIM> L{logn};
   int i, j, k;
   L.coords(t, i, j, k);
+  const int co[3] = {i, j, k};
   const int m[3] = {L.index(i - 1, j, k), L.index(i, j - 1, k), DIM == 3 ? L.index(i, j, k - 1) : t};
   const T ph = phi[t];
-  const bool wall_face = walls && (DIM == 3 ? k : j) == 0;
 #pragma unroll
   for (int a = 0; a < DIM; ++a) {
     T mv = vmean ? (T)vmean[a] : T(0);
-    v[a * C + t] = (wall_face && a == DIM - 1) ? T(0) : v[a * C + t] - mv + h * (ph - phi[m[a]]);
+    const bool wall_face = ((walls >> a) & 1) && co[a] == 0;
+    v[a * C + t] = wall_face ? T(0) : v[a * C + t] - mv + h * (ph - phi[m[a]]);
   }
   pi[t] = -c0h2 * ph + eta * q[t];
 }
@@ -181,7 +192,8 @@ __device__ inline void st4(T* p, const Q4<T>& q) {
 template <int DIM>
 struct Group {
   int H, own, oth, xl, xr, ym, yp, zm, zp;
-  int w;     // coordinate along the last axis (the walls' axis)
+  int j, k;  // the group's row
+  int i0;    // x coordinate of its first cell; cell u sits at i0 + 2u
   bool odd;  // the group's cells sit at i = 2m + 1
   __device__ Group(int t, int logn) {
     const int C = 1 << (DIM * logn);
@@ -197,10 +209,10 @@ struct Group {
     const int u = ((t >> (lb + 1)) << lb) | (t & ((1 << lb) - 1));
     const int m0 = (u & ((1 << (hl - 2)) - 1)) << 2;
     const int row = u >> (hl - 2);
-    const int j = row & mask;
-    const int k = DIM == 3 ? (row >> logn) : 0;
+    j = row & mask;
+    k = DIM == 3 ? (row >> logn) : 0;
     odd = ((c + j + k) & 1) != 0;
-    w = DIM == 3 ? k : j;
+    i0 = 2 * m0 + (odd ? 1 : 0);
     const int ob = (1 - c) * H;
     own = c * H + (row << hl) + m0;
     oth = ob + (row << hl) + m0;
@@ -247,37 +259,58 @@ __global__ void __launch_bounds__(256) k_stokes_split4(const T* __restrict__ v, 
       vzm = ld4(va + g.zm);
       vzp = ld4(va + g.zp);
     }
-    bool zero_row = false;
+    // walls (axis bits): along y and z the group's 4 cells share the
+    // coordinate; along x each cell has its own
+    const int n = 1 << logn;
+    bool zero_rows = false;
     if (walls) {
-      // neighbours along the walls' axis: mirror images, or the wall faces' zeros
-      Q4<T>& wm = DIM == 3 ? vzm : vym;
-      Q4<T>& wp = DIM == 3 ? vzp : vyp;
-      const int n = 1 << logn;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        if (a == DIM - 1) {
-          if (g.w == 0) vc.v[u] = T(0);
-          if (g.w == 1) wm.v[u] = T(0);
-          if (g.w == n - 1) wp.v[u] = T(0);
-        } else {
-          if (g.w == 0) wm.v[u] = -vc.v[u];
-          if (g.w == n - 1) wp.v[u] = -vc.v[u];
+      for (int b = 1; b < DIM; ++b) {
+        if (!((walls >> b) & 1)) continue;
+        const int cb = b == 1 ? g.j : g.k;
+        Q4<T>& nm = b == 1 ? vym : vzm;
+        Q4<T>& np = b == 1 ? vyp : vzp;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if (b == a) {
+            if (cb == 0) vc.v[u] = T(0);
+            if (cb == 1) nm.v[u] = T(0);
+            if (cb == n - 1) np.v[u] = T(0);
+          } else {
+            if (cb == 0) nm.v[u] = -vc.v[u];
+            if (cb == n - 1) np.v[u] = -vc.v[u];
+          }
         }
+        if (b == a && cb == 0) zero_rows = true;
       }
-      zero_row = a == DIM - 1 && g.w == 0;
     }
     Q4<T> out;
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const T xl = odd ? vo.v[u] : (u == 0 ? ve : vo.v[u - 1]);
-      const T xr = odd ? (u == 3 ? ve : vo.v[u + 1]) : vo.v[u];
+      T xl = odd ? vo.v[u] : (u == 0 ? ve : vo.v[u - 1]);
+      T xr = odd ? (u == 3 ? ve : vo.v[u + 1]) : vo.v[u];
+      T c = vc.v[u];
+      bool zero_row = zero_rows;
+      if (walls & 1) {
+        const int iu = g.i0 + 2 * u;
+        if (a == 0) {
+          if (iu == 0) {
+            c = T(0);
+            zero_row = true;
+          }
+          if (iu == 1) xl = T(0);
+          if (iu == n - 1) xr = T(0);
+        } else {
+          if (iu == 0) xl = -c;
+          if (iu == n - 1) xr = -c;
+        }
+      }
       // neighbour differences (exact for nearby values; no cancellation of a sum)
-      const T c = vc.v[u];
       T lap = ((xl - c) + (xr - c)) + ((vym.v[u] - c) + (vyp.v[u] - c));
       if (DIM == 3) lap += (vzm.v[u] - c) + (vzp.v[u] - c);
-      out.v[u] = zero_row ? T(0) : c0 * vc.v[u] - ch2 * lap + (pc.v[u] - pm[a].v[u]) * inv_h;
+      out.v[u] = zero_row ? T(0) : c0 * c - ch2 * lap + (pc.v[u] - pm[a].v[u]) * inv_h;
       const T vplus = a == 0 ? xr : (a == 1 ? vyp.v[u] : vzp.v[u]);
-      div[u] += (vplus - vc.v[u]) * inv_h;
+      div[u] += (vplus - c) * inv_h;
     }
     st4(yv + a * C + g.own, out);
   }
@@ -331,7 +364,6 @@ __global__ void __launch_bounds__(256) k_ps_finish_split4(T* __restrict__ v, con
   const int t = (int)(xcd_block(gridDim.x) * blockDim.x + threadIdx.x);
   if (t >= (int)(C >> 2)) return;
   const Group<DIM> g(t, logn);
-  const bool wall_face = walls && g.w == 0;  // the normal component's wall faces stay 0
   const bool odd = g.odd;
   const Q4<T> ph = ld4(phi + g.own);
   Q4<T> pm[3];
@@ -347,9 +379,14 @@ __global__ void __launch_bounds__(256) k_ps_finish_split4(T* __restrict__ v, con
   for (int a = 0; a < DIM; ++a) {
     const T mv = vmean ? (T)vmean[a] : T(0);
     Q4<T> va = ld4(v + a * C + g.own);
+    // the normal component's wall faces (index 0 along its own walled axis) stay 0
+    const bool walled = (walls >> a) & 1;
+    const bool row_face = walled && a > 0 && (a == 1 ? g.j : g.k) == 0;
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
-      va.v[u] = (wall_face && a == DIM - 1) ? T(0) : va.v[u] - mv + h * (ph.v[u] - pm[a].v[u]);
+    for (int u = 0; u < 4; ++u) {
+      const bool wall_face = row_face || (walled && a == 0 && g.i0 + 2 * u == 0);
+      va.v[u] = wall_face ? T(0) : va.v[u] - mv + h * (ph.v[u] - pm[a].v[u]);
+    }
     st4(v + a * C + g.own, va);
   }
   const Q4<T> qq = ld4(q + g.own);
@@ -402,10 +439,10 @@ __global__ void __launch_bounds__(256) k_combine_from_split(const TZ* __restrict
 
 // Centred advective term N(v)^a = sum_b vbar^b (v^a_{c+e_b} - v^a_{c-e_b}) / (2h),
 // vbar^b the average of the four b-faces around the a-face (b != a).
-// walls: along the last axis a tangential component's neighbour beyond a
-// wall is its negated self; the normal component's wall faces hold 0, so the
-// averaged normal velocity and the normal component's own differences need
-// no ghost, and its rows on the wall faces are 0.
+// walls (axis bits): along a walled axis a tangential component's neighbour
+// beyond a wall is its negated self; the normal component's wall faces hold
+// 0, so the averaged normal velocity and the normal component's own
+// differences need no ghost, and its rows on the wall faces are 0.
 template <int DIM>
 __global__ void __launch_bounds__(256) k_advect(const double* __restrict__ v, double* __restrict__ N, int logn,
                                                 double inv_2h, int walls) {
@@ -413,12 +450,13 @@ __global__ void __launch_bounds__(256) k_advect(const double* __restrict__ v, do
   const int64_t c = xcd_block(gridDim.x) * blockDim.x + threadIdx.x;
   if (c >= C) return;
   const int n = 1 << logn;
+  const int mask = n - 1;
   const Nbr nb = neighbours<DIM>(c, logn);
-  const int w = (int)(c >> ((DIM - 1) * logn));  // coordinate along the last axis
+  const int co[3] = {(int)(c & mask), (int)((c >> logn) & mask), DIM == 3 ? (int)(c >> (2 * logn)) : 0};
 #pragma unroll
   for (int a = 0; a < DIM; ++a) {
     const double* va = v + a * C;
-    if (walls && a == DIM - 1 && w == 0) {
+    if (((walls >> a) & 1) && co[a] == 0) {
       N[a * C + c] = 0.0;
       continue;
     }
@@ -436,9 +474,9 @@ __global__ void __launch_bounds__(256) k_advect(const double* __restrict__ v, do
         vb = 0.25 * (wv[c] + wv[nb.p[b]] + wv[cm] + wv[nm.p[b]]);
       }
       double up = va[nb.p[b]], dn = va[nb.m[b]];
-      if (walls && b == DIM - 1 && a != DIM - 1) {
-        if (w == n - 1) up = -va[c];
-        if (w == 0) dn = -va[c];
+      if (((walls >> b) & 1) && a != b) {
+        if (co[b] == n - 1) up = -va[c];
+        if (co[b] == 0) dn = -va[c];
       }
       acc += vb * (up - dn) * inv_2h;
     }
@@ -446,7 +484,7 @@ __global__ void __launch_bounds__(256) k_advect(const double* __restrict__ v, do
   }
 }
 
-// Index and sign that lattice index j (any integer) reads along the walls'
+// Index and sign that lattice index j (any integer) reads along a walled
 // axis through the mirror extension: repeated mirroring has period 2n.  A
 // tangential component (cell-centred along the axis) is odd about each wall;
 // the normal component is odd about the wall faces 0 and n, which hold 0.
@@ -470,8 +508,8 @@ __device__ inline int wall_fold(int j, int n, bool normal, double& sign) {
 // along the face velocity of the advective form (v^a itself and the four-face
 // averages of the other components) to x - dt u, in lattice units the face
 // index minus dtoh u, and v_d is v^a interpolated there multilinearly on the
-// a-face lattice.  Periodic axes wrap with the power-of-two mask; along the
-// walls' axis the taps read through the mirror extension.  The displacement
+// a-face lattice.  Periodic axes wrap with the power-of-two mask; along a
+// walled axis the taps read through the mirror extension.  The displacement
 // is clamped to +-2^20 cells so every index stays on the lattice whatever
 // the velocity (a non-finite velocity still yields a non-finite N through
 // v^a at the same face, or at the neighbour that carries it).
@@ -491,7 +529,7 @@ __global__ void __launch_bounds__(256) k_advect_sl(const double* __restrict__ v,
 #pragma unroll
   for (int a = 0; a < DIM; ++a) {
     const double* va = v + a * C;
-    if (walls && a == DIM - 1 && coord[DIM - 1] == 0) {
+    if (((walls >> a) & 1) && coord[a] == 0) {
       N[a * C + c] = 0.0;
       continue;
     }
@@ -524,8 +562,8 @@ __global__ void __launch_bounds__(256) k_advect_sl(const double* __restrict__ v,
         const int o = (corner >> b) & 1;
         w *= o ? fr[b] : 1.0 - fr[b];
         int j = lo[b] + o;
-        if (walls && b == DIM - 1)
-          j = wall_fold(j, n, a == DIM - 1, sign);
+        if ((walls >> b) & 1)
+          j = wall_fold(j, n, a == b, sign);
         else
           j &= mask;
         idx = (idx << logn) | j;
@@ -534,6 +572,20 @@ __global__ void __launch_bounds__(256) k_advect_sl(const double* __restrict__ v,
     }
     N[a * C + c] = (va[c] - acc) * inv_dt;
   }
+}
+
+// Zero the normal components' wall faces (index 0 along a walled axis a of
+// component a); natural storage, one thread per cell.
+template <int DIM>
+__global__ void __launch_bounds__(256) k_zero_wall_faces(double* __restrict__ v, int logn, int walls) {
+  const int64_t C = (int64_t)1 << (DIM * logn);
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= C) return;
+  const int mask = (1 << logn) - 1;
+  const int co[3] = {(int)(c & mask), (int)((c >> logn) & mask), DIM == 3 ? (int)(c >> (2 * logn)) : 0};
+#pragma unroll
+  for (int a = 0; a < DIM; ++a)
+    if (((walls >> a) & 1) && co[a] == 0) v[a * C + c] = 0.0;
 }
 
 // g = (rho/dt) v - rho (w1 N1 + w0 N0)   (N0 may be null)
@@ -668,6 +720,14 @@ template void launch_combine_from_split<double, double>(int, int, const double*,
                                                         double*, int, bool, hipStream_t);
 template void launch_combine_from_split<float, float>(int, int, const float*, int64_t, int, const double*, float*,
                                                       int, bool, hipStream_t);
+
+void launch_zero_wall_faces(int dim, int logn, double* v, int walls, hipStream_t s) {
+  const int64_t C = (int64_t)1 << (dim * logn);
+  if (dim == 3)
+    hipLaunchKernelGGL(k_zero_wall_faces<3>, dim3(nblk(C)), dim3(256), 0, s, v, logn, walls);
+  else
+    hipLaunchKernelGGL(k_zero_wall_faces<2>, dim3(nblk(C)), dim3(256), 0, s, v, logn, walls);
+}
 
 void launch_advect(int dim, int logn, const double* v, double* N, double inv_2h, hipStream_t s, int walls) {
   const int64_t C = (int64_t)1 << (dim * logn);

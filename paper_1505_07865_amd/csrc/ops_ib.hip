@@ -17,7 +17,8 @@ inline unsigned nblk(int64_t len, int bs = 256) { return (unsigned)((len + bs - 
 __device__ inline int tap_base_index(int m, int s, int beta) { return (m * 2 + s) * 3 + beta; }
 
 // ---------------------------------------------------------------- marker set-up
-// walls: along the last axis the taps beyond a no-slip wall fold back onto
+// walls (bit beta = no-slip walls at both ends of axis beta): along a walled
+// axis the taps beyond a wall fold back onto
 // their mirror images with the sign reversed and taps on the wall faces of
 // the normal component are dropped (J = J0 E, S = E^T S0 with the extension
 // E of the appendix on physical boundary conditions); the folded taps are
@@ -71,7 +72,7 @@ __global__ void k_marker_setup(int dim, int logn, int N, double h, double L, con
       const int bi = tap_base_index(m, s, beta);
       double w[4];
       for (int t = 0; t < 4; ++t) w[t] = phi4<double>(sc - (double)(b0 + t));
-      if (walls && beta == dim - 1) fold_wall_taps(b0, w, n, s == 1);
+      if ((walls >> beta) & 1) fold_wall_taps(b0, w, n, s == 1);
       base[bi] = b0;
       for (int t = 0; t < 4; ++t) {
         w64[bi * 4 + t] = w[t];

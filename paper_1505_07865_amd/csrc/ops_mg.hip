@@ -581,8 +581,9 @@ template void launch_sub_field_mean<double>(double*, int, int64_t, const double*
 template void launch_sub_field_mean<float>(float*, int, int64_t, const double*, hipStream_t);
 
 template <typename T>
-void MGHier<T>::init(int dim_, int logn_, int maxf, bool walls) {
+void MGHier<T>::init(int dim_, int logn_, int maxf, int wall_mask_) {
   dim = dim_;
+  wall_mask = wall_mask_;
   logn = logn_;
   nfmax = maxf;
   levels.clear();
@@ -606,7 +607,7 @@ void MGHier<T>::init(int dim_, int logn_, int maxf, bool walls) {
   x0_tmp = (!levels.empty() && may_fuse<T>(dim, logn)) ? dev_alloc<T>(((int64_t)1 << (dim * logn)) * nfmax) : nullptr;
   wall_x.assign(logn > 2 ? logn - 1 : 1, nullptr);
   wall_b.assign(logn > 2 ? logn - 1 : 1, nullptr);
-  if (walls)
+  if (wall_mask)
     for (int l = 1; l <= logn - 2; ++l) {
       const int64_t Cl = (int64_t)1 << (dim * (logn - l));
       wall_x[l] = dev_alloc<T>(Cl * nfmax);
@@ -693,7 +694,8 @@ template <typename T>
 void MGHier<T>::vcycle(int nf, const T* b, T* x, double c0, double c1, int nu_pre, int nu_post, int nu_coarse,
                        hipStream_t s, int wall_mode) {
   if (wall_mode != 0) {
-    launch_wall_vcycle<T>(dim, logn, nf, b, x, wall_x, wall_b, c0, c1, nu_pre, nu_post, nu_coarse, wall_mode, s);
+    launch_wall_vcycle<T>(dim, logn, nf, b, x, wall_x, wall_b, c0, c1, nu_pre, nu_post, nu_coarse, wall_mode,
+                          wall_mask, s);
     return;
   }
   const bool three = dim == 3;

@@ -1,260 +1,298 @@
-// Multigrid V-cycle with no-slip walls at both ends of the last axis (z in
-// 3D, y in 2D), periodic along the others: the slit channel of Sec. 7 with
-// the boundary rules of the appendix on physical boundary conditions.
+// Multigrid V-cycle with no-slip walls at both ends of any set of axes (the
+// slit channel of Sec. 7 has them on the last axis; the box of Secs. 7.1 and
+// 7.3 on every side), periodic along the others, with the boundary rules of
+// the appendix on physical boundary conditions.
 //
 // Same cycle as the periodic one (red-black Gauss-Seidel, nu_pre sweeps from
 // zero, residual restriction, rediscretised coarse operator c0 - (c1/4) L,
 // prolongation, nu_post sweeps, nu_coarse sweeps on the 4^dim grid), with
-// the walls' rules per field kind along the wall axis:
+// per field and axis one of four kinds:
+//   periodic (no walls along the axis);
 //   tangential velocity (cell-centred, mirror with the sign reversed) and the
 //   pressure (cell-centred, mirror with the sign kept): a boundary cell's
 //   ghost neighbour is the cell itself, so it moves into the diagonal
-//   (c0 + (2 dim +- 1) c1); restriction averages the 2^dim children;
-//   prolongation is multilinear (3/4, 1/4) with the ghost coarse value;
-//   normal velocity (faces, the wall faces pinned to 0): vertex-centred along
-//   the wall axis, so coarse face K sits on fine face 2K; restriction weights
-//   the fine faces 2K-1, 2K, 2K+1 by 1/4, 1/2, 1/4 (and averages across the
-//   periodic axes); prolongation copies coarse faces onto the even fine faces
-//   and averages neighbours onto the odd ones (the wall faces get nothing).
-// The singular Neumann problem (pressure, c0 = 0) loses the mean of its
-// coarsest right-hand side; its finest right-hand side has zero mean when it
-// is a divergence, as in P_S^-1.
+//   (c0 + (2 dim +- 1) c1); restriction averages the 2 children along the
+//   axis; prolongation interpolates 3/4, 1/4 with the ghost coarse value;
+//   normal velocity along its own axis (faces, the wall faces pinned to 0):
+//   vertex-centred, so coarse face K sits on fine face 2K; restriction
+//   weights the fine faces 2K-1, 2K, 2K+1 by 1/4, 1/2, 1/4; prolongation
+//   copies coarse faces onto the even fine faces and averages neighbours onto
+//   the odd ones (the wall faces get nothing).
+// Transfers are tensor products of these one-dimensional rules.  The singular
+// Neumann problem (pressure, c0 = 0) loses the mean of its coarsest
+// right-hand side; its finest right-hand side has zero mean when it is a
+// divergence, as in P_S^-1.
 //
 // Fields are in split (red half, black half) storage like the periodic
 // hierarchy; these kernels take one cell per thread and address neighbours
-// through split_index: the walls change the stencil only in the two boundary
-// layers, and the slit path is not the bandwidth-tuned periodic one.  From
-// 4096 cells (16^3, 64^2) down, the cycle runs in one workgroup per field
-// with the levels in LDS (k_wvcycle_lds), on the same per-cell steps.
+// through split_index: the walls change the stencil only in the boundary
+// layers, and this path is not the bandwidth-tuned periodic one.  From 4096
+// cells (16^3, 64^2) down, the cycle runs in one workgroup per field with the
+// levels in LDS (k_wvcycle_lds), on the same per-cell steps.
 #include "kernels.h"
 
 namespace ibr {
 
 namespace {
 
-enum WallKind : int { kCellDir = 1, kFaceDir = 2, kCellNeu = 3 };
+enum WallKind : int { kPer = 0, kCellDir = 1, kFaceDir = 2, kCellNeu = 3 };
 
-// mode 1: a velocity cycle (fields 0..dim-2 tangential, field dim-1 normal);
-// mode 2: the pressure cycle (one Neumann field).
+// Kinds of field f along the axes, two bits per axis (axis 0 lowest).
+// mode 1: a velocity cycle (field f = component f); mode 2: the pressure
+// cycle (one Neumann field).  wm: bit b = walls along axis b.
 template <int DIM>
-__device__ inline int wall_kind(int mode, int f) {
-  return mode == 2 ? kCellNeu : (f == DIM - 1 ? kFaceDir : kCellDir);
+__device__ inline int field_kinds(int mode, int f, int wm) {
+  int kinds = 0;
+  for (int b = 0; b < DIM; ++b) {
+    int k = kPer;
+    if ((wm >> b) & 1) k = mode == 2 ? kCellNeu : (b == f ? kFaceDir : kCellDir);
+    kinds |= k << (2 * b);
+  }
+  return kinds;
+}
+
+__device__ inline int kind_of(int kinds, int b) { return (kinds >> (2 * b)) & 3; }
+
+// A wall face: index 0 along an axis of face kind.
+template <int DIM>
+__device__ inline bool on_wall_face(const int* co, int kinds) {
+  for (int b = 0; b < DIM; ++b)
+    if (kind_of(kinds, b) == kFaceDir && co[b] == 0) return true;
+  return false;
 }
 
 inline unsigned nblk(int64_t len, int bs = 256) { return (unsigned)((len + bs - 1) / bs); }
 
 // Cell of colour `color` with half-index t: natural coordinates.
 template <int DIM>
-__device__ inline void colour_cell(int t, int color, int logn, int& i, int& j, int& k) {
+__device__ inline void colour_cell(int t, int color, int logn, int* co) {
   const int hl = logn - 1;
   const int mask = (1 << logn) - 1;
   const int m = t & ((1 << hl) - 1);
   const int row = t >> hl;
-  j = row & mask;
-  k = DIM == 3 ? (row >> logn) : 0;
-  i = 2 * m + ((color + j + k) & 1);
+  co[1] = row & mask;
+  co[2] = DIM == 3 ? (row >> logn) : 0;
+  co[0] = 2 * m + ((color + co[1] + co[2]) & 1);
 }
 
 template <typename T, int DIM>
-__device__ inline T at(const T* x, int i, int j, int k, int logn) {
-  return x[split_index<DIM>(i, j, k, logn)];
+__device__ inline T at(const T* x, const int* co, int logn) {
+  return x[split_index<DIM>(co[0], co[1], co[2], logn)];
 }
 
 // Sum of the neighbours that are other unknowns, and the diagonal of
-// (c0 - c1 L) at cell (i, j, k); w is the wall-axis coordinate.
+// (c0 - c1 L) at cell co.
 template <typename T, int DIM>
-__device__ inline T nbr_sum(const T* x, int i, int j, int k, int logn, int kind, T c0, T c1, T& diag) {
+__device__ inline T nbr_sum(const T* x, const int* co, int logn, int kinds, T c0, T c1, T& diag) {
   const int n = 1 << logn;
-  const int w = DIM == 3 ? k : j;
+  const int mask = n - 1;
   diag = c0 + T(2 * DIM) * c1;
-  const T s = kind == kCellDir ? T(1) : T(-1);
-  T up = T(0), dn = T(0);
-  if (DIM == 3) {
-    if (kind == kFaceDir) {
-      up = w + 1 < n ? at<T, DIM>(x, i, j, k + 1, logn) : T(0);
-      dn = at<T, DIM>(x, i, j, k - 1, logn);
+  T sum = T(0);
+  for (int b = DIM - 1; b >= 0; --b) {
+    const int kind = kind_of(kinds, b);
+    int q[3] = {co[0], co[1], co[2]};
+    T up = T(0), dn = T(0);
+    if (kind == kPer) {
+      q[b] = (co[b] + 1) & mask;
+      up = at<T, DIM>(x, q, logn);
+      q[b] = (co[b] - 1) & mask;
+      dn = at<T, DIM>(x, q, logn);
+    } else if (kind == kFaceDir) {
+      // face n is the other wall (0); the wall face's own row is not an equation
+      if (co[b] + 1 < n) {
+        q[b] = co[b] + 1;
+        up = at<T, DIM>(x, q, logn);
+      }
+      if (co[b] > 0) {
+        q[b] = co[b] - 1;
+        dn = at<T, DIM>(x, q, logn);
+      }
     } else {
-      if (w + 1 < n) up = at<T, DIM>(x, i, j, k + 1, logn); else diag += s * c1;
-      if (w > 0) dn = at<T, DIM>(x, i, j, k - 1, logn); else diag += s * c1;
+      const T s = kind == kCellDir ? T(1) : T(-1);
+      if (co[b] + 1 < n) {
+        q[b] = co[b] + 1;
+        up = at<T, DIM>(x, q, logn);
+      } else {
+        diag += s * c1;
+      }
+      if (co[b] > 0) {
+        q[b] = co[b] - 1;
+        dn = at<T, DIM>(x, q, logn);
+      } else {
+        diag += s * c1;
+      }
     }
-  } else {
-    if (kind == kFaceDir) {
-      up = w + 1 < n ? at<T, DIM>(x, i, j + 1, k, logn) : T(0);
-      dn = at<T, DIM>(x, i, j - 1, k, logn);
-    } else {
-      if (w + 1 < n) up = at<T, DIM>(x, i, j + 1, k, logn); else diag += s * c1;
-      if (w > 0) dn = at<T, DIM>(x, i, j - 1, k, logn); else diag += s * c1;
-    }
+    sum += up + dn;
   }
-  T sum = up + dn;
-  if (DIM == 3) sum += at<T, DIM>(x, i, j + 1, k, logn) + at<T, DIM>(x, i, j - 1, k, logn);
-  sum += at<T, DIM>(x, i + 1, j, k, logn) + at<T, DIM>(x, i - 1, j, k, logn);
   return sum;
 }
 
 template <typename T, int DIM>
-__device__ inline T resid_at(const T* x, const T* b, int i, int j, int k, int logn, int kind, T c0, T c1) {
-  const int w = DIM == 3 ? k : j;
-  if (kind == kFaceDir && w == 0) return T(0);
+__device__ inline T resid_at(const T* x, const T* b, const int* co, int logn, int kinds, T c0, T c1) {
+  if (on_wall_face<DIM>(co, kinds)) return T(0);
   T diag;
-  const T sum = nbr_sum<T, DIM>(x, i, j, k, logn, kind, c0, c1, diag);
-  return at<T, DIM>(b, i, j, k, logn) - (diag * at<T, DIM>(x, i, j, k, logn) - c1 * sum);
+  const T sum = nbr_sum<T, DIM>(x, co, logn, kinds, c0, c1, diag);
+  return at<T, DIM>(b, co, logn) - (diag * at<T, DIM>(x, co, logn) - c1 * sum);
 }
 
 // ---- per-cell steps (global kernels: one cell per thread; the tail: loops)
 // Half sweep at cell t of colour `color`.
 template <typename T, int DIM>
-__device__ inline void wrb_cell(T* x, const T* b, int logn, T c0, T c1, int color, int t, int kind) {
+__device__ inline void wrb_cell(T* x, const T* b, int logn, T c0, T c1, int color, int t, int kinds) {
   const int C = 1 << (DIM * logn);
-  int i, j, k;
-  colour_cell<DIM>(t, color, logn, i, j, k);
+  int co[3];
+  colour_cell<DIM>(t, color, logn, co);
   const int own = color * (C >> 1) + t;
-  const int w = DIM == 3 ? k : j;
-  if (kind == kFaceDir && w == 0) {
+  if (on_wall_face<DIM>(co, kinds)) {
     x[own] = T(0);
     return;
   }
   T diag;
-  const T sum = nbr_sum<T, DIM>(x, i, j, k, logn, kind, c0, c1, diag);
+  const T sum = nbr_sum<T, DIM>(x, co, logn, kinds, c0, c1, diag);
   x[own] = (b[own] + c1 * sum) / diag;
 }
 
 // Coarse right-hand side of coarse cell t (natural index) from the fine
-// residual: its split index on the coarse level is returned in *at_c.
+// residual: its split index on the coarse level is returned in *at_c.  Per
+// axis the fine points and weights of the one-dimensional restriction; the
+// coarse value is their tensor product.
 template <typename T, int DIM>
-__device__ inline T wrestrict_cell(const T* x, const T* b, int logn, T c0, T c1, int t, int kind, int* at_c) {
+__device__ inline T wrestrict_cell(const T* x, const T* b, int logn, T c0, T c1, int t, int kinds, int* at_c) {
   const int lognc = logn - 1;
   const int maskc = (1 << lognc) - 1;
-  const int I = t & maskc, J = (t >> lognc) & maskc, K = DIM == 3 ? (t >> (2 * lognc)) : 0;
-  const int W = DIM == 3 ? K : J;
-  *at_c = split_index<DIM>(I, J, K, lognc);
-  T out = T(0);
-  if (kind == kFaceDir) {
-    if (W > 0) {
-      // full weighting along the wall axis over fine faces 2W-1, 2W, 2W+1; average across
-      const T wz[3] = {T(0.25), T(0.5), T(0.25)};
-      for (int q = 0; q < 3; ++q) {
-        const int wf = 2 * W - 1 + q;
-        T acc = T(0);
-        if (DIM == 3) {
-          for (int dy = 0; dy < 2; ++dy)
-            for (int dx = 0; dx < 2; ++dx)
-              acc += resid_at<T, DIM>(x, b, 2 * I + dx, 2 * J + dy, wf, logn, kind, c0, c1);
-          acc *= T(0.25);
-        } else {
-          for (int dx = 0; dx < 2; ++dx) acc += resid_at<T, DIM>(x, b, 2 * I + dx, wf, 0, logn, kind, c0, c1);
-          acc *= T(0.5);
-        }
-        out += wz[q] * acc;
-      }
-    }
-  } else {
-    for (int dz = 0; dz < (DIM == 3 ? 2 : 1); ++dz)
-      for (int dy = 0; dy < 2; ++dy)
-        for (int dx = 0; dx < 2; ++dx)
-          out += resid_at<T, DIM>(x, b, 2 * I + dx, 2 * J + dy, 2 * K + dz, logn, kind, c0, c1);
-    out *= DIM == 3 ? T(0.125) : T(0.25);
+  const int cc[3] = {t & maskc, (t >> lognc) & maskc, DIM == 3 ? (t >> (2 * lognc)) : 0};
+  *at_c = split_index<DIM>(cc[0], cc[1], cc[2], lognc);
+  int fi[3][3];
+  T fw[3][3];
+  int cnt[3] = {1, 1, 1};
+  for (int a = 0; a < 3; ++a) {
+    fi[a][0] = 0;
+    fw[a][0] = T(1);
   }
+  for (int a = 0; a < DIM; ++a) {
+    if (kind_of(kinds, a) == kFaceDir) {
+      if (cc[a] == 0) return T(0);  // the coarse wall face
+      cnt[a] = 3;
+      fi[a][0] = 2 * cc[a] - 1;
+      fi[a][1] = 2 * cc[a];
+      fi[a][2] = 2 * cc[a] + 1;
+      fw[a][0] = T(0.25);
+      fw[a][1] = T(0.5);
+      fw[a][2] = T(0.25);
+    } else {
+      cnt[a] = 2;
+      fi[a][0] = 2 * cc[a];
+      fi[a][1] = 2 * cc[a] + 1;
+      fw[a][0] = T(0.5);
+      fw[a][1] = T(0.5);
+    }
+  }
+  T out = T(0);
+  for (int qz = 0; qz < cnt[2]; ++qz)
+    for (int qy = 0; qy < cnt[1]; ++qy) {
+      T row = T(0);
+      for (int qx = 0; qx < cnt[0]; ++qx) {
+        const int co[3] = {fi[0][qx], fi[1][qy], fi[2][qz]};
+        row += fw[0][qx] * resid_at<T, DIM>(x, b, co, logn, kinds, c0, c1);
+      }
+      out += fw[1][qy] * fw[2][qz] * row;
+    }
   return out;
 }
 
-// Coarse value used by the prolongation at coarse wall-axis index Wn (may be
-// one beyond the lattice: the ghost), periodic axes already chosen.
+// x += P e at fine cell t (natural index).  Per axis the coarse points and
+// weights of the one-dimensional interpolation (with a sign for a mirror
+// ghost); the correction is their tensor product.
 template <typename T, int DIM>
-__device__ inline T coarse_at(const T* e, int I, int J, int Wn, int Wp, int lognc, int kind) {
-  const int nc = 1 << lognc;
-  int Wu = Wn;
-  T s = T(1);
-  if (Wn < 0 || Wn >= nc) {
-    if (kind == kFaceDir) return T(0);  // the wall face (only Wn == nc arises)
-    Wu = Wp;
-    s = kind == kCellDir ? T(-1) : T(1);
-  }
-  return DIM == 3 ? s * at<T, DIM>(e, I, J, Wu, lognc) : s * at<T, DIM>(e, I, Wu, 0, lognc);
-}
-
-// x += P e at fine cell t (natural index).
-template <typename T, int DIM>
-__device__ inline void wprolong_cell(T* x, const T* e, int logn, int t, int kind) {
+__device__ inline void wprolong_cell(T* x, const T* e, int logn, int t, int kinds) {
   const int lognc = logn - 1;
+  const int nc = 1 << lognc;
   const int mask = (1 << logn) - 1;
-  const int i = t & mask, j = (t >> logn) & mask, k = DIM == 3 ? (t >> (2 * logn)) : 0;
-  const int w = DIM == 3 ? k : j;
-  if (kind == kFaceDir && w == 0) return;
-  // periodic axes: cell-centred 3/4, 1/4
-  const int I = i >> 1, In = (i & 1) ? I + 1 : I - 1;
-  int J = 0, Jn = 0;
-  if (DIM == 3) {
-    J = j >> 1;
-    Jn = (j & 1) ? J + 1 : J - 1;
+  const int co[3] = {t & mask, (t >> logn) & mask, DIM == 3 ? (t >> (2 * logn)) : 0};
+  if (on_wall_face<DIM>(co, kinds)) return;
+  int ci[3][2];
+  T cw[3][2];
+  int cnt[3] = {1, 1, 1};
+  for (int a = 0; a < 3; ++a) {
+    ci[a][0] = 0;
+    cw[a][0] = T(1);
   }
-  // wall axis: two coarse indices and their weights
-  int W0, W1;
-  T a0, a1;
-  const int Wp = w >> 1;
-  if (kind == kFaceDir) {
-    W0 = Wp;
-    W1 = Wp + 1;
-    a0 = (w & 1) ? T(0.5) : T(1);
-    a1 = (w & 1) ? T(0.5) : T(0);
-  } else {
-    W0 = Wp;
-    W1 = (w & 1) ? Wp + 1 : Wp - 1;
-    a0 = T(0.75);
-    a1 = T(0.25);
+  for (int a = 0; a < DIM; ++a) {
+    const int kind = kind_of(kinds, a);
+    const int w = co[a], P = w >> 1;
+    if (kind == kFaceDir) {
+      // coarse face P on fine face 2P; odd faces average P and P + 1 (face nc is the wall)
+      ci[a][0] = P;
+      cw[a][0] = (w & 1) ? T(0.5) : T(1);
+      cnt[a] = 1;
+      if ((w & 1) && P + 1 < nc) {
+        ci[a][1] = P + 1;
+        cw[a][1] = T(0.5);
+        cnt[a] = 2;
+      }
+    } else {
+      int Q = (w & 1) ? P + 1 : P - 1;
+      T s = T(1);
+      if (kind == kPer) {
+        Q &= nc - 1;
+      } else if (Q < 0 || Q >= nc) {
+        // beyond a wall: the boundary cell's mirror image
+        Q = P;
+        s = kind == kCellDir ? T(-1) : T(1);
+      }
+      ci[a][0] = P;
+      cw[a][0] = T(0.75);
+      ci[a][1] = Q;
+      cw[a][1] = T(0.25) * s;
+      cnt[a] = 2;
+    }
   }
   T val = T(0);
-  for (int q = 0; q < 2; ++q) {
-    const int Wq = q == 0 ? W0 : W1;
-    const T aq = q == 0 ? a0 : a1;
-    if (aq == T(0)) continue;
-    T plane;
-    if (DIM == 3) {
-      const T r0 = T(0.75) * coarse_at<T, DIM>(e, I, J, Wq, Wp, lognc, kind) +
-                   T(0.25) * coarse_at<T, DIM>(e, In, J, Wq, Wp, lognc, kind);
-      const T r1 = T(0.75) * coarse_at<T, DIM>(e, I, Jn, Wq, Wp, lognc, kind) +
-                   T(0.25) * coarse_at<T, DIM>(e, In, Jn, Wq, Wp, lognc, kind);
-      plane = T(0.75) * r0 + T(0.25) * r1;
-    } else {
-      plane = T(0.75) * coarse_at<T, DIM>(e, I, 0, Wq, Wp, lognc, kind) +
-              T(0.25) * coarse_at<T, DIM>(e, In, 0, Wq, Wp, lognc, kind);
+  for (int qz = 0; qz < cnt[2]; ++qz)
+    for (int qy = 0; qy < cnt[1]; ++qy) {
+      T row = T(0);
+      for (int qx = 0; qx < cnt[0]; ++qx) {
+        const int cc[3] = {ci[0][qx], ci[1][qy], ci[2][qz]};
+        row += cw[0][qx] * at<T, DIM>(e, cc, lognc);
+      }
+      val += cw[1][qy] * cw[2][qz] * row;
     }
-    val += aq * plane;
-  }
-  x[split_index<DIM>(i, j, k, logn)] += val;
+  x[split_index<DIM>(co[0], co[1], co[2], logn)] += val;
 }
 
 // ---- global kernels: fields in blockIdx.y
 template <typename T, int DIM>
 __global__ void __launch_bounds__(256) k_wrb(T* __restrict__ x, const T* __restrict__ b, int logn, T c0, T c1,
-                                             int color, int mode) {
+                                             int color, int mode, int wm) {
   const int C = 1 << (DIM * logn);
   const int t = (int)(blockIdx.x * blockDim.x + threadIdx.x);
   if (t >= (C >> 1)) return;
   const int f = blockIdx.y;
-  wrb_cell<T, DIM>(x + (int64_t)f * C, b + (int64_t)f * C, logn, c0, c1, color, t, wall_kind<DIM>(mode, f));
+  wrb_cell<T, DIM>(x + (int64_t)f * C, b + (int64_t)f * C, logn, c0, c1, color, t, field_kinds<DIM>(mode, f, wm));
 }
 
 template <typename T, int DIM>
 __global__ void __launch_bounds__(256) k_wresid_restrict(const T* __restrict__ x, const T* __restrict__ b,
-                                                         T* __restrict__ bc, int logn, T c0, T c1, int mode) {
+                                                         T* __restrict__ bc, int logn, T c0, T c1, int mode,
+                                                         int wm) {
   const int C = 1 << (DIM * logn), Cc = C >> DIM;
   const int t = (int)(blockIdx.x * blockDim.x + threadIdx.x);
   if (t >= Cc) return;
   const int f = blockIdx.y;
   int at_c;
   const T r = wrestrict_cell<T, DIM>(x + (int64_t)f * C, b + (int64_t)f * C, logn, c0, c1, t,
-                                     wall_kind<DIM>(mode, f), &at_c);
+                                     field_kinds<DIM>(mode, f, wm), &at_c);
   bc[(int64_t)f * Cc + at_c] = r;
 }
 
 template <typename T, int DIM>
-__global__ void __launch_bounds__(256) k_wprolong(T* __restrict__ x, const T* __restrict__ e, int logn, int mode) {
+__global__ void __launch_bounds__(256) k_wprolong(T* __restrict__ x, const T* __restrict__ e, int logn, int mode,
+                                                  int wm) {
   const int C = 1 << (DIM * logn), Cc = C >> DIM;
   const int t = (int)(blockIdx.x * blockDim.x + threadIdx.x);
   if (t >= C) return;
   const int f = blockIdx.y;
-  wprolong_cell<T, DIM>(x + (int64_t)f * C, e + (int64_t)f * Cc, logn, t, wall_kind<DIM>(mode, f));
+  wprolong_cell<T, DIM>(x + (int64_t)f * C, e + (int64_t)f * Cc, logn, t, field_kinds<DIM>(mode, f, wm));
 }
 
 // ---- the coarse tail in one workgroup per field
@@ -274,7 +312,7 @@ constexpr int wall_pyramid(int C) {
 template <typename T, int DIM>
 __global__ void __launch_bounds__(kWallTailThreads) k_wvcycle_lds(const T* __restrict__ bg, T* __restrict__ xg,
                                                                   int logn, T c0, T c1, int nu_pre, int nu_post,
-                                                                  int nu_coarse, int mode) {
+                                                                  int nu_coarse, int mode, int wm) {
   constexpr int kX = wall_pyramid<DIM>(kWallTailCells);
   constexpr int kB = wall_pyramid<DIM>(kWallTailCells >> DIM) + 1;
   __shared__ T xs[kX];
@@ -282,7 +320,7 @@ __global__ void __launch_bounds__(kWallTailThreads) k_wvcycle_lds(const T* __res
   __shared__ T red[kWallTailThreads / kWave];
   const int tid = threadIdx.x, nt = blockDim.x;
   const int f = blockIdx.x;
-  const int kind = wall_kind<DIM>(mode, f);
+  const int kinds = field_kinds<DIM>(mode, f, wm);
   const int C0 = 1 << (DIM * logn);
   const T* b0 = bg + (int64_t)f * C0;
   T* x0 = xg + (int64_t)f * C0;
@@ -305,7 +343,7 @@ __global__ void __launch_bounds__(kWallTailThreads) k_wvcycle_lds(const T* __res
     const int H = 1 << (DIM * lg - 1);
     for (int sw = 0; sw < nsw; ++sw)
       for (int color = 0; color < 2; ++color) {
-        for (int t = tid; t < H; t += nt) wrb_cell<T, DIM>(xs + off[l], bl(l), lg, c0, cc, color, t, kind);
+        for (int t = tid; t < H; t += nt) wrb_cell<T, DIM>(xs + off[l], bl(l), lg, c0, cc, color, t, kinds);
         __syncthreads();
       }
   };
@@ -317,7 +355,7 @@ __global__ void __launch_bounds__(kWallTailThreads) k_wvcycle_lds(const T* __res
     sweeps(l, cl, nu_pre);
     for (int t = tid; t < (Cl >> DIM); t += nt) {
       int at_c;
-      const T r = wrestrict_cell<T, DIM>(xs + off[l], bl(l), lg, c0, cl, t, kind, &at_c);
+      const T r = wrestrict_cell<T, DIM>(xs + off[l], bl(l), lg, c0, cl, t, kinds, &at_c);
       bs[boff[l + 1] + at_c] = r;
     }
     __syncthreads();
@@ -344,7 +382,7 @@ __global__ void __launch_bounds__(kWallTailThreads) k_wvcycle_lds(const T* __res
     cl = cl * T(4);
     const int lg = logn - l;
     const int Cl = 1 << (DIM * lg);
-    for (int t = tid; t < Cl; t += nt) wprolong_cell<T, DIM>(xs + off[l], xs + off[l + 1], lg, t, kind);
+    for (int t = tid; t < Cl; t += nt) wprolong_cell<T, DIM>(xs + off[l], xs + off[l + 1], lg, t, kinds);
     __syncthreads();
     sweeps(l, cl, nu_post);
   }
@@ -356,7 +394,7 @@ __global__ void __launch_bounds__(kWallTailThreads) k_wvcycle_lds(const T* __res
 template <typename T>
 void launch_wall_vcycle(int dim, int logn, int nf, const T* b, T* x, const std::vector<T*>& wx,
                         const std::vector<T*>& wb, double c0, double c1, int nu_pre, int nu_post, int nu_coarse,
-                        int mode, hipStream_t s) {
+                        int mode, int wm, hipStream_t s) {
   if (logn < 3) throw DeviceError("walls: grids need n >= 8");
   // levels above the tail run the global kernels; the tail starts at <= kWallTailCells cells
   int lt = 0;
@@ -375,10 +413,10 @@ void launch_wall_vcycle(int dim, int logn, int nf, const T* b, T* x, const std::
     const TimerEvents ev = l == 0 ? timer_sample(kTimerWallRbFine, 1.5 * (double)Cl * nf * sizeof(T)) : TimerEvents();
     if (three)
       hipExtLaunchKernelGGL(k_wrb<T, 3>, g, dim3(256), 0, s, ev.start, ev.stop, 0, xl(l), bl(l), lg, tc0, cl, color,
-                            mode);
+                            mode, wm);
     else
       hipExtLaunchKernelGGL(k_wrb<T, 2>, g, dim3(256), 0, s, ev.start, ev.stop, 0, xl(l), bl(l), lg, tc0, cl, color,
-                            mode);
+                            mode, wm);
   };
   for (int l = 0; l < lt; ++l) {
     const int lg = logn - l;
@@ -388,26 +426,26 @@ void launch_wall_vcycle(int dim, int logn, int nf, const T* b, T* x, const std::
       for (int color = 0; color < 2; ++color) half(l, color);
     const dim3 g(nblk(Cl >> dim), nf);
     if (three)
-      hipLaunchKernelGGL((k_wresid_restrict<T, 3>), g, dim3(256), 0, s, xl(l), bl(l), wb[l + 1], lg, tc0, cl, mode);
+      hipLaunchKernelGGL((k_wresid_restrict<T, 3>), g, dim3(256), 0, s, xl(l), bl(l), wb[l + 1], lg, tc0, cl, mode, wm);
     else
-      hipLaunchKernelGGL((k_wresid_restrict<T, 2>), g, dim3(256), 0, s, xl(l), bl(l), wb[l + 1], lg, tc0, cl, mode);
+      hipLaunchKernelGGL((k_wresid_restrict<T, 2>), g, dim3(256), 0, s, xl(l), bl(l), wb[l + 1], lg, tc0, cl, mode, wm);
     cl = cl * T(0.25);
   }
   if (three)
     hipLaunchKernelGGL((k_wvcycle_lds<T, 3>), dim3(nf), dim3(kWallTailThreads), 0, s, bl(lt), xl(lt), logn - lt,
-                       tc0, cl, nu_pre, nu_post, nu_coarse, mode);
+                       tc0, cl, nu_pre, nu_post, nu_coarse, mode, wm);
   else
     hipLaunchKernelGGL((k_wvcycle_lds<T, 2>), dim3(nf), dim3(kWallTailThreads), 0, s, bl(lt), xl(lt), logn - lt,
-                       tc0, cl, nu_pre, nu_post, nu_coarse, mode);
+                       tc0, cl, nu_pre, nu_post, nu_coarse, mode, wm);
   for (int l = lt - 1; l >= 0; --l) {
     cl = cl * T(4);
     const int lg = logn - l;
     const int64_t Cl = (int64_t)1 << (dim * lg);
     const dim3 g(nblk(Cl), nf);
     if (three)
-      hipLaunchKernelGGL((k_wprolong<T, 3>), g, dim3(256), 0, s, xl(l), (const T*)xl(l + 1), lg, mode);
+      hipLaunchKernelGGL((k_wprolong<T, 3>), g, dim3(256), 0, s, xl(l), (const T*)xl(l + 1), lg, mode, wm);
     else
-      hipLaunchKernelGGL((k_wprolong<T, 2>), g, dim3(256), 0, s, xl(l), (const T*)xl(l + 1), lg, mode);
+      hipLaunchKernelGGL((k_wprolong<T, 2>), g, dim3(256), 0, s, xl(l), (const T*)xl(l + 1), lg, mode, wm);
     for (int sw = 0; sw < nu_post; ++sw)
       for (int color = 0; color < 2; ++color) half(l, color);
   }
@@ -415,9 +453,9 @@ void launch_wall_vcycle(int dim, int logn, int nf, const T* b, T* x, const std::
 
 template void launch_wall_vcycle<double>(int, int, int, const double*, double*, const std::vector<double*>&,
                                          const std::vector<double*>&, double, double, int, int, int, int,
-                                         hipStream_t);
+                                         int, hipStream_t);
 template void launch_wall_vcycle<float>(int, int, int, const float*, float*, const std::vector<float*>&,
                                         const std::vector<float*>&, double, double, int, int, int, int,
-                                        hipStream_t);
+                                        int, hipStream_t);
 
 }  // namespace ibr

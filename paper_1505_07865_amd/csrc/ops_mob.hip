@@ -32,9 +32,55 @@ __device__ void fb_far(double r, const MobParams& p, double& f, double& g) {
   }
 }
 
+// Fitted f(r), g(r) (Sec. 4.2 fitting procedure, Appendix A forms; x = r/h).
+// Steady: ft = 8 pi eta r (f + shift), gt = 8 pi eta r g.  Finite beta:
+// f = -(beta/(eta h)) ft_b / (4 pi x^3), g = (beta/(eta h)) 3 gt_b / (4 pi x^3),
+// and f(0) = phi0 beta / (eta h), g(0) = 0.
+__device__ void mob_fg_fit(double r, const MobParams& p, double& f, double& g) {
+  const double x = r / p.h;
+  if (p.fit == 1) {
+    const double* b = p.fs;
+    const double c = 1.0 / (8.0 * kPi * p.eta * p.h);
+    if (x < 0.8) {
+      // ft / (8 pi eta r) = 1 / (8 pi eta h (3a/4h + b0 x^2)): finite at x = 0
+      f = c / (0.75 * p.ah + b[0] * x * x);
+    } else {
+      const double x2 = x * x, x4 = x2 * x2;
+      const double ft = b[1] * x * exp(-b[2] * x) + (b[3] * x2 + x4) / (1.0 + b[4] * x2 + x4);
+      f = c * ft / x;
+    }
+    f -= p.periodic_shift;
+    f += p.mean_mode;
+    const double x2 = x * x;
+    g = c * x2 / (b[5] + b[6] * x2 + x2 * x);
+    return;
+  }
+  const double pre = p.beta / (p.eta * p.h);
+  if (x < 1e-3) {
+    f = p.phi0 * pre + p.mean_mode;
+    g = 0.0;
+    return;
+  }
+  const double* a = p.fa;
+  const double* b = p.fb;
+  const double x2 = x * x, x3 = x2 * x, x4 = x2 * x2, x5 = x4 * x, x7 = x5 * x2;
+  const double sb = sqrt(p.beta);
+  const double ft = p.phi0 * (-4.0 * kPi * x3 + a[4] * (x5 - x7 * exp(-a[3] * x / sb) / (2.0 * p.beta))) /
+                        (1.0 + a[0] * x + a[1] * x2 + a[2] * x3 + a[4] * p.phi0 * x5) +
+                    (a[5] * x4 * exp(-a[6] * x) + a[7] * x4) / (1.0 + a[8] * x3 + a[9] * x5);
+  const double gt = p.phi0 * b[5] * (x5 + x7 * exp(-b[0] * x / sb) / (6.0 * p.beta)) /
+                    (1.0 + b[1] * x + b[2] * x2 + b[3] * x3 + b[4] * x4 + b[5] * p.phi0 * x5);
+  f = -pre * ft / (4.0 * kPi * x3) + p.mean_mode;
+  g = pre * 3.0 * gt / (4.0 * kPi * x3);
+}
+
 // f(r), g(r) of the approximate mobility (same forms as the documented reading
-// of Sec. 4 / Appendices A and B).
+// of Sec. 4 / Appendices A and B), or the fitted forms.
 __device__ void mob_fg(double r, const MobParams& p, double& f, double& g) {
+  if (p.fit) {
+    mob_fg_fit(r, p, f, g);
+    return;
+  }
   const double a = p.a;
   if (p.steady) {
     if (p.dim == 3) {

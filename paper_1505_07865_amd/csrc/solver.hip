@@ -30,6 +30,8 @@ using namespace ibr;
 
 namespace {
 
+#include "mobility_fit_4pt.inc"
+
 constexpr double kPi = 3.14159265358979323846;
 constexpr double kA3D = 1.25;      // four-point marker hydrodynamic radius, units of h (3D)
 constexpr double kA2D = 1.04;      // four-point marker radius in the 2D periodic self-mobility
@@ -38,6 +40,13 @@ constexpr double kPivotTol = 1e-8;
 constexpr double kShifts[] = {0.0, 0.02, 0.05, 0.1, 0.15, 0.2, 0.3, 0.4, 0.5, 0.7, 1.0, 1.5, 2.0, 3.0, 5.0, 10.0};
 constexpr int kNumShifts = sizeof(kShifts) / sizeof(kShifts[0]);
 constexpr int kMaxBlockRows = 8192;
+
+// Axes with no-slip walls at both ends, one bit per axis.
+int wall_mask(int walls, int dim) {
+  if (walls == IBR_WALLS_NOSLIP) return 1 << (dim - 1);
+  if (walls == IBR_WALLS_BOX) return (1 << dim) - 1;
+  return 0;
+}
 
 int ilog2(int n) {
   int l = 0;
@@ -58,13 +67,16 @@ struct ibr_ctx {
   int64_t C = 0;
   double h = 0, L = 0, c0 = 0, ch2 = 0, inv_h = 0, vol = 0;
   bool steady = true;
-  // no-slip walls at both ends of the last axis (slit channel); the velocity
-  // then has no null space, so only periodic steady Stokes (vnull) carries
-  // the mean-velocity condition and S'
+  // no-slip walls: wm bit a = walls at both ends of axis a (the slit channel
+  // has the last axis, the box every axis); the velocity then has no null
+  // space, so only periodic steady Stokes (vnull) carries the mean-velocity
+  // condition and S'
   bool walls = false;
+  int wm = 0;
   bool vnull = true;
-  // per body along the walls' axis (host): centre, marker extent below and
-  // above it, prescribed velocity; ibr_step checks the next position
+  // per body and axis (host, [nb][dim]): centre, marker extent below and
+  // above it, prescribed velocity; ibr_step checks the next position along
+  // every walled axis
   std::vector<double> wall_z, wall_lo, wall_hi, wall_uz;
   bool mixed = false;
   hipStream_t stream = nullptr;
@@ -200,7 +212,7 @@ void apply_K(ibr_ctx* c, const TI* x, double* y, const double* xmean = nullptr) 
   }
   const TimerEvents ev = timer_sample(kTimerStokes, (double)(d + 1) * c->C * (sizeof(TI) + sizeof(double)));
   launch_stokes_apply<TI, double>(d, c->logn, xv, xp, y, y + (int64_t)d * c->C, c->c0, c->ch2, c->inv_h, addc, s,
-                                  false, ev, c->walls ? 1 : 0);
+                                  false, ev, c->wm);
   launch_spread<double, double>(d, c->logn, c->tile_log, c->act_cap, c->active, c->nactive_d, c->toff, c->perm,
                                 c->taps, c->lamd, y, -std::pow(c->h, -d), s);
   launch_interp<TI>(d, c->logn, c->N, c->taps, xv, -1.0, nullptr, 0.0, y + c->NF, s, xmean);
@@ -234,7 +246,7 @@ void ps_inv(ibr_ctx* c, const T* in, T* out) {
   launch_div_q<T>(d, c->logn, v, hp, q, c->inv_h, s, true);
   // L_p phi = q  <=>  (0 - (-1) L) phi = q
   mg.vcycle(1, q, phi, 0.0, -1.0, c->p.mg_pre, c->p.mg_post, c->p.mg_coarse, s, wp);
-  launch_ps_finish<T>(d, c->logn, v, phi, q, pi, c->h, c->c0 * c->h * c->h, c->p.eta, vmean, s, true, wv);
+  launch_ps_finish<T>(d, c->logn, v, phi, q, pi, c->h, c->c0 * c->h * c->h, c->p.eta, vmean, s, true, c->wm);
   c->cnt_ps += 1;
   c->cnt_vc += d + 1;
 }
@@ -264,7 +276,7 @@ void inner_gmres(ibr_ctx* c, const T* rhs, T* out) {
       T* Wj = Q + (int64_t)j * NF;
       ps_inv<T>(c, pj, Zj);
       launch_stokes_apply<T, T>(d, c->logn, Zj, Zj + (int64_t)d * c->C, Wj, Wj + (int64_t)d * c->C, c->c0, c->ch2,
-                                c->inv_h, nullptr, s, true, TimerEvents(), c->walls ? 1 : 0);
+                                c->inv_h, nullptr, s, true, TimerEvents(), c->wm);
     }
     launch_gram_solve<T>(Q, NF, ns, rhs, NF, c->part, c->part_blocks, c->yi, s);
     launch_combine_from_split<T, T>(d, c->logn, Z, NF, ns, c->yi, out, d + 1, true, s);
@@ -282,7 +294,7 @@ void inner_gmres(ibr_ctx* c, const T* rhs, T* out) {
     T* w = Q + (int64_t)(j + 1) * NF;
     ps_inv<T>(c, Qj, Zj);
     launch_stokes_apply<T, T>(d, c->logn, Zj, Zj + (int64_t)d * c->C, w, w + (int64_t)d * c->C, c->c0, c->ch2,
-                              c->inv_h, nullptr, s, true, TimerEvents(), c->walls ? 1 : 0);
+                              c->inv_h, nullptr, s, true, TimerEvents(), c->wm);
     double* hcol = c->Hi + (int64_t)j * ldh;
     // one Gram-Schmidt pass: the inner solve is only a preconditioner (FGMRES is flexible)
     arnoldi_step<T>(Q, NF, j, hcol, c->hc2i, c->part, c->part2, c->part_blocks, c->flag, s, false, false);
@@ -514,9 +526,13 @@ void validate(const ibr_params* p) {
   if (p->mg_pre < 0 || p->mg_post < 0 || p->mg_coarse < 1 || p->mg_pre > 16 || p->mg_post > 16 ||
       p->mg_coarse > 256)
     throw Status(IBR_EINVAL, "bad multigrid sweep counts");
-  if (p->walls != IBR_WALLS_NONE && p->walls != IBR_WALLS_NOSLIP) throw Status(IBR_EINVAL, "bad walls");
+  if (p->walls != IBR_WALLS_NONE && p->walls != IBR_WALLS_NOSLIP && p->walls != IBR_WALLS_BOX)
+    throw Status(IBR_EINVAL, "bad walls");
   if (p->advection != IBR_ADVECT_CENTRED && p->advection != IBR_ADVECT_SL)
     throw Status(IBR_EINVAL, "bad advection");
+  if (p->mobility != IBR_MOB_ANALYTIC && p->mobility != IBR_MOB_FITTED) throw Status(IBR_EINVAL, "bad mobility");
+  if (p->mobility == IBR_MOB_FITTED && (p->dim != 3 || kFitRows == 0))
+    throw Status(IBR_EINVAL, "the fitted mobility exists for 3D only");
 }
 
 MobParams mob_params(const ibr_ctx* c) {
@@ -538,10 +554,41 @@ MobParams mob_params(const ibr_ctx* c) {
     mp.alpha = std::sqrt(c->p.rho / (mp.eta * c->p.dt));
     mp.dt_rho = c->p.dt / c->p.rho;
   }
+  mp.h = c->h;
+  if (c->p.mobility == IBR_MOB_FITTED && kFitRows > 0) {
+    mp.ah = kFitAh;
+    for (int i = 0; i < 7; ++i) mp.fs[i] = kFitSteady[i];
+    const double beta = c->steady ? 0.0 : c->p.eta * c->p.dt / (c->p.rho * c->h * c->h);
+    // the fitted forms describe the kernel's pair mobility without the box;
+    // an unsteady periodic box adds its mean mode (walls block it)
+    if (!c->steady && !c->walls) mp.mean_mode = c->p.dt / (c->p.rho * c->vol);
+    if (c->steady || beta > kFitBeta[kFitRows - 1]) {
+      mp.fit = 1;
+      if (!c->steady) mp.periodic_shift = 0.0;  // an unsteady box keeps S: no mean-flow shift
+    } else {
+      mp.fit = 2;
+      mp.beta = beta;
+      const double z1 = kFitZ[0], z2 = kFitZ[1], z3 = kFitZ[2];
+      const double z0 = 1.5 * std::pow(8.0 / 3.0, 3);  // 3 V_m / (2 h^3), the inviscid self mobility
+      mp.phi0 = (1.0 + z1 * std::sqrt(beta) + z2 * beta) / (z0 + z3 * beta + 6.0 * kPi * kFitAh * z2 * beta * beta);
+      int i = 0;
+      while (i + 1 < kFitRows && kFitBeta[i + 1] < beta) ++i;
+      double t = 0.0;
+      int k = i;
+      if (beta > kFitBeta[i] && i + 1 < kFitRows) {
+        k = i + 1;
+        t = (beta - kFitBeta[i]) / (kFitBeta[k] - kFitBeta[i]);
+      }
+      for (int q = 0; q < 10; ++q) mp.fa[q] = (1.0 - t) * kFitA[i][q] + t * kFitA[k][q];
+      for (int q = 0; q < 6; ++q) mp.fb[q] = (1.0 - t) * kFitB[i][q] + t * kFitB[k][q];
+    }
+  }
   return mp;
 }
 
 double self_term(const MobParams& mp) {
+  if (mp.fit == 1) return 1.0 / (6.0 * kPi * mp.eta * mp.ah * mp.h) - mp.periodic_shift + mp.mean_mode;
+  if (mp.fit == 2) return mp.phi0 * mp.beta / (mp.eta * mp.h) + mp.mean_mode;
   if (!mp.steady) return mp.f00;
   if (mp.dim == 3) return mp.finf0 - mp.periodic_shift;
   return mp.finf0;
@@ -549,8 +596,7 @@ double self_term(const MobParams& mp) {
 
 void setup_markers(ibr_ctx* c) {
   hipStream_t s = c->stream;
-  launch_marker_setup(c->dim, c->logn, c->N, c->h, c->L, c->R, c->taps, c->tile_of, c->tile_log, s,
-                      c->walls ? 1 : 0);
+  launch_marker_setup(c->dim, c->logn, c->N, c->h, c->L, c->R, c->taps, c->tile_of, c->tile_log, s, c->wm);
   launch_bin_markers(c->N, c->ntiles, c->tile_of, c->counts, c->toff, c->cursor, c->perm, s);
   launch_active_tiles(c->dim, c->tiles_log, c->toff, c->flags, c->active, c->nactive_d, s);
   int na = 0;
@@ -616,12 +662,12 @@ void build_rhs_markers(ibr_ctx* c) {
 // nearly coincide.  Only pairs of bodies whose bounding spheres (about the
 // given centres, minimum image along periodic axes) come within h of each
 // other are compared marker by marker.  Throws IBR_EINVAL naming the bodies.
-void check_overlap(int d, double h, double L, bool walls, int nb, const int* off, const double* R,
+void check_overlap(int d, double h, double L, int wm, int nb, const int* off, const double* R,
                    const double* X) {
   if (nb < 2) return;
   auto delta = [&](const double* a, const double* b, int ax) {
     double dx = a[ax] - b[ax];
-    if (!(walls && ax == d - 1)) dx -= L * std::nearbyint(dx / L);
+    if (!((wm >> ax) & 1)) dx -= L * std::nearbyint(dx / L);
     return dx;
   };
   std::vector<double> rad(nb, 0.0);
@@ -792,10 +838,10 @@ void ibr_ctx::alloc_grid() {
   qT = talloc(C);
   phiT = talloc(C);
   if (mixed) {
-    mg32.init(d, logn, d, walls);
+    mg32.init(d, logn, d, wm);
     bytes += MGHier<float>::bytes(d, logn, d, walls);
   } else {
-    mg64.init(d, logn, d, walls);
+    mg64.init(d, logn, d, wm);
     bytes += MGHier<double>::bytes(d, logn, d, walls);
   }
   IBR_HIP(hipHostMalloc((void**)&hres, 64, hipHostMallocDefault));
@@ -878,6 +924,7 @@ void ibr_default_params(ibr_params* p) {
   p->graphs = 1;
   p->walls = IBR_WALLS_NONE;
   p->advection = IBR_ADVECT_CENTRED;
+  p->mobility = IBR_MOB_ANALYTIC;
 }
 
 const char* ibr_status_string(int st) {
@@ -911,7 +958,8 @@ ibr_status ibr_create(const ibr_params* params, ibr_ctx** out) {
     c->L = params->n * params->h;
     c->vol = std::pow(c->L, c->dim);
     c->steady = params->rho == 0.0;
-    c->walls = params->walls == IBR_WALLS_NOSLIP;
+    c->wm = wall_mask(params->walls, params->dim);
+    c->walls = c->wm != 0;
     c->vnull = c->steady && !c->walls;
     c->c0 = c->steady ? 0.0 : params->rho / params->dt;
     c->ch2 = params->eta / (c->h * c->h);
@@ -957,7 +1005,7 @@ size_t ibr_footprint_bytes(const ibr_params* p, int nbodies, int nmarkers) {
   b += (size_t)4 * NV * 8;             // x, b, two temporaries
   b += (size_t)2 * d * C * 8;          // advection history
   b += (size_t)((2 * ns + 2) * NF + 2 * C) * ts;  // inner bases and P_S^-1 scratch
-  const bool w = p->walls == IBR_WALLS_NOSLIP;
+  const bool w = p->walls == IBR_WALLS_NOSLIP || p->walls == IBR_WALLS_BOX;
   b += ts == 4 ? MGHier<float>::bytes(d, ilog2(p->n), d, w) : MGHier<double>::bytes(d, ilog2(p->n), d, w);
   // mobility blocks (4 buffers of sum (d N_p)^2), bounded by one block of all markers per body
   const int64_t per = nbodies > 0 ? (int64_t)d * nmarkers / nbodies : 0;
@@ -985,27 +1033,30 @@ ibr_status ibr_set_bodies(ibr_ctx* c, int nbodies, const int* offsets, const dou
       if (!std::isfinite(R[i])) throw Status(IBR_EINVAL, "marker positions must be finite");
     for (int64_t i = 0; i < (int64_t)nbodies * d; ++i)
       if (!std::isfinite(centres[i])) throw Status(IBR_EINVAL, "centres must be finite");
-    check_overlap(d, c->h, c->L, c->walls, nbodies, offsets, R, centres);
+    check_overlap(d, c->h, c->L, c->wm, nbodies, offsets, R, centres);
     if (c->walls) {
-      for (int64_t m = 0; m < N; ++m) {
-        const double z = R[m * d + d - 1];
-        if (!(z > 0.0 && z < c->L)) throw Status(IBR_EINVAL, "markers must lie strictly between the walls");
-      }
-      c->wall_z.assign(nbodies, 0.0);
-      c->wall_lo.assign(nbodies, 0.0);
-      c->wall_hi.assign(nbodies, 0.0);
-      c->wall_uz.assign(nbodies, 0.0);
-      for (int b = 0; b < nbodies; ++b) {
-        const double zc = centres[b * d + d - 1];
-        double lo = 0.0, hi = 0.0;
-        for (int m = offsets[b]; m < offsets[b + 1]; ++m) {
-          lo = std::min(lo, R[(int64_t)m * d + d - 1] - zc);
-          hi = std::max(hi, R[(int64_t)m * d + d - 1] - zc);
+      for (int64_t m = 0; m < N; ++m)
+        for (int a = 0; a < d; ++a) {
+          if (!((c->wm >> a) & 1)) continue;
+          const double z = R[m * d + a];
+          if (!(z > 0.0 && z < c->L)) throw Status(IBR_EINVAL, "markers must lie strictly between the walls");
         }
-        c->wall_z[b] = zc;
-        c->wall_lo[b] = lo;
-        c->wall_hi[b] = hi;
-      }
+      c->wall_z.assign((size_t)nbodies * d, 0.0);
+      c->wall_lo.assign((size_t)nbodies * d, 0.0);
+      c->wall_hi.assign((size_t)nbodies * d, 0.0);
+      c->wall_uz.assign((size_t)nbodies * d, 0.0);
+      for (int b = 0; b < nbodies; ++b)
+        for (int a = 0; a < d; ++a) {
+          const double zc = centres[b * d + a];
+          double lo = 0.0, hi = 0.0;
+          for (int m = offsets[b]; m < offsets[b + 1]; ++m) {
+            lo = std::min(lo, R[(int64_t)m * d + a] - zc);
+            hi = std::max(hi, R[(int64_t)m * d + a] - zc);
+          }
+          c->wall_z[b * d + a] = zc;
+          c->wall_lo[b * d + a] = lo;
+          c->wall_hi[b * d + a] = hi;
+        }
     }
     IBR_HIP(hipSetDevice(c->p.device));
     sync(c);
@@ -1124,7 +1175,7 @@ ibr_status ibr_set_velocities(ibr_ctx* c, const double* U, const double* Omega) 
     }
     c->rotating = rot;
     if (c->walls)
-      for (int b = 0; b < c->nb; ++b) c->wall_uz[b] = U[b * d + d - 1];
+      for (int64_t i = 0; i < (int64_t)c->nb * d; ++i) c->wall_uz[i] = U[i];
     IBR_HIP(hipSetDevice(c->p.device));
     IBR_HIP(hipMemcpyAsync(c->U, U, (size_t)c->nb * d * sizeof(double), hipMemcpyHostToDevice, c->stream));
     IBR_HIP(hipMemcpyAsync(c->Om, Omega, (size_t)c->nb * no * sizeof(double), hipMemcpyHostToDevice, c->stream));
@@ -1166,8 +1217,8 @@ void set_rhs_impl(ibr_ctx* c, const double* gh, const double* hp, hipMemcpyKind 
   // consistency: <h> = 0 always, <g> = 0 for periodic steady Stokes (Sec. 3.4)
   launch_field_means<double>(c->Bs + (int64_t)d * c->C, 1, c->C, c->mpart, 256, c->vmean, s);
   launch_sub_field_mean<double>(c->Bs + (int64_t)d * c->C, 1, c->C, c->vmean, s);
-  // with walls the normal component's wall faces are not unknowns: no momentum there
-  if (c->walls) launch_fill<double>(c->Bs + (int64_t)(d - 1) * c->C, c->C >> c->logn, 0.0, s);
+  // with walls the normal components' wall faces are not unknowns: no momentum there
+  if (c->walls) launch_zero_wall_faces(d, c->logn, c->Bs, c->wm, s);
   if (c->vnull) {
     launch_field_means<double>(c->Bs, d, c->C, c->mpart, 256, c->vmean, s);
     launch_sub_field_mean<double>(c->Bs, d, c->C, c->vmean, s);
@@ -1241,11 +1292,15 @@ ibr_status ibr_step(ibr_ctx* c, ibr_info* info) {
     if (c->nfree) throw Status(IBR_EINVAL, "ibr_step moves bodies with prescribed velocities only: no free bodies");
     if (c->walls) {
       // bodies translate with their prescribed velocity: every marker must stay between the walls
-      for (int b = 0; b < c->nb; ++b) {
-        const double zc = c->wall_z[b] + c->p.dt * c->wall_uz[b];
-        if (!(zc + c->wall_lo[b] > 0.0 && zc + c->wall_hi[b] < c->L))
-          throw Status(IBR_EINVAL, "ibr_step: body " + std::to_string(b) + " would cross a wall");
-      }
+      const int d0 = c->dim;
+      for (int b = 0; b < c->nb; ++b)
+        for (int a = 0; a < d0; ++a) {
+          if (!((c->wm >> a) & 1)) continue;
+          const int i = b * d0 + a;
+          const double zc = c->wall_z[i] + c->p.dt * c->wall_uz[i];
+          if (!(zc + c->wall_lo[i] > 0.0 && zc + c->wall_hi[i] < c->L))
+            throw Status(IBR_EINVAL, "ibr_step: body " + std::to_string(b) + " would cross a wall");
+        }
     }
     IBR_HIP(hipSetDevice(c->p.device));
     hipStream_t s = c->stream;
@@ -1256,10 +1311,10 @@ ibr_status ibr_step(ibr_ctx* c, ibr_info* info) {
     // centred form with AB2 (forward Euler on the first step)
     const double rho = c->p.rho;
     if (c->p.advection == IBR_ADVECT_SL) {
-      launch_advect_sl(d, c->logn, c->Xs, c->Ncur, c->p.dt / c->h, 1.0 / c->p.dt, s, c->walls ? 1 : 0);
+      launch_advect_sl(d, c->logn, c->Xs, c->Ncur, c->p.dt / c->h, 1.0 / c->p.dt, s, c->wm);
       launch_ns_rhs(c->Xs, c->Ncur, nullptr, c->Bs, len, c->c0, rho, 1.0, 0.0, s);
     } else {
-      launch_advect(d, c->logn, c->Xs, c->Ncur, 0.5 / c->h, s, c->walls ? 1 : 0);
+      launch_advect(d, c->logn, c->Xs, c->Ncur, 0.5 / c->h, s, c->wm);
       if (c->have_prev)
         launch_ns_rhs(c->Xs, c->Ncur, c->Nprev, c->Bs, len, c->c0, rho, 1.5, -0.5, s);
       else
@@ -1269,7 +1324,7 @@ ibr_status ibr_step(ibr_ctx* c, ibr_info* info) {
     // move the bodies, re-bin the markers (the mobility blocks are translation invariant)
     launch_move_markers(d, c->N, c->nb, c->R, c->X, c->body_d, c->U, c->p.dt, c->L, s);
     if (c->walls)
-      for (int b = 0; b < c->nb; ++b) c->wall_z[b] += c->p.dt * c->wall_uz[b];
+      for (size_t i = 0; i < c->wall_z.size(); ++i) c->wall_z[i] += c->p.dt * c->wall_uz[i];
     setup_markers(c);
     build_rhs_markers(c);
     st = c->mixed ? fgmres<float>(c, info) : fgmres<double>(c, info);
@@ -1472,9 +1527,9 @@ ibr_status ibr_vcycle(ibr_ctx* c, double c0, double c1, int nf, const double* b,
     if (nf < 1 || nf > c->dim) throw Status(IBR_EINVAL, "nfields must be in [1, dim]");
     if (c->walls && nf != 1 && nf != c->dim)
       throw Status(IBR_EINVAL, "with walls nfields is dim (velocity) or 1 (pressure)");
-    // with walls: the velocity cycle (tangential components, then the normal one) or the Neumann pressure cycle
-    const int wm = c->walls ? (nf == 1 ? 2 : 1) : 0;
-    const bool singular = c0 == 0.0 && wm != 1;
+    // with walls: the velocity cycle (field a = component a) or the Neumann pressure cycle
+    const int mode = c->walls ? (nf == 1 ? 2 : 1) : 0;
+    const bool singular = c0 == 0.0 && mode != 1;
     if (!(c0 >= 0) || !std::isfinite(c1) || c1 == 0.0) throw Status(IBR_EINVAL, "need c0 >= 0 and c1 != 0");
     IBR_HIP(hipSetDevice(c->p.device));
     hipStream_t s = c->stream;
@@ -1488,7 +1543,7 @@ ibr_status ibr_vcycle(ibr_ctx* c, double c0, double c1, int nf, const double* b,
       float* bf = (float*)c->Qi;
       float* xf = (float*)c->Zi;
       launch_to_split<double, float>(c->dim, c->logn, bd, bf, nf, s);
-      c->mg32.vcycle(nf, bf, xf, c0, c1, c->p.mg_pre, c->p.mg_post, c->p.mg_coarse, s, wm);
+      c->mg32.vcycle(nf, bf, xf, c0, c1, c->p.mg_pre, c->p.mg_post, c->p.mg_coarse, s, mode);
       if (singular) {
         launch_field_means<float>(xf, nf, c->C, c->mpart, 256, c->vmean, s);
         launch_sub_field_mean<float>(xf, nf, c->C, c->vmean, s);
@@ -1498,7 +1553,7 @@ ibr_status ibr_vcycle(ibr_ctx* c, double c0, double c1, int nf, const double* b,
       double* bs = (double*)c->Qi;
       double* xs = (double*)c->Zi;
       launch_to_split<double, double>(c->dim, c->logn, bd, bs, nf, s);
-      c->mg64.vcycle(nf, bs, xs, c0, c1, c->p.mg_pre, c->p.mg_post, c->p.mg_coarse, s, wm);
+      c->mg64.vcycle(nf, bs, xs, c0, c1, c->p.mg_pre, c->p.mg_post, c->p.mg_coarse, s, mode);
       if (singular) {
         launch_field_means<double>(xs, nf, c->C, c->mpart, 256, c->vmean, s);
         launch_sub_field_mean<double>(xs, nf, c->C, c->vmean, s);
@@ -1572,9 +1627,9 @@ ibr_status ibr_advect(ibr_ctx* c, const double* u, double* N) {
       throw Status(IBR_EINVAL, "semi-Lagrangian advection needs dt > 0 (unsteady)");
     IBR_HIP(hipMemcpyAsync(c->Nprev, u, (size_t)d * c->C * sizeof(double), hipMemcpyHostToDevice, s));
     if (c->p.advection == IBR_ADVECT_SL)
-      launch_advect_sl(d, c->logn, c->Nprev, c->Ncur, c->p.dt / c->h, 1.0 / c->p.dt, s, c->walls ? 1 : 0);
+      launch_advect_sl(d, c->logn, c->Nprev, c->Ncur, c->p.dt / c->h, 1.0 / c->p.dt, s, c->wm);
     else
-      launch_advect(d, c->logn, c->Nprev, c->Ncur, 0.5 / c->h, s, c->walls ? 1 : 0);
+      launch_advect(d, c->logn, c->Nprev, c->Ncur, 0.5 / c->h, s, c->wm);
     IBR_HIP(hipMemcpyAsync(N, c->Ncur, (size_t)d * c->C * sizeof(double), hipMemcpyDeviceToHost, s));
     c->have_prev = false;
     sync(c);

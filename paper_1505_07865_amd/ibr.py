@@ -18,8 +18,9 @@ LIB_PATH = os.path.join(_HERE, "libibr.so")
 
 FP64, MIXED = 0, 1
 PC_LOWER, PC_FULL = 0, 1
-WALLS_NONE, WALLS_NOSLIP = 0, 1
+WALLS_NONE, WALLS_NOSLIP, WALLS_BOX = 0, 1, 2
 ADVECT_CENTRED, ADVECT_SL = 0, 1
+MOB_ANALYTIC, MOB_FITTED = 0, 1
 
 STATUS = {0: "IBR_OK", 1: "IBR_EINVAL", 2: "IBR_ENOMEM", 3: "IBR_ENOCONV", 4: "IBR_EBREAKDOWN",
           5: "IBR_EFACTOR", 6: "IBR_ENUMERIC", 7: "IBR_EDEVICE", 8: "IBR_ESTATE"}
@@ -38,7 +39,7 @@ class Params(ctypes.Structure):
                 ("restart", ctypes.c_int), ("max_iters", ctypes.c_int), ("rtol", ctypes.c_double),
                 ("mg_pre", ctypes.c_int), ("mg_post", ctypes.c_int), ("mg_coarse", ctypes.c_int),
                 ("device", ctypes.c_int), ("stream", ctypes.c_void_p), ("graphs", ctypes.c_int),
-                ("walls", ctypes.c_int), ("advection", ctypes.c_int)]
+                ("walls", ctypes.c_int), ("advection", ctypes.c_int), ("mobility", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):

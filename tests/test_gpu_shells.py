@@ -33,14 +33,14 @@ pytestmark = pytest.mark.gpu
 LEVELS = ((32, 0), (64, 1), (128, 2))
 
 
-def _study(n, level, solver):
+def _study(n, level, solver, walls=False):
     p1 = single_shell(n, level)
     s = solver(p1)
     s.solve()
     F1, _ = s.forces()
     s.close()
     R1h = hasimoto.radius3d(abs(F1[0, 0]), 1.0)
-    p2 = concentric_shells(n, level)
+    p2 = concentric_shells(n, level, walls=walls)
     s = solver(p2)
     info = s.solve()
     sol = s.solution()
@@ -86,4 +86,32 @@ def test_concentric_shells_accuracy_table():
     out = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
     os.makedirs(out, exist_ok=True)
     with open(os.path.join(out, "shells_table.json"), "w") as f:
+        json.dump(rows, f, indent=1)
+
+
+def test_concentric_shells_walled_box_table():
+    """The same study in the paper's closed box (no-slip walls on every side,
+    at rest in the cavity's frame; the inner radius still comes from the
+    periodic lattice's drag law, as in the paper).  The cavity isolates its
+    interior, so the errors converge as in the periodic box and stay close to
+    its numbers; written to gpurun_out/shells_box_table.json."""
+    from paper_1505_07865_amd import ibr
+
+    def solver(prob):
+        return ibr.from_problem(prob, rtol=1e-8, restart=100, max_iters=3000, graphs=0)
+
+    rows = []
+    for n, level in LEVELS:
+        print("concentric shells in the walled box", n, level, flush=True)
+        rows.append(_study(n, level, solver, walls=True))
+        print(json.dumps(rows[-1]), flush=True)
+    for a, b in zip(rows, rows[1:]):
+        assert b["R2h_over_R2g"] > a["R2h_over_R2g"]
+        for nm in ("L1", "L2"):
+            rate = math.log2(a["v"][nm] / b["v"][nm])
+            b["v"]["rate_" + nm] = rate
+            assert rate > 0.7, (nm, rate)
+    out = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
+    os.makedirs(out, exist_ok=True)
+    with open(os.path.join(out, "shells_box_table.json"), "w") as f:
         json.dump(rows, f, indent=1)
