@@ -72,9 +72,12 @@ typedef enum { IBR_ADVECT_CENTRED = 0, IBR_ADVECT_SL = 1 } ibr_advection;
  * self term (finite beta), regularised logarithms (2D).  FITTED (3D only):
  * the forms of Appendix A fitted to pair mobilities of the four-point kernel
  * measured with this solver (the Sec. 4.2 procedure); at viscous CFL number
- * beta = eta dt / (rho h^2) the table rows around beta are interpolated
- * linearly, and beta above the last row uses the steady fit. */
-typedef enum { IBR_MOB_ANALYTIC = 0, IBR_MOB_FITTED = 1 } ibr_mobility;
+ * beta = eta dt / (rho h^2) the forms of the two table rows around beta,
+ * both evaluated at beta, are blended linearly in log beta; beta above the
+ * last row uses the steady fit; an unsteady periodic box adds its mean mode
+ * dt / (rho l^3).
+ * AUTO: FITTED in 3D, ANALYTIC in 2D. */
+typedef enum { IBR_MOB_ANALYTIC = 0, IBR_MOB_FITTED = 1, IBR_MOB_AUTO = 2 } ibr_mobility;
 
 /* Problem and solver parameters.  Sec. 3.2 (eq. A_def) defines
  * A = (rho/dt) I - eta h^-2 L; rho == 0 selects steady Stokes, where the
@@ -133,8 +136,10 @@ typedef struct {
                          so that g = (rho/dt) v_d; stable at any cell Reynolds
                          number and CFL number.  ibr_advect returns the
                          selected form's N. */
-  int mobility;       /* IBR_MOB_ANALYTIC (default) or IBR_MOB_FITTED (3D only;
-                         IBR_EINVAL otherwise) */
+  int mobility;       /* IBR_MOB_AUTO (default), IBR_MOB_ANALYTIC or
+                         IBR_MOB_FITTED (3D only; IBR_EINVAL otherwise).  It
+                         changes the preconditioner, hence iteration counts,
+                         not the converged solution. */
 } ibr_params;
 
 /* Per-solve report.  ps_applications counts P_S^-1 applications, the cost

@@ -267,12 +267,14 @@ struct MobParams {
   int steady;
   double a, eta, L, finf0, f00, alpha, dt_rho, periodic_shift;
   // fitted forms (3D): 0 = the analytic readings; 1 = the steady fit (ah =
-  // a/h, fs = b0..b6); 2 = the finite-beta fit at viscous CFL number beta
-  // (phi0, fa = a0..a9, fb = b0..b5, interpolated between table rows)
+  // a/h, fs = b0..b6); 2 = the finite-beta fit at viscous CFL number beta:
+  // phi0(beta), and the two table rows around beta (fa = a0..a9, fb =
+  // b0..b5), whose forms, both evaluated at beta, are blended with weights
+  // 1 - tw, tw (tw linear in log beta).
   // mean_mode: dt / (rho l^3), the uniform velocity a unit force gives the
   // fluid of an unsteady periodic box, added to f by the fitted forms
   int fit;
-  double h, beta, phi0, ah, mean_mode, fs[7], fa[10], fb[6];
+  double h, beta, phi0, ah, mean_mode, tw, fs[7], fa[2][10], fb[2][6];
 };
 void launch_mob_assemble(int dim, int nb, const int* offsets, const int64_t* moff, const double* R, MobParams p,
                          double* M, int max_np, hipStream_t s);

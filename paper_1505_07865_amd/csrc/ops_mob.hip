@@ -61,15 +61,23 @@ __device__ void mob_fg_fit(double r, const MobParams& p, double& f, double& g) {
     g = 0.0;
     return;
   }
-  const double* a = p.fa;
-  const double* b = p.fb;
   const double x2 = x * x, x3 = x2 * x, x4 = x2 * x2, x5 = x4 * x, x7 = x5 * x2;
-  const double sb = sqrt(p.beta);
-  const double ft = p.phi0 * (-4.0 * kPi * x3 + a[4] * (x5 - x7 * exp(-a[3] * x / sb) / (2.0 * p.beta))) /
-                        (1.0 + a[0] * x + a[1] * x2 + a[2] * x3 + a[4] * p.phi0 * x5) +
-                    (a[5] * x4 * exp(-a[6] * x) + a[7] * x4) / (1.0 + a[8] * x3 + a[9] * x5);
-  const double gt = p.phi0 * b[5] * (x5 + x7 * exp(-b[0] * x / sb) / (6.0 * p.beta)) /
-                    (1.0 + b[1] * x + b[2] * x2 + b[3] * x3 + b[4] * x4 + b[5] * p.phi0 * x5);
+  const double bq = p.beta, ph = p.phi0, sb = sqrt(bq);
+  double ft = 0.0, gt = 0.0;
+  for (int q = 0; q < 2; ++q) {
+    const double w = q == 0 ? 1.0 - p.tw : p.tw;
+    if (w == 0.0) continue;
+    // the forms of row q at beta itself
+    const double* a = p.fa[q];
+    const double* b = p.fb[q];
+    const double ftq = ph * (-4.0 * kPi * x3 + a[4] * (x5 - x7 * exp(-a[3] * x / sb) / (2.0 * bq))) /
+                           (1.0 + a[0] * x + a[1] * x2 + a[2] * x3 + a[4] * ph * x5) +
+                       (a[5] * x4 * exp(-a[6] * x) + a[7] * x4) / (1.0 + a[8] * x3 + a[9] * x5);
+    const double gtq = ph * b[5] * (x5 + x7 * exp(-b[0] * x / sb) / (6.0 * bq)) /
+                       (1.0 + b[1] * x + b[2] * x2 + b[3] * x3 + b[4] * x4 + b[5] * ph * x5);
+    ft += w * ftq;
+    gt += w * gtq;
+  }
   f = -pre * ft / (4.0 * kPi * x3) + p.mean_mode;
   g = pre * 3.0 * gt / (4.0 * kPi * x3);
 }

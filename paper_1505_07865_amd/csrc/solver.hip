@@ -530,7 +530,8 @@ void validate(const ibr_params* p) {
     throw Status(IBR_EINVAL, "bad walls");
   if (p->advection != IBR_ADVECT_CENTRED && p->advection != IBR_ADVECT_SL)
     throw Status(IBR_EINVAL, "bad advection");
-  if (p->mobility != IBR_MOB_ANALYTIC && p->mobility != IBR_MOB_FITTED) throw Status(IBR_EINVAL, "bad mobility");
+  if (p->mobility != IBR_MOB_ANALYTIC && p->mobility != IBR_MOB_FITTED && p->mobility != IBR_MOB_AUTO)
+    throw Status(IBR_EINVAL, "bad mobility");
   if (p->mobility == IBR_MOB_FITTED && (p->dim != 3 || kFitRows == 0))
     throw Status(IBR_EINVAL, "the fitted mobility exists for 3D only");
 }
@@ -555,7 +556,8 @@ MobParams mob_params(const ibr_ctx* c) {
     mp.dt_rho = c->p.dt / c->p.rho;
   }
   mp.h = c->h;
-  if (c->p.mobility == IBR_MOB_FITTED && kFitRows > 0) {
+  const bool fitted = c->p.mobility == IBR_MOB_FITTED || (c->p.mobility == IBR_MOB_AUTO && c->dim == 3);
+  if (fitted && kFitRows > 0) {
     mp.ah = kFitAh;
     for (int i = 0; i < 7; ++i) mp.fs[i] = kFitSteady[i];
     const double beta = c->steady ? 0.0 : c->p.eta * c->p.dt / (c->p.rho * c->h * c->h);
@@ -571,16 +573,22 @@ MobParams mob_params(const ibr_ctx* c) {
       const double z1 = kFitZ[0], z2 = kFitZ[1], z3 = kFitZ[2];
       const double z0 = 1.5 * std::pow(8.0 / 3.0, 3);  // 3 V_m / (2 h^3), the inviscid self mobility
       mp.phi0 = (1.0 + z1 * std::sqrt(beta) + z2 * beta) / (z0 + z3 * beta + 6.0 * kPi * kFitAh * z2 * beta * beta);
+      // the rows around beta: their forms at beta are blended with weights
+      // linear in log beta (below the first row, that row alone)
       int i = 0;
       while (i + 1 < kFitRows && kFitBeta[i + 1] < beta) ++i;
       double t = 0.0;
       int k = i;
       if (beta > kFitBeta[i] && i + 1 < kFitRows) {
         k = i + 1;
-        t = (beta - kFitBeta[i]) / (kFitBeta[k] - kFitBeta[i]);
+        t = std::log(beta / kFitBeta[i]) / std::log(kFitBeta[k] / kFitBeta[i]);
       }
-      for (int q = 0; q < 10; ++q) mp.fa[q] = (1.0 - t) * kFitA[i][q] + t * kFitA[k][q];
-      for (int q = 0; q < 6; ++q) mp.fb[q] = (1.0 - t) * kFitB[i][q] + t * kFitB[k][q];
+      mp.tw = t;
+      const int row[2] = {i, k};
+      for (int r = 0; r < 2; ++r) {
+        for (int q = 0; q < 10; ++q) mp.fa[r][q] = kFitA[row[r]][q];
+        for (int q = 0; q < 6; ++q) mp.fb[r][q] = kFitB[row[r]][q];
+      }
     }
   }
   return mp;
@@ -924,7 +932,7 @@ void ibr_default_params(ibr_params* p) {
   p->graphs = 1;
   p->walls = IBR_WALLS_NONE;
   p->advection = IBR_ADVECT_CENTRED;
-  p->mobility = IBR_MOB_ANALYTIC;
+  p->mobility = IBR_MOB_AUTO;
 }
 
 const char* ibr_status_string(int st) {

@@ -20,7 +20,7 @@ FP64, MIXED = 0, 1
 PC_LOWER, PC_FULL = 0, 1
 WALLS_NONE, WALLS_NOSLIP, WALLS_BOX = 0, 1, 2
 ADVECT_CENTRED, ADVECT_SL = 0, 1
-MOB_ANALYTIC, MOB_FITTED = 0, 1
+MOB_ANALYTIC, MOB_FITTED, MOB_AUTO = 0, 1, 2
 
 STATUS = {0: "IBR_OK", 1: "IBR_EINVAL", 2: "IBR_ENOMEM", 3: "IBR_ENOCONV", 4: "IBR_EBREAKDOWN",
           5: "IBR_EFACTOR", 6: "IBR_ENUMERIC", 7: "IBR_EDEVICE", 8: "IBR_ESTATE"}

@@ -39,8 +39,10 @@ Fitted forms (Appendix A):
     gt_b = phi0 b5 [x^5 + x^7 e^{-b0 x/sqrt(beta)} / (6 beta)]
            / (1 + b1 x + b2 x^2 + b3 x^3 + b4 x^4 + b5 phi0 x^5).
     The inviscid end of the table is beta = 0.01 (the solver needs eta > 0);
-    smaller beta use that row, larger than the last row the steady fit, and
-    rows in between are interpolated linearly (Appendix A).
+    smaller beta use that row, larger than the last row the steady fit; in
+    between, the library blends the two rows' fitted functions linearly in
+    beta (Appendix A interpolates the coefficients, which for independently
+    fitted rational forms is not a blend of the functions).
 
 The table is written to csrc/mobility_fit_4pt.inc and compiled into the
 library; params.mobility = IBR_MOB_FITTED selects it.
@@ -54,7 +56,10 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 TABLE = os.path.join(HERE, "csrc", "mobility_fit_4pt.inc")
 
-BETAS = (0.01, 0.1, 0.25, 0.5, 1.0, 10.0, 100.0, 1000.0)
+# the paper's table (its inviscid row measured at 0.01), with rows added between
+# its decades: the fitted functions change too much over a decade of beta for
+# a linear blend between two rows
+BETAS = (0.01, 0.1, 0.25, 0.5, 1.0, 2.0, 5.0, 10.0, 20.0, 50.0, 100.0, 200.0, 500.0, 1000.0)
 VM_OVER_H3 = (8.0 / 3.0) ** 3          # four-point marker volume: squared weights sum to 3/8 per dimension
 Z0 = 1.5 * VM_OVER_H3                  # phi0(0) = 2 h^3 / (3 V_m) = 1 / z0
 SHIFT_3D = 2.84
@@ -129,10 +134,10 @@ def fit_phi0(betas, phis, ah):
 
 
 # Bounds of the finite-beta coefficients: every denominator coefficient is
-# non-negative (no pole at any distance, also after linear interpolation
-# between two rows), the decay rates a3, a6, b0 and the far-field weights a4,
-# b5 positive, and all magnitudes below 1e3 (the rational forms are
-# otherwise free to scale numerator and denominator together without bound).
+# non-negative (no pole at any distance), the decay rates a3, a6, b0 and the
+# far-field weights a4, b5 positive, and all magnitudes below 1e3 (the
+# rational forms are otherwise free to scale numerator and denominator
+# together without bound).
 LB_A = [0.0, 0.0, 0.0, 1e-3, 1e-6, -1e3, 1e-3, -1e3, 0.0, 0.0]
 UB_A = [1e3, 1e3, 1e3, 1e2, 1e3, 1e3, 1e2, 1e3, 1e3, 1e3]
 LB_B = [1e-3, 0.0, 0.0, 0.0, 0.0, 1e-6]
@@ -231,7 +236,10 @@ def write_table(path, ah, bst, z, rows):
     lines = ["// Fitted approximate mobility of the four-point kernel (forms of the",
              "// paper's Appendix A, Sec. 4.2 fitting procedure); generated by",
              "// paper_1505_07865_amd/mobility_fit.py from pair mobilities measured with",
-             "// this library's solver.  Do not edit.",
+             "// this library's solver (64^3, two clouds of 120 markers):",
+             "//   python -m paper_1505_07865_amd.mobility_fit --measure-only --pairs P.npz   (GPU)",
+             "//   python -m paper_1505_07865_amd.mobility_fit --fit-only --pairs P.npz[,Q.npz]",
+             "// Do not edit.",
              "constexpr int kFitRows = %d;" % len(rows),
              "constexpr double kFitAh = %.17g;" % ah,
              "constexpr double kFitSteady[7] = {%s};" % fmt(bst),
@@ -250,19 +258,20 @@ def measure_clouds(clouds, n, h, rho, eta, dt, L):
     return tuple(np.concatenate([p[k] for p in parts]) for k in range(4))
 
 
-def measure_all(n=64, N=120, seed=0):
-    """Pair data of two clouds of N markers, steady and at every tabulated
-    beta: one cloud in a cube of side l/8 (the paper's, dense pairs from h
-    to 14 h) and one of side l/4 (pairs out to about 27 h).  Returns
+def measure_all(n=64, N=120, seed=0, betas=BETAS, steady=True):
+    """Pair data of two clouds of N markers, steady and at the given betas:
+    one cloud in a cube of side l/8 (the paper's, dense pairs from h to
+    14 h) and one of side l/4 (pairs out to about 27 h).  Returns
     {key: (x, mu_par, mu_perp, self)} with key "steady" or the beta."""
     h = 1.0 / n
     L = n * h
     clouds = [cloud(seed, N, L, h), cloud(seed + 1, N, L, h, side=0.25)]
     data = {}
-    print("steady: 2 clouds of %d markers" % N, flush=True)
-    r, par, perp, self_ = measure_clouds(clouds, n, h, 0.0, 1.0, 0.0, L)
-    data["steady"] = (r / h, par, perp, self_)
-    for beta in BETAS:
+    if steady:
+        print("steady: 2 clouds of %d markers" % N, flush=True)
+        r, par, perp, self_ = measure_clouds(clouds, n, h, 0.0, 1.0, 0.0, L)
+        data["steady"] = (r / h, par, perp, self_)
+    for beta in betas:
         # rho = 1, dt = 1: eta = beta h^2
         print("beta %g" % beta, flush=True)
         r, par, perp, self_ = measure_clouds(clouds, n, h, 1.0, beta * h * h, 1.0, L)
@@ -275,12 +284,22 @@ def save_pairs(path, data, n):
              **{("self_steady" if k == "steady" else "self_beta%r" % k): v[3] for k, v in data.items()})
 
 
-def load_pairs(path):
-    z = np.load(path)
-    data = {"steady": tuple(z["steady"]) + (z["self_steady"],)}
-    for beta in BETAS:
-        data[beta] = tuple(z["beta%r" % beta]) + (z["self_beta%r" % beta],)
-    return data, int(z["n"])
+def load_pairs(paths):
+    """Pair data from one or more files written by save_pairs (comma-separated
+    paths; later files add keys)."""
+    data, n = {}, None
+    for path in paths.split(","):
+        z = np.load(path)
+        n = int(z["n"])
+        if "steady" in z.files:
+            data["steady"] = tuple(z["steady"]) + (z["self_steady"],)
+        for beta in BETAS:
+            if "beta%r" % beta in z.files:
+                data[beta] = tuple(z["beta%r" % beta]) + (z["self_beta%r" % beta],)
+    missing = [b for b in ("steady",) + BETAS if b not in data]
+    if missing:
+        raise ValueError("pair data missing for %s" % missing)
+    return data, n
 
 
 def binned(x, par, perp, xmax, nbins=160):
@@ -330,11 +349,12 @@ def fit_all(data, n, xmax=16.0):
     return ah, bst, z, rows
 
 
-def main(n=64, N=120, seed=0, out=TABLE, pairs=None, measure_only=False, fit_only=False):
+def main(n=64, N=120, seed=0, out=TABLE, pairs=None, measure_only=False, fit_only=False, betas=BETAS,
+         steady=True):
     if fit_only:
         data, n = load_pairs(pairs)
     else:
-        data = measure_all(n, N, seed)
+        data = measure_all(n, N, seed, betas, steady)
         if pairs:
             save_pairs(pairs, data, n)
             print("wrote", pairs, flush=True)
@@ -353,6 +373,11 @@ if __name__ == "__main__":
     ap.add_argument("--n", type=int, default=64)
     ap.add_argument("--pairs", default=None, help="pair data file (.npz) to write after measuring, or to fit")
     ap.add_argument("--measure-only", action="store_true", help="measure and write --pairs, no fit")
-    ap.add_argument("--fit-only", action="store_true", help="fit the pair data in --pairs (no GPU)")
+    ap.add_argument("--fit-only", action="store_true",
+                    help="fit the pair data in --pairs (comma-separated files; no GPU)")
+    ap.add_argument("--betas", default=None, help="measure: comma-separated subset of the table's betas")
+    ap.add_argument("--no-steady", action="store_true", help="measure: skip the steady data")
     a = ap.parse_args()
-    main(n=a.n, N=a.markers, out=a.out, pairs=a.pairs, measure_only=a.measure_only, fit_only=a.fit_only)
+    betas = BETAS if a.betas is None else tuple(float(b) for b in a.betas.split(","))
+    main(n=a.n, N=a.markers, out=a.out, pairs=a.pairs, measure_only=a.measure_only, fit_only=a.fit_only,
+         betas=betas, steady=not a.no_steady)

@@ -38,6 +38,7 @@ def test_default_params_and_status(lib):
     p = ibr.Params()
     lib.ibr_default_params(ctypes.byref(p))
     assert p.dim == 3 and p.restart == 100 and p.n_s == 2 and p.rtol == 1e-8 and p.walls == 0 and p.advection == 0
+    assert p.mobility == 2          # IBR_MOB_AUTO
     assert lib.ibr_status_string(0) == b"ok"
     assert lib.ibr_status_string(5).startswith(b"mobility")
 
@@ -73,7 +74,8 @@ def test_params_layout_matches_header(tmp_path):
 def test_invalid_params_rejected_before_device_work(lib):
     from paper_1505_07865_amd import ibr
     for bad in (dict(dim=4), dict(n=48), dict(h=0.0), dict(eta=-1.0), dict(rho=1.0, dt=0.0), dict(n_s=0),
-                dict(rtol=0.0), dict(precision=7), dict(walls=3), dict(walls=-1), dict(advection=2), dict(advection=-1)):
+                dict(rtol=0.0), dict(precision=7), dict(walls=3), dict(walls=-1), dict(advection=2), dict(advection=-1),
+                dict(mobility=3), dict(mobility=-1), dict(dim=2, n=32, h=1.0 / 32, mobility=1)):
         p = ibr.default_params(**bad)
         ctx = ctypes.c_void_p()
         assert lib.ibr_create(ctypes.byref(p), ctypes.byref(ctx)) == 1, bad

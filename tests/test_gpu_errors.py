@@ -113,7 +113,7 @@ def test_shifted_factorisation_reaches_oracle(dim):
     _, shift_oracle = mobility.factor_block(blocks[0], mobility.self_term(p))
     print("dense markers, %dD, oracle shift %g" % (dim, shift_oracle), flush=True)
     assert shift_oracle > 0                                  # the fallback is exercised
-    s = ibr.from_problem(prob, rtol=1e-10)
+    s = ibr.from_problem(prob, rtol=1e-10, mobility=ibr.MOB_ANALYTIC)
     M, shift = s.mobility_block(0)
     info = s.solve()
     sol = s.solution()

@@ -55,7 +55,9 @@ def _body_block(prob, z):
 
 
 def _solver(prob, mask, F, T, **kw):
+    """The oracle's preconditioner uses the analytic approximate mobility."""
     from paper_1505_07865_amd import ibr
+    kw.setdefault("mobility", ibr.MOB_ANALYTIC)
     s = ibr.from_problem(prob, **kw)
     s.set_free_bodies(mask, F, T)
     return s

@@ -99,7 +99,7 @@ def test_steady256_100_spheres_true_residual():
     from paper_1505_07865_amd import ibr
     prob = config4_spheres256(0)
     print("256^3 steady, %d markers, mixed, restart 50" % prob.nmarkers, flush=True)
-    s = ibr.from_problem(prob, rtol=1e-8, precision=ibr.MIXED, restart=50, graphs=0)
+    s = ibr.from_problem(prob, rtol=1e-8, precision=ibr.MIXED, restart=50, graphs=0, mobility=ibr.MOB_ANALYTIC)
     blocks, p = mobility.blocks_for_problem(prob)
     for body in (0, 57, prob.nbodies - 1):
         M, _ = s.mobility_block(body)

@@ -3,9 +3,10 @@
 * The block the library assembles with params.mobility = IBR_MOB_FITTED equals
   the Appendix A forms evaluated in NumPy from the compiled table (1e-12),
   plus the mean mode dt / (rho l^3) of an unsteady periodic box:
-  steady Stokes, beta between table rows (coefficients interpolated linearly),
-  beta below the first row (that row), beta beyond the last (the steady form,
-  without the periodic shift of a steady box).
+  steady Stokes, beta between table rows (the two rows' forms at beta,
+  blended with weights linear in log beta), beta below the first row (that
+  row), beta beyond the last (the steady form, without the periodic shift of
+  a steady box).
 * On a random marker cloud the fitted block is closer to the exact mobility
   (the oracle's Fourier solve, Sec. 3.3) than the analytic reading's block,
   steady and at finite beta: what the fit is for (Sec. 4.2).
@@ -58,19 +59,21 @@ def _fitted_fg(r, h, eta, L, beta, T, dt_rho=1.0):
     pre = beta / (eta * h)
     if r == 0.0:
         return ph * pre + mean, 0.0
+    # the forms of the two rows around beta, both at beta, blended with
+    # weights linear in log beta
     bs = T["beta"]
     i = 0
     while i + 1 < len(bs) and bs[i + 1] < beta:
         i += 1
+    rows = [(i, 1.0)]
     if beta > bs[i] and i + 1 < len(bs):
-        t = (beta - bs[i]) / (bs[i + 1] - bs[i])
-        a = (1 - t) * T["A"][i] + t * T["A"][i + 1]
-        b = (1 - t) * T["B"][i] + t * T["B"][i + 1]
-    else:
-        a, b = T["A"][i], T["B"][i]
+        t = math.log(beta / bs[i]) / math.log(bs[i + 1] / bs[i])
+        rows = [(i, 1.0 - t), (i + 1, t)]
     x = r / h
-    ft = float(mf.ft_beta(x, beta, ph, a))
-    gt = float(mf.gt_beta(x, beta, ph, b))
+    ft = gt = 0.0
+    for k, w in rows:
+        ft += w * float(mf.ft_beta(x, beta, ph, T["A"][k]))
+        gt += w * float(mf.gt_beta(x, beta, ph, T["B"][k]))
     return -pre * ft / (4.0 * math.pi * x ** 3) + mean, pre * 3.0 * gt / (4.0 * math.pi * x ** 3)
 
 

@@ -23,7 +23,9 @@ CASES = {
 
 
 def _solver(prob, **kw):
+    """The oracle's preconditioner uses the analytic approximate mobility."""
     from paper_1505_07865_amd import ibr
+    kw.setdefault("mobility", ibr.MOB_ANALYTIC)
     return ibr.from_problem(prob, **kw)
 
 
