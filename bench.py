@@ -72,6 +72,7 @@ def parse():
                     help="centred advective form with AB2, or semi-Lagrangian transport; auto takes the "
                          "centred form while the cell Reynolds number Re h/R is at most 8 (where it is stable)")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--n-s", type=int, default=2, help="inner GMRES(N_s) iterations of the preconditioner")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", choices=["both", "mixed", "fp64"], default="both")
     ap.add_argument("--serving", action="store_true",
@@ -147,12 +148,12 @@ def advection_scheme(args):
     return "centred" if args.re / 6.0 <= 8.0 else "sl"
 
 
-def run_precision(prob, prec, steps, warmup, torch, scheme="centred"):
+def run_precision(prob, prec, steps, warmup, torch, scheme="centred", n_s=2):
     from paper_1505_07865_amd import ibr
     # kernels go straight onto the stream (iteration graphs measured no faster,
     # and the live event timers bracket individual launches)
     s = ibr.from_problem(prob, rtol=1e-8, precision=ibr.MIXED if prec == "mixed" else ibr.FP64, device=0,
-                         graphs=0, advection=ibr.ADVECT_SL if scheme == "sl" else ibr.ADVECT_CENTRED)
+                         graphs=0, advection=ibr.ADVECT_SL if scheme == "sl" else ibr.ADVECT_CENTRED, n_s=n_s)
     # sampled event timing keeps the instrumentation cost small; enabling
     # again before the timed region resets the counters
     for t in ibr.TIMERS:
@@ -296,7 +297,7 @@ def second_re(args, torch):
     for p in ("fp64", "mixed"):
         print("bench: Re %g, %s, %d warmup + %d timed steps" % (re, p, args.warmup, args.steps), file=sys.stderr,
               flush=True)
-        res[p] = run_precision(prob, p, args.steps, args.warmup, torch, scheme)
+        res[p] = run_precision(prob, p, args.steps, args.warmup, torch, scheme, args.n_s)
         out[p] = {"solves_per_s": round(res[p]["solves_per_s"], 3), "p50_ms": round(res[p]["p50_ms"], 3),
                   "p99_ms": round(res[p]["p99_ms"], 3),
                   "fgmres_iters_mean": round(res[p]["fgmres_iters_mean"], 2),
@@ -820,9 +821,13 @@ def mobility_study(args, torch):
       the 128^3 moving-spheres workload at Re = 10 (beta = 0.3): the first
       three time steps, mixed precision as benchmarked;
       the 256^3 configuration (steady, 100 spheres of 200 markers): one
-      solve from rest, mixed precision, restart 50."""
+      solve from rest, mixed precision, restart 50;
+      in 2D (Appendix B's forms): the 64^2 disk (rtol 1e-10), 8 disks of
+      radius 6h at 256^2 (both precisions) and 4 disks at 128^2, one
+      unsteady solve at beta = 0.3."""
     from paper_1505_07865_amd import ibr
-    from synthetic import box_shell, config2_spheres_ns, config4_spheres256, shell_problem
+    from synthetic import (box_shell, config0_disk2d, config2_spheres_ns, config4_spheres256, shell_problem,
+                           small_problem)
     rows = []
     mobs = (("analytic", ibr.MOB_ANALYTIC), ("fitted", ibr.MOB_FITTED))
 
@@ -859,6 +864,16 @@ def mobility_study(args, torch):
     print("bench: mobility study 128^3 done", file=sys.stderr, flush=True)
     prob = config4_spheres256(args.seed)
     solve_row(prob, "spheres_256_steady", rtol=1e-8, precision=ibr.MIXED, restart=50, max_iters=400)
+    # two dimensions (Appendix B's forms): the 64^2 disk, many disks at 256^2 (the serving trace's hard
+    # case), and an unsteady solve (beta = 0.3)
+    solve_row(config0_disk2d(args.seed), "disk_64", rtol=1e-10)
+    for prec in (ibr.FP64, ibr.MIXED):
+        solve_row(small_problem(args.seed, 2, 256, nbodies=8, radius_h=6.0), "disks8_256_steady", rtol=1e-8,
+                  precision=prec, max_iters=1000)
+    h = 1.0 / 128
+    solve_row(small_problem(args.seed, 2, 128, nbodies=4, radius_h=6.0, rho=1.0, eta=0.6 * h, dt=0.5 * h),
+              "disks4_128_beta0.3", rtol=1e-8, max_iters=1000)
+    print("bench: mobility study 2D done", file=sys.stderr, flush=True)
     line = {"metric": "P_S^-1 applications to relative residual 1e-8, fitted vs analytic approximate mobility",
             "value": None, "unit": "P_S^-1 applications", "n_gpus": 1, "higher_is_better": False,
             "vs_baseline": None, "data": "synthetic",
@@ -913,7 +928,7 @@ def main():
     for p in precs:
         print("bench: %s, %d warmup + %d timed steps" % (p, args.warmup, args.steps), file=sys.stderr,
               flush=True)
-        res[p] = run_precision(prob, p, args.steps, args.warmup, torch, scheme)
+        res[p] = run_precision(prob, p, args.steps, args.warmup, torch, scheme, args.n_s)
         print("bench: %s %.2f solves/s, %.1f FGMRES iters/step" % (p, res[p]["solves_per_s"],
                                                                    res[p]["fgmres_iters_mean"]),
               file=sys.stderr, flush=True)
@@ -933,11 +948,12 @@ def main():
         "dtype": "f32 preconditioner + f64 outer" if "mixed" in res else "f64",
         "data": "synthetic",
         "config": {"workload": "3D unsteady NS, periodic 128^3 MAC grid, Re=%g, dt=0.5h, 16 moving spheres "
-                               "R=6h x 110 markers, rtol 1e-8, N_s=2, lower-triangular Schur preconditioner "
+                               "R=6h x 110 markers, rtol 1e-8, N_s=%d, lower-triangular Schur preconditioner "
                                "with the fitted approximate mobility, %s advection"
-                               % (args.re, "semi-Lagrangian" if scheme == "sl" else "centred AB2"),
+                               % (args.re, args.n_s, "semi-Lagrangian" if scheme == "sl" else "centred AB2"),
                    "grid": 128, "bodies": 16, "markers": int(prob.nmarkers), "re": args.re, "seed": args.seed,
-                   "rtol": 1e-8, "advection": scheme, "approximate_mobility": "fitted (Appendix A forms)"},
+                   "rtol": 1e-8, "n_s": args.n_s, "advection": scheme,
+                   "approximate_mobility": "fitted (Appendix A forms)"},
         "p50_ms": round(head["p50_ms"], 3),
         "p99_ms": round(head["p99_ms"], 3),
         "fgmres_iters_per_step": round(head["fgmres_iters_mean"], 2),

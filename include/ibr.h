@@ -69,14 +69,14 @@ typedef enum { IBR_WALLS_NONE = 0, IBR_WALLS_NOSLIP = 1, IBR_WALLS_BOX = 2 } ibr
 typedef enum { IBR_ADVECT_CENTRED = 0, IBR_ADVECT_SL = 1 } ibr_advection;
 /* Approximate mobility M~ of the preconditioner (Sec. 4).  ANALYTIC: the RPY
  * tensor with the periodic shift (steady 3D), the Brinkmanlet with a blended
- * self term (finite beta), regularised logarithms (2D).  FITTED (3D only):
- * the forms of Appendix A fitted to pair mobilities of the four-point kernel
- * measured with this solver (the Sec. 4.2 procedure); at viscous CFL number
- * beta = eta dt / (rho h^2) the forms of the two table rows around beta,
- * both evaluated at beta, are blended linearly in log beta; beta above the
- * last row uses the steady fit; an unsteady periodic box adds its mean mode
- * dt / (rho l^3).
- * AUTO: FITTED in 3D, ANALYTIC in 2D. */
+ * self term (finite beta), regularised logarithms (2D).  FITTED: the forms
+ * of Appendix A (3D) and Appendix B (2D) fitted to pair mobilities of the
+ * four-point kernel measured with this solver (the Sec. 4.2 procedure); at
+ * viscous CFL number beta = eta dt / (rho h^2) the forms of the two table
+ * rows around beta, both evaluated at beta, are blended linearly in log
+ * beta; beta above the last row uses the steady fit; an unsteady periodic
+ * box adds its mean mode dt / (rho l^d).  AUTO: FITTED where the library
+ * holds a table for the dimension, else ANALYTIC. */
 typedef enum { IBR_MOB_ANALYTIC = 0, IBR_MOB_FITTED = 1, IBR_MOB_AUTO = 2 } ibr_mobility;
 
 /* Problem and solver parameters.  Sec. 3.2 (eq. A_def) defines
@@ -137,9 +137,9 @@ typedef struct {
                          number and CFL number.  ibr_advect returns the
                          selected form's N. */
   int mobility;       /* IBR_MOB_AUTO (default), IBR_MOB_ANALYTIC or
-                         IBR_MOB_FITTED (3D only; IBR_EINVAL otherwise).  It
-                         changes the preconditioner, hence iteration counts,
-                         not the converged solution. */
+                         IBR_MOB_FITTED (IBR_EINVAL without a table for the
+                         dimension).  It changes the preconditioner, hence
+                         iteration counts, not the converged solution. */
 } ibr_params;
 
 /* Per-solve report.  ps_applications counts P_S^-1 applications, the cost

@@ -271,10 +271,13 @@ struct MobParams {
   // phi0(beta), and the two table rows around beta (fa = a0..a9, fb =
   // b0..b5), whose forms, both evaluated at beta, are blended with weights
   // 1 - tw, tw (tw linear in log beta).
-  // mean_mode: dt / (rho l^3), the uniform velocity a unit force gives the
+  // 2D (Appendix B): 3 = the steady fit (self0 = f(0), f2s = a0..a4,
+  // b0..b3); 4 = the finite-beta fit (phi0, rows f2r = a0..a3, p1, b1, b2,
+  // c0..c3, p2, p3, blended like the 3D rows).
+  // mean_mode: dt / (rho l^d), the uniform velocity a unit force gives the
   // fluid of an unsteady periodic box, added to f by the fitted forms
   int fit;
-  double h, beta, phi0, ah, mean_mode, tw, fs[7], fa[2][10], fb[2][6];
+  double h, beta, phi0, ah, mean_mode, tw, self0, fs[7], fa[2][10], fb[2][6], f2s[9], f2r[2][13];
 };
 void launch_mob_assemble(int dim, int nb, const int* offsets, const int64_t* moff, const double* R, MobParams p,
                          double* M, int max_np, hipStream_t s);

@@ -38,6 +38,47 @@ __device__ void fb_far(double r, const MobParams& p, double& f, double& g) {
 // and f(0) = phi0 beta / (eta h), g(0) = 0.
 __device__ void mob_fg_fit(double r, const MobParams& p, double& f, double& g) {
   const double x = r / p.h;
+  if (p.fit == 3) {
+    // 2D steady: f = f(0) - f~ / (4 pi eta), g = g~ / (4 pi eta)
+    if (x < 1e-3) {
+      f = p.self0 + p.mean_mode;
+      g = 0.0;
+      return;
+    }
+    const double* c = p.f2s;
+    const double c4 = 1.0 / (4.0 * kPi * p.eta);
+    const double x2 = x * x, x3 = x2 * x, lx = log(x);
+    const double ft = (c[0] * x2 + c[1] * x3 + c[2] * x3 * lx) / (1.0 + c[3] * x + c[4] * x2 + c[2] * x3);
+    const double gt = (c[5] * x2 + c[6] * x3) / (1.0 + c[7] * x + c[8] * x2 + c[6] * x3);
+    f = p.self0 - c4 * ft + p.mean_mode;
+    g = c4 * gt;
+    return;
+  }
+  if (p.fit == 4) {
+    // 2D finite beta: f = -(beta / (2 pi eta x^2)) f~, g = (beta / (pi eta x^2)) g~
+    const double be = p.beta / p.eta;
+    if (x < 1e-3) {
+      f = p.phi0 * be + p.mean_mode;
+      g = 0.0;
+      return;
+    }
+    const double x2 = x * x, x3 = x2 * x, x4 = x2 * x2, lx = log(x), sb = sqrt(p.beta);
+    double ft = 0.0, gt = 0.0;
+    for (int q = 0; q < 2; ++q) {
+      const double w = q == 0 ? 1.0 - p.tw : p.tw;
+      if (w == 0.0) continue;
+      const double* c = p.f2r[q];
+      const double ftq = x3 * lx / (p.beta * (c[0] + 2.0 * x)) * exp(-c[4] * x / sb) +
+                         (c[1] * x2 + c[2] * x3 + c[3] * x4) / (1.0 + c[5] * x2 + c[6] * x3 + c[3] * x4);
+      const double gtq = x3 / (p.beta * (c[7] + 4.0 * x)) * exp(-c[11] * x / sb) +
+                         x3 / (exp(-c[12] * x) * (c[8] + c[9] * x + c[10] * x2) + x3);
+      ft += w * ftq;
+      gt += w * gtq;
+    }
+    f = -be * ft / (2.0 * kPi * x2) + p.mean_mode;
+    g = be * gt / (kPi * x2);
+    return;
+  }
   if (p.fit == 1) {
     const double* b = p.fs;
     const double c = 1.0 / (8.0 * kPi * p.eta * p.h);

@@ -31,6 +31,7 @@ using namespace ibr;
 namespace {
 
 #include "mobility_fit_4pt.inc"
+#include "mobility_fit_4pt_2d.inc"
 
 constexpr double kPi = 3.14159265358979323846;
 constexpr double kA3D = 1.25;      // four-point marker hydrodynamic radius, units of h (3D)
@@ -532,8 +533,8 @@ void validate(const ibr_params* p) {
     throw Status(IBR_EINVAL, "bad advection");
   if (p->mobility != IBR_MOB_ANALYTIC && p->mobility != IBR_MOB_FITTED && p->mobility != IBR_MOB_AUTO)
     throw Status(IBR_EINVAL, "bad mobility");
-  if (p->mobility == IBR_MOB_FITTED && (p->dim != 3 || kFitRows == 0))
-    throw Status(IBR_EINVAL, "the fitted mobility exists for 3D only");
+  if (p->mobility == IBR_MOB_FITTED && (p->dim == 3 ? kFitRows : kFit2Rows) == 0)
+    throw Status(IBR_EINVAL, "no fitted mobility table for this dimension");
 }
 
 MobParams mob_params(const ibr_ctx* c) {
@@ -556,8 +557,37 @@ MobParams mob_params(const ibr_ctx* c) {
     mp.dt_rho = c->p.dt / c->p.rho;
   }
   mp.h = c->h;
-  const bool fitted = c->p.mobility == IBR_MOB_FITTED || (c->p.mobility == IBR_MOB_AUTO && c->dim == 3);
-  if (fitted && kFitRows > 0) {
+  const bool fitted = c->p.mobility == IBR_MOB_FITTED || c->p.mobility == IBR_MOB_AUTO;
+  if (fitted && c->dim == 2 && kFit2Rows > 0) {
+    // Appendix B's forms
+    mp.ah = kFit2Ah;
+    for (int i = 0; i < 9; ++i) mp.f2s[i] = kFit2Steady[i];
+    const double beta = c->steady ? 0.0 : c->p.eta * c->p.dt / (c->p.rho * c->h * c->h);
+    if (!c->steady && !c->walls) mp.mean_mode = c->p.dt / (c->p.rho * c->vol);
+    if (c->steady || beta > kFit2Beta[kFit2Rows - 1]) {
+      mp.fit = 3;
+      // the periodic square's self mobility ln(l / (3.708 a)) / (4 pi eta)
+      mp.self0 = std::log(c->L / (3.708 * kFit2Ah * c->h)) / (4.0 * kPi * mp.eta);
+    } else {
+      mp.fit = 4;
+      mp.beta = beta;
+      const double z0 = 1.0 / (2.0 * (8.0 / 3.0) * (8.0 / 3.0));  // h^2 / (2 V_m), the inviscid self mobility
+      mp.phi0 = (z0 + kFit2Z[0] * beta * beta * beta * std::log(beta)) /
+                (1.0 + kFit2Z[1] * beta + kFit2Z[2] * beta * beta + kFit2Z[3] * beta * beta * beta * beta);
+      int i = 0;
+      while (i + 1 < kFit2Rows && kFit2Beta[i + 1] < beta) ++i;
+      double t = 0.0;
+      int k = i;
+      if (beta > kFit2Beta[i] && i + 1 < kFit2Rows) {
+        k = i + 1;
+        t = std::log(beta / kFit2Beta[i]) / std::log(kFit2Beta[k] / kFit2Beta[i]);
+      }
+      mp.tw = t;
+      const int row[2] = {i, k};
+      for (int r = 0; r < 2; ++r)
+        for (int q = 0; q < 13; ++q) mp.f2r[r][q] = kFit2Row[row[r]][q];
+    }
+  } else if (fitted && c->dim == 3 && kFitRows > 0) {
     mp.ah = kFitAh;
     for (int i = 0; i < 7; ++i) mp.fs[i] = kFitSteady[i];
     const double beta = c->steady ? 0.0 : c->p.eta * c->p.dt / (c->p.rho * c->h * c->h);
@@ -597,6 +627,8 @@ MobParams mob_params(const ibr_ctx* c) {
 double self_term(const MobParams& mp) {
   if (mp.fit == 1) return 1.0 / (6.0 * kPi * mp.eta * mp.ah * mp.h) - mp.periodic_shift + mp.mean_mode;
   if (mp.fit == 2) return mp.phi0 * mp.beta / (mp.eta * mp.h) + mp.mean_mode;
+  if (mp.fit == 3) return mp.self0 + mp.mean_mode;
+  if (mp.fit == 4) return mp.phi0 * mp.beta / mp.eta + mp.mean_mode;
   if (!mp.steady) return mp.f00;
   if (mp.dim == 3) return mp.finf0 - mp.periodic_shift;
   return mp.finf0;

@@ -169,29 +169,29 @@ def fit_beta(x, par, perp, beta, eta, h, ph, prev=None):
 
 
 def pair_stats(M, R, L):
-    """x-independent pair data of a measured mobility M (3N x 3N, markers R):
+    """Pair data of a measured mobility M (dN x dN, markers R [N][d]):
     distances r, mu_par, mu_perp for every pair i < j, self mobilities."""
-    N = R.shape[0]
+    N, d = R.shape
     i, j = np.triu_indices(N, 1)
-    d = R[i] - R[j]
-    d -= L * np.round(d / L)
-    r = np.linalg.norm(d, axis=1)
-    rh = d / r[:, None]
-    B = M.reshape(N, 3, N, 3)[i, :, j, :]
+    dr = R[i] - R[j]
+    dr -= L * np.round(dr / L)
+    r = np.linalg.norm(dr, axis=1)
+    rh = dr / r[:, None]
+    B = M.reshape(N, d, N, d)[i, :, j, :]
     par = np.einsum("pa,pab,pb->p", rh, B, rh)
-    perp = (np.trace(B, axis1=1, axis2=2) - par) / 2.0
-    self_ = np.array([np.trace(M[3 * k:3 * k + 3, 3 * k:3 * k + 3]) / 3.0 for k in range(N)])
+    perp = (np.trace(B, axis1=1, axis2=2) - par) / (d - 1)
+    self_ = np.array([np.trace(M[d * k:d * k + d, d * k:d * k + d]) / d for k in range(N)])
     return r, par, perp, self_
 
 
-def cloud(seed, N, L, h, min_dist=1.05, side=0.125):
-    """N random markers in a cube of side side * L at the box centre, at
-    least min_dist h apart."""
+def cloud(seed, N, L, h, min_dist=1.05, side=0.125, dim=3):
+    """N random markers in a cube (square) of side side * L at the box
+    centre, at least min_dist h apart."""
     rng = np.random.default_rng(seed)
-    c = np.full(3, L / 2)
+    c = np.full(dim, L / 2)
     R = []
     while len(R) < N:
-        p = c + rng.uniform(-0.5 * side * L, 0.5 * side * L, 3)
+        p = c + rng.uniform(-0.5 * side * L, 0.5 * side * L, dim)
         if all(np.linalg.norm(p - q) >= min_dist * h for q in R):
             R.append(p)
     return np.array(R)
@@ -199,30 +199,31 @@ def cloud(seed, N, L, h, min_dist=1.05, side=0.125):
 
 # ---------------------------------------------------------------- measurement (GPU)
 def measure(R, n, h, rho, eta, dt):
-    """M of the marker cloud R from 3N constrained solves.  For the columns of
+    """M of the marker cloud R from dN constrained solves.  For the columns of
     marker k, marker k is one body and the other N - 1 markers a second one
     at rest: the second body's block of the approximate mobility then covers
     their interactions, which keeps FGMRES short (with one body per marker
     the preconditioner sees only self mobilities and needs thousands of
     iterations)."""
     from . import ibr
-    N = R.shape[0]
-    s = ibr.Solver(dim=3, n=n, h=h, rho=rho, eta=eta, dt=dt, rtol=2e-9, max_iters=2000, restart=200,
-                   precision=ibr.FP64, graphs=0)
-    Minv = np.zeros((3 * N, 3 * N))
+    N, d = R.shape
+    nrot = 3 if d == 3 else 1
+    s = ibr.Solver(dim=d, n=n, h=h, rho=rho, eta=eta, dt=dt, rtol=2e-9, max_iters=2000, restart=200,
+                   precision=ibr.FP64, graphs=0, mobility=ibr.MOB_ANALYTIC)
+    Minv = np.zeros((d * N, d * N))
     t0 = time.perf_counter()
     for k in range(N):
         order = np.r_[np.delete(np.arange(N), k), k]
         Rk = R[order]
         s.set_bodies(Rk, np.array([0, N - 1, N]), np.vstack([Rk[:-1].mean(axis=0), Rk[-1]]))
-        for a in range(3):
-            U = np.zeros((2, 3))
+        for a in range(d):
+            U = np.zeros((2, d))
             U[1, a] = 1.0
-            s.set_velocities(U, np.zeros((2, 3)))
+            s.set_velocities(U, np.zeros((2, nrot)))
             s.solve()
-            col = np.zeros((N, 3))
+            col = np.zeros((N, d))
             col[order] = s.solution().lam
-            Minv[:, 3 * k + a] = col.reshape(-1)
+            Minv[:, d * k + a] = col.reshape(-1)
         if (k + 1) % 20 == 0:
             print("  %d / %d markers, %.1f s" % (k + 1, N, time.perf_counter() - t0), flush=True)
     s.close()
@@ -284,7 +285,7 @@ def save_pairs(path, data, n):
              **{("self_steady" if k == "steady" else "self_beta%r" % k): v[3] for k, v in data.items()})
 
 
-def load_pairs(paths):
+def load_pairs(paths, betas=BETAS):
     """Pair data from one or more files written by save_pairs (comma-separated
     paths; later files add keys)."""
     data, n = {}, None
@@ -293,10 +294,10 @@ def load_pairs(paths):
         n = int(z["n"])
         if "steady" in z.files:
             data["steady"] = tuple(z["steady"]) + (z["self_steady"],)
-        for beta in BETAS:
+        for beta in betas:
             if "beta%r" % beta in z.files:
                 data[beta] = tuple(z["beta%r" % beta]) + (z["self_beta%r" % beta],)
-    missing = [b for b in ("steady",) + BETAS if b not in data]
+    missing = [b for b in ("steady",) + tuple(betas) if b not in data]
     if missing:
         raise ValueError("pair data missing for %s" % missing)
     return data, n
@@ -349,28 +350,219 @@ def fit_all(data, n, xmax=16.0):
     return ah, bst, z, rows
 
 
+# ---------------------------------------------------------------- two dimensions (Appendix B)
+# The paper's 2D table is beta in {0, 0.1, 0.25, 0.5, 1, 5, 10}; the inviscid row
+# is measured at 0.01 and a row at 2 is added; above 10 the steady fit applies.
+BETAS_2D = (0.01, 0.1, 0.25, 0.5, 1.0, 2.0, 5.0, 10.0)
+CV_2D = (8.0 / 3.0) ** 2               # four-point marker area V_m / h^2
+Z0_2D = 1.0 / (2.0 * CV_2D)            # phi0(0) = eta f_0(0) / beta = h^2 / (2 V_m)
+HASIMOTO_2D = 3.708                    # f(0) = ln(l / (3.708 a)) / (4 pi eta), periodic square
+TABLE_2D = os.path.join(HERE, "csrc", "mobility_fit_4pt_2d.inc")
+
+
+def ft2_steady(x, c):
+    """-(4 pi eta)(f(r) - f(0)), coefficients a0..a4 = c[0:5]."""
+    a0, a1, a2, a3, a4 = c[:5]
+    x = np.asarray(x, dtype=np.float64)
+    lx = np.log(np.maximum(x, 1e-300))
+    return (a0 * x ** 2 + a1 * x ** 3 + a2 * x ** 3 * lx) / (1.0 + a3 * x + a4 * x ** 2 + a2 * x ** 3)
+
+
+def gt2_steady(x, c):
+    """(4 pi eta) g(r), coefficients b0..b3 = c[5:9]."""
+    b0, b1, b2, b3 = c[5:9]
+    x = np.asarray(x, dtype=np.float64)
+    return (b0 * x ** 2 + b1 * x ** 3) / (1.0 + b2 * x + b3 * x ** 2 + b1 * x ** 3)
+
+
+def phi0_2d(beta, z):
+    """eta f(0) / beta, z = (z1, z2, z3, z4)."""
+    z1, z2, z3, z4 = z
+    beta = np.asarray(beta, dtype=np.float64)
+    return (Z0_2D + z1 * beta ** 3 * np.log(beta)) / (1.0 + z2 * beta + z3 * beta ** 2 + z4 * beta ** 4)
+
+
+def ft2_beta(x, beta, c):
+    """f~ with f(r) = -(beta / (2 pi eta x^2)) f~; c = (a0, a1, a2, a3, p1, b1, b2, ...)."""
+    a0, a1, a2, a3, p1, b1, b2 = c[:7]
+    x = np.asarray(x, dtype=np.float64)
+    lx = np.log(np.maximum(x, 1e-300))
+    vis = x ** 3 * lx / (beta * (a0 + 2.0 * x)) * np.exp(-p1 * x / math.sqrt(beta))
+    return vis + (a1 * x ** 2 + a2 * x ** 3 + a3 * x ** 4) / (1.0 + b1 * x ** 2 + b2 * x ** 3 + a3 * x ** 4)
+
+
+def gt2_beta(x, beta, c):
+    """g~ with g(r) = (beta / (pi eta x^2)) g~; c[7:13] = (c0, c1, c2, c3, p2, p3)."""
+    c0, c1, c2, c3, p2, p3 = c[7:13]
+    x = np.asarray(x, dtype=np.float64)
+    vis = x ** 3 / (beta * (c0 + 4.0 * x)) * np.exp(-p2 * x / math.sqrt(beta))
+    return vis + x ** 3 / (np.exp(-p3 * x) * (c1 + c2 * x + c3 * x ** 2) + x ** 3)
+
+
+# bounds: every denominator positive at every distance; decay rates positive
+LB_2S = [-1e3, -1e3, 1e-6, 0.0, 0.0, -1e3, 1e-6, 0.0, 0.0]
+UB_2S = [1e3, 1e3, 1e3, 1e3, 1e3, 1e3, 1e3, 1e3, 1e3]
+LB_2B = [0.0, -1e3, -1e3, 1e-6, 1e-3, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 1e-3, 1e-3]
+UB_2B = [1e3, 1e3, 1e3, 1e3, 1e2, 1e3, 1e3, 1e3, 1e3, 1e3, 1e3, 1e2, 1e2]
+LB_Z2 = [-1.0, -1e3, -1e3, 0.0]
+UB_Z2 = [1.0, 1e3, 1e3, 1e3]
+
+
+def fit_steady_2d(x, par, perp, self_mean, eta, h, L):
+    """(a/h, a0..a4, b0..b3) from steady 2D pair data."""
+    from scipy.optimize import least_squares
+    ah = L / (HASIMOTO_2D * math.exp(4.0 * math.pi * eta * self_mean)) / h
+    ft = -4.0 * math.pi * eta * (perp - self_mean)
+    gt = 4.0 * math.pi * eta * (par - perp)
+    w = 1.0 / (np.abs(ft) + 0.05)
+    rf = least_squares(lambda q: (ft2_steady(x, np.r_[q, np.zeros(4)]) - ft) * w, [1.0, 1.0, 1.0, 1.0, 1.0],
+                       bounds=(LB_2S[:5], UB_2S[:5]))
+    wg = 1.0 / (np.abs(gt) + 0.05)
+    rg = least_squares(lambda q: (gt2_steady(x, np.r_[np.zeros(5), q]) - gt) * wg, [1.0, 1.0, 1.0, 1.0],
+                       bounds=(LB_2S[5:], UB_2S[5:]))
+    return ah, np.r_[rf.x, rg.x]
+
+
+def phi0_2d_positive(z, lo=1e-4, hi=1e5):
+    """Numerator and denominator of phi0_2d positive over beta in [lo, hi]."""
+    b = np.geomspace(lo, hi, 4000)
+    num = Z0_2D + z[0] * b ** 3 * np.log(b)
+    den = 1.0 + z[1] * b + z[2] * b ** 2 + z[3] * b ** 4
+    return bool(np.all(num > 0) and np.all(den > 0))
+
+
+def fit_phi0_2d(betas, phis):
+    """z1..z4 from the self mobilities; several starts, the best fit whose
+    numerator and denominator stay positive (a sign change would put a pole
+    or a negative self mobility at some beta)."""
+    from scipy.optimize import least_squares
+    betas = np.asarray(betas)
+    phis = np.asarray(phis)
+    fits = []
+    for z0 in ([0.01, 1.0, 1.0, 0.01], [0.001, 1.3, -0.3, 0.01], [0.05, 2.0, 0.0, 0.1]):
+        r = least_squares(lambda z: (phi0_2d(betas, z) - phis) / phis, np.clip(z0, LB_Z2, UB_Z2),
+                          bounds=(LB_Z2, UB_Z2))
+        if phi0_2d_positive(r.x):
+            fits.append(r)
+    if not fits:
+        raise RuntimeError("no 2D phi0 fit keeps its numerator and denominator positive")
+    return min(fits, key=lambda r: r.cost).x
+
+
+def fit_beta_2d(x, par, perp, beta, h, prev=None):
+    """The 13 coefficients of one 2D row from pair data (rho = dt = 1, the
+    box's mean mode removed)."""
+    from scipy.optimize import least_squares
+    ft = -2.0 * math.pi * x ** 2 * h ** 2 * perp
+    gt = math.pi * x ** 2 * h ** 2 * (par - perp)
+
+    def best(fun, starts, lb, ub):
+        with np.errstate(over="ignore", invalid="ignore"):
+            fits = [least_squares(fun, np.clip(p0, lb, ub), bounds=(lb, ub), max_nfev=20000) for p0 in starts]
+        return min(fits, key=lambda r: r.cost).x
+
+    sa = [np.array([1.0, 1.0, 1.0, 1.0, 1.0, 1.0, 1.0])]
+    sb = [np.array([1.0, 1.0, 1.0, 1.0, 1.0, 1.0])]
+    if prev is not None:
+        sa.append(np.asarray(prev[:7]))
+        sb.append(np.asarray(prev[7:]))
+    a = best(lambda q: (ft2_beta(x, beta, np.r_[q, np.zeros(6)]) - ft) / (np.abs(ft) + 0.05), sa, LB_2B[:7],
+             UB_2B[:7])
+    b = best(lambda q: (gt2_beta(x, beta, np.r_[np.zeros(7), q]) - gt) / (np.abs(gt) + 0.05), sb, LB_2B[7:],
+             UB_2B[7:])
+    return np.r_[a, b]
+
+
+def measure_all_2d(n=256, N=120, seed=0, betas=BETAS_2D, steady=True):
+    """2D pair data: two clouds of N markers in squares of side l/8 and l/4."""
+    h = 1.0 / n
+    L = n * h
+    clouds = [cloud(seed, N, L, h, dim=2), cloud(seed + 1, N, L, h, side=0.25, dim=2)]
+    data = {}
+    if steady:
+        print("2D steady: 2 clouds of %d markers" % N, flush=True)
+        r, par, perp, self_ = measure_clouds(clouds, n, h, 0.0, 1.0, 0.0, L)
+        data["steady"] = (r / h, par, perp, self_)
+    for beta in betas:
+        print("2D beta %g" % beta, flush=True)
+        r, par, perp, self_ = measure_clouds(clouds, n, h, 1.0, beta * h * h, 1.0, L)
+        data[beta] = (r / h, par, perp, self_)
+    return data
+
+
+def fit_all_2d(data, n, xmax=None):
+    """The 2D table from measured pair data (pairs within a quarter of the box)."""
+    h = 1.0 / n
+    L = n * h
+    xmax = xmax or n / 4.0
+    x, par, perp, self_ = data["steady"]
+    xb, pb, qb, _ = binned(x, par, perp, xmax)
+    ah, cst = fit_steady_2d(xb, pb, qb, self_.mean(), 1.0, h, L)
+    print("  2D steady: a/h %.4f  c %s" % (ah, np.array2string(cst, precision=4)), flush=True)
+    mean_mode = 1.0 / L ** 2             # dt / (rho l^2) with rho = dt = 1
+    phis = [(data[b][3].mean() - mean_mode) * h ** 2 for b in BETAS_2D]   # eta f(0) / beta
+    z = fit_phi0_2d(BETAS_2D, phis)
+    print("  2D phi0: z %s" % np.array2string(z, precision=4), flush=True)
+    rows = []
+    prev = None
+    for beta in BETAS_2D[::-1]:
+        x, par, perp, _ = data[beta]
+        xb, pb, qb, _ = binned(x, par - mean_mode, perp - mean_mode, xmax)
+        t0 = time.perf_counter()
+        c = fit_beta_2d(xb, pb, qb, beta, h, prev)
+        print("  2D beta %g fitted (%.1f s)" % (beta, time.perf_counter() - t0), flush=True)
+        rows.insert(0, (beta, c))
+        prev = c
+    return ah, cst, z, rows
+
+
+def write_table_2d(path, ah, cst, z, rows):
+    def fmt(v):
+        return ", ".join("%.17g" % x for x in v)
+    lines = ["// Fitted approximate mobility of the four-point kernel in two dimensions",
+             "// (forms of the paper's Appendix B, Sec. 4.2 fitting procedure); generated",
+             "// by paper_1505_07865_amd/mobility_fit.py from pair mobilities measured with",
+             "// this library's solver (256^2, two clouds of 120 markers):",
+             "//   python -m paper_1505_07865_amd.mobility_fit --dim 2 --measure-only --pairs P.npz   (GPU)",
+             "//   python -m paper_1505_07865_amd.mobility_fit --dim 2 --fit-only --pairs P.npz",
+             "// Do not edit.",
+             "constexpr int kFit2Rows = %d;" % len(rows),
+             "constexpr double kFit2Ah = %.17g;" % ah,
+             "constexpr double kFit2Steady[9] = {%s};" % fmt(cst),
+             "constexpr double kFit2Z[4] = {%s};" % fmt(z),
+             "constexpr double kFit2Beta[%d] = {%s};" % (len(rows), fmt([r[0] for r in rows])),
+             "constexpr double kFit2Row[%d][13] = {%s};" % (len(rows), ", ".join("{%s}" % fmt(r[1]) for r in rows))]
+    with open(path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
 def main(n=64, N=120, seed=0, out=TABLE, pairs=None, measure_only=False, fit_only=False, betas=BETAS,
-         steady=True):
+         steady=True, dim=3):
     if fit_only:
-        data, n = load_pairs(pairs)
+        data, n = load_pairs(pairs, BETAS if dim == 3 else BETAS_2D)
     else:
-        data = measure_all(n, N, seed, betas, steady)
+        data = measure_all(n, N, seed, betas, steady) if dim == 3 else measure_all_2d(n, N, seed, betas, steady)
         if pairs:
             save_pairs(pairs, data, n)
             print("wrote", pairs, flush=True)
         if measure_only:
             return
-    ah, bst, z, rows = fit_all(data, n)
-    write_table(out, ah, bst, z, rows)
+    if dim == 3:
+        ah, bst, z, rows = fit_all(data, n)
+        write_table(out, ah, bst, z, rows)
+    else:
+        ah, cst, z, rows = fit_all_2d(data, n)
+        write_table_2d(out, ah, cst, z, rows)
     print("wrote", out, flush=True)
 
 
 if __name__ == "__main__":
     import argparse
     ap = argparse.ArgumentParser()
-    ap.add_argument("--out", default=TABLE, help="table file to write")
+    ap.add_argument("--dim", type=int, default=3, choices=(2, 3))
+    ap.add_argument("--out", default=None, help="table file to write (default: the library's table)")
     ap.add_argument("--markers", type=int, default=120)
-    ap.add_argument("--n", type=int, default=64)
+    ap.add_argument("--n", type=int, default=None, help="grid (default 64 in 3D, 256 in 2D)")
     ap.add_argument("--pairs", default=None, help="pair data file (.npz) to write after measuring, or to fit")
     ap.add_argument("--measure-only", action="store_true", help="measure and write --pairs, no fit")
     ap.add_argument("--fit-only", action="store_true",
@@ -378,6 +570,8 @@ if __name__ == "__main__":
     ap.add_argument("--betas", default=None, help="measure: comma-separated subset of the table's betas")
     ap.add_argument("--no-steady", action="store_true", help="measure: skip the steady data")
     a = ap.parse_args()
-    betas = BETAS if a.betas is None else tuple(float(b) for b in a.betas.split(","))
-    main(n=a.n, N=a.markers, out=a.out, pairs=a.pairs, measure_only=a.measure_only, fit_only=a.fit_only,
-         betas=betas, steady=not a.no_steady)
+    table = BETAS if a.dim == 3 else BETAS_2D
+    betas = table if a.betas is None else tuple(float(b) for b in a.betas.split(","))
+    main(n=a.n or (64 if a.dim == 3 else 256), N=a.markers, out=a.out or (TABLE if a.dim == 3 else TABLE_2D),
+         pairs=a.pairs, measure_only=a.measure_only, fit_only=a.fit_only, betas=betas, steady=not a.no_steady,
+         dim=a.dim)

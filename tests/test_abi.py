@@ -75,7 +75,7 @@ def test_invalid_params_rejected_before_device_work(lib):
     from paper_1505_07865_amd import ibr
     for bad in (dict(dim=4), dict(n=48), dict(h=0.0), dict(eta=-1.0), dict(rho=1.0, dt=0.0), dict(n_s=0),
                 dict(rtol=0.0), dict(precision=7), dict(walls=3), dict(walls=-1), dict(advection=2), dict(advection=-1),
-                dict(mobility=3), dict(mobility=-1), dict(dim=2, n=32, h=1.0 / 32, mobility=1)):
+                dict(mobility=3), dict(mobility=-1)):
         p = ibr.default_params(**bad)
         ctx = ctypes.c_void_p()
         assert lib.ibr_create(ctypes.byref(p), ctypes.byref(ctx)) == 1, bad

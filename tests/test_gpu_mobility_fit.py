@@ -179,3 +179,142 @@ def test_fitted_preconditioner_solves_to_oracle(unsteady):
         print("%s: %d iterations, err v %.2e F %.2e" % (name, info["iters"], err, errF), flush=True)
         assert info["rel_residual"] <= 1e-10
         assert err < 1e-8 and errF < 1e-8
+
+
+# ---------------------------------------------------------------- two dimensions (Appendix B)
+def _table2():
+    from paper_1505_07865_amd import mobility_fit as mf
+    text = open(mf.TABLE_2D).read()
+    rows = int(re.search(r"kFit2Rows = (\d+);", text).group(1))
+    if rows == 0:
+        pytest.skip("no 2D fitted table compiled in")
+
+    def arr(pattern):
+        body = re.search(pattern + r"\s*=\s*\{(.*?)\};", text, re.S).group(1)
+        return np.array([float(v) for v in re.findall(r"[-+]?(?:\d+\.?\d*|\.\d+)(?:[eE][-+]?\d+)?", body)])
+
+    return dict(rows=rows, ah=float(re.search(r"kFit2Ah = ([^;]+);", text).group(1)),
+                steady=arr(r"kFit2Steady\[9\]"), z=arr(r"kFit2Z\[4\]"), beta=arr(r"kFit2Beta\[\d+\]"),
+                R=arr(r"kFit2Row\[\d+\]\[13\]").reshape(rows, 13))
+
+
+def _fitted_fg2(r, h, eta, L, beta, T, dt_rho=1.0):
+    """f(r), g(r) of the 2D forms in a periodic square; beta = None for steady
+    Stokes; an unsteady box adds its mean mode dt / (rho L^2)."""
+    from paper_1505_07865_amd import mobility_fit as mf
+    mean = 0.0 if beta is None else dt_rho / L ** 2
+    x = r / h
+    if beta is None or beta > T["beta"][-1]:
+        f0 = math.log(L / (3.708 * T["ah"] * h)) / (4.0 * math.pi * eta)
+        if r == 0.0:
+            return f0 + mean, 0.0
+        c = 4.0 * math.pi * eta
+        return f0 - float(mf.ft2_steady(x, T["steady"])) / c + mean, float(mf.gt2_steady(x, T["steady"])) / c
+    ph = float(mf.phi0_2d(beta, T["z"]))
+    if r == 0.0:
+        return ph * beta / eta + mean, 0.0
+    bs = T["beta"]
+    i = 0
+    while i + 1 < len(bs) and bs[i + 1] < beta:
+        i += 1
+    rows = [(i, 1.0)]
+    if beta > bs[i] and i + 1 < len(bs):
+        t = math.log(beta / bs[i]) / math.log(bs[i + 1] / bs[i])
+        rows = [(i, 1.0 - t), (i + 1, t)]
+    ft = sum(w * float(mf.ft2_beta(x, beta, T["R"][k])) for k, w in rows)
+    gt = sum(w * float(mf.gt2_beta(x, beta, T["R"][k])) for k, w in rows)
+    be = beta / eta
+    return -be * ft / (2.0 * math.pi * x ** 2) + mean, be * gt / (math.pi * x ** 2)
+
+
+def _fitted_block2(R, h, eta, L, beta, T):
+    N = len(R)
+    M = np.zeros((2 * N, 2 * N))
+    for i in range(N):
+        for j in range(N):
+            d = R[i] - R[j]
+            d -= L * np.round(d / L)
+            r = float(np.linalg.norm(d))
+            f, g = _fitted_fg2(r, h, eta, L, beta, T)
+            e = d / r if r > 0 else np.zeros(2)
+            M[2 * i:2 * i + 2, 2 * j:2 * j + 2] = f * np.eye(2) + g * np.outer(e, e)
+    return M
+
+
+def _library_block2(R, n, rho, eta, dt, mobility):
+    from paper_1505_07865_amd import ibr
+    s = ibr.Solver(dim=2, n=n, h=1.0 / n, rho=rho, eta=eta, dt=dt, mobility=mobility)
+    s.set_bodies(R, np.array([0, len(R)]), R.mean(axis=0)[None, :])
+    M, _ = s.mobility_block(0)
+    s.close()
+    return M
+
+
+CASES2 = [(None, "steady"), (0.3, "beta0.3"), (3.0, "beta3"), (0.003, "beta0.003"), (50.0, "beta50")]
+
+
+@pytest.mark.parametrize("beta,label", CASES2, ids=[c[1] for c in CASES2])
+def test_fitted_block_2d_equals_the_forms(beta, label):
+    from paper_1505_07865_amd import ibr
+    from paper_1505_07865_amd import mobility_fit as mf
+    T = _table2()
+    n, N = 128, 40
+    h = 1.0 / n
+    R = mf.cloud(1, N, 1.0, h, dim=2)
+    if beta is None:
+        rho, eta, dt = 0.0, 1.0, 0.0
+    else:
+        rho, dt = 1.0, 1.0
+        eta = beta * h * h
+    print("2D fitted block, %s" % label, flush=True)
+    M = _library_block2(R, n, rho, eta, dt, ibr.MOB_FITTED)
+    ref = _fitted_block2(R, h, eta, 1.0, beta, T)
+    assert np.abs(M - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("beta", [None, 0.3, 3.0], ids=["steady", "beta0.3", "beta3"])
+def test_fitted_block_2d_closer_to_exact_mobility(beta):
+    from paper_1505_07865_amd import ibr
+    from paper_1505_07865_amd import mobility_fit as mf
+    _table2()
+    n, N = 256, 60
+    h = 1.0 / n
+    R = mf.cloud(7, N, 1.0, h, dim=2)
+    if beta is None:
+        rho, eta, dt, c0 = 0.0, 1.0, 0.0, 0.0
+    else:
+        rho, dt = 1.0, 1.0
+        eta = beta * h * h
+        c0 = rho / dt
+    M = constrained.System(2, n, h, c0, eta, R).mobility_dense()
+    M = 0.5 * (M + M.T)
+    out = {}
+    for name, mob in (("fitted", ibr.MOB_FITTED), ("analytic", ibr.MOB_ANALYTIC)):
+        Mt = _library_block2(R, n, rho, eta, dt, mob)
+        err = np.linalg.norm(Mt - M) / np.linalg.norm(M)
+        w = np.linalg.eigvals(np.linalg.solve(Mt, M))
+        cond = np.abs(w).max() / np.abs(w).min()
+        out[name] = (err, cond)
+        print("2D %s beta %s: rel F-norm error %.3e, cond(M~^-1 M) %.3g" % (name, beta, err, cond), flush=True)
+    assert out["fitted"][0] < out["analytic"][0]
+
+
+@pytest.mark.parametrize("unsteady", [False, True], ids=["steady", "unsteady"])
+def test_fitted_preconditioner_2d_solves_to_oracle(unsteady):
+    from paper_1505_07865_amd import ibr
+    _table2()
+    if unsteady:
+        prob = small_problem(3, 2, 64, nbodies=3, radius_h=4.0, rho=1.0, eta=0.02, dt=0.5 / 64)
+    else:
+        prob = small_problem(3, 2, 64, nbodies=3, radius_h=4.0)
+    ex = constrained.solve_problem(prob)
+    for name, mob in (("fitted", ibr.MOB_FITTED), ("analytic", ibr.MOB_ANALYTIC)):
+        s = ibr.from_problem(prob, rtol=1e-10, mobility=mob)
+        info = s.solve()
+        sol = s.solution()
+        s.close()
+        err = np.linalg.norm(sol.u - ex.v) / np.linalg.norm(ex.v)
+        errF = np.linalg.norm(sol.F - ex.F) / np.linalg.norm(ex.F)
+        print("2D %s: %d iterations, err v %.2e F %.2e" % (name, info["iters"], err, errF), flush=True)
+        assert info["rel_residual"] <= 1e-10
+        assert err < 1e-8 and errF < 1e-8

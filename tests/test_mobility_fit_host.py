@@ -108,3 +108,55 @@ def test_compiled_table_is_well_formed():
         ph = float(mf.phi0(beta, z, ah))
         with np.errstate(over="ignore"):
             assert np.all(np.isfinite(mf.ft_beta(xs, beta, ph, A[k]))) and np.all(np.isfinite(mf.gt_beta(xs, beta, ph, B[k])))
+
+
+def test_2d_fits_recover_forms():
+    """Appendix B's forms: the 2D fits recover known coefficients, and
+    phi0_2d starts at the inviscid value h^2 / (2 V_m)."""
+    c_true = np.array([0.5, 0.3, 0.8, 0.6, 0.9, 0.2, 0.7, 0.4, 0.3])
+    x = np.geomspace(1.0, 60.0, 200)
+    f = mf.ft2_steady(x, c_true)
+    g = mf.gt2_steady(x, c_true)
+    eta, h, L, self_mean = 1.0, 1.0 / 256, 1.0, 0.3
+    perp = self_mean - f / (4.0 * math.pi * eta)
+    par = perp + g / (4.0 * math.pi * eta)
+    ah, c = mf.fit_steady_2d(x, par, perp, self_mean, eta, h, L)
+    assert abs(ah - L / (3.708 * math.exp(4.0 * math.pi * eta * self_mean)) / h) < 1e-12
+    assert np.allclose(mf.ft2_steady(x, c), f, atol=1e-9) and np.allclose(mf.gt2_steady(x, c), g, atol=1e-9)
+    beta = 0.5
+    ct = np.array([1.0, 0.5, 0.7, 0.9, 1.2, 0.4, 0.3, 0.8, 0.5, 0.6, 0.2, 1.1, 0.9])
+    ft = mf.ft2_beta(x, beta, ct)
+    gt = mf.gt2_beta(x, beta, ct)
+    perp = -ft / (2.0 * math.pi * x ** 2 * h ** 2)
+    par = perp + gt / (math.pi * x ** 2 * h ** 2)
+    cc = mf.fit_beta_2d(x, par, perp, beta, h)
+    assert np.abs(mf.ft2_beta(x, beta, cc) - ft).max() < 1e-6 * np.abs(ft).max()
+    assert np.abs(mf.gt2_beta(x, beta, cc) - gt).max() < 1e-6 * np.abs(gt).max()
+    assert abs(mf.phi0_2d(1e-12, [0.1, 1.0, 1.0, 1.0]) - 1.0 / (2.0 * (8.0 / 3.0) ** 2)) < 1e-12
+
+
+def test_compiled_2d_table_is_well_formed():
+    text = open(mf.TABLE_2D).read()
+    rows = int(re.search(r"kFit2Rows = (\d+);", text).group(1))
+    if rows == 0:
+        pytest.skip("no 2D fitted table generated")
+
+    def arr(pattern):
+        body = re.search(pattern + r"\s*=\s*\{(.*?)\};", text, re.S).group(1)
+        return np.array([float(v) for v in re.findall(r"[-+]?(?:\d+\.?\d*|\.\d+)(?:[eE][-+]?\d+)?", body)])
+
+    betas = arr(r"kFit2Beta\[\d+\]")
+    assert len(betas) == rows and np.all(np.diff(betas) > 0)
+    ah = float(re.search(r"kFit2Ah = ([^;]+);", text).group(1))
+    assert 0.9 < ah < 1.2                      # the four-point marker radius in 2D, about 1.04 h
+    z = arr(r"kFit2Z\[4\]")
+    assert mf.phi0_2d_positive(z)
+    st = arr(r"kFit2Steady\[9\]")
+    assert np.all(st >= np.array(mf.LB_2S) - 1e-12) and np.all(st <= np.array(mf.UB_2S) + 1e-12)
+    R = arr(r"kFit2Row\[\d+\]\[13\]").reshape(rows, 13)
+    assert np.all(R >= np.array(mf.LB_2B) - 1e-12) and np.all(R <= np.array(mf.UB_2B) + 1e-12)
+    xs = np.linspace(0.1, 200.0, 2000)
+    assert np.all(np.isfinite(mf.ft2_steady(xs, st))) and np.all(np.isfinite(mf.gt2_steady(xs, st)))
+    for k, beta in enumerate(betas):
+        with np.errstate(over="ignore"):
+            assert np.all(np.isfinite(mf.ft2_beta(xs, beta, R[k]))) and np.all(np.isfinite(mf.gt2_beta(xs, beta, R[k])))
