@@ -660,3 +660,135 @@ def run(prob, nsteps, walls=None, scheme="centred", **kw):
         N_prev = N_n
         v = sol.v
     return out
+
+
+# ---------------------------------------------------------------- moving walls
+# Walls with a prescribed velocity (inhomogeneous Dirichlet data; Sec. 7.3's
+# box moves with the cavity, the appendix on physical boundaries gives the
+# mirror rule).  wall_vel[beta] = (U_lo, U_hi): the velocity vectors of the
+# walls at coordinate 0 and at l along walled axis beta.  Along beta a
+# component tangential to the wall has ghost values 2 U - v (the mirror
+# image about the wall value); the normal component's wall faces hold
+# U . e_beta, and its ghost faces are 2 U - v as well.  Written here on an
+# explicitly padded lattice (two ghost layers per side along every axis,
+# periodic axes wrapped), independently of the folded taps above.
+PAD = 2
+
+
+def padded(v, walls, wall_vel):
+    """Velocity components on the padded lattice: v [d, n..] (the normal
+    components' wall faces ignored).  Returns [d] arrays of shape (n+2 PAD,)*d,
+    index j + PAD for lattice index j (face n, the high wall, included)."""
+    d, n = v.shape[0], v.shape[-1]
+    out = []
+    for a in range(d):
+        x = np.asarray(v[a], dtype=np.float64)
+        for ax in range(d):
+            beta = d - 1 - ax
+            x = np.moveaxis(x, ax, 0)
+            if not walls[beta]:
+                y = np.concatenate([x[-PAD:], x, x[:PAD]], axis=0)
+            else:
+                lo, hi = (np.asarray(wall_vel[beta][0])[a], np.asarray(wall_vel[beta][1])[a]) \
+                    if wall_vel is not None and wall_vel.get(beta) is not None else (0.0, 0.0)
+                y = np.zeros((n + 2 * PAD,) + x.shape[1:])
+                y[PAD:PAD + n] = x
+                if beta == a:
+                    # faces: 0 and n on the walls, ghosts mirror about the wall values
+                    y[PAD] = lo
+                    y[PAD + n] = hi
+                    for m in range(1, PAD + 1):
+                        y[PAD - m] = 2.0 * lo - y[PAD + m]
+                    for m in range(1, PAD):
+                        y[PAD + n + m] = 2.0 * hi - y[PAD + n - m]
+                else:
+                    for m in range(PAD):
+                        y[PAD - 1 - m] = 2.0 * lo - x[m]
+                        y[PAD + n + m] = 2.0 * hi - x[n - 1 - m]
+            x = np.moveaxis(y, 0, ax)
+        out.append(x)
+    return out
+
+
+def stokes_apply_padded(v, p, c0, eta, h, walls, wall_vel):
+    """[[A, G], [-D, 0]] (v, pi) evaluated on the padded lattice with the
+    walls' data; rows of the normal components' wall faces are 0."""
+    d, n = v.shape[0], v.shape[-1]
+    V = padded(v, walls, wall_vel)
+    inner = tuple([slice(PAD, PAD + n)] * d)
+    mv = np.zeros_like(np.asarray(v, dtype=np.float64))
+    div = np.zeros((n,) * d)
+    for a in range(d):
+        x = V[a]
+        lap = np.zeros((n,) * d)
+        c = x[inner]
+        for ax in range(d):
+            up = [slice(PAD, PAD + n)] * d
+            dn = [slice(PAD, PAD + n)] * d
+            up[ax] = slice(PAD + 1, PAD + n + 1)
+            dn[ax] = slice(PAD - 1, PAD + n - 1)
+            lap += (x[tuple(up)] - c) + (x[tuple(dn)] - c)
+        ax = d - 1 - a
+        up = [slice(PAD, PAD + n)] * d
+        up[ax] = slice(PAD + 1, PAD + n + 1)
+        div += (x[tuple(up)] - c) / h
+        mv[a] = c0 * c - eta / (h * h) * lap
+    mv = mv + grad(p, h, walls)
+    for a in range(d):
+        mv[a][wall_mask(n, d, walls, a)] = 0.0
+    return mv, -div
+
+
+def interp_padded(v, R, h, walls, wall_vel):
+    """J v with the walls' data: the standard kernel taps on the padded
+    lattice (no folding)."""
+    d, n = v.shape[0], v.shape[-1]
+    V = padded(v, walls, wall_vel)
+    N = R.shape[0]
+    out = np.zeros((N, d))
+    for a in range(d):
+        for m in range(N):
+            taps = []
+            for beta in range(d):
+                s = R[m, beta] / h - (0.0 if beta == a else 0.5)
+                base = int(np.floor(s)) - 1
+                js = base + np.arange(4)
+                ws = kernel.phi(s - js)
+                if not walls[beta]:
+                    js = np.mod(js, n)
+                taps.append((js + PAD, ws))
+            acc = 0.0
+            for combo in itertools.product(range(4), repeat=d):
+                idx = tuple(taps[d - 1 - ax][0][combo[d - 1 - ax]] for ax in range(d))
+                w = 1.0
+                for beta in range(d):
+                    w *= taps[beta][1][combo[beta]]
+                acc += w * V[a][idx]
+            out[m, a] = acc
+    return out
+
+
+def solve_problem_moving(prob, wall_vel, walls=None, g=None, hp=None, **kw):
+    """Exact solution with moving walls: the walls' data enter as the affine
+    parts of the stencils and of J on the padded lattice (the homogeneous
+    operator applied to zero interior values), moved to the right-hand side;
+    the homogeneous constrained system is solved as in ``solve_problem``; the
+    normal components' wall faces then take the wall values."""
+    d, n, h = prob.dim, prob.n, prob.h
+    walls = all_walls(d) if walls is None else normalise(walls, d)
+    c0 = 0.0 if prob.steady else prob.rho / prob.dt
+    zero = np.zeros((d,) + (n,) * d)
+    am, ac = stokes_apply_padded(zero, np.zeros((n,) * d), c0, prob.eta, h, walls, wall_vel)
+    ja = interp_padded(zero, prob.R, h, walls, wall_vel)
+    g = (np.zeros((d,) + (n,) * d) if g is None else np.asarray(g, dtype=np.float64)) - am
+    hp = (np.zeros((n,) * d) if hp is None else np.asarray(hp, dtype=np.float64)) - ac
+    sysm = System(d, n, h, c0, prob.eta, prob.R, walls)
+    V = ib.marker_velocities(prob.R, prob.offsets, prob.centres, prob.U, prob.Omega, prob.L)
+    sol = constrained.solve(sysm, g, hp, -V + ja, prob.offsets, prob.centres, **kw)
+    for beta in range(d):
+        if walls[beta]:
+            sl = [slice(None)] * d
+            sl[d - 1 - beta] = 0
+            lo = 0.0 if wall_vel is None or wall_vel.get(beta) is None else float(np.asarray(wall_vel[beta][0])[beta])
+            sol.v[beta][tuple(sl)] = lo
+    return sol

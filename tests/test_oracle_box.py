@@ -265,3 +265,83 @@ def test_box_steps_reproduce_the_slit():
     for sa, sb in zip(a, b):
         assert np.abs(sa.v - sb.v).max() < 1e-10 * np.abs(sb.v).max()
         assert np.abs(sa.F - sb.F).max() < 1e-10 * np.abs(sb.F).max()
+
+
+# ---------------------------------------------------------------- moving walls
+@pytest.mark.parametrize("d,wl", [(2, (True, True)), (3, (True, True, True)), (3, (False, False, True))])
+def test_padded_lattice_matches_the_folded_operators(d, wl):
+    """With the walls at rest the padded-lattice stencils and interpolation
+    (written separately) equal the folded ones."""
+    rng = np.random.default_rng(11)
+    n = 8
+    h = 1.0 / n
+    v, p = _fields(rng, d, n, wl)
+    mv, mc = box.stokes_apply(v, p, 2.0, 0.7, h, wl)
+    pv, pc = box.stokes_apply_padded(v, p, 2.0, 0.7, h, wl, None)
+    assert np.abs(pv - mv).max() < 1e-11 * np.abs(mv).max() and np.abs(pc - mc).max() < 1e-11 * np.abs(mc).max()
+    R = rng.uniform(0.02, 0.98, (9, d))
+    sysm = box.System(d, n, h, 0.0, 1.0, R, wl)
+    assert np.abs(box.interp_padded(v, R, h, wl, None) - sysm.interp(v)).max() < 1e-13 * np.abs(v).max()
+
+
+def _rigid_problem(d, n, R, U, rho=0.0, eta=1.0, dt=0.0):
+    from synthetic.workloads import _assemble
+    c = R.mean(axis=0)
+    return _assemble(d, n, 1.0 / n, rho, eta, dt, [R], c[None, :], np.asarray(U, dtype=np.float64)[None, :],
+                     np.zeros((1, 3 if d == 3 else 1)), [0.1], 0, "moving_walls")
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_box_moving_with_a_body_carries_the_fluid(d):
+    """Every wall and the body moving with the same U: the fluid moves with U
+    everywhere, with no force on the body (steady and unsteady)."""
+    from synthetic import fibonacci_sphere, disk_ring
+    n = 8 if d == 3 else 16
+    h = 1.0 / n
+    U = np.array([0.7, -0.4, 0.3][:d])
+    R = fibonacci_sphere(20, 2.0 * h, np.full(3, 0.5)) if d == 3 else disk_ring(12, 3.0 * h, np.full(2, 0.5))
+    wv = {beta: (U, U) for beta in range(d)}
+    for rho, dt in ((0.0, 0.0), (1.0, 0.05)):
+        prob = _rigid_problem(d, n, R, U, rho=rho, dt=dt)
+        # the uniform flow's own inertia term (rho / dt) U is the right-hand side
+        g = None if rho == 0.0 else np.stack([np.full((n,) * d, (rho / dt) * U[a]) for a in range(d)])
+        sol = box.solve_problem_moving(prob, wv, g=g)
+        for a in range(d):
+            assert np.abs(sol.v[a] - U[a]).max() < 1e-10
+        assert np.abs(sol.lam).max() < 1e-8
+
+
+def test_slit_couette_is_linear():
+    """Slit channel (walls on y, 2D), the bottom wall at rest and the top one
+    sliding with U: the discrete flow is the linear profile exactly; a marker
+    moving with the local fluid velocity feels no force."""
+    n = 16
+    h = 1.0 / n
+    U = 0.8
+    wl = (False, True)
+    wv = {1: (np.zeros(2), np.array([U, 0.0]))}
+    c = np.array([0.5, 0.375])
+    # one marker (a rigid body of several would not follow the shear)
+    prob = _rigid_problem(2, n, c[None, :], [U * c[1], 0.0])
+    sol = box.solve_problem_moving(prob, wv, walls=wl)
+    y = (np.arange(n) + 0.5) * h
+    assert np.abs(sol.v[0] - (U * y)[:, None]).max() < 1e-12
+    assert np.abs(sol.v[1]).max() < 1e-12 and np.abs(sol.lam).max() < 1e-9
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_moving_walls_equal_the_shifted_frame(d):
+    """The box's walls moving with U around a body at rest equal, shifted by
+    U, the box at rest around the body moving with -U (steady Stokes)."""
+    from synthetic import box_problem
+    prob = box_problem(4, dim=d, n=8 if d == 3 else 16, nbodies=1, radius_h=2.0 if d == 3 else 3.0,
+                       wall_gap_h=1.0, rotate=False)
+    U = np.array([0.6, -0.3, 0.2][:d])
+    lab = _rigid_problem(d, prob.n, prob.R, np.zeros(d))
+    wv = {beta: (U, U) for beta in range(d)}
+    sl = box.solve_problem_moving(lab, wv)
+    cav = _rigid_problem(d, prob.n, prob.R, -U)
+    sc = box.solve_problem(cav)
+    for a in range(d):
+        assert np.abs(sl.v[a] - (sc.v[a] + U[a])).max() < 1e-10 * np.abs(U).max()
+    assert np.abs(sl.lam - sc.lam).max() < 1e-9 * np.abs(sc.lam).max()
