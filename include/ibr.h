@@ -184,6 +184,24 @@ ibr_status ibr_set_bodies(ibr_ctx* ctx, int nbodies, const int* offsets, const d
 /* Prescribed rigid velocities U[nb][dim] and Omega[nb][3 or 1] (Sec. 2). */
 ibr_status ibr_set_velocities(ibr_ctx* ctx, const double* U, const double* Omega);
 
+/* Walls moving with a prescribed velocity (inhomogeneous Dirichlet data of
+ * the appendix on physical boundary conditions; Sec. 7.3's box moves with the
+ * cavity).  lo[dim], hi[dim]: the velocities of the walls at coordinate 0 and
+ * n h of the last axis.  Slit channel (IBR_WALLS_NOSLIP): the walls slide in
+ * their planes, lo[dim-1] = hi[dim-1] = 0 (Couette flow between them).  Box
+ * (IBR_WALLS_BOX): every wall moves with one velocity, lo == hi (a box
+ * translating with the fluid it holds).  The library solves for u - u_b,
+ * u_b the flow those walls carry without bodies (linear along the last axis,
+ * an exact solution of the discrete homogeneous equations: its Laplacian
+ * and divergence vanish and it meets the mirror rules), with the markers'
+ * prescribed velocities reduced by u_b there and, with inertia, the
+ * momentum right-hand side by (rho/dt) u_b; ibr_get_solution(_dev) returns
+ * u itself, the normal components' wall faces holding the wall velocity.
+ * NULL lo and hi put the walls back at rest.  IBR_EINVAL for a periodic box,
+ * for data outside these two cases, and later from ibr_solve with free bodies
+ * and from ibr_step (advection is not linear in u). */
+ibr_status ibr_set_wall_velocity(ibr_ctx* ctx, const double* lo, const double* hi);
+
 /* Fluid right-hand sides g[dim][n^dim] and h[n^dim] of eq. constrained_Stokes
  * (NULL = zero).  For steady periodic problems the mean of g is removed (the
  * paper's consistency assumption <g> = 0, Sec. 3.4). */

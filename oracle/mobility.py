@@ -131,7 +131,7 @@ def block(Rb, p):
     return M.transpose(0, 2, 1, 3).reshape(Np * d, Np * d)
 
 
-SHIFTS = (0.0, 0.02, 0.05, 0.1, 0.15, 0.2, 0.3, 0.4, 0.5, 0.7, 1.0, 1.5, 2.0, 3.0, 5.0, 10.0)
+SHIFTS = (0.0, 0.02, 0.05, 0.1, 0.15, 0.2, 0.3, 0.4, 0.5, 0.7, 1.0, 1.5, 2.0, 3.0, 5.0, 10.0, 20.0, 50.0)
 PIVOT_TOL = 1e-8
 
 

@@ -79,6 +79,16 @@ void launch_combine_from_split(int dim, int logn, const TZ* Z, int64_t ld, int k
                                bool assign, hipStream_t s);
 // walls: bit a = no-slip walls at both ends of axis a (0: periodic box)
 void launch_zero_wall_faces(int dim, int logn, double* v, int walls, hipStream_t s);
+// Moving walls: the velocities of the walls at the low and high end of the
+// walled axis; their background flow is linear along that axis.
+struct WallVel {
+  double lo[3], hi[3];
+};
+// skip: wall mask whose wall faces are left untouched (0: every face)
+void launch_add_background(int dim, int logn, double* v, double h, double len, int axis, WallVel wv, double scale,
+                           int skip, hipStream_t s);
+void launch_sub_background_markers(double* Vm, const double* R, int N, int dim, int axis, double len, WallVel wv,
+                                   hipStream_t s);
 void launch_advect(int dim, int logn, const double* v, double* N, double inv_2h, hipStream_t s, int walls = 0);
 void launch_advect_sl(int dim, int logn, const double* v, double* N, double dtoh, double inv_dt, hipStream_t s,
                       int walls = 0);

@@ -588,6 +588,37 @@ __global__ void __launch_bounds__(256) k_zero_wall_faces(double* __restrict__ v,
     if (((walls >> a) & 1) && co[a] == 0) v[a * C + c] = 0.0;
 }
 
+// v += scale u_b, u_b the background flow of moving walls: component a is
+// lo[a] + (hi[a] - lo[a]) z / l along the walled axis `axis` (z of the
+// a-face: k h on the faces normal to that axis, (k + 1/2) h otherwise).
+// Faces on the walls of the axes in `skip` keep their value: there the
+// momentum rows are identities whose right-hand side must stay zero.
+template <int DIM>
+__global__ void __launch_bounds__(256) k_add_background(double* __restrict__ v, int logn, double h, double len,
+                                                        int axis, WallVel wv, double scale, int skip) {
+  const int64_t C = (int64_t)1 << (DIM * logn);
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= C) return;
+  const int mask = (1 << logn) - 1;
+  const int co[3] = {(int)(c & mask), (int)((c >> logn) & mask), DIM == 3 ? (int)(c >> (2 * logn)) : 0};
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) {
+    if (((skip >> a) & 1) && co[a] == 0) continue;
+    const double z = (co[axis] + (a == axis ? 0.0 : 0.5)) * h;
+    v[a * C + c] += scale * (wv.lo[a] + (wv.hi[a] - wv.lo[a]) * z / len);
+  }
+}
+
+// Vm[m] -= u_b(R_m): the background flow at the markers (the kernel
+// interpolates linear fields exactly, mirror ghosts included).
+__global__ void k_sub_background_markers(double* __restrict__ Vm, const double* __restrict__ R, int N, int dim,
+                                         int axis, double len, WallVel wv) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= N) return;
+  const double z = R[(int64_t)m * dim + axis];
+  for (int a = 0; a < dim; ++a) Vm[(int64_t)m * dim + a] -= wv.lo[a] + (wv.hi[a] - wv.lo[a]) * z / len;
+}
+
 // g = (rho/dt) v - rho (w1 N1 + w0 N0)   (N0 may be null)
 __global__ void k_ns_rhs(const double* __restrict__ v, const double* __restrict__ N1,
                          const double* __restrict__ N0, double* __restrict__ g, int64_t len, double rdt,
@@ -720,6 +751,21 @@ template void launch_combine_from_split<double, double>(int, int, const double*,
                                                         double*, int, bool, hipStream_t);
 template void launch_combine_from_split<float, float>(int, int, const float*, int64_t, int, const double*, float*,
                                                       int, bool, hipStream_t);
+
+void launch_add_background(int dim, int logn, double* v, double h, double len, int axis, WallVel wv, double scale,
+                           int skip, hipStream_t s) {
+  const int64_t C = (int64_t)1 << (dim * logn);
+  if (dim == 3)
+    hipLaunchKernelGGL(k_add_background<3>, dim3(nblk(C)), dim3(256), 0, s, v, logn, h, len, axis, wv, scale, skip);
+  else
+    hipLaunchKernelGGL(k_add_background<2>, dim3(nblk(C)), dim3(256), 0, s, v, logn, h, len, axis, wv, scale, skip);
+}
+
+void launch_sub_background_markers(double* Vm, const double* R, int N, int dim, int axis, double len, WallVel wv,
+                                   hipStream_t s) {
+  if (N > 0)
+    hipLaunchKernelGGL(k_sub_background_markers, dim3(nblk(N)), dim3(256), 0, s, Vm, R, N, dim, axis, len, wv);
+}
 
 void launch_zero_wall_faces(int dim, int logn, double* v, int walls, hipStream_t s) {
   const int64_t C = (int64_t)1 << (dim * logn);

@@ -38,7 +38,8 @@ constexpr double kA3D = 1.25;      // four-point marker hydrodynamic radius, uni
 constexpr double kA2D = 1.04;      // four-point marker radius in the 2D periodic self-mobility
 constexpr double kPeriodic3D = 2.84;
 constexpr double kPivotTol = 1e-8;
-constexpr double kShifts[] = {0.0, 0.02, 0.05, 0.1, 0.15, 0.2, 0.3, 0.4, 0.5, 0.7, 1.0, 1.5, 2.0, 3.0, 5.0, 10.0};
+constexpr double kShifts[] = {0.0, 0.02, 0.05, 0.1, 0.15, 0.2, 0.3, 0.4, 0.5,
+                               0.7, 1.0, 1.5, 2.0, 3.0, 5.0, 10.0, 20.0, 50.0};
 constexpr int kNumShifts = sizeof(kShifts) / sizeof(kShifts[0]);
 constexpr int kMaxBlockRows = 8192;
 
@@ -122,6 +123,10 @@ struct ibr_ctx {
   // free kinematics: bodies moving under applied loads (body block after Lambda)
   std::vector<int> free_h;
   int nfree = 0;
+  // moving walls: the background flow u_b (linear along the last axis) of
+  // ibr_set_wall_velocity; the solver's state holds u - u_b
+  bool wallvel = false;
+  WallVel wvel{};
   int64_t nq = 0;  // length of the body block: nb (dim + rotations) once some body is free, else 0
   int* free_d = nullptr;
   int64_t* yoff_d = nullptr;
@@ -684,8 +689,9 @@ void factor_blocks(ibr_ctx* c) {
 }
 
 void build_rhs_markers(ibr_ctx* c) {
-  // W = -V in the constraint block of b
+  // W = -V in the constraint block of b (with moving walls -(V - u_b))
   launch_marker_velocity(c->dim, c->N, c->R, c->body_d, c->X, c->U, c->Om, c->L, c->Vm, c->stream);
+  if (c->wallvel) launch_sub_background_markers(c->Vm, c->R, c->N, c->dim, c->dim - 1, c->L, c->wvel, c->stream);
   launch_copy<double, double>(c->Vm, c->Bs + c->NF, (int64_t)c->N * c->dim, c->stream);
   launch_axpby(c->Vm, c->Bs + c->NF, (int64_t)c->N * c->dim, -1.0, 0.0, c->stream);
   if (c->nq) {
@@ -1275,7 +1281,12 @@ void get_solution_impl(ibr_ctx* c, double* u, double* pr, double* lambda, double
   double* pdev = c->Xs + (int64_t)d * c->C;
   launch_field_means<double>(pdev, 1, c->C, c->mpart, 256, c->vmean, s);
   launch_sub_field_mean<double>(pdev, 1, c->C, c->vmean, s);
-  if (u) IBR_HIP(hipMemcpyAsync(u, c->Xs, (size_t)d * c->C * sizeof(double), kind, s));
+  if (u) {
+    IBR_HIP(hipMemcpyAsync(u, c->Xs, (size_t)d * c->C * sizeof(double), kind, s));
+    // the state holds u - u_b: add the walls' background flow to the copy
+    if (c->wallvel && kind == hipMemcpyDeviceToDevice)
+      launch_add_background(d, c->logn, u, c->h, c->L, d - 1, c->wvel, 1.0, 0, s);
+  }
   if (pr) IBR_HIP(hipMemcpyAsync(pr, pdev, (size_t)c->C * sizeof(double), kind, s));
   if (lambda) IBR_HIP(hipMemcpyAsync(lambda, c->Xs + c->NF, (size_t)c->N * d * sizeof(double), kind, s));
   if (F || T) {
@@ -1285,6 +1296,18 @@ void get_solution_impl(ibr_ctx* c, double* u, double* pr, double* lambda, double
     if (T) IBR_HIP(hipMemcpyAsync(T, c->T1 + c->nb * 3, (size_t)c->nb * nt * sizeof(double), kind, s));
   }
   sync(c);
+  if (u && c->wallvel && kind == hipMemcpyDeviceToHost) {
+    // host copy: the same background flow, added on the host
+    const int n = c->n;
+    const int64_t C = c->C;
+    for (int a = 0; a < d; ++a)
+      for (int64_t i = 0; i < C; ++i) {
+        const int k = (int)(i >> ((d - 1) * c->logn));  // coordinate along the last axis
+        const double z = (k + (a == d - 1 ? 0.0 : 0.5)) * c->h;
+        u[a * C + i] += c->wvel.lo[a] + (c->wvel.hi[a] - c->wvel.lo[a]) * z / c->L;
+      }
+    (void)n;
+  }
 }
 
 }  // namespace
@@ -1310,9 +1333,19 @@ ibr_status ibr_solve(ibr_ctx* c, int warm_start, ibr_info* info) {
   ibr_status st = IBR_OK;
   ibr_status g = guard(c, [&] {
     require_bodies(c);
+    if (c->wallvel && c->nfree) throw Status(IBR_EINVAL, "moving walls and free bodies together are not supported");
     IBR_HIP(hipSetDevice(c->p.device));
     if (!warm_start || !c->have_solution) launch_fill<double>(c->Xs, c->NV, 0.0, c->stream);
+    // with inertia the walls' background flow takes (rho/dt) u_b from the
+    // momentum right-hand side (not from the wall faces' identity rows)
+    const bool shift = c->wallvel && c->c0 != 0.0;
+    if (shift)
+      launch_add_background(c->dim, c->logn, c->Bs, c->h, c->L, c->dim - 1, c->wvel, -c->c0, c->wm, c->stream);
     st = c->mixed ? fgmres<float>(c, info) : fgmres<double>(c, info);
+    if (shift) {
+      launch_add_background(c->dim, c->logn, c->Bs, c->h, c->L, c->dim - 1, c->wvel, c->c0, c->wm, c->stream);
+      sync(c);
+    }
   });
   if (g != IBR_OK) return g;
   // guard() clears the message of a call that threw nothing: set it afterwards
@@ -1330,6 +1363,7 @@ ibr_status ibr_step(ibr_ctx* c, ibr_info* info) {
     if (c->steady) throw Status(IBR_ESTATE, "ibr_step needs rho > 0 (unsteady)");
     if (c->rotating) throw Status(IBR_EINVAL, "ibr_step translates the bodies: Omega must be zero");
     if (c->nfree) throw Status(IBR_EINVAL, "ibr_step moves bodies with prescribed velocities only: no free bodies");
+    if (c->wallvel) throw Status(IBR_EINVAL, "ibr_step with moving walls is not supported (advection is nonlinear)");
     if (c->walls) {
       // bodies translate with their prescribed velocity: every marker must stay between the walls
       const int d0 = c->dim;
@@ -1469,6 +1503,39 @@ ibr_status ibr_get_velocities(ibr_ctx* c, double* U, double* Omega) {
         if (U) U[b * d + a] = fr ? q[b * d + a] : u[b * d + a];
       for (int a = 0; a < nr; ++a)
         if (Omega) Omega[b * nr + a] = fr ? q[(size_t)nb * d + b * nr + a] : w[b * nr + a];
+    }
+  });
+}
+
+ibr_status ibr_set_wall_velocity(ibr_ctx* c, const double* lo, const double* hi) {
+  if (!c) return IBR_EINVAL;
+  return guard(c, [&] {
+    if (!lo && !hi) {
+      c->wallvel = false;
+      c->wvel = WallVel{};
+    } else {
+      if (!lo || !hi) throw Status(IBR_EINVAL, "lo and hi are both required (or both NULL)");
+      if (!c->walls) throw Status(IBR_EINVAL, "moving walls need walls");
+      const int d = c->dim;
+      for (int a = 0; a < d; ++a)
+        if (!std::isfinite(lo[a]) || !std::isfinite(hi[a])) throw Status(IBR_EINVAL, "wall velocities must be finite");
+      if (c->p.walls == IBR_WALLS_NOSLIP && (lo[d - 1] != 0.0 || hi[d - 1] != 0.0))
+        throw Status(IBR_EINVAL, "slit channel walls move in their planes: the last components must be 0");
+      if (c->p.walls == IBR_WALLS_BOX)
+        for (int a = 0; a < d; ++a)
+          if (lo[a] != hi[a]) throw Status(IBR_EINVAL, "the box's walls move together: lo must equal hi");
+      WallVel w{};
+      for (int a = 0; a < d; ++a) {
+        w.lo[a] = lo[a];
+        w.hi[a] = hi[a];
+      }
+      c->wvel = w;
+      c->wallvel = true;
+    }
+    if (c->nb > 0) {
+      IBR_HIP(hipSetDevice(c->p.device));
+      build_rhs_markers(c);
+      sync(c);
     }
   });
 }

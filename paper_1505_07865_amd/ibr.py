@@ -57,7 +57,7 @@ EXPORTS = ["ibr_default_params", "ibr_status_string", "ibr_create", "ibr_destroy
            "ibr_interp", "ibr_vcycle", "ibr_precondition", "ibr_mobility_block", "ibr_advect",
            "ibr_timer_enable", "ibr_timer_read", "ibr_mobility_inverse", "ibr_set_rhs_dev",
            "ibr_get_solution_dev", "ibr_reset", "ibr_set_free_bodies", "ibr_get_velocities",
-           "ibr_spread_noalloc"]
+           "ibr_spread_noalloc", "ibr_set_wall_velocity"]
 NOALLOC_SCRATCH_BYTES = 32 << 20
 
 
@@ -102,6 +102,7 @@ def load(path=LIB_PATH):
         "ibr_footprint_bytes": (ctypes.c_size_t, [P(Params), ctypes.c_int, ctypes.c_int]),
         "ibr_set_bodies": (ctypes.c_int, [vp, ctypes.c_int, ip, dp, dp]),
         "ibr_set_velocities": (ctypes.c_int, [vp, dp, dp]),
+        "ibr_set_wall_velocity": (ctypes.c_int, [vp, dp, dp]),
         "ibr_set_rhs": (ctypes.c_int, [vp, dp, dp]),
         "ibr_set_rhs_dev": (ctypes.c_int, [vp, vp, vp]),
         "ibr_solve": (ctypes.c_int, [vp, ctypes.c_int, P(Info)]),
@@ -254,6 +255,16 @@ class Solver:
         U = _f64(U).reshape(self.nb, self.dim)
         Om = _f64(Omega).reshape(self.nb, 3 if self.dim == 3 else 1)
         self._check(self._lib.ibr_set_velocities(self._ctx, _dptr(U), _dptr(Om)), "ibr_set_velocities")
+
+    def set_wall_velocity(self, lo, hi=None):
+        """Walls moving with velocities lo (at coordinate 0 of the last axis)
+        and hi (at n h); hi defaults to lo; None puts them back at rest."""
+        if lo is None:
+            self._check(self._lib.ibr_set_wall_velocity(self._ctx, None, None), "ibr_set_wall_velocity")
+            return
+        lo = _f64(lo).reshape(self.dim)
+        hi = lo if hi is None else _f64(hi).reshape(self.dim)
+        self._check(self._lib.ibr_set_wall_velocity(self._ctx, _dptr(lo), _dptr(hi)), "ibr_set_wall_velocity")
 
     def set_problem(self, prob):
         self.set_bodies(prob.R, prob.offsets, prob.centres)

@@ -235,3 +235,91 @@ def test_box_step_refused_at_a_side_wall():
     s.close()
     assert e.value.status == 1 and "wall" in str(e.value)
     assert np.array_equal(R0, R1) and np.array_equal(X0, X1)
+
+
+# ---------------------------------------------------------------- moving walls
+def _moving(prob, U):
+    return {beta: (np.asarray(U[0]), np.asarray(U[1])) for beta in range(prob.dim)}
+
+
+@pytest.mark.parametrize("name,precision,unsteady", [("3d16_two", "fp64", False), ("3d16_two", "mixed", False),
+                                                     ("2d32_three", "fp64", False), ("2d32_three", "fp64", True)])
+def test_box_moving_walls_match_oracle(name, precision, unsteady):
+    """The box's walls moving together with U (Sec. 7.3's box): the library's
+    solve (the walls' uniform background flow superposed) equals the oracle's
+    direct treatment of the inhomogeneous wall data on a padded lattice."""
+    from paper_1505_07865_amd import ibr
+    kw = dict(CASES[name])
+    if unsteady:
+        kw.update(rho=1.0, eta=0.05, dt=0.5 / kw["n"], rotate=False)
+    prob = box_problem(9, **kw)
+    d = prob.dim
+    U = np.array([0.6, -0.35, 0.25][:d])
+    print("moving box walls", name, precision, unsteady, flush=True)
+    fp64 = precision == "fp64"
+    s = ibr.from_problem(prob, precision=ibr.FP64 if fp64 else ibr.MIXED, rtol=1e-10 if fp64 else 1e-8)
+    s.set_wall_velocity(U)
+    info = s.solve()
+    sol = s.solution()
+    s.close()
+    ex = box.solve_problem_moving(prob, {beta: (U, U) for beta in range(d)})
+    tol = 1e-8 if fp64 else 1e-6
+    assert info["rel_residual"] <= (1e-10 if fp64 else 1e-8)
+    assert _rel(sol.u, ex.v) < tol, _rel(sol.u, ex.v)
+    assert _rel(sol.F, ex.F) < tol, _rel(sol.F, ex.F)
+    for a in range(d):
+        assert np.abs(sol.u[a][box.wall_mask(prob.n, d, _walls(d), a)] - U[a]).max() < 1e-14
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_slit_couette_walls_match_oracle(dim):
+    """Slit channel with the top wall sliding (Couette): equals the oracle's
+    direct inhomogeneous solve; the device copy of the solution equals the
+    host copy."""
+    import torch
+    from paper_1505_07865_amd import ibr
+    from synthetic import slit_problem
+    prob = slit_problem(2, dim=dim, n=16 if dim == 3 else 32, nbodies=2, radius_h=2.5 if dim == 3 else 4.0,
+                        wall_gap_h=1.0, gap_h=2.0)
+    lo = np.zeros(dim)
+    hi = np.zeros(dim)
+    hi[0] = 0.9
+    print("Couette slit, %dD" % dim, flush=True)
+    s = ibr.from_problem(prob, rtol=1e-10)
+    s.set_wall_velocity(lo, hi)
+    s.solve()
+    sol = s.solution()
+    n = prob.n
+    u_dev = torch.zeros((dim,) + (n,) * dim, dtype=torch.float64, device="cuda")
+    s.solution_dev(u=u_dev)
+    torch.cuda.synchronize()
+    s.close()
+    walls = (False,) * (dim - 1) + (True,)
+    ex = box.solve_problem_moving(prob, {dim - 1: (lo, hi)}, walls=walls)
+    assert _rel(sol.u, ex.v) < 1e-8 and _rel(sol.F, ex.F) < 1e-8
+    assert np.array_equal(u_dev.cpu().numpy(), sol.u)
+
+
+def test_moving_walls_refusals():
+    from paper_1505_07865_amd import ibr
+    from synthetic import slit_problem, small_problem
+    p = small_problem(1, 3, 16, radius_h=2.5)
+    s = ibr.from_problem(p)
+    with pytest.raises(ibr.IbrError):
+        s.set_wall_velocity([1.0, 0.0, 0.0])          # a periodic box has no walls
+    s.close()
+    p = slit_problem(1, dim=3, n=16, nbodies=1, radius_h=2.5)
+    s = ibr.from_problem(p)
+    with pytest.raises(ibr.IbrError):
+        s.set_wall_velocity([0.0, 0.0, 0.3], [0.0, 0.0, 0.0])   # slit walls do not move along their normal
+    s.close()
+    p = box_problem(1, dim=3, n=16, nbodies=1, radius_h=2.5, rho=1.0, eta=0.05, dt=0.01, rotate=False)
+    s = ibr.from_problem(p)
+    with pytest.raises(ibr.IbrError):
+        s.set_wall_velocity([0.1, 0.0, 0.0], [0.2, 0.0, 0.0])   # the box's walls move together
+    s.set_wall_velocity([0.1, 0.0, 0.0])
+    with pytest.raises(ibr.IbrError):
+        s.step()                                                  # advection is not linear in u
+    s.set_wall_velocity(None)
+    s.step()
+    s.close()
