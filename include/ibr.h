@@ -120,9 +120,8 @@ typedef struct {
                          nothing) when a body would cross a wall.  Between
                          walls P_S^-1 approximates the Stokes block less well
                          (Sec. 7.1): n_s = 4 is the robust choice for many
-                         markers.  Wall velocities are zero: a moving box is
-                         solved in its own frame (Stokes flow has no inertia
-                         to change with the frame). */
+                         markers.  The walls are at rest unless
+                         ibr_set_wall_velocity gives them a velocity. */
   int advection;      /* IBR_ADVECT_CENTRED (default) or IBR_ADVECT_SL.
                          CENTRED: N(v) = sum_b vbar^b (v^a_{c+e_b} -
                          v^a_{c-e_b}) / 2h with vbar^b the average of the four
