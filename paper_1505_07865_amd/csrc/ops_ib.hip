@@ -229,9 +229,13 @@ __global__ void k_active_tiles(int dim, int tiles_log, const int* __restrict__ o
 // ---------------------------------------------------------------- spreading (gather)
 // One workgroup of four wavefronts per (active tile, component a).  The
 // candidate markers (those binned in the neighbouring tiles, tiles in a fixed
-// order, markers sorted inside each tile) are taken 256 at a time: each thread
-// tests one candidate against the tile and the hits are compacted, in order,
-// into LDS with their first taps and weights (lam folded into the x weights).
+// order, markers sorted inside each tile) are taken kChunk at a time: each
+// thread tests one candidate against the tile and the hits are compacted, in
+// order, into LDS with their first taps and weights (lam folded into the x
+// weights).  A chunk of 192 covers the neighbourhood of a tile of spheres at
+// a marker spacing of about 2h in one pass and keeps the workgroup's LDS
+// under 40 KB, so four workgroups share a compute unit; the tile's own
+// values of y are loaded at the start, while the candidates are gathered.
 // Wavefront w then takes hits w, w+4, ...; for one marker its 64 lanes are the
 // 4^3 taps (distinct faces) and add into that wavefront's own accumulator.  The
 // four accumulators are summed in a fixed order at the end: no atomics, and
@@ -245,11 +249,12 @@ __global__ void __launch_bounds__(256) k_spread(int logn, int tile_log, const in
   if ((int)blockIdx.x >= nactive[0]) return;  // grid sized to a capacity, count read on the device
   constexpr int kCells = DIM == 3 ? 512 : 256;  // 8^3 or 16^2
   constexpr int kWaves = 4;
-  constexpr int kChunk = 256;
+  constexpr int kChunk = 192;
+  constexpr int kPer = kCells / 256;  // cells of the tile per thread
   __shared__ double acc[kWaves][kCells];
   __shared__ double sw[kChunk][DIM][4];
   __shared__ int sd[kChunk][DIM];
-  __shared__ int rlo[27], rpre[28];
+  __shared__ int rlo[27], rpre[28];  // first candidate of neighbour tile r; prefix sums of their counts
   __shared__ int wcnt[kWaves];
 
   const int n = 1 << logn;
@@ -265,7 +270,18 @@ __global__ void __launch_bounds__(256) k_spread(int logn, int tile_log, const in
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
   const int cells = 1 << (DIM * tile_log);
-  __shared__ int rlen[27];
+  // this thread's cells of the tile: their indices in y and their old values
+  int64_t yidx[kPer];
+  TY yold[kPer];
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int q = tid + 256 * u;
+    const int l0 = q & (tsz - 1), l1 = (q >> tile_log) & (tsz - 1), l2 = DIM == 3 ? (q >> (2 * tile_log)) : 0;
+    const int64_t c = SPLIT ? (int64_t)split_index<DIM>(lo[0] + l0, lo[1] + l1, lo[2] + l2, logn)
+                            : (int64_t)natural_index<DIM>(lo[0] + l0, lo[1] + l1, lo[2] + l2, logn);
+    yidx[u] = q < cells ? (int64_t)a * C + c : -1;
+    yold[u] = q < cells ? y[yidx[u]] : TY(0);
+  }
   for (int q = tid; q < kWaves * kCells; q += 256) (&acc[0][0])[q] = 0.0;
   {
     // neighbour tile r (in a fixed order) fetched by thread r
@@ -275,25 +291,26 @@ __global__ void __launch_bounds__(256) k_spread(int logn, int tile_log, const in
     int nz = 1;
     cz[0] = 0;
     if (DIM == 3) nz = nbr_coords(tc[2], nt, cz);
-    if (tid < 27) {
+    if (wave == 0) {
       int lo_r = 0, len = 0;
-      if (tid < nx * ny * nz) {
-        const int c3 = tid % nx, b3 = (tid / nx) % ny, a3 = tid / (nx * ny);
+      if (lane < nx * ny * nz) {
+        const int c3 = lane % nx, b3 = (lane / nx) % ny, a3 = lane / (nx * ny);
         const int tt = cx[c3] | (cy[b3] << tiles_log) | (cz[a3] << (2 * tiles_log));
         lo_r = off[tt];
         len = off[tt + 1] - lo_r;
       }
-      rlo[tid] = lo_r;
-      rlen[tid] = len;
-    }
-    __syncthreads();
-    if (tid == 0) {
-      int tot = 0;
-      for (int r = 0; r < 27; ++r) {
-        rpre[r] = tot;
-        tot += rlen[r];
+      // inclusive scan of the lengths over the wavefront's first 32 lanes
+      int incl = len;
+#pragma unroll
+      for (int o = 1; o < 32; o <<= 1) {
+        const int t = __shfl_up(incl, o, kWave);
+        if (lane >= o) incl += t;
       }
-      rpre[27] = tot;
+      if (lane < 27) {
+        rlo[lane] = lo_r;
+        rpre[lane + 1] = incl;
+      }
+      if (lane == 0) rpre[0] = 0;
     }
   }
   __syncthreads();
@@ -306,14 +323,26 @@ __global__ void __launch_bounds__(256) k_spread(int logn, int tile_log, const in
     const int q = c0 + tid;
     bool hit = false;
     int m = 0, d[3] = {0, 0, 0};
-    if (q < total) {
-      int r = 0;
-      while (q >= rpre[r + 1]) ++r;
+    double lm = 0.0, wv[DIM][4];
+    if (tid < kChunk && q < total) {
+      // neighbour tile of candidate q: rpre[r] <= q < rpre[r + 1] (rpre[27] = total > q)
+      int r = 0, rh = 27;
+      while (rh - r > 1) {
+        const int mid = (r + rh) >> 1;
+        if (rpre[mid] <= q)
+          r = mid;
+        else
+          rh = mid;
+      }
       m = perm[rlo[r] + (q - rpre[r])];
       hit = true;
+      // the candidate's weights and force are loaded with its taps, whether it hits or not
+      lm = (double)lam[m * DIM + a];
       for (int beta = 0; beta < DIM; ++beta) {
         const int s = beta == a ? 1 : 0;
         d[beta] = (tbase[(m * 2 + s) * 3 + beta] - lo[beta]) & mask;
+        const double* wp = tw + ((m * 2 + s) * 3 + beta) * 4;
+        for (int t = 0; t < 4; ++t) wv[beta][t] = wp[t];
         // the 4 taps along beta meet the tile when the first one is within [-3, tsz)
         hit = hit && (d[beta] < tsz || d[beta] >= n - 3);
       }
@@ -329,12 +358,9 @@ __global__ void __launch_bounds__(256) k_spread(int logn, int tile_log, const in
     }
     if (hit) {
       const int slot = base + rank;
-      const double lm = (double)lam[m * DIM + a];
       for (int beta = 0; beta < DIM; ++beta) {
-        const int s = beta == a ? 1 : 0;
-        const double* wp = tw + ((m * 2 + s) * 3 + beta) * 4;
         sd[slot][beta] = d[beta];
-        for (int t = 0; t < 4; ++t) sw[slot][beta][t] = beta == 0 ? lm * wp[t] : wp[t];
+        for (int t = 0; t < 4; ++t) sw[slot][beta][t] = beta == 0 ? lm * wv[beta][t] : wv[beta][t];
       }
     }
     __syncthreads();
@@ -353,13 +379,12 @@ __global__ void __launch_bounds__(256) k_spread(int logn, int tile_log, const in
     }
     __syncthreads();
   }
-  for (int q = tid; q < cells; q += 256) {
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int q = tid + 256 * u;
+    if (yidx[u] < 0) continue;
     const double v = ((acc[0][q] + acc[1][q]) + acc[2][q]) + acc[3][q];
-    const int l0 = q & (tsz - 1), l1 = (q >> tile_log) & (tsz - 1), l2 = DIM == 3 ? (q >> (2 * tile_log)) : 0;
-    const int64_t c = SPLIT ? (int64_t)split_index<DIM>(lo[0] + l0, lo[1] + l1, lo[2] + l2, logn)
-                            : (int64_t)natural_index<DIM>(lo[0] + l0, lo[1] + l1, lo[2] + l2, logn);
-    const int64_t idx = (int64_t)a * C + c;
-    y[idx] = (TY)((double)y[idx] + scale * v);
+    y[yidx[u]] = (TY)((double)yold[u] + scale * v);
   }
 }
 
