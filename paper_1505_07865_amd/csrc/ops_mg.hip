@@ -392,22 +392,66 @@ __global__ void __launch_bounds__(256) k_prolong_add(T* __restrict__ x, const T*
 }
 
 // ---------------------------------------------------------------- one-workgroup tail
-template <typename T>
-__device__ void lds_remove_mean(T* b, int C, T* red) {
-  T s = 0;
-  for (int c = threadIdx.x; c < C; c += blockDim.x) s += b[c];
-  s = block_sum(s, red);
-  const T m = s / T(C);
-  __syncthreads();
-  for (int c = threadIdx.x; c < C; c += blockDim.x) b[c] -= m;
-  __syncthreads();
+// Orders one wavefront's LDS accesses across its lanes: every access before
+// it is complete and visible to the wavefront's other lanes before any after it.
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Tail levels of at most this many cells run in wavefront 0 alone (at most
+// two items per lane and phase, 3D 8^3 and 2D 32^2 down): each phase then
+// ends with a wavefront-level ordering instead of a workgroup barrier, whose
+// cost dominates phases that small.
+constexpr int kWaveCells = 1024;
+
+// One level's pre-smoothing from zero and restriction of its residual into
+// the next level's b.  Items t = i0, i0 + st, ...; sync() ends each phase.
+template <typename T, int DIM, typename Sync>
+__device__ inline void tail_pre(T* x, const T* b, T* bc, int lg, T c0, T cl, int nu_pre, int i0, int st, Sync sync) {
+  const int Cl = 1 << (DIM * lg);
+  if (nu_pre > 0) {
+    for (int g = i0; g < (Cl >> 3); g += st) rb_first_group<T, DIM>(x, b, lg, c0, cl, g);
+    sync();
+    for (int sw = 1; sw < nu_pre; ++sw)
+      for (int color = 0; color < 2; ++color) {
+        for (int g = i0; g < (Cl >> 3); g += st) rb_group<T, DIM>(x, b, lg, c0, cl, color, g);
+        sync();
+      }
+  } else {
+    for (int c = i0; c < Cl; c += st) x[c] = T(0);
+    sync();
+  }
+  for (int g = i0; g < ((Cl >> DIM) >> 2); g += st) restrict_group<T, DIM>(x, b, bc, lg, c0, cl, g);
+  sync();
+}
+
+// One level's prolongation of the coarse correction xc and post-smoothing.
+template <typename T, int DIM, typename Sync>
+__device__ inline void tail_post(T* x, const T* xc, const T* b, int lg, T c0, T cl, int nu_post, int i0, int st,
+                                 Sync sync) {
+  const int Cl = 1 << (DIM * lg);
+  if (nu_post > 0) {
+    for (int g = i0; g < (Cl >> 3); g += st) prolong_group<T, DIM, true>(x, xc, lg, g);
+  } else {
+    for (int g = i0; g < (Cl >> 3); g += st) prolong_group<T, DIM, false>(x, xc, lg, g);
+  }
+  sync();
+  for (int sw = 0; sw < nu_post; ++sw)
+    for (int color = 0; color < 2; ++color) {
+      for (int g = i0; g < (Cl >> 3); g += st) rb_group<T, DIM>(x, b, lg, c0, cl, color, g);
+      sync();
+    }
 }
 
 // V-cycle from the tail's entry level down to n = 4, one field per workgroup
 // of kLdsThreads threads, on split storage like the global levels: the
 // iterates of every tail level and the right-hand sides below the entry level
 // live in LDS; the entry level's right-hand side is read from global memory.
-// c1 is the coefficient at the entry level.
+// Levels above kWaveCells cells use the whole workgroup, the smaller ones
+// wavefront 0 (the others wait at the workgroup barrier after them).  c1 is
+// the coefficient at the entry level; level l uses c1 / 4^l (exact).
 template <typename T, int DIM>
 __global__ void __launch_bounds__(kLdsThreads) k_vcycle_lds(const T* __restrict__ bg, T* __restrict__ xg, int logn,
                                                             T c0, T c1, int nu_pre, int nu_post, int nu_coarse) {
@@ -415,7 +459,6 @@ __global__ void __launch_bounds__(kLdsThreads) k_vcycle_lds(const T* __restrict_
   constexpr int kB = (int)pyramid_cells<DIM>(kTailMaxCells >> DIM) + 64;
   __shared__ Quad<T> xs4[kX / 4];  // x of every level back to back, entry level first
   __shared__ Quad<T> bs4[kB / 4];  // b of the levels below the entry level
-  __shared__ T red[kLdsThreads / kWave];
   T* xs = &xs4[0].v[0];
   T* bs = &bs4[0].v[0];
   const int tid = threadIdx.x, nt = blockDim.x;
@@ -444,63 +487,50 @@ __global__ void __launch_bounds__(kLdsThreads) k_vcycle_lds(const T* __restrict_
     for (int c = tid; c < C0; c += nt) bl[0][c] = b0[c];
     __syncthreads();
   }
+  auto level_b = [&](int l) -> const T* { return l == 0 ? b0 : bl[l]; };
+  auto coef = [&](int l) { return c1 / T(1 << (2 * l)); };
+  auto block_sync = [] { __syncthreads(); };
+  auto wsync = [] { wave_sync(); };
 
-  T cl = c1;
-  for (int l = 0; l < nlev - 1; ++l) {
-    const int lg = logn - l;
-    const int Cl = 1 << (DIM * lg);
-    T* x = xs + off[l];
-    const T* b = l == 0 ? b0 : bl[l];
-    if (nu_pre > 0) {
-      for (int g = tid; g < (Cl >> 3); g += nt) rb_first_group<T, DIM>(x, b, lg, c0, cl, g);
-      __syncthreads();
-      for (int sw = 1; sw < nu_pre; ++sw)
+  // first level small enough for one wavefront (the coarsest always is)
+  int lw = 0;
+  while (lw < nlev - 1 && (1 << (DIM * (logn - lw))) > kWaveCells) ++lw;
+  for (int l = 0; l < lw; ++l)
+    tail_pre<T, DIM>(xs + off[l], level_b(l), bl[l + 1], logn - l, c0, coef(l), nu_pre, tid, nt, block_sync);
+  if (tid < kWave) {
+    const int lane = tid;
+    for (int l = lw; l < nlev - 1; ++l)
+      tail_pre<T, DIM>(xs + off[l], level_b(l), bl[l + 1], logn - l, c0, coef(l), nu_pre, lane, kWave, wsync);
+    {
+      // coarsest grid (n = 4): nu_coarse sweeps from zero
+      const int l = nlev - 1;
+      const int lg = logn - l;
+      const int Cl = 1 << (DIM * lg);
+      const T cl = coef(l);
+      T* x = xs + off[l];
+      T* b = bl[l];
+      if (singular) {
+        T sm = 0;
+        for (int c = lane; c < Cl; c += kWave) sm += b[c];
+        const T m = wave_sum(sm) / T(Cl);
+        for (int c = lane; c < Cl; c += kWave) b[c] -= m;
+      }
+      for (int c = lane; c < Cl; c += kWave) x[c] = T(0);
+      wsync();
+      for (int sw = 0; sw < nu_coarse; ++sw)
         for (int color = 0; color < 2; ++color) {
-          for (int g = tid; g < (Cl >> 3); g += nt) rb_group<T, DIM>(x, b, lg, c0, cl, color, g);
-          __syncthreads();
+          for (int t = lane; t < (Cl >> 1); t += kWave) rb_cell<T, DIM>(x, b, lg, c0, cl, color, t);
+          wsync();
         }
-    } else {
-      for (int c = tid; c < Cl; c += nt) x[c] = T(0);
-      __syncthreads();
     }
-    for (int g = tid; g < ((Cl >> DIM) >> 2); g += nt) restrict_group<T, DIM>(x, b, bl[l + 1], lg, c0, cl, g);
-    __syncthreads();
-    cl = cl * T(0.25);
+    for (int l = nlev - 2; l >= lw; --l)
+      tail_post<T, DIM>(xs + off[l], xs + off[l + 1], level_b(l), logn - l, c0, coef(l), nu_post, lane, kWave,
+                        wsync);
   }
-  {
-    // coarsest grid (n = 4): nu_coarse sweeps from zero
-    const int l = nlev - 1;
-    const int lg = logn - l;
-    const int Cl = 1 << (DIM * lg);
-    T* x = xs + off[l];
-    T* b = bl[l];
-    if (singular) lds_remove_mean<T>(b, Cl, red);
-    for (int c = tid; c < Cl; c += nt) x[c] = T(0);
-    __syncthreads();
-    for (int sw = 0; sw < nu_coarse; ++sw)
-      for (int color = 0; color < 2; ++color) {
-        for (int t = tid; t < (Cl >> 1); t += nt) rb_cell<T, DIM>(x, b, lg, c0, cl, color, t);
-        __syncthreads();
-      }
-  }
-  for (int l = nlev - 2; l >= 0; --l) {
-    cl = cl * T(4);
-    const int lg = logn - l;
-    const int Cl = 1 << (DIM * lg);
-    T* x = xs + off[l];
-    const T* b = l == 0 ? b0 : bl[l];
-    if (nu_post > 0) {
-      for (int g = tid; g < (Cl >> 3); g += nt) prolong_group<T, DIM, true>(x, xs + off[l + 1], lg, g);
-    } else {
-      for (int g = tid; g < (Cl >> 3); g += nt) prolong_group<T, DIM, false>(x, xs + off[l + 1], lg, g);
-    }
-    __syncthreads();
-    for (int sw = 0; sw < nu_post; ++sw)
-      for (int color = 0; color < 2; ++color) {
-        for (int g = tid; g < (Cl >> 3); g += nt) rb_group<T, DIM>(x, b, lg, c0, cl, color, g);
-        __syncthreads();
-      }
-  }
+  __syncthreads();
+  for (int l = lw - 1; l >= 0; --l)
+    tail_post<T, DIM>(xs + off[l], xs + off[l + 1], level_b(l), logn - l, c0, coef(l), nu_post, tid, nt,
+                      block_sync);
   for (int q = tid; q < (C0 >> 2); q += nt) stq(x0 + 4 * q, ldq(xs + 4 * q));
 }
 
