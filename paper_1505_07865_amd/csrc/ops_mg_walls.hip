@@ -51,13 +51,50 @@ __device__ inline int field_kinds(int mode, int f, int wm) {
   return kinds;
 }
 
-__device__ inline int kind_of(int kinds, int b) { return (kinds >> (2 * b)) & 3; }
+// Kind of axis b.  K >= 0: the kinds are the compile-time constant K (the
+// per-cell steps below are instantiated for the combinations the slit and
+// the box produce, so every per-axis branch folds away); K < 0: the run-time
+// value `kinds`.
+template <int K>
+__device__ inline int kind_of(int kinds, int b) {
+  return K >= 0 ? (K >> (2 * b)) & 3 : (kinds >> (2 * b)) & 3;
+}
+
+// Calls f(std::integral_constant<int, K>) with K = kinds for the field kinds
+// of the slit channel and of the box (3D: walls on z, on every axis; 2D: on
+// y, on both), K = -1 (run-time kinds) otherwise.
+template <int DIM, typename F>
+__device__ inline void with_kinds(int kinds, F&& f) {
+  using std::integral_constant;
+  if constexpr (DIM == 3) {
+    switch (kinds) {
+      case 16: f(integral_constant<int, 16>{}); return;  // slit: tangential velocity
+      case 32: f(integral_constant<int, 32>{}); return;  // slit: normal velocity
+      case 48: f(integral_constant<int, 48>{}); return;  // slit: pressure
+      case 22: f(integral_constant<int, 22>{}); return;  // box: velocity along x
+      case 25: f(integral_constant<int, 25>{}); return;  // box: velocity along y
+      case 37: f(integral_constant<int, 37>{}); return;  // box: velocity along z
+      case 63: f(integral_constant<int, 63>{}); return;  // box: pressure
+      default: f(integral_constant<int, -1>{}); return;
+    }
+  } else {
+    switch (kinds) {
+      case 4: f(integral_constant<int, 4>{}); return;    // slit: tangential velocity
+      case 8: f(integral_constant<int, 8>{}); return;    // slit: normal velocity
+      case 12: f(integral_constant<int, 12>{}); return;  // slit: pressure
+      case 6: f(integral_constant<int, 6>{}); return;    // box: velocity along x
+      case 9: f(integral_constant<int, 9>{}); return;    // box: velocity along y
+      case 15: f(integral_constant<int, 15>{}); return;  // box: pressure
+      default: f(integral_constant<int, -1>{}); return;
+    }
+  }
+}
 
 // A wall face: index 0 along an axis of face kind.
-template <int DIM>
+template <int DIM, int K>
 __device__ inline bool on_wall_face(const int* co, int kinds) {
   for (int b = 0; b < DIM; ++b)
-    if (kind_of(kinds, b) == kFaceDir && co[b] == 0) return true;
+    if (kind_of<K>(kinds, b) == kFaceDir && co[b] == 0) return true;
   return false;
 }
 
@@ -82,14 +119,15 @@ __device__ inline T at(const T* x, const int* co, int logn) {
 
 // Sum of the neighbours that are other unknowns, and the diagonal of
 // (c0 - c1 L) at cell co.
-template <typename T, int DIM>
+template <typename T, int DIM, int K>
 __device__ inline T nbr_sum(const T* x, const int* co, int logn, int kinds, T c0, T c1, T& diag) {
   const int n = 1 << logn;
   const int mask = n - 1;
   diag = c0 + T(2 * DIM) * c1;
   T sum = T(0);
+#pragma unroll
   for (int b = DIM - 1; b >= 0; --b) {
-    const int kind = kind_of(kinds, b);
+    const int kind = kind_of<K>(kinds, b);
     int q[3] = {co[0], co[1], co[2]};
     T up = T(0), dn = T(0);
     if (kind == kPer) {
@@ -127,28 +165,28 @@ __device__ inline T nbr_sum(const T* x, const int* co, int logn, int kinds, T c0
   return sum;
 }
 
-template <typename T, int DIM>
+template <typename T, int DIM, int K>
 __device__ inline T resid_at(const T* x, const T* b, const int* co, int logn, int kinds, T c0, T c1) {
-  if (on_wall_face<DIM>(co, kinds)) return T(0);
+  if (on_wall_face<DIM, K>(co, kinds)) return T(0);
   T diag;
-  const T sum = nbr_sum<T, DIM>(x, co, logn, kinds, c0, c1, diag);
+  const T sum = nbr_sum<T, DIM, K>(x, co, logn, kinds, c0, c1, diag);
   return at<T, DIM>(b, co, logn) - (diag * at<T, DIM>(x, co, logn) - c1 * sum);
 }
 
 // ---- per-cell steps (global kernels: one cell per thread; the tail: loops)
 // Half sweep at cell t of colour `color`.
-template <typename T, int DIM>
+template <typename T, int DIM, int K>
 __device__ inline void wrb_cell(T* x, const T* b, int logn, T c0, T c1, int color, int t, int kinds) {
   const int C = 1 << (DIM * logn);
   int co[3];
   colour_cell<DIM>(t, color, logn, co);
   const int own = color * (C >> 1) + t;
-  if (on_wall_face<DIM>(co, kinds)) {
+  if (on_wall_face<DIM, K>(co, kinds)) {
     x[own] = T(0);
     return;
   }
   T diag;
-  const T sum = nbr_sum<T, DIM>(x, co, logn, kinds, c0, c1, diag);
+  const T sum = nbr_sum<T, DIM, K>(x, co, logn, kinds, c0, c1, diag);
   x[own] = (b[own] + c1 * sum) / diag;
 }
 
@@ -156,7 +194,7 @@ __device__ inline void wrb_cell(T* x, const T* b, int logn, T c0, T c1, int colo
 // residual: its split index on the coarse level is returned in *at_c.  Per
 // axis the fine points and weights of the one-dimensional restriction; the
 // coarse value is their tensor product.
-template <typename T, int DIM>
+template <typename T, int DIM, int K>
 __device__ inline T wrestrict_cell(const T* x, const T* b, int logn, T c0, T c1, int t, int kinds, int* at_c) {
   const int lognc = logn - 1;
   const int maskc = (1 << lognc) - 1;
@@ -169,8 +207,9 @@ __device__ inline T wrestrict_cell(const T* x, const T* b, int logn, T c0, T c1,
     fi[a][0] = 0;
     fw[a][0] = T(1);
   }
+#pragma unroll
   for (int a = 0; a < DIM; ++a) {
-    if (kind_of(kinds, a) == kFaceDir) {
+    if (kind_of<K>(kinds, a) == kFaceDir) {
       if (cc[a] == 0) return T(0);  // the coarse wall face
       cnt[a] = 3;
       fi[a][0] = 2 * cc[a] - 1;
@@ -188,28 +227,35 @@ __device__ inline T wrestrict_cell(const T* x, const T* b, int logn, T c0, T c1,
     }
   }
   T out = T(0);
-  for (int qz = 0; qz < cnt[2]; ++qz)
-    for (int qy = 0; qy < cnt[1]; ++qy) {
+#pragma unroll
+  for (int qz = 0; qz < 3; ++qz) {
+    if (qz >= cnt[2]) break;
+#pragma unroll
+    for (int qy = 0; qy < 3; ++qy) {
+      if (qy >= cnt[1]) break;
       T row = T(0);
-      for (int qx = 0; qx < cnt[0]; ++qx) {
+#pragma unroll
+      for (int qx = 0; qx < 3; ++qx) {
+        if (qx >= cnt[0]) break;
         const int co[3] = {fi[0][qx], fi[1][qy], fi[2][qz]};
-        row += fw[0][qx] * resid_at<T, DIM>(x, b, co, logn, kinds, c0, c1);
+        row += fw[0][qx] * resid_at<T, DIM, K>(x, b, co, logn, kinds, c0, c1);
       }
       out += fw[1][qy] * fw[2][qz] * row;
     }
+  }
   return out;
 }
 
 // x += P e at fine cell t (natural index).  Per axis the coarse points and
 // weights of the one-dimensional interpolation (with a sign for a mirror
 // ghost); the correction is their tensor product.
-template <typename T, int DIM>
+template <typename T, int DIM, int K>
 __device__ inline void wprolong_cell(T* x, const T* e, int logn, int t, int kinds) {
   const int lognc = logn - 1;
   const int nc = 1 << lognc;
   const int mask = (1 << logn) - 1;
   const int co[3] = {t & mask, (t >> logn) & mask, DIM == 3 ? (t >> (2 * logn)) : 0};
-  if (on_wall_face<DIM>(co, kinds)) return;
+  if (on_wall_face<DIM, K>(co, kinds)) return;
   int ci[3][2];
   T cw[3][2];
   int cnt[3] = {1, 1, 1};
@@ -217,8 +263,9 @@ __device__ inline void wprolong_cell(T* x, const T* e, int logn, int t, int kind
     ci[a][0] = 0;
     cw[a][0] = T(1);
   }
+#pragma unroll
   for (int a = 0; a < DIM; ++a) {
-    const int kind = kind_of(kinds, a);
+    const int kind = kind_of<K>(kinds, a);
     const int w = co[a], P = w >> 1;
     if (kind == kFaceDir) {
       // coarse face P on fine face 2P; odd faces average P and P + 1 (face nc is the wall)
@@ -248,15 +295,22 @@ __device__ inline void wprolong_cell(T* x, const T* e, int logn, int t, int kind
     }
   }
   T val = T(0);
-  for (int qz = 0; qz < cnt[2]; ++qz)
-    for (int qy = 0; qy < cnt[1]; ++qy) {
+#pragma unroll
+  for (int qz = 0; qz < 2; ++qz) {
+    if (qz >= cnt[2]) break;
+#pragma unroll
+    for (int qy = 0; qy < 2; ++qy) {
+      if (qy >= cnt[1]) break;
       T row = T(0);
-      for (int qx = 0; qx < cnt[0]; ++qx) {
+#pragma unroll
+      for (int qx = 0; qx < 2; ++qx) {
+        if (qx >= cnt[0]) break;
         const int cc[3] = {ci[0][qx], ci[1][qy], ci[2][qz]};
         row += cw[0][qx] * at<T, DIM>(e, cc, lognc);
       }
       val += cw[1][qy] * cw[2][qz] * row;
     }
+  }
   x[split_index<DIM>(co[0], co[1], co[2], logn)] += val;
 }
 
@@ -268,7 +322,10 @@ __global__ void __launch_bounds__(256) k_wrb(T* __restrict__ x, const T* __restr
   const int t = (int)(blockIdx.x * blockDim.x + threadIdx.x);
   if (t >= (C >> 1)) return;
   const int f = blockIdx.y;
-  wrb_cell<T, DIM>(x + (int64_t)f * C, b + (int64_t)f * C, logn, c0, c1, color, t, field_kinds<DIM>(mode, f, wm));
+  const int kinds = field_kinds<DIM>(mode, f, wm);
+  with_kinds<DIM>(kinds, [&](auto kc) {
+    wrb_cell<T, DIM, decltype(kc)::value>(x + (int64_t)f * C, b + (int64_t)f * C, logn, c0, c1, color, t, kinds);
+  });
 }
 
 template <typename T, int DIM>
@@ -279,10 +336,13 @@ __global__ void __launch_bounds__(256) k_wresid_restrict(const T* __restrict__ x
   const int t = (int)(blockIdx.x * blockDim.x + threadIdx.x);
   if (t >= Cc) return;
   const int f = blockIdx.y;
-  int at_c;
-  const T r = wrestrict_cell<T, DIM>(x + (int64_t)f * C, b + (int64_t)f * C, logn, c0, c1, t,
-                                     field_kinds<DIM>(mode, f, wm), &at_c);
-  bc[(int64_t)f * Cc + at_c] = r;
+  const int kinds = field_kinds<DIM>(mode, f, wm);
+  with_kinds<DIM>(kinds, [&](auto kc) {
+    int at_c;
+    const T r = wrestrict_cell<T, DIM, decltype(kc)::value>(x + (int64_t)f * C, b + (int64_t)f * C, logn, c0, c1,
+                                                            t, kinds, &at_c);
+    bc[(int64_t)f * Cc + at_c] = r;
+  });
 }
 
 template <typename T, int DIM>
@@ -292,7 +352,10 @@ __global__ void __launch_bounds__(256) k_wprolong(T* __restrict__ x, const T* __
   const int t = (int)(blockIdx.x * blockDim.x + threadIdx.x);
   if (t >= C) return;
   const int f = blockIdx.y;
-  wprolong_cell<T, DIM>(x + (int64_t)f * C, e + (int64_t)f * Cc, logn, t, field_kinds<DIM>(mode, f, wm));
+  const int kinds = field_kinds<DIM>(mode, f, wm);
+  with_kinds<DIM>(kinds, [&](auto kc) {
+    wprolong_cell<T, DIM, decltype(kc)::value>(x + (int64_t)f * C, e + (int64_t)f * Cc, logn, t, kinds);
+  });
 }
 
 // ---- the coarse tail in one workgroup per field
@@ -309,54 +372,51 @@ constexpr int wall_pyramid(int C) {
   return t;
 }
 
-template <typename T, int DIM>
-__global__ void __launch_bounds__(kWallTailThreads) k_wvcycle_lds(const T* __restrict__ bg, T* __restrict__ xg,
-                                                                  int logn, T c0, T c1, int nu_pre, int nu_post,
-                                                                  int nu_coarse, int mode, int wm) {
-  constexpr int kX = wall_pyramid<DIM>(kWallTailCells);
-  constexpr int kB = wall_pyramid<DIM>(kWallTailCells >> DIM) + 1;
-  __shared__ T xs[kX];
-  __shared__ T bs[kB];
-  __shared__ T red[kWallTailThreads / kWave];
+// Offset of level l in the tail's pyramid of levels (entry level 0 first).
+template <int DIM>
+__device__ inline int pyramid_off(int logn, int l) {
+  int o = 0;
+  for (int i = 0; i < l; ++i) o += 1 << (DIM * (logn - i));
+  return o;
+}
+
+// The tail's V-cycle for one field whose kinds are K (or the run-time kinds).
+// xs: x of every level, entry level first; bs: b of the levels below the entry
+// level (level l >= 1 at pyramid_off(l) - C0).
+template <typename T, int DIM, int K>
+__device__ inline void wvcycle_body(const T* __restrict__ b0, T* __restrict__ x0, T* xs, T* bs, T* red, int logn,
+                                    T c0, T c1, int nu_pre, int nu_post, int nu_coarse, int mode, int kinds) {
   const int tid = threadIdx.x, nt = blockDim.x;
-  const int f = blockIdx.x;
-  const int kinds = field_kinds<DIM>(mode, f, wm);
   const int C0 = 1 << (DIM * logn);
-  const T* b0 = bg + (int64_t)f * C0;
-  T* x0 = xg + (int64_t)f * C0;
   const int nlev = logn - 1;  // entry level down to n = 4
-  int off[12], boff[12];
-  {
-    int xo = 0, bo = 0;
-    for (int l = 0; l < nlev; ++l) {
-      const int Cl = 1 << (DIM * (logn - l));
-      off[l] = xo;
-      xo += Cl;
-      boff[l] = bo;
-      if (l > 0) bo += Cl;
-    }
-  }
-  auto bl = [&](int l) -> const T* { return l == 0 ? b0 : bs + boff[l]; };
+  auto xl = [&](int l) { return xs + pyramid_off<DIM>(logn, l); };
+  auto bl = [&](int l) -> T* { return l == 0 ? nullptr : bs + (pyramid_off<DIM>(logn, l) - C0); };
+  auto bread = [&](int l) -> const T* { return l == 0 ? b0 : bl(l); };
   T cl = c1;
   auto sweeps = [&](int l, T cc, int nsw) {
     const int lg = logn - l;
     const int H = 1 << (DIM * lg - 1);
+    T* x = xl(l);
+    const T* b = bread(l);
     for (int sw = 0; sw < nsw; ++sw)
       for (int color = 0; color < 2; ++color) {
-        for (int t = tid; t < H; t += nt) wrb_cell<T, DIM>(xs + off[l], bl(l), lg, c0, cc, color, t, kinds);
+        for (int t = tid; t < H; t += nt) wrb_cell<T, DIM, K>(x, b, lg, c0, cc, color, t, kinds);
         __syncthreads();
       }
   };
   for (int l = 0; l < nlev - 1; ++l) {
     const int lg = logn - l;
     const int Cl = 1 << (DIM * lg);
-    for (int c = tid; c < Cl; c += nt) xs[off[l] + c] = T(0);
+    T* x = xl(l);
+    for (int c = tid; c < Cl; c += nt) x[c] = T(0);
     __syncthreads();
     sweeps(l, cl, nu_pre);
+    const T* b = bread(l);
+    T* bc = bl(l + 1);
     for (int t = tid; t < (Cl >> DIM); t += nt) {
       int at_c;
-      const T r = wrestrict_cell<T, DIM>(xs + off[l], bl(l), lg, c0, cl, t, kinds, &at_c);
-      bs[boff[l + 1] + at_c] = r;
+      const T r = wrestrict_cell<T, DIM, K>(x, b, lg, c0, cl, t, kinds, &at_c);
+      bc[at_c] = r;
     }
     __syncthreads();
     cl = cl * T(0.25);
@@ -366,7 +426,7 @@ __global__ void __launch_bounds__(kWallTailThreads) k_wvcycle_lds(const T* __res
     const int Cl = 1 << (DIM * (logn - l));
     if (mode == 2 && c0 == T(0)) {
       // the singular Neumann problem: the coarsest right-hand side loses its mean
-      T* b = bs + boff[l];
+      T* b = bl(l);
       T sm = T(0);
       for (int c = tid; c < Cl; c += nt) sm += b[c];
       sm = block_sum(sm, red);
@@ -374,7 +434,8 @@ __global__ void __launch_bounds__(kWallTailThreads) k_wvcycle_lds(const T* __res
       __syncthreads();
       for (int c = tid; c < Cl; c += nt) b[c] -= mean;
     }
-    for (int c = tid; c < Cl; c += nt) xs[off[l] + c] = T(0);
+    T* x = xl(l);
+    for (int c = tid; c < Cl; c += nt) x[c] = T(0);
     __syncthreads();
     sweeps(l, cl, nu_coarse);
   }
@@ -382,11 +443,31 @@ __global__ void __launch_bounds__(kWallTailThreads) k_wvcycle_lds(const T* __res
     cl = cl * T(4);
     const int lg = logn - l;
     const int Cl = 1 << (DIM * lg);
-    for (int t = tid; t < Cl; t += nt) wprolong_cell<T, DIM>(xs + off[l], xs + off[l + 1], lg, t, kinds);
+    T* x = xl(l);
+    const T* xc = xl(l + 1);
+    for (int t = tid; t < Cl; t += nt) wprolong_cell<T, DIM, K>(x, xc, lg, t, kinds);
     __syncthreads();
     sweeps(l, cl, nu_post);
   }
   for (int c = tid; c < C0; c += nt) x0[c] = xs[c];
+}
+
+template <typename T, int DIM>
+__global__ void __launch_bounds__(kWallTailThreads) k_wvcycle_lds(const T* __restrict__ bg, T* __restrict__ xg,
+                                                                  int logn, T c0, T c1, int nu_pre, int nu_post,
+                                                                  int nu_coarse, int mode, int wm) {
+  constexpr int kX = wall_pyramid<DIM>(kWallTailCells);
+  constexpr int kB = wall_pyramid<DIM>(kWallTailCells >> DIM) + 1;
+  __shared__ T xs[kX];
+  __shared__ T bs[kB];
+  __shared__ T red[kWallTailThreads / kWave];
+  const int f = blockIdx.x;
+  const int kinds = field_kinds<DIM>(mode, f, wm);
+  const int C0 = 1 << (DIM * logn);
+  with_kinds<DIM>(kinds, [&](auto kc) {
+    wvcycle_body<T, DIM, decltype(kc)::value>(bg + (int64_t)f * C0, xg + (int64_t)f * C0, xs, bs, red, logn, c0, c1,
+                                             nu_pre, nu_post, nu_coarse, mode, kinds);
+  });
 }
 
 }  // namespace
@@ -400,6 +481,8 @@ void launch_wall_vcycle(int dim, int logn, int nf, const T* b, T* x, const std::
   int lt = 0;
   while (((int64_t)1 << (dim * (logn - lt))) > kWallTailCells) ++lt;
   if ((int)wx.size() <= lt || (int)wb.size() <= lt) throw DeviceError("walls: multigrid buffers missing");
+  // the tail keeps b of its levels below the entry level in LDS: it needs at least two levels
+  if (logn - lt < 3) throw DeviceError("walls: the multigrid tail needs an entry level of n >= 8");
   const bool three = dim == 3;
   const T tc0 = (T)c0;
   T cl = (T)c1;
