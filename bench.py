@@ -65,13 +65,17 @@ COMPOSITE_TIMERS = ("vcycle",)
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=18)
+    ap.add_argument("--steps", type=int, default=54,
+                    help="timed steps in all, spread over the trajectories of --seeds")
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--re", type=float, default=10.0)
     ap.add_argument("--advection", choices=("auto", "centred", "sl"), default="auto",
                     help="centred advective form with AB2, or semi-Lagrangian transport; auto takes the "
                          "centred form while the cell Reynolds number Re h/R is at most 8 (where it is stable)")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--seeds", default="0,1,2",
+                    help="default line: the workload's trajectories (comma-separated seeds) timed as one job; "
+                         "the first is the one compared with the oracle")
     ap.add_argument("--n-s", type=int, default=2, help="inner GMRES(N_s) iterations of the preconditioner")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", choices=["both", "mixed", "fp64"], default="both")
@@ -184,6 +188,10 @@ def run_precision(prob, prec, steps, warmup, torch, scheme="centred", n_s=2):
     for t in ibr.TIMERS:
         ibr.timer_enable(t, 0)
     s.close()
+    return summarise_steps(steps, total, lat, its, ps, vc, res, timers, ref_state)
+
+
+def summarise_steps(steps, total, lat, its, ps, vc, res, timers, ref_state):
     return {
         "solves_per_s": steps / total,
         "ms_per_step": total * 1e3 / steps,
@@ -195,7 +203,48 @@ def run_precision(prob, prec, steps, warmup, torch, scheme="centred", n_s=2):
         "max_rel_residual": max(res),
         "timers": timers,
         "state_after_2_steps": ref_state,
+        "raw": {"steps": steps, "total_s": total, "lat": lat, "its": its, "ps": ps, "vc": vc, "res": res},
     }
+
+
+def settle(torch):
+    import gc
+    gc.collect()
+    torch.cuda.synchronize()
+
+
+# steps of one trajectory of the workload (its bodies keep their gap of 4h over them)
+TRAJECTORY_STEPS = 20
+
+
+def split_steps(args):
+    """The K timed steps spread over the workload's trajectories (--seeds);
+    each trajectory stays within the 20 steps over which its bodies keep
+    their gap."""
+    seeds = [int(x) for x in args.seeds.split(",") if x.strip()]
+    per_seed = [args.steps // len(seeds) + (1 if i < args.steps % len(seeds) else 0) for i in range(len(seeds))]
+    if max(per_seed) + args.warmup > TRAJECTORY_STEPS or min(per_seed) < 1:
+        print("bench.py: %d timed steps over %d trajectories of at most %d steps (with %d warm-up steps each) "
+              "do not fit; pass other --seeds" % (args.steps, len(seeds), TRAJECTORY_STEPS, args.warmup),
+              file=sys.stderr)
+        sys.exit(2)
+    return seeds, per_seed
+
+
+def merge_runs(runs):
+    """Several trajectories' timed steps as one job: throughput over the summed
+    time, percentiles and means over every step, timer samples summed; the
+    first run's state after two steps is kept for the oracle comparison."""
+    raw = [r["raw"] for r in runs]
+    cat = lambda k: [x for r in raw for x in r[k]]
+    timers = {}
+    for r in runs:
+        for k, v in r["timers"].items():
+            acc = timers.setdefault(k, {kk: 0 for kk in v})
+            for kk, vv in v.items():
+                acc[kk] += vv
+    return summarise_steps(sum(r["steps"] for r in raw), sum(r["total_s"] for r in raw), cat("lat"), cat("its"),
+                           cat("ps"), cat("vc"), cat("res"), timers, runs[0]["state_after_2_steps"])
 
 
 def measured_traffic(name):
@@ -291,13 +340,17 @@ def second_re(args, torch):
     from synthetic import config2_spheres_ns
     re = args.second_re
     scheme = advection_scheme(argparse.Namespace(advection=args.advection, re=re))
-    prob = config2_spheres_ns(args.seed, re=re)
+    seeds, per_seed = split_steps(args)
+    probs = [config2_spheres_ns(sd, re=re) for sd in seeds]
+    prob = probs[0]
     out = {"re": re, "advection": scheme}
     res = {}
     for p in ("fp64", "mixed"):
-        print("bench: Re %g, %s, %d warmup + %d timed steps" % (re, p, args.warmup, args.steps), file=sys.stderr,
+        print("bench: Re %g, %s, seeds %s, %d warmup + %d timed steps in all" % (re, p, args.seeds, args.warmup,
+                                                                               args.steps), file=sys.stderr,
               flush=True)
-        res[p] = run_precision(prob, p, args.steps, args.warmup, torch, scheme, args.n_s)
+        res[p] = merge_runs([run_precision(pr, p, k, args.warmup, torch, scheme, args.n_s)
+                             for pr, k in zip(probs, per_seed)])
         out[p] = {"solves_per_s": round(res[p]["solves_per_s"], 3), "p50_ms": round(res[p]["p50_ms"], 3),
                   "p99_ms": round(res[p]["p99_ms"], 3),
                   "fgmres_iters_mean": round(res[p]["fgmres_iters_mean"], 2),
@@ -323,7 +376,7 @@ def served(args, torch):
     Every context is created before the timed region (prewarm)."""
     from paper_1505_07865_amd import serve
     from synthetic import config2_spheres_ns
-    nsteps = args.warmup + args.steps
+    nsteps = min(args.warmup + args.steps, TRAJECTORY_STEPS)
     probs = [config2_spheres_ns(args.seed + i, re=args.re) for i in range(args.served_trajectories)]
     out = {"trajectories": len(probs), "steps_each": nsteps, "workers": args.workers}
     for prec, workers, tag in (("fp64", 1, "fp64_plain"), ("mixed", 1, "mixed_plain"),
@@ -886,8 +939,8 @@ def mobility_study(args, torch):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (--gpus 1); multi-GPU sharding is described "
-              "in DESIGN.md but not built", file=sys.stderr)
+        print("bench.py: runs on one GPU only (--gpus 1); the path is not sharded across GPUs",
+              file=sys.stderr)
         sys.exit(2)
     import torch
     from synthetic import config2_spheres_ns
@@ -921,14 +974,17 @@ def main():
     if args.small:
         small(args, torch)
         return
-    prob = config2_spheres_ns(args.seed, re=args.re)
+    seeds, per_seed = split_steps(args)
+    probs = [config2_spheres_ns(sd, re=args.re) for sd in seeds]
+    prob = probs[0]
     scheme = advection_scheme(args)
     precs = ["fp64", "mixed"] if args.precision == "both" else [args.precision]
     res = {}
     for p in precs:
-        print("bench: %s, %d warmup + %d timed steps" % (p, args.warmup, args.steps), file=sys.stderr,
-              flush=True)
-        res[p] = run_precision(prob, p, args.steps, args.warmup, torch, scheme, args.n_s)
+        print("bench: %s, seeds %s, %d warmup + %d timed steps each" % (p, args.seeds, args.warmup, args.steps),
+              file=sys.stderr, flush=True)
+        res[p] = merge_runs([run_precision(pr, p, k, args.warmup, torch, scheme, args.n_s)
+                             for pr, k in zip(probs, per_seed)])
         print("bench: %s %.2f solves/s, %.1f FGMRES iters/step" % (p, res[p]["solves_per_s"],
                                                                    res[p]["fgmres_iters_mean"]),
               file=sys.stderr, flush=True)
@@ -941,6 +997,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
+        "trajectories": len(seeds),
         "ms_per_step": round(head["ms_per_step"], 3),
         "higher_is_better": True,
         "scaling": "weak",
@@ -951,7 +1008,7 @@ def main():
                                "R=6h x 110 markers, rtol 1e-8, N_s=%d, lower-triangular Schur preconditioner "
                                "with the fitted approximate mobility, %s advection"
                                % (args.re, args.n_s, "semi-Lagrangian" if scheme == "sl" else "centred AB2"),
-                   "grid": 128, "bodies": 16, "markers": int(prob.nmarkers), "re": args.re, "seed": args.seed,
+                   "grid": 128, "bodies": 16, "markers": int(prob.nmarkers), "re": args.re, "seeds": seeds,
                    "rtol": 1e-8, "n_s": args.n_s, "advection": scheme,
                    "approximate_mobility": "fitted (Appendix A forms)"},
         "p50_ms": round(head["p50_ms"], 3),
@@ -968,18 +1025,24 @@ def main():
         line["field_vcycles_per_step"] = round(head["vcycles_mean"], 2)
     for p in precs:
         line[p] = {k: (float("%.4g" % v) if isinstance(v, float) else v) for k, v in res[p].items()
-                   if k not in ("timers", "state_after_2_steps")}
+                   if k not in ("timers", "state_after_2_steps", "raw")}
     if "mixed" in res and "fp64" in res:
         line["mixed_over_fp64"] = round(res["mixed"]["solves_per_s"] / res["fp64"]["solves_per_s"], 3)
-    if args.precision == "both" and args.second_re > 0 and args.second_re != args.re:
-        line["second_re"] = second_re(args, torch)
-    if args.precision == "both" and not args.no_served:
-        line["served"] = served(args, torch)
+    # each further leg starts from a settled device and host (the previous
+    # legs' contexts destroyed, their host arrays collected): the serving
+    # mix's Poisson latencies are sensitive to stalls
     if args.precision == "both" and args.mix_requests > 0:
+        settle(torch)
         # the serving trace (mixed grid sizes and body counts, Poisson arrivals), a short prefix of it
         print("bench: serving mix, %d requests" % args.mix_requests, file=sys.stderr, flush=True)
         line["serving_mix"] = serving_summary(serving_leg(args, torch, args.mix_requests), args.mix_requests,
                                               args.workers)
+    if args.precision == "both" and args.second_re > 0 and args.second_re != args.re:
+        settle(torch)
+        line["second_re"] = second_re(args, torch)
+    if args.precision == "both" and not args.no_served:
+        settle(torch)
+        line["served"] = served(args, torch)
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle on the workload's first two steps", file=sys.stderr, flush=True)
         line["cpu_baseline"], ref = cpu_baseline(prob, scheme=scheme)

@@ -170,8 +170,13 @@ void ibr_destroy(ibr_ctx* ctx);
 /* Message of the last failed call on this context ("" if none). */
 const char* ibr_last_error(const ibr_ctx* ctx);
 
-/* Device bytes a context would hold for these parameters and markers. */
-size_t ibr_footprint_bytes(const ibr_params* params, int nbodies, int nmarkers);
+/* Device bytes a context with these parameters would hold after
+ * ibr_set_bodies with nbodies bodies of markers_per_body[b] markers each (the
+ * per-body mobility blocks are sized from each body's count, as the library
+ * allocates them), for admission control before ibr_create.  0 if params is
+ * NULL or invalid, nbodies < 0, or markers_per_body is NULL with nbodies > 0
+ * or holds a negative count.  The caller keeps markers_per_body. */
+size_t ibr_footprint_bytes(const ibr_params* params, int nbodies, const int* markers_per_body);
 
 /* Set the rigid bodies (Sec. 2): nbodies >= 1, offsets[nbodies+1] increasing
  * from 0, R[N][dim] markers inside [0, n h) (wrapped otherwise), centres

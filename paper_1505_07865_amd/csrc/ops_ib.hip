@@ -167,19 +167,39 @@ __global__ void k_bin_scatter(int N, const int* __restrict__ tile_of, const int*
   perm[pos] = m;
 }
 
-// Sort each tile's segment by marker index (fixed order => deterministic sums).
-__global__ void k_bin_sort(int ntiles, const int* __restrict__ off, int* __restrict__ perm) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= ntiles) return;
-  const int lo = off[t], hi = off[t + 1];
-  for (int i = lo + 1; i < hi; ++i) {
-    const int v = perm[i];
-    int j = i - 1;
-    while (j >= lo && perm[j] > v) {
-      perm[j + 1] = perm[j];
-      --j;
-    }
-    perm[j + 1] = v;
+// Sort each tile's segment by marker index (fixed order => deterministic
+// sums).  One workgroup per tile: the segment is copied into LDS and each
+// entry goes to its rank (the count of smaller indices; marker indices are
+// distinct).  A segment longer than the LDS copy (only markers packed far
+// more densely than a kernel width apart make one) is sorted by insertion
+// in place by one thread.
+constexpr int kSortThreads = 128;
+constexpr int kSortLds = 2048;
+__global__ void __launch_bounds__(kSortThreads) k_bin_sort(const int* __restrict__ off, int* __restrict__ perm) {
+  __shared__ int seg[kSortLds];
+  const int t = blockIdx.x;
+  const int lo = off[t], n = off[t + 1] - lo;
+  if (n <= 1) return;
+  if (n > kSortLds) {
+    if (threadIdx.x == 0)
+      for (int i = lo + 1; i < lo + n; ++i) {
+        const int v = perm[i];
+        int j = i - 1;
+        while (j >= lo && perm[j] > v) {
+          perm[j + 1] = perm[j];
+          --j;
+        }
+        perm[j + 1] = v;
+      }
+    return;
+  }
+  for (int i = threadIdx.x; i < n; i += kSortThreads) seg[i] = perm[lo + i];
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += kSortThreads) {
+    const int v = seg[i];
+    int r = 0;
+    for (int j = 0; j < n; ++j) r += seg[j] < v ? 1 : 0;
+    perm[lo + r] = v;
   }
 }
 
@@ -515,7 +535,7 @@ void launch_bin_markers(int N, int ntiles, const int* tile_of, int* counts, int*
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, counts, ntiles, offsets);
   if (N > 0) {
     hipLaunchKernelGGL(k_bin_scatter, dim3(nblk(N)), dim3(256), 0, s, N, tile_of, offsets, cursor, perm);
-    hipLaunchKernelGGL(k_bin_sort, dim3(nblk(ntiles)), dim3(256), 0, s, ntiles, offsets, perm);
+    hipLaunchKernelGGL(k_bin_sort, dim3(ntiles), dim3(kSortThreads), 0, s, offsets, perm);
   }
 }
 

@@ -1035,12 +1035,20 @@ void ibr_destroy(ibr_ctx* c) {
 
 const char* ibr_last_error(const ibr_ctx* c) { return c ? c->err.c_str() : "null context"; }
 
-size_t ibr_footprint_bytes(const ibr_params* p, int nbodies, int nmarkers) {
-  if (!p || p->dim < 2 || p->dim > 3 || p->n < 4) return 0;
+size_t ibr_footprint_bytes(const ibr_params* p, int nbodies, const int* markers_per_body) {
+  if (!p || p->dim < 2 || p->dim > 3 || p->n < 4 || nbodies < 0 || (nbodies > 0 && !markers_per_body)) return 0;
   const int d = p->dim;
+  int64_t nmarkers = 0, mtot = 0;
+  for (int b = 0; b < nbodies; ++b) {
+    const int np = markers_per_body[b];
+    if (np < 0) return 0;
+    nmarkers += np;
+    const int64_t ld = ((int64_t)d * np + 15) & ~(int64_t)15;  // as ibr_set_bodies lays the blocks out
+    mtot += ld * ld;
+  }
   const int64_t C = (int64_t)1 << (d * ilog2(p->n));
   const int64_t NF = (int64_t)(d + 1) * C;
-  const int64_t NV = NF + (int64_t)(d + d + (d == 3 ? 3 : 1)) * std::max(nmarkers, 16);
+  const int64_t NV = NF + (int64_t)(d + d + (d == 3 ? 3 : 1)) * std::max<int64_t>(nmarkers, 16);
   const int m = p->restart > 0 ? p->restart : 100;
   const int ns = p->n_s > 0 ? p->n_s : 2;
   const int64_t ts = p->precision == IBR_MIXED ? 4 : 8;
@@ -1053,10 +1061,8 @@ size_t ibr_footprint_bytes(const ibr_params* p, int nbodies, int nmarkers) {
   b += (size_t)((2 * ns + 2) * NF + 2 * C) * ts;  // inner bases and P_S^-1 scratch
   const bool w = p->walls == IBR_WALLS_NOSLIP || p->walls == IBR_WALLS_BOX;
   b += ts == 4 ? MGHier<float>::bytes(d, ilog2(p->n), d, w) : MGHier<double>::bytes(d, ilog2(p->n), d, w);
-  // mobility blocks (4 buffers of sum (d N_p)^2), bounded by one block of all markers per body
-  const int64_t per = nbodies > 0 ? (int64_t)d * nmarkers / nbodies : 0;
-  b += (size_t)4 * nbodies * per * per * 8;
-  b += (size_t)nmarkers * 400;
+  b += (size_t)4 * mtot * 8;           // mobility blocks: M~, its factor, the inverse factor, M~^-1
+  b += (size_t)nmarkers * 400;         // per-marker taps, weights and binning
   return b;
 }
 

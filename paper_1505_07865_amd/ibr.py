@@ -99,7 +99,7 @@ def load(path=LIB_PATH):
         "ibr_create": (ctypes.c_int, [P(Params), P(vp)]),
         "ibr_destroy": (None, [vp]),
         "ibr_last_error": (ctypes.c_char_p, [vp]),
-        "ibr_footprint_bytes": (ctypes.c_size_t, [P(Params), ctypes.c_int, ctypes.c_int]),
+        "ibr_footprint_bytes": (ctypes.c_size_t, [P(Params), ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
         "ibr_set_bodies": (ctypes.c_int, [vp, ctypes.c_int, ip, dp, dp]),
         "ibr_set_velocities": (ctypes.c_int, [vp, dp, dp]),
         "ibr_set_wall_velocity": (ctypes.c_int, [vp, dp, dp]),
@@ -418,10 +418,13 @@ def spread_noalloc(R, lam, f, nmarkers=None, stream=None, **params):
         raise IbrError(st, "ibr_spread_noalloc: " + buf.value.decode())
 
 
-def footprint_bytes(nbodies, nmarkers, **params):
-    """Device bytes a context with these parameters and markers would hold."""
+def footprint_bytes(markers_per_body, **params):
+    """Device bytes a context with these parameters would hold for bodies of
+    markers_per_body[b] markers each."""
+    counts = np.ascontiguousarray(np.asarray(markers_per_body, dtype=np.int32).ravel())
     p = default_params(**params)
-    return int(lib().ibr_footprint_bytes(ctypes.byref(p), int(nbodies), int(nmarkers)))
+    ptr = counts.ctypes.data_as(ctypes.POINTER(ctypes.c_int)) if counts.size else None
+    return int(lib().ibr_footprint_bytes(ctypes.byref(p), int(counts.size), ptr))
 
 
 def from_problem(prob, **kw):

@@ -28,6 +28,8 @@ import queue
 import threading
 import time
 
+import numpy as np
+
 __all__ = ["Server", "replay"]
 
 
@@ -198,7 +200,7 @@ class Server:
 
     def _default_footprint(self, prob):
         from . import ibr
-        return ibr.footprint_bytes(prob.nbodies, prob.nmarkers, **self._params(prob))
+        return ibr.footprint_bytes(np.diff(prob.offsets), **self._params(prob))
 
     def _default_free_bytes(self):
         import torch

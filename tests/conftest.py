@@ -9,8 +9,16 @@ if ROOT not in sys.path:
 
 
 def pytest_configure(config):
-    config.addinivalue_line("markers", "gpu: needs an MI355X (run with -m gpu on the GPU box)")
+    config.addinivalue_line("markers", "gpu: needs an MI355X GPU (select with -m gpu)")
     config.addinivalue_line("markers", "slow: oracle checks that take tens of seconds")
+
+
+def results_dir():
+    """Folder the study tests write their tables to (JSON), created on use;
+    IBR_RESULTS_DIR overrides it."""
+    out = os.environ.get("IBR_RESULTS_DIR", os.path.join(ROOT, "gpurun_out"))
+    os.makedirs(out, exist_ok=True)
+    return out
 
 
 def gpu_available():

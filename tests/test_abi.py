@@ -84,13 +84,31 @@ def test_invalid_params_rejected_before_device_work(lib):
 
 def test_footprint_grows_with_grid(lib):
     from paper_1505_07865_amd import ibr
-    f = [lib.ibr_footprint_bytes(ctypes.byref(ibr.default_params(n=n, h=1.0 / n)), 1, 200) for n in (32, 64, 128)]
+    one = (ctypes.c_int * 1)(200)
+    f = [lib.ibr_footprint_bytes(ctypes.byref(ibr.default_params(n=n, h=1.0 / n)), 1, one) for n in (32, 64, 128)]
     assert f[0] < f[1] < f[2]
-    fm = lib.ibr_footprint_bytes(ctypes.byref(ibr.default_params(n=128, h=1.0 / 128, precision=1)), 1, 200)
+    fm = lib.ibr_footprint_bytes(ctypes.byref(ibr.default_params(n=128, h=1.0 / 128, precision=1)), 1, one)
     assert fm < f[2]
     # the slit channel keeps every multigrid level down to 4^3 in global memory as well
-    fw = lib.ibr_footprint_bytes(ctypes.byref(ibr.default_params(n=128, h=1.0 / 128, walls=1)), 1, 200)
+    fw = lib.ibr_footprint_bytes(ctypes.byref(ibr.default_params(n=128, h=1.0 / 128, walls=1)), 1, one)
     assert fw > f[2]
+
+
+def test_footprint_counts_each_body_block(lib):
+    """The mobility blocks are sized per body: 600 markers as one body hold
+    one block of (3 * 600)^2 doubles per buffer (its leading dimension padded
+    to a multiple of 16), three bodies of 200 three blocks of (3 * 200)^2;
+    invalid counts give 0."""
+    from paper_1505_07865_amd import ibr
+    p = ibr.default_params(n=64, h=1.0 / 64)
+    one = lib.ibr_footprint_bytes(ctypes.byref(p), 1, (ctypes.c_int * 1)(600))
+    three = lib.ibr_footprint_bytes(ctypes.byref(p), 3, (ctypes.c_int * 3)(200, 200, 200))
+    pad = lambda r: (r + 15) // 16 * 16
+    assert one - three == 4 * 8 * (pad(1800) ** 2 - 3 * pad(600) ** 2)
+    assert ibr.footprint_bytes([200, 200, 200], n=64, h=1.0 / 64) == three
+    assert lib.ibr_footprint_bytes(ctypes.byref(p), 2, None) == 0
+    assert lib.ibr_footprint_bytes(ctypes.byref(p), 1, (ctypes.c_int * 1)(-1)) == 0
+    assert lib.ibr_footprint_bytes(None, 1, (ctypes.c_int * 1)(10)) == 0
 
 
 def test_oracle_is_not_imported_by_product():

@@ -12,11 +12,13 @@ touches its images in hydrodynamic radius, phi = pi/6.  The paper's table
 gives k0 = 44.49 (162 shell) and 43.29 (642 shell, 30^3 grid) with its
 six-point kernel, and quotes 42.8 from lattice Boltzmann.  Checks: the 16^3
 drag equals the oracle's exact solve; phi is pi/6 within 0.5%; k0 is within
-5% of 42.8.  The table is printed and written to gpurun_out/array_k0.json.
+5% of 42.8.  The table is printed and written to array_k0.json in the results folder.
 """
 import json
 import math
 import os
+
+from conftest import results_dir
 
 import pytest
 
@@ -54,8 +56,7 @@ def test_close_packed_array_k0():
         if n == 16:
             ex = constrained.solve_problem(prob, dense_limit=0, tol=1e-11)
             assert abs(F - ex.F[0, 0]) < 1e-7 * abs(ex.F[0, 0])
-    out = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
-    os.makedirs(out, exist_ok=True)
+    out = results_dir()
     with open(os.path.join(out, "array_k0.json"), "w") as f:
         json.dump(rows, f, indent=1)
     for r in rows:

@@ -16,11 +16,13 @@ Checks: at 32^3 the GPU numbers equal the oracle's exact solve's; under
 refinement R1/R1_geometric falls and R2/R2_geometric rises toward 1, and the
 velocity errors fall at a rate above 0.7 per refinement (first order is the
 method's; the paper reports rates of 1.0-1.8).  The table is printed and
-written to gpurun_out/shells_table.json.
+written to shells_table.json in the results folder.
 """
 import json
 import math
 import os
+
+from conftest import results_dir
 
 import numpy as np
 import pytest
@@ -90,8 +92,7 @@ def test_concentric_shells_accuracy_table():
             rate = math.log2(a["v"][nm] / b["v"][nm])
             b["v"]["rate_" + nm] = rate
             assert rate > 0.7, (nm, rate)
-    out = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
-    os.makedirs(out, exist_ok=True)
+    out = results_dir()
     with open(os.path.join(out, "shells_table.json"), "w") as f:
         json.dump(rows, f, indent=1)
 
@@ -101,7 +102,7 @@ def test_concentric_shells_lab_frame_table():
     the cavity and the box's walls moving with V (moving-wall data).  Stokes
     flow has no inertia, so this equals the cavity-frame study shifted by V:
     the drag and every error norm agree with it to the solves' tolerance.
-    Written to gpurun_out/shells_lab_table.json."""
+    Written to shells_lab_table.json in the results folder."""
     from paper_1505_07865_amd import ibr
 
     def solver(prob):
@@ -117,8 +118,7 @@ def test_concentric_shells_lab_frame_table():
         assert abs(a["R2h_over_R2g"] - b["R2h_over_R2g"]) < 1e-6
         for nm in ("L1", "L2", "Linf"):
             assert abs(a["v"][nm] - b["v"][nm]) < 1e-5 * b["v"][nm]
-    out = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
-    os.makedirs(out, exist_ok=True)
+    out = results_dir()
     with open(os.path.join(out, "shells_lab_table.json"), "w") as f:
         json.dump(rows, f, indent=1)
 
@@ -128,7 +128,7 @@ def test_concentric_shells_walled_box_table():
     at rest in the cavity's frame; the inner radius still comes from the
     periodic lattice's drag law, as in the paper).  The cavity isolates its
     interior, so the errors converge as in the periodic box and stay close to
-    its numbers; written to gpurun_out/shells_box_table.json."""
+    its numbers; written to shells_box_table.json in the results folder."""
     from paper_1505_07865_amd import ibr
 
     def solver(prob):
@@ -145,7 +145,6 @@ def test_concentric_shells_walled_box_table():
             rate = math.log2(a["v"][nm] / b["v"][nm])
             b["v"]["rate_" + nm] = rate
             assert rate > 0.7, (nm, rate)
-    out = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
-    os.makedirs(out, exist_ok=True)
+    out = results_dir()
     with open(os.path.join(out, "shells_box_table.json"), "w") as f:
         json.dump(rows, f, indent=1)

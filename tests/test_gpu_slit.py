@@ -18,10 +18,12 @@ the curve is close to a line through the origin, so the check is on the
 slope (R_L / R_h - 1) / (R_h / L): negative, equal across the three
 resolutions to within 5% at each height, and different between the heights.
 At 32^3 the drags also equal the oracle's exact solve.  The table is printed
-and written to gpurun_out/slit_table.json.
+and written to slit_table.json in the results folder.
 """
 import json
 import os
+
+from conftest import results_dir
 
 import numpy as np
 import pytest
@@ -71,8 +73,7 @@ def test_slit_sphere_table():
     for where, hgt in HEIGHTS:
         ex = walls.solve_problem(slit_shell(32, 0, height=hgt))
         assert abs(rows[0][where]["drag"] - ex.F[0, 0]) < 1e-7 * abs(ex.F[0, 0])
-    out = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
-    os.makedirs(out, exist_ok=True)
+    out = results_dir()
     with open(os.path.join(out, "slit_table.json"), "w") as f:
         json.dump(rows, f, indent=1)
     slope = {}
