@@ -31,6 +31,14 @@ __device__ inline int64_t xcd_block(int64_t nblocks) {
   return (b % kXcds) * per + b / kXcds;
 }
 
+// Orders one wavefront's LDS accesses across its lanes: every access before
+// it is complete and visible to the wavefront's other lanes before any after it.
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <typename T>
 __device__ inline T wave_sum(T v) {
   for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);

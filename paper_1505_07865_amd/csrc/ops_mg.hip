@@ -392,14 +392,6 @@ __global__ void __launch_bounds__(256) k_prolong_add(T* __restrict__ x, const T*
 }
 
 // ---------------------------------------------------------------- one-workgroup tail
-// Orders one wavefront's LDS accesses across its lanes: every access before
-// it is complete and visible to the wavefront's other lanes before any after it.
-__device__ inline void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // Tail levels of at most this many cells run in wavefront 0 alone (at most
 // two items per lane and phase, 3D 8^3 and 2D 32^2 down): each phase then
 // ends with a wavefront-level ordering instead of a workgroup barrier, whose

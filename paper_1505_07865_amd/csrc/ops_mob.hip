@@ -382,6 +382,8 @@ __global__ void __launch_bounds__(256) k_chol_diag(const int* __restrict__ off, 
                                                    double f0, double pivot_tol, int* __restrict__ fail) {
   __shared__ double D[kBlk * kSld];
   __shared__ double X[kBlk * kSld];
+  __shared__ double rdiag[kBlk];  // 1 / L_jj: the substitutions multiply instead of dividing
+  __shared__ double colbuf[2][16];  // the pivot column of the register factor, double-buffered
   __shared__ int bad_s;
   const int b = blockIdx.x;
   if (!active[b]) return;
@@ -399,7 +401,10 @@ __global__ void __launch_bounds__(256) k_chol_diag(const int* __restrict__ off, 
   __syncthreads();
   for (int q = 0; q < nt; ++q) {
     const int q0 = 16 * q;
-    // diagonal tile in registers of wavefront 0: lane r (mod 16) holds row r
+    // diagonal tile in registers of wavefront 0: lane r (mod 16) holds row r.
+    // Step jj broadcasts column jj through LDS (one write, then independent
+    // reads of all its entries; lane-to-lane shuffles here were serialised,
+    // about 800 cycles per step)
     if (wv == 0) {
       double row[16];
 #pragma unroll
@@ -407,14 +412,22 @@ __global__ void __launch_bounds__(256) k_chol_diag(const int* __restrict__ off, 
       bool bad = false;
 #pragma unroll
       for (int jj = 0; jj < 16; ++jj) {
-        const double d = __shfl(row[jj], jj, 16);
+        double* cb = colbuf[jj & 1];
+        if (lane < 16) cb[lane] = row[jj];
+        wave_sync();
+        double cv[16];
+#pragma unroll
+        for (int c = jj; c < 16; ++c) cv[c] = cb[c];
+        const double d = cv[jj];
         bad = bad || !(d > pivot_tol * f0);
         const double sd = sqrt(d > 0.0 ? d : 1.0);
+        const double rs = 1.0 / sd;
+        if (lane == jj) rdiag[q0 + jj] = rs;
         if (r16 == jj) row[jj] = sd;
-        else if (r16 > jj) row[jj] = row[jj] / sd;
+        else if (r16 > jj) row[jj] = row[jj] * rs;
 #pragma unroll
         for (int c = jj + 1; c < 16; ++c) {
-          const double lc = __shfl(row[jj], c, 16);
+          const double lc = cv[c] * rs;
           if (r16 >= c) row[c] -= row[jj] * lc;
         }
       }
@@ -437,7 +450,7 @@ __global__ void __launch_bounds__(256) k_chol_diag(const int* __restrict__ off, 
           double t = x[c];
 #pragma unroll
           for (int k = 0; k < c; ++k) t -= x[k] * D[(q0 + c) * kSld + q0 + k];
-          x[c] = t / D[(q0 + c) * kSld + q0 + c];
+          x[c] = t * rdiag[q0 + c];
         }
 #pragma unroll
         for (int c = 0; c < 16; ++c) Lr[c] = x[c];
@@ -467,7 +480,7 @@ __global__ void __launch_bounds__(256) k_chol_diag(const int* __restrict__ off, 
         double v = i == c ? 1.0 : 0.0;
 #pragma unroll
         for (int k = 0; k < i; ++k) v -= D[(q0 + i) * kSld + q0 + k] * col[k];
-        col[i] = i < c ? 0.0 : v / D[(q0 + i) * kSld + q0 + i];
+        col[i] = i < c ? 0.0 : v * rdiag[q0 + i];
       }
 #pragma unroll
       for (int i = 0; i < 16; ++i) X[(q0 + i) * kSld + q0 + c] = col[i];
