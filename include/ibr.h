@@ -173,8 +173,11 @@ const char* ibr_last_error(const ibr_ctx* ctx);
 /* Device bytes a context with these parameters would hold after
  * ibr_set_bodies with nbodies bodies of markers_per_body[b] markers each (the
  * per-body mobility blocks are sized from each body's count, as the library
- * allocates them), for admission control before ibr_create.  0 if params is
- * NULL or invalid, nbodies < 0, or markers_per_body is NULL with nbodies > 0
+ * allocates them, plus an allowance for the allocator's rounding), for
+ * admission control before ibr_create.  Not included: the one-time device
+ * memory of the HIP runtime and the library's code, taken by the process's
+ * first context and kept until the process ends (about 150 MiB).  0 if params
+ * is NULL or invalid, nbodies < 0, or markers_per_body is NULL with nbodies > 0
  * or holds a negative count.  The caller keeps markers_per_body. */
 size_t ibr_footprint_bytes(const ibr_params* params, int nbodies, const int* markers_per_body);
 

@@ -1062,7 +1062,8 @@ size_t ibr_footprint_bytes(const ibr_params* p, int nbodies, const int* markers_
   const bool w = p->walls == IBR_WALLS_NOSLIP || p->walls == IBR_WALLS_BOX;
   b += ts == 4 ? MGHier<float>::bytes(d, ilog2(p->n), d, w) : MGHier<double>::bytes(d, ilog2(p->n), d, w);
   b += (size_t)4 * mtot * 8;           // mobility blocks: M~, its factor, the inverse factor, M~^-1
-  b += (size_t)nmarkers * 400;         // per-marker taps, weights and binning
+  b += (size_t)nmarkers * 420;         // per-marker positions, taps, weights, binning, forces
+  b += (size_t)16 << 20;               // the allocator's rounding of the context's ~80 buffers
   return b;
 }
 
