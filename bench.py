@@ -74,8 +74,9 @@ def parse():
                          "centred form while the cell Reynolds number Re h/R is at most 8 (where it is stable)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--seeds", default="0,1,2",
-                    help="default line: the workload's trajectories (comma-separated seeds) timed as one job; "
-                         "the first is the one compared with the oracle")
+                    help="default line: the workload's trajectories (comma-separated seeds) timed as one job, "
+                         "extended by the next seeds when --steps needs more; the first is the one compared "
+                         "with the oracle")
     ap.add_argument("--n-s", type=int, default=2, help="inner GMRES(N_s) iterations of the preconditioner")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", choices=["both", "mixed", "fp64"], default="both")
@@ -222,12 +223,18 @@ def split_steps(args):
     each trajectory stays within the 20 steps over which its bodies keep
     their gap."""
     seeds = [int(x) for x in args.seeds.split(",") if x.strip()]
-    per_seed = [args.steps // len(seeds) + (1 if i < args.steps % len(seeds) else 0) for i in range(len(seeds))]
-    if max(per_seed) + args.warmup > TRAJECTORY_STEPS or min(per_seed) < 1:
-        print("bench.py: %d timed steps over %d trajectories of at most %d steps (with %d warm-up steps each) "
-              "do not fit; pass other --seeds" % (args.steps, len(seeds), TRAJECTORY_STEPS, args.warmup),
-              file=sys.stderr)
+    room = TRAJECTORY_STEPS - args.warmup
+    if args.steps < 1 or room < 1 or not seeds:
+        print("bench.py: need --steps >= 1, --warmup < %d and at least one seed" % TRAJECTORY_STEPS, file=sys.stderr)
         sys.exit(2)
+    # more trajectories (the next seeds) when K steps do not fit in the given ones
+    while len(seeds) * room < args.steps:
+        seeds.append(max(seeds) + 1)
+    # the fewest of them that hold K steps, K spread evenly
+    n = min(len(seeds), args.steps)
+    n = max(n, -(-args.steps // room))
+    seeds = seeds[:n]
+    per_seed = [args.steps // n + (1 if i < args.steps % n else 0) for i in range(n)]
     return seeds, per_seed
 
 
