@@ -144,7 +144,8 @@ struct ibr_ctx {
   // these means removed, so <v> = 0 holds in fp64 whatever Z's precision
   double* zmean = nullptr;
   int* flag = nullptr;
-  int part_blocks = 0;
+  int part_blocks = 0;  // blocks of the vector reductions' partial sums
+  int mean_blocks = 0;  // blocks of the per-field means' partial sums
   double* hres = nullptr;  // pinned
 
   // inner (precision T)
@@ -246,7 +247,7 @@ void ps_inv(ibr_ctx* c, const T* in, T* out) {
   mg.vcycle(d, g, v, c->c0, c->ch2, c->p.mg_pre, c->p.mg_post, c->p.mg_coarse, s, wv);
   const double* vmean = nullptr;
   if (c->vnull) {
-    launch_field_means<T>(v, d, C, c->mpart, 256, c->vmean, s);
+    launch_field_means<T>(v, d, C, c->mpart, c->mean_blocks, c->vmean, s);
     vmean = c->vmean;
   }
   launch_div_q<T>(d, c->logn, v, hp, q, c->inv_h, s, true);
@@ -359,7 +360,7 @@ void iteration_body(ibr_ctx* c, int k) {
   // means taken in fp64 from the stored (fp32 in mixed precision) values.
   const double* zm = nullptr;
   if (c->vnull) {
-    launch_field_means<TZ>(zk, c->dim, c->C, c->mpart, 256, c->zmean + 4 * k, c->stream);
+    launch_field_means<TZ>(zk, c->dim, c->C, c->mpart, c->mean_blocks, c->zmean + 4 * k, c->stream);
     zm = c->zmean + 4 * k;
   }
   apply_K<TZ>(c, zk, w, zm);
@@ -854,7 +855,11 @@ void ibr_ctx::alloc_grid() {
   resid = track<double>(1);
   beta = track<double>(1);
   hc2 = track<double>(m + 2);
-  part_blocks = 1024;
+  // partial-sum blocks of the reductions, from the vector length: enough to
+  // stream a 128^3 state at full bandwidth, few for small grids, whose
+  // finishing kernels then sum few partials (all reductions are grid-stride)
+  part_blocks = (int)std::min<int64_t>(1024, std::max<int64_t>(8, (NF + 2047) / 2048));
+  mean_blocks = (int)std::min<int64_t>(256, std::max<int64_t>(1, (C + 4095) / 4096));
   part = track<double>((int64_t)(2 * m + 8) * part_blocks);
   part2 = track<double>((int64_t)(m + 3) * part_blocks);
   G = track<double>(2 * m + 8);
@@ -1268,12 +1273,12 @@ void set_rhs_impl(ibr_ctx* c, const double* gh, const double* hp, hipMemcpyKind 
   else
     launch_fill<double>(c->Bs + (int64_t)d * c->C, c->C, 0.0, s);
   // consistency: <h> = 0 always, <g> = 0 for periodic steady Stokes (Sec. 3.4)
-  launch_field_means<double>(c->Bs + (int64_t)d * c->C, 1, c->C, c->mpart, 256, c->vmean, s);
+  launch_field_means<double>(c->Bs + (int64_t)d * c->C, 1, c->C, c->mpart, c->mean_blocks, c->vmean, s);
   launch_sub_field_mean<double>(c->Bs + (int64_t)d * c->C, 1, c->C, c->vmean, s);
   // with walls the normal components' wall faces are not unknowns: no momentum there
   if (c->walls) launch_zero_wall_faces(d, c->logn, c->Bs, c->wm, s);
   if (c->vnull) {
-    launch_field_means<double>(c->Bs, d, c->C, c->mpart, 256, c->vmean, s);
+    launch_field_means<double>(c->Bs, d, c->C, c->mpart, c->mean_blocks, c->vmean, s);
     launch_sub_field_mean<double>(c->Bs, d, c->C, c->vmean, s);
   }
   sync(c);
@@ -1286,7 +1291,7 @@ void get_solution_impl(ibr_ctx* c, double* u, double* pr, double* lambda, double
   hipStream_t s = c->stream;
   const int d = c->dim;
   double* pdev = c->Xs + (int64_t)d * c->C;
-  launch_field_means<double>(pdev, 1, c->C, c->mpart, 256, c->vmean, s);
+  launch_field_means<double>(pdev, 1, c->C, c->mpart, c->mean_blocks, c->vmean, s);
   launch_sub_field_mean<double>(pdev, 1, c->C, c->vmean, s);
   if (u) {
     IBR_HIP(hipMemcpyAsync(u, c->Xs, (size_t)d * c->C * sizeof(double), kind, s));
@@ -1659,7 +1664,7 @@ ibr_status ibr_vcycle(ibr_ctx* c, double c0, double c1, int nf, const double* b,
       launch_to_split<double, float>(c->dim, c->logn, bd, bf, nf, s);
       c->mg32.vcycle(nf, bf, xf, c0, c1, c->p.mg_pre, c->p.mg_post, c->p.mg_coarse, s, mode);
       if (singular) {
-        launch_field_means<float>(xf, nf, c->C, c->mpart, 256, c->vmean, s);
+        launch_field_means<float>(xf, nf, c->C, c->mpart, c->mean_blocks, c->vmean, s);
         launch_sub_field_mean<float>(xf, nf, c->C, c->vmean, s);
       }
       launch_from_split<float, double>(c->dim, c->logn, xf, xd, nf, s);
@@ -1669,7 +1674,7 @@ ibr_status ibr_vcycle(ibr_ctx* c, double c0, double c1, int nf, const double* b,
       launch_to_split<double, double>(c->dim, c->logn, bd, bs, nf, s);
       c->mg64.vcycle(nf, bs, xs, c0, c1, c->p.mg_pre, c->p.mg_post, c->p.mg_coarse, s, mode);
       if (singular) {
-        launch_field_means<double>(xs, nf, c->C, c->mpart, 256, c->vmean, s);
+        launch_field_means<double>(xs, nf, c->C, c->mpart, c->mean_blocks, c->vmean, s);
         launch_sub_field_mean<double>(xs, nf, c->C, c->vmean, s);
       }
       launch_from_split<double, double>(c->dim, c->logn, xs, xd, nf, s);
