@@ -855,11 +855,13 @@ void ibr_ctx::alloc_grid() {
   resid = track<double>(1);
   beta = track<double>(1);
   hc2 = track<double>(m + 2);
-  // partial-sum blocks of the reductions, from the vector length: enough to
-  // stream a 128^3 state at full bandwidth, few for small grids, whose
-  // finishing kernels then sum few partials (all reductions are grid-stride)
-  part_blocks = (int)std::min<int64_t>(1024, std::max<int64_t>(8, (NF + 2047) / 2048));
-  mean_blocks = (int)std::min<int64_t>(256, std::max<int64_t>(1, (C + 4095) / 4096));
+  // partial-sum blocks of the reductions, from the vector length: one
+  // element per thread at least, up to the 1024 blocks that stream a large
+  // state at full bandwidth (the update pass shares this grid, so fewer
+  // blocks on mid-size grids slowed it); small grids' finishing kernels
+  // then sum few partials (all reductions are grid-stride)
+  part_blocks = (int)std::min<int64_t>(1024, std::max<int64_t>(8, (NF + 255) / 256));
+  mean_blocks = (int)std::min<int64_t>(256, std::max<int64_t>(1, (C + 1023) / 1024));
   part = track<double>((int64_t)(2 * m + 8) * part_blocks);
   part2 = track<double>((int64_t)(m + 3) * part_blocks);
   G = track<double>(2 * m + 8);
