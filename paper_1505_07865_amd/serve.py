@@ -14,10 +14,15 @@ and no request pays for allocating or tearing down a context.
 
 Admission: contexts are created under one server-wide lock.  A new context
 is admitted when its device footprint (``ibr_footprint_bytes``) fits in the
-free device memory minus a reserve; otherwise the least recently used idle
-context of any worker is closed first, and when every remaining context is
-in use the request waits until a worker releases one.  Only a request that
-does not fit with no context left on the device fails, with MemoryError.
+free device memory minus a reserve and minus what admitted contexts have yet
+to allocate; otherwise the least recently used idle context of any worker is
+closed first, and when every remaining context is in use the request waits
+until a worker releases one.  Only a request that does not fit with no
+context left on the device fails, with MemoryError.  A context's body blocks
+are allocated when its first request sets the bodies, outside the lock: until
+then the part of its footprint that creation did not take from the free
+memory stays counted as pending, so that concurrent admissions cannot spend
+it twice.
 
 Every steady solve starts from a zero initial guess and every trajectory from
 a fluid at rest, so a request's result does not depend on what the context
@@ -57,7 +62,7 @@ class _Worker(threading.Thread):
                 srv._busy.add(ck)
                 return srv._lru[ck]
             need = srv.footprint(prob)
-            while srv.free_bytes() - srv.reserve_bytes < need:
+            while srv.free_bytes() - srv.reserve_bytes - sum(srv._pending.values()) < need:
                 victim = next((k for k in srv._lru if k not in srv._busy), None)
                 if victim is not None:
                     srv._lru.pop(victim).close()
@@ -67,15 +72,29 @@ class _Worker(threading.Thread):
                     raise MemoryError("request of %d bytes does not fit on the device" % need)
                 srv.admission_waits += 1
                 srv._adm.wait()
+            before = srv.free_bytes()
             s = srv.factory(prob)
+            left = need - max(0, before - srv.free_bytes())
+            if left > 0:
+                srv._pending[ck] = left
             srv._lru[ck] = s
             srv._busy.add(ck)
             return s
 
+    def _settled(self, prob):
+        """The context's bodies are set: what it allocates now shows in the
+        free memory, so none of its footprint is pending any more."""
+        srv = self.server
+        with srv._adm:
+            if srv._pending.pop((self.wid, _context_key(prob)), None) is not None:
+                srv._adm.notify_all()
+
     def _release(self, prob):
         srv = self.server
         with srv._adm:
-            srv._busy.discard((self.wid, _context_key(prob)))
+            ck = (self.wid, _context_key(prob))
+            srv._pending.pop(ck, None)
+            srv._busy.discard(ck)
             srv._adm.notify_all()
 
     def run(self):
@@ -90,6 +109,7 @@ class _Worker(threading.Thread):
                 s = self._context(prob)
                 held = True
                 s.set_bodies(prob.R, prob.offsets, prob.centres)
+                self._settled(prob)
                 s.set_velocities(prob.U, prob.Omega)
                 if nsteps is None:
                     info = s.solve(warm_start=False)
@@ -177,6 +197,9 @@ class Server:
         self._adm = threading.Condition()
         self._lru = collections.OrderedDict()
         self._busy = set()
+        # (worker, key) -> bytes of an admitted context's footprint that the
+        # device's free memory does not show yet (its bodies are not set)
+        self._pending = {}
         self.evictions = 0
         self.admission_waits = 0
         self.workers = [_Worker(self, w) for w in range(workers)]
@@ -250,6 +273,7 @@ class Server:
                     s = w._context(p)
                     try:
                         s.set_bodies(p.R, p.offsets, p.centres)
+                        w._settled(p)
                         s.set_velocities(p.U, p.Omega)
                         if p.rho > 0:
                             s.reset()

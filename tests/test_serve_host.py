@@ -229,3 +229,48 @@ def test_admission_evicts_other_workers_idle_contexts():
         f.result(timeout=10)
         assert srv.evictions == 1
         assert sum(len(w.contexts) for w in srv.workers) == 1
+
+
+def test_admission_counts_body_blocks_not_yet_allocated():
+    """A context takes 30 of its 100-byte footprint when created and the other
+    70 when its first request sets the bodies, outside the admission lock.  Two
+    workers take requests for two grids at once with 150 bytes free: the
+    second admission must count the first context's 70 pending bytes and wait,
+    so the free memory never goes negative."""
+    FakeSolver.created = []
+    lock = threading.Lock()
+    state = {"free": 150, "min_free": 150}
+
+    def take(nbytes):
+        with lock:
+            state["free"] -= nbytes
+            state["min_free"] = min(state["min_free"], state["free"])
+
+    class Bodies(FakeSolver):
+        def __init__(self, p):
+            super().__init__(p, delay=0.01)
+            self.held = 30
+            take(30)
+
+        def set_bodies(self, R, offsets, centres):
+            time.sleep(0.05)      # the other worker's admission runs meanwhile
+            if self.held == 30:
+                take(70)
+                self.held = 100
+            super().set_bodies(R, offsets, centres)
+
+        def close(self):
+            take(-self.held)
+            super().close()
+
+    probs = [_prob(2, n, u=i) for i, n in enumerate((16, 32) * 3)]
+    with serve.Server(workers=2, factory=Bodies, footprint=lambda p: 100, free_bytes=lambda: state["free"],
+                      reserve_bytes=0) as srv:
+        futs = [srv.submit(p) for p in probs]
+        res = [f.result(timeout=20) for f in futs]
+        assert srv.admission_waits > 0
+        assert not srv._pending
+    for p, r in zip(probs, res):
+        assert np.array_equal(r["F"], p.U * 2.0)
+    assert state["min_free"] >= 0
+    assert state["free"] == 150
