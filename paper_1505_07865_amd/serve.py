@@ -22,7 +22,10 @@ context left on the device fails, with MemoryError.  A context's body blocks
 are allocated when its first request sets the bodies, outside the lock: until
 then the part of its footprint that creation did not take from the free
 memory stays counted as pending, so that concurrent admissions cannot spend
-it twice.
+it twice.  A resident context that takes a request with larger body blocks
+than it holds grows by the difference without a new admission: a request's
+body blocks (under about 100 MB for the requests served) are small next to
+a context's grids and hierarchies.
 
 Every steady solve starts from a zero initial guess and every trajectory from
 a fluid at rest, so a request's result does not depend on what the context
