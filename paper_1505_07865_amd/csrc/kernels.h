@@ -234,9 +234,13 @@ void arnoldi_step(const T* V, int64_t ld, int k, double* hcol, double* h2, doubl
 // V_k pending on entry, w = V_{k+1}; afterwards V_k is final, V_{k+1} pending,
 // H column k-1 final and rotated, column k provisional, *resid the estimate.
 // G needs 2(k+2) doubles, coef 2k+2, part 2(k+2)*nblocks.
-template <typename T>
+// With split non-null, the new pending V_{k+1}'s first nsplit = (dim+1) C
+// entries (velocity and pressure) are also written to split, in split storage
+// and type TS, as the conversion of the next preconditioner input would.
+template <typename T, typename TS>
 void dcgs2_step(T* V, int64_t ld, int64_t len, int k, double* H, int ldh, double* G, double* coef, double* part,
-                int nblocks, double* cs, double* sn, double* g, double* resid, hipStream_t s, bool timed);
+                int nblocks, double* cs, double* sn, double* g, double* resid, hipStream_t s, bool timed,
+                TS* split, int dim, int logn, int64_t nsplit);
 // x += sum_j y[j] Z_j  (Z in TZ, x in TX); with assign, x = sum_j y[j] Z_j.
 // With zmean (stride 4 per column), the first dim blocks of C entries of
 // column j are taken as Z_j - zmean[4j + a]: the velocity components of the

@@ -378,12 +378,34 @@ __global__ void __launch_bounds__(1024) k_dcgs2_coef(const double* __restrict__ 
   colk[k] = ck;
 }
 
+// Copy of the new pending vector's first nsplit entries (its velocity and
+// pressure fields, C cells each) into split storage in TS: the next outer
+// iteration preconditions exactly this vector, so the copy saves that
+// iteration a pass over it.
+template <typename TS>
+struct SplitOut {
+  TS* dst;  // null: no copy
+  int dim, logn;
+  int64_t nsplit;
+};
+
+template <typename TS>
+__device__ inline void split_store(const SplitOut<TS>& so, int64_t i, double v) {
+  const int lc = so.dim * so.logn;
+  const int64_t f = i >> lc;
+  const int c = (int)(i & (((int64_t)1 << lc) - 1));
+  const int mask = (1 << so.logn) - 1;
+  const int x = c & mask, y = (c >> so.logn) & mask;
+  const int pos = so.dim == 3 ? split_index<3>(x, y, c >> (2 * so.logn), so.logn) : split_index<2>(x, y, 0, so.logn);
+  so.dst[(f << lc) + pos] = (TS)v;
+}
+
 // V_k <- (V_k - sum_{j<k} s_j V_j) / nu ;  w <- w - sum_{j<k} c_j V_j - c_k V_k(new).
 // part[block] = partial sums of the new w^2.
-template <typename T>
+template <typename T, typename TS>
 __global__ void __launch_bounds__(256) k_dcgs2_axpy(T* __restrict__ V, int64_t ld, int k,
                                                     const double* __restrict__ coef, int len,
-                                                    double* __restrict__ part) {
+                                                    double* __restrict__ part, SplitOut<TS> so) {
   __shared__ double red[256 / kWave];
   const unsigned stride = gridDim.x * blockDim.x;
   T* __restrict__ vk = V + (int64_t)k * ld;
@@ -418,6 +440,7 @@ __global__ void __launch_bounds__(256) k_dcgs2_axpy(T* __restrict__ V, int64_t l
     a -= c[k] * q;
     const T o = (T)a;
     w[i] = o;
+    if (so.dst && (int64_t)i < so.nsplit) split_store(so, i, (double)o);
     ss += (double)o * (double)o;
   }
   ss = block_sum(ss, red);
@@ -648,9 +671,10 @@ void launch_axpby(const double* x, double* y, int64_t len, double a, double b, h
   hipLaunchKernelGGL(k_axpby, dim3(g), dim3(256), 0, s, x, y, len, a, b);
 }
 
-template <typename T>
+template <typename T, typename TS>
 void dcgs2_step(T* V, int64_t ld, int64_t len, int k, double* H, int ldh, double* G, double* coef, double* part,
-                int nblocks, double* cs, double* sn, double* g, double* resid, hipStream_t s, bool timed) {
+                int nblocks, double* cs, double* sn, double* g, double* resid, hipStream_t s, bool timed,
+                TS* split, int dim, int logn, int64_t nsplit) {
   if (len >= ((int64_t)1 << 28)) throw DeviceError("dcgs2_step: vectors longer than 2^28 entries");
   const int ncols = k + 2;
   const double vb = (double)len * sizeof(T);
@@ -675,13 +699,21 @@ void dcgs2_step(T* V, int64_t ld, int64_t len, int k, double* H, int ldh, double
     }
   }
   hipLaunchKernelGGL(k_dcgs2_coef, dim3(1), dim3(1024), 0, s, part, nblocks, G, k, H, ldh, coef);
-  const TimerEvents eva = timed ? timer_sample(kTimerOrthoAxpy, (ncols + 2) * vb) : TimerEvents();
-  hipExtLaunchKernelGGL(k_dcgs2_axpy<T>, dim3(nblocks), dim3(256), 0, s, eva.start, eva.stop, 0, V, ld, k,
-                        (const double*)coef, (int)len, part);
+  if (split && (nsplit > len || nsplit != ((int64_t)(dim + 1) << (dim * logn))))
+    throw DeviceError("dcgs2_step: split copy does not cover the fluid fields of the vectors");
+  const SplitOut<TS> so{split, dim, logn, split ? nsplit : 0};
+  const double sb = split ? (double)nsplit * sizeof(TS) : 0.0;
+  const TimerEvents eva = timed ? timer_sample(kTimerOrthoAxpy, (ncols + 2) * vb + sb) : TimerEvents();
+  hipExtLaunchKernelGGL((k_dcgs2_axpy<T, TS>), dim3(nblocks), dim3(256), 0, s, eva.start, eva.stop, 0, V, ld, k,
+                        (const double*)coef, (int)len, part, so);
   hipLaunchKernelGGL(k_dcgs2_finish, dim3(1), dim3(256), 0, s, part, nblocks, H, ldh, k, cs, sn, g, resid);
 }
-template void dcgs2_step<double>(double*, int64_t, int64_t, int, double*, int, double*, double*, double*, int,
-                                 double*, double*, double*, double*, hipStream_t, bool);
+template void dcgs2_step<double, float>(double*, int64_t, int64_t, int, double*, int, double*, double*, double*,
+                                        int, double*, double*, double*, double*, hipStream_t, bool, float*, int, int,
+                                        int64_t);
+template void dcgs2_step<double, double>(double*, int64_t, int64_t, int, double*, int, double*, double*, double*,
+                                         int, double*, double*, double*, double*, hipStream_t, bool, double*, int, int,
+                                         int64_t);
 
 void launch_givens_step(double* H, int ldh, int k, double* cs, double* sn, double* g, double* resid,
                         hipStream_t s) {

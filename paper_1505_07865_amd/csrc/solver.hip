@@ -312,14 +312,16 @@ void inner_gmres(ibr_ctx* c, const T* rhs, T* out) {
   launch_combine_from_split<T, T>(d, c->logn, Z, NF, ns, c->yi, out, d + 1, true, s);
 }
 
-// z = P r (Sec. 5.1).  r fp64 stacked; z stacked in T.
+// z = P r (Sec. 5.1).  r fp64 stacked; z stacked in T.  rhs_ready: the
+// fluid fields of r are already in rhsT, in split storage (the previous outer
+// iteration's Arnoldi update wrote them there).
 template <typename T>
-void precondition(ibr_ctx* c, const double* r, T* z) {
+void precondition(ibr_ctx* c, const double* r, T* z, bool rhs_ready = false) {
   hipStream_t s = c->stream;
   const int d = c->dim;
   const int64_t NF = c->NF;
   T* rhs = (T*)c->rhsT;
-  launch_to_split<double, T>(d, c->logn, r, rhs, d + 1, s);
+  if (!rhs_ready) launch_to_split<double, T>(d, c->logn, r, rhs, d + 1, s);
   inner_gmres<T>(c, rhs, z);
   // slip dU = -(J v + r_L)
   launch_interp<T>(d, c->logn, c->N, c->taps, z, -1.0, r + NF, -1.0, c->dU, s);
@@ -353,7 +355,9 @@ void iteration_body(ibr_ctx* c, int k) {
   double* vk = V + (int64_t)k * ld;
   double* w = V + (int64_t)(k + 1) * ld;
   TZ* zk = Z + (int64_t)k * ld;
-  precondition<TZ>(c, vk, zk);
+  // V_k for k > 0 is the vector the previous iteration's update left pending,
+  // and that update also wrote its split copy
+  precondition<TZ>(c, vk, zk, k > 0);
   // Steady periodic Stokes (eq. constrained_periodic): K has d null vectors
   // that carry a mean velocity (and a net force), invisible to the residual,
   // so the gauge <v> = 0 is kept exactly: z_k counts as z_k - <z_k>, the
@@ -364,8 +368,8 @@ void iteration_body(ibr_ctx* c, int k) {
     zm = c->zmean + 4 * k;
   }
   apply_K<TZ>(c, zk, w, zm);
-  dcgs2_step<double>(V, ld, NV, k, c->H, c->m + 1, c->G, c->coef, c->part, c->part_blocks, c->cs, c->sn, c->g,
-                     c->resid, c->stream, true);
+  dcgs2_step<double, TZ>(V, ld, NV, k, c->H, c->m + 1, c->G, c->coef, c->part, c->part_blocks, c->cs, c->sn, c->g,
+                         c->resid, c->stream, true, (TZ*)c->rhsT, c->dim, c->logn, c->NF);
 }
 
 // The graph of iteration k, captured on first use (and again when buffers or
