@@ -62,6 +62,14 @@ template <typename TI, typename TO>
 void launch_stokes_apply(int dim, int logn, const TI* v, const TI* p, TO* yv, TO* yp, double c0, double ch2,
                          double inv_h, const double* addc, hipStream_t s, bool split = false,
                          TimerEvents ev = TimerEvents(), int walls = 0);
+// Partial sums of the normal equations of min_y || r - [W_0 .. W_{ns-2}, w] y ||
+// with w = K (v, p) (split storage, ns in 1..3) formed without storing w:
+// stokes_gram_blocks(dim, logn) workgroups, part needs (ns(ns+1)/2 + ns) times
+// that many doubles; launch_gram_finish solves for y from them.
+int stokes_gram_blocks(int dim, int logn);
+template <typename T>
+void launch_stokes_gram(int dim, int logn, const T* v, const T* p, const T* W, int64_t ld, int ns, const T* r,
+                        double c0, double ch2, double inv_h, int walls, double* part, hipStream_t s);
 template <typename T>
 void launch_div_q(int dim, int logn, const T* v, const T* hp, T* q, double inv_h, hipStream_t s,
                   bool split = false);
@@ -248,12 +256,10 @@ void dcgs2_step(T* V, int64_t ld, int64_t len, int k, double* H, int ldh, double
 template <typename TZ, typename TX>
 void launch_combine(const TZ* Z, int64_t ld, int k, const double* y, TX* x, int64_t len, hipStream_t s,
                     bool assign = false, const double* zmean = nullptr, int64_t C = 0, int dim = 0);
-// y[0..ns) = argmin || r - sum_j y_j W_j ||  (W_j = W + j*ld, ns in 1..3) from the
-// normal equations: one reduction pass over W and r, one single-block solve.
-// part needs (ns(ns+1)/2 + ns) * nblocks doubles.
+// y[0..ns) = argmin || r - sum_j y_j W_j ||  (ns in 1..3) from the partial
+// sums of the normal equations (launch_stokes_gram), nblocks per product.
 template <typename T>
-void launch_gram_solve(const T* W, int64_t ld, int ns, const T* r, int64_t len, double* part, int nblocks,
-                       double* y, hipStream_t s);
+void launch_gram_finish(const double* part, int nblocks, int ns, double* y, hipStream_t s);
 void launch_norm_finish(const double* part, int nblocks, double* out, hipStream_t s);
 template <typename T>
 void launch_sumsq_partial(const T* w, int64_t len, double* part, int nblocks, hipStream_t s);

@@ -225,15 +225,13 @@ struct Group {
   }
 };
 
-// yv = A v + G p, yp = -D v on split storage (the preconditioner's operator).
-template <typename T, int DIM>
-__global__ void __launch_bounds__(256) k_stokes_split4(const T* __restrict__ v, const T* __restrict__ p,
-                                                       T* __restrict__ yv, T* __restrict__ yp, int logn, T c0, T ch2,
-                                                       T inv_h, int walls) {
+// (A v + G p, -D v) on split storage (the preconditioner's operator) for the
+// 4-cell group g; out(f, off, q) receives field f's 4 values at storage
+// offset off (f < DIM: velocity component f, f = DIM: the pressure row).
+template <typename T, int DIM, typename Out>
+__device__ inline void stokes_split4_group(const T* __restrict__ v, const T* __restrict__ p, int logn, T c0, T ch2,
+                                           T inv_h, int walls, const Group<DIM>& g, Out&& out_fn) {
   const int64_t C = (int64_t)1 << (DIM * logn);
-  const int t = (int)(xcd_block(gridDim.x) * blockDim.x + threadIdx.x);
-  if (t >= (int)(C >> 2)) return;
-  const Group<DIM> g(t, logn);
   const bool odd = g.odd;
   const Q4<T> pc = ld4(p + g.own);
   // p at c - e_a
@@ -312,12 +310,87 @@ __global__ void __launch_bounds__(256) k_stokes_split4(const T* __restrict__ v, 
       const T vplus = a == 0 ? xr : (a == 1 ? vyp.v[u] : vzp.v[u]);
       div[u] += (vplus - c) * inv_h;
     }
-    st4(yv + a * C + g.own, out);
+    out_fn(a, g.own, out);
   }
   Q4<T> q;
 #pragma unroll
   for (int u = 0; u < 4; ++u) q.v[u] = -div[u];
-  st4(yp + g.own, q);
+  out_fn(DIM, g.own, q);
+}
+
+// yv = A v + G p, yp = -D v on split storage.
+template <typename T, int DIM>
+__global__ void __launch_bounds__(256) k_stokes_split4(const T* __restrict__ v, const T* __restrict__ p,
+                                                       T* __restrict__ yv, T* __restrict__ yp, int logn, T c0, T ch2,
+                                                       T inv_h, int walls) {
+  const int64_t C = (int64_t)1 << (DIM * logn);
+  const int t = (int)(xcd_block(gridDim.x) * blockDim.x + threadIdx.x);
+  if (t >= (int)(C >> 2)) return;
+  const Group<DIM> g(t, logn);
+  stokes_split4_group<T, DIM>(v, p, logn, c0, ch2, inv_h, walls, g, [&](int f, int off, const Q4<T>& q) {
+    if (f < DIM)
+      st4(yv + f * C + off, q);
+    else
+      st4(yp + off, q);
+  });
+}
+
+// The last column of a few-column least-squares problem formed on the fly:
+// w = K (v, p) (as k_stokes_split4 computes it, rounded to T as it would be
+// stored) is not written; instead each workgroup adds up, in fp64, its part
+// of the normal equations of min_y || r - [W_0 .. W_{NS-2}, w] y || in the
+// row order of the Gram reduction (upper triangle of the Gram matrix row by
+// row, then the products with r).  W_b and r are stacked (DIM+1) C fluid
+// vectors in split storage, W_b at stride ld.  part[q * gridDim.x + block].
+template <typename T, int DIM, int NS>
+__global__ void __launch_bounds__(256) k_stokes_gram4(const T* __restrict__ v, const T* __restrict__ p,
+                                                      const T* __restrict__ W, int64_t ld, const T* __restrict__ r,
+                                                      int logn, T c0, T ch2, T inv_h, int walls,
+                                                      double* __restrict__ part) {
+  constexpr int NQ = NS * (NS + 1) / 2 + NS;
+  __shared__ double red[NQ][256 / kWave];
+  const int64_t C = (int64_t)1 << (DIM * logn);
+  const int t = (int)(xcd_block(gridDim.x) * blockDim.x + threadIdx.x);
+  double acc[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
+  if (t < (int)(C >> 2)) {
+    const Group<DIM> g(t, logn);
+    stokes_split4_group<T, DIM>(v, p, logn, c0, ch2, inv_h, walls, g, [&](int f, int off, const Q4<T>& q4) {
+      const int64_t o = f * C + off;
+      const Q4<T> rr = ld4(r + o);
+      Q4<T> wb[NS > 1 ? NS - 1 : 1];
+#pragma unroll
+      for (int b = 0; b < NS - 1; ++b) wb[b] = ld4(W + b * ld + o);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        double w[NS];
+#pragma unroll
+        for (int b = 0; b < NS - 1; ++b) w[b] = (double)wb[b].v[u];
+        w[NS - 1] = (double)q4.v[u];
+        const double ri = (double)rr.v[u];
+        int q = 0;
+#pragma unroll
+        for (int a = 0; a < NS; ++a)
+#pragma unroll
+          for (int b = a; b < NS; ++b) acc[q++] += w[a] * w[b];
+#pragma unroll
+        for (int a = 0; a < NS; ++a) acc[q++] += w[a] * ri;
+      }
+    });
+  }
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const double s = wave_sum(acc[q]);
+    if (lane == 0) red[q][wv] = s;
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < NQ) {
+    double s = 0;
+    for (int u = 0; u < (int)(blockDim.x / kWave); ++u) s += red[threadIdx.x][u];
+    part[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = s;
+  }
 }
 
 // q = -D v - hp on split storage (hp may be null).
@@ -670,6 +743,29 @@ template void launch_stokes_apply<float, double>(int, int, const float*, const f
                                                  TimerEvents, int);
 template void launch_stokes_apply<float, float>(int, int, const float*, const float*, float*, float*, double,
                                                 double, double, const double*, hipStream_t, bool, TimerEvents, int);
+
+int stokes_gram_blocks(int dim, int logn) { return (int)nblk(((int64_t)1 << (dim * logn)) / 4); }
+
+template <typename T>
+void launch_stokes_gram(int dim, int logn, const T* v, const T* p, const T* W, int64_t ld, int ns, const T* r,
+                        double c0, double ch2, double inv_h, int walls, double* part, hipStream_t s) {
+  const dim3 grid(stokes_gram_blocks(dim, logn));
+  switch (dim * 8 + ns) {
+#define IBR_SG(D, NS)                                                                                           \
+  case D * 8 + NS:                                                                                             \
+    hipLaunchKernelGGL((k_stokes_gram4<T, D, NS>), grid, dim3(256), 0, s, v, p, W, ld, r, logn, (T)c0, (T)ch2, \
+                       (T)inv_h, walls, part);                                                                 \
+    break;
+    IBR_SG(2, 1) IBR_SG(2, 2) IBR_SG(2, 3) IBR_SG(3, 1) IBR_SG(3, 2) IBR_SG(3, 3)
+#undef IBR_SG
+    default:
+      throw DeviceError("launch_stokes_gram: n_s must be 1, 2 or 3");
+  }
+}
+template void launch_stokes_gram<float>(int, int, const float*, const float*, const float*, int64_t, int,
+                                        const float*, double, double, double, int, double*, hipStream_t);
+template void launch_stokes_gram<double>(int, int, const double*, const double*, const double*, int64_t, int,
+                                         const double*, double, double, double, int, double*, hipStream_t);
 
 template <typename T>
 void launch_div_q(int dim, int logn, const T* v, const T* hp, T* q, double inv_h, hipStream_t s, bool split) {

@@ -97,62 +97,35 @@ __global__ void __launch_bounds__(256) k_combine(const TZ* __restrict__ Z, int64
   }
 }
 
-// Normal equations of min_y || r - W y || for a few columns W_0..W_{NS-1}
-// (stride ld): per-block partial sums, in fp64, of the upper triangle of W^T W
-// (row-major) followed by W^T r.  part[q * gridDim.x + block].
-template <typename T, int NS>
-__global__ void __launch_bounds__(256) k_gram_partial(const T* __restrict__ W, int64_t ld, const T* __restrict__ r,
-                                                      int64_t len, double* __restrict__ part) {
-  constexpr int NQ = NS * (NS + 1) / 2 + NS;
-  __shared__ double red[NQ][256 / kWave];
-  double acc[NQ];
-#pragma unroll
-  for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += stride) {
-    double w[NS];
-#pragma unroll
-    for (int a = 0; a < NS; ++a) w[a] = (double)W[(int64_t)a * ld + i];
-    const double ri = (double)r[i];
-    int q = 0;
-#pragma unroll
-    for (int a = 0; a < NS; ++a)
-#pragma unroll
-      for (int b = a; b < NS; ++b) acc[q++] += w[a] * w[b];
-#pragma unroll
-    for (int a = 0; a < NS; ++a) acc[q++] += w[a] * ri;
-  }
-  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
-#pragma unroll
-  for (int q = 0; q < NQ; ++q) {
-    const double v = wave_sum(acc[q]);
-    if (lane == 0) red[q][wv] = v;
-  }
-  __syncthreads();
-  if (threadIdx.x < NQ) {
-    double v = 0;
-    for (int u = 0; u < (int)(blockDim.x / kWave); ++u) v += red[threadIdx.x][u];
-    part[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = v;
-  }
-}
-
-// Sums the partials (fixed order) and solves (W^T W) y = W^T r by Cholesky.
-// A column that is numerically in the span of the earlier ones (squared
-// pivot <= drop * its squared norm) is dropped and gets y = 0, so a zero or
-// rank-deficient W still yields a finite minimiser.
+// Normal equations of min_y || r - W y || for a few columns W_0..W_{NS-1}:
+// part holds nblocks per-workgroup partial sums, in fp64, of each product in
+// the order (upper triangle of W^T W row by row, then W^T r), row q at
+// part[q * nblocks].  Sums the rows (one wavefront per row, fixed order) and
+// solves (W^T W) y = W^T r by Cholesky.  A column that is numerically in the
+// span of the earlier ones (squared pivot <= drop * its squared norm) is
+// dropped and gets y = 0, so a zero or rank-deficient W still yields a finite
+// minimiser.
 template <int NS>
-__global__ void __launch_bounds__(256) k_gram_solve(const double* __restrict__ part, int nblocks,
-                                                    double* __restrict__ y, double drop) {
+__global__ void __launch_bounds__(1024) k_gram_solve(const double* __restrict__ part, int nblocks,
+                                                     double* __restrict__ y, double drop) {
   constexpr int NQ = NS * (NS + 1) / 2 + NS;
   __shared__ double tot[NQ];
-  __shared__ double red[256 / kWave];
-  for (int q = 0; q < NQ; ++q) {
-    double v = 0;
-    for (int i = threadIdx.x; i < nblocks; i += blockDim.x) v += part[(int64_t)q * nblocks + i];
-    v = block_sum(v, red);
-    if (threadIdx.x == 0) tot[q] = v;
-    __syncthreads();
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+  for (int q = wv; q < NQ; q += (int)(blockDim.x / kWave)) {
+    const double* pr = part + (int64_t)q * nblocks;
+    double v0 = 0, v1 = 0, v2 = 0, v3 = 0;
+    int i = lane;
+    for (; i + 3 * kWave < nblocks; i += 4 * kWave) {
+      v0 += pr[i];
+      v1 += pr[i + kWave];
+      v2 += pr[i + 2 * kWave];
+      v3 += pr[i + 3 * kWave];
+    }
+    for (; i < nblocks; i += kWave) v0 += pr[i];
+    const double v = wave_sum((v0 + v1) + (v2 + v3));
+    if (lane == 0) tot[q] = v;
   }
+  __syncthreads();
   if (threadIdx.x != 0) return;
   double G[NS][NS], L[NS][NS], rhs[NS], z[NS];
   bool keep[NS];
@@ -607,30 +580,32 @@ template void launch_combine<float, double>(const float*, int64_t, int, const do
 template void launch_combine<float, float>(const float*, int64_t, int, const double*, float*, int64_t,
                                            hipStream_t, bool, const double*, int64_t, int);
 
+// A column whose squared distance from the span of the previous ones is
+// below this fraction of its squared norm is dropped (rounding level of T).
 template <typename T>
-void launch_gram_solve(const T* W, int64_t ld, int ns, const T* r, int64_t len, double* part, int nblocks,
-                       double* y, hipStream_t s) {
-  // a column whose squared distance from the span of the previous ones is
-  // below this fraction of its squared norm is dropped (rounding level of T)
-  const double drop = sizeof(T) == 4 ? 1e-5 : 1e-13;
+constexpr double gram_drop() {
+  return sizeof(T) == 4 ? 1e-5 : 1e-13;
+}
+
+template <typename T>
+void launch_gram_finish(const double* part, int nblocks, int ns, double* y, hipStream_t s) {
+  const double drop = gram_drop<T>();
   switch (ns) {
-#define IBR_GRAM(NS)                                                                                      \
-  case NS:                                                                                                \
-    hipLaunchKernelGGL((k_gram_partial<T, NS>), dim3(nblocks), dim3(256), 0, s, W, ld, r, len, part);     \
-    hipLaunchKernelGGL((k_gram_solve<NS>), dim3(1), dim3(256), 0, s, part, nblocks, y, drop);              \
-    break;
-    IBR_GRAM(1)
-    IBR_GRAM(2)
-    IBR_GRAM(3)
-#undef IBR_GRAM
+    case 1:
+      hipLaunchKernelGGL((k_gram_solve<1>), dim3(1), dim3(1024), 0, s, part, nblocks, y, drop);
+      break;
+    case 2:
+      hipLaunchKernelGGL((k_gram_solve<2>), dim3(1), dim3(1024), 0, s, part, nblocks, y, drop);
+      break;
+    case 3:
+      hipLaunchKernelGGL((k_gram_solve<3>), dim3(1), dim3(1024), 0, s, part, nblocks, y, drop);
+      break;
     default:
-      throw DeviceError("launch_gram_solve: n_s must be 1, 2 or 3");
+      throw DeviceError("launch_gram_finish: n_s must be 1, 2 or 3");
   }
 }
-template void launch_gram_solve<double>(const double*, int64_t, int, const double*, int64_t, double*, int, double*,
-                                        hipStream_t);
-template void launch_gram_solve<float>(const float*, int64_t, int, const float*, int64_t, double*, int, double*,
-                                       hipStream_t);
+template void launch_gram_finish<double>(const double*, int, int, double*, hipStream_t);
+template void launch_gram_finish<float>(const double*, int, int, double*, hipStream_t);
 
 void launch_norm_finish(const double* part, int nblocks, double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_norm_finish, dim3(1), dim3(256), 0, s, part, nblocks, out);

@@ -145,6 +145,10 @@ struct ibr_ctx {
   double* zmean = nullptr;
   int* flag = nullptr;
   int part_blocks = 0;  // blocks of the vector reductions' partial sums
+  // partial sums of the inner solve's normal equations, one row of
+  // stokes_gram_blocks per product (n_s <= 3)
+  double* gpart = nullptr;
+  int gpart_blocks = 0;
   int mean_blocks = 0;  // blocks of the per-field means' partial sums
   double* hres = nullptr;  // pinned
 
@@ -282,10 +286,16 @@ void inner_gmres(ibr_ctx* c, const T* rhs, T* out) {
       T* Zj = Z + (int64_t)j * NF;
       T* Wj = Q + (int64_t)j * NF;
       ps_inv<T>(c, pj, Zj);
-      launch_stokes_apply<T, T>(d, c->logn, Zj, Zj + (int64_t)d * c->C, Wj, Wj + (int64_t)d * c->C, c->c0, c->ch2,
-                                c->inv_h, nullptr, s, true, TimerEvents(), c->wm);
+      if (j + 1 < ns) {
+        launch_stokes_apply<T, T>(d, c->logn, Zj, Zj + (int64_t)d * c->C, Wj, Wj + (int64_t)d * c->C, c->c0,
+                                  c->ch2, c->inv_h, nullptr, s, true, TimerEvents(), c->wm);
+      } else {
+        // the last column serves only the normal equations: formed there, not stored
+        launch_stokes_gram<T>(d, c->logn, Zj, Zj + (int64_t)d * c->C, Q, NF, ns, rhs, c->c0, c->ch2, c->inv_h,
+                              c->wm, c->gpart, s);
+      }
     }
-    launch_gram_solve<T>(Q, NF, ns, rhs, NF, c->part, c->part_blocks, c->yi, s);
+    launch_gram_finish<T>(c->gpart, c->gpart_blocks, ns, c->yi, s);
     launch_combine_from_split<T, T>(d, c->logn, Z, NF, ns, c->yi, out, d + 1, true, s);
     return;
   }
@@ -867,6 +877,10 @@ void ibr_ctx::alloc_grid() {
   part_blocks = (int)std::min<int64_t>(1024, std::max<int64_t>(8, (NF + 255) / 256));
   mean_blocks = (int)std::min<int64_t>(256, std::max<int64_t>(1, (C + 1023) / 1024));
   part = track<double>((int64_t)(2 * m + 8) * part_blocks);
+  if (ns <= 3) {
+    gpart_blocks = stokes_gram_blocks(d, logn);
+    gpart = track<double>((int64_t)(ns * (ns + 1) / 2 + ns) * gpart_blocks);
+  }
   part2 = track<double>((int64_t)(m + 3) * part_blocks);
   G = track<double>(2 * m + 8);
   coef = track<double>(2 * m + 8);
@@ -1070,6 +1084,7 @@ size_t ibr_footprint_bytes(const ibr_params* p, int nbodies, const int* markers_
   b += (size_t)4 * NV * 8;             // x, b, two temporaries
   b += (size_t)2 * d * C * 8;          // advection history
   b += (size_t)((2 * ns + 2) * NF + 2 * C) * ts;  // inner bases and P_S^-1 scratch
+  if (ns <= 3) b += (size_t)(ns * (ns + 1) / 2 + ns) * (size_t)stokes_gram_blocks(d, ilog2(p->n)) * 8;  // Gram partials
   const bool w = p->walls == IBR_WALLS_NOSLIP || p->walls == IBR_WALLS_BOX;
   b += ts == 4 ? MGHier<float>::bytes(d, ilog2(p->n), d, w) : MGHier<double>::bytes(d, ilog2(p->n), d, w);
   b += (size_t)4 * mtot * 8;           // mobility blocks: M~, its factor, the inverse factor, M~^-1
