@@ -51,8 +51,8 @@ HBM_PEAK_GBS = 8000.0
 # only for the kernel source it was taken on: the digest of that file is
 # checked and the figure dropped (null) once the source differs.
 MEASURED_TRAFFIC = {
-    "rb_fine": {"bytes_per_launch": 27428000.0, "file": "paper_1505_07865_amd/csrc/ops_mg.hip",
-                "sha256_16": "52fbe58c74067533", "summary": "profiles/rb_fine_128cube_mixed_hbm_counters.md"},
+    "rb_fine": {"bytes_per_launch": 27808000.0, "file": "paper_1505_07865_amd/csrc/ops_mg.hip",
+                "sha256_16": "3bb6e3447f74bfc3", "summary": "profiles/rb_fine_128cube_mixed_hbm_counters.md"},
 }
 # strides coprime with the launch pattern (12 finest-level sweeps per P_S^-1, 2 V-cycle calls
 # per P_S^-1) so the samples cycle through it; sparse enough that the sampled launches' events

@@ -151,6 +151,7 @@ struct MGHier {
   void rb_half(T* x, const T* b, int lg, int nf, T c0, T c1, int color, bool fine, hipStream_t s);
   // first sweep (red then black) from a zero guess, in one pass
   void rb_first(T* x, const T* b, int lg, int nf, T c0, T c1, bool fine, hipStream_t s);
+  void rb_red_prolong(T* x, const T* b, const T* e, int lg, int nf, T c0, T c1, bool fine, hipStream_t s);
 };
 
 // V-cycle with no-slip walls at both ends of the axes in wm (bit b: axis b;

@@ -322,6 +322,179 @@ __device__ inline void prolong_group(T* __restrict__ x, const T* __restrict__ e,
   if (!BLACK_ONLY || !even_black) stq(xo, qo);
 }
 
+// Coarse cells m0-1 .. m0+4 of coarse row (Jr, Kr) (wrapped), m0 a multiple
+// of 4: the x-range that the fine cells 2 m0 - 1 .. 2 m0 + 8 interpolate from
+// (as prolong_group loads them).
+template <typename T, int DIM>
+__device__ inline void coarse_row6(const T* __restrict__ e, int lognc, int Jr, int Kr, int m0, T E[6]) {
+  const int Cc = 1 << (DIM * lognc), Hc = Cc >> 1, hlc = lognc - 1;
+  const int maskc = (1 << lognc) - 1, hmaskc = (1 << hlc) - 1;
+  Jr &= maskc;
+  Kr = DIM == 3 ? (Kr & maskc) : 0;
+  const int rowc = Jr | (Kr << lognc);
+  const int cq = (Jr + Kr) & 1;  // colour of the even coarse cells
+  const T* ee = e + cq * Hc + (rowc << hlc);
+  const T* eo = e + (1 - cq) * Hc + (rowc << hlc);
+  const int mc = m0 >> 1;
+  const Pair<T> pe = *reinterpret_cast<const Pair<T>*>(ee + mc);
+  const Pair<T> po = *reinterpret_cast<const Pair<T>*>(eo + mc);
+  E[0] = eo[(mc - 1) & hmaskc];
+  E[1] = pe.v[0];
+  E[2] = po.v[0];
+  E[3] = pe.v[1];
+  E[4] = po.v[1];
+  E[5] = ee[(mc + 2) & hmaskc];
+}
+
+// The first red half sweep after prolongation, with the prolongation folded
+// in.  Post-smoothing corrects only the black cells (the red half sweep
+// overwrites the red ones without reading them), and the black half sweep
+// that follows overwrites the black ones from their red neighbours alone: so
+// the corrected black values are read only here.  This red half sweep takes
+// each black neighbour as x + P e, forming P e from the coarse e with the
+// interpolation of prolong_group (per coarse row along x, then y, then z,
+// weights 3/4 and 1/4), and leaves the black cells as they are.  The red cells
+// of group g (rows (j, k)) read black cells in 5 fine rows, whose corrections
+// come from 8 coarse rows in 3D (3 in 2D): Y in {J, J+sj, J-sj} x Z in
+// {K, K+sk, K-sk}, sj and sk the side of the fine row within its coarse cell.
+template <typename T, int DIM>
+__device__ inline void rb_red_prolong_group(T* __restrict__ x, const T* __restrict__ b, const T* __restrict__ e,
+                                            int logn, T c0, T c1, int g) {
+  const int C = 1 << (DIM * logn);
+  const int H = C >> 1;
+  const int hl = logn - 1;
+  const int mask = (1 << logn) - 1, hmask = (1 << hl) - 1;
+  const int m0 = (g & ((1 << (hl - 2)) - 1)) << 2;
+  const int row = g >> (hl - 2);
+  const int j = row & mask;
+  const int k = DIM == 3 ? (row >> logn) : 0;
+  const bool odd = ((j + k) & 1) != 0;  // red cells at i = 2m + 1 (black at 2m), else the other way
+  const T* oth = x + H;
+  Quad<T> o = ldq(oth + (row << hl) + m0);
+  T ext = oth[(row << hl) + ((odd ? m0 + 4 : m0 - 1) & hmask)];
+  const int ry0 = ((j - 1) & mask) | (k << logn), ry1 = ((j + 1) & mask) | (k << logn);
+  Quad<T> ym = ldq(oth + (ry0 << hl) + m0);
+  Quad<T> yp = ldq(oth + (ry1 << hl) + m0);
+  Quad<T> zm, zp;
+  if (DIM == 3) {
+    const int rz0 = j | (((k - 1) & mask) << logn), rz1 = j | (((k + 1) & mask) << logn);
+    zm = ldq(oth + (rz0 << hl) + m0);
+    zp = ldq(oth + (rz1 << hl) + m0);
+  }
+  const Quad<T> bc = ldq(b + (row << hl) + m0);
+
+  // Coarse rows by (Y, Z) offset from the fine row's own coarse cell (J, K):
+  // r0 (0,0), r1 (sj,0), r2 (0,sk), r3 (sj,sk), r4 (-sj,0), r5 (-sj,sk),
+  // r6 (0,-sk), r7 (sj,-sk) (2D: r0, r1, r4).  Each fine row combines 4 of
+  // them as prolong_group does, b0 = w0 a(near Y) + w1 a(far Y) in its own Z
+  // row, b1 likewise in the other Z row, P e = w0 b0 + w1 b1:
+  //   own row (j, k): r0 r1 | r2 r3      far y row (j+sj): r1 r0 | r3 r2
+  //   near y row (j-sj): r0 r4 | r2 r5   far z row (k+sk): r2 r3 | r0 r1
+  //   near z row (k-sk): r0 r1 | r6 r7
+  // The rows come in pairs and each combination is finished as soon as its
+  // rows are in, so only a few partial sums stay live.  a = the x-interpolation
+  // of one coarse row at the 4 black cells of the fine row (parity pb0 for the
+  // own row, the other parity for the 4 neighbour rows); both parities are
+  // formed and chosen by value (a choice between array elements would keep
+  // the row in memory).
+  const int lognc = logn - 1;
+  const int J = j >> 1, K = k >> 1;
+  const int sj = (j & 1) ? 1 : -1, sk = (k & 1) ? 1 : -1;
+  const T w0 = T(0.75), w1 = T(0.25);
+  const bool pb0 = !odd;  // black cells of the own row at fine x = 2m + pb0
+  // own-parity (q) and neighbour-parity (p) interpolations of a coarse row,
+  // and the own row's cell beyond the group (xg)
+  auto lerps = [&](int dy, int dz, Quad<T>& q, Quad<T>& p, T& xg) {
+    T E[6];
+    coarse_row6<T, DIM>(e, lognc, J + dy, K + dz, m0, E);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const T lo = w0 * E[1 + u] + w1 * E[u];
+      const T hi = w0 * E[1 + u] + w1 * E[2 + u];
+      q.v[u] = pb0 ? hi : lo;
+      p.v[u] = pb0 ? lo : hi;
+    }
+    const T xo = w0 * E[0] + w1 * E[1];  // coarse m0-1 (odd fine x)
+    const T xe = w0 * E[5] + w1 * E[4];  // coarse m0+4 (even fine x)
+    xg = pb0 ? xo : xe;
+  };
+  Quad<T> q0, p0, q1, p1, own_b0, yfar_b0, zfar_b1;
+  T x0, x1, xg_b0;
+  lerps(0, 0, q0, p0, x0);
+  lerps(sj, 0, q1, p1, x1);
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    own_b0.v[u] = w0 * q0.v[u] + w1 * q1.v[u];
+    yfar_b0.v[u] = w0 * p1.v[u] + w1 * p0.v[u];
+    zfar_b1.v[u] = w0 * p0.v[u] + w1 * p1.v[u];  // also the near z row's b0
+  }
+  xg_b0 = w0 * x0 + w1 * x1;
+  if constexpr (DIM == 3) {
+    Quad<T> q2, p2, q3, p3;
+    T x2, x3;
+    lerps(0, sk, q2, p2, x2);
+    lerps(sj, sk, q3, p3, x3);
+    Quad<T> yfar, zfar;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const T own_b1 = w0 * q2.v[u] + w1 * q3.v[u];
+      o.v[u] += w0 * own_b0.v[u] + w1 * own_b1;
+      const T yfar_b1 = w0 * p3.v[u] + w1 * p2.v[u];
+      yfar.v[u] = w0 * yfar_b0.v[u] + w1 * yfar_b1;
+      const T zfar_b0 = w0 * p2.v[u] + w1 * p3.v[u];
+      zfar.v[u] = w0 * zfar_b0 + w1 * zfar_b1.v[u];
+    }
+    ext += w0 * xg_b0 + w1 * (w0 * x2 + w1 * x3);
+    Quad<T> q4, p4, q5, p5, ynear;
+    T x4, x5;
+    lerps(-sj, 0, q4, p4, x4);
+    lerps(-sj, sk, q5, p5, x5);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const T b0 = w0 * p0.v[u] + w1 * p4.v[u];
+      const T b1 = w0 * p2.v[u] + w1 * p5.v[u];
+      ynear.v[u] = w0 * b0 + w1 * b1;
+    }
+    Quad<T> q6, p6, q7, p7;
+    T x6, x7;
+    lerps(0, -sk, q6, p6, x6);
+    lerps(sj, -sk, q7, p7, x7);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const T b1 = w0 * p6.v[u] + w1 * p7.v[u];
+      const T znear = w0 * zfar_b1.v[u] + w1 * b1;
+      ym.v[u] += sj < 0 ? yfar.v[u] : ynear.v[u];
+      yp.v[u] += sj < 0 ? ynear.v[u] : yfar.v[u];
+      zm.v[u] += sk < 0 ? zfar.v[u] : znear;
+      zp.v[u] += sk < 0 ? znear : zfar.v[u];
+    }
+  } else {
+    Quad<T> q4, p4;
+    T x4;
+    lerps(-sj, 0, q4, p4, x4);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      o.v[u] += own_b0.v[u];
+      const T ynear = w0 * p0.v[u] + w1 * p4.v[u];
+      ym.v[u] += sj < 0 ? yfar_b0.v[u] : ynear;
+      yp.v[u] += sj < 0 ? ynear : yfar_b0.v[u];
+    }
+    ext += xg_b0;
+  }
+
+  const T inv_diag = T(1) / (c0 + T(2 * DIM) * c1);
+  Quad<T> out;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const T xl = odd ? o.v[u] : (u == 0 ? ext : o.v[u - 1]);
+    const T xr = odd ? (u == 3 ? ext : o.v[u + 1]) : o.v[u];
+    T sum = xl + xr + ym.v[u] + yp.v[u];
+    if (DIM == 3) sum += zm.v[u] + zp.v[u];
+    out.v[u] = (bc.v[u] + c1 * sum) * inv_diag;
+  }
+  stq(x + (row << hl) + m0, out);
+}
+
 // Half sweep of one cell of colour `color` (t < C/2), for the 4^dim coarsest
 // grid, whose half rows (2 cells) are shorter than a 4-cell group.
 template <typename T, int DIM>
@@ -389,6 +562,19 @@ __global__ void __launch_bounds__(256) k_prolong_add(T* __restrict__ x, const T*
   if (g >= (C >> 3)) return;
   const int64_t f = blockIdx.y;
   prolong_group<T, DIM, BLACK_ONLY>(x + f * C, e + f * Cc, logn, g);
+}
+
+// Post-smoothing's first red half sweep with the black cells' prolongation
+// folded in (rb_red_prolong_group); FINE marks the finest level.
+template <typename T, int DIM, bool FINE>
+__global__ void __launch_bounds__(256) k_rb_red_prolong(T* __restrict__ x, const T* __restrict__ b,
+                                                        const T* __restrict__ e, int logn, T c0, T c1) {
+  const int C = 1 << (DIM * logn);
+  const int Cc = C >> DIM;
+  const int g = flat_thread(gridDim.x);
+  if (g >= (C >> 3)) return;
+  const int64_t f = blockIdx.y;
+  rb_red_prolong_group<T, DIM>(x + f * C, b + f * C, e + f * Cc, logn, c0, c1, g);
 }
 
 // ---------------------------------------------------------------- one-workgroup tail
@@ -693,6 +879,30 @@ void MGHier<T>::rb_half(T* x, const T* b, int lg, int nf, T c0, T c1, int color,
 }
 
 template <typename T>
+void MGHier<T>::rb_red_prolong(T* x, const T* b, const T* e, int lg, int nf, T c0, T c1, bool fine,
+                               hipStream_t s) {
+  const int64_t Cl = (int64_t)1 << (dim * lg);
+  check_quad_aligned(x, b);
+  const dim3 g(nblk(Cl / 8), nf);
+  // algorithmic traffic: a half sweep's plus the coarse correction read once
+  const TimerEvents ev =
+      fine ? timer_sample(kTimerRbFine, (1.5 + 1.0 / (1 << dim)) * (double)Cl * nf * sizeof(T)) : TimerEvents();
+  if (dim == 3) {
+    if (fine)
+      hipExtLaunchKernelGGL(k_rb_red_prolong<T, 3, true>, g, dim3(256), 0, s, ev.start, ev.stop, 0, x, b, e, lg, c0,
+                            c1);
+    else
+      hipLaunchKernelGGL((k_rb_red_prolong<T, 3, false>), g, dim3(256), 0, s, x, b, e, lg, c0, c1);
+  } else {
+    if (fine)
+      hipExtLaunchKernelGGL(k_rb_red_prolong<T, 2, true>, g, dim3(256), 0, s, ev.start, ev.stop, 0, x, b, e, lg, c0,
+                            c1);
+    else
+      hipLaunchKernelGGL((k_rb_red_prolong<T, 2, false>), g, dim3(256), 0, s, x, b, e, lg, c0, c1);
+  }
+}
+
+template <typename T>
 void MGHier<T>::rb_first(T* x, const T* b, int lg, int nf, T c0, T c1, bool fine, hipStream_t s) {
   const int64_t Cl = (int64_t)1 << (dim * lg);
   check_quad_aligned(x, b);
@@ -730,9 +940,10 @@ void MGHier<T>::vcycle(int nf, const T* b, T* x, double c0, double c1, int nu_pr
   // the fused kernel, which cannot update x in place.
   // whole-cycle timer; algorithmic bytes: per level of C cells and field the
   // per-step kernels' (first sweep 2, each further sweep 3, residual and
-  // restriction 2 + 1/8, black prolongation 1 + 1/8, words of w per cell),
-  // over the levels about 8/7 of the finest one
-  const double words_per_cell = 2.0 + 3.0 * (nu_pre > 0 ? nu_pre - 1 : 0) + 2.125 + 1.125 + 3.0 * nu_post;
+  // restriction 2 + 1/8, the coarse correction read by the first red half
+  // sweep 1/8, words of w per cell), over the levels about 8/7 of the finest one
+  const double words_per_cell =
+      2.0 + 3.0 * (nu_pre > 0 ? nu_pre - 1 : 0) + 2.125 + (nu_post > 0 ? 0.125 + 3.0 * nu_post : 1.125);
   const TimerEvents evc =
       timer_sample(kTimerVcycle, words_per_cell * 8.0 / 7.0 * (double)((int64_t)1 << (dim * logn)) * nf * sizeof(T));
   if (evc.start) IBR_HIP(hipEventRecord(evc.start, s));
@@ -795,21 +1006,20 @@ void MGHier<T>::vcycle(int nf, const T* b, T* x, double c0, double c1, int nu_pr
       continue;
     }
     T* xl = xin(l);  // == xout(l): updated in place
-    // with post-smoothing the first (red) half sweep overwrites the red cells
-    const dim3 gp(nblk(Cl / 8), nf);
-    if (three) {
-      if (nu_post > 0)
-        hipLaunchKernelGGL((k_prolong_add<T, 3, true>), gp, dim3(256), 0, s, xl, e, lg);
-      else
-        hipLaunchKernelGGL((k_prolong_add<T, 3, false>), gp, dim3(256), 0, s, xl, e, lg);
+    if (nu_post > 0) {
+      // the prolongation folded into the first red half sweep (which alone
+      // reads the corrected black cells; the black half sweep rewrites them)
+      rb_red_prolong(xl, bl, e, lg, nf, tc0, cl, l == 0, s);
+      rb_half(xl, bl, lg, nf, tc0, cl, 1, l == 0, s);
+      for (int sw = 1; sw < nu_post; ++sw)
+        for (int color = 0; color < 2; ++color) rb_half(xl, bl, lg, nf, tc0, cl, color, l == 0, s);
     } else {
-      if (nu_post > 0)
-        hipLaunchKernelGGL((k_prolong_add<T, 2, true>), gp, dim3(256), 0, s, xl, e, lg);
+      const dim3 gp(nblk(Cl / 8), nf);
+      if (three)
+        hipLaunchKernelGGL((k_prolong_add<T, 3, false>), gp, dim3(256), 0, s, xl, e, lg);
       else
         hipLaunchKernelGGL((k_prolong_add<T, 2, false>), gp, dim3(256), 0, s, xl, e, lg);
     }
-    for (int sw = 0; sw < nu_post; ++sw)
-      for (int color = 0; color < 2; ++color) rb_half(xl, bl, lg, nf, tc0, cl, color, l == 0, s);
   }
   if (evc.stop) IBR_HIP(hipEventRecord(evc.stop, s));
 }
