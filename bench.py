@@ -51,13 +51,14 @@ HBM_PEAK_GBS = 8000.0
 # only for the kernel source it was taken on: the digest of that file is
 # checked and the figure dropped (null) once the source differs.
 MEASURED_TRAFFIC = {
-    "rb_fine": {"bytes_per_launch": 27808000.0, "file": "paper_1505_07865_amd/csrc/ops_mg.hip",
-                "sha256_16": "3bb6e3447f74bfc3", "summary": "profiles/rb_fine_128cube_mixed_hbm_counters.md"},
+    "rb_fine": {"bytes_per_launch": 27629000.0, "file": "paper_1505_07865_amd/csrc/ops_mg.hip",
+                "sha256_16": "6464b3451ec49239", "summary": "profiles/rb_fine_128cube_mixed_hbm_counters.md"},
 }
 # strides coprime with the launch pattern (12 finest-level sweeps per P_S^-1, 2 V-cycle calls
 # per P_S^-1) so the samples cycle through it; sparse enough that the sampled launches' events
 # cost about 1% of the step
-TIMER_STRIDE = {"rb_fine": 29, "ortho_dot": 7, "ortho_axpy": 7, "stokes_apply": 7, "vcycle": 9, "wall_rb_fine": 29}
+TIMER_STRIDE = {"rb_fine": 29, "ortho_dot": 7, "ortho_axpy": 7, "stokes_apply": 7, "vcycle": 9, "wall_rb_fine": 29,
+                "rb_red_prolong": 7}
 # composite classes (several kernels per sample): reported, never the roofline kernel
 COMPOSITE_TIMERS = ("vcycle",)
 

@@ -347,9 +347,13 @@ ibr_status ibr_spread_noalloc(const ibr_params* params, int nmarkers, const void
 
 /* Bracket every stride-th launch of one kernel class with HIP events on its
  * stream and accumulate that launch's algorithmic bytes (stride 0 = off).
- * Classes: "rb_fine" (red-black half sweep on the finest multigrid level),
- * "ortho_dot" and "ortho_axpy" (the reduction and update passes of the outer
- * Arnoldi step), "stokes_apply" (the MAC stencil of the outer operator).
+ * Classes: "rb_fine" (red-black half sweeps and first sweeps on the finest
+ * multigrid level), "rb_red_prolong" (the finest level's first post-smoothing
+ * red half sweep, which also forms the prolonged correction of its black
+ * neighbours), "ortho_dot" and "ortho_axpy" (the reduction and update passes
+ * of the outer Arnoldi step), "stokes_apply" (the MAC stencil of the outer
+ * operator), "vcycle" (whole V-cycle calls), "wall_rb_fine" (finest-level half
+ * sweeps of the walled V-cycle).
  * Process-wide; enabling resets the class's counters.  While any class is
  * enabled the solver launches its kernels directly on the stream instead of
  * replaying captured iteration graphs, so every launch can be bracketed.

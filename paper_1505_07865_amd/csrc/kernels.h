@@ -43,7 +43,8 @@ enum TimerId {
   kTimerStokes = 3,
   kTimerVcycle = 4,  // whole V-cycles (events recorded around all of their kernels)
   kTimerWallRbFine = 5,  // finest-level half sweeps of the slit channel's V-cycle
-  kTimerCount = 6
+  kTimerRbRedProlong = 6,  // finest-level red half sweeps with the prolongation folded in
+  kTimerCount = 7
 };
 // A launch of a timed class is sampled (every stride-th one): the sampled launch
 // gets a start and a stop event to pass to hipExtLaunchKernelGGL, which stamps

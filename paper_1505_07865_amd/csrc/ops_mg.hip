@@ -886,7 +886,7 @@ void MGHier<T>::rb_red_prolong(T* x, const T* b, const T* e, int lg, int nf, T c
   const dim3 g(nblk(Cl / 8), nf);
   // algorithmic traffic: a half sweep's plus the coarse correction read once
   const TimerEvents ev =
-      fine ? timer_sample(kTimerRbFine, (1.5 + 1.0 / (1 << dim)) * (double)Cl * nf * sizeof(T)) : TimerEvents();
+      fine ? timer_sample(kTimerRbRedProlong, (1.5 + 1.0 / (1 << dim)) * (double)Cl * nf * sizeof(T)) : TimerEvents();
   if (dim == 3) {
     if (fine)
       hipExtLaunchKernelGGL(k_rb_red_prolong<T, 3, true>, g, dim3(256), 0, s, ev.start, ev.stop, 0, x, b, e, lg, c0,

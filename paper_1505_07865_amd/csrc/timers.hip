@@ -29,8 +29,8 @@ struct TimerState {
 
 TimerState g_timers[kTimerCount];
 
-const char* const kTimerNames[kTimerCount] = {"rb_fine", "ortho_dot", "ortho_axpy", "stokes_apply", "vcycle",
-                                              "wall_rb_fine"};
+const char* const kTimerNames[kTimerCount] = {"rb_fine", "ortho_dot",    "ortho_axpy",    "stokes_apply",
+                                              "vcycle",  "wall_rb_fine", "rb_red_prolong"};
 
 int timer_index(const char* name) {
   if (!name) return -1;

@@ -382,7 +382,7 @@ class Solver:
         return N
 
 
-TIMERS = ("rb_fine", "ortho_dot", "ortho_axpy", "stokes_apply", "vcycle", "wall_rb_fine")
+TIMERS = ("rb_fine", "ortho_dot", "ortho_axpy", "stokes_apply", "vcycle", "wall_rb_fine", "rb_red_prolong")
 
 
 def timer_enable(kernel, stride=1):
