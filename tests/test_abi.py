@@ -118,3 +118,27 @@ def test_oracle_is_not_imported_by_product():
             if fn.endswith((".py", ".hip", ".h", ".cpp")):
                 txt = open(os.path.join(dirpath, fn)).read()
                 assert "import oracle" not in txt and "from oracle" not in txt, fn
+
+
+def test_timer_classes_known_to_library_and_bench(lib):
+    """Every live timer class the binding lists is one the library accepts
+    (enable, read back empty, switch off: no launch, so no device work), the
+    header documents it, and bench.py has a sampling stride for it; unknown
+    classes and negative strides are rejected."""
+    import importlib.util
+    from paper_1505_07865_amd import ibr
+    spec = importlib.util.spec_from_file_location("bench_module", os.path.join(ROOT, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    header = open(os.path.join(ROOT, "include", "ibr.h")).read()
+    for name in ibr.TIMERS:
+        ibr.timer_enable(name, 3)
+        assert ibr.timer_read(name) == {"ms": 0.0, "launches": 0, "bytes": 0.0}
+        ibr.timer_enable(name, 0)
+        assert '"%s"' % name in header, name
+        assert bench.TIMER_STRIDE.get(name, 0) > 0, name
+    assert set(bench.TIMER_STRIDE) == set(ibr.TIMERS)
+    with pytest.raises(ibr.IbrError):
+        ibr.timer_enable("no_such_kernel", 1)
+    with pytest.raises(ibr.IbrError):
+        ibr.timer_enable("rb_fine", -1)
