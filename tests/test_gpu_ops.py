@@ -259,3 +259,26 @@ def test_mobility_inverse_matches_oracle(which):
         Mi = s.mobility_inverse(b)
         assert _rel(Mi, ref) < 1e-10, _rel(Mi, ref)
     s.close()
+
+
+@pytest.mark.parametrize("pre,post", [(1, 1), (2, 3), (2, 0), (0, 2)])
+@pytest.mark.parametrize("dim,n,nf", [(3, 64, 3), (2, 128, 2)])
+def test_vcycle_sweep_counts_match_oracle(pre, post, dim, n, nf):
+    """Other smoothing sweep counts take other kernel sequences: one post
+    sweep is the red sweep with the prolongation folded in plus one black
+    sweep; three sweeps leave the fused LDS levels for the per-step kernels;
+    no post-smoothing uses the plain prolongation, no pre-smoothing starts
+    from zero.  Each equals the oracle's cycle with the same counts (fp64,
+    1e-11) and repeats bitwise."""
+    from paper_1505_07865_amd import ibr
+    print("V-cycle sweeps %d/%d dim %d n %d nf %d" % (pre, post, dim, n, nf), flush=True)
+    s = ibr.Solver(dim=dim, n=n, h=1.0 / n, precision=ibr.FP64, mg_pre=pre, mg_post=post)
+    rng = np.random.default_rng(100 * pre + 10 * post + dim)
+    b = rng.standard_normal((nf,) + (n,) * dim)
+    c0, c1 = 2.5, 0.7
+    x = s.vcycle(c0, c1, b).reshape(b.shape)
+    for f in range(nf):
+        xe = multigrid.vcycle(b[f], c0, c1, nu_pre=pre, nu_post=post)
+        assert _rel(x[f], xe) < 1e-11, (f, _rel(x[f], xe))
+    assert np.array_equal(x, s.vcycle(c0, c1, b).reshape(b.shape))
+    s.close()
